@@ -1,0 +1,431 @@
+"""Seeded synthetic workloads for the visual-inertial bundle-adjustment step.
+
+This module only *simulates sensors*.  It draws a smooth, periodic rig
+trajectory, samples an ideal IMU along it, gives every keyframe its own smooth
+inverse-depth field and projects each keyframe's pixels into its neighbours to
+make correspondence targets.  It holds none of the solver's arithmetic: no
+residual linearisation, no preintegration, no normal equations.  Both the CPU
+oracle and the HIP path consume the arrays it returns, and nothing else is
+shared between them.
+
+Ground truth is *discrete-consistent*: the rig state at every IMU tick is
+defined by integrating the sampled angular rate and specific force with a
+zero-order hold (rotation by the exact exponential of ``omega*dt``, velocity and
+position with the exact constant-acceleration update).  With zero noise and a
+bias linearisation point equal to the true bias, a preintegrated IMU factor is
+therefore exactly satisfied by the ground truth, up to rounding.
+
+Conventions (the paper leaves them open; Sec. 3.1, Eq. 1-3):
+  * world frame is z-up, gravity ``(0, 0, -9.81)``;
+  * the camera frame equals the body frame (identity camera-IMU extrinsics);
+  * a pose is world-from-body, stored ``(px, py, pz, qx, qy, qz, qw)``;
+  * pixel ``(x, y)`` = (column, row) at integer coordinates;
+  * ``fx = fy = 60 * W / 64``, ``cx = W / 2``, ``cy = H / 2`` (60/60/32/24 at
+    48x64 and 75/75/40/30 at 60x80, i.e. the same field of view).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+from typing import List, Optional, Tuple
+
+import numpy as np
+
+GRAVITY = np.array([0.0, 0.0, -9.81])
+TRAJ_PERIOD_S = 6.4          # trajectory period: 64 keyframes at 10 Hz
+
+
+# --------------------------------------------------------------------------
+# small quaternion helpers (Hamilton product, xyzw storage)
+# --------------------------------------------------------------------------
+def _qmul(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    ax, ay, az, aw = a[..., 0], a[..., 1], a[..., 2], a[..., 3]
+    bx, by, bz, bw = b[..., 0], b[..., 1], b[..., 2], b[..., 3]
+    return np.stack([
+        aw * bx + ax * bw + ay * bz - az * by,
+        aw * by - ax * bz + ay * bw + az * bx,
+        aw * bz + ax * by - ay * bx + az * bw,
+        aw * bw - ax * bx - ay * by - az * bz,
+    ], axis=-1)
+
+
+def _quat_from_rotvec(v: np.ndarray) -> np.ndarray:
+    """Unit quaternion of the rotation by angle |v| about v/|v| (half-angle form)."""
+    v = np.asarray(v, dtype=np.float64)
+    ang = np.linalg.norm(v, axis=-1, keepdims=True)
+    half = 0.5 * ang
+    # sin(half)/ang with its series near zero
+    with np.errstate(invalid="ignore", divide="ignore"):
+        k = np.where(ang > 1e-8, np.sin(half) / np.where(ang > 0, ang, 1.0),
+                     0.5 - ang * ang / 48.0)
+    return np.concatenate([v * k, np.cos(half)], axis=-1)
+
+
+def _quat_to_mat(q: np.ndarray) -> np.ndarray:
+    x, y, z, w = q[..., 0], q[..., 1], q[..., 2], q[..., 3]
+    n = x * x + y * y + z * z + w * w
+    s = 2.0 / n
+    return np.stack([
+        np.stack([1 - s * (y * y + z * z), s * (x * y - z * w), s * (x * z + y * w)], -1),
+        np.stack([s * (x * y + z * w), 1 - s * (x * x + z * z), s * (y * z - x * w)], -1),
+        np.stack([s * (x * z - y * w), s * (y * z + x * w), 1 - s * (x * x + y * y)], -1),
+    ], -2)
+
+
+def _unit(rng: np.random.Generator, n: int) -> np.ndarray:
+    v = rng.normal(size=(n, 3))
+    return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+# --------------------------------------------------------------------------
+# configuration
+# --------------------------------------------------------------------------
+@dataclass
+class SceneConfig:
+    """Shape and noise of one synthetic window (one keyframe graph)."""
+    n_kf: int = 8
+    H: int = 48
+    W: int = 64
+    k_out: int = 3                      # outgoing edges per keyframe, nearest by index
+    n_loop: int = 0                     # extra long-range edges (|i-j| >= loop_gap)
+    loop_gap: int = 55
+    out_degrees: Optional[List[int]] = None   # per-KF out-degree (overrides k_out)
+    imu_rate: float = 200.0
+    kf_gap: int = 20                    # IMU samples between keyframes
+    gap_range: Optional[Tuple[int, int]] = None   # uniform integer gaps instead
+    sigma_px: float = 0.5
+    w_lo: float = 0.1
+    w_hi: float = 1.0
+    sigma_g: float = 1.7e-4             # rad/s/sqrt(Hz)
+    sigma_a: float = 2e-3               # m/s^2/sqrt(Hz)
+    sigma_bgw: float = 2e-5             # rad/s^2/sqrt(Hz)
+    sigma_baw: float = 3e-3             # m/s^3/sqrt(Hz)
+    bg0_std: float = 0.005
+    ba0_std: float = 0.05
+    init_dp: float = 0.05               # m
+    init_dtheta_deg: float = 2.0
+    init_depth_rel: float = 0.1
+    init_dv_std: float = 0.05
+    z_min: float = 0.1
+    noiseless: bool = False             # no pixel/IMU noise, no bias random walk
+    zero_bias: bool = False             # true bias identically zero
+
+    @property
+    def fx(self) -> float:
+        return 60.0 * self.W / 64.0
+
+    @property
+    def fy(self) -> float:
+        return 60.0 * self.W / 64.0
+
+    @property
+    def cx(self) -> float:
+        return self.W / 2.0
+
+    @property
+    def cy(self) -> float:
+        return self.H / 2.0
+
+
+def config_small() -> SceneConfig:
+    """8 keyframes, 48x64 maps, 3 outgoing edges each (24 edges), 4 GN iterations."""
+    return SceneConfig(n_kf=8, H=48, W=64, k_out=3)
+
+
+def config_window() -> SceneConfig:
+    """24-keyframe sliding window, 60x80 maps, 12 outgoing edges each (288 edges)."""
+    return SceneConfig(n_kf=24, H=60, W=80, k_out=12)
+
+
+def config_global() -> SceneConfig:
+    """512 keyframes, 60x80 maps, 11 outgoing edges each + 200 loop edges."""
+    return SceneConfig(n_kf=512, H=60, W=80, k_out=11, n_loop=200)
+
+
+def config_batched_window(w: int) -> SceneConfig:
+    """Window ``w`` of the 64-window batch: N ~ U{8..32}, out-degree ~ U{3..8},
+    map 48x64 or 60x80, IMU gaps ~ U{5..40} samples."""
+    rng = np.random.default_rng(4000 + w)
+    n = int(rng.integers(8, 33))
+    degs = [int(rng.integers(3, min(8, n - 1) + 1)) for _ in range(n)]
+    if rng.random() < 0.5:
+        H, W = 48, 64
+    else:
+        H, W = 60, 80
+    return SceneConfig(n_kf=n, H=H, W=W, out_degrees=degs, gap_range=(5, 40))
+
+
+# --------------------------------------------------------------------------
+# problem container
+# --------------------------------------------------------------------------
+@dataclass
+class Problem:
+    """All arrays of one window.  Estimate arrays are the solver's initial state."""
+    cfg: SceneConfig
+    seed: int
+    # camera
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    H: int
+    W: int
+    gravity: np.ndarray
+    # initial estimate
+    pose: np.ndarray         # (N,7) float64
+    vel: np.ndarray          # (N,3) float64
+    bias: np.ndarray         # (N,6) float64 (bg, ba)
+    invdepth: np.ndarray     # (N,H,W) float64
+    # frame graph
+    ii: np.ndarray           # (E,) int32 source keyframe (owns the depth)
+    jj: np.ndarray           # (E,) int32 target keyframe
+    target: np.ndarray       # (E,2,H,W) float32 pixel coordinates (x, y)
+    weight: np.ndarray       # (E,2,H,W) float32 information weights
+    target64: np.ndarray     # (E,2,H,W) float64 (exact values, for noiseless pins)
+    # IMU stream, CSR over the N-1 consecutive pairs
+    imu_off: np.ndarray      # (N,) int32
+    gyro: np.ndarray         # (S,3) float64
+    accel: np.ndarray        # (S,3) float64
+    imu_dt: np.ndarray       # (S,) float64
+    bias_hat: np.ndarray     # (N-1,6) float64 bias linearisation point per factor
+    noise: np.ndarray        # (4,) sigma_g, sigma_a, sigma_bgw, sigma_baw
+    # ground truth
+    pose_gt: np.ndarray
+    vel_gt: np.ndarray
+    bias_gt: np.ndarray
+    invdepth_gt: np.ndarray
+    kf_tick: np.ndarray      # (N,) IMU tick index of each keyframe
+    z_min: float = 0.1
+
+    @property
+    def n_kf(self) -> int:
+        return self.pose.shape[0]
+
+    @property
+    def n_edges(self) -> int:
+        return int(self.ii.shape[0])
+
+    def copy_state(self):
+        return (self.pose.copy(), self.vel.copy(), self.bias.copy(), self.invdepth.copy())
+
+
+# --------------------------------------------------------------------------
+# generator pieces
+# --------------------------------------------------------------------------
+class _Trajectory:
+    """Smooth periodic motion: sinusoidal position, sinusoidal body rate."""
+
+    def __init__(self, rng: np.random.Generator):
+        T = TRAJ_PERIOD_S
+        self.fp = np.array([1.0, 2.0, 3.0]) / T                    # Hz
+        self.Ap = rng.uniform(0.06, 0.12, size=(3, 3))              # axis x harmonic
+        self.Ap[:, 0] *= 1.6                                        # more lateral motion
+        self.php = rng.uniform(0, 2 * np.pi, size=(3, 3))
+        self.fw = np.array([1.0, 2.0, 3.0]) / T
+        self.Aw = rng.uniform(0.08, 0.18, size=(3, 3))              # rad/s
+        self.phw = rng.uniform(0, 2 * np.pi, size=(3, 3))
+
+    def pos(self, t):
+        t = np.atleast_1d(t)[:, None, None]
+        return (self.Ap[None] * np.sin(2 * np.pi * self.fp[None, None] * t + self.php[None])).sum(-1)
+
+    def vel(self, t):
+        t = np.atleast_1d(t)[:, None, None]
+        w = 2 * np.pi * self.fp[None, None]
+        return (self.Ap[None] * w * np.cos(w * t + self.php[None])).sum(-1)
+
+    def acc(self, t):
+        t = np.atleast_1d(t)[:, None, None]
+        w = 2 * np.pi * self.fp[None, None]
+        return (-self.Ap[None] * w * w * np.sin(w * t + self.php[None])).sum(-1)
+
+    def omega(self, t):
+        t = np.atleast_1d(t)[:, None, None]
+        return (self.Aw[None] * np.cos(2 * np.pi * self.fw[None, None] * t + self.phw[None])).sum(-1)
+
+
+# camera looking along world +y, image-down along world -z
+_Q0 = np.array([-np.sqrt(0.5), 0.0, 0.0, np.sqrt(0.5)])
+
+
+def _edge_list(cfg: SceneConfig, rng: np.random.Generator):
+    N = cfg.n_kf
+    ii, jj = [], []
+    for i in range(N):
+        k = cfg.out_degrees[i] if cfg.out_degrees is not None else cfg.k_out
+        k = min(k, N - 1)
+        cand = []
+        for s in range(1, N):
+            for j in (i + s, i - s):          # forward neighbour first on ties
+                if 0 <= j < N:
+                    cand.append(j)
+        for j in cand[:k]:
+            ii.append(i)
+            jj.append(j)
+    have = set(zip(ii, jj))
+    n_loop = 0
+    period_kf = int(round(TRAJ_PERIOD_S * cfg.imu_rate / cfg.kf_gap)) if cfg.gap_range is None else 0
+    tries = 0
+    while n_loop < cfg.n_loop and tries < 100000:
+        tries += 1
+        i = int(rng.integers(0, N))
+        if period_kf > 0:
+            # near-revisits of the periodic trajectory
+            m = int(rng.integers(1, max(2, N // period_kf + 1)))
+            j = i + (m if rng.random() < 0.5 else -m) * period_kf + int(rng.integers(-1, 2))
+        else:
+            j = int(rng.integers(0, N))
+        if not (0 <= j < N) or abs(i - j) < cfg.loop_gap or (i, j) in have:
+            continue
+        have.add((i, j))
+        ii.append(i)
+        jj.append(j)
+        n_loop += 1
+    return np.array(ii, dtype=np.int32), np.array(jj, dtype=np.int32)
+
+
+def _depth_field(cfg: SceneConfig, rng: np.random.Generator) -> np.ndarray:
+    H, W = cfg.H, cfg.W
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    u = np.stack([xs / W, ys / H], 0)
+    acc = np.zeros((H, W))
+    for _ in range(4):
+        f = rng.uniform(-2.0, 2.0, size=2)
+        f *= min(1.0, 2.0 / max(np.linalg.norm(f), 1e-12))
+        a = rng.uniform(0.6, 1.4)
+        ph = rng.uniform(0, 2 * np.pi)
+        acc += a * np.cos(2 * np.pi * (f[0] * u[0] + f[1] * u[1]) + ph)
+    return 0.2 + 1.8 / (1.0 + np.exp(-acc))
+
+
+def _project(cfg: SceneConfig, R_i, p_i, R_j, p_j, invdepth_i):
+    """Pixel coordinates in camera j of camera i's pixels back-projected at their
+    inverse depth; also the depth seen from j."""
+    H, W = cfg.H, cfg.W
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    ray = np.stack([(xs - cfg.cx) / cfg.fx, (ys - cfg.cy) / cfg.fy, np.ones_like(xs)], 0)
+    X_ci = ray / invdepth_i[None]
+    X_w = np.einsum("ab,bhw->ahw", R_i, X_ci) + p_i[:, None, None]
+    X_cj = np.einsum("ba,bhw->ahw", R_j, X_w - p_j[:, None, None])
+    z = X_cj[2]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = cfg.fx * X_cj[0] / z + cfg.cx
+        v = cfg.fy * X_cj[1] / z + cfg.cy
+    return np.stack([u, v], 0), z
+
+
+def make_problem(cfg: SceneConfig, seed: int, bias_hat_mode: str = "zero") -> Problem:
+    """Build one seeded window.
+
+    ``bias_hat_mode``: ``"zero"`` linearises every IMU factor at zero bias (the
+    solver's initial bias estimate), ``"gt"`` at the true bias.
+    """
+    rng = np.random.default_rng(seed)
+    N = cfg.n_kf
+    dt_imu = 1.0 / cfg.imu_rate
+    if cfg.gap_range is None:
+        gaps = np.full(N - 1, cfg.kf_gap, dtype=np.int64)
+    else:
+        gaps = rng.integers(cfg.gap_range[0], cfg.gap_range[1] + 1, size=N - 1)
+    kf_tick = np.concatenate([[0], np.cumsum(gaps)]).astype(np.int64)
+    n_ticks = int(kf_tick[-1])
+
+    traj = _Trajectory(rng)
+    t = np.arange(n_ticks + 1) * dt_imu
+    omega = traj.omega(t)                                   # body rate at ticks
+    acc_w = traj.acc(t)                                     # world acceleration
+
+    # biases: constant per keyframe interval, random walk between intervals
+    bias_gt = np.zeros((N, 6))
+    b0 = np.r_[rng.normal(0, cfg.bg0_std, 3), rng.normal(0, cfg.ba0_std, 3)]
+    rw = np.r_[np.full(3, cfg.sigma_bgw), np.full(3, cfg.sigma_baw)]
+    steps = rng.normal(size=(N, 6))
+    if not cfg.zero_bias:
+        bias_gt[0] = b0
+        for i in range(1, N):
+            Dt = gaps[i - 1] * dt_imu
+            bias_gt[i] = bias_gt[i - 1] + (0.0 if cfg.noiseless else 1.0) * rw * np.sqrt(Dt) * steps[i]
+
+    # discrete-consistent ground truth along the IMU ticks
+    q = np.empty((n_ticks + 1, 4))
+    v = np.empty((n_ticks + 1, 3))
+    p = np.empty((n_ticks + 1, 3))
+    f_body = np.empty((n_ticks, 3))                         # true specific force
+    q[0] = _Q0
+    v[0] = traj.vel(0.0)[0]
+    p[0] = traj.pos(0.0)[0]
+    dq = _quat_from_rotvec(omega[:-1] * dt_imu)
+    for k in range(n_ticks):
+        R = _quat_to_mat(q[k])
+        f_body[k] = R.T @ (acc_w[k] - GRAVITY)
+        Rf = R @ f_body[k]
+        v[k + 1] = v[k] + GRAVITY * dt_imu + Rf * dt_imu
+        p[k + 1] = p[k] + v[k] * dt_imu + 0.5 * GRAVITY * dt_imu ** 2 + 0.5 * Rf * dt_imu ** 2
+        qn = _qmul(q[k], dq[k])
+        q[k + 1] = qn / np.linalg.norm(qn)
+
+    # IMU measurements: truth + interval bias + white noise
+    interval = np.searchsorted(kf_tick, np.arange(n_ticks), side="right") - 1
+    gyro = omega[:-1] + bias_gt[interval, :3]
+    accel = f_body + bias_gt[interval, 3:]
+    if not cfg.noiseless:
+        gyro = gyro + rng.normal(0, cfg.sigma_g / np.sqrt(dt_imu), size=gyro.shape)
+        accel = accel + rng.normal(0, cfg.sigma_a / np.sqrt(dt_imu), size=accel.shape)
+    imu_dt = np.full(n_ticks, dt_imu)
+
+    pose_gt = np.concatenate([p[kf_tick], q[kf_tick]], axis=1)
+    vel_gt = v[kf_tick].copy()
+    R_gt = _quat_to_mat(q[kf_tick])
+
+    invdepth_gt = np.stack([_depth_field(cfg, rng) for _ in range(N)], 0)
+    ii, jj = _edge_list(cfg, rng)
+    E = ii.shape[0]
+    H, W = cfg.H, cfg.W
+    target64 = np.empty((E, 2, H, W))
+    weight = np.empty((E, 2, H, W), dtype=np.float32)
+    for e in range(E):
+        i, j = int(ii[e]), int(jj[e])
+        uv, z = _project(cfg, R_gt[i], pose_gt[i, :3], R_gt[j], pose_gt[j, :3], invdepth_gt[i])
+        ok = z > cfg.z_min
+        uv = np.where(ok[None], uv, 0.0)
+        target64[e] = uv
+        w = rng.uniform(cfg.w_lo, cfg.w_hi, size=(2, H, W))
+        weight[e] = np.where(ok[None], w, 0.0)
+    if not cfg.noiseless:
+        target64 = target64 + rng.normal(0, cfg.sigma_px, size=target64.shape)
+    target = target64.astype(np.float32)
+
+    # perturbed initial estimate (keyframe 0 keeps its true pose: it is the gauge)
+    pose0 = pose_gt.copy()
+    vel0 = vel_gt.copy()
+    if N > 1:
+        dth = np.deg2rad(cfg.init_dtheta_deg) * _unit(rng, N - 1)
+        pose0[1:, :3] += cfg.init_dp * _unit(rng, N - 1)
+        qp = _qmul(pose_gt[1:, 3:], _quat_from_rotvec(dth))
+        pose0[1:, 3:] = qp / np.linalg.norm(qp, axis=1, keepdims=True)
+        vel0 += rng.normal(0, cfg.init_dv_std, size=vel0.shape)
+    eps = np.clip(rng.normal(size=invdepth_gt.shape), -3.0, 3.0)
+    invdepth0 = invdepth_gt * (1.0 + cfg.init_depth_rel * eps)
+    bias0 = np.zeros((N, 6))
+    if bias_hat_mode == "gt":
+        bias_hat = bias_gt[:-1].copy()
+    else:
+        bias_hat = np.zeros((N - 1, 6))
+
+    return Problem(
+        cfg=cfg, seed=seed, fx=cfg.fx, fy=cfg.fy, cx=cfg.cx, cy=cfg.cy, H=H, W=W,
+        gravity=GRAVITY.copy(),
+        pose=pose0, vel=vel0, bias=bias0, invdepth=invdepth0,
+        ii=ii, jj=jj, target=target, weight=weight, target64=target64,
+        imu_off=kf_tick.astype(np.int32), gyro=gyro, accel=accel, imu_dt=imu_dt,
+        bias_hat=bias_hat,
+        noise=np.array([cfg.sigma_g, cfg.sigma_a, cfg.sigma_bgw, cfg.sigma_baw]),
+        pose_gt=pose_gt, vel_gt=vel_gt, bias_gt=bias_gt, invdepth_gt=invdepth_gt,
+        kf_tick=kf_tick, z_min=cfg.z_min,
+    )
+
+
+def tiny_config(n_kf: int = 3, H: int = 4, W: int = 5, k_out: int = 2,
+                noiseless: bool = False, zero_bias: bool = False, kf_gap: int = 20) -> SceneConfig:
+    """Tiny windows used for brute-force checks (finite differences, dense solves)."""
+    return SceneConfig(n_kf=n_kf, H=H, W=W, k_out=k_out, noiseless=noiseless,
+                       zero_bias=zero_bias, kf_gap=kf_gap)
