@@ -1,0 +1,190 @@
+"""Benchmark of the visual-inertial Gauss-Newton step on one MI355X.
+
+Workload: the 24-keyframe sliding window (60x80 inverse-depth maps, 288 edges,
+each keyframe to its 12 nearest by index, 200 Hz IMU with 20 samples per
+keyframe gap), seeded synthetic data.  One benchmark step is one whole pass of
+the hot path: IMU preintegration of the window's 23 factors, then a solve of 8
+damped Gauss-Newton iterations (each: residual/Jacobian assembly, inertial
+factors, Schur elimination of the inverse depths, FP64 Cholesky of the 360x360
+reduced system, back-substitution and retraction) and the final cost, all in
+FP64, replayed from one captured HIP graph.  Every step restarts from the same
+initial estimate (a device-to-device copy of the four state arrays, inside the
+timed region).
+
+Prints one JSON line: pixel-residuals per second (edges x pixels x iterations
+per second of wall time), ms per step and per GN iteration, the roofline
+position of the dominant kernel (per-stage GPU times from HIP events on the
+library's stream) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pixel-residuals/s + ms per GN iter (24-KF window); time-to-tol learned vs plain"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+GN_ITERS = 8
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=4, help="oracle GN iterations in the CPU sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
+    return ap.parse_args()
+
+
+def stage_models(prob):
+    """Algorithmic work of one launch of each stage (one GN iteration).
+
+    vis_imu_assemble (HBM): every pixel-residual must read its target and
+      weight once (2 + 2 float32 = 16 B); every source pixel reads its float64
+      inverse depth (8 B) and writes C and w_d (16 B).
+    gram (FP64 MFMA): the symmetric (6k+1)^2 Gram of each source pixel,
+      (6k+1)(6k+2)/2 multiply-adds = (6k+1)(6k+2) flops per pixel.
+    cholesky (FP64): n^3/3 flops for the 15N x 15N reduced system.
+    """
+    import numpy as np
+    N, E, HW = prob.n_kf, prob.n_edges, prob.H * prob.W
+    ks = np.bincount(prob.ii, minlength=N)
+    gram_flops = float(sum((6 * k + 1) * (6 * k + 2) for k in ks if k > 0)) * HW
+    n = 15 * N
+    return {
+        "vis_imu_assemble": dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, scale=1e9,
+                                 work=float(E * HW * 16 + N * HW * 24), work_name="algorithmic_bytes_per_launch",
+                                 per_unit="16 B per pixel-residual + 24 B per source pixel"),
+        "gram": dict(bound="mfma", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, scale=1e12, work=gram_flops,
+                     work_name="algorithmic_flops_per_launch", per_unit="(6k+1)(6k+2) flops per source pixel"),
+        "cholesky": dict(bound="alu", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, scale=1e12, work=n ** 3 / 3.0,
+                         work_name="algorithmic_flops_per_launch", per_unit="n^3/3 flops, n = 15 N"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU sharding is not built "
+                                   "(--gpus must be 1)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2512_02293_amd import binding, synth
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    cfg = synth.config_window()
+    prob = synth.make_problem(cfg, 2)
+    N, E, H, W = prob.n_kf, prob.n_edges, prob.H, prob.W
+    HW = H * W
+    ctx = binding.Context(0)
+    dp = binding.DeviceProblem(prob, dev)
+    opts = binding.make_opts()
+    ws = torch.empty(ctx.workspace_size(dp.cam, N, dp.ii, dp.jj, opts), dtype=torch.uint8, device=dev)
+    init = [t.clone() for t in (dp.pose, dp.vel, dp.bias, dp.invdepth)]
+    imu = torch.empty((N - 1, binding.PREINT_DOUBLES), dtype=torch.float64, device=dev)
+
+    def step():
+        for dst, src in zip((dp.pose, dp.vel, dp.bias, dp.invdepth), init):
+            dst.copy_(src)
+        ctx.imu_preintegrate(dp.off, dp.gyro, dp.accel, dp.imu_dt, dp.bias_hat, dp.noise, out=imu)
+        return ctx.solve(dp.cam, dp.pose, dp.vel, dp.bias, dp.invdepth, dp.ii, dp.jj, dp.target, dp.weight, imu,
+                         opts, GN_ITERS, ws, costs=True)
+
+    for _ in range(args.warmup):
+        rep = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rep = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    pxres_per_step = E * HW * GN_ITERS
+    value = pxres_per_step / (elapsed / args.steps)
+
+    # per-stage GPU time (HIP events on the library stream), summed over the 8 iterations
+    reps = 5
+    acc = None
+    for _ in range(reps):
+        for dst, src in zip((dp.pose, dp.vel, dp.bias, dp.invdepth), init):
+            dst.copy_(src)
+        r = ctx.solve(dp.cam, dp.pose, dp.vel, dp.bias, dp.invdepth, dp.ii, dp.jj, dp.target, dp.weight, imu, opts,
+                      GN_ITERS, ws, stage_ms=True)
+        s = r["stage_ms"]
+        acc = s if acc is None else {k: acc[k] + s[k] for k in s}
+    stage_ms = {k: v / reps for k, v in acc.items()}           # per solve
+    per_iter_ms = {k: v / GN_ITERS for k, v in stage_ms.items() if k != "final_cost"}
+    models = stage_models(prob)
+    dom = max(per_iter_ms, key=per_iter_ms.get)
+    key = dom if dom in models else max(models, key=lambda k: per_iter_ms.get(k, 0.0))
+    m = models[key]
+    achieved = m["work"] / (per_iter_ms[key] * 1e-3) / m["scale"]
+    roof = {"bound": m["bound"], "achieved": achieved, "peak": m["peak"], "unit": m["unit"],
+            "frac": achieved / m["peak"], "traffic": None, "stage": key, "dominant_stage": dom,
+            "stage_ms": per_iter_ms[key], m["work_name"]: m["work"], "per_unit": m["per_unit"]}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pixel-residuals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "ms_per_gn_iter": ms_step / GN_ITERS,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "sliding window: 24 keyframes, 60x80 inverse-depth maps, 288 edges (12 nearest "
+                               "by index), 200 Hz IMU / 10 Hz keyframes, 8 GN iterations, FP64",
+                   "n_kf": N, "n_edges": E, "H": H, "W": W, "gn_iters": GN_ITERS,
+                   "pixel_residuals_per_step": pxres_per_step, "final_cost": float(rep["cost_after"])},
+        "stage_ms_per_iter": {k: round(v, 5) for k, v in per_iter_ms.items()},
+        "roofline": roof,
+    }
+    if args.copy_calibration:
+        # a plain copy of known size: 256 MiB read + 256 MiB written per launch
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4, "launches": 3}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_iters)
+    print(json.dumps(out))
+    ctx.close()
+
+
+def cpu_baseline(prob, iters):
+    """The FP64 oracle, single-threaded, on a bounded sample of the same window."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import normal_eq as ne
+    from oracle import solve as osolve
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        cam, st, gr = osolve.from_problem(prob)        # includes the oracle's preintegration
+        st, _ = osolve.solve(cam, st, gr, ne.Options(), iters)
+        dt = time.perf_counter() - t0
+    pxres = prob.n_edges * prob.H * prob.W * iters
+    return {"value": pxres / dt, "unit": "pixel-residuals/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle preintegration + {iters} of the 8 GN iterations on the same 24-KF window "
+                      f"({dt:.1f} s, NumPy float64, 1 BLAS thread)"}
+
+
+if __name__ == "__main__":
+    main()

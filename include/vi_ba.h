@@ -1,0 +1,201 @@
+/*
+ * vi_ba.h - C ABI of the MI355X (gfx950) visual-inertial bundle-adjustment step.
+ *
+ * The library computes one damped Gauss-Newton (fixed-damping Levenberg-
+ * Marquardt) step, or a fixed number of them, of the joint visual-inertial
+ * problem of VIGS-SLAM, Sec. 3.1: keyframe poses, per-pixel inverse depths,
+ * velocities and gyro/accel biases minimise the sum of the vision energy of
+ * Eq. 1 and the inertial energy of Eq. 2-3; the normal equations are reduced
+ * by eliminating the (diagonal) inverse-depth block as in Eq. 4 and the
+ * reduced pose/velocity/bias system is solved by an FP64 Cholesky.  IMU
+ * measurements between consecutive keyframes are preintegrated first
+ * (Sec. 3.1, "Inertial Residual").
+ *
+ * Conventions used throughout:
+ *   - pose of keyframe i: world-from-body (R_i, p_i), stored as 7 doubles
+ *     (px, py, pz, qx, qy, qz, qw), unit quaternion, Hamilton product;
+ *   - the camera frame equals the body frame (identity extrinsics);
+ *   - per-keyframe tangent (15): (dtheta, dp, dv, db_g, db_a) with the
+ *     right perturbation R <- R Exp(dtheta) and additive world-frame p, v and
+ *     additive biases; bias = (b_g, b_a);
+ *   - edge (i, j): pixels of source keyframe i, whose inverse depth the edge
+ *     uses, are projected into target keyframe j.  Pixel (x, y) is (column,
+ *     row) at integer coordinates;
+ *   - vision cost of a pixel: w_x r_x^2 + w_y r_y^2 with r = target - projection
+ *     (weights are information); a pixel-residual counts only when its inverse
+ *     depth is positive and the point lies more than z_min in front of camera j;
+ *   - inertial factor (i, i+1) uses the bias of keyframe i; its velocity term
+ *     uses the full 6-vector bias; information = blkdiag(cov, diag(cov_bias))^-1;
+ *   - cost F = sum_vision w r^2 + sum_imu r^T Lambda r (no 1/2 factor);
+ *   - damping: B_rr += lm_lambda * B_rr on every solved pose/velocity/bias
+ *     coordinate and C += depth_eta, before elimination, so the step is the
+ *     exact solution of the damped full system; 0/0 gives pure Gauss-Newton;
+ *   - gauge: the pose coordinates of keyframes 0..n_fixed-1 are not solved.
+ *
+ * Memory: every array is owned by the caller.  Pointers documented "device"
+ * are HIP device pointers on the context's device; "host" pointers are read
+ * during the call only.  The library never frees caller memory.  The context
+ * owns only its stream handle, index tables uploaded from host inputs, captured
+ * graphs and a few bytes of status memory.
+ *
+ * Errors: every function returns a vi_status and never aborts.  On error the
+ * caller's state arrays are unchanged by the failing step (increments are
+ * committed only by the last kernel of a step, which is skipped when an earlier
+ * kernel raised an error), and vi_last_error() describes the failure.
+ * A context must not be used from two threads at once.
+ */
+#ifndef VI_BA_H
+#define VI_BA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VI_OK = 0,
+  VI_EINVAL = -1,        /* bad argument (checked on the host before any launch) */
+  VI_ENOMEM = -2,        /* workspace too small or device allocation failed */
+  VI_EDEVICE = -3,       /* HIP runtime error */
+  VI_ENOTPD = -4,        /* reduced system not positive definite (pivot <= 0) */
+  VI_ENONFINITE = -5,    /* non-finite value in the assembled system */
+  VI_EUNSUPPORTED = -6   /* option combination not implemented */
+} vi_status;
+
+typedef struct vi_ctx vi_ctx;
+
+/* Create a context bound to HIP device `device` and stream `stream` (a
+ * hipStream_t, or NULL for the null stream).  Writes the handle to *out. */
+vi_status vi_ctx_create(int32_t device, void* stream, vi_ctx** out);
+/* Destroy a context (waits for its stream).  NULL is accepted. */
+void vi_ctx_destroy(vi_ctx* ctx);
+/* Change the stream later calls enqueue on. */
+vi_status vi_ctx_set_stream(vi_ctx* ctx, void* stream);
+/* Message describing the last failing call on this context ("" if none). */
+const char* vi_last_error(const vi_ctx* ctx);
+/* Library version string. */
+const char* vi_version(void);
+
+typedef struct {
+  double fx, fy, cx, cy;     /* pinhole intrinsics, pixels */
+  int32_t H, W;              /* inverse-depth map rows and columns */
+  double gravity[3];         /* world gravity vector g (Eq. 3), e.g. {0, 0, -9.81} */
+} vi_camera;
+
+typedef struct {
+  double sigma_g;            /* gyro white-noise density, rad/s/sqrt(Hz) */
+  double sigma_a;            /* accel white-noise density, m/s^2/sqrt(Hz) */
+  double sigma_bgw;          /* gyro bias random walk, rad/s^2/sqrt(Hz) */
+  double sigma_baw;          /* accel bias random walk, m/s^3/sqrt(Hz) */
+} vi_imu_noise;
+
+/* One preintegrated IMU factor (Sec. 3.1: "relative rotation, position and
+ * velocity, their Jacobians and covariance").  154 doubles, row-major. */
+typedef struct {
+  double dt;                 /* Delta t_ij, seconds */
+  double dR[9];              /* Delta R_ij */
+  double dv[3];              /* Delta v_ij */
+  double dp[3];              /* Delta p_ij */
+  double J_rot[9];           /* d(Delta R)/d(b_g), right-perturbation form */
+  double J_vel[18];          /* 3x6 d(Delta v)/d(b_g, b_a) */
+  double J_pos[18];          /* 3x6 d(Delta p)/d(b_g, b_a) */
+  double cov[81];            /* 9x9 covariance, order (rot, pos, vel) as in Eq. 3 */
+  double bias_hat[6];        /* bias the factor was integrated at */
+  double cov_bias[6];        /* bias random-walk variances over Delta t_ij */
+} vi_preint;
+
+/* Preintegrate IMU samples into n_factors factors (Sec. 3.1, following Forster
+ * et al.; zero-order hold per sample: Delta R <- Delta R Exp((w - b_g) dt),
+ * velocity and position by the constant-acceleration update, white-noise
+ * covariance sigma^2/dt per sample).
+ *   off      host   [n_factors+1]  CSR: factor f uses samples off[f]..off[f+1]-1;
+ *                                  off[0] = 0, non-decreasing, >= 1 sample each
+ *   gyro     device [S][3]  angular rate, rad/s, body frame
+ *   accel    device [S][3]  specific force, m/s^2, body frame
+ *   dt       device [S]     duration each sample is held, s (> 0)
+ *   bias_hat device [n_factors][6] (b_g, b_a) linearisation point per factor
+ *   out      device [n_factors]
+ * Synchronous.  VI_EINVAL for a malformed CSR or a non-positive dt. */
+vi_status imu_preintegrate(vi_ctx* ctx, int32_t n_factors, const int32_t* off,
+                           const double* gyro, const double* accel, const double* dt,
+                           const double* bias_hat, const vi_imu_noise* noise,
+                           vi_preint* out);
+
+/* Estimate, updated in place by a step. */
+typedef struct {
+  int32_t n_kf;              /* N >= 2 keyframes */
+  double* pose;              /* device [N][7] (p, q xyzw) */
+  double* vel;               /* device [N][3] world frame */
+  double* bias;              /* device [N][6] (b_g, b_a) */
+  double* invdepth;          /* device [N][H][W] inverse depth (float64) */
+} vi_state;
+
+/* Frame graph: directed co-visible pairs and their correspondence targets
+ * (Eq. 1: u*_ij and the confidence w_ij). */
+typedef struct {
+  int32_t n_edges;           /* E >= 1 */
+  const int32_t* ii;         /* host [E] source keyframe (its inverse depth is used) */
+  const int32_t* jj;         /* host [E] target keyframe, jj != ii, no duplicate pairs */
+  const float* target;       /* device [E][2][H][W] target pixel x (plane 0), y (plane 1) */
+  const float* weight;       /* device [E][2][H][W] weights >= 0, per coordinate */
+} vi_edges;
+
+typedef struct {
+  int32_t n_fixed;           /* gauge: leading keyframes whose pose is held (>= 1 typical) */
+  int32_t use_imu;           /* 0: vision only (velocity and bias are not solved) */
+  int32_t bias_fixed;        /* 1: biases are not solved */
+  int32_t reserved;          /* must be 0 */
+  double lm_lambda;          /* Marquardt factor on the pose/vel/bias diagonal (>= 0) */
+  double depth_eta;          /* added to the inverse-depth diagonal C (>= 0) */
+  double z_min;              /* minimum depth in the target camera, m */
+  double d_min;              /* inverse depth is clamped to >= d_min after a step */
+} vi_opts;
+
+/* Stages reported by vi_report.stage_ms, in launch order:
+ *  0 vision residual/Jacobian assembly with the inertial factors (one launch)
+ *  1 Schur Gram (MFMA)         2 per-source local blocks and cost reduction
+ *  3 reduced-system assembly   4 Cholesky factor and solves
+ *  5 back-substitution and retraction
+ *  6 final cost evaluation */
+#define VI_NUM_STAGES 7
+
+typedef struct {
+  double cost_before;        /* F at the input state of the (last) step */
+  double cost_after;         /* F at the output state */
+  int64_t n_valid;           /* valid pixel-residuals at the (last) linearisation point */
+  int32_t iters_done;        /* steps applied */
+  int32_t reserved;
+  double* dxi;               /* optional device [N][15]: increments of the last step */
+  double* dd;                /* optional device [N][H][W]: depth increments of the last step */
+  double* costs;             /* optional host [iters+1]: F before each step, then final F */
+  float* stage_ms;           /* optional host [VI_NUM_STAGES]: when set, the call runs without a
+                                graph and returns the GPU time of each stage (HIP events on the
+                                library's stream), summed over the steps */
+} vi_report;
+
+/* Device workspace (bytes) needed by vi_ba_step / vi_ba_solve for this shape. */
+size_t vi_workspace_size(const vi_camera* cam, int32_t n_kf, const vi_edges* edges,
+                         const vi_opts* opts);
+
+/* One damped Gauss-Newton step (Eq. 4), in place on *state.
+ *   imu        device [N-1] factors for pairs (i, i+1); may be NULL iff !use_imu
+ *   workspace  device, >= vi_workspace_size() bytes, 256-byte aligned
+ * Synchronous (the report is filled on return). */
+vi_status vi_ba_step(vi_ctx* ctx, const vi_camera* cam, vi_state* state, const vi_edges* edges,
+                     const vi_preint* imu, const vi_opts* opts, void* workspace,
+                     size_t workspace_bytes, vi_report* report);
+
+/* `iters` steps (Sec. 3.1: the local bundle adjustment iterates the LM step),
+ * captured once per shape into a HIP graph and replayed.  On error at step t the
+ * state holds the result of steps 0..t-1 and report->iters_done = t. */
+vi_status vi_ba_solve(vi_ctx* ctx, const vi_camera* cam, vi_state* state, const vi_edges* edges,
+                      const vi_preint* imu, const vi_opts* opts, int32_t iters,
+                      void* workspace, size_t workspace_bytes, vi_report* report);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VI_BA_H */

@@ -1,0 +1,261 @@
+"""Thin ctypes binding of the HIP library (include/vi_ba.h).
+
+Argument marshalling only: device arrays are torch tensors on the GPU (their
+data pointers are passed through), host arrays are NumPy, and every step of
+the computation runs in the library's HIP kernels.  Loading fails loudly when
+the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from ._build import LIB_PATH
+
+VI_OK, VI_EINVAL, VI_ENOMEM, VI_EDEVICE, VI_ENOTPD, VI_ENONFINITE, VI_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "VI_OK", -1: "VI_EINVAL", -2: "VI_ENOMEM", -3: "VI_EDEVICE", -4: "VI_ENOTPD",
+                -5: "VI_ENONFINITE", -6: "VI_EUNSUPPORTED"}
+NUM_STAGES = 7
+STAGE_NAMES = ["vis_imu_assemble", "gram", "local", "assemble", "cholesky", "backsub_retract", "final_cost"]
+PREINT_DOUBLES = 154
+
+
+class ViError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Camera(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("H", C.c_int32), ("W", C.c_int32), ("gravity", C.c_double * 3)]
+
+
+class ImuNoise(C.Structure):
+    _fields_ = [("sigma_g", C.c_double), ("sigma_a", C.c_double), ("sigma_bgw", C.c_double),
+                ("sigma_baw", C.c_double)]
+
+
+class State(C.Structure):
+    _fields_ = [("n_kf", C.c_int32), ("pose", C.c_void_p), ("vel", C.c_void_p), ("bias", C.c_void_p),
+                ("invdepth", C.c_void_p)]
+
+
+class Edges(C.Structure):
+    _fields_ = [("n_edges", C.c_int32), ("ii", C.c_void_p), ("jj", C.c_void_p), ("target", C.c_void_p),
+                ("weight", C.c_void_p)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("n_fixed", C.c_int32), ("use_imu", C.c_int32), ("bias_fixed", C.c_int32),
+                ("reserved", C.c_int32), ("lm_lambda", C.c_double), ("depth_eta", C.c_double),
+                ("z_min", C.c_double), ("d_min", C.c_double)]
+
+
+class Report(C.Structure):
+    _fields_ = [("cost_before", C.c_double), ("cost_after", C.c_double), ("n_valid", C.c_int64),
+                ("iters_done", C.c_int32), ("reserved", C.c_int32), ("dxi", C.c_void_p), ("dd", C.c_void_p),
+                ("costs", C.c_void_p), ("stage_ms", C.c_void_p)]
+
+
+EXPORTS = ["vi_ctx_create", "vi_ctx_destroy", "vi_ctx_set_stream", "vi_last_error", "vi_version",
+           "imu_preintegrate", "vi_workspace_size", "vi_ba_step", "vi_ba_solve"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the built library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    lib.vi_ctx_create.argtypes = [C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+    lib.vi_ctx_create.restype = C.c_int
+    lib.vi_ctx_destroy.argtypes = [C.c_void_p]
+    lib.vi_ctx_destroy.restype = None
+    lib.vi_ctx_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+    lib.vi_ctx_set_stream.restype = C.c_int
+    lib.vi_last_error.argtypes = [C.c_void_p]
+    lib.vi_last_error.restype = C.c_char_p
+    lib.vi_version.argtypes = []
+    lib.vi_version.restype = C.c_char_p
+    lib.imu_preintegrate.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.POINTER(ImuNoise), C.c_void_p]
+    lib.imu_preintegrate.restype = C.c_int
+    lib.vi_workspace_size.argtypes = [C.POINTER(Camera), C.c_int32, C.POINTER(Edges), C.POINTER(Opts)]
+    lib.vi_workspace_size.restype = C.c_size_t
+    lib.vi_ba_step.argtypes = [C.c_void_p, C.POINTER(Camera), C.POINTER(State), C.POINTER(Edges), C.c_void_p,
+                               C.POINTER(Opts), C.c_void_p, C.c_size_t, C.POINTER(Report)]
+    lib.vi_ba_step.restype = C.c_int
+    lib.vi_ba_solve.argtypes = [C.c_void_p, C.POINTER(Camera), C.POINTER(State), C.POINTER(Edges), C.c_void_p,
+                                C.POINTER(Opts), C.c_int32, C.c_void_p, C.c_size_t, C.POINTER(Report)]
+    lib.vi_ba_solve.restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_dev(t, shape, dtype, name, min_rows=None):
+    """Device tensor of the given dtype, contiguous, with the given shape
+    (None = any extent)."""
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name}: expected a contiguous {dtype} GPU tensor")
+    if len(t.shape) != len(shape) or any(s is not None and int(a) != s for a, s in zip(t.shape, shape)):
+        raise ValueError(f"{name}: shape {tuple(t.shape)} does not match {shape}")
+    if min_rows is not None and int(t.shape[0]) < min_rows:
+        raise ValueError(f"{name}: {int(t.shape[0])} rows, {min_rows} needed")
+
+
+def make_camera(fx, fy, cx, cy, H, W, gravity=(0.0, 0.0, -9.81)) -> Camera:
+    return Camera(fx, fy, cx, cy, H, W, (C.c_double * 3)(*gravity))
+
+
+def make_opts(n_fixed=1, use_imu=True, bias_fixed=False, lm_lambda=1e-4, depth_eta=1e-8, z_min=0.1,
+              d_min=1e-3) -> Opts:
+    return Opts(n_fixed, int(bool(use_imu)), int(bool(bias_fixed)), 0, lm_lambda, depth_eta, z_min, d_min)
+
+
+class Context:
+    """A library context bound to one device and torch's current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.lib = load()
+        self.torch = torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        rc = self.lib.vi_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h))
+        if rc != VI_OK:
+            raise ViError(rc, "vi_ctx_create failed")
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.vi_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != VI_OK:
+            raise ViError(rc, self.lib.vi_last_error(self.h).decode())
+
+    def last_error(self) -> str:
+        return self.lib.vi_last_error(self.h).decode()
+
+    # -- preintegration ------------------------------------------------------
+    def imu_preintegrate(self, off: np.ndarray, gyro, accel, dt, bias_hat, noise, out=None):
+        """Returns a (F, 154) float64 device tensor of vi_preint records."""
+        torch = self.torch
+        off = np.ascontiguousarray(off, dtype=np.int32)
+        F = off.shape[0] - 1
+        S = int(off[-1]) if F >= 0 else 0
+        _check_dev(gyro, (None, 3), torch.float64, "gyro", min_rows=S)
+        _check_dev(accel, (None, 3), torch.float64, "accel", min_rows=S)
+        _check_dev(dt, (None,), torch.float64, "dt", min_rows=S)
+        _check_dev(bias_hat, (max(F, 0), 6), torch.float64, "bias_hat")
+        if out is None:
+            out = torch.empty((F, PREINT_DOUBLES), dtype=torch.float64, device=gyro.device)
+        nz = ImuNoise(*[float(x) for x in noise])
+        rc = self.lib.imu_preintegrate(self.h, F, off.ctypes.data_as(C.c_void_p), _ptr(gyro), _ptr(accel),
+                                       _ptr(dt), _ptr(bias_hat), C.byref(nz), _ptr(out))
+        self._check(rc)
+        return out
+
+    # -- BA ------------------------------------------------------------------
+    def workspace_size(self, cam: Camera, n_kf: int, ii: np.ndarray, jj: np.ndarray, opts: Opts) -> int:
+        ed = Edges(int(ii.shape[0]), ii.ctypes.data_as(C.c_void_p), jj.ctypes.data_as(C.c_void_p), None, None)
+        return int(self.lib.vi_workspace_size(C.byref(cam), n_kf, C.byref(ed), C.byref(opts)))
+
+    def solve(self, cam: Camera, pose, vel, bias, invdepth, ii: np.ndarray, jj: np.ndarray, target, weight,
+              imu, opts: Opts, iters: int, workspace, dxi=None, dd=None, costs: bool = False,
+              stage_ms: bool = False):
+        """Run ``iters`` steps in place.  Returns a dict report."""
+        torch = self.torch
+        ii = np.ascontiguousarray(ii, dtype=np.int32)
+        jj = np.ascontiguousarray(jj, dtype=np.int32)
+        N, E, H, W = int(pose.shape[0]), int(ii.shape[0]), int(cam.H), int(cam.W)
+        if jj.shape != ii.shape:
+            raise ValueError("ii and jj differ in length")
+        _check_dev(pose, (N, 7), torch.float64, "pose")
+        _check_dev(vel, (N, 3), torch.float64, "vel")
+        _check_dev(bias, (N, 6), torch.float64, "bias")
+        _check_dev(invdepth, (N, H, W), torch.float64, "invdepth")
+        _check_dev(target, (E, 2, H, W), torch.float32, "target")
+        _check_dev(weight, (E, 2, H, W), torch.float32, "weight")
+        if imu is not None:
+            _check_dev(imu, (N - 1, PREINT_DOUBLES), torch.float64, "imu")
+        if dxi is not None:
+            _check_dev(dxi, (N, 15), torch.float64, "dxi")
+        if dd is not None:
+            _check_dev(dd, (N, H, W), torch.float64, "dd")
+        _check_dev(workspace, (None,), torch.uint8, "workspace")
+        st = State(int(pose.shape[0]), _ptr(pose), _ptr(vel), _ptr(bias), _ptr(invdepth))
+        ed = Edges(int(ii.shape[0]), ii.ctypes.data_as(C.c_void_p), jj.ctypes.data_as(C.c_void_p),
+                   _ptr(target), _ptr(weight))
+        cost_arr = np.zeros(iters + 1) if costs else None
+        stage_arr = np.zeros(NUM_STAGES, dtype=np.float32) if stage_ms else None
+        rep = Report(0.0, 0.0, 0, 0, 0, _ptr(dxi), _ptr(dd),
+                     cost_arr.ctypes.data_as(C.c_void_p) if costs else None,
+                     stage_arr.ctypes.data_as(C.c_void_p) if stage_ms else None)
+        nbytes = workspace.numel() * workspace.element_size()
+        if iters == 1 and not costs and not stage_ms:
+            rc = self.lib.vi_ba_step(self.h, C.byref(cam), C.byref(st), C.byref(ed), _ptr(imu), C.byref(opts),
+                                     _ptr(workspace), nbytes, C.byref(rep))
+        else:
+            rc = self.lib.vi_ba_solve(self.h, C.byref(cam), C.byref(st), C.byref(ed), _ptr(imu), C.byref(opts),
+                                      iters, _ptr(workspace), nbytes, C.byref(rep))
+        out = dict(cost_before=rep.cost_before, cost_after=rep.cost_after, n_valid=int(rep.n_valid),
+                   iters_done=int(rep.iters_done), status=rc)
+        if costs:
+            out["costs"] = cost_arr
+        if stage_ms:
+            out["stage_ms"] = dict(zip(STAGE_NAMES, stage_arr.tolist()))
+        self._check(rc)
+        return out
+
+
+class DeviceProblem:
+    """A synthetic problem's arrays moved to the GPU (inputs resident in HBM)."""
+
+    def __init__(self, prob, device="cuda:0"):
+        import torch
+        self.prob = prob
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
+        self.pose = t(prob.pose, torch.float64)
+        self.vel = t(prob.vel, torch.float64)
+        self.bias = t(prob.bias, torch.float64)
+        self.invdepth = t(prob.invdepth, torch.float64)
+        self.target = t(prob.target, torch.float32)
+        self.weight = t(prob.weight, torch.float32)
+        self.gyro = t(prob.gyro, torch.float64)
+        self.accel = t(prob.accel, torch.float64)
+        self.imu_dt = t(prob.imu_dt, torch.float64)
+        self.bias_hat = t(prob.bias_hat, torch.float64)
+        self.ii = np.ascontiguousarray(prob.ii, dtype=np.int32)
+        self.jj = np.ascontiguousarray(prob.jj, dtype=np.int32)
+        self.off = np.ascontiguousarray(prob.imu_off, dtype=np.int32)
+        self.cam = make_camera(prob.fx, prob.fy, prob.cx, prob.cy, prob.H, prob.W, tuple(prob.gravity))
+        self.noise = tuple(float(x) for x in prob.noise)
+
+    def reset_state(self):
+        import torch
+        p = self.prob
+        self.pose.copy_(torch.as_tensor(p.pose))
+        self.vel.copy_(torch.as_tensor(p.vel))
+        self.bias.copy_(torch.as_tensor(p.bias))
+        self.invdepth.copy_(torch.as_tensor(p.invdepth))

@@ -1,0 +1,244 @@
+// IMU preintegration between consecutive keyframes (Sec. 3.1, "Inertial
+// Residual": relative rotation, velocity and position, their bias Jacobians
+// and covariance, following Forster et al.) and the per-factor information
+// matrix used by the inertial residual of Eq. 2-3.
+//
+// One 64-lane workgroup per factor.  The sample loop is inherently serial; the
+// lanes share each sample's work: the 63 mean/Jacobian entries and the 81
+// covariance entries are updated in parallel, with the transition matrix A of
+// the (rot, vel, pos) error state built in LDS.
+#include "vi_internal.h"
+#include "vi_math.h"
+
+namespace vi {
+
+namespace {
+
+__device__ __forceinline__ void set_status(DevStatus* st, int code, int detail) {
+  if (atomicCAS(&st->code, 0, code) == 0) st->detail = detail;
+}
+
+// LDS layout of one factor's running state
+struct PreintLds {
+  double dR[9], dv[3], dp[3], JR[9], Jvg[9], Jva[9], Jpg[9], Jpa[9];
+  double nR[9], nv[3], np_[3], nJR[9], nJvg[9], nJva[9], nJpg[9], nJpa[9];
+  double dRk[9], Jrk[9], Ra[3], M1[9];   // per-sample: Exp(w h), Jr(w h), dR a, dR [a]x
+  double M1JR[9];
+  double A[81], Qn[81], T[81], cov[81];
+};
+
+__global__ void __launch_bounds__(64) k_preint(int F, const int32_t* __restrict__ off,
+                                               const double* __restrict__ gyro,
+                                               const double* __restrict__ accel,
+                                               const double* __restrict__ dt,
+                                               const double* __restrict__ bias_hat,
+                                               vi_imu_noise noise, vi_preint* __restrict__ out,
+                                               DevStatus* st) {
+  __shared__ PreintLds S;
+  const int f = blockIdx.x;
+  const int l = threadIdx.x;
+  if (f >= F) return;
+  const int s0 = off[f], s1 = off[f + 1];
+  const double bg0 = bias_hat[f * 6 + 0], bg1 = bias_hat[f * 6 + 1], bg2 = bias_hat[f * 6 + 2];
+  const double ba0 = bias_hat[f * 6 + 3], ba1 = bias_hat[f * 6 + 4], ba2 = bias_hat[f * 6 + 5];
+  const double sg2 = noise.sigma_g * noise.sigma_g, sa2 = noise.sigma_a * noise.sigma_a;
+
+  if (l < 9) {
+    S.dR[l] = (l % 4 == 0) ? 1.0 : 0.0;
+    S.JR[l] = 0.0; S.Jvg[l] = 0.0; S.Jva[l] = 0.0; S.Jpg[l] = 0.0; S.Jpa[l] = 0.0;
+  }
+  if (l < 3) { S.dv[l] = 0.0; S.dp[l] = 0.0; }
+  for (int e = l; e < 81; e += 64) S.cov[e] = 0.0;
+  double total = 0.0;
+  __syncthreads();
+
+  for (int s = s0; s < s1; ++s) {
+    const double h = dt[s];
+    if (!(h > 0.0) || !isfinite(h)) {
+      if (l == 0) set_status(st, VI_EINVAL, s);
+    }
+    total += h;
+    const double w[3] = {(gyro[s * 3 + 0] - bg0) * h, (gyro[s * 3 + 1] - bg1) * h, (gyro[s * 3 + 2] - bg2) * h};
+    const double a[3] = {accel[s * 3 + 0] - ba0, accel[s * 3 + 1] - ba1, accel[s * 3 + 2] - ba2};
+    // phase 1: per-sample matrices (one lane each group)
+    if (l == 0) {
+      so3_exp(w, S.dRk);
+      so3_jr(w, S.Jrk);
+    } else if (l == 1) {
+      double Ra[3], ax[9], M1[9];
+      m3_vec(S.dR, a, Ra);
+      skew(a, ax);
+      m3_mul(S.dR, ax, M1);
+      for (int k = 0; k < 3; ++k) S.Ra[k] = Ra[k];
+      for (int k = 0; k < 9; ++k) S.M1[k] = M1[k];
+    }
+    __syncthreads();
+    // phase 2: transition A, noise Qn, and M1 * J^rot
+    for (int e = l; e < 81; e += 64) {
+      const int r = e / 9, c = e % 9, br = r / 3, bc = c / 3, rr = r % 3, cc = c % 3;
+      double v = 0.0;
+      if (br == 0 && bc == 0) v = S.dRk[cc * 3 + rr];                       // dRk^T
+      else if (br == 1 && bc == 0) v = -S.M1[rr * 3 + cc] * h;               // -dR [a]x h
+      else if (br == 2 && bc == 0) v = -0.5 * S.M1[rr * 3 + cc] * h * h;    // -1/2 dR [a]x h^2
+      else if (br == 2 && bc == 1) v = (rr == cc) ? h : 0.0;                 // I h
+      else if (br == bc) v = (rr == cc) ? 1.0 : 0.0;
+      S.A[e] = v;
+      // noise: Bg (sg^2/h) Bg^T with Bg = [Jr h; 0; 0]; Ba (sa^2/h) Ba^T with
+      // Ba = [0; dR h; 1/2 dR h^2] and dR dR^T = I
+      double q = 0.0;
+      if (br == 0 && bc == 0) {
+        double jj = 0.0;
+        for (int m = 0; m < 3; ++m) jj += S.Jrk[rr * 3 + m] * S.Jrk[cc * 3 + m];
+        q = sg2 * h * jj;
+      } else if (br >= 1 && bc >= 1 && rr == cc) {
+        const double fr = (br == 1) ? h : 0.5 * h * h;
+        const double fc = (bc == 1) ? h : 0.5 * h * h;
+        q = sa2 / h * fr * fc;
+      }
+      S.Qn[e] = q;
+    }
+    if (l < 9) {
+      const int r = l / 3, c = l % 3;
+      double v = 0.0;
+      for (int m = 0; m < 3; ++m) v += S.M1[r * 3 + m] * S.JR[m * 3 + c];
+      S.M1JR[l] = v;
+    }
+    __syncthreads();
+    // phase 3: T = A cov, and the new mean / Jacobians (old values on the right)
+    for (int e = l; e < 81; e += 64) {
+      const int r = e / 9, c = e % 9;
+      double v = 0.0;
+      for (int m = 0; m < 9; ++m) v += S.A[r * 9 + m] * S.cov[m * 9 + c];
+      S.T[e] = v;
+    }
+    if (l < 9) {
+      const int r = l / 3, c = l % 3;
+      const double hh = h * h;
+      S.nJpa[l] = S.Jpa[l] + S.Jva[l] * h - 0.5 * S.dR[l] * hh;
+      S.nJpg[l] = S.Jpg[l] + S.Jvg[l] * h - 0.5 * S.M1JR[l] * hh;
+      S.nJva[l] = S.Jva[l] - S.dR[l] * h;
+      S.nJvg[l] = S.Jvg[l] - S.M1JR[l] * h;
+      double v = 0.0, u = 0.0;
+      for (int m = 0; m < 3; ++m) {
+        v += S.dRk[m * 3 + r] * S.JR[m * 3 + c];     // dRk^T J^rot
+        u += S.dR[r * 3 + m] * S.dRk[m * 3 + c];     // dR dRk
+      }
+      S.nJR[l] = v - S.Jrk[l] * h;
+      S.nR[l] = u;
+    } else if (l >= 16 && l < 19) {
+      const int i = l - 16;
+      S.np_[i] = S.dp[i] + S.dv[i] * h + 0.5 * S.Ra[i] * h * h;
+      S.nv[i] = S.dv[i] + S.Ra[i] * h;
+    }
+    __syncthreads();
+    // phase 4: cov = T A^T + Qn; commit the mean
+    for (int e = l; e < 81; e += 64) {
+      const int r = e / 9, c = e % 9;
+      double v = 0.0;
+      for (int m = 0; m < 9; ++m) v += S.T[r * 9 + m] * S.A[c * 9 + m];
+      S.cov[e] = v + S.Qn[e];
+    }
+    if (l < 9) {
+      S.dR[l] = S.nR[l]; S.JR[l] = S.nJR[l];
+      S.Jvg[l] = S.nJvg[l]; S.Jva[l] = S.nJva[l]; S.Jpg[l] = S.nJpg[l]; S.Jpa[l] = S.nJpa[l];
+    } else if (l >= 16 && l < 19) {
+      S.dp[l - 16] = S.np_[l - 16];
+      S.dv[l - 16] = S.nv[l - 16];
+    }
+    __syncthreads();
+  }
+
+  vi_preint* o = out + f;
+  if (l == 0) o->dt = total;
+  if (l < 9) {
+    o->dR[l] = S.dR[l];
+    o->J_rot[l] = S.JR[l];
+    const int r = l / 3, c = l % 3;
+    o->J_vel[r * 6 + c] = S.Jvg[l];
+    o->J_vel[r * 6 + 3 + c] = S.Jva[l];
+    o->J_pos[r * 6 + c] = S.Jpg[l];
+    o->J_pos[r * 6 + 3 + c] = S.Jpa[l];
+  }
+  if (l < 3) { o->dv[l] = S.dv[l]; o->dp[l] = S.dp[l]; }
+  // internal (rot, vel, pos) -> residual order (rot, pos, vel)
+  for (int e = l; e < 81; e += 64) {
+    const int r = e / 9, c = e % 9;
+    const int pr = (r < 3) ? r : (r < 6 ? r + 3 : r - 3);
+    const int pc = (c < 3) ? c : (c < 6 ? c + 3 : c - 3);
+    o->cov[e] = S.cov[pr * 9 + pc];
+  }
+  if (l < 6) {
+    o->bias_hat[l] = bias_hat[f * 6 + l];
+    const double sw = (l < 3) ? noise.sigma_bgw : noise.sigma_baw;
+    o->cov_bias[l] = sw * sw * total;
+  }
+}
+
+// Lambda = blkdiag(cov^-1, diag(1 / cov_bias)) per factor.  The 9x9 inverse
+// goes through a Cholesky factor in LDS (one lane per column of the inverse).
+__global__ void __launch_bounds__(64) k_imu_info(int F, const vi_preint* __restrict__ imu,
+                                                 double* __restrict__ Lam, DevStatus* st) {
+  __shared__ double C[81];
+  __shared__ double Li[81];     // L^-1
+  const int f = blockIdx.x;
+  const int l = threadIdx.x;
+  if (f >= F) return;
+  const vi_preint* P = imu + f;
+  for (int e = l; e < 81; e += 64) C[e] = P->cov[e];
+  __syncthreads();
+  if (l == 0) {
+    // in-place lower Cholesky
+    bool ok = true;
+    for (int k = 0; k < 9; ++k) {
+      double d = C[k * 9 + k];
+      for (int m = 0; m < k; ++m) d -= C[k * 9 + m] * C[k * 9 + m];
+      if (!(d > 0.0)) { ok = false; d = 1.0; }
+      d = sqrt(d);
+      C[k * 9 + k] = d;
+      for (int i = k + 1; i < 9; ++i) {
+        double v = C[i * 9 + k];
+        for (int m = 0; m < k; ++m) v -= C[i * 9 + m] * C[k * 9 + m];
+        C[i * 9 + k] = v / d;
+      }
+    }
+    if (!ok) set_status(st, VI_ENOTPD, -1 - f);
+  }
+  __syncthreads();
+  if (l < 9) {
+    // column l of L^-1 by forward substitution
+    for (int r = 0; r < 9; ++r) {
+      double v = (r == l) ? 1.0 : 0.0;
+      for (int m = l; m < r; ++m) v -= C[r * 9 + m] * Li[m * 9 + l];
+      Li[r * 9 + l] = (r < l) ? 0.0 : v / C[r * 9 + r];
+    }
+  }
+  __syncthreads();
+  double* o = Lam + (size_t)f * 225;
+  for (int e = l; e < 225; e += 64) {
+    const int r = e / 15, c = e % 15;
+    double v = 0.0;
+    if (r < 9 && c < 9) {
+      // (L^-T L^-1)[r][c] = sum_m Li[m][r] Li[m][c]
+      for (int m = 0; m < 9; ++m) v += Li[m * 9 + r] * Li[m * 9 + c];
+    } else if (r == c) {
+      v = 1.0 / P->cov_bias[r - 9];
+    }
+    o[e] = v;
+  }
+}
+
+}  // namespace
+
+void launch_preint(hipStream_t s, int F, const int32_t* off, const double* gyro, const double* accel,
+                   const double* dt, const double* bias_hat, vi_imu_noise noise, vi_preint* out,
+                   DevStatus* st) {
+  if (F <= 0) return;
+  hipLaunchKernelGGL(k_preint, dim3(F), dim3(64), 0, s, F, off, gyro, accel, dt, bias_hat, noise, out, st);
+}
+
+void launch_imu_info(hipStream_t s, int F, const vi_preint* imu, double* Lam, DevStatus* st) {
+  if (F <= 0) return;
+  hipLaunchKernelGGL(k_imu_info, dim3(F), dim3(64), 0, s, F, imu, Lam, st);
+}
+
+}  // namespace vi

@@ -1,0 +1,95 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, and the ctypes structures match the C layouts (no GPU call)."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2512_02293_amd import binding
+from paper_2512_02293_amd._build import LIB_PATH
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vi_ba.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s+([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_built_and_exports_declared_symbols():
+    assert os.path.exists(LIB_PATH), "run __graft_entry__.build() first"
+    lib = C.CDLL(LIB_PATH)
+    names = _declared_functions()
+    assert len(names) >= 9, names
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in vi_ba.h but not exported"
+    assert set(binding.EXPORTS) == set(names)
+
+
+def test_struct_layouts_match_c():
+    src = r"""
+    #include <stdio.h>
+    #include <stddef.h>
+    #include "vi_ba.h"
+    #define P(T) printf(#T " %zu\n", sizeof(T));
+    #define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+    int main(void) {
+      P(vi_camera) P(vi_imu_noise) P(vi_preint) P(vi_state) P(vi_edges) P(vi_opts) P(vi_report)
+      O(vi_camera, H) O(vi_camera, gravity) O(vi_preint, cov) O(vi_preint, cov_bias)
+      O(vi_state, invdepth) O(vi_edges, weight) O(vi_opts, lm_lambda) O(vi_opts, d_min)
+      O(vi_report, n_valid) O(vi_report, dxi) O(vi_report, stage_ms)
+      return 0;
+    }
+    """
+    with tempfile.TemporaryDirectory() as d:
+        cfile = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(cfile, "w").write(src)
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), cfile, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+    got = {k: int(v) for k, v in got.items()}
+    py = {
+        "vi_camera": C.sizeof(binding.Camera), "vi_imu_noise": C.sizeof(binding.ImuNoise),
+        "vi_preint": 8 * binding.PREINT_DOUBLES, "vi_state": C.sizeof(binding.State),
+        "vi_edges": C.sizeof(binding.Edges), "vi_opts": C.sizeof(binding.Opts), "vi_report": C.sizeof(binding.Report),
+        "vi_camera.H": binding.Camera.H.offset, "vi_camera.gravity": binding.Camera.gravity.offset,
+        "vi_preint.cov": 8 * 61, "vi_preint.cov_bias": 8 * 148,
+        "vi_state.invdepth": binding.State.invdepth.offset, "vi_edges.weight": binding.Edges.weight.offset,
+        "vi_opts.lm_lambda": binding.Opts.lm_lambda.offset, "vi_opts.d_min": binding.Opts.d_min.offset,
+        "vi_report.n_valid": binding.Report.n_valid.offset, "vi_report.dxi": binding.Report.dxi.offset,
+        "vi_report.stage_ms": binding.Report.stage_ms.offset,
+    }
+    assert got == py
+
+
+def test_workspace_size_host_only():
+    """vi_workspace_size builds the plan on the host; invalid graphs give 0."""
+    lib = binding.load()
+    cam = binding.make_camera(75, 75, 40, 30, 60, 80)
+    opts = binding.make_opts()
+
+    def ws(n, ii, jj):
+        ii = np.asarray(ii, np.int32)
+        jj = np.asarray(jj, np.int32)
+        ed = binding.Edges(len(ii), ii.ctypes.data_as(C.c_void_p), jj.ctypes.data_as(C.c_void_p), None, None)
+        return lib.vi_workspace_size(C.byref(cam), n, C.byref(ed), C.byref(opts))
+
+    a = ws(3, [0, 1, 2], [1, 2, 0])
+    b = ws(3, [0, 1, 2, 0], [1, 2, 0, 2])
+    assert a > 0 and b > a
+    # the E-block alone is 6 doubles per (edge, pixel)
+    assert b - a >= 6 * 8 * 60 * 80
+    assert ws(3, [0, 1], [1, 3]) == 0          # index out of range
+    assert ws(3, [0, 1], [0, 2]) == 0          # self edge
+    assert ws(3, [0, 0], [1, 1]) == 0          # duplicate pair
+    assert ws(1, [0], [0]) == 0                # too few keyframes
+    many = list(range(1, 20))
+    assert ws(20, [0] * 19, many) == 0         # out-degree above the supported maximum
