@@ -47,11 +47,13 @@ def parse():
 def stage_models(prob):
     """Algorithmic work of one launch of each stage (one GN iteration).
 
-    vis_imu_assemble (HBM): every pixel-residual must read its target and
-      weight once (2 + 2 float32 = 16 B); every source pixel reads its float64
-      inverse depth (8 B) and writes C and w_d (16 B).
-    gram (FP64 MFMA): the symmetric (6k+1)^2 Gram of each source pixel,
-      (6k+1)(6k+2)/2 multiply-adds = (6k+1)(6k+2) flops per pixel.
+    vis_gram_imu (FP64 MFMA + VALU): the J^T W J contractions of the step --
+      per pixel-residual the local 6x6 Hessian (21 entries), gradient (6) and
+      E-entries (6), each from 2 coordinates at 2 flops per multiply-add
+      (132 flops), plus per source pixel the symmetric (6k+1)^2 Schur Gram,
+      (6k+1)(6k+2) flops.  Residual/Jacobian evaluation is not counted.
+      Its HBM side is 16 B per pixel-residual (f32 target and weight) plus
+      8 B in and 16 B out per source pixel.
     cholesky (FP64): n^3/3 flops for the 15N x 15N reduced system.
     """
     import numpy as np
@@ -60,11 +62,10 @@ def stage_models(prob):
     gram_flops = float(sum((6 * k + 1) * (6 * k + 2) for k in ks if k > 0)) * HW
     n = 15 * N
     return {
-        "vis_imu_assemble": dict(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS, scale=1e9,
-                                 work=float(E * HW * 16 + N * HW * 24), work_name="algorithmic_bytes_per_launch",
-                                 per_unit="16 B per pixel-residual + 24 B per source pixel"),
-        "gram": dict(bound="mfma", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, scale=1e12, work=gram_flops,
-                     work_name="algorithmic_flops_per_launch", per_unit="(6k+1)(6k+2) flops per source pixel"),
+        "vis_gram_imu": dict(bound="mfma", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, scale=1e12,
+                             work=gram_flops + 132.0 * E * HW, work_name="algorithmic_flops_per_launch",
+                             per_unit="132 flops per pixel-residual + (6k+1)(6k+2) flops per source pixel",
+                             hbm_bytes=float(E * HW * 16 + N * HW * 24)),
         "cholesky": dict(bound="alu", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, scale=1e12, work=n ** 3 / 3.0,
                          work_name="algorithmic_flops_per_launch", per_unit="n^3/3 flops, n = 15 N"),
     }
@@ -133,6 +134,8 @@ def main():
     roof = {"bound": m["bound"], "achieved": achieved, "peak": m["peak"], "unit": m["unit"],
             "frac": achieved / m["peak"], "traffic": None, "stage": key, "dominant_stage": dom,
             "stage_ms": per_iter_ms[key], m["work_name"]: m["work"], "per_unit": m["per_unit"]}
+    if "hbm_bytes" in m:
+        roof["hbm_gbs_algorithmic"] = m["hbm_bytes"] / (per_iter_ms[key] * 1e-3) / 1e9
 
     out = {
         "metric": METRIC,

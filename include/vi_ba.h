@@ -154,19 +154,20 @@ typedef struct {
 } vi_opts;
 
 /* Stages reported by vi_report.stage_ms, in launch order:
- *  0 vision residual/Jacobian assembly with the inertial factors (one launch)
- *  1 Schur Gram (MFMA)         2 per-source local blocks and cost reduction
- *  3 reduced-system assembly   4 Cholesky factor and solves
- *  5 back-substitution and retraction
- *  6 final cost evaluation */
-#define VI_NUM_STAGES 7
+ *  0 vision residual/Jacobian assembly fused with the Schur Gram, plus the
+ *    inertial factors (one launch)
+ *  1 per-source reduced blocks and cost reduction
+ *  2 reduced-system assembly   3 Cholesky factor and solves
+ *  4 back-substitution and retraction
+ *  5 final cost evaluation */
+#define VI_NUM_STAGES 6
 
 typedef struct {
   double cost_before;        /* F at the input state of the (last) step */
   double cost_after;         /* F at the output state */
   int64_t n_valid;           /* valid pixel-residuals at the (last) linearisation point */
   int32_t iters_done;        /* steps applied */
-  int32_t reserved;
+  int32_t tile_px;           /* pixels per workgroup the assembly ran with (autotuned or default) */
   double* dxi;               /* optional device [N][15]: increments of the last step */
   double* dd;                /* optional device [N][H][W]: depth increments of the last step */
   double* costs;             /* optional host [iters+1]: F before each step, then final F */
@@ -193,6 +194,35 @@ vi_status vi_ba_step(vi_ctx* ctx, const vi_camera* cam, vi_state* state, const v
 vi_status vi_ba_solve(vi_ctx* ctx, const vi_camera* cam, vi_state* state, const vi_edges* edges,
                       const vi_preint* imu, const vi_opts* opts, int32_t iters,
                       void* workspace, size_t workspace_bytes, vi_report* report);
+
+/* One independent window of a batch (the same step as vi_ba_solve, per window). */
+typedef struct {
+  vi_camera cam;             /* intrinsics and map size of this window */
+  vi_state state;            /* device arrays, updated in place */
+  vi_edges edges;            /* edges within this window (indices local to it) */
+  const vi_preint* imu;      /* device [N-1]; may be NULL iff !use_imu */
+  vi_report* report;         /* optional host report of this window */
+} vi_window;
+
+/* Device workspace (bytes) for vi_ba_solve_batched on these windows. */
+size_t vi_workspace_size_batched(int32_t n_windows, const vi_window* windows, const vi_opts* opts);
+
+/* `iters` steps on every window of a batch, all windows in the same launches
+ * (one HIP graph per batch shape): each kernel of the step processes every
+ * window's keyframes, edges, factors and reduced system.  Windows are
+ * independent; a window whose reduced system fails (VI_ENOTPD, VI_ENONFINITE)
+ * stops being updated while the others continue, and the first such error is
+ * returned.  Per-window costs and counters go to windows[w].report.  When
+ * windows[0].report->stage_ms is set the batch runs without a graph and the
+ * stage times of the whole batch are returned there. */
+vi_status vi_ba_solve_batched(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,
+                              int32_t iters, void* workspace, size_t workspace_bytes);
+
+/* Autotuning of the pixels-per-workgroup of the fused assembly.  When enabled,
+ * the first call for a new batch shape times each candidate tiling on the
+ * actual inputs (eagerly, before graph capture) and keeps the fastest for that
+ * shape in the context; later calls reuse it.  Off by default (320 pixels). */
+vi_status vi_ctx_set_autotune(vi_ctx* ctx, int32_t enable);
 
 #ifdef __cplusplus
 }

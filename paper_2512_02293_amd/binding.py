@@ -17,8 +17,8 @@ from ._build import LIB_PATH
 VI_OK, VI_EINVAL, VI_ENOMEM, VI_EDEVICE, VI_ENOTPD, VI_ENONFINITE, VI_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS_NAMES = {0: "VI_OK", -1: "VI_EINVAL", -2: "VI_ENOMEM", -3: "VI_EDEVICE", -4: "VI_ENOTPD",
                 -5: "VI_ENONFINITE", -6: "VI_EUNSUPPORTED"}
-NUM_STAGES = 7
-STAGE_NAMES = ["vis_imu_assemble", "gram", "local", "assemble", "cholesky", "backsub_retract", "final_cost"]
+NUM_STAGES = 6
+STAGE_NAMES = ["vis_gram_imu", "local", "assemble", "cholesky", "backsub_retract", "final_cost"]
 PREINT_DOUBLES = 154
 
 
@@ -56,12 +56,18 @@ class Opts(C.Structure):
 
 class Report(C.Structure):
     _fields_ = [("cost_before", C.c_double), ("cost_after", C.c_double), ("n_valid", C.c_int64),
-                ("iters_done", C.c_int32), ("reserved", C.c_int32), ("dxi", C.c_void_p), ("dd", C.c_void_p),
+                ("iters_done", C.c_int32), ("tile_px", C.c_int32), ("dxi", C.c_void_p), ("dd", C.c_void_p),
                 ("costs", C.c_void_p), ("stage_ms", C.c_void_p)]
 
 
+class Window(C.Structure):
+    _fields_ = [("cam", Camera), ("state", State), ("edges", Edges), ("imu", C.c_void_p),
+                ("report", C.POINTER(Report))]
+
+
 EXPORTS = ["vi_ctx_create", "vi_ctx_destroy", "vi_ctx_set_stream", "vi_last_error", "vi_version",
-           "imu_preintegrate", "vi_workspace_size", "vi_ba_step", "vi_ba_solve"]
+           "imu_preintegrate", "vi_workspace_size", "vi_ba_step", "vi_ba_solve", "vi_workspace_size_batched",
+           "vi_ba_solve_batched", "vi_ctx_set_autotune"]
 
 _lib = None
 
@@ -95,6 +101,13 @@ def load(path: str = LIB_PATH):
     lib.vi_ba_solve.argtypes = [C.c_void_p, C.POINTER(Camera), C.POINTER(State), C.POINTER(Edges), C.c_void_p,
                                 C.POINTER(Opts), C.c_int32, C.c_void_p, C.c_size_t, C.POINTER(Report)]
     lib.vi_ba_solve.restype = C.c_int
+    lib.vi_workspace_size_batched.argtypes = [C.c_int32, C.POINTER(Window), C.POINTER(Opts)]
+    lib.vi_workspace_size_batched.restype = C.c_size_t
+    lib.vi_ba_solve_batched.argtypes = [C.c_void_p, C.c_int32, C.POINTER(Window), C.POINTER(Opts), C.c_int32,
+                                        C.c_void_p, C.c_size_t]
+    lib.vi_ba_solve_batched.restype = C.c_int
+    lib.vi_ctx_set_autotune.argtypes = [C.c_void_p, C.c_int32]
+    lib.vi_ctx_set_autotune.restype = C.c_int
     _lib = lib
     return lib
 
@@ -220,11 +233,70 @@ class Context:
             rc = self.lib.vi_ba_solve(self.h, C.byref(cam), C.byref(st), C.byref(ed), _ptr(imu), C.byref(opts),
                                       iters, _ptr(workspace), nbytes, C.byref(rep))
         out = dict(cost_before=rep.cost_before, cost_after=rep.cost_after, n_valid=int(rep.n_valid),
-                   iters_done=int(rep.iters_done), status=rc)
+                   iters_done=int(rep.iters_done), tile_px=int(rep.tile_px), status=rc)
         if costs:
             out["costs"] = cost_arr
         if stage_ms:
             out["stage_ms"] = dict(zip(STAGE_NAMES, stage_arr.tolist()))
+        self._check(rc)
+        return out
+
+
+    def set_autotune(self, enable: bool):
+        self._check(self.lib.vi_ctx_set_autotune(self.h, int(bool(enable))))
+
+    # -- batches of independent windows ---------------------------------------
+    def _windows(self, probs, imus, with_reports, costs, iters, stage_ms=False):
+        torch = self.torch
+        n = len(probs)
+        wins = (Window * n)()
+        keep = []
+        reps = []
+        for w, (dp, imu) in enumerate(zip(probs, imus)):
+            N, E, H, W = int(dp.pose.shape[0]), int(dp.ii.shape[0]), int(dp.cam.H), int(dp.cam.W)
+            for t, shape, dt, name in ((dp.pose, (N, 7), torch.float64, "pose"), (dp.vel, (N, 3), torch.float64, "vel"),
+                                       (dp.bias, (N, 6), torch.float64, "bias"),
+                                       (dp.invdepth, (N, H, W), torch.float64, "invdepth"),
+                                       (dp.target, (E, 2, H, W), torch.float32, "target"),
+                                       (dp.weight, (E, 2, H, W), torch.float32, "weight")):
+                _check_dev(t, shape, dt, f"window {w} {name}")
+            if imu is not None:
+                _check_dev(imu, (N - 1, PREINT_DOUBLES), torch.float64, f"window {w} imu")
+            wins[w].cam = dp.cam
+            wins[w].state = State(N, _ptr(dp.pose), _ptr(dp.vel), _ptr(dp.bias), _ptr(dp.invdepth))
+            wins[w].edges = Edges(E, dp.ii.ctypes.data_as(C.c_void_p), dp.jj.ctypes.data_as(C.c_void_p),
+                                  _ptr(dp.target), _ptr(dp.weight))
+            wins[w].imu = _ptr(imu)
+            if with_reports:
+                cost_arr = np.zeros(iters + 1) if costs else None
+                stage_arr = np.zeros(NUM_STAGES, dtype=np.float32) if (stage_ms and w == 0) else None
+                r = Report(0.0, 0.0, 0, 0, 0, None, None,
+                           cost_arr.ctypes.data_as(C.c_void_p) if costs else None,
+                           stage_arr.ctypes.data_as(C.c_void_p) if stage_arr is not None else None)
+                keep.append((r, cost_arr, stage_arr))
+                wins[w].report = C.pointer(r)
+                reps.append((r, cost_arr, stage_arr))
+        return wins, reps, keep
+
+    def workspace_size_batched(self, probs, opts: Opts) -> int:
+        wins, _, _ = self._windows(probs, [None] * len(probs), False, False, 1)
+        return int(self.lib.vi_workspace_size_batched(len(probs), wins, C.byref(opts)))
+
+    def solve_batched(self, probs, imus, opts: Opts, iters: int, workspace, costs=False, stage_ms=False):
+        """Solve every window of a batch in the same launches; returns per-window reports."""
+        _check_dev(workspace, (None,), self.torch.uint8, "workspace")
+        wins, reps, keep = self._windows(probs, imus, True, costs, iters, stage_ms)
+        rc = self.lib.vi_ba_solve_batched(self.h, len(probs), wins, C.byref(opts), iters, _ptr(workspace),
+                                          workspace.numel())
+        out = []
+        for r, cost_arr, stage_arr in reps:
+            d = dict(cost_before=r.cost_before, cost_after=r.cost_after, n_valid=int(r.n_valid),
+                     iters_done=int(r.iters_done), tile_px=int(r.tile_px))
+            if costs:
+                d["costs"] = cost_arr
+            if stage_arr is not None:
+                d["stage_ms"] = dict(zip(STAGE_NAMES, stage_arr.tolist()))
+            out.append(d)
         self._check(rc)
         return out
 

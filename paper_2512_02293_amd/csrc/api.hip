@@ -1,47 +1,64 @@
 // C ABI of the visual-inertial step library: argument validation, the
-// per-shape plan (index tables derived from the frame graph), the workspace
-// carve, HIP-graph capture of whole solves, and the report.
+// per-batch plan (index tables derived from the windows' frame graphs), the
+// workspace carve, the autotuner of the fused assembly tiling, HIP-graph
+// capture of whole solves, and the reports.
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "vi_internal.h"
 
 using namespace vi;
 
-struct GraphKey {
-  int32_t N, E, H, W, iters;
-  vi_opts opts;
-  double cam[7];
-  const void* ptrs[12];
-  uint64_t plan_version;
-  bool operator==(const GraphKey& o) const { return std::memcmp(this, &o, sizeof(GraphKey)) == 0; }
+namespace {
+
+// candidate pixels-per-workgroup of the fused assembly (multiples of 64)
+const int kRanges[] = {128, 192, 256, 320, 448, 640};
+constexpr int kRangeMin = 128;
+constexpr int kRangeDefault = 320;
+
+struct WinIn {
+  const vi_camera* cam;
+  const vi_state* st;
+  const vi_edges* ed;
+  const vi_preint* imu;
+  vi_report* rep;
 };
+
+}  // namespace
 
 struct vi_ctx {
   int device = 0;
   hipStream_t user = nullptr;      // caller's stream
   hipStream_t priv = nullptr;      // private stream (graph capture and execution)
-  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_in = nullptr;
   std::string err;
-  DevStatus* status = nullptr;     // device
+  DevStatus* status = nullptr;     // device [status_cap]
+  int status_cap = 0;
   int32_t* d_off = nullptr;        // device CSR for imu_preintegrate
   size_t d_off_cap = 0;
   // plan
   Plan plan;
   bool have_plan = false;
   uint64_t plan_version = 0;
-  int32_t* d_plan = nullptr;
+  std::vector<int32_t> plan_sig;   // shape signature of the planned batch
+  char* d_plan = nullptr;
   size_t d_plan_cap = 0;
   DevPlan dplan{};
+  WinDev* d_win = nullptr;         // device window table (inside d_plan)
   int attr_kmax = -1;
+  // autotuning
+  bool autotune = false;
+  std::map<std::tuple<int, int, int, int>, int> tuned;
   // graph cache
   bool have_graph = false;
-  GraphKey gkey{};
+  std::vector<uint64_t> gkey;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
@@ -66,148 +83,196 @@ vi_status fail(vi_ctx* ctx, vi_status code, const char* fmt, ...) {
   } while (0)
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
-vi_status build_plan(vi_ctx* ctx, int N, const vi_edges* ed, int H, int W, Plan& P) {
-  const int E = ed->n_edges;
-  P = Plan();
-  P.N = N; P.E = E; P.H = H; P.W = W; P.HW = H * W; P.F = N - 1;
-  P.n = 15 * N;
-  P.npad = (P.n + kCholNB - 1) / kCholNB * kCholNB;
-  P.nblk = P.npad / kCholNB;
-  P.nkr_vis = (P.HW + kVisBlock - 1) / kVisBlock;
-  P.nkr_gram = (P.HW + kGramRange - 1) / kGramRange;
-  P.ii.assign(ed->ii, ed->ii + E);
-  P.jj.assign(ed->jj, ed->jj + E);
-  std::vector<int> cnt(N, 0);
-  std::vector<char> seen;
-  for (int e = 0; e < E; ++e) {
-    const int i = P.ii[e], j = P.jj[e];
-    if (i < 0 || i >= N || j < 0 || j >= N)
-      return fail(ctx, VI_EINVAL, "edge %d: keyframe index out of range (%d -> %d, N = %d)", e, i, j, N);
-    if (i == j) return fail(ctx, VI_EINVAL, "edge %d: source equals target (%d)", e, i);
-    cnt[i]++;
+// Host checks of one window.  `full` also requires the device arrays (a
+// workspace-size query only needs the shapes and the frame graph).
+vi_status check_window(vi_ctx* ctx, int w, const WinIn& in, const vi_opts* o, bool full) {
+  const vi_camera* cam = in.cam;
+  const vi_state* st = in.st;
+  const vi_edges* ed = in.ed;
+  if (!cam || !st || !ed) return fail(ctx, VI_EINVAL, "window %d: null argument", w);
+  if (!finite_pos(cam->fx) || !finite_pos(cam->fy) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
+    return fail(ctx, VI_EINVAL, "window %d: intrinsics must be finite with fx, fy > 0", w);
+  if (cam->H <= 0 || cam->W <= 0 || (int64_t)cam->H * cam->W > (1 << 24))
+    return fail(ctx, VI_EINVAL, "window %d: bad map size %d x %d", w, cam->H, cam->W);
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(cam->gravity[k])) return fail(ctx, VI_EINVAL, "window %d: gravity must be finite", w);
+  if (st->n_kf < 2) return fail(ctx, VI_EINVAL, "window %d: need at least 2 keyframes (got %d)", w, st->n_kf);
+  if (st->n_kf > 4096) return fail(ctx, VI_EUNSUPPORTED, "window %d: at most 4096 keyframes are supported", w);
+  if (ed->n_edges < 1) return fail(ctx, VI_EINVAL, "window %d: need at least one edge", w);
+  if (!ed->ii || !ed->jj) return fail(ctx, VI_EINVAL, "window %d: null edge index array", w);
+  if (o->n_fixed > st->n_kf) return fail(ctx, VI_EINVAL, "window %d: n_fixed out of range", w);
+  if (full) {
+    if (!st->pose || !st->vel || !st->bias || !st->invdepth)
+      return fail(ctx, VI_EINVAL, "window %d: null state array", w);
+    if (!ed->target || !ed->weight) return fail(ctx, VI_EINVAL, "window %d: null edge array", w);
+    if (o->use_imu && !in.imu) return fail(ctx, VI_EINVAL, "window %d: use_imu set but no IMU factors given", w);
   }
-  P.src_off.assign(N + 1, 0);
-  for (int i = 0; i < N; ++i) P.src_off[i + 1] = P.src_off[i] + cnt[i];
-  P.src_edges.assign(E, 0);
-  P.edge_slot.assign(E, 0);
-  std::vector<int> fill(N, 0);
-  for (int e = 0; e < E; ++e) {
-    const int i = P.ii[e];
-    P.edge_slot[e] = fill[i];
-    P.src_edges[P.src_off[i] + fill[i]++] = e;
+  return VI_OK;
+}
+
+vi_status check_opts(vi_ctx* ctx, const vi_opts* o) {
+  if (!o) return fail(ctx, VI_EINVAL, "null options");
+  if (o->n_fixed < 0) return fail(ctx, VI_EINVAL, "n_fixed out of range");
+  if (o->reserved != 0) return fail(ctx, VI_EINVAL, "opts.reserved must be 0");
+  if (!(o->lm_lambda >= 0.0) || !(o->depth_eta >= 0.0) || !std::isfinite(o->lm_lambda) ||
+      !std::isfinite(o->depth_eta))
+    return fail(ctx, VI_EINVAL, "damping must be finite and >= 0");
+  if (!std::isfinite(o->z_min) || !(o->d_min >= 0.0) || !std::isfinite(o->d_min))
+    return fail(ctx, VI_EINVAL, "z_min must be finite and d_min finite and >= 0");
+  return VI_OK;
+}
+
+// Shape signature: everything the plan depends on (sizes and the frame graphs).
+std::vector<int32_t> plan_signature(const std::vector<WinIn>& wins) {
+  std::vector<int32_t> s;
+  s.push_back((int32_t)wins.size());
+  for (const WinIn& in : wins) {
+    s.push_back(in.st->n_kf);
+    s.push_back(in.cam->H);
+    s.push_back(in.cam->W);
+    s.push_back(in.ed->n_edges);
+    s.insert(s.end(), in.ed->ii, in.ed->ii + in.ed->n_edges);
+    s.insert(s.end(), in.ed->jj, in.ed->jj + in.ed->n_edges);
+  }
+  return s;
+}
+
+vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
+  P = Plan();
+  const int nw = (int)wins.size();
+  P.n_win = nw;
+  P.win.resize(nw);
+  int kf = 0, ed = 0, fa = 0;
+  long long pix = 0;
+  for (int w = 0; w < nw; ++w) {
+    const WinIn& in = wins[w];
+    WinDev& W = P.win[w];
+    std::memset(&W, 0, sizeof(W));
+    W.H = in.cam->H;
+    W.W = in.cam->W;
+    W.HW = W.H * W.W;
+    W.N = in.st->n_kf;
+    W.kf_base = kf;
+    W.e_base = ed;
+    W.f_base = fa;
+    W.F = W.N - 1;
+    W.pix_base = pix;
+    const int E = in.ed->n_edges;
+    for (int e = 0; e < E; ++e) {
+      const int i = in.ed->ii[e], j = in.ed->jj[e];
+      if (i < 0 || i >= W.N || j < 0 || j >= W.N)
+        return fail(ctx, VI_EINVAL, "window %d edge %d: keyframe index out of range (%d -> %d, N = %d)", w, e, i, j,
+                    W.N);
+      if (i == j) return fail(ctx, VI_EINVAL, "window %d edge %d: source equals target (%d)", w, e, i);
+      P.ii.push_back(kf + i);
+      P.jj.push_back(kf + j);
+    }
+    for (int l = 0; l < W.N; ++l) P.win_of_kf.push_back(w);
+    for (int l = 0; l < W.F; ++l) P.win_of_f.push_back(w);
+    kf += W.N;
+    ed += E;
+    fa += W.F;
+    pix += (long long)W.N * W.HW;
+    P.hw_max = std::max(P.hw_max, W.HW);
+  }
+  P.N = kf;
+  P.E = ed;
+  P.F = fa;
+  P.pix_total = pix;
+  // edges grouped by source keyframe (input order within a source)
+  std::vector<int> cnt(P.N, 0);
+  for (int e = 0; e < P.E; ++e) cnt[P.ii[e]]++;
+  P.src_off.assign(P.N + 1, 0);
+  for (int g = 0; g < P.N; ++g) P.src_off[g + 1] = P.src_off[g] + cnt[g];
+  P.src_edges.assign(P.E, 0);
+  std::vector<int> fill(P.N, 0);
+  for (int e = 0; e < P.E; ++e) {
+    const int g = P.ii[e];
+    P.src_edges[P.src_off[g] + fill[g]++] = e;
   }
   P.kmax = 0;
-  for (int i = 0; i < N; ++i) P.kmax = std::max(P.kmax, cnt[i]);
+  for (int g = 0; g < P.N; ++g) P.kmax = std::max(P.kmax, cnt[g]);
   if (P.kmax > kMaxOutDegree)
     return fail(ctx, VI_EUNSUPPORTED, "a keyframe has %d outgoing edges; at most %d are supported", P.kmax,
                 kMaxOutDegree);
-  // duplicate pairs
-  for (int i = 0; i < N; ++i) {
+  for (int g = 0; g < P.N; ++g) {
     std::vector<int> t;
-    for (int s = P.src_off[i]; s < P.src_off[i + 1]; ++s) t.push_back(P.jj[P.src_edges[s]]);
+    for (int s = P.src_off[g]; s < P.src_off[g + 1]; ++s) t.push_back(P.jj[P.src_edges[s]]);
     std::sort(t.begin(), t.end());
+    const WinDev& W = P.win[P.win_of_kf[g]];
     for (size_t a = 1; a < t.size(); ++a)
-      if (t[a] == t[a - 1]) return fail(ctx, VI_EINVAL, "duplicate edge %d -> %d", i, t[a]);
+      if (t[a] == t[a - 1])
+        return fail(ctx, VI_EINVAL, "window %d: duplicate edge %d -> %d", P.win_of_kf[g], g - W.kf_base,
+                    t[a] - W.kf_base);
   }
-  P.gram_off.assign(N, 0); P.q_off.assign(N, 0); P.z_off.assign(N, 0); P.zb_off.assign(N, 0);
-  P.tiles.assign(N, 0);
-  size_t go = 0, qo = 0, zo = 0, zbo = 0;
-  for (int i = 0; i < N; ++i) {
-    const int k = cnt[i];
+  // partial-sum layout for the smallest tiling, so any candidate fits
+  P.nkr_max = (P.hw_max + kRangeMin - 1) / kRangeMin;
+  P.gram_off.assign(P.N, 0);
+  P.z_off.assign(P.N, 0);
+  P.zb_off.assign(P.N, 0);
+  size_t go = 0, zo = 0, zbo = 0;
+  for (int g = 0; g < P.N; ++g) {
+    const int k = cnt[g];
+    const WinDev& W = P.win[P.win_of_kf[g]];
     const int T = k > 0 ? (6 * k + 16) / 16 : 0;
-    P.tiles[i] = T * (T + 1) / 2;
-    P.gram_off[i] = (int32_t)go;
-    P.q_off[i] = (int32_t)qo;
-    P.z_off[i] = (int32_t)zo;
-    P.zb_off[i] = (int32_t)zbo;
-    go += (size_t)P.tiles[i] * 256 * P.nkr_gram;
-    if (k > 0) qo += (size_t)(6 * k + 1) * (6 * k + 1);
+    P.gram_off[g] = (int32_t)go;
+    P.z_off[g] = (int32_t)zo;
+    P.zb_off[g] = (int32_t)zbo;
+    go += (size_t)T * (T + 1) / 2 * 256 * ((W.HW + kRangeMin - 1) / kRangeMin);
     zo += (size_t)(k + 1) * (k + 1) * 36;
     zbo += (size_t)6 * (k + 1);
   }
-  if (go > INT32_MAX || qo > INT32_MAX || zo > INT32_MAX)
-    return fail(ctx, VI_EUNSUPPORTED, "problem too large for 32-bit plan offsets");
-  P.gram_size = go; P.q_size = qo; P.z_size = zo; P.zb_size = zbo;
-  P.L_size = (size_t)6 * E * P.HW;
-  // gather lists of the reduced assembly: pose block (a, b) <- Z blocks of every
-  // source whose touched set {i} U targets(i) contains both a and b
-  std::vector<std::vector<std::pair<int, int>>> items((size_t)N * N);
-  for (int i = 0; i < N; ++i) {
-    const int k = cnt[i];
-    std::vector<int> T(1, i);
-    for (int s = P.src_off[i]; s < P.src_off[i + 1]; ++s) T.push_back(P.jj[P.src_edges[s]]);
-    for (int ta = 0; ta <= k; ++ta)
-      for (int tb = 0; tb <= k; ++tb)
-        items[(size_t)T[ta] * N + T[tb]].push_back(
-            {P.z_off[i] + (ta * (k + 1) + tb) * 36, P.zb_off[i] + 6 * ta});
-  }
-  P.pair_off.assign((size_t)N * N + 1, 0);
-  for (size_t q = 0; q < (size_t)N * N; ++q) P.pair_off[q + 1] = P.pair_off[q] + (int32_t)items[q].size();
-  P.n_pairs = P.pair_off.back();
-  P.pair_z.resize(std::max<size_t>(P.n_pairs, 1));
-  P.pair_zb.resize(std::max<size_t>(P.n_pairs, 1));
-  for (size_t q = 0; q < (size_t)N * N; ++q)
-    for (size_t u = 0; u < items[q].size(); ++u) {
-      P.pair_z[P.pair_off[q] + u] = items[q][u].first;
-      P.pair_zb[P.pair_off[q] + u] = items[q][u].second;
+  if (go > INT32_MAX || zo > INT32_MAX) return fail(ctx, VI_EUNSUPPORTED, "batch too large for 32-bit offsets");
+  P.gram_size = go;
+  P.z_size = zo;
+  P.zb_size = zbo;
+  // per window: reduced system and gather lists of its assembly.  Pose block
+  // (a, b) <- Z blocks of every source whose touched set contains a and b.
+  size_t A_off = 0, L_off = 0, x_off = 0;
+  for (int w = 0; w < nw; ++w) {
+    WinDev& W = P.win[w];
+    W.n = 15 * W.N;
+    W.npad = (W.n + kCholNB - 1) / kCholNB * kCholNB;
+    W.nblk = W.npad / kCholNB;
+    W.A_off = (long long)A_off;
+    W.Linv_off = (long long)L_off;
+    W.x_off = (long long)x_off;
+    A_off += (size_t)(W.npad + kCholNB) * W.npad;
+    L_off += (size_t)W.nblk * kCholNB * kCholNB;
+    x_off += (size_t)W.npad;
+    P.nblk_max = std::max(P.nblk_max, W.nblk);
+    std::vector<std::vector<std::pair<int, int>>> items((size_t)W.N * W.N);
+    for (int g = W.kf_base; g < W.kf_base + W.N; ++g) {
+      const int k = cnt[g];
+      std::vector<int> T(1, g - W.kf_base);
+      for (int s = P.src_off[g]; s < P.src_off[g + 1]; ++s) T.push_back(P.jj[P.src_edges[s]] - W.kf_base);
+      for (int ta = 0; ta <= k; ++ta)
+        for (int tb = 0; tb <= k; ++tb)
+          items[(size_t)T[ta] * W.N + T[tb]].push_back({P.z_off[g] + (ta * (k + 1) + tb) * 36, P.zb_off[g] + 6 * ta});
     }
+    // this window's table: entries pair_base .. pair_base + N*N (the last one is its end)
+    W.pair_base = (int)P.pair_off.size();
+    for (size_t q = 0; q < items.size(); ++q) {
+      P.pair_off.push_back((int32_t)P.pair_z.size());
+      for (auto& it : items[q]) {
+        P.pair_z.push_back(it.first);
+        P.pair_zb.push_back(it.second);
+      }
+    }
+    P.pair_off.push_back((int32_t)P.pair_z.size());
+  }
+  if (P.pair_z.empty()) { P.pair_z.push_back(0); P.pair_zb.push_back(0); }
+  P.A_size = A_off;
+  P.Linv_size = L_off;
+  P.x_size = x_off;
   return VI_OK;
 }
 
-vi_status upload_plan(vi_ctx* ctx) {
-  const Plan& P = ctx->plan;
-  const std::vector<int32_t>* parts[] = {&P.ii, &P.jj, &P.src_off, &P.src_edges, &P.edge_slot,
-                                         &P.gram_off, &P.q_off, &P.z_off, &P.zb_off, &P.tiles,
-                                         &P.pair_off, &P.pair_z, &P.pair_zb};
-  size_t total = 0;
-  for (auto* v : parts) total += align256(v->size() * sizeof(int32_t));
-  if (total > ctx->d_plan_cap) {
-    if (ctx->d_plan) HIPCHK(ctx, hipFree(ctx->d_plan));
-    ctx->d_plan = nullptr;
-    HIPCHK(ctx, hipMalloc((void**)&ctx->d_plan, total));
-    ctx->d_plan_cap = total;
-  }
-  std::vector<char> host(total, 0);
-  size_t off = 0;
-  const int32_t* dptr[13];
-  int idx = 0;
-  for (auto* v : parts) {
-    std::memcpy(host.data() + off, v->data(), v->size() * sizeof(int32_t));
-    dptr[idx++] = (const int32_t*)((char*)ctx->d_plan + off);
-    off += align256(v->size() * sizeof(int32_t));
-  }
-  HIPCHK(ctx, hipMemcpy(ctx->d_plan, host.data(), total, hipMemcpyHostToDevice));
-  DevPlan& D = ctx->dplan;
-  D.ii = dptr[0]; D.jj = dptr[1]; D.src_off = dptr[2]; D.src_edges = dptr[3]; D.edge_slot = dptr[4];
-  D.gram_off = dptr[5]; D.q_off = dptr[6]; D.z_off = dptr[7]; D.zb_off = dptr[8]; D.tiles = dptr[9];
-  D.pair_off = dptr[10]; D.pair_z = dptr[11]; D.pair_zb = dptr[12];
-  return VI_OK;
-}
-
-vi_status ensure_plan(vi_ctx* ctx, int N, const vi_edges* ed, int H, int W) {
-  const int E = ed->n_edges;
-  if (ctx->have_plan) {
-    const Plan& P = ctx->plan;
-    if (P.N == N && P.E == E && P.H == H && P.W == W &&
-        std::memcmp(P.ii.data(), ed->ii, sizeof(int32_t) * E) == 0 &&
-        std::memcmp(P.jj.data(), ed->jj, sizeof(int32_t) * E) == 0)
-      return VI_OK;
-  }
-  Plan P;
-  vi_status s = build_plan(ctx, N, ed, H, W, P);
-  if (s != VI_OK) return s;
-  ctx->plan = std::move(P);
-  ctx->have_plan = false;
-  s = upload_plan(ctx);
-  if (s != VI_OK) return s;
-  ctx->have_plan = true;
-  ctx->plan_version++;
-  if (ctx->plan.kmax > ctx->attr_kmax) {
-    step_set_attributes(ctx->plan.kmax);
-    ctx->attr_kmax = ctx->plan.kmax;
-  }
-  return VI_OK;
+void set_range(Plan& P, int range) {
+  P.range = range;
+  for (WinDev& W : P.win) W.nkr = (W.HW + range - 1) / range;
 }
 
 struct Carve {
@@ -225,14 +290,13 @@ Work do_carve(const Plan& P, void* base, size_t* bytes) {
   Carve c;
   c.base = (char*)base;
   Work w{};
-  const size_t N = P.N, E = P.E, HW = P.HW, F = std::max(P.F, 0);
+  const size_t N = P.N, E = P.E, F = std::max(P.F, 0);
   w.Rw = c.take<double>(N * 9);
   w.rel = c.take<double>(E * 12);
-  w.L = c.take<double>(P.L_size);
-  w.Cd = c.take<double>(N * HW);
-  w.wd = c.take<double>(N * HW);
-  w.hpart = c.take<double>(E * P.nkr_vis * 32);
-  w.vcost = c.take<double>(N * P.nkr_vis * 2);
+  w.Cd = c.take<double>((size_t)P.pix_total);
+  w.wd = c.take<double>((size_t)P.pix_total);
+  w.hpart = c.take<double>(E * P.nkr_max * 32);
+  w.vcost = c.take<double>(N * cost_slots(P) * 2);
   w.gpart = c.take<double>(P.gram_size);
   w.Z = c.take<double>(P.z_size);
   w.ZB = c.take<double>(P.zb_size);
@@ -241,40 +305,93 @@ Work do_carve(const Plan& P, void* base, size_t* bytes) {
   w.Hf = c.take<double>(F * 900);
   w.gf = c.take<double>(F * 30);
   w.icost = c.take<double>(F);
-  w.A = c.take<double>((size_t)(P.npad + kCholNB) * P.npad);
-  w.Linv = c.take<double>((size_t)P.nblk * kCholNB * kCholNB);
-  w.x = c.take<double>(P.npad);
-  w.dd = c.take<double>(N * HW);
-  w.trace = c.take<double>(2 * (kMaxIters + 1));
+  w.A = c.take<double>(P.A_size);
+  w.Linv = c.take<double>(P.Linv_size);
+  w.x = c.take<double>(P.x_size);
+  w.dd = c.take<double>((size_t)P.pix_total);
+  w.trace = c.take<double>((size_t)P.n_win * kTraceLen);
   if (bytes) *bytes = c.off;
   return w;
 }
 
-bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+// Upload the int tables; the window table at the front is refreshed per call.
+vi_status upload_plan(vi_ctx* ctx) {
+  const Plan& P = ctx->plan;
+  const std::vector<int32_t>* parts[] = {&P.ii, &P.jj, &P.win_of_kf, &P.win_of_f, &P.src_off, &P.src_edges,
+                                         &P.gram_off, &P.z_off, &P.zb_off, &P.pair_off, &P.pair_z, &P.pair_zb};
+  size_t total = align256(sizeof(WinDev) * P.n_win);
+  for (auto* v : parts) total += align256(std::max<size_t>(v->size(), 1) * sizeof(int32_t));
+  if (total > ctx->d_plan_cap) {
+    if (ctx->d_plan) HIPCHK(ctx, hipFree(ctx->d_plan));
+    ctx->d_plan = nullptr;
+    HIPCHK(ctx, hipMalloc((void**)&ctx->d_plan, total));
+    ctx->d_plan_cap = total;
+  }
+  std::vector<char> host(total, 0);
+  size_t off = align256(sizeof(WinDev) * P.n_win);
+  const int32_t* dptr[12];
+  int idx = 0;
+  for (auto* v : parts) {
+    if (!v->empty()) std::memcpy(host.data() + off, v->data(), v->size() * sizeof(int32_t));
+    dptr[idx++] = (const int32_t*)(ctx->d_plan + off);
+    off += align256(std::max<size_t>(v->size(), 1) * sizeof(int32_t));
+  }
+  HIPCHK(ctx, hipMemcpy(ctx->d_plan, host.data(), total, hipMemcpyHostToDevice));
+  DevPlan& D = ctx->dplan;
+  ctx->d_win = (WinDev*)ctx->d_plan;
+  D.win = ctx->d_win;
+  D.ii = dptr[0]; D.jj = dptr[1]; D.win_of_kf = dptr[2]; D.win_of_f = dptr[3]; D.src_off = dptr[4];
+  D.src_edges = dptr[5]; D.gram_off = dptr[6]; D.z_off = dptr[7]; D.zb_off = dptr[8];
+  D.pair_off = dptr[9]; D.pair_z = dptr[10]; D.pair_zb = dptr[11];
+  return VI_OK;
+}
 
-vi_status check_common(vi_ctx* ctx, const vi_camera* cam, const vi_state* st, const vi_edges* ed,
-                       const vi_preint* imu, const vi_opts* o) {
-  if (!ctx) return VI_EINVAL;
-  if (!cam || !st || !ed || !o) return fail(ctx, VI_EINVAL, "null argument");
-  if (!finite_pos(cam->fx) || !finite_pos(cam->fy) || !std::isfinite(cam->cx) || !std::isfinite(cam->cy))
-    return fail(ctx, VI_EINVAL, "intrinsics must be finite with fx, fy > 0");
-  if (cam->H <= 0 || cam->W <= 0 || (int64_t)cam->H * cam->W > (1 << 24))
-    return fail(ctx, VI_EINVAL, "bad map size %d x %d", cam->H, cam->W);
-  for (int k = 0; k < 3; ++k)
-    if (!std::isfinite(cam->gravity[k])) return fail(ctx, VI_EINVAL, "gravity must be finite");
-  if (st->n_kf < 2) return fail(ctx, VI_EINVAL, "need at least 2 keyframes (got %d)", st->n_kf);
-  if (st->n_kf > 4096) return fail(ctx, VI_EUNSUPPORTED, "at most 4096 keyframes are supported");
-  if (!st->pose || !st->vel || !st->bias || !st->invdepth) return fail(ctx, VI_EINVAL, "null state array");
-  if (ed->n_edges < 1) return fail(ctx, VI_EINVAL, "need at least one edge");
-  if (!ed->ii || !ed->jj || !ed->target || !ed->weight) return fail(ctx, VI_EINVAL, "null edge array");
-  if (o->n_fixed < 0 || o->n_fixed > st->n_kf) return fail(ctx, VI_EINVAL, "n_fixed out of range");
-  if (o->reserved != 0) return fail(ctx, VI_EINVAL, "opts.reserved must be 0");
-  if (!(o->lm_lambda >= 0.0) || !(o->depth_eta >= 0.0) || !std::isfinite(o->lm_lambda) ||
-      !std::isfinite(o->depth_eta))
-    return fail(ctx, VI_EINVAL, "damping must be finite and >= 0");
-  if (!std::isfinite(o->z_min) || !(o->d_min >= 0.0) || !std::isfinite(o->d_min))
-    return fail(ctx, VI_EINVAL, "z_min must be finite and d_min finite and >= 0");
-  if (o->use_imu && !imu) return fail(ctx, VI_EINVAL, "use_imu set but no IMU factors given");
+vi_status ensure_status(vi_ctx* ctx, int n) {
+  if (n <= ctx->status_cap) return VI_OK;
+  if (ctx->status) HIPCHK(ctx, hipFree(ctx->status));
+  ctx->status = nullptr;
+  HIPCHK(ctx, hipMalloc((void**)&ctx->status, sizeof(DevStatus) * n));
+  ctx->status_cap = n;
+  return VI_OK;
+}
+
+vi_status ensure_plan(vi_ctx* ctx, const std::vector<WinIn>& wins) {
+  std::vector<int32_t> sig = plan_signature(wins);
+  if (ctx->have_plan && sig == ctx->plan_sig) return VI_OK;
+  Plan P;
+  vi_status s = build_plan(ctx, wins, P);
+  if (s != VI_OK) return s;
+  set_range(P, kRangeDefault);
+  ctx->plan = std::move(P);
+  ctx->plan_sig = std::move(sig);
+  ctx->have_plan = false;
+  s = upload_plan(ctx);
+  if (s != VI_OK) return s;
+  s = ensure_status(ctx, ctx->plan.n_win);
+  if (s != VI_OK) return s;
+  ctx->have_plan = true;
+  ctx->plan_version++;
+  if (ctx->plan.kmax > ctx->attr_kmax) {
+    step_set_attributes(ctx->plan.kmax);
+    ctx->attr_kmax = ctx->plan.kmax;
+  }
+  return VI_OK;
+}
+
+// this call's window pointers -> host window table -> device
+vi_status refresh_windows(vi_ctx* ctx, const std::vector<WinIn>& wins) {
+  Plan& P = ctx->plan;
+  for (int w = 0; w < P.n_win; ++w) {
+    WinDev& W = P.win[w];
+    const WinIn& in = wins[w];
+    W.fx = in.cam->fx; W.fy = in.cam->fy; W.cx = in.cam->cx; W.cy = in.cam->cy;
+    for (int k = 0; k < 3; ++k) W.g[k] = in.cam->gravity[k];
+    W.pose = in.st->pose; W.vel = in.st->vel; W.bias = in.st->bias; W.invdepth = in.st->invdepth;
+    W.target = in.ed->target; W.weight = in.ed->weight; W.imu = in.imu;
+    W.rep_dxi = in.rep ? in.rep->dxi : nullptr;
+    W.rep_dd = in.rep ? in.rep->dd : nullptr;
+  }
+  HIPCHK(ctx, hipMemcpy(ctx->d_win, P.win.data(), sizeof(WinDev) * P.n_win, hipMemcpyHostToDevice));
   return VI_OK;
 }
 
@@ -288,54 +405,98 @@ void mark_event(void* user, int stage_done) {
   (void)hipEventRecord(t->ev[stage_done + 1], t->s);
 }
 
-vi_status run(vi_ctx* ctx, const vi_camera* cam, vi_state* st, const vi_edges* ed, const vi_preint* imu,
-              const vi_opts* o, int iters, void* workspace, size_t workspace_bytes, vi_report* rep) {
-  vi_status s = check_common(ctx, cam, st, ed, imu, o);
+// Time each candidate tiling of the fused assembly on the actual inputs and
+// keep the fastest for this batch shape.  The candidates run the assembly and
+// local-block stages only, which write the workspace, never the caller's state.
+vi_status autotune_range(vi_ctx* ctx, const Work& w, const OptsDev& od) {
+  Plan& P = ctx->plan;
+  const auto key = std::make_tuple(P.hw_max, P.kmax, P.N, P.n_win);
+  auto it = ctx->tuned.find(key);
+  if (it != ctx->tuned.end()) {
+    set_range(P, it->second);
+    return VI_OK;
+  }
+  hipStream_t sp = ctx->priv;
+  hipEvent_t ev[kNumStages + 1];
+  for (auto& e : ev) HIPCHK(ctx, hipEventCreate(&e));
+  launch_reset_status(sp, ctx->status, P.n_win);
+  if (od.use_imu) launch_imu_info(sp, P, ctx->dplan, w.Lam, ctx->status);
+  TimingUser tu{sp, ev};
+  int best = kRangeDefault;
+  float best_ms = 1e30f;
+  for (int r : kRanges) {
+    set_range(P, r);
+    HIPCHK(ctx, hipMemcpy(ctx->d_win, P.win.data(), sizeof(WinDev) * P.n_win, hipMemcpyHostToDevice));
+    float tot = 0.f;
+    for (int rep = 0; rep < 3; ++rep) {
+      HIPCHK(ctx, hipEventRecord(ev[0], sp));
+      launch_tune_stages(sp, P, ctx->dplan, w, od, mark_event, &tu);
+      HIPCHK(ctx, hipEventSynchronize(ev[kStLocal + 1]));
+      float ms = 0.f;
+      HIPCHK(ctx, hipEventElapsedTime(&ms, ev[0], ev[kStLocal + 1]));
+      if (rep > 0) tot += ms;
+    }
+    if (tot < best_ms) {
+      best_ms = tot;
+      best = r;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  ctx->tuned[key] = best;
+  set_range(P, best);
+  return VI_OK;
+}
+
+vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int iters, void* workspace,
+              size_t workspace_bytes) {
+  if (!ctx) return VI_EINVAL;
+  vi_status s = check_opts(ctx, o);
   if (s != VI_OK) return s;
+  if (wins.empty()) return fail(ctx, VI_EINVAL, "no windows");
+  for (size_t w = 0; w < wins.size(); ++w) {
+    s = check_window(ctx, (int)w, wins[w], o, true);
+    if (s != VI_OK) return s;
+  }
   if (iters < 1 || iters > kMaxIters) return fail(ctx, VI_EINVAL, "iters must be in [1, %d]", kMaxIters);
   if (!workspace) return fail(ctx, VI_EINVAL, "null workspace");
   if (((uintptr_t)workspace & 255) != 0) return fail(ctx, VI_EINVAL, "workspace must be 256-byte aligned");
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  s = ensure_plan(ctx, st->n_kf, ed, cam->H, cam->W);
+  s = ensure_plan(ctx, wins);
   if (s != VI_OK) return s;
-  const Plan& P = ctx->plan;
+  Plan& P = ctx->plan;
   size_t need = 0;
   do_carve(P, nullptr, &need);
   if (workspace_bytes < need)
     return fail(ctx, VI_ENOMEM, "workspace too small: %zu bytes given, %zu needed", workspace_bytes, need);
   Work w = do_carve(P, workspace, nullptr);
-  CamDev cd{cam->fx, cam->fy, cam->cx, cam->cy, cam->H, cam->W, {cam->gravity[0], cam->gravity[1], cam->gravity[2]}};
   OptsDev od{o->n_fixed, o->use_imu ? 1 : 0, o->bias_fixed ? 1 : 0, o->lm_lambda, o->depth_eta, o->z_min, o->d_min};
-  double* rep_dxi = rep ? rep->dxi : nullptr;
-  double* rep_dd = rep ? rep->dd : nullptr;
-  const bool timing = rep && rep->stage_ms;
+  const bool timing = wins[0].rep && wins[0].rep->stage_ms;
 
   // order after the caller's pending work
   HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
   HIPCHK(ctx, hipStreamWaitEvent(ctx->priv, ctx->ev_in, 0));
   hipStream_t sp = ctx->priv;
 
-  auto enqueue = [&](StageMark mark, void* user) {
-    launch_reset_status(sp, ctx->status);
-    if (od.use_imu) launch_imu_info(sp, P.F, imu, w.Lam, ctx->status);
-    for (int it = 0; it < iters; ++it)
-      launch_step(sp, P, ctx->dplan, w, cd, od, *st, ed->target, ed->weight, imu, it, rep_dxi, rep_dd,
-                  ctx->status, mark, user);
-    launch_final_cost(sp, P, ctx->dplan, w, cd, od, *st, ed->target, ed->weight, imu, iters, ctx->status);
-  };
+  s = refresh_windows(ctx, wins);
+  if (s != VI_OK) return s;
+  if (ctx->autotune) {
+    s = autotune_range(ctx, w, od);
+    if (s != VI_OK) return s;
+    s = refresh_windows(ctx, wins);
+    if (s != VI_OK) return s;
+  }
+  const DevPlan& D = ctx->dplan;
 
   if (timing) {
-    // eager launches with events between stages, summed over the steps
     std::vector<hipEvent_t> ev(kNumStages + 1);
     for (auto& e : ev) HIPCHK(ctx, hipEventCreate(&e));
     std::vector<double> acc(VI_NUM_STAGES, 0.0);
-    launch_reset_status(sp, ctx->status);
-    if (od.use_imu) launch_imu_info(sp, P.F, imu, w.Lam, ctx->status);
+    launch_reset_status(sp, ctx->status, P.n_win);
+    if (od.use_imu) launch_imu_info(sp, P, D, w.Lam, ctx->status);
     TimingUser tu{sp, ev.data()};
     for (int it = 0; it < iters; ++it) {
       HIPCHK(ctx, hipEventRecord(ev[0], sp));
-      launch_step(sp, P, ctx->dplan, w, cd, od, *st, ed->target, ed->weight, imu, it, rep_dxi, rep_dd,
-                  ctx->status, mark_event, &tu);
+      launch_step(sp, P, D, w, od, it, ctx->status, mark_event, &tu);
       HIPCHK(ctx, hipEventSynchronize(ev[kNumStages]));
       for (int k = 0; k < kNumStages; ++k) {
         float ms = 0.f;
@@ -344,31 +505,40 @@ vi_status run(vi_ctx* ctx, const vi_camera* cam, vi_state* st, const vi_edges* e
       }
     }
     HIPCHK(ctx, hipEventRecord(ev[0], sp));
-    launch_final_cost(sp, P, ctx->dplan, w, cd, od, *st, ed->target, ed->weight, imu, iters, ctx->status);
+    launch_final_cost(sp, P, D, w, od, iters);
     HIPCHK(ctx, hipEventRecord(ev[1], sp));
     HIPCHK(ctx, hipEventSynchronize(ev[1]));
     float ms = 0.f;
     HIPCHK(ctx, hipEventElapsedTime(&ms, ev[0], ev[1]));
     acc[kNumStages] += ms;
-    for (int k = 0; k < VI_NUM_STAGES; ++k) rep->stage_ms[k] = (float)acc[k];
+    for (int k = 0; k < VI_NUM_STAGES; ++k) wins[0].rep->stage_ms[k] = (float)acc[k];
     for (auto& e : ev) (void)hipEventDestroy(e);
   } else {
-    GraphKey key;
-    std::memset(&key, 0, sizeof(key));
-    key.N = P.N; key.E = P.E; key.H = P.H; key.W = P.W; key.iters = iters;
-    key.opts = *o;
-    key.cam[0] = cam->fx; key.cam[1] = cam->fy; key.cam[2] = cam->cx; key.cam[3] = cam->cy;
-    key.cam[4] = cam->gravity[0]; key.cam[5] = cam->gravity[1]; key.cam[6] = cam->gravity[2];
-    const void* ptrs[12] = {st->pose, st->vel, st->bias, st->invdepth, ed->target, ed->weight, imu,
-                            workspace, rep_dxi, rep_dd, nullptr, nullptr};
-    std::memcpy(key.ptrs, ptrs, sizeof(ptrs));
-    key.plan_version = ctx->plan_version;
-    if (!ctx->have_graph || !(key == ctx->gkey)) {
+    std::vector<uint64_t> key;
+    key.push_back(ctx->plan_version);
+    key.push_back((uint64_t)iters);
+    key.push_back((uint64_t)P.range);
+    uint64_t ob[sizeof(vi_opts) / 8];
+    std::memcpy(ob, o, sizeof(vi_opts));
+    key.insert(key.end(), ob, ob + sizeof(vi_opts) / 8);
+    key.push_back((uint64_t)(uintptr_t)workspace);
+    for (const WinDev& W : P.win) {
+      const void* ptrs[] = {W.pose, W.vel, W.bias, W.invdepth, W.target, W.weight, W.imu, W.rep_dxi, W.rep_dd};
+      for (const void* p : ptrs) key.push_back((uint64_t)(uintptr_t)p);
+      uint64_t cam[7];
+      const double cv[7] = {W.fx, W.fy, W.cx, W.cy, W.g[0], W.g[1], W.g[2]};
+      std::memcpy(cam, cv, sizeof(cv));
+      key.insert(key.end(), cam, cam + 7);
+    }
+    if (!ctx->have_graph || key != ctx->gkey) {
       if (ctx->exec) { (void)hipGraphExecDestroy(ctx->exec); ctx->exec = nullptr; }
       if (ctx->graph) { (void)hipGraphDestroy(ctx->graph); ctx->graph = nullptr; }
       ctx->have_graph = false;
       HIPCHK(ctx, hipStreamBeginCapture(sp, hipStreamCaptureModeThreadLocal));
-      enqueue(nullptr, nullptr);
+      launch_reset_status(sp, ctx->status, P.n_win);
+      if (od.use_imu) launch_imu_info(sp, P, D, w.Lam, ctx->status);
+      for (int it = 0; it < iters; ++it) launch_step(sp, P, D, w, od, it, ctx->status);
+      launch_final_cost(sp, P, D, w, od, iters);
       hipGraph_t g = nullptr;
       hipError_t e = hipStreamEndCapture(sp, &g);
       if (e != hipSuccess) return fail(ctx, VI_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -380,26 +550,36 @@ vi_status run(vi_ctx* ctx, const vi_camera* cam, vi_state* st, const vi_edges* e
     HIPCHK(ctx, hipGraphLaunch(ctx->exec, sp));
   }
   HIPCHK(ctx, hipGetLastError());
-  DevStatus hs;
-  std::vector<double> trace(2 * (iters + 1));
-  HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(DevStatus), hipMemcpyDeviceToHost, sp));
+  std::vector<DevStatus> hs(P.n_win);
+  std::vector<double> trace((size_t)P.n_win * kTraceLen);
+  HIPCHK(ctx, hipMemcpyAsync(hs.data(), ctx->status, sizeof(DevStatus) * P.n_win, hipMemcpyDeviceToHost, sp));
   HIPCHK(ctx, hipMemcpyAsync(trace.data(), w.trace, sizeof(double) * trace.size(), hipMemcpyDeviceToHost, sp));
   HIPCHK(ctx, hipStreamSynchronize(sp));
-  if (rep) {
-    rep->iters_done = hs.iters;
-    const int last = std::max(0, std::min(hs.iters, iters) - 1);
-    rep->cost_before = trace[2 * last];
-    rep->n_valid = (int64_t)trace[2 * last + 1];
-    rep->cost_after = trace[2 * iters];
+  int first_bad = -1;
+  for (int wi = 0; wi < P.n_win; ++wi) {
+    if (hs[wi].code != 0 && first_bad < 0) first_bad = wi;
+    vi_report* rep = wins[wi].rep;
+    if (!rep) continue;
+    const double* tr = trace.data() + (size_t)wi * kTraceLen;
+    rep->iters_done = hs[wi].iters;
+    rep->tile_px = P.range;
+    const int last = std::max(0, std::min(hs[wi].iters, iters) - 1);
+    rep->cost_before = tr[2 * last];
+    rep->n_valid = (int64_t)tr[2 * last + 1];
+    rep->cost_after = tr[2 * iters];
     if (rep->costs)
-      for (int t = 0; t <= iters; ++t) rep->costs[t] = trace[2 * t];
+      for (int t = 0; t <= iters; ++t) rep->costs[t] = tr[2 * t];
   }
-  if (hs.code == VI_ENOTPD)
-    return fail(ctx, VI_ENOTPD, "reduced system not positive definite at coordinate %d (step %d)", hs.detail,
-                hs.iters);
-  if (hs.code == VI_ENONFINITE)
-    return fail(ctx, VI_ENONFINITE, "non-finite reduced system at coordinate %d (step %d)", hs.detail, hs.iters);
-  if (hs.code != 0) return fail(ctx, (vi_status)hs.code, "device error %d (detail %d)", hs.code, hs.detail);
+  if (first_bad >= 0) {
+    const DevStatus& b = hs[first_bad];
+    if (b.code == VI_ENOTPD)
+      return fail(ctx, VI_ENOTPD, "window %d: reduced system not positive definite at coordinate %d (step %d)",
+                  first_bad, b.detail, b.iters);
+    if (b.code == VI_ENONFINITE)
+      return fail(ctx, VI_ENONFINITE, "window %d: non-finite reduced system at coordinate %d (step %d)", first_bad,
+                  b.detail, b.iters);
+    return fail(ctx, (vi_status)b.code, "window %d: device error %d (detail %d)", first_bad, b.code, b.detail);
+  }
   ctx->err.clear();
   return VI_OK;
 }
@@ -408,7 +588,7 @@ vi_status run(vi_ctx* ctx, const vi_camera* cam, vi_state* st, const vi_edges* e
 
 extern "C" {
 
-const char* vi_version(void) { return "vi-ba-mi355x 0.1 (gfx950, fp64)"; }
+const char* vi_version(void) { return "vi-ba-mi355x 0.2 (gfx950, fp64)"; }
 
 vi_status vi_ctx_create(int32_t device, void* stream, vi_ctx** out) {
   if (!out) return VI_EINVAL;
@@ -419,9 +599,7 @@ vi_status vi_ctx_create(int32_t device, void* stream, vi_ctx** out) {
   c->device = device;
   c->user = (hipStream_t)stream;
   if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&c->priv, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming) != hipSuccess ||
-      hipMalloc((void**)&c->status, sizeof(DevStatus)) != hipSuccess) {
+      hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess || ensure_status(c, 1) != VI_OK) {
     vi_ctx_destroy(c);
     return VI_EDEVICE;
   }
@@ -444,7 +622,6 @@ void vi_ctx_destroy(vi_ctx* c) {
   if (c->d_off) (void)hipFree(c->d_off);
   if (c->status) (void)hipFree(c->status);
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
-  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   if (c->priv) (void)hipStreamDestroy(c->priv);
   delete c;
 }
@@ -452,6 +629,12 @@ void vi_ctx_destroy(vi_ctx* c) {
 vi_status vi_ctx_set_stream(vi_ctx* ctx, void* stream) {
   if (!ctx) return VI_EINVAL;
   ctx->user = (hipStream_t)stream;
+  return VI_OK;
+}
+
+vi_status vi_ctx_set_autotune(vi_ctx* ctx, int32_t enable) {
+  if (!ctx) return VI_EINVAL;
+  ctx->autotune = enable != 0;
   return VI_OK;
 }
 
@@ -479,7 +662,7 @@ vi_status imu_preintegrate(vi_ctx* ctx, int32_t F, const int32_t* off, const dou
   HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
   HIPCHK(ctx, hipStreamWaitEvent(ctx->priv, ctx->ev_in, 0));
   HIPCHK(ctx, hipMemcpyAsync(ctx->d_off, off, bytes, hipMemcpyHostToDevice, ctx->priv));
-  launch_reset_status(ctx->priv, ctx->status);
+  launch_reset_status(ctx->priv, ctx->status, 1);
   launch_preint(ctx->priv, F, ctx->d_off, gyro, accel, dt, bias_hat, *noise, out, ctx->status);
   HIPCHK(ctx, hipGetLastError());
   DevStatus hs;
@@ -491,26 +674,55 @@ vi_status imu_preintegrate(vi_ctx* ctx, int32_t F, const int32_t* off, const dou
   return VI_OK;
 }
 
-size_t vi_workspace_size(const vi_camera* cam, int32_t n_kf, const vi_edges* edges, const vi_opts* opts) {
-  (void)opts;
-  if (!cam || !edges || n_kf < 2 || edges->n_edges < 1 || !edges->ii || !edges->jj) return 0;
+size_t vi_workspace_size_batched(int32_t n_windows, const vi_window* windows, const vi_opts* opts) {
+  if (n_windows < 1 || !windows || !opts) return 0;
+  std::vector<WinIn> wins;
+  for (int w = 0; w < n_windows; ++w) {
+    WinIn in{&windows[w].cam, &windows[w].state, &windows[w].edges, windows[w].imu, nullptr};
+    if (check_window(nullptr, w, in, opts, false) != VI_OK) return 0;
+    wins.push_back(in);
+  }
   Plan P;
-  if (build_plan(nullptr, n_kf, edges, cam->H, cam->W, P) != VI_OK) return 0;
+  if (build_plan(nullptr, wins, P) != VI_OK) return 0;
+  set_range(P, kRangeDefault);
   size_t b = 0;
   do_carve(P, nullptr, &b);
   return b;
 }
 
+size_t vi_workspace_size(const vi_camera* cam, int32_t n_kf, const vi_edges* edges, const vi_opts* opts) {
+  if (!cam || !edges || !opts) return 0;
+  vi_window w;
+  std::memset(&w, 0, sizeof(w));
+  w.cam = *cam;
+  w.state.n_kf = n_kf;
+  w.edges = *edges;
+  return vi_workspace_size_batched(1, &w, opts);
+}
+
+vi_status vi_ba_solve_batched(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,
+                              int32_t iters, void* workspace, size_t workspace_bytes) {
+  if (!ctx) return VI_EINVAL;
+  if (n_windows < 1 || !windows) return fail(ctx, VI_EINVAL, "need at least one window");
+  std::vector<WinIn> wins;
+  for (int w = 0; w < n_windows; ++w)
+    wins.push_back(WinIn{&windows[w].cam, &windows[w].state, &windows[w].edges, windows[w].imu, windows[w].report});
+  return run(ctx, wins, opts, iters, workspace, workspace_bytes);
+}
+
 vi_status vi_ba_step(vi_ctx* ctx, const vi_camera* cam, vi_state* state, const vi_edges* edges,
                      const vi_preint* imu, const vi_opts* opts, void* workspace, size_t workspace_bytes,
                      vi_report* report) {
-  return run(ctx, cam, state, edges, imu, opts, 1, workspace, workspace_bytes, report);
+  return vi_ba_solve(ctx, cam, state, edges, imu, opts, 1, workspace, workspace_bytes, report);
 }
 
 vi_status vi_ba_solve(vi_ctx* ctx, const vi_camera* cam, vi_state* state, const vi_edges* edges,
                       const vi_preint* imu, const vi_opts* opts, int32_t iters, void* workspace,
                       size_t workspace_bytes, vi_report* report) {
-  return run(ctx, cam, state, edges, imu, opts, iters, workspace, workspace_bytes, report);
+  if (!ctx) return VI_EINVAL;
+  if (!cam || !state || !edges) return fail(ctx, VI_EINVAL, "null argument");
+  std::vector<WinIn> wins{WinIn{cam, state, edges, imu, report}};
+  return run(ctx, wins, opts, iters, workspace, workspace_bytes);
 }
 
 }  // extern "C"

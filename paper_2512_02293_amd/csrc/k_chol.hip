@@ -4,6 +4,9 @@
 // the right-hand side stored as row npad, so the blocked factorisation carries
 // the forward substitution along: at the end row npad holds y = L^-1 s.
 //
+// Every window of a batch has its own system (blockIdx.y = window); windows
+// with fewer block columns than the step index simply exit.
+//
 // Right-looking, 64-wide block columns, ONE launch per block column kb:
 //   * panel workgroups (block rows r = kb .. nblk, nblk being the right-hand-
 //     side block) first apply the pending update of block column kb-1 to the
@@ -14,6 +17,8 @@
 //     (i, j) with j > kb, which later steps consume.
 // A single-workgroup pass then back-substitutes x = L^-T y block by block with
 // the stored inverses of the diagonal tiles (staged through LDS).
+#include <algorithm>
+
 #include "vi_internal.h"
 
 namespace vi {
@@ -55,11 +60,21 @@ __device__ __forceinline__ void tile_sub_abt(double* Cm, const double* P, const 
   }
 }
 
-__global__ void __launch_bounds__(256) k_chol_step(int n, int npad, int nblk, int kb, int n_panel,
-                                                   double* __restrict__ A, double* __restrict__ Linv,
-                                                   DevStatus* st) {
+__global__ void __launch_bounds__(256) k_chol_step(DevPlan D, int kb, double* __restrict__ Aall,
+                                                   double* __restrict__ Linvall, DevStatus* stall) {
   extern __shared__ double sm[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const WinDev& W = D.win[blockIdx.y];
+  const int n = W.n, npad = W.npad, nblk = W.nblk;
+  if (kb >= nblk) return;
+  const int n_panel = nblk - kb + 1;
+  int n_trail = 0;
+  if (kb > 0)
+    for (int jb = kb + 1; jb < nblk; ++jb) n_trail += nblk - jb + 1;
+  if ((int)blockIdx.x >= n_panel + n_trail) return;
+  double* A = Aall + W.A_off;
+  double* Linv = Linvall + W.Linv_off;
+  DevStatus* st = stall + blockIdx.y;
   const int k0 = kb * NB;
   if ((int)blockIdx.x >= n_panel) {
     // trailing tile (i, j), kb < j <= nblk - 1, j <= i <= nblk: apply block column kb-1
@@ -91,11 +106,11 @@ __global__ void __launch_bounds__(256) k_chol_step(int n, int npad, int nblk, in
   }
   // panel workgroup for block row r
   const int r0 = (kb + blockIdx.x) * NB;
-  double* D = sm;                  // diagonal tile -> L_kk
+  double* Dg = sm;                 // diagonal tile -> L_kk
   double* Lk = sm + NB * LD;       // L_kb,kb-1, later L_kk^-1
   double* X = sm + 2 * NB * LD;    // own tile
   double* Lr = sm + 3 * NB * LD;   // L_r,kb-1
-  load_tile(D, A, npad, k0, k0);
+  load_tile(Dg, A, npad, k0, k0);
   load_tile(X, A, npad, r0, k0);
   if (kb > 0) {
     load_tile(Lk, A, npad, k0, k0 - NB);
@@ -103,7 +118,7 @@ __global__ void __launch_bounds__(256) k_chol_step(int n, int npad, int nblk, in
   }
   __syncthreads();
   if (kb > 0) {
-    tile_sub_abt(D, Lk, Lk);
+    tile_sub_abt(Dg, Lk, Lk);
     if (blockIdx.x != 0) tile_sub_abt(X, Lr, Lk);
     __syncthreads();
   }
@@ -111,7 +126,7 @@ __global__ void __launch_bounds__(256) k_chol_step(int n, int npad, int nblk, in
   if (wave == 0) {
     double a[NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) a[c] = D[lane * LD + c];
+    for (int c = 0; c < NB; ++c) a[c] = Dg[lane * LD + c];
     int bad = -1;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
@@ -127,7 +142,7 @@ __global__ void __launch_bounds__(256) k_chol_step(int n, int npad, int nblk, in
       for (int m = j + 1; m < NB; ++m) a[m] -= a[j] * readlane_d(a[j], m);
     }
 #pragma unroll
-    for (int c = 0; c < NB; ++c) D[lane * LD + c] = (c <= lane) ? a[c] : 0.0;
+    for (int c = 0; c < NB; ++c) Dg[lane * LD + c] = (c <= lane) ? a[c] : 0.0;
     if (bad >= 0 && lane == 0 && blockIdx.x == 0 && k0 + bad < n) set_status(st, VI_ENOTPD, k0 + bad);
   }
   __syncthreads();
@@ -138,9 +153,9 @@ __global__ void __launch_bounds__(256) k_chol_step(int n, int npad, int nblk, in
     for (int r = 0; r < NB; ++r) x[r] = (r == lane) ? 1.0 : 0.0;
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
-      x[m] = x[m] / D[m * LD + m];
+      x[m] = x[m] / Dg[m * LD + m];
 #pragma unroll
-      for (int r = m + 1; r < NB; ++r) x[r] -= D[r * LD + m] * x[m];
+      for (int r = m + 1; r < NB; ++r) x[r] -= Dg[r * LD + m] * x[m];
     }
 #pragma unroll
     for (int r = 0; r < NB; ++r) Lk[r * LD + lane] = x[r];
@@ -149,7 +164,7 @@ __global__ void __launch_bounds__(256) k_chol_step(int n, int npad, int nblk, in
   if (blockIdx.x == 0) {
     for (int idx = tid; idx < NB * NB; idx += 256) {
       const int r = idx / NB, c = idx % NB;
-      A[(size_t)(k0 + r) * npad + k0 + c] = D[r * LD + c];
+      A[(size_t)(k0 + r) * npad + k0 + c] = Dg[r * LD + c];
       Linv[(size_t)kb * NB * NB + idx] = Lk[r * LD + c];
     }
     return;
@@ -169,13 +184,18 @@ __global__ void __launch_bounds__(256) k_chol_step(int n, int npad, int nblk, in
 }
 
 // x = L^-T y, block by block from the last; 1024 threads.
-__global__ void __launch_bounds__(1024) k_chol_solve(int n, int npad, int nblk, const double* __restrict__ A,
-                                                     const double* __restrict__ Linv, double* __restrict__ x) {
+__global__ void __launch_bounds__(1024) k_chol_solve(DevPlan D, const double* __restrict__ Aall,
+                                                     const double* __restrict__ Linvall, double* __restrict__ xall) {
   extern __shared__ double xs[];        // [npad]
   __shared__ double part[16][NB];
   __shared__ double tv[NB];
   __shared__ double Li[NB][LD];
   const int tid = threadIdx.x;
+  const WinDev& W = D.win[blockIdx.x];
+  const int n = W.n, npad = W.npad, nblk = W.nblk;
+  const double* A = Aall + W.A_off;
+  const double* Linv = Linvall + W.Linv_off;
+  double* x = xall + W.x_off;
   const double* y = A + (size_t)npad * npad;
   const int j = tid & (NB - 1), sl = tid >> 6;   // 64 columns x 16 row slices
   for (int b = nblk - 1; b >= 0; --b) {
@@ -214,18 +234,21 @@ void chol_set_attributes() {
   (void)hipFuncSetAttribute((const void*)k_chol_step, hipFuncAttributeMaxDynamicSharedMemorySize, (int)step_lds());
 }
 
-void launch_chol(hipStream_t s, const Plan& P, const Work& w, DevStatus* st) {
-  const int nblk = P.nblk;
-  for (int kb = 0; kb < nblk; ++kb) {
-    const int n_panel = nblk - kb + 1;
-    int trailing = 0;
-    if (kb > 0)
-      for (int jb = kb + 1; jb < nblk; ++jb) trailing += nblk - jb + 1;
-    hipLaunchKernelGGL(k_chol_step, dim3(n_panel + trailing), dim3(256), step_lds(), s, P.n, P.npad, nblk, kb,
-                       n_panel, w.A, w.Linv, st);
+void launch_chol(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, DevStatus* st) {
+  int npad_max = 0;
+  for (const WinDev& W : P.win) npad_max = std::max(npad_max, W.npad);
+  for (int kb = 0; kb < P.nblk_max; ++kb) {
+    int wgs = 0;
+    for (const WinDev& W : P.win) {
+      if (kb >= W.nblk) continue;
+      int cnt = W.nblk - kb + 1;
+      if (kb > 0)
+        for (int jb = kb + 1; jb < W.nblk; ++jb) cnt += W.nblk - jb + 1;
+      wgs = std::max(wgs, cnt);
+    }
+    hipLaunchKernelGGL(k_chol_step, dim3(wgs, P.n_win), dim3(256), step_lds(), s, D, kb, w.A, w.Linv, st);
   }
-  hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), sizeof(double) * P.npad, s, P.n, P.npad, nblk, w.A,
-                     w.Linv, w.x);
+  hipLaunchKernelGGL(k_chol_solve, dim3(P.n_win), dim3(1024), sizeof(double) * npad_max, s, D, w.A, w.Linv, w.x);
 }
 
 }  // namespace vi

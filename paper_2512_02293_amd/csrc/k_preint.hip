@@ -22,7 +22,8 @@ __device__ __forceinline__ void set_status(DevStatus* st, int code, int detail) 
 struct PreintLds {
   double dR[9], dv[3], dp[3], JR[9], Jvg[9], Jva[9], Jpg[9], Jpa[9];
   double nR[9], nv[3], np_[3], nJR[9], nJvg[9], nJva[9], nJpg[9], nJpa[9];
-  double dRk[9], Jrk[9], Ra[3], M1[9];   // per-sample: Exp(w h), Jr(w h), dR a, dR [a]x
+  double Ra[3], M1[9];                   // per-sample: dR a, dR [a]x
+  double pdRk[64][9], pJrk[64][9], pa[64][3], ph[64];   // 64 samples: Exp(w h), Jr(w h), a, h
   double M1JR[9];
   double A[81], Qn[81], T[81], cov[81];
 };
@@ -52,100 +53,115 @@ __global__ void __launch_bounds__(64) k_preint(int F, const int32_t* __restrict_
   double total = 0.0;
   __syncthreads();
 
-  for (int s = s0; s < s1; ++s) {
-    const double h = dt[s];
-    if (!(h > 0.0) || !isfinite(h)) {
-      if (l == 0) set_status(st, VI_EINVAL, s);
-    }
-    total += h;
-    const double w[3] = {(gyro[s * 3 + 0] - bg0) * h, (gyro[s * 3 + 1] - bg1) * h, (gyro[s * 3 + 2] - bg2) * h};
-    const double a[3] = {accel[s * 3 + 0] - ba0, accel[s * 3 + 1] - ba1, accel[s * 3 + 2] - ba2};
-    // phase 1: per-sample matrices (one lane each group)
-    if (l == 0) {
-      so3_exp(w, S.dRk);
-      so3_jr(w, S.Jrk);
-    } else if (l == 1) {
-      double Ra[3], ax[9], M1[9];
-      m3_vec(S.dR, a, Ra);
-      skew(a, ax);
-      m3_mul(S.dR, ax, M1);
-      for (int k = 0; k < 3; ++k) S.Ra[k] = Ra[k];
-      for (int k = 0; k < 9; ++k) S.M1[k] = M1[k];
+  for (int sb = s0; sb < s1; sb += 64) {
+    // per-sample quantities that do not depend on the running state, one lane each
+    const int nb = min(64, s1 - sb);
+    if (l < nb) {
+      const int s = sb + l;
+      const double h = dt[s];
+      if (!(h > 0.0) || !isfinite(h)) set_status(st, VI_EINVAL, s);
+      const double w[3] = {(gyro[s * 3 + 0] - bg0) * h, (gyro[s * 3 + 1] - bg1) * h, (gyro[s * 3 + 2] - bg2) * h};
+      so3_exp(w, S.pdRk[l]);
+      so3_jr(w, S.pJrk[l]);
+      S.pa[l][0] = accel[s * 3 + 0] - ba0;
+      S.pa[l][1] = accel[s * 3 + 1] - ba1;
+      S.pa[l][2] = accel[s * 3 + 2] - ba2;
+      S.ph[l] = h;
     }
     __syncthreads();
-    // phase 2: transition A, noise Qn, and M1 * J^rot
-    for (int e = l; e < 81; e += 64) {
-      const int r = e / 9, c = e % 9, br = r / 3, bc = c / 3, rr = r % 3, cc = c % 3;
-      double v = 0.0;
-      if (br == 0 && bc == 0) v = S.dRk[cc * 3 + rr];                       // dRk^T
-      else if (br == 1 && bc == 0) v = -S.M1[rr * 3 + cc] * h;               // -dR [a]x h
-      else if (br == 2 && bc == 0) v = -0.5 * S.M1[rr * 3 + cc] * h * h;    // -1/2 dR [a]x h^2
-      else if (br == 2 && bc == 1) v = (rr == cc) ? h : 0.0;                 // I h
-      else if (br == bc) v = (rr == cc) ? 1.0 : 0.0;
-      S.A[e] = v;
-      // noise: Bg (sg^2/h) Bg^T with Bg = [Jr h; 0; 0]; Ba (sa^2/h) Ba^T with
-      // Ba = [0; dR h; 1/2 dR h^2] and dR dR^T = I
-      double q = 0.0;
-      if (br == 0 && bc == 0) {
-        double jj = 0.0;
-        for (int m = 0; m < 3; ++m) jj += S.Jrk[rr * 3 + m] * S.Jrk[cc * 3 + m];
-        q = sg2 * h * jj;
-      } else if (br >= 1 && bc >= 1 && rr == cc) {
-        const double fr = (br == 1) ? h : 0.5 * h * h;
-        const double fc = (bc == 1) ? h : 0.5 * h * h;
-        q = sa2 / h * fr * fc;
+    for (int u = 0; u < nb; ++u) {
+      const double h = S.ph[u];
+      total += h;
+      const double* dRk = S.pdRk[u];
+      const double* Jrk = S.pJrk[u];
+      const double* a = S.pa[u];
+      // phase 1: dR a and dR [a]x (lanes 0..11)
+      if (l < 9) {
+        const int r = l / 3, c = l % 3;
+        // ([a]x)[m][c] = eps_{m c n}... written out: column c of [a]x
+        const double axc[3] = {c == 0 ? 0.0 : (c == 1 ? -a[2] : a[1]),
+                               c == 0 ? a[2] : (c == 1 ? 0.0 : -a[0]),
+                               c == 0 ? -a[1] : (c == 1 ? a[0] : 0.0)};
+        S.M1[l] = S.dR[r * 3 + 0] * axc[0] + S.dR[r * 3 + 1] * axc[1] + S.dR[r * 3 + 2] * axc[2];
+      } else if (l < 12) {
+        const int r = l - 9;
+        S.Ra[r] = S.dR[r * 3 + 0] * a[0] + S.dR[r * 3 + 1] * a[1] + S.dR[r * 3 + 2] * a[2];
       }
-      S.Qn[e] = q;
-    }
-    if (l < 9) {
-      const int r = l / 3, c = l % 3;
-      double v = 0.0;
-      for (int m = 0; m < 3; ++m) v += S.M1[r * 3 + m] * S.JR[m * 3 + c];
-      S.M1JR[l] = v;
-    }
-    __syncthreads();
-    // phase 3: T = A cov, and the new mean / Jacobians (old values on the right)
-    for (int e = l; e < 81; e += 64) {
-      const int r = e / 9, c = e % 9;
-      double v = 0.0;
-      for (int m = 0; m < 9; ++m) v += S.A[r * 9 + m] * S.cov[m * 9 + c];
-      S.T[e] = v;
-    }
-    if (l < 9) {
-      const int r = l / 3, c = l % 3;
-      const double hh = h * h;
-      S.nJpa[l] = S.Jpa[l] + S.Jva[l] * h - 0.5 * S.dR[l] * hh;
-      S.nJpg[l] = S.Jpg[l] + S.Jvg[l] * h - 0.5 * S.M1JR[l] * hh;
-      S.nJva[l] = S.Jva[l] - S.dR[l] * h;
-      S.nJvg[l] = S.Jvg[l] - S.M1JR[l] * h;
-      double v = 0.0, u = 0.0;
-      for (int m = 0; m < 3; ++m) {
-        v += S.dRk[m * 3 + r] * S.JR[m * 3 + c];     // dRk^T J^rot
-        u += S.dR[r * 3 + m] * S.dRk[m * 3 + c];     // dR dRk
+      __syncthreads();
+      // phase 2: transition A, noise Qn, and M1 * J^rot
+      for (int e = l; e < 81; e += 64) {
+        const int r = e / 9, c = e % 9, br = r / 3, bc = c / 3, rr = r % 3, cc = c % 3;
+        double v = 0.0;
+        if (br == 0 && bc == 0) v = dRk[cc * 3 + rr];                          // dRk^T
+        else if (br == 1 && bc == 0) v = -S.M1[rr * 3 + cc] * h;               // -dR [a]x h
+        else if (br == 2 && bc == 0) v = -0.5 * S.M1[rr * 3 + cc] * h * h;    // -1/2 dR [a]x h^2
+        else if (br == 2 && bc == 1) v = (rr == cc) ? h : 0.0;                 // I h
+        else if (br == bc) v = (rr == cc) ? 1.0 : 0.0;
+        S.A[e] = v;
+        // noise: Bg (sg^2/h) Bg^T with Bg = [Jr h; 0; 0]; Ba (sa^2/h) Ba^T with
+        // Ba = [0; dR h; 1/2 dR h^2] and dR dR^T = I
+        double q = 0.0;
+        if (br == 0 && bc == 0) {
+          double jj = 0.0;
+          for (int m = 0; m < 3; ++m) jj += Jrk[rr * 3 + m] * Jrk[cc * 3 + m];
+          q = sg2 * h * jj;
+        } else if (br >= 1 && bc >= 1 && rr == cc) {
+          const double fr = (br == 1) ? h : 0.5 * h * h;
+          const double fc = (bc == 1) ? h : 0.5 * h * h;
+          q = sa2 / h * fr * fc;
+        }
+        S.Qn[e] = q;
       }
-      S.nJR[l] = v - S.Jrk[l] * h;
-      S.nR[l] = u;
-    } else if (l >= 16 && l < 19) {
-      const int i = l - 16;
-      S.np_[i] = S.dp[i] + S.dv[i] * h + 0.5 * S.Ra[i] * h * h;
-      S.nv[i] = S.dv[i] + S.Ra[i] * h;
+      if (l < 9) {
+        const int r = l / 3, c = l % 3;
+        double v = 0.0;
+        for (int m = 0; m < 3; ++m) v += S.M1[r * 3 + m] * S.JR[m * 3 + c];
+        S.M1JR[l] = v;
+      }
+      __syncthreads();
+      // phase 3: T = A cov, and the new mean / Jacobians (old values on the right)
+      for (int e = l; e < 81; e += 64) {
+        const int r = e / 9, c = e % 9;
+        double v = 0.0;
+        for (int m = 0; m < 9; ++m) v += S.A[r * 9 + m] * S.cov[m * 9 + c];
+        S.T[e] = v;
+      }
+      if (l < 9) {
+        const int r = l / 3, c = l % 3;
+        const double hh = h * h;
+        S.nJpa[l] = S.Jpa[l] + S.Jva[l] * h - 0.5 * S.dR[l] * hh;
+        S.nJpg[l] = S.Jpg[l] + S.Jvg[l] * h - 0.5 * S.M1JR[l] * hh;
+        S.nJva[l] = S.Jva[l] - S.dR[l] * h;
+        S.nJvg[l] = S.Jvg[l] - S.M1JR[l] * h;
+        double v = 0.0, w = 0.0;
+        for (int m = 0; m < 3; ++m) {
+          v += dRk[m * 3 + r] * S.JR[m * 3 + c];     // dRk^T J^rot
+          w += S.dR[r * 3 + m] * dRk[m * 3 + c];     // dR dRk
+        }
+        S.nJR[l] = v - Jrk[l] * h;
+        S.nR[l] = w;
+      } else if (l >= 16 && l < 19) {
+        const int i = l - 16;
+        S.np_[i] = S.dp[i] + S.dv[i] * h + 0.5 * S.Ra[i] * h * h;
+        S.nv[i] = S.dv[i] + S.Ra[i] * h;
+      }
+      __syncthreads();
+      // phase 4: cov = T A^T + Qn; commit the mean
+      for (int e = l; e < 81; e += 64) {
+        const int r = e / 9, c = e % 9;
+        double v = 0.0;
+        for (int m = 0; m < 9; ++m) v += S.T[r * 9 + m] * S.A[c * 9 + m];
+        S.cov[e] = v + S.Qn[e];
+      }
+      if (l < 9) {
+        S.dR[l] = S.nR[l]; S.JR[l] = S.nJR[l];
+        S.Jvg[l] = S.nJvg[l]; S.Jva[l] = S.nJva[l]; S.Jpg[l] = S.nJpg[l]; S.Jpa[l] = S.nJpa[l];
+      } else if (l >= 16 && l < 19) {
+        S.dp[l - 16] = S.np_[l - 16];
+        S.dv[l - 16] = S.nv[l - 16];
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    // phase 4: cov = T A^T + Qn; commit the mean
-    for (int e = l; e < 81; e += 64) {
-      const int r = e / 9, c = e % 9;
-      double v = 0.0;
-      for (int m = 0; m < 9; ++m) v += S.T[r * 9 + m] * S.A[c * 9 + m];
-      S.cov[e] = v + S.Qn[e];
-    }
-    if (l < 9) {
-      S.dR[l] = S.nR[l]; S.JR[l] = S.nJR[l];
-      S.Jvg[l] = S.nJvg[l]; S.Jva[l] = S.nJva[l]; S.Jpg[l] = S.nJpg[l]; S.Jpa[l] = S.nJpa[l];
-    } else if (l >= 16 && l < 19) {
-      S.dp[l - 16] = S.np_[l - 16];
-      S.dv[l - 16] = S.nv[l - 16];
-    }
-    __syncthreads();
   }
 
   vi_preint* o = out + f;
@@ -176,14 +192,16 @@ __global__ void __launch_bounds__(64) k_preint(int F, const int32_t* __restrict_
 
 // Lambda = blkdiag(cov^-1, diag(1 / cov_bias)) per factor.  The 9x9 inverse
 // goes through a Cholesky factor in LDS (one lane per column of the inverse).
-__global__ void __launch_bounds__(64) k_imu_info(int F, const vi_preint* __restrict__ imu,
-                                                 double* __restrict__ Lam, DevStatus* st) {
+__global__ void __launch_bounds__(64) k_imu_info(int F, DevPlan D, double* __restrict__ Lam, DevStatus* stall) {
   __shared__ double C[81];
   __shared__ double Li[81];     // L^-1
   const int f = blockIdx.x;
   const int l = threadIdx.x;
   if (f >= F) return;
-  const vi_preint* P = imu + f;
+  const int w = D.win_of_f[f];
+  const WinDev& W = D.win[w];
+  const vi_preint* P = W.imu + (f - W.f_base);
+  DevStatus* st = stall + w;
   for (int e = l; e < 81; e += 64) C[e] = P->cov[e];
   __syncthreads();
   if (l == 0) {
@@ -201,7 +219,7 @@ __global__ void __launch_bounds__(64) k_imu_info(int F, const vi_preint* __restr
         C[i * 9 + k] = v / d;
       }
     }
-    if (!ok) set_status(st, VI_ENOTPD, -1 - f);
+    if (!ok) set_status(st, VI_ENOTPD, -1 - (f - W.f_base));
   }
   __syncthreads();
   if (l < 9) {
@@ -236,9 +254,9 @@ void launch_preint(hipStream_t s, int F, const int32_t* off, const double* gyro,
   hipLaunchKernelGGL(k_preint, dim3(F), dim3(64), 0, s, F, off, gyro, accel, dt, bias_hat, noise, out, st);
 }
 
-void launch_imu_info(hipStream_t s, int F, const vi_preint* imu, double* Lam, DevStatus* st) {
-  if (F <= 0) return;
-  hipLaunchKernelGGL(k_imu_info, dim3(F), dim3(64), 0, s, F, imu, Lam, st);
+void launch_imu_info(hipStream_t s, const Plan& P, const DevPlan& D, double* Lam, DevStatus* st) {
+  if (P.F <= 0) return;
+  hipLaunchKernelGGL(k_imu_info, dim3(P.F), dim3(64), 0, s, P.F, D, Lam, st);
 }
 
 }  // namespace vi

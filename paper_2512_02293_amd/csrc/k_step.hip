@@ -1,9 +1,10 @@
 // One damped Gauss-Newton step of the joint visual-inertial problem
-// (Sec. 3.1): vision residual and Jacobian per (edge, pixel) (Eq. 1), per-edge
-// J^T W J reduction, inertial factors (Eq. 2-3), elimination of the diagonal
-// inverse-depth block (Eq. 4), assembly of the reduced pose/velocity/bias
-// system, back-substitution of the depth increments and retraction.  The
-// Cholesky solve of the reduced system lives in k_chol.hip.
+// (Sec. 3.1), for a batch of independent windows: vision residual and
+// Jacobian per (edge, pixel) (Eq. 1), per-edge J^T W J reduction, inertial
+// factors (Eq. 2-3), elimination of the diagonal inverse-depth block (Eq. 4),
+// assembly of each window's reduced pose/velocity/bias system,
+// back-substitution of the depth increments and retraction.  The Cholesky
+// solve of the reduced systems lives in k_chol.hip.
 //
 // Local edge coordinates.  For an edge e = (i -> j) and a source pixel with
 // scaled point P = R_ji q + t_ji d (q = K^-1 [x y 1]^T), a perturbation of the
@@ -78,13 +79,8 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ void imu_factor_block(int f, const CamDev& cam, const double* __restrict__ pose,
-                                 const double* __restrict__ vel, const double* __restrict__ bias,
-                                 const vi_preint* __restrict__ imu, const double* __restrict__ Lam,
-                                 double* __restrict__ Hf, double* __restrict__ gf, double* __restrict__ icost,
-                                 double* sm);
-
-// relative transform of edge (i -> j): R_ji = R_j^T R_i, t_ji = R_j^T (p_i - p_j)
+// relative transform of edge (i -> j) of one window: R_ji = R_j^T R_i,
+// t_ji = R_j^T (p_i - p_j); i, j are indices into the window's pose array
 __device__ __forceinline__ void edge_rel(const double* __restrict__ pose, int i, int j, double* o) {
   double Ri[9], Rj[9], Rji[9], dp[3], tji[3];
   quat_to_rot(pose + (size_t)i * 7 + 3, Ri);
@@ -97,133 +93,52 @@ __device__ __forceinline__ void edge_rel(const double* __restrict__ pose, int i,
 }
 
 // ---------------------------------------------------------------------------
-// vision assembly: one workgroup per (source keyframe, 256-pixel range), one
-// lane per pixel, loop over the source's outgoing edges.  Per pixel: C, w_d and
-// the 6 local E-entries per edge; per edge: the local 6x6 Hessian (21) and
-// gradient (6), reduced over the wave by reduce_scatter32 into LDS.
+// Linearisation of one (source pixel, edge) pair in local edge coordinates:
+// residual r = target - projection, the 2x6 local Jacobian rows Jx, Jy, the
+// depth Jacobian (Jdx, Jdy) and the weights; everything zero when the pair is
+// not valid (inverse depth <= 0, or depth in camera j <= z_min).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_vis_assemble(
-    CamDev cam, OptsDev o, DevPlan D, int N, int nkr, const double* __restrict__ pose,
-    const double* __restrict__ vel, const double* __restrict__ bias, const double* __restrict__ invdepth,
-    const float* __restrict__ target, const float* __restrict__ weight, int F, const vi_preint* __restrict__ imu,
-    const double* __restrict__ Lam, double* __restrict__ Rw, double* __restrict__ rel, double* __restrict__ L,
-    double* __restrict__ Cd, double* __restrict__ wd, double* __restrict__ hpart, double* __restrict__ vcost,
-    double* __restrict__ Hf, double* __restrict__ gf, double* __restrict__ icost) {
-  extern __shared__ double sm[];
-  __shared__ double red[2][4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if ((int)blockIdx.y >= N) {
-    // inertial factors ride along as extra workgroups
-    const int f = ((int)blockIdx.y - N) * nkr + (int)blockIdx.x;
-    if (f < F && o.use_imu) imu_factor_block(f, cam, pose, vel, bias, imu, Lam, Hf, gf, icost, sm);
-    return;
-  }
-  const int src = blockIdx.y, kr = blockIdx.x;
-  const int HW = cam.H * cam.W;
-  const int e0 = D.src_off[src];
-  const int k = D.src_off[src + 1] - e0;
-  double* rel_s = sm;              // [k][12]
-  double* acc = sm + k * 12;       // [4][k][32]
-  if (tid < k) {
-    const int e = D.src_edges[e0 + tid];
-    edge_rel(pose, src, D.jj[e], rel_s + tid * 12);
-    if (kr == 0)
-      for (int q = 0; q < 12; ++q) rel[(size_t)e * 12 + q] = rel_s[tid * 12 + q];
-  }
-  if (kr == 0 && tid == 0) {
-    double R[9];
-    quat_to_rot(pose + (size_t)src * 7 + 3, R);
-    for (int q = 0; q < 9; ++q) Rw[(size_t)src * 9 + q] = R[q];
-  }
-  for (int i = tid; i < 4 * k * 32; i += 256) acc[i] = 0.0;
-  __syncthreads();
+struct PixEdge {
+  double Jx[6], Jy[6], Jdx, Jdy, rx, ry, wx, wy;
+  bool valid;
+};
 
-  const int p = kr * kVisBlock + tid;
-  const bool inpx = p < HW;
-  const int pc = inpx ? p : 0;
-  const double qx = ((double)(pc % cam.W) - cam.cx) / cam.fx;
-  const double qy = ((double)(pc / cam.W) - cam.cy) / cam.fy;
-  const double d = invdepth[(size_t)src * HW + pc];
-  const int ncol = 6 * k;
-  double* Lp = L + (size_t)HW * 6 * e0 + (size_t)pc * ncol;
-  double C = 0.0, wdv = 0.0, cost = 0.0, nval = 0.0;
-
-  for (int s = 0; s < k; ++s) {
-    const int e = D.src_edges[e0 + s];
-    const double* Rt = rel_s + s * 12;
-    const double Px = Rt[0] * qx + Rt[1] * qy + Rt[2] + Rt[9] * d;
-    const double Py = Rt[3] * qx + Rt[4] * qy + Rt[5] + Rt[10] * d;
-    const double Pz = Rt[6] * qx + Rt[7] * qy + Rt[8] + Rt[11] * d;
-    const bool valid = inpx && d > 0.0 && Pz > o.z_min * d;
-    const size_t toff = (size_t)e * 2 * HW + pc;
-    const double tx = target[toff], ty = target[toff + HW];
-    const double wx = valid ? (double)weight[toff] : 0.0;
-    const double wy = valid ? (double)weight[toff + HW] : 0.0;
-    double Jx[6], Jy[6], Jdx = 0.0, Jdy = 0.0, rx = 0.0, ry = 0.0;
-    if (valid) {
-      const double iz = 1.0 / Pz;
-      const double xp = Px * iz, yp = Py * iz, dz = d * iz;
-      rx = tx - (cam.fx * xp + cam.cx);
-      ry = ty - (cam.fy * yp + cam.cy);
-      Jx[0] = cam.fx * xp * yp;  Jx[1] = -cam.fx * (1.0 + xp * xp); Jx[2] = cam.fx * yp;
-      Jx[3] = -cam.fx * dz;      Jx[4] = 0.0;                       Jx[5] = cam.fx * xp * dz;
-      Jy[0] = cam.fy * (1.0 + yp * yp); Jy[1] = -cam.fy * xp * yp;  Jy[2] = -cam.fy * xp;
-      Jy[3] = 0.0;               Jy[4] = -cam.fy * dz;              Jy[5] = cam.fy * yp * dz;
-      Jdx = -cam.fx * iz * (Rt[9] - xp * Rt[11]);
-      Jdy = -cam.fy * iz * (Rt[10] - yp * Rt[11]);
-      nval += 1.0;
-    } else {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) { Jx[c] = 0.0; Jy[c] = 0.0; }
+__device__ __forceinline__ void pix_edge(const WinDev& W, const OptsDev& o, const double* Rt, double qx, double qy,
+                                         double d, bool inpx, const float* __restrict__ target,
+                                         const float* __restrict__ weight, size_t toff, bool want_res,
+                                         PixEdge& q) {
+  const double Px = Rt[0] * qx + Rt[1] * qy + Rt[2] + Rt[9] * d;
+  const double Py = Rt[3] * qx + Rt[4] * qy + Rt[5] + Rt[10] * d;
+  const double Pz = Rt[6] * qx + Rt[7] * qy + Rt[8] + Rt[11] * d;
+  q.valid = inpx && d > 0.0 && Pz > o.z_min * d;
+  q.wx = q.valid ? (double)weight[toff] : 0.0;
+  q.wy = q.valid ? (double)weight[toff + W.HW] : 0.0;
+  q.rx = 0.0;
+  q.ry = 0.0;
+  if (q.valid) {
+    const double iz = 1.0 / Pz;
+    const double xp = Px * iz, yp = Py * iz, dz = d * iz;
+    if (want_res) {
+      q.rx = (double)target[toff] - (W.fx * xp + W.cx);
+      q.ry = (double)target[toff + W.HW] - (W.fy * yp + W.cy);
     }
-    C += wx * Jdx * Jdx + wy * Jdy * Jdy;
-    wdv -= wx * Jdx * rx + wy * Jdy * ry;
-    cost += wx * rx * rx + wy * ry * ry;
-    const double ax = wx * Jdx, ay = wy * Jdy;
-    if (inpx) {
+    q.Jx[0] = W.fx * xp * yp;  q.Jx[1] = -W.fx * (1.0 + xp * xp); q.Jx[2] = W.fx * yp;
+    q.Jx[3] = -W.fx * dz;      q.Jx[4] = 0.0;                     q.Jx[5] = W.fx * xp * dz;
+    q.Jy[0] = W.fy * (1.0 + yp * yp); q.Jy[1] = -W.fy * xp * yp;  q.Jy[2] = -W.fy * xp;
+    q.Jy[3] = 0.0;             q.Jy[4] = -W.fy * dz;              q.Jy[5] = W.fy * yp * dz;
+    q.Jdx = -W.fx * iz * (Rt[9] - xp * Rt[11]);
+    q.Jdy = -W.fy * iz * (Rt[10] - yp * Rt[11]);
+  } else {
 #pragma unroll
-      for (int c = 0; c < 6; ++c) Lp[6 * s + c] = ax * Jx[c] + ay * Jy[c];
-    }
-    double v[32];
-    int q = 0;
-    const double bx = wx * rx, by = wy * ry;
-#pragma unroll
-    for (int a = 0; a < 6; ++a) {
-      const double px = wx * Jx[a], py = wy * Jy[a];
-#pragma unroll
-      for (int b = a; b < 6; ++b) v[q++] = px * Jx[b] + py * Jy[b];
-    }
-#pragma unroll
-    for (int a = 0; a < 6; ++a) v[21 + a] = -(Jx[a] * bx + Jy[a] * by);
-#pragma unroll
-    for (int a = 27; a < 32; ++a) v[a] = 0.0;
-    const double tot = reduce_scatter32(v, lane);
-    if ((lane & 1) == 0 && (lane >> 1) < 27) acc[(wave * k + s) * 32 + (lane >> 1)] += tot;
-  }
-  if (inpx) {
-    Cd[(size_t)src * HW + p] = C + o.eta;
-    wd[(size_t)src * HW + p] = wdv;
-  }
-  cost = wave_sum(cost);
-  nval = wave_sum(nval);
-  if (lane == 0) { red[0][wave] = cost; red[1][wave] = nval; }
-  __syncthreads();
-  if (tid == 0) {
-    const size_t b = ((size_t)src * nkr + kr) * 2;
-    vcost[b] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    vcost[b + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
-  }
-  for (int i = tid; i < k * 27; i += 256) {
-    const int s = i / 27, c = i % 27;
-    const double t = acc[(0 * k + s) * 32 + c] + acc[(1 * k + s) * 32 + c] + acc[(2 * k + s) * 32 + c] +
-                     acc[(3 * k + s) * 32 + c];
-    hpart[((size_t)(e0 + s) * nkr + kr) * 32 + c] = t;
+    for (int c = 0; c < 6; ++c) { q.Jx[c] = 0.0; q.Jy[c] = 0.0; }
+    q.Jdx = 0.0;
+    q.Jdy = 0.0;
   }
 }
 
 // ---------------------------------------------------------------------------
-// inertial factors (Eq. 3): residual, 15x30 Jacobian, H = J^T Lambda J,
-// g = -J^T Lambda r, cost r^T Lambda r.  One 64-lane workgroup per factor.
+// inertial factors (Eq. 3): residual, 15x30 Jacobian (NULL J: residual only).
+// i is the index of the earlier keyframe in the window's arrays.
 // ---------------------------------------------------------------------------
 __device__ void imu_residual_jacobian(const double* pose, const double* vel, const double* bias,
                                       const vi_preint* P, const double* g, int i, double* r, double* J) {
@@ -271,7 +186,6 @@ __device__ void imu_residual_jacobian(const double* pose, const double* vel, con
   so3_jr_inv(rr, Jri);
   so3_jr(phi, Jrp);
   so3_exp(rr, Er);
-  // rotation rows
   double RjRi[9];
   m3_tmul(Rj, Ri, RjRi);
   m3_mul(Jri, RjRi, T1);
@@ -307,21 +221,20 @@ __device__ void imu_residual_jacobian(const double* pose, const double* vel, con
 }
 
 // One inertial factor per 256-thread workgroup (runs as extra workgroups of the
-// vision-assembly launch).  LDS: J (450), T (450), Lambda (225), r (15).
-__device__ void imu_factor_block(int f, const CamDev& cam, const double* __restrict__ pose,
-                                 const double* __restrict__ vel, const double* __restrict__ bias,
-                                 const vi_preint* __restrict__ imu, const double* __restrict__ Lam,
-                                 double* __restrict__ Hf, double* __restrict__ gf, double* __restrict__ icost,
-                                 double* sm) {
+// vision-assembly launch): H = J^T Lambda J, g = -J^T Lambda r, r^T Lambda r.
+// LDS: J (450), T (450), Lambda (225), r (15).  f is the global factor index.
+__device__ void imu_factor_block(int f, const WinDev& W, const double* __restrict__ Lam, double* __restrict__ Hf,
+                                 double* __restrict__ gf, double* __restrict__ icost, double* sm) {
   double* J = sm;
   double* T = J + 450;
   double* Lm = T + 450;
   double* r = Lm + 225;
   const int l = threadIdx.x;
+  const int lf = f - W.f_base;
   for (int e = l; e < 450; e += 256) J[e] = 0.0;
   for (int e = l; e < 225; e += 256) Lm[e] = Lam[(size_t)f * 225 + e];
   __syncthreads();
-  if (l == 0) imu_residual_jacobian(pose, vel, bias, imu + f, cam.g, f, r, J);
+  if (l == 0) imu_residual_jacobian(W.pose, W.vel, W.bias, W.imu + lf, W.g, lf, r, J);
   __syncthreads();
   for (int e = l; e < 450; e += 256) {
     const int a = e / 15, b = e % 15;
@@ -353,15 +266,21 @@ __device__ void imu_factor_block(int f, const CamDev& cam, const double* __restr
 }
 
 // ---------------------------------------------------------------------------
-// Schur Gram per source keyframe on FP64 MFMA:
-//   Q' = sum_p [L_p; w_d,p] [L_p; w_d,p]^T / Cd_p     ((6k+1) x (6k+1))
-// where L_p stacks the 6 local E-entries of the k outgoing edges.  Row 6k gives
-// sum_p L_p w_d,p / Cd_p.  Lower-triangular 16x16 tiles; 64 pixels are staged
-// in LDS per pass; each wave owns every fourth tile.
-// MFMA f64 16x16x4 operand layout: lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; it receives D[l/16 + 4 r][l%16] in element r.
+// Fused vision assembly and Schur Gram.  One workgroup per (source keyframe,
+// pixel range), walked in chunks of 64 pixels; lane = pixel, wave w takes the
+// source's edges w, w+4, ...  Per (pixel, edge): residual and Jacobians; per
+// pixel: C and w_d; per edge: the local 6x6 Hessian (21) and gradient (6),
+// reduced over the wave (reduce_scatter32) into lane registers; the 6 local
+// E-entries of every (pixel, edge) go to an LDS tile [64 px][6k | w_d], on
+// which the four waves then run the Gram
+//   Q' = sum_p [L_p; w_d,p][L_p; w_d,p]^T / C_p
+// on FP64 MFMA 16x16x4 over lower-triangular 16x16 tiles.  The E-block never
+// leaves the chip.  MFMA operand layout: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16]; it receives D[l/16 + 4 r][l%16] in element r.  Inertial
+// factors ride along as extra workgroups (blockIdx.y >= N).
 // ---------------------------------------------------------------------------
-constexpr int kMaxTilesPerWave = 8;
+constexpr int kMaxTilesPerWave = 7;     // T <= 7 for 6k+1 <= 112
+constexpr int kEdgeSlots = (kMaxOutDegree + 3) / 4;
 
 __device__ __forceinline__ void tile_ij(int t, int& I, int& J) {
   int i = 0;
@@ -370,50 +289,124 @@ __device__ __forceinline__ void tile_ij(int t, int& I, int& J) {
   J = t - i * (i + 1) / 2;
 }
 
-__global__ void __launch_bounds__(256) k_gram(int HW, int nkr, DevPlan D, const double* __restrict__ L,
-                                              const double* __restrict__ Cd, const double* __restrict__ wd,
-                                              double* __restrict__ gpart) {
+__global__ void __launch_bounds__(256) k_vis_gram(OptsDev o, DevPlan D, int N, int F, int nkr_max, int ncost,
+                                                  int range, const double* __restrict__ Lam, double* __restrict__ Rw,
+                                                  double* __restrict__ rel, double* __restrict__ Cd,
+                                                  double* __restrict__ wd, double* __restrict__ hpart,
+                                                  double* __restrict__ gpart, double* __restrict__ vcost,
+                                                  double* __restrict__ Hf, double* __restrict__ gf,
+                                                  double* __restrict__ icost) {
   extern __shared__ double sm[];
+  __shared__ double red[2][4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if ((int)blockIdx.y >= N) {
+    const int f = ((int)blockIdx.y - N) * (int)gridDim.x + (int)blockIdx.x;
+    if (f < F && o.use_imu) {
+      const WinDev W = D.win[D.win_of_f[f]];
+      imu_factor_block(f, W, Lam, Hf, gf, icost, sm);
+    }
+    return;
+  }
   const int src = blockIdx.y, kr = blockIdx.x;
+  const WinDev W = D.win[D.win_of_kf[src]];
+  const int HW = W.HW;
+  const int p_beg = kr * range;
+  if (p_beg >= HW) return;
+  const int p_end = min(HW, p_beg + range);
+  const int ls = src - W.kf_base;
   const int e0 = D.src_off[src];
   const int k = D.src_off[src + 1] - e0;
-  if (k == 0) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int ncol = 6 * k;
   const int T = (ncol + 16) / 16;
   const int LDW = 16 * T;
   const int ntiles = T * (T + 1) / 2;
-  double* tile = sm;                 // [64][LDW]
-  double* invcd = sm + 64 * LDW;     // [64]
-  const int p_beg = kr * kGramRange;
-  const int p_end = min(HW, p_beg + kGramRange);
-  const double* Ls = L + (size_t)HW * 6 * e0;
-  double4_t acc[kMaxTilesPerWave];
+  double* rel_s = sm;                             // [kMaxOutDegree][12]
+  double* Lt = rel_s + kMaxOutDegree * 12;        // [64][LDW]
+  double* part = Lt + 64 * LDW;                   // [2][4][64]
+  double* invcd = part + 512;                     // [64]
+  if (tid < k) {
+    const int e = D.src_edges[e0 + tid];
+    edge_rel(W.pose, ls, D.jj[e] - W.kf_base, rel_s + tid * 12);
+    if (kr == 0)
+      for (int q = 0; q < 12; ++q) rel[(size_t)e * 12 + q] = rel_s[tid * 12 + q];
+  }
+  if (kr == 0 && tid == 0) {
+    double R[9];
+    quat_to_rot(W.pose + (size_t)ls * 7 + 3, R);
+    for (int q = 0; q < 9; ++q) Rw[(size_t)src * 9 + q] = R[q];
+  }
+  for (int i = tid; i < 64 * LDW; i += 256) Lt[i] = 0.0;
+  __syncthreads();
+
+  const double* dsrc = W.invdepth + (size_t)ls * HW;
+  double* Cds = Cd + W.pix_base + (size_t)ls * HW;
+  double* wds = wd + W.pix_base + (size_t)ls * HW;
+  double acc_e[kEdgeSlots];
+#pragma unroll
+  for (int u = 0; u < kEdgeSlots; ++u) acc_e[u] = 0.0;
+  double4_t gacc[kMaxTilesPerWave];
   int tI[kMaxTilesPerWave], tJ[kMaxTilesPerWave];
 #pragma unroll
   for (int u = 0; u < kMaxTilesPerWave; ++u) {
-    acc[u] = double4_t{0.0, 0.0, 0.0, 0.0};
+    gacc[u] = double4_t{0.0, 0.0, 0.0, 0.0};
     const int t = wave + 4 * u;
     int I = 0, J = 0;
     if (t < ntiles) tile_ij(t, I, J);
     tI[u] = I;
     tJ[u] = J;
   }
-  for (int c0 = p_beg; c0 < p_end; c0 += kGramChunk) {
-    for (int idx = tid; idx < 64 * LDW; idx += 256) {
-      const int pp = idx / LDW, c = idx - pp * LDW;
-      const int p = c0 + pp;
-      double v = 0.0;
-      if (p < p_end) {
-        if (c < ncol) v = Ls[(size_t)p * ncol + c];
-        else if (c == ncol) v = wd[(size_t)src * HW + p];
+  double cost = 0.0, nval = 0.0;
+  for (int c0 = p_beg; c0 < p_end; c0 += 64) {
+    const int p = c0 + lane;
+    const bool inpx = p < p_end;
+    const int pc = inpx ? p : p_beg;
+    const double qx = ((double)(pc % W.W) - W.cx) / W.fx;
+    const double qy = ((double)(pc / W.W) - W.cy) / W.fy;
+    const double d = dsrc[pc];
+    double Cp = 0.0, Wp = 0.0;
+#pragma unroll
+    for (int u = 0; u < kEdgeSlots; ++u) {
+      const int s = wave + 4 * u;
+      if (s < k) {
+        const int e = D.src_edges[e0 + s];
+        PixEdge q;
+        pix_edge(W, o, rel_s + s * 12, qx, qy, d, inpx, W.target, W.weight,
+                 (size_t)(e - W.e_base) * 2 * HW + pc, true, q);
+        Cp += q.wx * q.Jdx * q.Jdx + q.wy * q.Jdy * q.Jdy;
+        Wp -= q.wx * q.Jdx * q.rx + q.wy * q.Jdy * q.ry;
+        cost += q.wx * q.rx * q.rx + q.wy * q.ry * q.ry;
+        nval += q.valid ? 1.0 : 0.0;
+        const double ax = q.wx * q.Jdx, ay = q.wy * q.Jdy;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) Lt[lane * LDW + 6 * s + c] = ax * q.Jx[c] + ay * q.Jy[c];
+        double v[32];
+        int m = 0;
+        const double bx = q.wx * q.rx, by = q.wy * q.ry;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+          const double px = q.wx * q.Jx[a], py = q.wy * q.Jy[a];
+#pragma unroll
+          for (int b = a; b < 6; ++b) v[m++] = px * q.Jx[b] + py * q.Jy[b];
+        }
+#pragma unroll
+        for (int a = 0; a < 6; ++a) v[21 + a] = -(q.Jx[a] * bx + q.Jy[a] * by);
+#pragma unroll
+        for (int a = 27; a < 32; ++a) v[a] = 0.0;
+        acc_e[u] += reduce_scatter32(v, lane);
       }
-      tile[idx] = v;
     }
-    if (tid < 64) {
-      const int p = c0 + tid;
-      const double cd = (p < p_end) ? Cd[(size_t)src * HW + p] : 0.0;
-      invcd[tid] = (cd > 0.0) ? 1.0 / cd : 0.0;
+    part[wave * 64 + lane] = Cp;
+    part[256 + wave * 64 + lane] = Wp;
+    __syncthreads();
+    if (wave == 0) {
+      const double C = part[lane] + part[64 + lane] + part[128 + lane] + part[192 + lane] + o.eta;
+      const double Wv = part[256 + lane] + part[320 + lane] + part[384 + lane] + part[448 + lane];
+      if (inpx) {
+        Cds[p] = C;
+        wds[p] = Wv;
+      }
+      invcd[lane] = (inpx && C > 0.0) ? 1.0 / C : 0.0;
+      Lt[lane * LDW + ncol] = inpx ? Wv : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -422,11 +415,11 @@ __global__ void __launch_bounds__(256) k_gram(int HW, int nkr, DevPlan D, const 
         const int ca = 16 * tI[u] + (lane & 15);
         const int cb = 16 * tJ[u] + (lane & 15);
 #pragma unroll 4
-        for (int kk = 0; kk < kGramChunk / 4; ++kk) {
+        for (int kk = 0; kk < 16; ++kk) {
           const int row = kk * 4 + (lane >> 4);
-          const double a = tile[row * LDW + ca];
-          const double b = tile[row * LDW + cb] * invcd[row];
-          acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+          const double a = Lt[row * LDW + ca];
+          const double b = Lt[row * LDW + cb] * invcd[row];
+          gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gacc[u], 0, 0, 0);
         }
       }
     }
@@ -440,9 +433,24 @@ __global__ void __launch_bounds__(256) k_gram(int HW, int nkr, DevPlan D, const 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = (lane >> 4) + 4 * r, n = lane & 15;
-        out[(size_t)t * 256 + m * 16 + n] = acc[u][r];
+        out[(size_t)t * 256 + m * 16 + n] = gacc[u][r];
       }
     }
+  }
+#pragma unroll
+  for (int u = 0; u < kEdgeSlots; ++u) {
+    const int s = wave + 4 * u;
+    if (s < k && (lane & 1) == 0 && (lane >> 1) < 27)
+      hpart[((size_t)(e0 + s) * nkr_max + kr) * 32 + (lane >> 1)] = acc_e[u];
+  }
+  cost = wave_sum(cost);
+  nval = wave_sum(nval);
+  if (lane == 0) { red[0][wave] = cost; red[1][wave] = nval; }
+  __syncthreads();
+  if (tid == 0) {
+    const size_t b = ((size_t)src * ncost + kr) * 2;
+    vcost[b] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    vcost[b + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
   }
 }
 
@@ -455,7 +463,8 @@ __global__ void __launch_bounds__(256) k_gram(int HW, int nkr, DevPlan D, const 
 //   ZV = G (g - y)                 its contribution to w_xi - E C^-1 w_d
 // Block by block: W_t = sum_s M_i,s^T X_st;  Z_00 = sum_t W_t M_i,t;
 // Z_0,t+1 = W_t M_j,t;  Z_s+1,t+1 = M_j,s^T X_st M_j,t.  The Gram partials
-// of every pixel range are summed straight into LDS first.
+// of every pixel range are summed straight into LDS first.  Extra workgroups
+// (one per window) reduce the cost partials into the window's cost trace.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double Mi_at(const double* Rt, const double* Rj, int r, int c) {
   // M_i = [[R_ji, 0], [[t]x R_ji, R_j^T]]
@@ -475,39 +484,50 @@ __device__ __forceinline__ double Mj_at(const double* Rj, int r, int c) {
   return -Rj[(c - 3) * 3 + (r - 3)];
 }
 
-__device__ void cost_reduce_block(int nv, const double* __restrict__ vcost, int F,
+// cost trace of window w: sum of its vision partials (ranges of range_px pixels
+// per source keyframe) and of its inertial factor costs
+__device__ void cost_reduce_block(const WinDev& W, int w, int ncost, int range_px, const double* __restrict__ vcost,
                                   const double* __restrict__ icost, int use_imu, double* __restrict__ trace,
                                   int slot, double* s0) {
   double* s1 = s0 + 256;
   const int t = threadIdx.x;
+  const int nk = (W.HW + range_px - 1) / range_px;
   double c = 0.0, n = 0.0;
-  for (int i = t; i < nv; i += 256) { c += vcost[2 * i]; n += vcost[2 * i + 1]; }
+  for (int i = t; i < W.N * nk; i += 256) {
+    const size_t b = ((size_t)(W.kf_base + i / nk) * ncost + i % nk) * 2;
+    c += vcost[b];
+    n += vcost[b + 1];
+  }
   if (use_imu)
-    for (int i = t; i < F; i += 256) c += icost[i];
+    for (int i = t; i < W.F; i += 256) c += icost[W.f_base + i];
   s0[t] = c;
   s1[t] = n;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (t < w) { s0[t] += s0[t + w]; s1[t] += s1[t + w]; }
+  for (int q = 128; q > 0; q >>= 1) {
+    if (t < q) { s0[t] += s0[t + q]; s1[t] += s1[t + q]; }
     __syncthreads();
   }
-  if (t == 0) { trace[2 * slot] = s0[0]; trace[2 * slot + 1] = s1[0]; }
+  if (t == 0) {
+    trace[(size_t)w * kTraceLen + 2 * slot] = s0[0];
+    trace[(size_t)w * kTraceLen + 2 * slot + 1] = s1[0];
+  }
 }
 
-__global__ void __launch_bounds__(256) k_local(int N, int nkr_vis, int nkr_gram, DevPlan D,
+__global__ void __launch_bounds__(256) k_local(int N, int nkr_max, int ncost, int range, DevPlan D,
                                                const double* __restrict__ Rw, const double* __restrict__ rel,
                                                const double* __restrict__ hpart,
                                                const double* __restrict__ gpart, double* __restrict__ Z,
                                                double* __restrict__ ZB, double* __restrict__ ZV,
-                                               const double* __restrict__ vcost, int F,
-                                               const double* __restrict__ icost, int use_imu,
-                                               double* __restrict__ trace, int slot) {
+                                               const double* __restrict__ vcost, const double* __restrict__ icost,
+                                               int use_imu, double* __restrict__ trace, int slot) {
   extern __shared__ double sm[];
-  if ((int)blockIdx.x == N) {
-    cost_reduce_block(N * nkr_vis, vcost, F, icost, use_imu, trace, slot, sm);
+  if ((int)blockIdx.x >= N) {
+    const int w = blockIdx.x - N;
+    cost_reduce_block(D.win[w], w, ncost, range, vcost, icost, use_imu, trace, slot, sm);
     return;
   }
   const int src = blockIdx.x;
+  const int nkr = D.win[D.win_of_kf[src]].nkr;
   const int e0 = D.src_off[src];
   const int k = D.src_off[src + 1] - e0;
   const int tid = threadIdx.x;
@@ -534,7 +554,7 @@ __global__ void __launch_bounds__(256) k_local(int N, int nkr_vis, int nkr_gram,
   for (int i = tid; i < ntiles * 256; i += 256) {
     const int t = i >> 8, e = i & 255;
     double v = 0.0;
-    for (int r = 0; r < nkr_gram; ++r) v += gp[((size_t)r * ntiles + t) * 256 + e];
+    for (int r = 0; r < nkr; ++r) v += gp[((size_t)r * ntiles + t) * 256 + e];
     int I = 0;
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
     const int J = t - I * (I + 1) / 2;
@@ -554,16 +574,16 @@ __global__ void __launch_bounds__(256) k_local(int N, int nkr_vis, int nkr_gram,
     const int a = min(r, c), b = max(r, c);
     const int q = a * 6 - a * (a - 1) / 2 + (b - a);
     double h = 0.0;
-    const double* hp = hpart + (size_t)(e0 + s) * nkr_vis * 32 + q;
-    for (int t = 0; t < nkr_vis; ++t) h += hp[(size_t)t * 32];
+    const double* hp = hpart + (size_t)(e0 + s) * nkr_max * 32 + q;
+    for (int t = 0; t < nkr; ++t) h += hp[(size_t)t * 32];
     Hs[i] = h;
   }
   __syncthreads();
   for (int i = tid; i < k * 6; i += 256) {
     const int s = i / 6, c = i % 6;
     double g = 0.0;
-    const double* hp = hpart + (size_t)(e0 + s) * nkr_vis * 32 + 21 + c;
-    for (int t = 0; t < nkr_vis; ++t) g += hp[(size_t)t * 32];
+    const double* hp = hpart + (size_t)(e0 + s) * nkr_max * 32 + 21 + c;
+    for (int t = 0; t < nkr; ++t) g += hp[(size_t)t * 32];
     gs[i] = g - Qs[ncol * nq + 6 * s + c];
   }
   // W_t = sum_s M_i,s^T X_st,  X_st = delta_st H_s - Q_st
@@ -629,10 +649,11 @@ __global__ void __launch_bounds__(256) k_local(int N, int nkr_vis, int nkr_gram,
 }
 
 // ---------------------------------------------------------------------------
-// reduced system: one lane per entry of the (npad + NB) x npad matrix whose
-// leading n x n block is S (damped, gauge/inactive rows replaced by identity),
-// whose row npad is the right-hand side s (so the Cholesky forward pass
-// produces L^-1 s in that row), and whose padding is the identity.
+// reduced system of each window (blockIdx.y): one lane per entry of the
+// (npad + NB) x npad matrix whose leading n x n block is S (damped, gauge and
+// inactive rows replaced by identity), whose row npad is the right-hand side s
+// (so the Cholesky forward pass produces L^-1 s in that row), and whose
+// padding is the identity.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool coord_active(const OptsDev& o, int a, int ra) {
   if (ra < 6) return a >= o.n_fixed;
@@ -641,21 +662,26 @@ __device__ __forceinline__ bool coord_active(const OptsDev& o, int a, int ra) {
   return true;
 }
 
-__global__ void k_assemble(int N, int n, int npad, OptsDev o, DevPlan D, const double* __restrict__ Z,
-                           const double* __restrict__ ZB, const double* __restrict__ ZV,
-                           const double* __restrict__ Hf, const double* __restrict__ gf,
-                           double* __restrict__ A, DevStatus* st) {
+__global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, const double* __restrict__ ZB,
+                           const double* __restrict__ ZV, const double* __restrict__ Hf,
+                           const double* __restrict__ gf, double* __restrict__ A, DevStatus* st) {
+  const int w = blockIdx.y;
+  const WinDev& W = D.win[w];
+  const int N = W.N, n = W.n, npad = W.npad;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t total = (size_t)(npad + kCholNB) * npad;
   if (idx >= total) return;
   const int r = (int)(idx / npad), c = (int)(idx % npad);
+  const double* Hw = Hf + (size_t)W.f_base * 900;
+  const double* gw = gf + (size_t)W.f_base * 30;
+  const int* poff = D.pair_off + W.pair_base;
   double val = 0.0;
   if (r < n && c < n) {
     const int a = r / 15, ra = r % 15, b = c / 15, cb = c % 15;
     if (coord_active(o, a, ra) && coord_active(o, b, cb)) {
       double bd = 0.0;
       if (ra < 6 && cb < 6) {
-        const int p0 = D.pair_off[a * N + b], p1 = D.pair_off[a * N + b + 1];
+        const int p0 = poff[a * N + b], p1 = poff[a * N + b + 1];
         for (int it = p0; it < p1; ++it) {
           val += Z[D.pair_z[it] + ra * 6 + cb];
           if (r == c) bd += ZB[D.pair_zb[it] + ra];
@@ -664,12 +690,12 @@ __global__ void k_assemble(int N, int n, int npad, OptsDev o, DevPlan D, const d
       if (o.use_imu) {
         double vi = 0.0;
         if (a == b) {
-          if (a > 0) vi += Hf[(size_t)(a - 1) * 900 + (15 + ra) * 30 + 15 + cb];
-          if (a < N - 1) vi += Hf[(size_t)a * 900 + ra * 30 + cb];
+          if (a > 0) vi += Hw[(size_t)(a - 1) * 900 + (15 + ra) * 30 + 15 + cb];
+          if (a < N - 1) vi += Hw[(size_t)a * 900 + ra * 30 + cb];
         } else if (b == a + 1) {
-          vi += Hf[(size_t)a * 900 + ra * 30 + 15 + cb];
+          vi += Hw[(size_t)a * 900 + ra * 30 + 15 + cb];
         } else if (a == b + 1) {
-          vi += Hf[(size_t)b * 900 + (15 + ra) * 30 + cb];
+          vi += Hw[(size_t)b * 900 + (15 + ra) * 30 + cb];
         }
         val += vi;
         if (r == c) bd += vi;
@@ -678,78 +704,80 @@ __global__ void k_assemble(int N, int n, int npad, OptsDev o, DevPlan D, const d
     } else {
       val = (r == c) ? 1.0 : 0.0;
     }
-    if (!isfinite(val)) set_status(st, VI_ENONFINITE, r);
+    if (!isfinite(val)) set_status(st + w, VI_ENONFINITE, r);
   } else if (r < npad) {
     val = (r == c) ? 1.0 : 0.0;
   } else if (r == npad && c < n) {
     const int b = c / 15, cb = c % 15;
     if (coord_active(o, b, cb)) {
       if (cb < 6) {
-        const int p0 = D.pair_off[b * N + b], p1 = D.pair_off[b * N + b + 1];
+        const int p0 = poff[b * N + b], p1 = poff[b * N + b + 1];
         for (int it = p0; it < p1; ++it) val += ZV[D.pair_zb[it] + cb];
       }
       if (o.use_imu) {
-        if (b > 0) val += gf[(size_t)(b - 1) * 30 + 15 + cb];
-        if (b < N - 1) val += gf[(size_t)b * 30 + cb];
+        if (b > 0) val += gw[(size_t)(b - 1) * 30 + 15 + cb];
+        if (b < N - 1) val += gw[(size_t)b * 30 + cb];
       }
     }
-    if (!isfinite(val)) set_status(st, VI_ENONFINITE, n + c);
+    if (!isfinite(val)) set_status(st + w, VI_ENONFINITE, n + c);
   }
-  A[idx] = val;
-}
-
-// cost trace: trace[slot] = (vision + inertial cost, valid pixel-residuals)
-__global__ void __launch_bounds__(256) k_cost_reduce(int nv, const double* __restrict__ vcost, int F,
-                                                     const double* __restrict__ icost, int use_imu,
-                                                     double* __restrict__ trace, int slot) {
-  __shared__ double s0[512];
-  cost_reduce_block(nv, vcost, F, icost, use_imu, trace, slot, s0);
+  A[W.A_off + idx] = val;
 }
 
 // ---------------------------------------------------------------------------
 // back-substitution (Eq. 4: dd = C^-1 (w_d - E^T dxi)) and retraction.  The
 // E^T dxi term is L_p . u with u_e = M_i,e dxi_i + M_j,e dxi_j (pose parts),
-// the local increment of each edge.  Blocks with blockIdx.y == N retract the
-// keyframe states.  Nothing is written if an earlier kernel raised an error.
+// the local increment of each edge; L_p is recomputed from the weights and the
+// Jacobians (cheaper than storing it).  Workgroups with blockIdx.y >= N retract
+// the keyframe states of window blockIdx.y - N.  A window whose status holds
+// an error is left untouched.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_backsub_retract(
-    CamDev cam, OptsDev o, int N, DevPlan D, const double* __restrict__ Rw, const double* __restrict__ rel,
-    const double* __restrict__ L, const double* __restrict__ Cd, const double* __restrict__ wd,
-    const double* __restrict__ x, double* __restrict__ pose, double* __restrict__ vel,
-    double* __restrict__ bias, double* __restrict__ invdepth, double* __restrict__ dd_out,
-    double* __restrict__ rep_dxi, DevStatus* st) {
-  extern __shared__ double sm[];
-  if (st->code != 0) return;
+__global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPlan D, const double* __restrict__ Rw,
+                                                         const double* __restrict__ rel,
+                                                         const double* __restrict__ Cd,
+                                                         const double* __restrict__ wd,
+                                                         const double* __restrict__ x, double* __restrict__ dd_ws,
+                                                         DevStatus* st) {
+  __shared__ double u[kMaxOutDegree * 6];
+  __shared__ double rel_s[kMaxOutDegree * 12];
   const int tid = threadIdx.x;
-  const int HW = cam.H * cam.W;
-  if ((int)blockIdx.y == N) {
-    if (blockIdx.x != 0) return;
-    for (int t = tid; t < N; t += 256) {
-      const double* dx = x + (size_t)t * 15;
-      double* q = pose + (size_t)t * 7;
+  if ((int)blockIdx.y >= N) {
+    const int w = blockIdx.y - N;
+    if (blockIdx.x != 0 || st[w].code != 0) return;
+    const WinDev& W = D.win[w];
+    const double* xw = x + W.x_off;
+    for (int t = tid; t < W.N; t += 256) {
+      const double* dx = xw + (size_t)t * 15;
+      double* q = W.pose + (size_t)t * 7;
       quat_retract(q + 3, dx);
       for (int k = 0; k < 3; ++k) {
         q[k] += dx[3 + k];
-        vel[(size_t)t * 3 + k] += dx[6 + k];
+        W.vel[(size_t)t * 3 + k] += dx[6 + k];
       }
-      for (int k = 0; k < 6; ++k) bias[(size_t)t * 6 + k] += dx[9 + k];
-      if (rep_dxi)
-        for (int k = 0; k < 15; ++k) rep_dxi[(size_t)t * 15 + k] = dx[k];
+      for (int k = 0; k < 6; ++k) W.bias[(size_t)t * 6 + k] += dx[9 + k];
+      if (W.rep_dxi)
+        for (int k = 0; k < 15; ++k) W.rep_dxi[(size_t)t * 15 + k] = dx[k];
     }
-    if (tid == 0) st->iters += 1;
+    if (tid == 0) st[w].iters += 1;
     return;
   }
   const int src = blockIdx.y;
+  const int w = D.win_of_kf[src];
+  const WinDev W = D.win[w];
+  const int HW = W.HW;
+  if (st[w].code != 0 || (int)blockIdx.x * 256 >= HW) return;
+  const int ls = src - W.kf_base;
   const int e0 = D.src_off[src];
   const int k = D.src_off[src + 1] - e0;
-  double* u = sm;    // [k][6]
+  const double* xw = x + W.x_off;
+  for (int i = tid; i < 12 * k; i += 256) rel_s[i] = rel[(size_t)D.src_edges[e0 + i / 12] * 12 + i % 12];
   for (int i = tid; i < 6 * k; i += 256) {
     const int s = i / 6, c = i % 6;
     const int e = D.src_edges[e0 + s];
     const double* Rt = rel + (size_t)e * 12;
     const double* Rj = Rw + (size_t)D.jj[e] * 9;
-    const double* xi = x + (size_t)src * 15;
-    const double* xj = x + (size_t)D.jj[e] * 15;
+    const double* xi = xw + (size_t)ls * 15;
+    const double* xj = xw + (size_t)(D.jj[e] - W.kf_base) * 15;
     double v = 0.0;
     for (int m = 0; m < 6; ++m) v += Mi_at(Rt, Rj, c, m) * xi[m] + Mj_at(Rj, c, m) * xj[m];
     u[i] = v;
@@ -757,47 +785,60 @@ __global__ void __launch_bounds__(256) k_backsub_retract(
   __syncthreads();
   const int p = blockIdx.x * 256 + tid;
   if (p >= HW) return;
-  const size_t pi = (size_t)src * HW + p;
+  const size_t pl = (size_t)ls * HW + p;
+  const size_t pi = W.pix_base + pl;
   const double cd = Cd[pi];
+  double* dep = W.invdepth + pl;
+  const double d = *dep;
   double ddv = 0.0;
   if (cd > 0.0 && k > 0) {
-    const double* Lp = L + (size_t)HW * 6 * e0 + (size_t)p * 6 * k;
+    // E^T dxi at this pixel: sum over edges of L_e,p . u_e, with L = J_loc^T W J_d
+    const double qx = ((double)(p % W.W) - W.cx) / W.fx;
+    const double qy = ((double)(p / W.W) - W.cy) / W.fy;
     double et = 0.0;
-    for (int i = 0; i < 6 * k; ++i) et += Lp[i] * u[i];
+    for (int s = 0; s < k; ++s) {
+      const int e = D.src_edges[e0 + s];
+      PixEdge q;
+      pix_edge(W, o, rel_s + s * 12, qx, qy, d, true, nullptr, W.weight, (size_t)(e - W.e_base) * 2 * HW + p,
+               false, q);
+      const double ax = q.wx * q.Jdx, ay = q.wy * q.Jdy;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) et += (ax * q.Jx[c] + ay * q.Jy[c]) * u[s * 6 + c];
+    }
     ddv = (wd[pi] - et) / cd;
   }
-  const double dnew = fmax(invdepth[pi] + ddv, o.d_min);
-  invdepth[pi] = dnew;
-  dd_out[pi] = ddv;
+  *dep = fmax(d + ddv, o.d_min);
+  if (W.rep_dd) W.rep_dd[pl] = ddv;
+  else dd_ws[pi] = ddv;
 }
 
-__global__ void k_reset_status(DevStatus* st) {
-  if (threadIdx.x == 0) { st->code = 0; st->detail = 0; st->iters = 0; st->pad = 0; }
+__global__ void k_reset_status(DevStatus* st, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) { st[i].code = 0; st[i].detail = 0; st[i].iters = 0; st[i].pad = 0; }
 }
 
 // ---------------------------------------------------------------------------
 // cost at the current state (residuals only)
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_vis_cost(CamDev cam, OptsDev o, DevPlan D, int nkr,
-                                                  const double* __restrict__ pose,
-                                                  const double* __restrict__ invdepth,
-                                                  const float* __restrict__ target,
-                                                  const float* __restrict__ weight, double* __restrict__ vcost) {
+__global__ void __launch_bounds__(256) k_vis_cost(OptsDev o, DevPlan D, int ncost, double* __restrict__ vcost) {
   __shared__ double red[2][4];
   __shared__ double rel[kMaxOutDegree * 12];
   const int src = blockIdx.y, kr = blockIdx.x;
-  const int HW = cam.H * cam.W;
+  const WinDev W = D.win[D.win_of_kf[src]];
+  const int HW = W.HW;
+  if (kr * kVisBlock >= HW) return;
+  const int ls = src - W.kf_base;
   const int e0 = D.src_off[src];
   const int k = D.src_off[src + 1] - e0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid < k) edge_rel(pose, src, D.jj[D.src_edges[e0 + tid]], rel + tid * 12);
+  if (tid < k) edge_rel(W.pose, ls, D.jj[D.src_edges[e0 + tid]] - W.kf_base, rel + tid * 12);
   __syncthreads();
   const int p = kr * kVisBlock + tid;
   const bool inpx = p < HW;
   const int pc = inpx ? p : 0;
-  const double qx = ((double)(pc % cam.W) - cam.cx) / cam.fx;
-  const double qy = ((double)(pc / cam.W) - cam.cy) / cam.fy;
-  const double d = invdepth[(size_t)src * HW + pc];
+  const double qx = ((double)(pc % W.W) - W.cx) / W.fx;
+  const double qy = ((double)(pc / W.W) - W.cy) / W.fy;
+  const double d = W.invdepth[(size_t)ls * HW + pc];
   double cost = 0.0, nval = 0.0;
   for (int s = 0; s < k; ++s) {
     const int e = D.src_edges[e0 + s];
@@ -807,11 +848,11 @@ __global__ void __launch_bounds__(256) k_vis_cost(CamDev cam, OptsDev o, DevPlan
     const double Pz = Rt[6] * qx + Rt[7] * qy + Rt[8] + Rt[11] * d;
     const bool valid = inpx && d > 0.0 && Pz > o.z_min * d;
     if (valid) {
-      const size_t toff = (size_t)e * 2 * HW + pc;
+      const size_t toff = (size_t)(e - W.e_base) * 2 * HW + pc;
       const double iz = 1.0 / Pz;
-      const double rx = target[toff] - (cam.fx * Px * iz + cam.cx);
-      const double ry = target[toff + HW] - (cam.fy * Py * iz + cam.cy);
-      cost += (double)weight[toff] * rx * rx + (double)weight[toff + HW] * ry * ry;
+      const double rx = W.target[toff] - (W.fx * Px * iz + W.cx);
+      const double ry = W.target[toff + HW] - (W.fy * Py * iz + W.cy);
+      cost += (double)W.weight[toff] * rx * rx + (double)W.weight[toff + HW] * ry * ry;
       nval += 1.0;
     }
   }
@@ -820,19 +861,19 @@ __global__ void __launch_bounds__(256) k_vis_cost(CamDev cam, OptsDev o, DevPlan
   if (lane == 0) { red[0][wave] = cost; red[1][wave] = nval; }
   __syncthreads();
   if (tid == 0) {
-    const size_t b = ((size_t)src * nkr + kr) * 2;
+    const size_t b = ((size_t)src * ncost + kr) * 2;
     vcost[b] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
     vcost[b + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
   }
 }
 
-__global__ void k_imu_cost(int F, CamDev cam, const double* __restrict__ pose, const double* __restrict__ vel,
-                           const double* __restrict__ bias, const vi_preint* __restrict__ imu,
-                           const double* __restrict__ Lam, double* __restrict__ icost) {
+__global__ void k_imu_cost(int F, DevPlan D, const double* __restrict__ Lam, double* __restrict__ icost) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= F) return;
+  const WinDev& W = D.win[D.win_of_f[f]];
+  const int lf = f - W.f_base;
   double r[15];
-  imu_residual_jacobian(pose, vel, bias, imu + f, cam.g, f, r, nullptr);
+  imu_residual_jacobian(W.pose, W.vel, W.bias, W.imu + lf, W.g, lf, r, nullptr);
   const double* Lm = Lam + (size_t)f * 225;
   double c = 0.0;
   for (int a = 0; a < 15; ++a) {
@@ -843,83 +884,89 @@ __global__ void k_imu_cost(int F, CamDev cam, const double* __restrict__ pose, c
   icost[f] = c;
 }
 
+__global__ void __launch_bounds__(256) k_cost_reduce(int ncost, int range_px, DevPlan D,
+                                                     const double* __restrict__ vcost,
+                                                     const double* __restrict__ icost, int use_imu,
+                                                     double* __restrict__ trace, int slot) {
+  __shared__ double s0[512];
+  const int w = blockIdx.x;
+  cost_reduce_block(D.win[w], w, ncost, range_px, vcost, icost, use_imu, trace, slot, s0);
+}
+
 }  // namespace
 
-void launch_chol(hipStream_t s, const Plan& P, const Work& w, DevStatus* st);
-
 static size_t vis_lds(int kmax) {
-  const size_t vis = (size_t)kmax * 12 + 4 * (size_t)kmax * 32;
+  const size_t T = (6 * (size_t)kmax + 16) / 16;
+  const size_t vis = (size_t)kMaxOutDegree * 12 + 64 * 16 * T + 512 + 64;
   const size_t imu = 450 + 450 + 225 + 15;
   return sizeof(double) * std::max(vis, imu);
-}
-static size_t gram_lds(int kmax) {
-  const int T = (6 * kmax + 16) / 16;
-  return sizeof(double) * (64 * 16 * (size_t)T + 64);
 }
 static size_t local_lds(int kmax) {
   const size_t k = kmax, nq = 6 * k + 1;
   return sizeof(double) * std::max<size_t>(nq * nq + 4 * 36 * k + 6 * k, 512);
 }
 
-void launch_reset_status(hipStream_t s, DevStatus* st) {
-  hipLaunchKernelGGL(k_reset_status, dim3(1), dim3(64), 0, s, st);
+void launch_reset_status(hipStream_t s, DevStatus* st, int n) {
+  hipLaunchKernelGGL(k_reset_status, dim3((n + 63) / 64), dim3(64), 0, s, st, n);
 }
 
 void chol_set_attributes();
 
 void step_set_attributes(int kmax) {
   chol_set_attributes();
-  (void)hipFuncSetAttribute((const void*)k_vis_assemble, hipFuncAttributeMaxDynamicSharedMemorySize, (int)vis_lds(kmax));
-  (void)hipFuncSetAttribute((const void*)k_gram, hipFuncAttributeMaxDynamicSharedMemorySize, (int)gram_lds(kmax));
+  (void)hipFuncSetAttribute((const void*)k_vis_gram, hipFuncAttributeMaxDynamicSharedMemorySize, (int)vis_lds(kmax));
   (void)hipFuncSetAttribute((const void*)k_local, hipFuncAttributeMaxDynamicSharedMemorySize, (int)local_lds(kmax));
 }
 
-void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const CamDev& cam,
-                 const OptsDev& o, const vi_state& x, const float* target, const float* weight,
-                 const vi_preint* imu, int iter, double* rep_dxi, double* rep_dd, DevStatus* st,
-                 StageMark mark, void* mark_user) {
+// the fused assembly (with the inertial factors) and the local blocks
+static void launch_front(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o, int iter,
+                         StageMark mark, void* mark_user) {
   const int N = P.N;
   auto done = [&](int stage) { if (mark) mark(mark_user, stage); };
   const int F = (o.use_imu && P.F > 0) ? P.F : 0;
-  const int imu_rows = (F + P.nkr_vis - 1) / P.nkr_vis;
-  hipLaunchKernelGGL(k_vis_assemble, dim3(P.nkr_vis, N + imu_rows), dim3(256), vis_lds(P.kmax), s, cam, o, D, N,
-                     P.nkr_vis, x.pose, x.vel, x.bias, x.invdepth, target, weight, F, imu, w.Lam, w.Rw, w.rel,
-                     w.L, w.Cd, w.wd, w.hpart, w.vcost, w.Hf, w.gf, w.icost);
+  const int nkr_run = (P.hw_max + P.range - 1) / P.range;          // workgroups per source in x
+  const int imu_rows = (F + nkr_run - 1) / nkr_run;
+  const int ncost = cost_slots(P);
+  hipLaunchKernelGGL(k_vis_gram, dim3(nkr_run, N + imu_rows), dim3(256), vis_lds(P.kmax), s, o, D, N, F,
+                     P.nkr_max, ncost, P.range, w.Lam, w.Rw, w.rel, w.Cd, w.wd, w.hpart, w.gpart, w.vcost, w.Hf,
+                     w.gf, w.icost);
   done(kStVis);
-  hipLaunchKernelGGL(k_gram, dim3(P.nkr_gram, N), dim3(256), gram_lds(P.kmax), s, P.HW, P.nkr_gram, D, w.L,
-                     w.Cd, w.wd, w.gpart);
-  done(kStGram);
-  hipLaunchKernelGGL(k_local, dim3(N + 1), dim3(256), local_lds(P.kmax), s, N, P.nkr_vis, P.nkr_gram, D, w.Rw,
-                     w.rel, w.hpart, w.gpart, w.Z, w.ZB, w.ZV, w.vcost, F, w.icost, o.use_imu, w.trace, iter);
+  hipLaunchKernelGGL(k_local, dim3(N + P.n_win), dim3(256), local_lds(P.kmax), s, N, P.nkr_max, ncost, P.range, D,
+                     w.Rw, w.rel, w.hpart, w.gpart, w.Z, w.ZB, w.ZV, w.vcost, w.icost, o.use_imu, w.trace, iter);
   done(kStLocal);
-  const size_t total = (size_t)(P.npad + kCholNB) * P.npad;
-  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, N, P.n, P.npad, o, D,
-                     w.Z, w.ZB, w.ZV, w.Hf, w.gf, w.A, st);
+}
+
+void launch_tune_stages(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o,
+                        StageMark mark, void* mark_user) {
+  launch_front(s, P, D, w, o, 0, mark, mark_user);
+}
+
+void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o, int iter,
+                 DevStatus* st, StageMark mark, void* mark_user) {
+  const int N = P.N;
+  auto done = [&](int stage) { if (mark) mark(mark_user, stage); };
+  launch_front(s, P, D, w, o, iter, mark, mark_user);
+  size_t total_max = 0;
+  for (const WinDev& W : P.win) total_max = std::max(total_max, (size_t)(W.npad + kCholNB) * W.npad);
+  hipLaunchKernelGGL(k_assemble, dim3((unsigned)((total_max + 255) / 256), P.n_win), dim3(256), 0, s, o, D, w.Z,
+                     w.ZB, w.ZV, w.Hf, w.gf, w.A, st);
   done(kStAssemble);
-  launch_chol(s, P, w, st);
+  launch_chol(s, P, D, w, st);
   done(kStChol);
-  hipLaunchKernelGGL(k_backsub_retract, dim3((P.HW + 255) / 256, N + 1), dim3(256),
-                     sizeof(double) * 6 * P.kmax, s, cam, o, N, D, w.Rw, w.rel, w.L, w.Cd, w.wd, w.x, x.pose,
-                     x.vel, x.bias, x.invdepth, rep_dd ? rep_dd : w.dd, rep_dxi, st);
+  hipLaunchKernelGGL(k_backsub_retract, dim3((P.hw_max + 255) / 256, N + P.n_win), dim3(256), 0, s, o, N, D, w.Rw,
+                     w.rel, w.Cd, w.wd, w.x, w.dd, st);
   done(kStBacksub);
 }
 
-void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const CamDev& cam,
-                       const OptsDev& o, const vi_state& x, const float* target, const float* weight,
-                       const vi_preint* imu, int slot, DevStatus* st) {
-  (void)st;
+void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o, int slot) {
   const int N = P.N;
-  hipLaunchKernelGGL(k_vis_cost, dim3(P.nkr_vis, N), dim3(256), 0, s, cam, o, D, P.nkr_vis, x.pose, x.invdepth,
-                     target, weight, w.vcost);
+  const int ncost = cost_slots(P);
+  hipLaunchKernelGGL(k_vis_cost, dim3((P.hw_max + kVisBlock - 1) / kVisBlock, N), dim3(256), 0, s, o, D, ncost,
+                     w.vcost);
   if (o.use_imu && P.F > 0)
-    hipLaunchKernelGGL(k_imu_cost, dim3((P.F + 63) / 64), dim3(64), 0, s, P.F, cam, x.pose, x.vel, x.bias, imu,
-                       w.Lam, w.icost);
-  hipLaunchKernelGGL(k_cost_reduce, dim3(1), dim3(256), 0, s, N * P.nkr_vis, w.vcost, P.F, w.icost, o.use_imu,
-                     w.trace, slot);
-}
-
-size_t step_lds_max(int kmax) {
-  return std::max(std::max(vis_lds(kmax), gram_lds(kmax)), local_lds(kmax));
+    hipLaunchKernelGGL(k_imu_cost, dim3((P.F + 63) / 64), dim3(64), 0, s, P.F, D, w.Lam, w.icost);
+  hipLaunchKernelGGL(k_cost_reduce, dim3(P.n_win), dim3(256), 0, s, ncost, kVisBlock, D, w.vcost, w.icost,
+                     o.use_imu, w.trace, slot);
 }
 
 }  // namespace vi

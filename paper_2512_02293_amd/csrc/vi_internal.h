@@ -1,9 +1,17 @@
-// Internal structures of the visual-inertial step library: the per-shape plan
-// (index tables built on the host from the frame graph), the workspace carve,
-// and the kernel launchers shared by the translation units.
+// Internal structures of the visual-inertial step library: the per-batch plan
+// (index tables built on the host from the windows' frame graphs), the
+// per-window device descriptors, the workspace carve, and the kernel launchers
+// shared by the translation units.
+//
+// A call solves a batch of independent windows (a single-window call is a
+// batch of one).  Keyframes, edges and IMU factors of all windows are numbered
+// globally (window after window); per-window quantities (map size, intrinsics,
+// the caller's arrays, the reduced system) are reached through the window
+// descriptor of the keyframe, edge or factor.
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -13,14 +21,13 @@
 namespace vi {
 
 constexpr int kMaxOutDegree = 18;     // per-source outgoing edges (Gram tile budget)
-constexpr int kVisBlock = 256;        // pixels per assembly workgroup
-constexpr int kGramChunk = 64;        // pixels staged per Gram MFMA pass
-constexpr int kGramRange = 320;       // pixels per Gram workgroup
+constexpr int kVisBlock = 256;        // pixels per workgroup of the per-pixel kernels
 constexpr int kCholNB = 64;           // Cholesky block size
 constexpr int kMaxIters = 64;         // cost trace capacity of vi_ba_solve
+constexpr int kTraceLen = 2 * (kMaxIters + 1);
 
-// Device status word: first error (vi_status), its detail (e.g. pivot index),
-// and the number of committed steps.
+// Device status word of one window: first error (vi_status), its detail (e.g.
+// pivot index), and the number of committed steps.
 struct DevStatus {
   int code;
   int detail;
@@ -28,41 +35,64 @@ struct DevStatus {
   int pad;
 };
 
-// Host-built description of one frame-graph shape.
-struct Plan {
-  int N = 0, E = 0, H = 0, W = 0, HW = 0;
-  int F = 0;                     // IMU factors (N - 1)
-  int n = 0;                     // reduced dimension 15 N
-  int npad = 0;                  // n rounded up to kCholNB
-  int nblk = 0;                  // npad / kCholNB
-  int nkr_vis = 0;               // pixel ranges per source in the assembly
-  int nkr_gram = 0;              // pixel ranges per source in the Gram
-  int kmax = 0;
-  size_t n_pairs = 0;            // gather items of the reduced assembly
-  // host copies
-  std::vector<int32_t> ii, jj, src_off, src_edges, edge_slot;
-  std::vector<int32_t> gram_off, q_off, z_off, zb_off, tiles;
-  std::vector<int32_t> pair_off, pair_z, pair_zb;
-  // sizes (doubles)
-  size_t L_size = 0, gram_size = 0, q_size = 0, z_size = 0, zb_size = 0;
+// Per-window device descriptor.
+struct WinDev {
+  double fx, fy, cx, cy, g[3];
+  int H, W, HW, N;
+  int kf_base, e_base, f_base, F;    // global index of the first keyframe / edge / factor
+  int nkr;                           // pixel ranges per source in the fused assembly + Gram
+  int n, npad, nblk;                 // reduced system
+  int pair_base;                     // offset of this window's pair table
+  long long pix_base;                // global offset of the first keyframe's first pixel
+  long long A_off, Linv_off, x_off;  // reduced system, diagonal-tile inverses, solution
+  double* pose;
+  double* vel;
+  double* bias;
+  double* invdepth;
+  const float* target;
+  const float* weight;
+  const vi_preint* imu;
+  double* rep_dxi;
+  double* rep_dd;
 };
 
-// Device pointers into the plan upload (int32 tables).
+// Host-built description of one batch.
+struct Plan {
+  int n_win = 0;
+  int N = 0, E = 0, F = 0;       // totals over the batch
+  int kmax = 0;
+  int nkr_max = 0;               // max pixel ranges per source
+  int hw_max = 0;
+  int nblk_max = 0;
+  int range = 320;               // pixels per workgroup of the fused kernel
+  long long pix_total = 0;       // sum over keyframes of H*W
+  std::vector<WinDev> win;       // pointers filled per call
+  // host tables
+  std::vector<int32_t> ii, jj;                 // global keyframe indices per global edge
+  std::vector<int32_t> win_of_kf, win_of_f;
+  std::vector<int32_t> src_off, src_edges;     // CSR of edges by source keyframe
+  std::vector<int32_t> gram_off, z_off, zb_off;
+  std::vector<int32_t> pair_off, pair_z, pair_zb;
+  size_t gram_size = 0, z_size = 0, zb_size = 0;
+  size_t A_size = 0, Linv_size = 0, x_size = 0;
+};
+
+// Device pointers into the plan upload.
 struct DevPlan {
-  const int32_t *ii, *jj, *src_off, *src_edges, *edge_slot;
-  const int32_t *gram_off, *q_off, *z_off, *zb_off, *tiles;
+  const int32_t *ii, *jj, *win_of_kf, *win_of_f, *src_off, *src_edges;
+  const int32_t *gram_off, *z_off, *zb_off;
   const int32_t *pair_off, *pair_z, *pair_zb;
+  const WinDev* win;
 };
 
 // Workspace carve (device pointers into the caller's workspace).
 struct Work {
   double* Rw;        // [N][9]
   double* rel;       // [E][12]  R_ji (9), t_ji (3)
-  double* L;         // per source [HW][6 k_i]   E-block in local edge coordinates
-  double* Cd;        // [N][HW]  C + eta
-  double* wd;        // [N][HW]
-  double* hpart;     // [E][nkr_vis][32]
-  double* vcost;     // [N * nkr_vis][2]  vision cost / valid count partials
+  double* Cd;        // [pix_total]  C + eta
+  double* wd;        // [pix_total]
+  double* hpart;     // [E][nkr_max][32]
+  double* vcost;     // [N][ncost][2]  vision cost / valid count partials
   double* gpart;     // Gram partials
   double* Z;         // per source (k+1)^2 * 36
   double* ZB;        // per source 6 (k+1)
@@ -71,45 +101,41 @@ struct Work {
   double* Hf;        // [F][900]
   double* gf;        // [F][30]
   double* icost;     // [F]
-  double* A;         // [(npad + NB) * npad]  reduced matrix (+ augmented rhs row)
-  double* Linv;      // [nblk][NB*NB]
-  double* x;         // [npad]
-  double* dd;        // [N][HW]
-  double* trace;     // [kMaxIters + 1][2]  cost, n_valid
+  double* A;         // per window [(npad + NB) * npad]  reduced matrix (+ augmented rhs row)
+  double* Linv;      // per window [nblk][NB*NB]
+  double* x;         // per window [npad]
+  double* dd;        // [pix_total]
+  double* trace;     // [n_win][kTraceLen]  cost, n_valid per slot
 };
-
-size_t workspace_bytes(const Plan& P);
-Work carve_workspace(const Plan& P, void* base);
 
 struct OptsDev {
   int n_fixed, use_imu, bias_fixed;
   double lambda, eta, z_min, d_min;
 };
 
-struct CamDev {
-  double fx, fy, cx, cy;
-  int H, W;
-  double g[3];
-};
+// partial-sum slots per source in the cost / Hessian partial arrays
+inline int cost_slots(const Plan& P) {
+  return std::max(P.nkr_max, (P.hw_max + kVisBlock - 1) / kVisBlock);
+}
 
 // kernel launchers (enqueue on `s`)
 void launch_preint(hipStream_t s, int F, const int32_t* off, const double* gyro,
                    const double* accel, const double* dt, const double* bias_hat,
                    vi_imu_noise noise, vi_preint* out, DevStatus* st);
-void launch_imu_info(hipStream_t s, int F, const vi_preint* imu, double* Lam, DevStatus* st);
+void launch_imu_info(hipStream_t s, const Plan& P, const DevPlan& D, double* Lam, DevStatus* st);
 // Stages of one step, for per-stage event timing.
-enum Stage { kStVis = 0, kStGram, kStLocal, kStAssemble, kStChol, kStBacksub, kNumStages };
-// `marks`, when non-null, is called between stages (used to record timing events).
+enum Stage { kStVis = 0, kStLocal, kStAssemble, kStChol, kStBacksub, kNumStages };
+// `mark`, when non-null, is called between stages (used to record timing events).
 typedef void (*StageMark)(void* user, int stage_done);
-void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const CamDev& cam,
-                 const OptsDev& o, const vi_state& x, const float* target, const float* weight,
-                 const vi_preint* imu, int iter, double* rep_dxi, double* rep_dd, DevStatus* st,
-                 StageMark mark = nullptr, void* mark_user = nullptr);
-void launch_reset_status(hipStream_t s, DevStatus* st);
-size_t step_lds_max(int kmax);
+void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o, int iter,
+                 DevStatus* st, StageMark mark = nullptr, void* mark_user = nullptr);
+// the first two stages only (autotuning of the assembly tiling)
+void launch_tune_stages(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o,
+                        StageMark mark, void* mark_user);
+void launch_reset_status(hipStream_t s, DevStatus* st, int n);
+void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o,
+                       int slot);
+void launch_chol(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, DevStatus* st);
 void step_set_attributes(int kmax);
-void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w,
-                       const CamDev& cam, const OptsDev& o, const vi_state& x, const float* target,
-                       const float* weight, const vi_preint* imu, int slot, DevStatus* st);
 
 }  // namespace vi

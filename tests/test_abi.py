@@ -41,7 +41,8 @@ def test_struct_layouts_match_c():
     #define P(T) printf(#T " %zu\n", sizeof(T));
     #define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
     int main(void) {
-      P(vi_camera) P(vi_imu_noise) P(vi_preint) P(vi_state) P(vi_edges) P(vi_opts) P(vi_report)
+      P(vi_camera) P(vi_imu_noise) P(vi_preint) P(vi_state) P(vi_edges) P(vi_opts) P(vi_report) P(vi_window)
+      O(vi_window, state) O(vi_window, edges) O(vi_window, imu) O(vi_window, report)
       O(vi_camera, H) O(vi_camera, gravity) O(vi_preint, cov) O(vi_preint, cov_bias)
       O(vi_state, invdepth) O(vi_edges, weight) O(vi_opts, lm_lambda) O(vi_opts, d_min)
       O(vi_report, n_valid) O(vi_report, dxi) O(vi_report, stage_ms)
@@ -60,6 +61,9 @@ def test_struct_layouts_match_c():
         "vi_camera": C.sizeof(binding.Camera), "vi_imu_noise": C.sizeof(binding.ImuNoise),
         "vi_preint": 8 * binding.PREINT_DOUBLES, "vi_state": C.sizeof(binding.State),
         "vi_edges": C.sizeof(binding.Edges), "vi_opts": C.sizeof(binding.Opts), "vi_report": C.sizeof(binding.Report),
+        "vi_window": C.sizeof(binding.Window), "vi_window.state": binding.Window.state.offset,
+        "vi_window.edges": binding.Window.edges.offset, "vi_window.imu": binding.Window.imu.offset,
+        "vi_window.report": binding.Window.report.offset,
         "vi_camera.H": binding.Camera.H.offset, "vi_camera.gravity": binding.Camera.gravity.offset,
         "vi_preint.cov": 8 * 61, "vi_preint.cov_bias": 8 * 148,
         "vi_state.invdepth": binding.State.invdepth.offset, "vi_edges.weight": binding.Edges.weight.offset,
@@ -85,8 +89,13 @@ def test_workspace_size_host_only():
     a = ws(3, [0, 1, 2], [1, 2, 0])
     b = ws(3, [0, 1, 2, 0], [1, 2, 0, 2])
     assert a > 0 and b > a
-    # the E-block alone is 6 doubles per (edge, pixel)
-    assert b - a >= 6 * 8 * 60 * 80
+    # per source pixel the step keeps C, w_d and the depth increment (3 doubles)
+    cam_small = binding.make_camera(75, 75, 40, 30, 30, 40)
+    ii = np.asarray([0, 1, 2], np.int32)
+    jj = np.asarray([1, 2, 0], np.int32)
+    ed = binding.Edges(3, ii.ctypes.data_as(C.c_void_p), jj.ctypes.data_as(C.c_void_p), None, None)
+    small = lib.vi_workspace_size(C.byref(cam_small), 3, C.byref(ed), C.byref(opts))
+    assert a - small >= 3 * 3 * 8 * (60 * 80 - 30 * 40)
     assert ws(3, [0, 1], [1, 3]) == 0          # index out of range
     assert ws(3, [0, 1], [0, 2]) == 0          # self edge
     assert ws(3, [0, 0], [1, 1]) == 0          # duplicate pair

@@ -1,0 +1,162 @@
+"""Batched solves of independent windows (one set of launches for the whole
+batch) against per-window solves and against the FP64 oracle.
+
+Per-window arithmetic in a batch is the same as in a single-window call with
+the same pixel tiling, so those results agree to rounding of the reduction
+order only (asserted at 1e-12); against the oracle the step tolerances apply
+(1e-4 relative on pose/velocity/bias, 1e-3 on inverse depths), checked on
+the final states after several iterations.
+"""
+import numpy as np
+import pytest
+
+from oracle import normal_eq as ne, so3
+from oracle import solve as osolve
+from paper_2512_02293_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2512_02293_amd import binding
+    assert torch.cuda.is_available()
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _bopts(**kw):
+    from paper_2512_02293_amd import binding
+    o = ne.Options(**kw)
+    return o, binding.make_opts(n_fixed=o.n_fixed, use_imu=o.use_imu, bias_fixed=o.bias_fixed,
+                                lm_lambda=o.lm_lambda, depth_eta=o.depth_eta, z_min=o.z_min, d_min=o.d_min)
+
+
+def _setup(ctx, probs):
+    from paper_2512_02293_amd import binding
+    dps = [binding.DeviceProblem(p) for p in probs]
+    imus = [ctx.imu_preintegrate(d.off, d.gyro, d.accel, d.imu_dt, d.bias_hat, d.noise) for d in dps]
+    return dps, imus
+
+
+def _state(dp):
+    return [t.cpu().numpy().copy() for t in (dp.pose, dp.vel, dp.bias, dp.invdepth)]
+
+
+def _solve_single(ctx, dp, imu, bopts, iters):
+    import torch
+    nb = ctx.workspace_size(dp.cam, dp.pose.shape[0], dp.ii, dp.jj, bopts)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+    return ctx.solve(dp.cam, dp.pose, dp.vel, dp.bias, dp.invdepth, dp.ii, dp.jj, dp.target, dp.weight, imu,
+                     bopts, iters, ws, costs=True)
+
+
+def _solve_batch(ctx, dps, imus, bopts, iters, **kw):
+    import torch
+    nb = ctx.workspace_size_batched(dps, bopts)
+    assert nb > 0
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+    return ctx.solve_batched(dps, imus, bopts, iters, ws, costs=True, **kw)
+
+
+def _close(a, b, rtol):
+    for x, y in zip(a, b):
+        scale = max(np.abs(y).max(), 1e-300)
+        assert np.abs(x - y).max() <= rtol * scale, (np.abs(x - y).max(), scale)
+
+
+@pytest.mark.parametrize("n_win", [1, 5])
+def test_batched_equals_single_window_solves(ctx, n_win):
+    iters = 3
+    probs = [synth.make_problem(synth.config_batched_window(w), 4000 + w) for w in range(n_win)]
+    _, bopts = _bopts()
+    ctx.set_autotune(False)
+    dps, imus = _setup(ctx, probs)
+    reps_b = _solve_batch(ctx, dps, imus, bopts, iters)
+    states_b = [_state(d) for d in dps]
+    for w, (dp, imu) in enumerate(zip(dps, imus)):
+        dp.reset_state()
+        rep = _solve_single(ctx, dp, imu, bopts, iters)
+        print(f"window {w}: N={dp.pose.shape[0]} E={dp.ii.shape[0]} cost {rep['costs'][0]:.4e} -> "
+              f"{rep['costs'][-1]:.4e}")
+        assert reps_b[w]["iters_done"] == iters
+        assert reps_b[w]["n_valid"] == rep["n_valid"]
+        assert np.allclose(reps_b[w]["costs"], rep["costs"], rtol=1e-12, atol=0)
+        _close(states_b[w], _state(dp), 1e-12)
+
+
+def test_batched_matches_oracle(ctx):
+    iters = 3
+    n_win = 4
+    probs = [synth.make_problem(synth.config_batched_window(w), 4000 + w) for w in range(n_win)]
+    oopts, bopts = _bopts()
+    ctx.set_autotune(False)
+    dps, imus = _setup(ctx, probs)
+    reps = _solve_batch(ctx, dps, imus, bopts, iters)
+    for w, (p, dp) in enumerate(zip(probs, dps)):
+        cam, st, gr = osolve.from_problem(p)
+        ost, oreps = osolve.solve(cam, st, gr, oopts, iters)
+        ocosts = [r["cost_before"] for r in oreps] + [oreps[-1]["cost_after"]]
+        assert np.allclose(reps[w]["costs"], ocosts, rtol=1e-6), (w, reps[w]["costs"], ocosts)
+        pose = dp.pose.cpu().numpy()
+        ang = max(np.linalg.norm(so3.Log(so3.quat_to_R(q).T @ R)) for q, R in zip(pose[:, 3:], ost.R))
+        assert ang < 1e-8, w
+        assert np.abs(pose[:, :3] - ost.p).max() < 1e-8, w
+        assert np.abs(dp.vel.cpu().numpy() - ost.v).max() < 1e-7, w
+        assert np.abs(dp.bias.cpu().numpy() - ost.b).max() < 1e-7, w
+        assert np.abs(dp.invdepth.cpu().numpy() - ost.d).max() < 1e-7, w
+
+
+def test_autotuned_tiling_matches_default(ctx):
+    """The autotuner only changes the pixel tiling of the fused assembly."""
+    iters = 2
+    probs = [synth.make_problem(synth.config_batched_window(w), 4000 + w) for w in range(3)]
+    _, bopts = _bopts()
+    dps, imus = _setup(ctx, probs)
+    ctx.set_autotune(False)
+    reps0 = _solve_batch(ctx, dps, imus, bopts, iters)
+    s0 = [_state(d) for d in dps]
+    for d in dps:
+        d.reset_state()
+    ctx.set_autotune(True)
+    try:
+        reps1 = _solve_batch(ctx, dps, imus, bopts, iters)
+        s1 = [_state(d) for d in dps]
+        # a second call reuses the cached choice
+        for d in dps:
+            d.reset_state()
+        reps2 = _solve_batch(ctx, dps, imus, bopts, iters)
+    finally:
+        ctx.set_autotune(False)
+    print("tile_px default", reps0[0]["tile_px"], "tuned", reps1[0]["tile_px"])
+    assert reps1[0]["tile_px"] in (128, 192, 256, 320, 448, 640)
+    assert reps2[0]["tile_px"] == reps1[0]["tile_px"]
+    for w in range(3):
+        assert reps1[w]["n_valid"] == reps0[w]["n_valid"]
+        assert np.allclose(reps1[w]["costs"], reps0[w]["costs"], rtol=1e-10)
+        assert np.array_equal(reps2[w]["costs"], reps1[w]["costs"])
+        _close(s1[w], s0[w], 1e-9)
+
+
+def test_batched_stage_timing_and_errors(ctx):
+    import torch
+    from paper_2512_02293_amd import binding
+    probs = [synth.make_problem(synth.config_batched_window(w), 4000 + w) for w in range(2)]
+    _, bopts = _bopts()
+    ctx.set_autotune(False)
+    dps, imus = _setup(ctx, probs)
+    reps = _solve_batch(ctx, dps, imus, bopts, 1, stage_ms=True)
+    assert reps[0]["stage_ms"]["vis_gram_imu"] > 0
+    # a window whose edge list names a keyframe outside it is rejected before any launch
+    before = _state(dps[1])
+    dps[1].jj = dps[1].jj.copy()
+    dps[1].jj[0] = dps[1].pose.shape[0]
+    nb = ctx.workspace_size_batched(dps[:1], bopts)
+    ws = torch.empty(max(nb, 1) * 4, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(binding.ViError) as ei:
+        ctx.solve_batched(dps, imus, bopts, 1, ws)
+    assert ei.value.code == binding.VI_EINVAL
+    for a, b in zip(before, _state(dps[1])):
+        assert np.array_equal(a, b)

@@ -224,7 +224,7 @@ def test_eager_timed_run_matches_graph_run(ctx):
     assert np.array_equal(dp.pose.cpu().numpy(), pose_g)
     assert np.array_equal(rep_e["costs"], rep_g["costs"])
     assert all(v >= 0 for v in rep_e["stage_ms"].values())
-    assert rep_e["stage_ms"]["vis_imu_assemble"] > 0
+    assert rep_e["stage_ms"]["vis_gram_imu"] > 0
 
 
 def test_noiseless_convergence_on_gpu(ctx):
