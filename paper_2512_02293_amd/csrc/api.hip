@@ -99,7 +99,9 @@ vi_status check_window(vi_ctx* ctx, int w, const WinIn& in, const vi_opts* o, bo
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(cam->gravity[k])) return fail(ctx, VI_EINVAL, "window %d: gravity must be finite", w);
   if (st->n_kf < 2) return fail(ctx, VI_EINVAL, "window %d: need at least 2 keyframes (got %d)", w, st->n_kf);
-  if (st->n_kf > 4096) return fail(ctx, VI_EUNSUPPORTED, "window %d: at most 4096 keyframes are supported", w);
+  if (st->n_kf > kMaxKeyframes)
+    return fail(ctx, VI_EUNSUPPORTED, "window %d: at most %d keyframes are supported (dense reduced system)", w,
+                kMaxKeyframes);
   if (ed->n_edges < 1) return fail(ctx, VI_EINVAL, "window %d: need at least one edge", w);
   if (!ed->ii || !ed->jj) return fail(ctx, VI_EINVAL, "window %d: null edge index array", w);
   if (o->n_fixed > st->n_kf) return fail(ctx, VI_EINVAL, "window %d: n_fixed out of range", w);
@@ -239,6 +241,9 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
     W.A_off = (long long)A_off;
     W.Linv_off = (long long)L_off;
     W.x_off = (long long)x_off;
+    W.flag_off = (int)P.flags_size;
+    W.nflags = (W.nblk + 1) * W.nblk;
+    P.flags_size += (size_t)W.nflags;
     A_off += (size_t)(W.npad + kCholNB) * W.npad;
     L_off += (size_t)W.nblk * kCholNB * kCholNB;
     x_off += (size_t)W.npad;
@@ -264,6 +269,18 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
     P.pair_off.push_back((int32_t)P.pair_z.size());
   }
   if (P.pair_z.empty()) { P.pair_z.push_back(0); P.pair_zb.push_back(0); }
+  // Cholesky tickets: column j, then window, then block row i (nblk = the
+  // right-hand-side block), so that every tile depends on smaller tickets only
+  for (int j = 0; j < P.nblk_max; ++j)
+    for (int w = 0; w < nw; ++w) {
+      const WinDev& W = P.win[w];
+      if (j >= W.nblk) continue;
+      for (int i = j; i <= W.nblk; ++i) {
+        P.chol_tiles.push_back(w);
+        P.chol_tiles.push_back((i << 16) | j);
+      }
+    }
+  P.n_tickets = (int)(P.chol_tiles.size() / 2);
   P.A_size = A_off;
   P.Linv_size = L_off;
   P.x_size = x_off;
@@ -306,6 +323,8 @@ Work do_carve(const Plan& P, void* base, size_t* bytes) {
   w.gf = c.take<double>(F * 30);
   w.icost = c.take<double>(F);
   w.A = c.take<double>(P.A_size);
+  w.flags = c.take<int32_t>(P.flags_size);
+  w.sync = c.take<int32_t>(4);
   w.Linv = c.take<double>(P.Linv_size);
   w.x = c.take<double>(P.x_size);
   w.dd = c.take<double>((size_t)P.pix_total);
@@ -318,7 +337,8 @@ Work do_carve(const Plan& P, void* base, size_t* bytes) {
 vi_status upload_plan(vi_ctx* ctx) {
   const Plan& P = ctx->plan;
   const std::vector<int32_t>* parts[] = {&P.ii, &P.jj, &P.win_of_kf, &P.win_of_f, &P.src_off, &P.src_edges,
-                                         &P.gram_off, &P.z_off, &P.zb_off, &P.pair_off, &P.pair_z, &P.pair_zb};
+                                         &P.gram_off, &P.z_off, &P.zb_off, &P.pair_off, &P.pair_z, &P.pair_zb,
+                                         &P.chol_tiles};
   size_t total = align256(sizeof(WinDev) * P.n_win);
   for (auto* v : parts) total += align256(std::max<size_t>(v->size(), 1) * sizeof(int32_t));
   if (total > ctx->d_plan_cap) {
@@ -329,7 +349,7 @@ vi_status upload_plan(vi_ctx* ctx) {
   }
   std::vector<char> host(total, 0);
   size_t off = align256(sizeof(WinDev) * P.n_win);
-  const int32_t* dptr[12];
+  const int32_t* dptr[13];
   int idx = 0;
   for (auto* v : parts) {
     if (!v->empty()) std::memcpy(host.data() + off, v->data(), v->size() * sizeof(int32_t));
@@ -342,7 +362,7 @@ vi_status upload_plan(vi_ctx* ctx) {
   D.win = ctx->d_win;
   D.ii = dptr[0]; D.jj = dptr[1]; D.win_of_kf = dptr[2]; D.win_of_f = dptr[3]; D.src_off = dptr[4];
   D.src_edges = dptr[5]; D.gram_off = dptr[6]; D.z_off = dptr[7]; D.zb_off = dptr[8];
-  D.pair_off = dptr[9]; D.pair_z = dptr[10]; D.pair_zb = dptr[11];
+  D.pair_off = dptr[9]; D.pair_z = dptr[10]; D.pair_zb = dptr[11]; D.chol_tiles = dptr[12];
   return VI_OK;
 }
 

@@ -1,22 +1,27 @@
 // FP64 Cholesky solve of the reduced pose/velocity/bias system of Eq. 4.
 //
-// The matrix buffer holds S (npad x npad, row-major, lower triangle used) with
-// the right-hand side stored as row npad, so the blocked factorisation carries
-// the forward substitution along: at the end row npad holds y = L^-1 s.
+// The matrix buffer of a window holds S (npad x npad, row-major, lower
+// triangle used) followed by a 32-row right-hand-side block whose first row is
+// s, so the factorisation carries the forward substitution along: at the end
+// that row holds y = L^-1 s.
 //
-// Every window of a batch has its own system (blockIdx.y = window); windows
-// with fewer block columns than the step index simply exit.
+// Factorisation: a tile-level dataflow over 32 x 32 tiles (i, j), j <= i,
+// i = nblk being the right-hand-side block, of every window of the batch in
+// one launch.  Each tile is one wave:
+//   X = S_ij - sum_{k < j} L_ik L_jk^T        (FP64 MFMA 16x16x4, operands
+//                                              straight from global memory)
+//   i == j : factor X = L_jj L_jj^T in registers (lane = row) and invert it;
+//   i != j : L_ij = X L_jj^-T                 (FP64 MFMA)
+// and publishes the result with a release flag.  Tiles are handed out by an
+// atomic ticket counter in column-major order (column j, then window, then
+// row i), and a tile only ever waits for tiles of smaller tickets, which were
+// taken by running workgroups: every wait ends without any assumption on
+// how many workgroups are resident.  Every wait is also bounded: past the
+// limit the batch is aborted (VI_EDEVICE) and every workgroup exits.
 //
-// Right-looking, 64-wide block columns, ONE launch per block column kb:
-//   * panel workgroups (block rows r = kb .. nblk, nblk being the right-hand-
-//     side block) first apply the pending update of block column kb-1 to the
-//     diagonal tile and to their own tile, then factor the 64x64 diagonal tile
-//     (one wave, one row per lane, in registers), invert it (one wave, one
-//     column per lane), and form L_r,kb = S_r,kb L_kb,kb^-T;
-//   * trailing workgroups apply the update of block column kb-1 to every tile
-//     (i, j) with j > kb, which later steps consume.
-// A single-workgroup pass then back-substitutes x = L^-T y block by block with
-// the stored inverses of the diagonal tiles (staged through LDS).
+// Back-substitution x = L^-T y runs per window in one 1024-thread workgroup,
+// block column by block column: x_b = L_bb^-T t_b, then t_c -= L_bc^T x_b
+// for every c < b in parallel over the waves.
 #include <algorithm>
 
 #include "vi_internal.h"
@@ -25,8 +30,12 @@ namespace vi {
 
 namespace {
 
-constexpr int NB = kCholNB;       // 64
-constexpr int LD = NB + 1;        // padded LDS row
+constexpr int NB = kCholNB;          // 32
+constexpr int LD = NB + 1;
+constexpr int kSpinLimit = 1 << 22;  // polls (each with a short sleep) before the batch is aborted
+constexpr int kMaxDataflowWG = 4096;
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void set_status(DevStatus* st, int code, int detail) {
   if (atomicCAS(&st->code, 0, code) == 0) st->detail = detail;
@@ -39,216 +48,251 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __hiloint2double(hi, lo);
 }
 
-__device__ __forceinline__ void load_tile(double* dst, const double* A, int npad, int r0, int c0) {
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-    const int r = idx / NB, c = idx % NB;
-    dst[r * LD + c] = A[(size_t)(r0 + r) * npad + c0 + c];
-  }
+__device__ __forceinline__ int load_flag(const int* f) {
+  return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// C[r][c] -= sum_m P[r][m] Q[c][m] for the 64x64 tile C (all in LDS).
-__device__ __forceinline__ void tile_sub_abt(double* Cm, const double* P, const double* Q) {
-  for (int idx = threadIdx.x; idx < NB * NB; idx += blockDim.x) {
-    const int r = idx / NB, c = idx % NB;
-    double v0 = 0.0, v1 = 0.0;
-#pragma unroll 8
-    for (int m = 0; m < NB; m += 2) {
-      v0 += P[r * LD + m] * Q[c * LD + m];
-      v1 += P[r * LD + m + 1] * Q[c * LD + m + 1];
+// Wait (whole wave) until *f is set.  false: the batch was aborted.
+__device__ bool wait_flag(const int* f, int* sync) {
+  int spins = 0;
+  while (__builtin_amdgcn_readfirstlane(load_flag(f)) == 0) {
+    if (__builtin_amdgcn_readfirstlane(load_flag(sync + 1)) != 0) return false;
+    if (++spins > kSpinLimit) {
+      if (threadIdx.x == 0) __hip_atomic_store(sync + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
     }
-    Cm[r * LD + c] -= v0 + v1;
+    __builtin_amdgcn_s_sleep(2);
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
 }
 
-__global__ void __launch_bounds__(256) k_chol_step(DevPlan D, int kb, double* __restrict__ Aall,
-                                                   double* __restrict__ Linvall, DevStatus* stall) {
-  extern __shared__ double sm[];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const WinDev& W = D.win[blockIdx.y];
-  const int n = W.n, npad = W.npad, nblk = W.nblk;
-  if (kb >= nblk) return;
-  const int n_panel = nblk - kb + 1;
-  int n_trail = 0;
-  if (kb > 0)
-    for (int jb = kb + 1; jb < nblk; ++jb) n_trail += nblk - jb + 1;
-  if ((int)blockIdx.x >= n_panel + n_trail) return;
-  double* A = Aall + W.A_off;
-  double* Linv = Linvall + W.Linv_off;
-  DevStatus* st = stall + blockIdx.y;
-  const int k0 = kb * NB;
-  if ((int)blockIdx.x >= n_panel) {
-    // trailing tile (i, j), kb < j <= nblk - 1, j <= i <= nblk: apply block column kb-1
-    int t = blockIdx.x - n_panel;
-    int jb = kb + 1;
-    while (true) {
-      const int cnt = nblk - jb + 1;
-      if (t < cnt) break;
-      t -= cnt;
-      ++jb;
+__device__ __forceinline__ void publish(int* f) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (threadIdx.x == 0) __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// acc (2x2 blocks of 16x16 in MFMA output layout: lane l, element r holds row
+// (l >> 4) + 4 r, column l & 15 of its block) <-> a row-major 32x32 array
+__device__ __forceinline__ void acc_to_lds(const double4_t (&acc)[2][2], double* T) {
+  const int l = threadIdx.x;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) T[(16 * bm + (l >> 4) + 4 * r) * LD + 16 * bn + (l & 15)] = acc[bm][bn][r];
+}
+
+__device__ __forceinline__ double rsqrt_refined(double v) {
+  // hardware reciprocal square root, then two Newton steps to full precision
+  double y = __builtin_amdgcn_rsq(v);
+  const double h = 0.5 * v;
+  y = y * (1.5 - h * y * y);
+  y = y * (1.5 - h * y * y);
+  return y;
+}
+
+__global__ void __launch_bounds__(64) k_chol_df(DevPlan D, int ntickets, double* __restrict__ Aall,
+                                                double* __restrict__ Linvall, int* __restrict__ flagsall,
+                                                int* __restrict__ sync, DevStatus* __restrict__ stall) {
+  __shared__ double T[NB * LD];
+  __shared__ double rinv[NB];
+  const int lane = threadIdx.x;
+  const int mrow = lane & 15, kq = lane >> 4;
+  while (true) {
+    int t = 0;
+    if (lane == 0) t = atomicAdd(sync, 1);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if (t >= ntickets) return;
+    const int w = D.chol_tiles[2 * t];
+    const int ij = D.chol_tiles[2 * t + 1];
+    const int i = ij >> 16, j = ij & 0xffff;
+    const WinDev& W = D.win[w];
+    const int npad = W.npad, nblk = W.nblk;
+    double* A = Aall + W.A_off;
+    double* Lv = Linvall + W.Linv_off;
+    int* fl = flagsall + W.flag_off;
+    // X = S_ij in MFMA layout
+    double4_t acc[2][2];
+    const double* Sij = A + (size_t)(NB * i) * npad + NB * j;
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc[bm][bn][r] = Sij[(size_t)(16 * bm + kq + 4 * r) * npad + 16 * bn + mrow];
+    // X -= L_ik L_jk^T: lane supplies A[m][q] = L_ik[m][q], B[q][n] = L_jk[n][q]
+    for (int k = 0; k < j; ++k) {
+      if (!wait_flag(fl + i * nblk + k, sync)) return;
+      if (i != j && !wait_flag(fl + j * nblk + k, sync)) return;
+      const double* Li = A + (size_t)(NB * i) * npad + NB * k;
+      const double* Lj = A + (size_t)(NB * j) * npad + NB * k;
+      double a[2][8], b[2][8];
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          a[h][s] = -Li[(size_t)(16 * h + mrow) * npad + 4 * s + kq];
+          b[h][s] = Lj[(size_t)(16 * h + mrow) * npad + 4 * s + kq];
+        }
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < 2; ++bn)
+            acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm][s], b[bn][s], acc[bm][bn], 0, 0, 0);
     }
-    const int ib = jb + t;
-    double* Pa = sm;
-    double* Pb = sm + NB * LD;
-    load_tile(Pa, A, npad, ib * NB, k0 - NB);
-    load_tile(Pb, A, npad, jb * NB, k0 - NB);
+    acc_to_lds(acc, T);
     __syncthreads();
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-      const int r = idx / NB, c = idx % NB;
-      double v0 = 0.0, v1 = 0.0;
-#pragma unroll 8
-      for (int m = 0; m < NB; m += 2) {
-        v0 += Pa[r * LD + m] * Pb[c * LD + m];
-        v1 += Pa[r * LD + m + 1] * Pb[c * LD + m + 1];
+    if (i == j) {
+      // factor: lane i (< 32) holds row i; lanes >= 32 mirror rows 0..31 and are ignored
+      const int row = lane & 31;
+      double x[NB];
+#pragma unroll
+      for (int c = 0; c < NB; ++c) x[c] = T[row * LD + c];
+      int bad = -1;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        double piv = readlane_d(x[c], c);
+        if (!(piv > 0.0)) {
+          if (bad < 0) bad = c;
+          piv = 1.0;
+        }
+        const double r = rsqrt_refined(piv);
+        if (lane == c) rinv[c] = r;
+        x[c] = (row == c) ? piv * r : (row > c ? x[c] * r : x[c]);
+#pragma unroll
+        for (int m = c + 1; m < NB; ++m) {
+          const double lm = readlane_d(x[c], m);
+          if (row >= m) x[m] -= x[c] * lm;
+        }
       }
-      A[(size_t)(ib * NB + r) * npad + jb * NB + c] -= v0 + v1;
+      if (bad >= 0 && lane == 0 && NB * j + bad < W.n) set_status(stall + w, VI_ENOTPD, NB * j + bad);
+#pragma unroll
+      for (int c = 0; c < NB; ++c) T[row * LD + c] = (c <= row) ? x[c] : 0.0;
+      __syncthreads();
+      // inverse: lane c (< 32) computes column c of L^-1
+      double y[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        double v = (r == row) ? 1.0 : 0.0;
+#pragma unroll
+        for (int q = 0; q < r; ++q) v -= T[r * LD + q] * y[q];
+        y[r] = v * rinv[r];
+      }
+      if (lane < NB) {
+        double* Lo = Lv + (size_t)j * NB * NB;
+#pragma unroll
+        for (int r = 0; r < NB; ++r) Lo[r * NB + lane] = y[r];
+      }
+      publish(fl + j * nblk + j);
+    } else {
+      if (!wait_flag(fl + j * nblk + j, sync)) return;
+      // L_ij = X L_jj^-T: A[m][q] = X[m][q], B[q][n] = Linv[n][q]
+      const double* Li = Lv + (size_t)j * NB * NB;
+      double4_t out[2][2];
+#pragma unroll
+      for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) out[bm][bn] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        double a[2], b[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          a[h] = T[(16 * h + mrow) * LD + 4 * s + kq];
+          b[h] = Li[(16 * h + mrow) * NB + 4 * s + kq];
+        }
+#pragma unroll
+        for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < 2; ++bn)
+            out[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm], b[bn], out[bm][bn], 0, 0, 0);
+      }
+      double* Oij = A + (size_t)(NB * i) * npad + NB * j;
+#pragma unroll
+      for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Oij[(size_t)(16 * bm + kq + 4 * r) * npad + 16 * bn + mrow] = out[bm][bn][r];
+      publish(fl + i * nblk + j);
     }
-    return;
-  }
-  // panel workgroup for block row r
-  const int r0 = (kb + blockIdx.x) * NB;
-  double* Dg = sm;                 // diagonal tile -> L_kk
-  double* Lk = sm + NB * LD;       // L_kb,kb-1, later L_kk^-1
-  double* X = sm + 2 * NB * LD;    // own tile
-  double* Lr = sm + 3 * NB * LD;   // L_r,kb-1
-  load_tile(Dg, A, npad, k0, k0);
-  load_tile(X, A, npad, r0, k0);
-  if (kb > 0) {
-    load_tile(Lk, A, npad, k0, k0 - NB);
-    load_tile(Lr, A, npad, r0, k0 - NB);
-  }
-  __syncthreads();
-  if (kb > 0) {
-    tile_sub_abt(Dg, Lk, Lk);
-    if (blockIdx.x != 0) tile_sub_abt(X, Lr, Lk);
     __syncthreads();
-  }
-  // factor the diagonal tile: lane i holds row i
-  if (wave == 0) {
-    double a[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) a[c] = Dg[lane * LD + c];
-    int bad = -1;
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      double piv = readlane_d(a[j], j);
-      if (!(piv > 0.0)) {
-        if (bad < 0) bad = j;
-        piv = 1.0;
-      }
-      const double dj = sqrt(piv);
-      const double inv = 1.0 / dj;
-      a[j] = (lane == j) ? dj : a[j] * inv;
-#pragma unroll
-      for (int m = j + 1; m < NB; ++m) a[m] -= a[j] * readlane_d(a[j], m);
-    }
-#pragma unroll
-    for (int c = 0; c < NB; ++c) Dg[lane * LD + c] = (c <= lane) ? a[c] : 0.0;
-    if (bad >= 0 && lane == 0 && blockIdx.x == 0 && k0 + bad < n) set_status(st, VI_ENOTPD, k0 + bad);
-  }
-  __syncthreads();
-  // inverse of the diagonal factor: lane c of wave 0 owns column c
-  if (wave == 0) {
-    double x[NB];
-#pragma unroll
-    for (int r = 0; r < NB; ++r) x[r] = (r == lane) ? 1.0 : 0.0;
-#pragma unroll
-    for (int m = 0; m < NB; ++m) {
-      x[m] = x[m] / Dg[m * LD + m];
-#pragma unroll
-      for (int r = m + 1; r < NB; ++r) x[r] -= Dg[r * LD + m] * x[m];
-    }
-#pragma unroll
-    for (int r = 0; r < NB; ++r) Lk[r * LD + lane] = x[r];
-  }
-  __syncthreads();
-  if (blockIdx.x == 0) {
-    for (int idx = tid; idx < NB * NB; idx += 256) {
-      const int r = idx / NB, c = idx % NB;
-      A[(size_t)(k0 + r) * npad + k0 + c] = Dg[r * LD + c];
-      Linv[(size_t)kb * NB * NB + idx] = Lk[r * LD + c];
-    }
-    return;
-  }
-  // L_r,kb = X L^-T: out[r][c] = sum_{m <= c} X[r][m] Linv[c][m]
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int r = idx / NB, c = idx % NB;
-    double v0 = 0.0, v1 = 0.0;
-    int m = 0;
-    for (; m + 1 <= c; m += 2) {
-      v0 += X[r * LD + m] * Lk[c * LD + m];
-      v1 += X[r * LD + m + 1] * Lk[c * LD + m + 1];
-    }
-    if (m <= c) v0 += X[r * LD + m] * Lk[c * LD + m];
-    A[(size_t)(r0 + r) * npad + k0 + c] = v0 + v1;
   }
 }
 
-// x = L^-T y, block by block from the last; 1024 threads.
-__global__ void __launch_bounds__(1024) k_chol_solve(DevPlan D, const double* __restrict__ Aall,
-                                                     const double* __restrict__ Linvall, double* __restrict__ xall) {
-  extern __shared__ double xs[];        // [npad]
-  __shared__ double part[16][NB];
-  __shared__ double tv[NB];
-  __shared__ double Li[NB][LD];
-  const int tid = threadIdx.x;
+// x = L^-T y per window (blockIdx.x); 1024 threads.  After an aborted
+// factorisation every window is marked failed (its state is then left alone).
+__global__ void __launch_bounds__(1024) k_chol_backsolve(DevPlan D, const double* __restrict__ Aall,
+                                                         const double* __restrict__ Linvall, double* __restrict__ xall,
+                                                         const int* __restrict__ sync, DevStatus* __restrict__ stall) {
+  extern __shared__ double sh[];
   const WinDev& W = D.win[blockIdx.x];
   const int n = W.n, npad = W.npad, nblk = W.nblk;
+  if (load_flag(sync + 1) != 0) {
+    if (threadIdx.x == 0) set_status(stall + blockIdx.x, VI_EDEVICE, -1);
+    return;
+  }
   const double* A = Aall + W.A_off;
-  const double* Linv = Linvall + W.Linv_off;
-  double* x = xall + W.x_off;
-  const double* y = A + (size_t)npad * npad;
-  const int j = tid & (NB - 1), sl = tid >> 6;   // 64 columns x 16 row slices
+  const double* Lv = Linvall + W.Linv_off;
+  double* tv = sh;            // running right-hand side [npad]
+  double* xs = sh + npad;     // solution [npad]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int q = lane & 31, half = lane >> 5;
+  for (int r = tid; r < npad; r += 1024) tv[r] = A[(size_t)npad * npad + r];
+  __syncthreads();
   for (int b = nblk - 1; b >= 0; --b) {
-    for (int idx = tid; idx < NB * NB; idx += 1024) Li[idx / NB][idx % NB] = Linv[(size_t)b * NB * NB + idx];
-    double a0 = 0.0, a1 = 0.0;
-    int r = (b + 1) * NB + sl;
-    for (; r + 16 < npad; r += 32) {
-      a0 += A[(size_t)r * npad + b * NB + j] * xs[r];
-      a1 += A[(size_t)(r + 16) * npad + b * NB + j] * xs[r + 16];
-    }
-    if (r < npad) a0 += A[(size_t)r * npad + b * NB + j] * xs[r];
-    part[sl][j] = a0 + a1;
-    __syncthreads();
-    if (tid < NB) {
-      double v = y[b * NB + tid];
+    // prefetch this wave's first block L_bc (c = wave) while x_b is formed
+    double pre[16];
+    const bool has = wave < b;
+    if (has) {
 #pragma unroll
-      for (int s = 0; s < 16; ++s) v -= part[s][tid];
-      tv[tid] = v;
+      for (int u = 0; u < 16; ++u) pre[u] = A[(size_t)(NB * b + 16 * half + u) * npad + NB * wave + q];
+    }
+    if (tid < NB) {
+      const double* Lb = Lv + (size_t)b * NB * NB;
+      double v = 0.0;
+      for (int r = tid; r < NB; ++r) v += Lb[r * NB + tid] * tv[NB * b + r];
+      xs[NB * b + tid] = v;
     }
     __syncthreads();
-    if (tid < NB) {
+    for (int c = wave; c < b; c += 16) {
       double v = 0.0;
-      for (int m = tid; m < NB; ++m) v += Li[m][tid] * tv[m];
-      xs[b * NB + tid] = v;
+      if (c == wave) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v += pre[u] * xs[NB * b + 16 * half + u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          v += A[(size_t)(NB * b + 16 * half + u) * npad + NB * c + q] * xs[NB * b + 16 * half + u];
+      }
+      v += __shfl_xor(v, 32);
+      if (half == 0) tv[NB * c + q] -= v;
     }
     __syncthreads();
   }
+  double* x = xall + W.x_off;
   for (int i = tid; i < npad; i += 1024) x[i] = (i < n) ? xs[i] : 0.0;
 }
-
-size_t step_lds() { return sizeof(double) * 4 * NB * LD; }
 
 }  // namespace
 
 void chol_set_attributes() {
-  (void)hipFuncSetAttribute((const void*)k_chol_step, hipFuncAttributeMaxDynamicSharedMemorySize, (int)step_lds());
+  const int lds = (int)(sizeof(double) * 2 * ((15 * kMaxKeyframes + NB - 1) / NB * NB));
+  (void)hipFuncSetAttribute((const void*)k_chol_backsolve, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 void launch_chol(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, DevStatus* st) {
   int npad_max = 0;
   for (const WinDev& W : P.win) npad_max = std::max(npad_max, W.npad);
-  for (int kb = 0; kb < P.nblk_max; ++kb) {
-    int wgs = 0;
-    for (const WinDev& W : P.win) {
-      if (kb >= W.nblk) continue;
-      int cnt = W.nblk - kb + 1;
-      if (kb > 0)
-        for (int jb = kb + 1; jb < W.nblk; ++jb) cnt += W.nblk - jb + 1;
-      wgs = std::max(wgs, cnt);
-    }
-    hipLaunchKernelGGL(k_chol_step, dim3(wgs, P.n_win), dim3(256), step_lds(), s, D, kb, w.A, w.Linv, st);
-  }
-  hipLaunchKernelGGL(k_chol_solve, dim3(P.n_win), dim3(1024), sizeof(double) * npad_max, s, D, w.A, w.Linv, w.x);
+  const int grid = std::min(P.n_tickets, kMaxDataflowWG);
+  hipLaunchKernelGGL(k_chol_df, dim3(grid), dim3(64), 0, s, D, P.n_tickets, w.A, w.Linv, w.flags, w.sync, st);
+  hipLaunchKernelGGL(k_chol_backsolve, dim3(P.n_win), dim3(1024), sizeof(double) * 2 * npad_max, s, D, w.A, w.Linv,
+                     w.x, w.sync, st);
 }
 
 }  // namespace vi

@@ -277,7 +277,9 @@ __device__ void imu_factor_block(int f, const WinDev& W, const double* __restric
 // on FP64 MFMA 16x16x4 over lower-triangular 16x16 tiles.  The E-block never
 // leaves the chip.  MFMA operand layout: lane l supplies A[l%16][l/16] and
 // B[l/16][l%16]; it receives D[l/16 + 4 r][l%16] in element r.  Inertial
-// factors ride along as extra workgroups (blockIdx.y >= N).
+// factors ride along as extra workgroups (the first imu_rows rows of the grid,
+// so that their serial rotation algebra starts first and overlaps the vision
+// workgroups).
 // ---------------------------------------------------------------------------
 constexpr int kMaxTilesPerWave = 7;     // T <= 7 for 6k+1 <= 112
 constexpr int kEdgeSlots = (kMaxOutDegree + 3) / 4;
@@ -289,7 +291,7 @@ __device__ __forceinline__ void tile_ij(int t, int& I, int& J) {
   J = t - i * (i + 1) / 2;
 }
 
-__global__ void __launch_bounds__(256) k_vis_gram(OptsDev o, DevPlan D, int N, int F, int nkr_max, int ncost,
+__global__ void __launch_bounds__(256) k_vis_gram(OptsDev o, DevPlan D, int imu_rows, int F, int nkr_max, int ncost,
                                                   int range, const double* __restrict__ Lam, double* __restrict__ Rw,
                                                   double* __restrict__ rel, double* __restrict__ Cd,
                                                   double* __restrict__ wd, double* __restrict__ hpart,
@@ -299,15 +301,15 @@ __global__ void __launch_bounds__(256) k_vis_gram(OptsDev o, DevPlan D, int N, i
   extern __shared__ double sm[];
   __shared__ double red[2][4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if ((int)blockIdx.y >= N) {
-    const int f = ((int)blockIdx.y - N) * (int)gridDim.x + (int)blockIdx.x;
+  if ((int)blockIdx.y < imu_rows) {
+    const int f = (int)blockIdx.y * (int)gridDim.x + (int)blockIdx.x;
     if (f < F && o.use_imu) {
       const WinDev W = D.win[D.win_of_f[f]];
       imu_factor_block(f, W, Lam, Hf, gf, icost, sm);
     }
     return;
   }
-  const int src = blockIdx.y, kr = blockIdx.x;
+  const int src = blockIdx.y - imu_rows, kr = blockIdx.x;
   const WinDev W = D.win[D.win_of_kf[src]];
   const int HW = W.HW;
   const int p_beg = kr * range;
@@ -485,25 +487,27 @@ __device__ __forceinline__ double Mj_at(const double* Rj, int r, int c) {
 }
 
 // cost trace of window w: sum of its vision partials (ranges of range_px pixels
-// per source keyframe) and of its inertial factor costs
+// per source keyframe) and of its inertial factor costs.  Any power-of-two
+// block size; s0 holds 2 * blockDim.x doubles.
 __device__ void cost_reduce_block(const WinDev& W, int w, int ncost, int range_px, const double* __restrict__ vcost,
                                   const double* __restrict__ icost, int use_imu, double* __restrict__ trace,
                                   int slot, double* s0) {
-  double* s1 = s0 + 256;
+  const int nt = blockDim.x;
+  double* s1 = s0 + nt;
   const int t = threadIdx.x;
   const int nk = (W.HW + range_px - 1) / range_px;
   double c = 0.0, n = 0.0;
-  for (int i = t; i < W.N * nk; i += 256) {
+  for (int i = t; i < W.N * nk; i += nt) {
     const size_t b = ((size_t)(W.kf_base + i / nk) * ncost + i % nk) * 2;
     c += vcost[b];
     n += vcost[b + 1];
   }
   if (use_imu)
-    for (int i = t; i < W.F; i += 256) c += icost[W.f_base + i];
+    for (int i = t; i < W.F; i += nt) c += icost[W.f_base + i];
   s0[t] = c;
   s1[t] = n;
   __syncthreads();
-  for (int q = 128; q > 0; q >>= 1) {
+  for (int q = nt / 2; q > 0; q >>= 1) {
     if (t < q) { s0[t] += s0[t + q]; s1[t] += s1[t + q]; }
     __syncthreads();
   }
@@ -513,13 +517,37 @@ __device__ void cost_reduce_block(const WinDev& W, int w, int ncost, int range_p
   }
 }
 
-__global__ void __launch_bounds__(256) k_local(int N, int nkr_max, int ncost, int range, DevPlan D,
-                                               const double* __restrict__ Rw, const double* __restrict__ rel,
-                                               const double* __restrict__ hpart,
-                                               const double* __restrict__ gpart, double* __restrict__ Z,
-                                               double* __restrict__ ZB, double* __restrict__ ZV,
-                                               const double* __restrict__ vcost, const double* __restrict__ icost,
-                                               int use_imu, double* __restrict__ trace, int slot) {
+// Sum of n partials p[0], p[stride], ... in a fixed order, with U loads in
+// flight per step (the loads are clamped in range and masked, so they can all
+// be issued before the first one returns).
+template <int U>
+__device__ __forceinline__ double sum_partials(const double* __restrict__ p, size_t stride, int n) {
+  double acc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) acc[u] = 0.0;
+  for (int r0 = 0; r0 < n; r0 += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = p[(size_t)min(r0 + u, n - 1) * stride];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] += (r0 + u < n) ? v[u] : 0.0;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) s += acc[u];
+  return s;
+}
+
+constexpr int kLocalThreads = 512;
+
+__global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int ncost, int range, DevPlan D,
+                                                         const double* __restrict__ Rw, const double* __restrict__ rel,
+                                                         const double* __restrict__ hpart,
+                                                         const double* __restrict__ gpart, double* __restrict__ Z,
+                                                         double* __restrict__ ZB, double* __restrict__ ZV,
+                                                         const double* __restrict__ vcost,
+                                                         const double* __restrict__ icost, int use_imu,
+                                                         double* __restrict__ trace, int slot) {
   extern __shared__ double sm[];
   if ((int)blockIdx.x >= N) {
     const int w = blockIdx.x - N;
@@ -531,116 +559,163 @@ __global__ void __launch_bounds__(256) k_local(int N, int nkr_max, int ncost, in
   const int e0 = D.src_off[src];
   const int k = D.src_off[src + 1] - e0;
   const int tid = threadIdx.x;
+  constexpr int NT = kLocalThreads;
   const int K1 = k + 1;
   double* Zs = Z + D.z_off[src];
   double* ZBs = ZB + D.zb_off[src];
   double* ZVs = ZV + D.zb_off[src];
   if (k == 0) {
-    for (int i = tid; i < 36; i += 256) Zs[i] = 0.0;
-    for (int i = tid; i < 6; i += 256) { ZBs[i] = 0.0; ZVs[i] = 0.0; }
+    for (int i = tid; i < 36; i += NT) Zs[i] = 0.0;
+    for (int i = tid; i < 6; i += NT) { ZBs[i] = 0.0; ZVs[i] = 0.0; }
     return;
   }
   const int ncol = 6 * k, nq = ncol + 1;
   const int T = (ncol + 16) / 16;
   const int ntiles = T * (T + 1) / 2;
   double* Qs = sm;                  // [nq][nq] symmetric
-  double* Mi = Qs + nq * nq;        // [k][36]
-  double* Mj = Mi + 36 * k;         // [k][36]
-  double* Hs = Mj + 36 * k;         // [k][36] full symmetric
+  double* Mi = Qs + nq * nq;        // [k][36]  M_i of edge s
+  double* Rj = Mi + 36 * k;         // [k][9]   R_j of edge s (M_j = -blockdiag(I, R_j^T))
+  double* Hs = Rj + 9 * k;          // [k][36]  full symmetric
   double* gs = Hs + 36 * k;         // [k][6]   g - y
   double* Wt = gs + 6 * k;          // [k][36]
-  // Gram partials -> Q (lower tiles hold the data; mirror into both triangles)
+  // Gram partials -> Q.  The lower tiles hold the data; the lower triangle is
+  // mirrored into both halves (inside a diagonal tile the MFMA result is not
+  // exactly symmetric, so only its a >= b entries are used: one writer per slot).
   const double* gp = gpart + D.gram_off[src];
-  for (int i = tid; i < ntiles * 256; i += 256) {
+  const size_t gstride = (size_t)ntiles * 256;
+  for (int i = tid; i < ntiles * 256; i += NT) {
     const int t = i >> 8, e = i & 255;
-    double v = 0.0;
-    for (int r = 0; r < nkr; ++r) v += gp[((size_t)r * ntiles + t) * 256 + e];
     int I = 0;
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
     const int J = t - I * (I + 1) / 2;
     const int a = 16 * I + (e >> 4), b = 16 * J + (e & 15);
-    if (a < nq && b < nq) {
+    if (a < nq && b < nq && a >= b) {
+      const double v = sum_partials<8>(gp + i, gstride, nkr);
       Qs[a * nq + b] = v;
       Qs[b * nq + a] = v;
     }
   }
-  for (int i = tid; i < k * 36; i += 256) {
+  for (int i = tid; i < k * 36; i += NT) {
     const int s = i / 36, rc = i % 36, r = rc / 6, c = rc % 6;
     const int e = D.src_edges[e0 + s];
     const double* Rt = rel + (size_t)e * 12;
-    const double* Rj = Rw + (size_t)D.jj[e] * 9;
-    Mi[i] = Mi_at(Rt, Rj, r, c);
-    Mj[i] = Mj_at(Rj, r, c);
+    const double* Rjs = Rw + (size_t)D.jj[e] * 9;
+    Mi[i] = Mi_at(Rt, Rjs, r, c);
+    if (rc < 9) Rj[s * 9 + rc] = Rjs[rc];
     const int a = min(r, c), b = max(r, c);
     const int q = a * 6 - a * (a - 1) / 2 + (b - a);
-    double h = 0.0;
-    const double* hp = hpart + (size_t)(e0 + s) * nkr_max * 32 + q;
-    for (int t = 0; t < nkr; ++t) h += hp[(size_t)t * 32];
-    Hs[i] = h;
+    Hs[i] = sum_partials<8>(hpart + (size_t)(e0 + s) * nkr_max * 32 + q, 32, nkr);
+  }
+  for (int i = tid; i < k * 6; i += NT) {
+    const int s = i / 6;
+    gs[i] = sum_partials<8>(hpart + (size_t)(e0 + s) * nkr_max * 32 + 21 + i % 6, 32, nkr);
   }
   __syncthreads();
-  for (int i = tid; i < k * 6; i += 256) {
-    const int s = i / 6, c = i % 6;
-    double g = 0.0;
-    const double* hp = hpart + (size_t)(e0 + s) * nkr_max * 32 + 21 + c;
-    for (int t = 0; t < nkr; ++t) g += hp[(size_t)t * 32];
-    gs[i] = g - Qs[ncol * nq + 6 * s + c];
-  }
+  for (int i = tid; i < k * 6; i += NT) gs[i] -= Qs[ncol * nq + i];
   // W_t = sum_s M_i,s^T X_st,  X_st = delta_st H_s - Q_st
-  for (int i = tid; i < k * 36; i += 256) {
+  for (int i = tid; i < k * 36; i += NT) {
     const int t = i / 36, a = (i % 36) / 6, b = i % 6;
     double v = 0.0;
-    for (int s = 0; s < k; ++s)
+    for (int s2 = 0; s2 < k; ++s2) {
+      const double* Ms = Mi + s2 * 36;
+      const double* Qr = Qs + (6 * s2) * nq + 6 * t + b;
+#pragma unroll
       for (int m = 0; m < 6; ++m) {
-        double x = -Qs[(6 * s + m) * nq + 6 * t + b];
-        if (s == t) x += Hs[s * 36 + m * 6 + b];
-        v += Mi[s * 36 + m * 6 + a] * x;
+        double x = -Qr[m * nq];
+        if (s2 == t) x += Hs[s2 * 36 + m * 6 + b];
+        v += Ms[m * 6 + a] * x;
       }
+    }
     Wt[i] = v;
   }
-  __syncthreads();
-  // Z_s+1,t+1 = M_j,s^T X_st M_j,t for all s, t
-  for (int i = tid; i < k * k * 36; i += 256) {
-    const int st = i / 36, s = st / k, t = st % k, a = (i % 36) / 6, b = i % 6;
-    double v = 0.0;
-    for (int m = 0; m < 6; ++m) {
-      double u = 0.0;
-      for (int nn = 0; nn < 6; ++nn) {
-        double x = -Qs[(6 * s + m) * nq + 6 * t + nn];
-        if (s == t) x += Hs[s * 36 + m * 6 + nn];
-        u += x * Mj[t * 36 + nn * 6 + b];
+  // Z_s+1,t+1 = M_j,s^T X_st M_j,t = P_s^T X_st P_t with P = blockdiag(I, R_j^T):
+  // [[X11, X12 R_t^T], [R_s X21, R_s X22 R_t^T]]
+  for (int i = tid; i < k * k * 36; i += NT) {
+    const int st = i / 36, s2 = st / k, t = st % k, a = (i % 36) / 6, b = i % 6;
+    const double* Qb = Qs + (6 * s2) * nq + 6 * t;
+    const bool diag = s2 == t;
+    const double* Hb = Hs + s2 * 36;
+    auto X = [&](int m, int n) { return (diag ? Hb[m * 6 + n] : 0.0) - Qb[m * nq + n]; };
+    const double* Rs = Rj + s2 * 9;
+    const double* Rt = Rj + t * 9;
+    double v;
+    if (a < 3 && b < 3) {
+      v = X(a, b);
+    } else if (a < 3) {
+      v = 0.0;
+#pragma unroll
+      for (int n = 0; n < 3; ++n) v += X(a, 3 + n) * Rt[(b - 3) * 3 + n];
+    } else if (b < 3) {
+      v = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) v += Rs[(a - 3) * 3 + m] * X(3 + m, b);
+    } else {
+      v = 0.0;
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        double u = 0.0;
+#pragma unroll
+        for (int n = 0; n < 3; ++n) u += X(3 + m, 3 + n) * Rt[(b - 3) * 3 + n];
+        v += Rs[(a - 3) * 3 + m] * u;
       }
-      v += Mj[s * 36 + m * 6 + a] * u;
     }
-    Zs[(size_t)((s + 1) * K1 + t + 1) * 36 + a * 6 + b] = v;
+    Zs[(size_t)((s2 + 1) * K1 + t + 1) * 36 + a * 6 + b] = v;
   }
-  // Z_0,t+1 = W_t M_j,t and its transpose; Z_00 = sum_t W_t M_i,t
-  for (int i = tid; i < k * 36; i += 256) {
+  __syncthreads();
+  // Z_0,t+1 = W_t M_j,t = -W_t P_t and its transpose; Z_00 = sum_t W_t M_i,t
+  for (int i = tid; i < k * 36; i += NT) {
     const int t = i / 36, a = (i % 36) / 6, b = i % 6;
-    double v = 0.0;
-    for (int m = 0; m < 6; ++m) v += Wt[t * 36 + a * 6 + m] * Mj[t * 36 + m * 6 + b];
+    const double* Wb = Wt + t * 36 + a * 6;
+    double v;
+    if (b < 3) {
+      v = -Wb[b];
+    } else {
+      const double* Rt = Rj + t * 9;
+      v = -(Wb[3] * Rt[(b - 3) * 3 + 0] + Wb[4] * Rt[(b - 3) * 3 + 1] + Wb[5] * Rt[(b - 3) * 3 + 2]);
+    }
     Zs[(size_t)(0 * K1 + t + 1) * 36 + a * 6 + b] = v;
     Zs[(size_t)((t + 1) * K1 + 0) * 36 + b * 6 + a] = v;
   }
-  for (int i = tid; i < 36; i += 256) {
+  for (int i = tid; i < 36; i += NT) {
     const int a = i / 6, b = i % 6;
     double v = 0.0;
     for (int t = 0; t < k; ++t)
+#pragma unroll
       for (int m = 0; m < 6; ++m) v += Wt[t * 36 + a * 6 + m] * Mi[t * 36 + m * 6 + b];
     Zs[a * 6 + b] = v;
   }
-  for (int i = tid; i < 6 * K1; i += 256) {
+  for (int i = tid; i < 6 * K1; i += NT) {
     const int ra = i / 6, a = i % 6;
     double zb = 0.0, zv = 0.0;
-    const int s_lo = (ra == 0) ? 0 : ra - 1;
-    const int s_hi = (ra == 0) ? k : ra;
-    for (int s = s_lo; s < s_hi; ++s) {
-      const double* M = (ra == 0) ? Mi + s * 36 : Mj + s * 36;
-      for (int m = 0; m < 6; ++m) {
-        double hm = 0.0;
-        for (int nn = 0; nn < 6; ++nn) hm += Hs[s * 36 + m * 6 + nn] * M[nn * 6 + a];
-        zb += M[m * 6 + a] * hm;
-        zv += M[m * 6 + a] * gs[s * 6 + m];
+    if (ra == 0) {
+      for (int s2 = 0; s2 < k; ++s2) {
+        const double* M = Mi + s2 * 36;
+        for (int m = 0; m < 6; ++m) {
+          double hm = 0.0;
+#pragma unroll
+          for (int nn = 0; nn < 6; ++nn) hm += Hs[s2 * 36 + m * 6 + nn] * M[nn * 6 + a];
+          zb += M[m * 6 + a] * hm;
+          zv += M[m * 6 + a] * gs[s2 * 6 + m];
+        }
+      }
+    } else {
+      // M_j = -P: diag(P^T H P) and -P^T (g - y)
+      const int s2 = ra - 1;
+      const double* H = Hs + s2 * 36;
+      const double* g = gs + s2 * 6;
+      if (a < 3) {
+        zb = H[a * 6 + a];
+        zv = -g[a];
+      } else {
+        const double* R = Rj + s2 * 9 + (a - 3) * 3;   // row a-3 of R_j: P[3+m][a] = R_j[a-3][m]
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          double hm = 0.0;
+#pragma unroll
+          for (int nn = 0; nn < 3; ++nn) hm += H[(3 + m) * 6 + 3 + nn] * R[nn];
+          zb += R[m] * hm;
+          zv -= R[m] * g[3 + m];
+        }
       }
     }
     ZBs[i] = zb;
@@ -664,12 +739,16 @@ __device__ __forceinline__ bool coord_active(const OptsDev& o, int a, int ra) {
 
 __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, const double* __restrict__ ZB,
                            const double* __restrict__ ZV, const double* __restrict__ Hf,
-                           const double* __restrict__ gf, double* __restrict__ A, DevStatus* st) {
+                           const double* __restrict__ gf, double* __restrict__ A, int* __restrict__ flags,
+                           int* __restrict__ sync, DevStatus* st) {
   const int w = blockIdx.y;
   const WinDev& W = D.win[w];
   const int N = W.N, n = W.n, npad = W.npad;
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t total = (size_t)(npad + kCholNB) * npad;
+  // the Cholesky tile flags and ticket counter start from zero
+  if (idx < (size_t)W.nflags) flags[W.flag_off + idx] = 0;
+  if (w == 0 && idx < 4) sync[idx] = 0;
   if (idx >= total) return;
   const int r = (int)(idx / npad), c = (int)(idx % npad);
   const double* Hw = Hf + (size_t)W.f_base * 900;
@@ -903,7 +982,7 @@ static size_t vis_lds(int kmax) {
 }
 static size_t local_lds(int kmax) {
   const size_t k = kmax, nq = 6 * k + 1;
-  return sizeof(double) * std::max<size_t>(nq * nq + 4 * 36 * k + 6 * k, 512);
+  return sizeof(double) * std::max<size_t>(nq * nq + 3 * 36 * k + 9 * k + 6 * k, 2 * kLocalThreads);
 }
 
 void launch_reset_status(hipStream_t s, DevStatus* st, int n) {
@@ -927,11 +1006,12 @@ static void launch_front(hipStream_t s, const Plan& P, const DevPlan& D, const W
   const int nkr_run = (P.hw_max + P.range - 1) / P.range;          // workgroups per source in x
   const int imu_rows = (F + nkr_run - 1) / nkr_run;
   const int ncost = cost_slots(P);
-  hipLaunchKernelGGL(k_vis_gram, dim3(nkr_run, N + imu_rows), dim3(256), vis_lds(P.kmax), s, o, D, N, F,
+  hipLaunchKernelGGL(k_vis_gram, dim3(nkr_run, N + imu_rows), dim3(256), vis_lds(P.kmax), s, o, D, imu_rows, F,
                      P.nkr_max, ncost, P.range, w.Lam, w.Rw, w.rel, w.Cd, w.wd, w.hpart, w.gpart, w.vcost, w.Hf,
                      w.gf, w.icost);
   done(kStVis);
-  hipLaunchKernelGGL(k_local, dim3(N + P.n_win), dim3(256), local_lds(P.kmax), s, N, P.nkr_max, ncost, P.range, D,
+  hipLaunchKernelGGL(k_local, dim3(N + P.n_win), dim3(kLocalThreads), local_lds(P.kmax), s, N, P.nkr_max, ncost,
+                     P.range, D,
                      w.Rw, w.rel, w.hpart, w.gpart, w.Z, w.ZB, w.ZV, w.vcost, w.icost, o.use_imu, w.trace, iter);
   done(kStLocal);
 }
@@ -949,7 +1029,7 @@ void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, 
   size_t total_max = 0;
   for (const WinDev& W : P.win) total_max = std::max(total_max, (size_t)(W.npad + kCholNB) * W.npad);
   hipLaunchKernelGGL(k_assemble, dim3((unsigned)((total_max + 255) / 256), P.n_win), dim3(256), 0, s, o, D, w.Z,
-                     w.ZB, w.ZV, w.Hf, w.gf, w.A, st);
+                     w.ZB, w.ZV, w.Hf, w.gf, w.A, w.flags, w.sync, st);
   done(kStAssemble);
   launch_chol(s, P, D, w, st);
   done(kStChol);

@@ -22,8 +22,9 @@ namespace vi {
 
 constexpr int kMaxOutDegree = 18;     // per-source outgoing edges (Gram tile budget)
 constexpr int kVisBlock = 256;        // pixels per workgroup of the per-pixel kernels
-constexpr int kCholNB = 64;           // Cholesky block size
+constexpr int kCholNB = 32;           // Cholesky tile size
 constexpr int kMaxIters = 64;         // cost trace capacity of vi_ba_solve
+constexpr int kMaxKeyframes = 640;    // per window: the back-substitution keeps 2 x 15 N doubles in LDS
 constexpr int kTraceLen = 2 * (kMaxIters + 1);
 
 // Device status word of one window: first error (vi_status), its detail (e.g.
@@ -43,6 +44,7 @@ struct WinDev {
   int nkr;                           // pixel ranges per source in the fused assembly + Gram
   int n, npad, nblk;                 // reduced system
   int pair_base;                     // offset of this window's pair table
+  int flag_off, nflags;              // Cholesky tile flags [(nblk + 1) * nblk]
   long long pix_base;                // global offset of the first keyframe's first pixel
   long long A_off, Linv_off, x_off;  // reduced system, diagonal-tile inverses, solution
   double* pose;
@@ -73,6 +75,9 @@ struct Plan {
   std::vector<int32_t> src_off, src_edges;     // CSR of edges by source keyframe
   std::vector<int32_t> gram_off, z_off, zb_off;
   std::vector<int32_t> pair_off, pair_z, pair_zb;
+  std::vector<int32_t> chol_tiles;             // ticket -> (window, (i << 16) | j)
+  int n_tickets = 0;
+  size_t flags_size = 0;
   size_t gram_size = 0, z_size = 0, zb_size = 0;
   size_t A_size = 0, Linv_size = 0, x_size = 0;
 };
@@ -82,6 +87,7 @@ struct DevPlan {
   const int32_t *ii, *jj, *win_of_kf, *win_of_f, *src_off, *src_edges;
   const int32_t *gram_off, *z_off, *zb_off;
   const int32_t *pair_off, *pair_z, *pair_zb;
+  const int32_t* chol_tiles;
   const WinDev* win;
 };
 
@@ -102,6 +108,8 @@ struct Work {
   double* gf;        // [F][30]
   double* icost;     // [F]
   double* A;         // per window [(npad + NB) * npad]  reduced matrix (+ augmented rhs row)
+  int32_t* flags;    // Cholesky tile flags of all windows
+  int32_t* sync;     // [0] ticket counter, [1] abort flag
   double* Linv;      // per window [nblk][NB*NB]
   double* x;         // per window [npad]
   double* dd;        // [pix_total]
