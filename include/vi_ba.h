@@ -142,11 +142,23 @@ typedef struct {
   const float* weight;       /* device [E][2][H][W] weights >= 0, per coordinate */
 } vi_edges;
 
+/* Arithmetic of the step (vi_opts.precision).
+ *  VI_PREC_FP64   every stage in FP64.
+ *  VI_PREC_MIXED  per-pixel residuals and Jacobians (Eq. 1), the per-edge
+ *                 J^T W J reductions and the Schur Gram of Eq. 4 in FP32 (FP32
+ *                 MFMA; partial sums over 64-pixel blocks Kahan-compensated
+ *                 across blocks, then handed over in FP64); C and w_d, the
+ *                 inertial factors (Eq. 2-3), the reduced system, its Cholesky
+ *                 solve, the depth update and the retraction in FP64; IMU
+ *                 preintegration is always FP64. */
+#define VI_PREC_FP64 0
+#define VI_PREC_MIXED 1
+
 typedef struct {
   int32_t n_fixed;           /* gauge: leading keyframes whose pose is held (>= 1 typical) */
   int32_t use_imu;           /* 0: vision only (velocity and bias are not solved) */
   int32_t bias_fixed;        /* 1: biases are not solved */
-  int32_t reserved;          /* must be 0 */
+  int32_t precision;         /* VI_PREC_FP64 or VI_PREC_MIXED */
   double lm_lambda;          /* Marquardt factor on the pose/vel/bias diagonal (>= 0) */
   double depth_eta;          /* added to the inverse-depth diagonal C (>= 0) */
   double z_min;              /* minimum depth in the target camera, m */

@@ -15,6 +15,7 @@ import numpy as np
 from ._build import LIB_PATH
 
 VI_OK, VI_EINVAL, VI_ENOMEM, VI_EDEVICE, VI_ENOTPD, VI_ENONFINITE, VI_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+VI_PREC_FP64, VI_PREC_MIXED = 0, 1
 STATUS_NAMES = {0: "VI_OK", -1: "VI_EINVAL", -2: "VI_ENOMEM", -3: "VI_EDEVICE", -4: "VI_ENOTPD",
                 -5: "VI_ENONFINITE", -6: "VI_EUNSUPPORTED"}
 NUM_STAGES = 6
@@ -50,7 +51,7 @@ class Edges(C.Structure):
 
 class Opts(C.Structure):
     _fields_ = [("n_fixed", C.c_int32), ("use_imu", C.c_int32), ("bias_fixed", C.c_int32),
-                ("reserved", C.c_int32), ("lm_lambda", C.c_double), ("depth_eta", C.c_double),
+                ("precision", C.c_int32), ("lm_lambda", C.c_double), ("depth_eta", C.c_double),
                 ("z_min", C.c_double), ("d_min", C.c_double)]
 
 
@@ -132,8 +133,10 @@ def make_camera(fx, fy, cx, cy, H, W, gravity=(0.0, 0.0, -9.81)) -> Camera:
 
 
 def make_opts(n_fixed=1, use_imu=True, bias_fixed=False, lm_lambda=1e-4, depth_eta=1e-8, z_min=0.1,
-              d_min=1e-3) -> Opts:
-    return Opts(n_fixed, int(bool(use_imu)), int(bool(bias_fixed)), 0, lm_lambda, depth_eta, z_min, d_min)
+              d_min=1e-3, precision=0) -> Opts:
+    """precision: VI_PREC_FP64 (0) or VI_PREC_MIXED (1)."""
+    return Opts(n_fixed, int(bool(use_imu)), int(bool(bias_fixed)), int(precision), lm_lambda, depth_eta, z_min,
+                d_min)
 
 
 class Context:

@@ -117,7 +117,8 @@ vi_status check_window(vi_ctx* ctx, int w, const WinIn& in, const vi_opts* o, bo
 vi_status check_opts(vi_ctx* ctx, const vi_opts* o) {
   if (!o) return fail(ctx, VI_EINVAL, "null options");
   if (o->n_fixed < 0) return fail(ctx, VI_EINVAL, "n_fixed out of range");
-  if (o->reserved != 0) return fail(ctx, VI_EINVAL, "opts.reserved must be 0");
+  if (o->precision != VI_PREC_FP64 && o->precision != VI_PREC_MIXED)
+    return fail(ctx, VI_EINVAL, "opts.precision must be VI_PREC_FP64 or VI_PREC_MIXED");
   if (!(o->lm_lambda >= 0.0) || !(o->depth_eta >= 0.0) || !std::isfinite(o->lm_lambda) ||
       !std::isfinite(o->depth_eta))
     return fail(ctx, VI_EINVAL, "damping must be finite and >= 0");
@@ -249,14 +250,20 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
     x_off += (size_t)W.npad;
     P.nblk_max = std::max(P.nblk_max, W.nblk);
     std::vector<std::vector<std::pair<int, int>>> items((size_t)W.N * W.N);
+    int bw_kf = 1;   // inertial factors couple consecutive keyframes
     for (int g = W.kf_base; g < W.kf_base + W.N; ++g) {
       const int k = cnt[g];
       std::vector<int> T(1, g - W.kf_base);
       for (int s = P.src_off[g]; s < P.src_off[g + 1]; ++s) T.push_back(P.jj[P.src_edges[s]] - W.kf_base);
       for (int ta = 0; ta <= k; ++ta)
-        for (int tb = 0; tb <= k; ++tb)
+        for (int tb = 0; tb <= k; ++tb) {
           items[(size_t)T[ta] * W.N + T[tb]].push_back({P.z_off[g] + (ta * (k + 1) + tb) * 36, P.zb_off[g] + 6 * ta});
+          bw_kf = std::max(bw_kf, std::abs(T[ta] - T[tb]));
+        }
     }
+    // scalar half-bandwidth of S and the tile band of S and of its factor
+    const int wsc = 15 * bw_kf + 14;
+    W.band = std::min(W.nblk - 1, (wsc + kCholNB - 1) / kCholNB);
     // this window's table: entries pair_base .. pair_base + N*N (the last one is its end)
     W.pair_base = (int)P.pair_off.size();
     for (size_t q = 0; q < items.size(); ++q) {
@@ -269,12 +276,13 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
     P.pair_off.push_back((int32_t)P.pair_z.size());
   }
   if (P.pair_z.empty()) { P.pair_z.push_back(0); P.pair_zb.push_back(0); }
-  // Cholesky tickets: column j, then window, then block row i (nblk = the
-  // right-hand-side block), so that every tile depends on smaller tickets only
+  // Cholesky tickets of the windows too large for the one-workgroup path:
+  // column j, then window, then block row i (nblk = the right-hand-side
+  // block), so that every tile depends on smaller tickets only
   for (int j = 0; j < P.nblk_max; ++j)
     for (int w = 0; w < nw; ++w) {
       const WinDev& W = P.win[w];
-      if (j >= W.nblk) continue;
+      if (j >= W.nblk || W.npad <= kCholSmallMaxNpad) continue;
       for (int i = j; i <= W.nblk; ++i) {
         P.chol_tiles.push_back(w);
         P.chol_tiles.push_back((i << 16) | j);
@@ -489,7 +497,8 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
   if (workspace_bytes < need)
     return fail(ctx, VI_ENOMEM, "workspace too small: %zu bytes given, %zu needed", workspace_bytes, need);
   Work w = do_carve(P, workspace, nullptr);
-  OptsDev od{o->n_fixed, o->use_imu ? 1 : 0, o->bias_fixed ? 1 : 0, o->lm_lambda, o->depth_eta, o->z_min, o->d_min};
+  OptsDev od{o->n_fixed, o->use_imu ? 1 : 0, o->bias_fixed ? 1 : 0, o->precision, o->lm_lambda, o->depth_eta,
+             o->z_min, o->d_min};
   const bool timing = wins[0].rep && wins[0].rep->stage_ms;
 
   // order after the caller's pending work
@@ -608,7 +617,7 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
 
 extern "C" {
 
-const char* vi_version(void) { return "vi-ba-mi355x 0.2 (gfx950, fp64)"; }
+const char* vi_version(void) { return "vi-ba-mi355x 0.3 (gfx950; fp64 and mixed fp32/fp64)"; }
 
 vi_status vi_ctx_create(int32_t device, void* stream, vi_ctx** out) {
   if (!out) return VI_EINVAL;

@@ -22,6 +22,15 @@
 // Back-substitution x = L^-T y runs per window in one 1024-thread workgroup,
 // block column by block column: x_b = L_bb^-T t_b, then t_c -= L_bc^T x_b
 // for every c < b in parallel over the waves.
+//
+// Windows with npad <= kSmallMaxNpad (sliding windows) are factored and
+// solved entirely inside one 512-thread workgroup instead (no inter-
+// workgroup traffic; the critical path is the chain of diagonal-tile
+// factorisations).  That path skips the tiles outside the window's band: a
+// banded matrix (every nonzero within w of the diagonal) has a banded Cholesky
+// factor, so tiles with 32 (i - j) - 31 > w stay zero.  The diagonal tile is
+// factored recursively (two 16 x 16 leaves, the coupling block by MFMA), which
+// halves the serial broadcast chain of a flat 32-pivot factorisation.
 #include <algorithm>
 
 #include "vi_internal.h"
@@ -34,6 +43,7 @@ constexpr int NB = kCholNB;          // 32
 constexpr int LD = NB + 1;
 constexpr int kSpinLimit = 1 << 22;  // polls (each with a short sleep) before the batch is aborted
 constexpr int kMaxDataflowWG = 4096;
+constexpr int kSmallMaxNpad = kCholSmallMaxNpad;
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
 
@@ -53,7 +63,7 @@ __device__ __forceinline__ int load_flag(const int* f) {
 }
 
 // Wait (whole wave) until *f is set.  false: the batch was aborted.
-__device__ bool wait_flag(const int* f, int* sync) {
+__device__ __forceinline__ bool wait_flag(const int* f, int* sync) {
   int spins = 0;
   while (__builtin_amdgcn_readfirstlane(load_flag(f)) == 0) {
     if (__builtin_amdgcn_readfirstlane(load_flag(sync + 1)) != 0) return false;
@@ -165,9 +175,11 @@ __global__ void __launch_bounds__(64) k_chol_df(DevPlan D, int ntickets, double*
         if (lane == c) rinv[c] = r;
         x[c] = (row == c) ? piv * r : (row > c ? x[c] * r : x[c]);
 #pragma unroll
-        for (int m = c + 1; m < NB; ++m) {
-          const double lm = readlane_d(x[c], m);
-          if (row >= m) x[m] -= x[c] * lm;
+        for (int m = 1; m < NB; ++m) {
+          if (m > c) {
+            const double lm = readlane_d(x[c], m);
+            if (row >= m) x[m] -= x[c] * lm;
+          }
         }
       }
       if (bad >= 0 && lane == 0 && NB * j + bad < W.n) set_status(stall + w, VI_ENOTPD, NB * j + bad);
@@ -180,7 +192,8 @@ __global__ void __launch_bounds__(64) k_chol_df(DevPlan D, int ntickets, double*
       for (int r = 0; r < NB; ++r) {
         double v = (r == row) ? 1.0 : 0.0;
 #pragma unroll
-        for (int q = 0; q < r; ++q) v -= T[r * LD + q] * y[q];
+        for (int q = 0; q < NB - 1; ++q)
+          if (q < r) v -= T[r * LD + q] * y[q];
         y[r] = v * rinv[r];
       }
       if (lane < NB) {
@@ -225,6 +238,257 @@ __global__ void __launch_bounds__(64) k_chol_df(DevPlan D, int ntickets, double*
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// one-wave helpers on 16 x 16 blocks in LDS (row-major with stride ld)
+// ---------------------------------------------------------------------------
+// In-place Cholesky of the SPD block M (lower triangle of the result is L,
+// upper set to zero); rinv[c] = 1 / L[c][c].  Returns the first bad pivot
+// index or -1.  Lane r (< 16) holds row r; other lanes mirror it.
+__device__ __forceinline__ int leaf16_factor(double* M, int ld, double* rinv) {
+  const int lane = threadIdx.x & 63, row = lane & 15;
+  double x[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) x[c] = M[row * ld + c];
+  int bad = -1;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) {
+    double piv = readlane_d(x[c], c);
+    if (!(piv > 0.0)) {
+      if (bad < 0) bad = c;
+      piv = 1.0;
+    }
+    const double r = rsqrt_refined(piv);
+    if (lane == c) rinv[c] = r;
+    x[c] = (row == c) ? piv * r : (row > c ? x[c] * r : x[c]);
+#pragma unroll
+    for (int m = 1; m < 16; ++m) {
+      if (m > c) {   // constant trip count: fully unrolled, x stays in registers
+        const double lm = readlane_d(x[c], m);
+        if (row >= m) x[m] -= x[c] * lm;
+      }
+    }
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c) M[row * ld + c] = (c <= row) ? x[c] : 0.0;
+  }
+  return bad;
+}
+
+// Minv = L^-1 for the lower-triangular 16 x 16 L in M (rinv = 1 / diag);
+// lane c (< 16) computes column c.
+__device__ __forceinline__ void leaf16_inverse(const double* M, int ld, const double* rinv, double* Minv, int ldi) {
+  const int lane = threadIdx.x & 63, col = lane & 15;
+  double y[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    double v = (r == col) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < 15; ++q)
+      if (q < r) v -= M[r * ld + q] * y[q];
+    y[r] = v * rinv[r];
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Minv[r * ldi + col] = y[r];
+  }
+}
+
+// acc += sA * (A B) for 16 x 16 blocks: A(m, q) = Aop[m * lda + q] (or its
+// transpose when ta), B(q, n) = Bop[q * ldb + n] (or Bop[n * ldb + q] when tb).
+__device__ __forceinline__ double4_t mm16(double4_t acc, const double* Aop, int lda, bool ta, const double* Bop,
+                                          int ldb, bool tb, double sA) {
+  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int q = 4 * s + kq;
+    const double a = ta ? Aop[q * lda + mrow] : Aop[mrow * lda + q];
+    const double b = tb ? Bop[mrow * ldb + q] : Bop[q * ldb + mrow];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sA * a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+__device__ __forceinline__ double4_t load16(const double* M, int ld) {
+  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  double4_t v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) v[r] = M[(kq + 4 * r) * ld + mrow];
+  return v;
+}
+
+__device__ __forceinline__ void store16(double* M, int ld, double4_t v) {
+  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) M[(kq + 4 * r) * ld + mrow] = v[r];
+}
+
+// One wave: the 32 x 32 SPD tile T (LDS, stride LD) -> Li = L^-1 (LDS, stride
+// LD), via L11 = chol(A11), L21 = A21 L11^-T, L22 = chol(A22 - L21 L21^T),
+// L^-1 = [[L11^-1, 0], [-L22^-1 L21 L11^-1, L22^-1]].  T is overwritten.
+// Returns the first bad pivot (0..31) or -1.  U: 16 x 17 LDS scratch.
+__device__ __forceinline__ int factor_invert32(double* T, double* Li, double* U, double* rinv) {
+  int bad = leaf16_factor(T, LD, rinv);
+  leaf16_inverse(T, LD, rinv, Li, LD);                                   // I11
+  double4_t z = double4_t{0.0, 0.0, 0.0, 0.0};
+  // L21 = A21 I11^T
+  double4_t l21 = mm16(z, T + 16 * LD, LD, false, Li, LD, true, 1.0);
+  store16(T + 16 * LD, LD, l21);
+  // A22 -= L21 L21^T
+  double4_t a22 = load16(T + 16 * LD + 16, LD);
+  a22 = mm16(a22, T + 16 * LD, LD, false, T + 16 * LD, LD, true, -1.0);
+  store16(T + 16 * LD + 16, LD, a22);
+  const int bad2 = leaf16_factor(T + 16 * LD + 16, LD, rinv + 16);
+  if (bad < 0 && bad2 >= 0) bad = 16 + bad2;
+  leaf16_inverse(T + 16 * LD + 16, LD, rinv + 16, Li + 16 * LD + 16, LD);  // I22
+  // P = L21 I11 (into U), X = -I22 P
+  double4_t p = mm16(z, T + 16 * LD, LD, false, Li, LD, false, 1.0);
+  store16(U, 17, p);
+  double4_t xx = mm16(z, Li + 16 * LD + 16, LD, false, U, 17, false, -1.0);
+  store16(Li + 16 * LD, LD, xx);
+  const int lane = threadIdx.x & 63;
+  // upper-right block of L^-1 is zero
+  for (int e = lane; e < 256; e += 64) Li[(e >> 4) * LD + 16 + (e & 15)] = 0.0;
+  return bad;
+}
+
+// acc(2x2 blocks of 16x16) += sA * X Y^T over K = 32, X, Y 32 x 32 row-major
+// with strides ldx, ldy (global or LDS)
+__device__ __forceinline__ void mm32_abt(double4_t (&acc)[2][2], const double* X, size_t ldx, const double* Y,
+                                         size_t ldy, double sA) {
+  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  double a[2][8], b[2][8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      a[h][s] = sA * X[(16 * h + mrow) * ldx + 4 * s + kq];
+      b[h][s] = Y[(16 * h + mrow) * ldy + 4 * s + kq];
+    }
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+        acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm][s], b[bn][s], acc[bm][bn], 0, 0, 0);
+}
+
+__device__ __forceinline__ void load_tile32(double4_t (&acc)[2][2], const double* M, size_t ld) {
+  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[bm][bn][r] = M[(16 * bm + kq + 4 * r) * ld + 16 * bn + mrow];
+}
+
+__device__ __forceinline__ void store_tile32(const double4_t (&acc)[2][2], double* M, size_t ld) {
+  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) M[(16 * bm + kq + 4 * r) * ld + 16 * bn + mrow] = acc[bm][bn][r];
+}
+
+// Whole factorisation and solve of one small window per 512-thread workgroup.
+constexpr int kSmallThreads = 512;
+__global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double* __restrict__ Aall,
+                                                     double* __restrict__ Linvall, double* __restrict__ xall,
+                                                     DevStatus* __restrict__ stall) {
+  __shared__ double T[NB * LD];
+  __shared__ double Li[NB * LD];
+  __shared__ double U[16 * 17];
+  __shared__ double rinv[NB];
+  __shared__ double tv[kSmallMaxNpad];
+  __shared__ double xs[kSmallMaxNpad];
+  const int w = blockIdx.x;
+  const WinDev& W = D.win[w];
+  const int npad = W.npad, nblk = W.nblk, n = W.n;
+  if (npad > kSmallMaxNpad) return;
+  const int bw = W.band;
+  double* A = Aall + W.A_off;
+  double* Lv = Linvall + W.Linv_off;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  constexpr int NW = kSmallThreads / 64;
+  for (int b = 0; b < nblk; ++b) {
+    const int hi = min(b + bw, nblk - 1);       // last block row of column b inside the band
+    // diagonal tile: factor and invert (wave 0)
+    if (wave == 0) {
+      for (int e = lane; e < NB * NB; e += 64) T[(e >> 5) * LD + (e & 31)] = A[(size_t)(NB * b + (e >> 5)) * npad + NB * b + (e & 31)];
+      const int bad = factor_invert32(T, Li, U, rinv);
+      if (bad >= 0 && lane == 0 && NB * b + bad < n) set_status(stall + w, VI_ENOTPD, NB * b + bad);
+      for (int e = lane; e < NB * NB; e += 64) Lv[(size_t)b * NB * NB + e] = Li[(e >> 5) * LD + (e & 31)];
+    }
+    __syncthreads();
+    // panel: L_ib = A_ib L_bb^-T for b < i <= hi and the right-hand-side block
+    const int npanel = hi - b + 1;
+    for (int u = wave; u < npanel; u += NW) {
+      const int i = (u == npanel - 1) ? nblk : b + 1 + u;
+      double4_t acc[2][2];
+#pragma unroll
+      for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) acc[bm][bn] = double4_t{0.0, 0.0, 0.0, 0.0};
+      double* Aib = A + (size_t)(NB * i) * npad + NB * b;
+      mm32_abt(acc, Aib, npad, Li, LD, 1.0);
+      store_tile32(acc, Aib, npad);
+    }
+    __syncthreads();
+    // trailing update inside the band: (i, j), b < j <= hi, j <= i <= hi, and
+    // the right-hand-side row (i = nblk)
+    const int m = hi - b;                         // block columns to update
+    const int nupd = m * (m + 1) / 2 + m;
+    for (int u = wave; u < nupd; u += NW) {
+      int i, j;
+      if (u >= m * (m + 1) / 2) {
+        i = nblk;
+        j = b + 1 + (u - m * (m + 1) / 2);
+      } else {
+        int jj = 0, rem = u;
+        while (rem >= m - jj) { rem -= m - jj; ++jj; }
+        j = b + 1 + jj;
+        i = j + rem;
+      }
+      double4_t acc[2][2];
+      double* Aij = A + (size_t)(NB * i) * npad + NB * j;
+      load_tile32(acc, Aij, npad);
+      mm32_abt(acc, A + (size_t)(NB * i) * npad + NB * b, npad, A + (size_t)(NB * j) * npad + NB * b, npad, -1.0);
+      store_tile32(acc, Aij, npad);
+    }
+    __syncthreads();
+  }
+  // back-substitution x = L^-T y, inside the band
+  for (int r = tid; r < npad; r += kSmallThreads) tv[r] = A[(size_t)npad * npad + r];
+  __syncthreads();
+  const int q = lane & 31, half = lane >> 5;
+  for (int b = nblk - 1; b >= 0; --b) {
+    if (tid < NB) {
+      const double* Lb = Lv + (size_t)b * NB * NB;
+      double v = 0.0;
+      for (int r = tid; r < NB; ++r) v += Lb[r * NB + tid] * tv[NB * b + r];
+      xs[NB * b + tid] = v;
+    }
+    __syncthreads();
+    const int c0 = max(0, b - bw);
+    for (int c = c0 + wave; c < b; c += NW) {
+      double v = 0.0;
+#pragma unroll
+      for (int uu = 0; uu < 16; ++uu)
+        v += A[(size_t)(NB * b + 16 * half + uu) * npad + NB * c + q] * xs[NB * b + 16 * half + uu];
+      v += __shfl_xor(v, 32);
+      if (half == 0) tv[NB * c + q] -= v;
+    }
+    __syncthreads();
+  }
+  double* x = xall + W.x_off;
+  for (int i = tid; i < npad; i += kSmallThreads) x[i] = (i < n) ? xs[i] : 0.0;
+}
+
 // x = L^-T y per window (blockIdx.x); 1024 threads.  After an aborted
 // factorisation every window is marked failed (its state is then left alone).
 __global__ void __launch_bounds__(1024) k_chol_backsolve(DevPlan D, const double* __restrict__ Aall,
@@ -233,6 +497,7 @@ __global__ void __launch_bounds__(1024) k_chol_backsolve(DevPlan D, const double
   extern __shared__ double sh[];
   const WinDev& W = D.win[blockIdx.x];
   const int n = W.n, npad = W.npad, nblk = W.nblk;
+  if (npad <= kSmallMaxNpad) return;
   if (load_flag(sync + 1) != 0) {
     if (threadIdx.x == 0) set_status(stall + blockIdx.x, VI_EDEVICE, -1);
     return;
@@ -288,11 +553,18 @@ void chol_set_attributes() {
 
 void launch_chol(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, DevStatus* st) {
   int npad_max = 0;
-  for (const WinDev& W : P.win) npad_max = std::max(npad_max, W.npad);
-  const int grid = std::min(P.n_tickets, kMaxDataflowWG);
-  hipLaunchKernelGGL(k_chol_df, dim3(grid), dim3(64), 0, s, D, P.n_tickets, w.A, w.Linv, w.flags, w.sync, st);
-  hipLaunchKernelGGL(k_chol_backsolve, dim3(P.n_win), dim3(1024), sizeof(double) * 2 * npad_max, s, D, w.A, w.Linv,
-                     w.x, w.sync, st);
+  bool small = false;
+  for (const WinDev& W : P.win) {
+    npad_max = std::max(npad_max, W.npad);
+    small = small || W.npad <= kSmallMaxNpad;
+  }
+  if (small) hipLaunchKernelGGL(k_chol_small, dim3(P.n_win), dim3(kSmallThreads), 0, s, D, w.A, w.Linv, w.x, st);
+  if (P.n_tickets > 0) {
+    const int grid = std::min(P.n_tickets, kMaxDataflowWG);
+    hipLaunchKernelGGL(k_chol_df, dim3(grid), dim3(64), 0, s, D, P.n_tickets, w.A, w.Linv, w.flags, w.sync, st);
+    hipLaunchKernelGGL(k_chol_backsolve, dim3(P.n_win), dim3(1024), sizeof(double) * 2 * npad_max, s, D, w.A,
+                       w.Linv, w.x, w.sync, st);
+  }
 }
 
 }  // namespace vi

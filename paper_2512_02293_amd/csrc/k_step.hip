@@ -79,6 +79,116 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// ---------------------------------------------------------------------------
+// wave-wide reduce of 16 doubles: afterwards lane l holds the sum over the 64
+// lanes of element (l >> 2).  Halving steps keep the upper half of the
+// remaining elements in the lanes whose deciding bit is set: bit 5 and bit 4
+// through the gfx950 lane-swap instructions (which move exactly the halves
+// that the two partners need, so no selects), bit 3 and bit 2 through DPP row
+// mirrors (involutions that flip the deciding bit and only bits decided
+// later); bits 1 and 0 finish with a quad-permute butterfly.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double swap_sum32(double a, double b) {
+  // lanes < 32: a(l) + a(l + 32);  lanes >= 32: b(l - 32) + b(l)
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(a), __double2hiint(b), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double swap_sum16(double a, double b) {
+  // even 16-lane rows: a(l) + a(l + 16);  odd rows: b(l - 16) + b(l)
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(a), __double2loint(b), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(a), __double2hiint(b), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141;
+constexpr int kDppQuadXor2 = 0x4E, kDppQuadXor1 = 0xB1;   // quad_perm [2,3,0,1], [1,0,3,2]
+
+__device__ __forceinline__ double reduce16(double (&v)[16], int lane) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = swap_sum32(v[i], v[i + 8]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = swap_sum16(v[i], v[i + 4]);
+  {
+    const bool up = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double send = up ? v[i] : v[i + 2];
+      const double keep = up ? v[i + 2] : v[i];
+      v[i] = keep + dpp_d<kDppRowMirror>(send);
+    }
+  }
+  {
+    const bool up = lane & 4;
+    const double send = up ? v[0] : v[1];
+    const double keep = up ? v[1] : v[0];
+    v[0] = keep + dpp_d<kDppRowHalfMirror>(send);
+  }
+  double r = v[0] + dpp_d<kDppQuadXor2>(v[0]);
+  return r + dpp_d<kDppQuadXor1>(r);
+}
+
+// the same reduction on 32-bit values
+__device__ __forceinline__ float swap_sum32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_int(a), __float_as_int(b), false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+__device__ __forceinline__ float swap_sum16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_int(a), __float_as_int(b), false, false);
+  return __int_as_float(r[0]) + __int_as_float(r[1]);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float reduce16(float (&v)[16], int lane) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) v[i] = swap_sum32(v[i], v[i + 8]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = swap_sum16(v[i], v[i + 4]);
+  {
+    const bool up = lane & 8;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const float send = up ? v[i] : v[i + 2];
+      const float keep = up ? v[i + 2] : v[i];
+      v[i] = keep + dpp_f<kDppRowMirror>(send);
+    }
+  }
+  {
+    const bool up = lane & 4;
+    const float send = up ? v[0] : v[1];
+    const float keep = up ? v[1] : v[0];
+    v[0] = keep + dpp_f<kDppRowHalfMirror>(send);
+  }
+  float r = v[0] + dpp_f<kDppQuadXor2>(v[0]);
+  return r + dpp_f<kDppQuadXor1>(r);
+}
+
+// Running sum of per-block partial sums.  FP64: plain.  FP32: Kahan-
+// compensated (s holds the sum, c the running compensation), so the error
+// does not grow with the number of blocks.
+template <typename R>
+struct BlockSum {
+  R s = (R)0, c = (R)0;
+  __device__ __forceinline__ void add(R v) {
+    if constexpr (sizeof(R) == 8) {
+      s += v;
+    } else {
+      const R y = v - c;
+      const R t = s + y;
+      c = (t - s) - y;
+      s = t;
+    }
+  }
+  __device__ __forceinline__ double value() const { return (double)s - (double)c; }
+};
+
 // relative transform of edge (i -> j) of one window: R_ji = R_j^T R_i,
 // t_ji = R_j^T (p_i - p_j); i, j are indices into the window's pose array
 __device__ __forceinline__ void edge_rel(const double* __restrict__ pose, int i, int j, double* o) {
@@ -98,41 +208,58 @@ __device__ __forceinline__ void edge_rel(const double* __restrict__ pose, int i,
 // depth Jacobian (Jdx, Jdy) and the weights; everything zero when the pair is
 // not valid (inverse depth <= 0, or depth in camera j <= z_min).
 // ---------------------------------------------------------------------------
-struct PixEdge {
-  double Jx[6], Jy[6], Jdx, Jdy, rx, ry, wx, wy;
+template <typename R>
+struct PixEdgeT {
+  R Jx[6], Jy[6], Jdx, Jdy, rx, ry, wx, wy;
   bool valid;
 };
+typedef PixEdgeT<double> PixEdge;
 
-__device__ __forceinline__ void pix_edge(const WinDev& W, const OptsDev& o, const double* Rt, double qx, double qy,
-                                         double d, bool inpx, const float* __restrict__ target,
+template <typename R>
+__device__ __forceinline__ R recip(R v);
+template <>
+__device__ __forceinline__ double recip<double>(double v) { return 1.0 / v; }
+template <>
+__device__ __forceinline__ float recip<float>(float v) { return __builtin_amdgcn_rcpf(v); }   // 1 ulp
+
+// R = double: the FP64 path; R = float: the mixed-precision path (the
+// relative transform is rounded to float once per edge, everything per pixel
+// is float).
+template <typename R>
+__device__ __forceinline__ void pix_edge(const WinDev& W, const OptsDev& o, const double* Rtd, R qx, R qy, R d,
+                                         bool inpx, const float* __restrict__ target,
                                          const float* __restrict__ weight, size_t toff, bool want_res,
-                                         PixEdge& q) {
-  const double Px = Rt[0] * qx + Rt[1] * qy + Rt[2] + Rt[9] * d;
-  const double Py = Rt[3] * qx + Rt[4] * qy + Rt[5] + Rt[10] * d;
-  const double Pz = Rt[6] * qx + Rt[7] * qy + Rt[8] + Rt[11] * d;
-  q.valid = inpx && d > 0.0 && Pz > o.z_min * d;
-  q.wx = q.valid ? (double)weight[toff] : 0.0;
-  q.wy = q.valid ? (double)weight[toff + W.HW] : 0.0;
-  q.rx = 0.0;
-  q.ry = 0.0;
+                                         PixEdgeT<R>& q) {
+  R Rt[12];
+#pragma unroll
+  for (int c = 0; c < 12; ++c) Rt[c] = (R)Rtd[c];
+  const R fx = (R)W.fx, fy = (R)W.fy, cx = (R)W.cx, cy = (R)W.cy;
+  const R Px = Rt[0] * qx + Rt[1] * qy + Rt[2] + Rt[9] * d;
+  const R Py = Rt[3] * qx + Rt[4] * qy + Rt[5] + Rt[10] * d;
+  const R Pz = Rt[6] * qx + Rt[7] * qy + Rt[8] + Rt[11] * d;
+  q.valid = inpx && d > (R)0 && Pz > (R)o.z_min * d;
+  q.wx = q.valid ? (R)weight[toff] : (R)0;
+  q.wy = q.valid ? (R)weight[toff + W.HW] : (R)0;
+  q.rx = (R)0;
+  q.ry = (R)0;
   if (q.valid) {
-    const double iz = 1.0 / Pz;
-    const double xp = Px * iz, yp = Py * iz, dz = d * iz;
+    const R iz = recip<R>(Pz);
+    const R xp = Px * iz, yp = Py * iz, dz = d * iz;
     if (want_res) {
-      q.rx = (double)target[toff] - (W.fx * xp + W.cx);
-      q.ry = (double)target[toff + W.HW] - (W.fy * yp + W.cy);
+      q.rx = (R)target[toff] - (fx * xp + cx);
+      q.ry = (R)target[toff + W.HW] - (fy * yp + cy);
     }
-    q.Jx[0] = W.fx * xp * yp;  q.Jx[1] = -W.fx * (1.0 + xp * xp); q.Jx[2] = W.fx * yp;
-    q.Jx[3] = -W.fx * dz;      q.Jx[4] = 0.0;                     q.Jx[5] = W.fx * xp * dz;
-    q.Jy[0] = W.fy * (1.0 + yp * yp); q.Jy[1] = -W.fy * xp * yp;  q.Jy[2] = -W.fy * xp;
-    q.Jy[3] = 0.0;             q.Jy[4] = -W.fy * dz;              q.Jy[5] = W.fy * yp * dz;
-    q.Jdx = -W.fx * iz * (Rt[9] - xp * Rt[11]);
-    q.Jdy = -W.fy * iz * (Rt[10] - yp * Rt[11]);
+    q.Jx[0] = fx * xp * yp;  q.Jx[1] = -fx * ((R)1 + xp * xp); q.Jx[2] = fx * yp;
+    q.Jx[3] = -fx * dz;      q.Jx[4] = (R)0;                   q.Jx[5] = fx * xp * dz;
+    q.Jy[0] = fy * ((R)1 + yp * yp); q.Jy[1] = -fy * xp * yp;  q.Jy[2] = -fy * xp;
+    q.Jy[3] = (R)0;          q.Jy[4] = -fy * dz;               q.Jy[5] = fy * yp * dz;
+    q.Jdx = -fx * iz * (Rt[9] - xp * Rt[11]);
+    q.Jdy = -fy * iz * (Rt[10] - yp * Rt[11]);
   } else {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) { q.Jx[c] = 0.0; q.Jy[c] = 0.0; }
-    q.Jdx = 0.0;
-    q.Jdy = 0.0;
+    for (int c = 0; c < 6; ++c) { q.Jx[c] = (R)0; q.Jy[c] = (R)0; }
+    q.Jdx = (R)0;
+    q.Jdy = (R)0;
   }
 }
 
@@ -231,19 +358,19 @@ __device__ void imu_factor_block(int f, const WinDev& W, const double* __restric
   double* r = Lm + 225;
   const int l = threadIdx.x;
   const int lf = f - W.f_base;
-  for (int e = l; e < 450; e += 256) J[e] = 0.0;
-  for (int e = l; e < 225; e += 256) Lm[e] = Lam[(size_t)f * 225 + e];
+  for (int e = l; e < 450; e += (int)blockDim.x) J[e] = 0.0;
+  for (int e = l; e < 225; e += (int)blockDim.x) Lm[e] = Lam[(size_t)f * 225 + e];
   __syncthreads();
   if (l == 0) imu_residual_jacobian(W.pose, W.vel, W.bias, W.imu + lf, W.g, lf, r, J);
   __syncthreads();
-  for (int e = l; e < 450; e += 256) {
+  for (int e = l; e < 450; e += (int)blockDim.x) {
     const int a = e / 15, b = e % 15;
     double v = 0.0;
     for (int m = 0; m < 15; ++m) v += J[m * 30 + a] * Lm[m * 15 + b];
     T[a * 15 + b] = v;
   }
   __syncthreads();
-  for (int e = l; e < 900; e += 256) {
+  for (int e = l; e < 900; e += (int)blockDim.x) {
     const int a = e / 30, c = e % 30;
     double v = 0.0;
     for (int m = 0; m < 15; ++m) v += T[a * 15 + m] * J[m * 30 + c];
@@ -266,13 +393,13 @@ __device__ void imu_factor_block(int f, const WinDev& W, const double* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Fused vision assembly and Schur Gram.  One workgroup per (source keyframe,
-// pixel range), walked in chunks of 64 pixels; lane = pixel, wave w takes the
-// source's edges w, w+4, ...  Per (pixel, edge): residual and Jacobians; per
-// pixel: C and w_d; per edge: the local 6x6 Hessian (21) and gradient (6),
-// reduced over the wave (reduce_scatter32) into lane registers; the 6 local
-// E-entries of every (pixel, edge) go to an LDS tile [64 px][6k | w_d], on
-// which the four waves then run the Gram
+// Fused vision assembly and Schur Gram.  One 512-thread workgroup per (source
+// keyframe, pixel range), walked in chunks of 64 pixels; lane = pixel, wave w
+// takes the source's edges w, w+8, w+16.  Per (pixel, edge): residual and
+// Jacobians; per pixel: C and w_d; per edge: the local 6x6 Hessian (21) and
+// gradient (6), reduced over the wave in two 16-value passes (reduce16) into
+// lane registers; the 6 local E-entries of every (pixel, edge) go to an LDS
+// tile [64 px][6k | w_d], on which the eight waves then run the Gram
 //   Q' = sum_p [L_p; w_d,p][L_p; w_d,p]^T / C_p
 // on FP64 MFMA 16x16x4 over lower-triangular 16x16 tiles.  The E-block never
 // leaves the chip.  MFMA operand layout: lane l supplies A[l%16][l/16] and
@@ -281,8 +408,11 @@ __device__ void imu_factor_block(int f, const WinDev& W, const double* __restric
 // so that their serial rotation algebra starts first and overlaps the vision
 // workgroups).
 // ---------------------------------------------------------------------------
-constexpr int kMaxTilesPerWave = 7;     // T <= 7 for 6k+1 <= 112
-constexpr int kEdgeSlots = (kMaxOutDegree + 3) / 4;
+constexpr int kVisThreads = 512;
+constexpr int kVisWaves = kVisThreads / 64;
+constexpr int kMaxTilesPerWave = 4;     // T <= 7 for 6k+1 <= 112: 28 tiles over 8 waves
+constexpr int kEdgeSlots = (kMaxOutDegree + kVisWaves - 1) / kVisWaves;
+static_assert(kMaxTilesPerWave * kVisWaves >= 28, "Gram tiles per wave");
 
 __device__ __forceinline__ void tile_ij(int t, int& I, int& J) {
   int i = 0;
@@ -291,15 +421,22 @@ __device__ __forceinline__ void tile_ij(int t, int& I, int& J) {
   J = t - i * (i + 1) / 2;
 }
 
-__global__ void __launch_bounds__(256) k_vis_gram(OptsDev o, DevPlan D, int imu_rows, int F, int nkr_max, int ncost,
-                                                  int range, const double* __restrict__ Lam, double* __restrict__ Rw,
-                                                  double* __restrict__ rel, double* __restrict__ Cd,
-                                                  double* __restrict__ wd, double* __restrict__ hpart,
-                                                  double* __restrict__ gpart, double* __restrict__ vcost,
-                                                  double* __restrict__ Hf, double* __restrict__ gf,
-                                                  double* __restrict__ icost) {
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// R = double: FP64 MFMA 16x16x4 (output D[l/16 + 4 r][l%16]).  R = float:
+// FP32 MFMA 16x16x4 (output D[4 (l/16) + r][l%16]), each 64-pixel block
+// accumulated from zero and then Kahan-added into the running Gram.
+template <typename R>
+__global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, int imu_rows, int F, int nkr_max,
+                                                          int ncost, int range, const double* __restrict__ Lam,
+                                                          double* __restrict__ Rw, double* __restrict__ rel,
+                                                          double* __restrict__ Cd, double* __restrict__ wd,
+                                                          double* __restrict__ hpart, double* __restrict__ gpart,
+                                                          double* __restrict__ vcost, double* __restrict__ Hf,
+                                                          double* __restrict__ gf, double* __restrict__ icost) {
+  constexpr bool kF64 = sizeof(R) == 8;
   extern __shared__ double sm[];
-  __shared__ double red[2][4];
+  __shared__ double red[2][kVisWaves];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if ((int)blockIdx.y < imu_rows) {
     const int f = (int)blockIdx.y * (int)gridDim.x + (int)blockIdx.x;
@@ -323,9 +460,9 @@ __global__ void __launch_bounds__(256) k_vis_gram(OptsDev o, DevPlan D, int imu_
   const int LDW = 16 * T;
   const int ntiles = T * (T + 1) / 2;
   double* rel_s = sm;                             // [kMaxOutDegree][12]
-  double* Lt = rel_s + kMaxOutDegree * 12;        // [64][LDW]
-  double* part = Lt + 64 * LDW;                   // [2][4][64]
-  double* invcd = part + 512;                     // [64]
+  R* Lt = (R*)(rel_s + kMaxOutDegree * 12);       // [64][LDW]
+  R* part = Lt + 64 * LDW;                        // [2][kVisWaves][64]
+  R* invcd = part + 2 * kVisWaves * 64;           // [64]
   if (tid < k) {
     const int e = D.src_edges[e0 + tid];
     edge_rel(W.pose, ls, D.jj[e] - W.kf_base, rel_s + tid * 12);
@@ -333,95 +470,129 @@ __global__ void __launch_bounds__(256) k_vis_gram(OptsDev o, DevPlan D, int imu_
       for (int q = 0; q < 12; ++q) rel[(size_t)e * 12 + q] = rel_s[tid * 12 + q];
   }
   if (kr == 0 && tid == 0) {
-    double R[9];
-    quat_to_rot(W.pose + (size_t)ls * 7 + 3, R);
-    for (int q = 0; q < 9; ++q) Rw[(size_t)src * 9 + q] = R[q];
+    double Rm[9];
+    quat_to_rot(W.pose + (size_t)ls * 7 + 3, Rm);
+    for (int q = 0; q < 9; ++q) Rw[(size_t)src * 9 + q] = Rm[q];
   }
-  for (int i = tid; i < 64 * LDW; i += 256) Lt[i] = 0.0;
+  for (int i = tid; i < 64 * LDW; i += kVisThreads) Lt[i] = (R)0;
   __syncthreads();
 
   const double* dsrc = W.invdepth + (size_t)ls * HW;
   double* Cds = Cd + W.pix_base + (size_t)ls * HW;
   double* wds = wd + W.pix_base + (size_t)ls * HW;
-  double acc_e[kEdgeSlots];
-#pragma unroll
-  for (int u = 0; u < kEdgeSlots; ++u) acc_e[u] = 0.0;
-  double4_t gacc[kMaxTilesPerWave];
-  int tI[kMaxTilesPerWave], tJ[kMaxTilesPerWave];
+  BlockSum<R> acc_a[kEdgeSlots], acc_b[kEdgeSlots];
+  double4_t gacc[kMaxTilesPerWave];             // FP64 path
+  float4_t gs[kMaxTilesPerWave], gc[kMaxTilesPerWave];   // FP32 path: Kahan sum and compensation
 #pragma unroll
   for (int u = 0; u < kMaxTilesPerWave; ++u) {
     gacc[u] = double4_t{0.0, 0.0, 0.0, 0.0};
-    const int t = wave + 4 * u;
-    int I = 0, J = 0;
-    if (t < ntiles) tile_ij(t, I, J);
-    tI[u] = I;
-    tJ[u] = J;
+    gs[u] = float4_t{0.f, 0.f, 0.f, 0.f};
+    gc[u] = float4_t{0.f, 0.f, 0.f, 0.f};
   }
   double cost = 0.0, nval = 0.0;
   for (int c0 = p_beg; c0 < p_end; c0 += 64) {
     const int p = c0 + lane;
     const bool inpx = p < p_end;
     const int pc = inpx ? p : p_beg;
-    const double qx = ((double)(pc % W.W) - W.cx) / W.fx;
-    const double qy = ((double)(pc / W.W) - W.cy) / W.fy;
-    const double d = dsrc[pc];
-    double Cp = 0.0, Wp = 0.0;
+    const R qx = (R)(((double)(pc % W.W) - W.cx) / W.fx);
+    const R qy = (R)(((double)(pc / W.W) - W.cy) / W.fy);
+    const R d = (R)dsrc[pc];
+    R Cp = (R)0, Wp = (R)0, cst = (R)0;
 #pragma unroll
     for (int u = 0; u < kEdgeSlots; ++u) {
-      const int s = wave + 4 * u;
+      const int s = wave + kVisWaves * u;
       if (s < k) {
         const int e = D.src_edges[e0 + s];
-        PixEdge q;
-        pix_edge(W, o, rel_s + s * 12, qx, qy, d, inpx, W.target, W.weight,
-                 (size_t)(e - W.e_base) * 2 * HW + pc, true, q);
+        PixEdgeT<R> q;
+        pix_edge<R>(W, o, rel_s + s * 12, qx, qy, d, inpx, W.target, W.weight,
+                    (size_t)(e - W.e_base) * 2 * HW + pc, true, q);
         Cp += q.wx * q.Jdx * q.Jdx + q.wy * q.Jdy * q.Jdy;
         Wp -= q.wx * q.Jdx * q.rx + q.wy * q.Jdy * q.ry;
-        cost += q.wx * q.rx * q.rx + q.wy * q.ry * q.ry;
+        cst += q.wx * q.rx * q.rx + q.wy * q.ry * q.ry;
         nval += q.valid ? 1.0 : 0.0;
-        const double ax = q.wx * q.Jdx, ay = q.wy * q.Jdy;
+        const R ax = q.wx * q.Jdx, ay = q.wy * q.Jdy;
 #pragma unroll
         for (int c = 0; c < 6; ++c) Lt[lane * LDW + 6 * s + c] = ax * q.Jx[c] + ay * q.Jy[c];
-        double v[32];
+        // local Hessian (upper triangle, row-major: 21) and gradient (6)
+        R v[16];
         int m = 0;
-        const double bx = q.wx * q.rx, by = q.wy * q.ry;
+        const R bx = q.wx * q.rx, by = q.wy * q.ry;
 #pragma unroll
         for (int a = 0; a < 6; ++a) {
-          const double px = q.wx * q.Jx[a], py = q.wy * q.Jy[a];
+          const R px = q.wx * q.Jx[a], py = q.wy * q.Jy[a];
 #pragma unroll
-          for (int b = a; b < 6; ++b) v[m++] = px * q.Jx[b] + py * q.Jy[b];
+          for (int b = a; b < 6; ++b) {
+            const R h = px * q.Jx[b] + py * q.Jy[b];
+            if (m < 16) v[m] = h;
+            ++m;
+          }
+        }
+        acc_a[u].add(reduce16(v, lane));
+        m = 0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+          const R px = q.wx * q.Jx[a], py = q.wy * q.Jy[a];
+#pragma unroll
+          for (int b = a; b < 6; ++b) {
+            if (m >= 16) v[m - 16] = px * q.Jx[b] + py * q.Jy[b];
+            ++m;
+          }
         }
 #pragma unroll
-        for (int a = 0; a < 6; ++a) v[21 + a] = -(q.Jx[a] * bx + q.Jy[a] * by);
+        for (int a = 0; a < 6; ++a) v[5 + a] = -(q.Jx[a] * bx + q.Jy[a] * by);
 #pragma unroll
-        for (int a = 27; a < 32; ++a) v[a] = 0.0;
-        acc_e[u] += reduce_scatter32(v, lane);
+        for (int a = 11; a < 16; ++a) v[a] = (R)0;
+        acc_b[u].add(reduce16(v, lane));
       }
     }
+    cost += (double)cst;
     part[wave * 64 + lane] = Cp;
-    part[256 + wave * 64 + lane] = Wp;
+    part[kVisWaves * 64 + wave * 64 + lane] = Wp;
     __syncthreads();
     if (wave == 0) {
-      const double C = part[lane] + part[64 + lane] + part[128 + lane] + part[192 + lane] + o.eta;
-      const double Wv = part[256 + lane] + part[320 + lane] + part[384 + lane] + part[448 + lane];
+      double C = o.eta, Wv = 0.0;
+#pragma unroll
+      for (int q = 0; q < kVisWaves; ++q) {
+        C += (double)part[q * 64 + lane];
+        Wv += (double)part[kVisWaves * 64 + q * 64 + lane];
+      }
       if (inpx) {
         Cds[p] = C;
         wds[p] = Wv;
       }
-      invcd[lane] = (inpx && C > 0.0) ? 1.0 / C : 0.0;
-      Lt[lane * LDW + ncol] = inpx ? Wv : 0.0;
+      invcd[lane] = (inpx && C > 0.0) ? (R)(1.0 / C) : (R)0;
+      Lt[lane * LDW + ncol] = inpx ? (R)Wv : (R)0;
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kMaxTilesPerWave; ++u) {
-      if (wave + 4 * u < ntiles) {
-        const int ca = 16 * tI[u] + (lane & 15);
-        const int cb = 16 * tJ[u] + (lane & 15);
+      const int t = wave + kVisWaves * u;
+      if (t < ntiles) {
+        int I, J;
+        tile_ij(t, I, J);
+        const int ca = 16 * I + (lane & 15);
+        const int cb = 16 * J + (lane & 15);
+        if constexpr (kF64) {
 #pragma unroll 4
-        for (int kk = 0; kk < 16; ++kk) {
-          const int row = kk * 4 + (lane >> 4);
-          const double a = Lt[row * LDW + ca];
-          const double b = Lt[row * LDW + cb] * invcd[row];
-          gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gacc[u], 0, 0, 0);
+          for (int kk = 0; kk < 16; ++kk) {
+            const int row = kk * 4 + (lane >> 4);
+            const double a = Lt[row * LDW + ca];
+            const double b = Lt[row * LDW + cb] * invcd[row];
+            gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gacc[u], 0, 0, 0);
+          }
+        } else {
+          float4_t blk = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+          for (int kk = 0; kk < 16; ++kk) {
+            const int row = kk * 4 + (lane >> 4);
+            const float a = Lt[row * LDW + ca];
+            const float b = Lt[row * LDW + cb] * invcd[row];
+            blk = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, blk, 0, 0, 0);
+          }
+          const float4_t y = blk - gc[u];
+          const float4_t tt = gs[u] + y;
+          gc[u] = (tt - gs[u]) - y;
+          gs[u] = tt;
         }
       }
     }
@@ -430,29 +601,43 @@ __global__ void __launch_bounds__(256) k_vis_gram(OptsDev o, DevPlan D, int imu_
   double* out = gpart + D.gram_off[src] + (size_t)kr * ntiles * 256;
 #pragma unroll
   for (int u = 0; u < kMaxTilesPerWave; ++u) {
-    const int t = wave + 4 * u;
+    const int t = wave + kVisWaves * u;
     if (t < ntiles) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int m = (lane >> 4) + 4 * r, n = lane & 15;
-        out[(size_t)t * 256 + m * 16 + n] = gacc[u][r];
+        const int n = lane & 15;
+        if constexpr (kF64) {
+          const int m = (lane >> 4) + 4 * r;
+          out[(size_t)t * 256 + m * 16 + n] = gacc[u][r];
+        } else {
+          const int m = 4 * (lane >> 4) + r;
+          out[(size_t)t * 256 + m * 16 + n] = (double)gs[u][r] - (double)gc[u][r];
+        }
       }
     }
   }
+  // per-edge partials: lane l holds element l >> 2 of each 16-value half
 #pragma unroll
   for (int u = 0; u < kEdgeSlots; ++u) {
-    const int s = wave + 4 * u;
-    if (s < k && (lane & 1) == 0 && (lane >> 1) < 27)
-      hpart[((size_t)(e0 + s) * nkr_max + kr) * 32 + (lane >> 1)] = acc_e[u];
+    const int s = wave + kVisWaves * u;
+    if (s < k && (lane & 3) == 0) {
+      double* hp = hpart + ((size_t)(e0 + s) * nkr_max + kr) * 32;
+      const int el = lane >> 2;
+      hp[el] = acc_a[u].value();
+      if (el < 11) hp[16 + el] = acc_b[u].value();
+    }
   }
   cost = wave_sum(cost);
   nval = wave_sum(nval);
   if (lane == 0) { red[0][wave] = cost; red[1][wave] = nval; }
   __syncthreads();
   if (tid == 0) {
+    double c = 0.0, nv = 0.0;
+#pragma unroll
+    for (int q = 0; q < kVisWaves; ++q) { c += red[0][q]; nv += red[1][q]; }
     const size_t b = ((size_t)src * ncost + kr) * 2;
-    vcost[b] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
-    vcost[b + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    vcost[b] = c;
+    vcost[b + 1] = nv;
   }
 }
 
@@ -811,6 +996,7 @@ __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, c
 // the keyframe states of window blockIdx.y - N.  A window whose status holds
 // an error is left untouched.
 // ---------------------------------------------------------------------------
+template <typename R>
 __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPlan D, const double* __restrict__ Rw,
                                                          const double* __restrict__ rel,
                                                          const double* __restrict__ Cd,
@@ -872,19 +1058,19 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
   double ddv = 0.0;
   if (cd > 0.0 && k > 0) {
     // E^T dxi at this pixel: sum over edges of L_e,p . u_e, with L = J_loc^T W J_d
-    const double qx = ((double)(p % W.W) - W.cx) / W.fx;
-    const double qy = ((double)(p / W.W) - W.cy) / W.fy;
-    double et = 0.0;
+    const R qx = (R)(((double)(p % W.W) - W.cx) / W.fx);
+    const R qy = (R)(((double)(p / W.W) - W.cy) / W.fy);
+    R et = (R)0;
     for (int s = 0; s < k; ++s) {
       const int e = D.src_edges[e0 + s];
-      PixEdge q;
-      pix_edge(W, o, rel_s + s * 12, qx, qy, d, true, nullptr, W.weight, (size_t)(e - W.e_base) * 2 * HW + p,
-               false, q);
-      const double ax = q.wx * q.Jdx, ay = q.wy * q.Jdy;
+      PixEdgeT<R> q;
+      pix_edge<R>(W, o, rel_s + s * 12, qx, qy, (R)d, true, nullptr, W.weight,
+                  (size_t)(e - W.e_base) * 2 * HW + p, false, q);
+      const R ax = q.wx * q.Jdx, ay = q.wy * q.Jdy;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) et += (ax * q.Jx[c] + ay * q.Jy[c]) * u[s * 6 + c];
+      for (int c = 0; c < 6; ++c) et += (ax * q.Jx[c] + ay * q.Jy[c]) * (R)u[s * 6 + c];
     }
-    ddv = (wd[pi] - et) / cd;
+    ddv = (double)(((R)wd[pi] - et) / (R)cd);
   }
   *dep = fmax(d + ddv, o.d_min);
   if (W.rep_dd) W.rep_dd[pl] = ddv;
@@ -899,6 +1085,7 @@ __global__ void k_reset_status(DevStatus* st, int n) {
 // ---------------------------------------------------------------------------
 // cost at the current state (residuals only)
 // ---------------------------------------------------------------------------
+template <typename R>
 __global__ void __launch_bounds__(256) k_vis_cost(OptsDev o, DevPlan D, int ncost, double* __restrict__ vcost) {
   __shared__ double red[2][4];
   __shared__ double rel[kMaxOutDegree * 12];
@@ -915,23 +1102,26 @@ __global__ void __launch_bounds__(256) k_vis_cost(OptsDev o, DevPlan D, int ncos
   const int p = kr * kVisBlock + tid;
   const bool inpx = p < HW;
   const int pc = inpx ? p : 0;
-  const double qx = ((double)(pc % W.W) - W.cx) / W.fx;
-  const double qy = ((double)(pc / W.W) - W.cy) / W.fy;
-  const double d = W.invdepth[(size_t)ls * HW + pc];
+  const R qx = (R)(((double)(pc % W.W) - W.cx) / W.fx);
+  const R qy = (R)(((double)(pc / W.W) - W.cy) / W.fy);
+  const R d = (R)W.invdepth[(size_t)ls * HW + pc];
+  const R fx = (R)W.fx, fy = (R)W.fy, cx = (R)W.cx, cy = (R)W.cy;
   double cost = 0.0, nval = 0.0;
   for (int s = 0; s < k; ++s) {
     const int e = D.src_edges[e0 + s];
-    const double* Rt = rel + s * 12;
-    const double Px = Rt[0] * qx + Rt[1] * qy + Rt[2] + Rt[9] * d;
-    const double Py = Rt[3] * qx + Rt[4] * qy + Rt[5] + Rt[10] * d;
-    const double Pz = Rt[6] * qx + Rt[7] * qy + Rt[8] + Rt[11] * d;
-    const bool valid = inpx && d > 0.0 && Pz > o.z_min * d;
+    R Rt[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) Rt[c] = (R)rel[s * 12 + c];
+    const R Px = Rt[0] * qx + Rt[1] * qy + Rt[2] + Rt[9] * d;
+    const R Py = Rt[3] * qx + Rt[4] * qy + Rt[5] + Rt[10] * d;
+    const R Pz = Rt[6] * qx + Rt[7] * qy + Rt[8] + Rt[11] * d;
+    const bool valid = inpx && d > (R)0 && Pz > (R)o.z_min * d;
     if (valid) {
       const size_t toff = (size_t)(e - W.e_base) * 2 * HW + pc;
-      const double iz = 1.0 / Pz;
-      const double rx = W.target[toff] - (W.fx * Px * iz + W.cx);
-      const double ry = W.target[toff + HW] - (W.fy * Py * iz + W.cy);
-      cost += (double)W.weight[toff] * rx * rx + (double)W.weight[toff + HW] * ry * ry;
+      const R iz = recip<R>(Pz);
+      const R rx = (R)W.target[toff] - (fx * Px * iz + cx);
+      const R ry = (R)W.target[toff + HW] - (fy * Py * iz + cy);
+      cost += (double)((R)W.weight[toff] * rx * rx + (R)W.weight[toff + HW] * ry * ry);
       nval += 1.0;
     }
   }
@@ -976,7 +1166,7 @@ __global__ void __launch_bounds__(256) k_cost_reduce(int ncost, int range_px, De
 
 static size_t vis_lds(int kmax) {
   const size_t T = (6 * (size_t)kmax + 16) / 16;
-  const size_t vis = (size_t)kMaxOutDegree * 12 + 64 * 16 * T + 512 + 64;
+  const size_t vis = (size_t)kMaxOutDegree * 12 + 64 * 16 * T + 2 * kVisWaves * 64 + 64;
   const size_t imu = 450 + 450 + 225 + 15;
   return sizeof(double) * std::max(vis, imu);
 }
@@ -993,7 +1183,10 @@ void chol_set_attributes();
 
 void step_set_attributes(int kmax) {
   chol_set_attributes();
-  (void)hipFuncSetAttribute((const void*)k_vis_gram, hipFuncAttributeMaxDynamicSharedMemorySize, (int)vis_lds(kmax));
+  (void)hipFuncSetAttribute((const void*)k_vis_gram<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)vis_lds(kmax));
+  (void)hipFuncSetAttribute((const void*)k_vis_gram<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)vis_lds(kmax));
   (void)hipFuncSetAttribute((const void*)k_local, hipFuncAttributeMaxDynamicSharedMemorySize, (int)local_lds(kmax));
 }
 
@@ -1006,7 +1199,8 @@ static void launch_front(hipStream_t s, const Plan& P, const DevPlan& D, const W
   const int nkr_run = (P.hw_max + P.range - 1) / P.range;          // workgroups per source in x
   const int imu_rows = (F + nkr_run - 1) / nkr_run;
   const int ncost = cost_slots(P);
-  hipLaunchKernelGGL(k_vis_gram, dim3(nkr_run, N + imu_rows), dim3(256), vis_lds(P.kmax), s, o, D, imu_rows, F,
+  auto kern = (o.precision == VI_PREC_MIXED) ? k_vis_gram<float> : k_vis_gram<double>;
+  hipLaunchKernelGGL(kern, dim3(nkr_run, N + imu_rows), dim3(kVisThreads), vis_lds(P.kmax), s, o, D, imu_rows, F,
                      P.nkr_max, ncost, P.range, w.Lam, w.Rw, w.rel, w.Cd, w.wd, w.hpart, w.gpart, w.vcost, w.Hf,
                      w.gf, w.icost);
   done(kStVis);
@@ -1033,7 +1227,8 @@ void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, 
   done(kStAssemble);
   launch_chol(s, P, D, w, st);
   done(kStChol);
-  hipLaunchKernelGGL(k_backsub_retract, dim3((P.hw_max + 255) / 256, N + P.n_win), dim3(256), 0, s, o, N, D, w.Rw,
+  auto kbs = (o.precision == VI_PREC_MIXED) ? k_backsub_retract<float> : k_backsub_retract<double>;
+  hipLaunchKernelGGL(kbs, dim3((P.hw_max + 255) / 256, N + P.n_win), dim3(256), 0, s, o, N, D, w.Rw,
                      w.rel, w.Cd, w.wd, w.x, w.dd, st);
   done(kStBacksub);
 }
@@ -1041,7 +1236,8 @@ void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, 
 void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o, int slot) {
   const int N = P.N;
   const int ncost = cost_slots(P);
-  hipLaunchKernelGGL(k_vis_cost, dim3((P.hw_max + kVisBlock - 1) / kVisBlock, N), dim3(256), 0, s, o, D, ncost,
+  auto kvc = (o.precision == VI_PREC_MIXED) ? k_vis_cost<float> : k_vis_cost<double>;
+  hipLaunchKernelGGL(kvc, dim3((P.hw_max + kVisBlock - 1) / kVisBlock, N), dim3(256), 0, s, o, D, ncost,
                      w.vcost);
   if (o.use_imu && P.F > 0)
     hipLaunchKernelGGL(k_imu_cost, dim3((P.F + 63) / 64), dim3(64), 0, s, P.F, D, w.Lam, w.icost);

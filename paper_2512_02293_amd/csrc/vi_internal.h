@@ -23,6 +23,7 @@ namespace vi {
 constexpr int kMaxOutDegree = 18;     // per-source outgoing edges (Gram tile budget)
 constexpr int kVisBlock = 256;        // pixels per workgroup of the per-pixel kernels
 constexpr int kCholNB = 32;           // Cholesky tile size
+constexpr int kCholSmallMaxNpad = 512;  // systems up to this size are solved by one workgroup
 constexpr int kMaxIters = 64;         // cost trace capacity of vi_ba_solve
 constexpr int kMaxKeyframes = 640;    // per window: the back-substitution keeps 2 x 15 N doubles in LDS
 constexpr int kTraceLen = 2 * (kMaxIters + 1);
@@ -45,6 +46,7 @@ struct WinDev {
   int n, npad, nblk;                 // reduced system
   int pair_base;                     // offset of this window's pair table
   int flag_off, nflags;              // Cholesky tile flags [(nblk + 1) * nblk]
+  int band;                          // tiles (i, j) with i - j > band are zero in S and in L
   long long pix_base;                // global offset of the first keyframe's first pixel
   long long A_off, Linv_off, x_off;  // reduced system, diagonal-tile inverses, solution
   double* pose;
@@ -117,7 +119,7 @@ struct Work {
 };
 
 struct OptsDev {
-  int n_fixed, use_imu, bias_fixed;
+  int n_fixed, use_imu, bias_fixed, precision;
   double lambda, eta, z_min, d_min;
 };
 
