@@ -15,9 +15,11 @@ Modules
   normal_eq  Eq. 4: blocks B, E, C, w_xi, w_d; damping; Schur elimination
   dense      full stacked-Jacobian normal equations for tiny problems (a pin)
   solve      one step (linearise, eliminate, solve, retract) and the iteration
+  cnn        the learned warm-start network (features, forward, backward,
+             AdamW), the reference of the warm-start kernels
 
 Parity status per function is listed in each module header.  Every function
 here is pinned by a CPU test against something other than itself (closed
 forms, finite differences, a dense textbook solve, invariants).
 """
-from . import so3, preint, vision, imu, normal_eq, dense, solve  # noqa: F401
+from . import so3, preint, vision, imu, normal_eq, dense, solve, cnn  # noqa: F401
