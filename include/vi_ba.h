@@ -236,6 +236,69 @@ vi_status vi_ba_solve_batched(vi_ctx* ctx, int32_t n_windows, const vi_window* w
  * shape in the context; later calls reuse it.  Off by default (320 pixels). */
 vi_status vi_ctx_set_autotune(vi_ctx* ctx, int32_t enable);
 
+/* ---------------------------------------------------------------------------
+ * Learned warm start.  The paper's step has no learned initialisation; this
+ * is an addition: a small convolutional network proposes inverse-depth and
+ * bias corrections of a window before Gauss-Newton, and plain Gauss-Newton
+ * remains the judge (a caller keeps the corrected state only if its cost is
+ * lower than that of the plain initial state).
+ *
+ * Network (parameters: FP32 vector of vi_warm_param_count() floats, layout
+ * W1 [32][13][3][3], b1 [32], W2..W4 [32][32][3][3] with b2..b4 [32],
+ * Wd [1][32][3][3], bd [1], Wb [6][32], bb [6]): four 3x3 convolutions with 32
+ * channels and ReLU over a keyframe's 13 input planes on a grid of 4 x 4-pixel
+ * cells; a 3x3 convolution to one plane gives the per-cell inverse-depth
+ * correction dd; the mean of the last layer over the cells, times Wb plus bb,
+ * gives the keyframe's bias correction db (gyro, accel).  BF16 activations
+ * and MFMA operands, FP32 accumulation, FP32 weights and optimiser state.
+ *
+ * Images: every keyframe of the given windows, window after window; all share
+ * a canvas of hq x wq cells (hq <= 16, wq <= 24) and image k occupies its own
+ * grid dims[k] = (ceil(H/4), ceil(W/4)) in the top-left corner. */
+int32_t vi_warm_param_count(void);
+
+/* Device workspace (bytes) of vi_warm_gradients for n_img images. */
+size_t vi_warm_workspace_size(int32_t n_img, int32_t hq, int32_t wq);
+
+/* Input planes of every keyframe at the windows' current state (device
+ * feat [n_img][13][hq][wq] FP32, dims [n_img][2] int32):
+ *   0, 1  confidence-weighted mean x / y residual (Eq. 1) over the cell's
+ *         pixels and the keyframe's outgoing edges, px
+ *   2     mean confidence of those pixel-residuals
+ *   3     mean inverse depth of the cell
+ *   4-12  inertial residual (Eq. 3) of the factor (i, i+1): rotation x 100,
+ *         position x 10, velocity x 10 (zero for the last keyframe)
+ * Synchronous. */
+vi_status vi_warm_features(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,
+                           int32_t hq, int32_t wq, float* feat, int32_t* dims);
+
+/* Inference: dd [n_img][hq][wq] and db [n_img][6] (device FP32). */
+vi_status vi_warm_forward(vi_ctx* ctx, int32_t n_img, int32_t hq, int32_t wq, const int32_t* dims,
+                          const float* params, const float* feat, float* dd, float* db);
+
+/* Training loss and its gradient (grads: device [vi_warm_param_count()]):
+ *   L = sum_{img, valid cell} ((dd - label_dd) / 0.02)^2 / n_valid_cells
+ *     + sum_img sum_6 ((db - label_db) / s_b)^2 / n_img,
+ *   s_b = (0.005, 0.005, 0.005, 0.05, 0.05, 0.05);
+ * label_dd [n_img][hq][wq], label_db [n_img][6] (device FP32); *loss on the
+ * host.  Gradient partials are reduced over the images in a fixed order
+ * (deterministic).  Synchronous. */
+vi_status vi_warm_gradients(vi_ctx* ctx, int32_t n_img, int32_t hq, int32_t wq, const int32_t* dims,
+                            const float* params, const float* feat, const float* label_dd, const float* label_db,
+                            float n_valid_cells, void* workspace, size_t workspace_bytes, float* grads,
+                            float* loss);
+
+/* One AdamW step (t = 1, 2, ...; decoupled weight decay) on device params,
+ * first and second moments m, v. */
+vi_status vi_warm_adamw(vi_ctx* ctx, float* params, const float* grads, float* m, float* v, int32_t t, float lr,
+                        float beta1, float beta2, float eps, float weight_decay);
+
+/* Apply corrections in place: inverse depth d <- max(d + up(dd), opts->d_min),
+ * up = bilinear upsampling of the keyframe's cell grid (cell centres at
+ * 4 c + 1.5, clamped at the borders); bias b <- b + db. */
+vi_status vi_warm_apply(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts, int32_t hq,
+                        int32_t wq, const float* dd, const float* db);
+
 #ifdef __cplusplus
 }
 #endif

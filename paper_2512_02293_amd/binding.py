@@ -68,7 +68,8 @@ class Window(C.Structure):
 
 EXPORTS = ["vi_ctx_create", "vi_ctx_destroy", "vi_ctx_set_stream", "vi_last_error", "vi_version",
            "imu_preintegrate", "vi_workspace_size", "vi_ba_step", "vi_ba_solve", "vi_workspace_size_batched",
-           "vi_ba_solve_batched", "vi_ctx_set_autotune"]
+           "vi_ba_solve_batched", "vi_ctx_set_autotune", "vi_warm_param_count", "vi_warm_workspace_size",
+           "vi_warm_features", "vi_warm_forward", "vi_warm_gradients", "vi_warm_adamw", "vi_warm_apply"]
 
 _lib = None
 
@@ -109,6 +110,22 @@ def load(path: str = LIB_PATH):
     lib.vi_ba_solve_batched.restype = C.c_int
     lib.vi_ctx_set_autotune.argtypes = [C.c_void_p, C.c_int32]
     lib.vi_ctx_set_autotune.restype = C.c_int
+    vp, i32, f32 = C.c_void_p, C.c_int32, C.c_float
+    lib.vi_warm_param_count.argtypes = []
+    lib.vi_warm_param_count.restype = i32
+    lib.vi_warm_workspace_size.argtypes = [i32, i32, i32]
+    lib.vi_warm_workspace_size.restype = C.c_size_t
+    lib.vi_warm_features.argtypes = [vp, i32, C.POINTER(Window), C.POINTER(Opts), i32, i32, vp, vp]
+    lib.vi_warm_features.restype = C.c_int
+    lib.vi_warm_forward.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.vi_warm_forward.restype = C.c_int
+    lib.vi_warm_gradients.argtypes = [vp, i32, i32, i32, vp, vp, vp, vp, vp, f32, vp, C.c_size_t, vp,
+                                      C.POINTER(C.c_float)]
+    lib.vi_warm_gradients.restype = C.c_int
+    lib.vi_warm_adamw.argtypes = [vp, vp, vp, vp, vp, i32, f32, f32, f32, f32, f32]
+    lib.vi_warm_adamw.restype = C.c_int
+    lib.vi_warm_apply.argtypes = [vp, i32, C.POINTER(Window), C.POINTER(Opts), i32, i32, vp, vp]
+    lib.vi_warm_apply.restype = C.c_int
     _lib = lib
     return lib
 
@@ -302,6 +319,50 @@ class Context:
             out.append(d)
         self._check(rc)
         return out
+
+
+    # -- learned warm start ---------------------------------------------------
+    def warm_features(self, probs, imus, opts: Opts, hq: int, wq: int):
+        """Input planes of every keyframe of the windows: (feat [n][13][hq][wq], dims [n][2])."""
+        torch = self.torch
+        wins, _, _ = self._windows(probs, imus, False, False, 1)
+        n = sum(int(d.pose.shape[0]) for d in probs)
+        feat = torch.empty((n, 13, hq, wq), dtype=torch.float32, device=probs[0].pose.device)
+        dims = torch.empty((n, 2), dtype=torch.int32, device=probs[0].pose.device)
+        self._check(self.lib.vi_warm_features(self.h, len(probs), wins, C.byref(opts), hq, wq, _ptr(feat), _ptr(dims)))
+        return feat, dims
+
+    def warm_forward(self, params, feat, dims):
+        torch = self.torch
+        n, _, hq, wq = feat.shape
+        dd = torch.empty((n, hq, wq), dtype=torch.float32, device=feat.device)
+        db = torch.empty((n, 6), dtype=torch.float32, device=feat.device)
+        self._check(self.lib.vi_warm_forward(self.h, n, hq, wq, _ptr(dims), _ptr(params), _ptr(feat), _ptr(dd),
+                                             _ptr(db)))
+        return dd, db
+
+    def warm_gradients(self, params, feat, dims, label_dd, label_db, n_valid, workspace=None):
+        """(loss, grads) of the training loss; workspace is allocated when not given."""
+        torch = self.torch
+        n, _, hq, wq = feat.shape
+        nb = int(self.lib.vi_warm_workspace_size(n, hq, wq))
+        if workspace is None or workspace.numel() < nb:
+            workspace = torch.empty(nb, dtype=torch.uint8, device=feat.device)
+        grads = torch.empty_like(params)
+        loss = C.c_float(0.0)
+        self._check(self.lib.vi_warm_gradients(self.h, n, hq, wq, _ptr(dims), _ptr(params), _ptr(feat),
+                                               _ptr(label_dd), _ptr(label_db), float(n_valid), _ptr(workspace),
+                                               workspace.numel(), _ptr(grads), C.byref(loss)))
+        return float(loss.value), grads
+
+    def warm_adamw(self, params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4):
+        self._check(self.lib.vi_warm_adamw(self.h, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(t), float(lr),
+                                           float(beta1), float(beta2), float(eps), float(weight_decay)))
+
+    def warm_apply(self, probs, imus, opts: Opts, dd, db):
+        n, hq, wq = dd.shape
+        wins, _, _ = self._windows(probs, imus, False, False, 1)
+        self._check(self.lib.vi_warm_apply(self.h, len(probs), wins, C.byref(opts), hq, wq, _ptr(dd), _ptr(db)))
 
 
 class DeviceProblem:

@@ -632,6 +632,7 @@ vi_status vi_ctx_create(int32_t device, void* stream, vi_ctx** out) {
     vi_ctx_destroy(c);
     return VI_EDEVICE;
   }
+  wnet_set_attributes();
   DevStatus z{0, 0, 0, 0};
   if (hipMemcpy(c->status, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) {
     vi_ctx_destroy(c);
@@ -752,6 +753,163 @@ vi_status vi_ba_solve(vi_ctx* ctx, const vi_camera* cam, vi_state* state, const 
   if (!cam || !state || !edges) return fail(ctx, VI_EINVAL, "null argument");
   std::vector<WinIn> wins{WinIn{cam, state, edges, imu, report}};
   return run(ctx, wins, opts, iters, workspace, workspace_bytes);
+}
+
+// ---------------------------------------------------------------------------
+// learned warm start
+// ---------------------------------------------------------------------------
+int32_t vi_warm_param_count(void) { return kWParams; }
+
+size_t vi_warm_workspace_size(int32_t n_img, int32_t hq, int32_t wq) {
+  if (n_img < 1 || hq < 1 || wq < 1 || hq > kWHQMax || wq > kWWQMax) return 0;
+  const size_t n = n_img, cells = (size_t)hq * wq;
+  size_t b = 0;
+  b += align256(n * 5 * cells * kWC * 2);        // BF16 activations
+  b += 2 * align256(n * cells * sizeof(float));  // dd, g_dd
+  b += 2 * align256(n * 6 * sizeof(float));      // db, g_db
+  b += align256(n * sizeof(float));              // per-image loss
+  b += align256(n * kWParams * sizeof(float));   // per-image gradient partials
+  return b;
+}
+
+}  // extern "C"
+
+namespace {
+
+vi_status warm_check_canvas(vi_ctx* ctx, int32_t n_img, int32_t hq, int32_t wq) {
+  if (n_img < 1) return fail(ctx, VI_EINVAL, "need at least one image");
+  if (hq < 1 || wq < 1 || hq > kWHQMax || wq > kWWQMax)
+    return fail(ctx, VI_EINVAL, "canvas %d x %d cells outside [1, %d] x [1, %d]", hq, wq, kWHQMax, kWWQMax);
+  return VI_OK;
+}
+
+// order the private stream after the caller's pending work
+vi_status warm_begin(vi_ctx* ctx) {
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->priv, ctx->ev_in, 0));
+  return VI_OK;
+}
+
+vi_status warm_end(vi_ctx* ctx) {
+  HIPCHK(ctx, hipGetLastError());
+  HIPCHK(ctx, hipStreamSynchronize(ctx->priv));
+  ctx->err.clear();
+  return VI_OK;
+}
+
+// windows -> plan -> device window table (shared with the solver's plan cache)
+vi_status warm_windows(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* o, int32_t hq,
+                       int32_t wq, std::vector<WinIn>& wins) {
+  if (n_windows < 1 || !windows) return fail(ctx, VI_EINVAL, "need at least one window");
+  vi_status s = check_opts(ctx, o);
+  if (s != VI_OK) return s;
+  for (int w = 0; w < n_windows; ++w) {
+    wins.push_back(WinIn{&windows[w].cam, &windows[w].state, &windows[w].edges, windows[w].imu, nullptr});
+    s = check_window(ctx, w, wins.back(), o, true);
+    if (s != VI_OK) return s;
+    if ((windows[w].cam.H + 3) / 4 > hq || (windows[w].cam.W + 3) / 4 > wq)
+      return fail(ctx, VI_EINVAL, "window %d: its %d x %d cell grid does not fit the %d x %d canvas", w,
+                  (windows[w].cam.H + 3) / 4, (windows[w].cam.W + 3) / 4, hq, wq);
+  }
+  s = ensure_plan(ctx, wins);
+  if (s != VI_OK) return s;
+  return refresh_windows(ctx, wins);
+}
+
+}  // namespace
+
+extern "C" {
+
+vi_status vi_warm_features(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,
+                           int32_t hq, int32_t wq, float* feat, int32_t* dims) {
+  if (!ctx) return VI_EINVAL;
+  if (!feat || !dims) return fail(ctx, VI_EINVAL, "null output");
+  vi_status s = warm_check_canvas(ctx, 1, hq, wq);
+  if (s != VI_OK) return s;
+  std::vector<WinIn> wins;
+  s = warm_windows(ctx, n_windows, windows, opts, hq, wq, wins);
+  if (s != VI_OK) return s;
+  if ((s = warm_begin(ctx)) != VI_OK) return s;
+  OptsDev od{opts->n_fixed, opts->use_imu ? 1 : 0, opts->bias_fixed ? 1 : 0, opts->precision, opts->lm_lambda,
+             opts->depth_eta, opts->z_min, opts->d_min};
+  launch_warm_features(ctx->priv, ctx->plan, ctx->dplan, od, hq, wq, feat, dims);
+  return warm_end(ctx);
+}
+
+vi_status vi_warm_forward(vi_ctx* ctx, int32_t n_img, int32_t hq, int32_t wq, const int32_t* dims,
+                          const float* params, const float* feat, float* dd, float* db) {
+  if (!ctx) return VI_EINVAL;
+  vi_status s = warm_check_canvas(ctx, n_img, hq, wq);
+  if (s != VI_OK) return s;
+  if (!dims || !params || !feat || !dd || !db) return fail(ctx, VI_EINVAL, "null argument");
+  if ((s = warm_begin(ctx)) != VI_OK) return s;
+  launch_wnet_forward(ctx->priv, n_img, hq, wq, dims, params, feat, nullptr, dd, db);
+  return warm_end(ctx);
+}
+
+vi_status vi_warm_gradients(vi_ctx* ctx, int32_t n_img, int32_t hq, int32_t wq, const int32_t* dims,
+                            const float* params, const float* feat, const float* label_dd, const float* label_db,
+                            float n_valid_cells, void* workspace, size_t workspace_bytes, float* grads,
+                            float* loss) {
+  if (!ctx) return VI_EINVAL;
+  vi_status s = warm_check_canvas(ctx, n_img, hq, wq);
+  if (s != VI_OK) return s;
+  if (!dims || !params || !feat || !label_dd || !label_db || !grads || !loss || !workspace)
+    return fail(ctx, VI_EINVAL, "null argument");
+  if (!(n_valid_cells >= 1.0f)) return fail(ctx, VI_EINVAL, "n_valid_cells must be >= 1");
+  const size_t need = vi_warm_workspace_size(n_img, hq, wq);
+  if (workspace_bytes < need)
+    return fail(ctx, VI_ENOMEM, "warm-start workspace too small: %zu bytes given, %zu needed", workspace_bytes, need);
+  if (((uintptr_t)workspace & 255) != 0) return fail(ctx, VI_EINVAL, "workspace must be 256-byte aligned");
+  const size_t n = n_img, cells = (size_t)hq * wq;
+  char* b = (char*)workspace;
+  void* act = b;                       b += align256(n * 5 * cells * kWC * 2);
+  float* dd = (float*)b;               b += align256(n * cells * sizeof(float));
+  float* gdd = (float*)b;              b += align256(n * cells * sizeof(float));
+  float* db = (float*)b;               b += align256(n * 6 * sizeof(float));
+  float* gdb = (float*)b;              b += align256(n * 6 * sizeof(float));
+  float* lossv = (float*)b;            b += align256(n * sizeof(float));
+  float* partial = (float*)b;
+  if ((s = warm_begin(ctx)) != VI_OK) return s;
+  launch_wnet_forward(ctx->priv, n_img, hq, wq, dims, params, feat, act, dd, db);
+  launch_wnet_backward(ctx->priv, n_img, hq, wq, dims, params, act, dd, db, label_dd, label_db, n_valid_cells, gdd,
+                       gdb, lossv, partial, grads);
+  std::vector<float> hl(n);
+  HIPCHK(ctx, hipMemcpyAsync(hl.data(), lossv, n * sizeof(float), hipMemcpyDeviceToHost, ctx->priv));
+  s = warm_end(ctx);
+  if (s != VI_OK) return s;
+  double tot = 0.0;
+  for (float v : hl) tot += v;
+  *loss = (float)tot;
+  return VI_OK;
+}
+
+vi_status vi_warm_adamw(vi_ctx* ctx, float* params, const float* grads, float* m, float* v, int32_t t, float lr,
+                        float beta1, float beta2, float eps, float weight_decay) {
+  if (!ctx) return VI_EINVAL;
+  if (!params || !grads || !m || !v) return fail(ctx, VI_EINVAL, "null argument");
+  if (t < 1) return fail(ctx, VI_EINVAL, "step t must be >= 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr >= 0.0f))
+    return fail(ctx, VI_EINVAL, "bad AdamW hyper-parameters");
+  vi_status s = warm_begin(ctx);
+  if (s != VI_OK) return s;
+  launch_wnet_adamw(ctx->priv, kWParams, params, grads, m, v, t, lr, beta1, beta2, eps, weight_decay);
+  return warm_end(ctx);
+}
+
+vi_status vi_warm_apply(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts, int32_t hq,
+                        int32_t wq, const float* dd, const float* db) {
+  if (!ctx) return VI_EINVAL;
+  if (!dd || !db) return fail(ctx, VI_EINVAL, "null argument");
+  vi_status s = warm_check_canvas(ctx, 1, hq, wq);
+  if (s != VI_OK) return s;
+  std::vector<WinIn> wins;
+  s = warm_windows(ctx, n_windows, windows, opts, hq, wq, wins);
+  if (s != VI_OK) return s;
+  if ((s = warm_begin(ctx)) != VI_OK) return s;
+  launch_warm_apply(ctx->priv, ctx->plan, ctx->dplan, hq, wq, dd, db, opts->d_min);
+  return warm_end(ctx);
 }
 
 }  // extern "C"

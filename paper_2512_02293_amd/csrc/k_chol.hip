@@ -395,17 +395,72 @@ __device__ __forceinline__ void store_tile32(const double4_t (&acc)[2][2], doubl
       for (int r = 0; r < 4; ++r) M[(16 * bm + kq + 4 * r) * ld + 16 * bn + mrow] = acc[bm][bn][r];
 }
 
+// 32 x 32 tile in LDS without padding, column index XOR-swizzled by row so
+// that the MFMA operand reads (16 rows x 4 columns per instruction) and the
+// row-wise reads of the back-substitution hit distinct banks.
+__device__ __forceinline__ int swz(int r, int c) { return r * NB + (c ^ ((r * 4) & 31)); }
+
+// acc(2x2 blocks of 16x16) += sA * X Y^T over K = 32, X and Y swizzled LDS tiles
+__device__ __forceinline__ void mm32_abt_lds(double4_t (&acc)[2][2], const double* X, const double* Y, double sA) {
+  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    double a[2], b[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      a[h] = sA * X[swz(16 * h + mrow, 4 * s + kq)];
+      b[h] = Y[swz(16 * h + mrow, 4 * s + kq)];
+    }
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+        acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm], b[bn], acc[bm][bn], 0, 0, 0);
+  }
+}
+
+// global 32 x 32 tile -> padded LDS tile, all loads in flight at once (one wave)
+__device__ __forceinline__ void tile_to_lds(double* T, const double* M, size_t ld) {
+  const int lane = threadIdx.x & 63;
+  double v[16];
+#pragma unroll
+  for (int it = 0; it < 16; ++it) {
+    const int e = lane + 64 * it;
+    v[it] = M[(size_t)(e >> 5) * ld + (e & 31)];
+  }
+#pragma unroll
+  for (int it = 0; it < 16; ++it) {
+    const int e = lane + 64 * it;
+    T[(e >> 5) * LD + (e & 31)] = v[it];
+  }
+}
+
+// y_b <- L_bb^-1 y_b in place (32 entries of yv; Li padded, lower triangular); one wave
+__device__ __forceinline__ void fwd_block(const double* Li, double* yb) {
+  const int lane = threadIdx.x & 63, c = lane & 31;
+  double v = 0.0;
+#pragma unroll
+  for (int q = 0; q < NB; ++q) v += Li[c * LD + q] * yb[q];
+  if (lane < NB) yb[c] = v;
+}
+
 // Whole factorisation and solve of one small window per 512-thread workgroup.
+// Right-looking over 32-wide block columns inside the band, with the forward
+// substitution interleaved (y_b = L_bb^-1 s_b, then s_i -= L_ib y_b) and one
+// step of look-ahead: while waves 1.. apply the trailing update of column b,
+// wave 0 updates and factors the next diagonal tile.  The current panel
+// L_ib (b < i <= b + band) is kept in LDS for the trailing update.
 constexpr int kSmallThreads = 512;
+constexpr int kPanelSlots = kSmallMaxNpad / NB;     // 16: panel tiles, then the diagonal inverses
 __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double* __restrict__ Aall,
-                                                     double* __restrict__ Linvall, double* __restrict__ xall,
-                                                     DevStatus* __restrict__ stall) {
-  __shared__ double T[NB * LD];
-  __shared__ double Li[NB * LD];
+                                                              double* __restrict__ Linvall, double* __restrict__ xall,
+                                                              DevStatus* __restrict__ stall) {
+  extern __shared__ double P[];                 // [kPanelSlots][NB * NB], swizzled
+  __shared__ double T[NB * LD];                 // diagonal tile being factored; the solution in the back-solve
+  __shared__ double Li[2][NB * LD];             // L_bb^-1 of the current and the next column
   __shared__ double U[16 * 17];
   __shared__ double rinv[NB];
-  __shared__ double tv[kSmallMaxNpad];
-  __shared__ double xs[kSmallMaxNpad];
+  __shared__ double yv[kSmallMaxNpad];          // right-hand side -> y = L^-1 s -> running rhs of L^T x = y
   const int w = blockIdx.x;
   const WinDev& W = D.win[w];
   const int npad = W.npad, nblk = W.nblk, n = W.n;
@@ -415,73 +470,128 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   double* Lv = Linvall + W.Linv_off;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   constexpr int NW = kSmallThreads / 64;
+  for (int r = tid; r < npad; r += kSmallThreads) yv[r] = A[(size_t)npad * npad + r];
+  if (wave == 0) {
+    tile_to_lds(T, A, npad);
+    const int bad = factor_invert32(T, Li[0], U, rinv);
+    if (bad >= 0 && lane == 0 && bad < n) set_status(stall + w, VI_ENOTPD, bad);
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int e = lane + 64 * it;
+      Lv[e] = Li[0][(e >> 5) * LD + (e & 31)];
+    }
+  }
+  __syncthreads();
+  if (wave == 0) fwd_block(Li[0], yv);
+  __syncthreads();
   for (int b = 0; b < nblk; ++b) {
     const int hi = min(b + bw, nblk - 1);       // last block row of column b inside the band
-    // diagonal tile: factor and invert (wave 0)
-    if (wave == 0) {
-      for (int e = lane; e < NB * NB; e += 64) T[(e >> 5) * LD + (e & 31)] = A[(size_t)(NB * b + (e >> 5)) * npad + NB * b + (e & 31)];
-      const int bad = factor_invert32(T, Li, U, rinv);
-      if (bad >= 0 && lane == 0 && NB * b + bad < n) set_status(stall + w, VI_ENOTPD, NB * b + bad);
-      for (int e = lane; e < NB * NB; e += 64) Lv[(size_t)b * NB * NB + e] = Li[(e >> 5) * LD + (e & 31)];
-    }
-    __syncthreads();
-    // panel: L_ib = A_ib L_bb^-T for b < i <= hi and the right-hand-side block
-    const int npanel = hi - b + 1;
-    for (int u = wave; u < npanel; u += NW) {
-      const int i = (u == npanel - 1) ? nblk : b + 1 + u;
+    const int m = hi - b;                       // panel tiles below the diagonal
+    const double* Lc = Li[b & 1];
+    // panel: L_ib = A_ib L_bb^-T, b < i <= hi -> global (for the back-solve) and LDS
+    for (int u = wave; u < m; u += NW) {
+      const int i = b + 1 + u;
       double4_t acc[2][2];
 #pragma unroll
       for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
         for (int bn = 0; bn < 2; ++bn) acc[bm][bn] = double4_t{0.0, 0.0, 0.0, 0.0};
       double* Aib = A + (size_t)(NB * i) * npad + NB * b;
-      mm32_abt(acc, Aib, npad, Li, LD, 1.0);
+      mm32_abt(acc, Aib, npad, Lc, LD, 1.0);
       store_tile32(acc, Aib, npad);
+      double* Pu = P + u * NB * NB;
+      const int mrow = lane & 15, kq = lane >> 4;
+#pragma unroll
+      for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) Pu[swz(16 * bm + kq + 4 * r, 16 * bn + mrow)] = acc[bm][bn][r];
     }
     __syncthreads();
-    // trailing update inside the band: (i, j), b < j <= hi, j <= i <= hi, and
-    // the right-hand-side row (i = nblk)
-    const int m = hi - b;                         // block columns to update
-    const int nupd = m * (m + 1) / 2 + m;
-    for (int u = wave; u < nupd; u += NW) {
-      int i, j;
-      if (u >= m * (m + 1) / 2) {
-        i = nblk;
-        j = b + 1 + (u - m * (m + 1) / 2);
-      } else {
-        int jj = 0, rem = u;
-        while (rem >= m - jj) { rem -= m - jj; ++jj; }
-        j = b + 1 + jj;
-        i = j + rem;
+    // forward substitution: s_i -= L_ib y_b (one thread per row of the panel)
+    {
+      const int u = tid >> 5, r = tid & 31;
+      if (u < m) {
+        const double* Pu = P + u * NB * NB;
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) v += Pu[swz(r, q)] * yv[NB * b + q];
+        yv[NB * (b + 1 + u) + r] -= v;
       }
-      double4_t acc[2][2];
-      double* Aij = A + (size_t)(NB * i) * npad + NB * j;
-      load_tile32(acc, Aij, npad);
-      mm32_abt(acc, A + (size_t)(NB * i) * npad + NB * b, npad, A + (size_t)(NB * j) * npad + NB * b, npad, -1.0);
-      store_tile32(acc, Aij, npad);
+    }
+    if (m > 0) {
+      if (wave == 0) {
+        // look-ahead: the next diagonal tile (its rhs rows were updated by this
+        // wave just above), its factor, inverse and forward block
+        const int nb1 = b + 1;
+        double4_t acc[2][2];
+        load_tile32(acc, A + (size_t)(NB * nb1) * npad + NB * nb1, npad);
+        mm32_abt_lds(acc, P, P, -1.0);
+        acc_to_lds(acc, T);
+        double* Ln = Li[nb1 & 1];
+        const int bad = factor_invert32(T, Ln, U, rinv);
+        if (bad >= 0 && lane == 0 && NB * nb1 + bad < n) set_status(stall + w, VI_ENOTPD, NB * nb1 + bad);
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+          const int e = lane + 64 * it;
+          Lv[(size_t)nb1 * NB * NB + e] = Ln[(e >> 5) * LD + (e & 31)];
+        }
+        fwd_block(Ln, yv + NB * nb1);
+      } else {
+        // trailing update (i, j), b < j <= i <= hi, except (b+1, b+1)
+        const int ntri = m * (m + 1) / 2;
+        for (int u = wave; u < ntri; u += NW - 1) {
+          int jj = 0, rem = u;
+          while (rem >= m - jj) { rem -= m - jj; ++jj; }
+          const int j = b + 1 + jj, i = j + rem;
+          double4_t acc[2][2];
+          double* Aij = A + (size_t)(NB * i) * npad + NB * j;
+          load_tile32(acc, Aij, npad);
+          mm32_abt_lds(acc, P + (i - b - 1) * NB * NB, P + (j - b - 1) * NB * NB, -1.0);
+          store_tile32(acc, Aij, npad);
+        }
+      }
     }
     __syncthreads();
   }
-  // back-substitution x = L^-T y, inside the band
-  for (int r = tid; r < npad; r += kSmallThreads) tv[r] = A[(size_t)npad * npad + r];
+  // back-substitution x = L^-T y inside the band; the diagonal inverses go to LDS
+  double* xs = T;
+  for (int e = tid; e < nblk * NB * NB; e += kSmallThreads) {
+    const int bb = e >> 10, rc = e & 1023;
+    P[bb * NB * NB + swz(rc >> 5, rc & 31)] = Lv[e];
+  }
   __syncthreads();
   const int q = lane & 31, half = lane >> 5;
   for (int b = nblk - 1; b >= 0; --b) {
+    const int c0 = max(0, b - bw);
+    // prefetch this wave's first block L_bc while x_b is formed
+    const int cw = c0 + wave;
+    double pre[16];
+    if (cw < b) {
+#pragma unroll
+      for (int uu = 0; uu < 16; ++uu) pre[uu] = A[(size_t)(NB * b + 16 * half + uu) * npad + NB * cw + q];
+    }
     if (tid < NB) {
-      const double* Lb = Lv + (size_t)b * NB * NB;
+      const double* Lb = P + b * NB * NB;
       double v = 0.0;
-      for (int r = tid; r < NB; ++r) v += Lb[r * NB + tid] * tv[NB * b + r];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) v += Lb[swz(r, tid)] * yv[NB * b + r];
       xs[NB * b + tid] = v;
     }
     __syncthreads();
-    const int c0 = max(0, b - bw);
-    for (int c = c0 + wave; c < b; c += NW) {
+    for (int c = cw; c < b; c += NW) {
       double v = 0.0;
+      if (c == cw) {
 #pragma unroll
-      for (int uu = 0; uu < 16; ++uu)
-        v += A[(size_t)(NB * b + 16 * half + uu) * npad + NB * c + q] * xs[NB * b + 16 * half + uu];
+        for (int uu = 0; uu < 16; ++uu) v += pre[uu] * xs[NB * b + 16 * half + uu];
+      } else {
+#pragma unroll
+        for (int uu = 0; uu < 16; ++uu)
+          v += A[(size_t)(NB * b + 16 * half + uu) * npad + NB * c + q] * xs[NB * b + 16 * half + uu];
+      }
       v += __shfl_xor(v, 32);
-      if (half == 0) tv[NB * c + q] -= v;
+      if (half == 0) yv[NB * c + q] -= v;
     }
     __syncthreads();
   }
@@ -549,6 +659,8 @@ __global__ void __launch_bounds__(1024) k_chol_backsolve(DevPlan D, const double
 void chol_set_attributes() {
   const int lds = (int)(sizeof(double) * 2 * ((15 * kMaxKeyframes + NB - 1) / NB * NB));
   (void)hipFuncSetAttribute((const void*)k_chol_backsolve, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  (void)hipFuncSetAttribute((const void*)k_chol_small, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(double) * kPanelSlots * NB * NB));
 }
 
 void launch_chol(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, DevStatus* st) {
@@ -558,7 +670,9 @@ void launch_chol(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, 
     npad_max = std::max(npad_max, W.npad);
     small = small || W.npad <= kSmallMaxNpad;
   }
-  if (small) hipLaunchKernelGGL(k_chol_small, dim3(P.n_win), dim3(kSmallThreads), 0, s, D, w.A, w.Linv, w.x, st);
+  if (small)
+    hipLaunchKernelGGL(k_chol_small, dim3(P.n_win), dim3(kSmallThreads), sizeof(double) * kPanelSlots * NB * NB, s, D,
+                       w.A, w.Linv, w.x, st);
   if (P.n_tickets > 0) {
     const int grid = std::min(P.n_tickets, kMaxDataflowWG);
     hipLaunchKernelGGL(k_chol_df, dim3(grid), dim3(64), 0, s, D, P.n_tickets, w.A, w.Linv, w.flags, w.sync, st);

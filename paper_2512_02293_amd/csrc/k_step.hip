@@ -1162,6 +1162,104 @@ __global__ void __launch_bounds__(256) k_cost_reduce(int ncost, int range_px, De
   cost_reduce_block(D.win[w], w, ncost, range_px, vcost, icost, use_imu, trace, slot, s0);
 }
 
+// ---------------------------------------------------------------------------
+// warm-start inputs: per keyframe (as the source of its outgoing edges) and
+// 4 x 4-pixel cell of the canvas, at the current state:
+//   0: sum w_x r_x / (sum w_x + 1e-6)   1: sum w_y r_y / (sum w_y + 1e-6)
+//   2: sum (w_x + w_y) / (2 k n_cell)   3: mean inverse depth of the cell
+//   4-12: inertial residual of the factor (i, i+1) (rotation x 100,
+//         position x 10, velocity x 10), constant over the cells; zero for
+//         the last keyframe or without inertial factors
+// and dims[img] = the keyframe's own cell grid.  Zero outside it.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_warm_features(OptsDev o, DevPlan D, int HQ, int WQ, float* __restrict__ feat,
+                                                       int* __restrict__ dims) {
+  __shared__ double rel_s[kMaxOutDegree * 12];
+  __shared__ double rimu[15];
+  const int src = blockIdx.y;
+  const WinDev W = D.win[D.win_of_kf[src]];
+  const int ls = src - W.kf_base;
+  const int e0 = D.src_off[src];
+  const int k = D.src_off[src + 1] - e0;
+  const int tid = threadIdx.x;
+  const int hq0 = (W.H + 3) / 4, wq0 = (W.W + 3) / 4;
+  const int npix = HQ * WQ;
+  if (tid < k) edge_rel(W.pose, ls, D.jj[D.src_edges[e0 + tid]] - W.kf_base, rel_s + tid * 12);
+  if (blockIdx.x == 0 && tid == 0) {
+    for (int q = 0; q < 15; ++q) rimu[q] = 0.0;
+    if (o.use_imu && ls + 1 < W.N) imu_residual_jacobian(W.pose, W.vel, W.bias, W.imu + ls, W.g, ls, rimu, nullptr);
+    dims[2 * src] = hq0;
+    dims[2 * src + 1] = wq0;
+  }
+  __syncthreads();
+  float* f = feat + (size_t)src * kWCin * npix;
+  const int p = blockIdx.x * 256 + tid;
+  if (p < npix) {
+    const int cy = p / WQ, cx = p % WQ;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (cy < hq0 && cx < wq0) {
+      double sxr = 0.0, syr = 0.0, swx = 0.0, swy = 0.0, sd = 0.0;
+      int nc = 0;
+      for (int y = 4 * cy; y < min(4 * cy + 4, W.H); ++y)
+        for (int x = 4 * cx; x < min(4 * cx + 4, W.W); ++x) {
+          const int pix = y * W.W + x;
+          const double d = W.invdepth[(size_t)ls * W.HW + pix];
+          sd += d;
+          ++nc;
+          const double qx = ((double)x - W.cx) / W.fx, qy = ((double)y - W.cy) / W.fy;
+          for (int s2 = 0; s2 < k; ++s2) {
+            const int e = D.src_edges[e0 + s2];
+            PixEdge q;
+            pix_edge<double>(W, o, rel_s + s2 * 12, qx, qy, d, true, W.target, W.weight,
+                             (size_t)(e - W.e_base) * 2 * W.HW + pix, true, q);
+            sxr += q.wx * q.rx;
+            syr += q.wy * q.ry;
+            swx += q.wx;
+            swy += q.wy;
+          }
+        }
+      v[0] = sxr / (swx + 1e-6);
+      v[1] = syr / (swy + 1e-6);
+      v[2] = (swx + swy) / (2.0 * max(k, 1) * nc);
+      v[3] = sd / nc;
+    }
+    for (int c = 0; c < 4; ++c) f[(size_t)c * npix + p] = (float)v[c];
+  }
+  if (blockIdx.x == 0) {
+    for (int e = tid; e < 9 * npix; e += 256) {
+      const int c = e / npix, pp = e % npix;
+      const int cy = pp / WQ, cx = pp % WQ;
+      const double scale = c < 3 ? 100.0 : 10.0;
+      f[(size_t)(4 + c) * npix + pp] = (cy < hq0 && cx < wq0) ? (float)(rimu[c] * scale) : 0.0f;
+    }
+  }
+}
+
+// Apply the proposed corrections: d <- max(d + up4(dd), d_min) per pixel, where
+// up4 reads the keyframe's cell grid bilinearly at ((y - 1.5) / 4, (x - 1.5) / 4)
+// clamped to the grid, and b <- b + db per keyframe.
+__global__ void __launch_bounds__(256) k_warm_apply(DevPlan D, int HQ, int WQ, const float* __restrict__ dd,
+                                                    const float* __restrict__ db, double d_min) {
+  const int src = blockIdx.y;
+  const WinDev W = D.win[D.win_of_kf[src]];
+  const int ls = src - W.kf_base;
+  const int hq0 = (W.H + 3) / 4, wq0 = (W.W + 3) / 4;
+  const float* g = dd + (size_t)src * HQ * WQ;
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x < 6) W.bias[(size_t)ls * 6 + threadIdx.x] += (double)db[(size_t)src * 6 + threadIdx.x];
+  if (p >= W.HW) return;
+  const int y = p / W.W, x = p % W.W;
+  const double fy = fmin(fmax((y - 1.5) / 4.0, 0.0), hq0 - 1.0);
+  const double fx = fmin(fmax((x - 1.5) / 4.0, 0.0), wq0 - 1.0);
+  const int y0 = (int)floor(fy), x0 = (int)floor(fx);
+  const int y1 = min(y0 + 1, hq0 - 1), x1 = min(x0 + 1, wq0 - 1);
+  const double ay = fy - y0, ax = fx - x0;
+  const double v = (1 - ay) * ((1 - ax) * g[y0 * WQ + x0] + ax * g[y0 * WQ + x1]) +
+                   ay * ((1 - ax) * g[y1 * WQ + x0] + ax * g[y1 * WQ + x1]);
+  double* dep = W.invdepth + (size_t)ls * W.HW + p;
+  *dep = fmax(*dep + v, d_min);
+}
+
 }  // namespace
 
 static size_t vis_lds(int kmax) {
@@ -1243,6 +1341,16 @@ void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Wor
     hipLaunchKernelGGL(k_imu_cost, dim3((P.F + 63) / 64), dim3(64), 0, s, P.F, D, w.Lam, w.icost);
   hipLaunchKernelGGL(k_cost_reduce, dim3(P.n_win), dim3(256), 0, s, ncost, kVisBlock, D, w.vcost, w.icost,
                      o.use_imu, w.trace, slot);
+}
+
+void launch_warm_features(hipStream_t s, const Plan& P, const DevPlan& D, const OptsDev& o, int HQ, int WQ,
+                          float* feat, int* dims) {
+  hipLaunchKernelGGL(k_warm_features, dim3((HQ * WQ + 255) / 256, P.N), dim3(256), 0, s, o, D, HQ, WQ, feat, dims);
+}
+
+void launch_warm_apply(hipStream_t s, const Plan& P, const DevPlan& D, int HQ, int WQ, const float* dd,
+                       const float* db, double d_min) {
+  hipLaunchKernelGGL(k_warm_apply, dim3((P.hw_max + 255) / 256, P.N), dim3(256), 0, s, D, HQ, WQ, dd, db, d_min);
 }
 
 }  // namespace vi

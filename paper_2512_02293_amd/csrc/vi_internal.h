@@ -123,6 +123,12 @@ struct OptsDev {
   double lambda, eta, z_min, d_min;
 };
 
+// learned warm-start network (k_wnet.hip)
+constexpr int kWCin = 13, kWCinPad = 16, kWC = 32, kWLayers = 4;
+constexpr int kWParams = kWC * kWCin * 9 + kWC + 3 * (kWC * kWC * 9 + kWC) + kWC * 9 + 1 + 6 * kWC + 6;
+constexpr int kWHQMax = 16, kWWQMax = 24;       // canvas of 4x4-pixel cells (maps up to 64 x 96)
+constexpr float kWSd = 0.02f;                   // inverse-depth correction scale of the loss
+
 // partial-sum slots per source in the cost / Hessian partial arrays
 inline int cost_slots(const Plan& P) {
   return std::max(P.nkr_max, (P.hw_max + kVisBlock - 1) / kVisBlock);
@@ -147,5 +153,18 @@ void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Wor
                        int slot);
 void launch_chol(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, DevStatus* st);
 void step_set_attributes(int kmax);
+// warm start
+void wnet_set_attributes();
+void launch_wnet_forward(hipStream_t s, int n, int HQ, int WQ, const int* dims, const float* theta, const float* feat,
+                         void* act, float* dd, float* db);
+void launch_wnet_backward(hipStream_t s, int n, int HQ, int WQ, const int* dims, const float* theta, const void* act,
+                          const float* dd, const float* db, const float* lab_dd, const float* lab_db, float nv,
+                          float* g_dd, float* g_db, float* loss, float* partial, float* grads);
+void launch_wnet_adamw(hipStream_t s, int P, float* theta, const float* g, float* m, float* v, int t, float lr,
+                       float b1, float b2, float eps, float wd);
+void launch_warm_features(hipStream_t s, const Plan& P, const DevPlan& D, const OptsDev& o, int HQ, int WQ,
+                          float* feat, int* dims);
+void launch_warm_apply(hipStream_t s, const Plan& P, const DevPlan& D, int HQ, int WQ, const float* dd,
+                       const float* db, double d_min);
 
 }  // namespace vi

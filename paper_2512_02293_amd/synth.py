@@ -144,7 +144,13 @@ def config_global() -> SceneConfig:
 def config_batched_window(w: int) -> SceneConfig:
     """Window ``w`` of the 64-window batch: N ~ U{8..32}, out-degree ~ U{3..8},
     map 48x64 or 60x80, IMU gaps ~ U{5..40} samples."""
-    rng = np.random.default_rng(4000 + w)
+    return config_random_window(4000 + w)
+
+
+def config_random_window(seed: int) -> SceneConfig:
+    """A window drawn from the batched-window distribution with its own seed
+    (training windows of the warm start use seeds 100000 and up)."""
+    rng = np.random.default_rng(seed)
     n = int(rng.integers(8, 33))
     degs = [int(rng.integers(3, min(8, n - 1) + 1)) for _ in range(n)]
     if rng.random() < 0.5:

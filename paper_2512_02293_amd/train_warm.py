@@ -1,0 +1,56 @@
+"""Train the warm-start network on windows the solver itself generates and
+solves, then compare time to tolerance against plain Gauss-Newton.
+
+    python -m paper_2512_02293_amd.train_warm [--windows 20000] [--epochs 8] [--out PATH]
+
+Needs a GPU.  Prints one progress line per dataset chunk and per epoch, then a
+JSON summary line (loss history, iteration counts and times to tolerance of
+the 64-window evaluation batch, both ways).
+"""
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--windows", type=int, default=20000)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args(argv)
+
+    from . import binding, synth, warmstart
+    log = lambda m: print(m, flush=True)
+    ctx = binding.Context(0)
+    opts = binding.make_opts()
+    t0 = time.time()
+    data = warmstart.build_dataset(ctx, args.windows, opts, workers=args.workers, log=log)
+    t_data = time.time() - t0
+    log(f"dataset ready: {data[0].shape[0]} keyframe images in {t_data:.0f} s")
+    net = warmstart.WarmNet(ctx, seed=args.seed)
+    t1 = time.time()
+    hist = warmstart.train(ctx, net, data, args.epochs, batch=args.batch, lr=args.lr, log=log, seed=args.seed)
+    t_train = time.time() - t1
+    out = args.out or warmstart.PARAMS_FILE
+    net.save(out)
+    log(f"trained in {t_train:.1f} s, parameters saved to {out}")
+    evalp = [synth.make_problem(synth.config_batched_window(w), 4000 + w) for w in range(64)]
+    res = warmstart.time_to_tol(ctx, net, evalp, opts)
+    summary = dict(windows=args.windows, images=int(data[0].shape[0]), epochs=args.epochs, loss=hist,
+                   dataset_s=t_data, train_s=t_train, eval_windows=64,
+                   iters_plain_mean=float(np.mean(res["k_plain"])), iters_warm_mean=float(np.mean(res["k_warm"])),
+                   K_plain=res["K_plain"], K_warm=res["K_warm"], accepted=int(sum(res["accepted"])),
+                   ms_plain=res["ms_plain"], ms_warm=res["ms_warm"])
+    print(json.dumps(summary), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    sys.exit(main())

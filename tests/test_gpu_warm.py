@@ -1,0 +1,155 @@
+"""Learned warm-start kernels (features, BF16 network forward/backward,
+AdamW, application to the state) against the FP64 oracle (oracle/cnn.py).
+
+Tolerances:
+  * input planes: FP32 outputs of FP64 arithmetic -> 1e-5 relative (+1e-6);
+  * network forward and gradients: activations, activation gradients and MFMA
+    operands are rounded to BF16 (unit roundoff 2^-9 = 2e-3); an output sees
+    about ten such roundings in sequence (input, four layers, weights), so
+    relative 2-norm errors of ~1e-2 are expected (measured 2e-3 .. 1.4e-2,
+    and 5.6e-2 for the first layer, whose gradient carries the roundings of
+    all four backward layers); asserted: forward <= 3e-2, every parameter
+    group's gradient <= 1e-1 with cosine >= 0.995;
+  * AdamW: FP32 arithmetic -> 1e-5 relative;
+  * applying the corrections: FP32 corrections added in FP64 -> 1e-6.
+"""
+import numpy as np
+import pytest
+
+from oracle import cnn
+from oracle import solve as osolve
+from paper_2512_02293_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2512_02293_amd import binding
+    assert torch.cuda.is_available()
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _windows(ctx):
+    from paper_2512_02293_amd import binding
+    # a 48x64 and a 60x80 window: 12x16 and 15x20 cell grids on one canvas
+    probs = [synth.make_problem(synth.config_small(), 1),
+             synth.make_problem(synth.config_batched_window(3), 4003)]
+    assert (probs[0].H, probs[1].H) == (48, 60)
+    dps = [binding.DeviceProblem(p) for p in probs]
+    imus = [ctx.imu_preintegrate(d.off, d.gyro, d.accel, d.imu_dt, d.bias_hat, d.noise) for d in dps]
+    return probs, dps, imus
+
+
+def test_warm_features_match_oracle(ctx):
+    from paper_2512_02293_amd import binding
+    probs, dps, imus = _windows(ctx)
+    feat, dims = ctx.warm_features(dps, imus, binding.make_opts(), 15, 20)
+    refs, masks = [], []
+    for p in probs:
+        cam, st, gr = osolve.from_problem(p)
+        X, m = cnn.features(cam, st, gr, hq=15, wq=20)
+        refs.append(X)
+        masks.append(m)
+    ref = np.concatenate(refs)
+    got = feat.cpu().numpy().astype(np.float64)
+    err = np.abs(got - ref) / (1e-6 + 1e-5 * np.maximum(1.0, np.abs(ref)))
+    print("features max scaled error", err.max())
+    assert err.max() <= 1.0
+    d = dims.cpu().numpy()
+    for k, m in enumerate(np.concatenate(masks)):
+        assert m.sum() == d[k, 0] * d[k, 1] and m[: d[k, 0], : d[k, 1]].all()
+
+
+def _batch(seed, n=6, hq=12, wq=16):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, cnn.C_IN, hq, wq)) * np.array([2, 2, 0.3, 0.5] + [1] * 9)[None, :, None, None]
+    x[:, 2] = np.abs(x[:, 2])
+    dims = np.array([[hq, wq] if k % 2 == 0 else [hq - 3, wq - 4] for k in range(n)], dtype=np.int32)
+    mask = np.zeros((n, hq, wq))
+    for k in range(n):
+        mask[k, : dims[k, 0], : dims[k, 1]] = 1.0
+    x *= mask[:, None]
+    dd_lab = rng.standard_normal((n, hq, wq)) * 0.02 * mask
+    db_lab = rng.standard_normal((n, 6)) * cnn.S_B
+    return x, dims, mask, dd_lab, db_lab
+
+
+def _t(a, dtype=None):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float32, device="cuda:0")
+
+
+def test_warm_forward_matches_oracle(ctx):
+    import torch
+    x, dims, mask, _, _ = _batch(11)
+    theta = cnn.init_params(4).astype(np.float32).astype(np.float64)
+    theta[-6:] = [0.001, -0.002, 0.0005, 0.01, -0.02, 0.005]
+    dd, db = ctx.warm_forward(_t(theta), _t(x), _t(dims, torch.int32))
+    rdd, rdb, _ = cnn.forward(theta, x.astype(np.float32).astype(np.float64), mask)
+    e_dd, e_db = _rel(dd.cpu().numpy(), rdd), _rel(db.cpu().numpy(), rdb)
+    print(f"forward rel. error dd {e_dd:.2e} db {e_db:.2e}")
+    assert e_dd <= 3e-2 and e_db <= 3e-2
+    assert np.all(dd.cpu().numpy()[mask == 0] == 0.0)
+
+
+def test_warm_gradients_match_oracle(ctx):
+    import torch
+    x, dims, mask, dd_lab, db_lab = _batch(12)
+    theta = cnn.init_params(6).astype(np.float32).astype(np.float64)
+    xs = x.astype(np.float32).astype(np.float64)
+    loss, g = ctx.warm_gradients(_t(theta), _t(x), _t(dims, torch.int32), _t(dd_lab), _t(db_lab), float(mask.sum()))
+    rL, rg = cnn.backward(theta, xs, mask, dd_lab.astype(np.float32).astype(np.float64),
+                          db_lab.astype(np.float32).astype(np.float64))
+    g = g.cpu().numpy().astype(np.float64)
+    print(f"loss {loss:.6g} oracle {rL:.6g}")
+    assert loss == pytest.approx(rL, rel=3e-2)
+    o = 0
+    for name, shp in cnn.SHAPES:
+        n = int(np.prod(shp))
+        a, b = g[o:o + n], rg[o:o + n]
+        cos = float(a @ b / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30))
+        print(f"  grad {name:3s}: rel {_rel(a, b):.2e} cos {cos:.5f}")
+        assert _rel(a, b) <= 1e-1 and cos >= 0.995, name
+        o += n
+
+
+def test_warm_adamw_matches_oracle(ctx):
+    rng = np.random.default_rng(3)
+    P = cnn.n_params()
+    th = rng.standard_normal(P).astype(np.float32)
+    g = rng.standard_normal(P).astype(np.float32)
+    m = (rng.standard_normal(P) * 0.1).astype(np.float32)
+    v = (rng.random(P) * 0.01).astype(np.float32)
+    tt, tg, tm, tv = _t(th), _t(g), _t(m), _t(v)
+    ctx.warm_adamw(tt, tg, tm, tv, 7, 1e-3, weight_decay=1e-2)
+    rth, rm, rv = cnn.adamw_step(th.astype(np.float64), g.astype(np.float64), m.astype(np.float64),
+                                 v.astype(np.float64), 7, 1e-3, wd=1e-2)
+    assert _rel(tt.cpu().numpy(), rth) <= 1e-5
+    assert _rel(tm.cpu().numpy(), rm) <= 1e-5 and _rel(tv.cpu().numpy(), rv) <= 1e-5
+
+
+def test_warm_apply_matches_oracle(ctx):
+    import torch
+    from paper_2512_02293_amd import binding
+    probs, dps, imus = _windows(ctx)
+    n = sum(p.n_kf for p in probs)
+    rng = np.random.default_rng(5)
+    dd = (rng.standard_normal((n, 15, 20)) * 0.05).astype(np.float32)
+    db = (rng.standard_normal((n, 6)) * 0.01).astype(np.float32)
+    ctx.warm_apply(dps, imus, binding.make_opts(), _t(dd), _t(db))
+    k = 0
+    for p, d in zip(probs, dps):
+        hq, wq = (p.H + 3) // 4, (p.W + 3) // 4
+        for i in range(p.n_kf):
+            ref = np.maximum(p.invdepth[i] + cnn.upsample4(dd[k, :hq, :wq].astype(np.float64), p.H, p.W), 1e-3)
+            assert np.abs(d.invdepth[i].cpu().numpy() - ref).max() <= 1e-6
+            assert np.abs(d.bias[i].cpu().numpy() - (p.bias[i] + db[k])).max() <= 1e-7
+            k += 1
