@@ -224,12 +224,12 @@ __device__ __forceinline__ float recip<float>(float v) { return __builtin_amdgcn
 
 // R = double: the FP64 path; R = float: the mixed-precision path (the
 // relative transform is rounded to float once per edge, everything per pixel
-// is float).
+// is float).  tgx, tgy, wgx, wgy: the pair's target and weights, loaded by the
+// caller (so that loads can be issued ahead of the arithmetic).
 template <typename R>
-__device__ __forceinline__ void pix_edge(const WinDev& W, const OptsDev& o, const double* Rtd, R qx, R qy, R d,
-                                         bool inpx, const float* __restrict__ target,
-                                         const float* __restrict__ weight, size_t toff, bool want_res,
-                                         PixEdgeT<R>& q) {
+__device__ __forceinline__ void pix_edge_v(const WinDev& W, const OptsDev& o, const double* Rtd, R qx, R qy, R d,
+                                           bool inpx, float tgx, float tgy, float wgx, float wgy, bool want_res,
+                                           PixEdgeT<R>& q) {
   R Rt[12];
 #pragma unroll
   for (int c = 0; c < 12; ++c) Rt[c] = (R)Rtd[c];
@@ -238,16 +238,16 @@ __device__ __forceinline__ void pix_edge(const WinDev& W, const OptsDev& o, cons
   const R Py = Rt[3] * qx + Rt[4] * qy + Rt[5] + Rt[10] * d;
   const R Pz = Rt[6] * qx + Rt[7] * qy + Rt[8] + Rt[11] * d;
   q.valid = inpx && d > (R)0 && Pz > (R)o.z_min * d;
-  q.wx = q.valid ? (R)weight[toff] : (R)0;
-  q.wy = q.valid ? (R)weight[toff + W.HW] : (R)0;
+  q.wx = q.valid ? (R)wgx : (R)0;
+  q.wy = q.valid ? (R)wgy : (R)0;
   q.rx = (R)0;
   q.ry = (R)0;
   if (q.valid) {
     const R iz = recip<R>(Pz);
     const R xp = Px * iz, yp = Py * iz, dz = d * iz;
     if (want_res) {
-      q.rx = (R)target[toff] - (fx * xp + cx);
-      q.ry = (R)target[toff + W.HW] - (fy * yp + cy);
+      q.rx = (R)tgx - (fx * xp + cx);
+      q.ry = (R)tgy - (fy * yp + cy);
     }
     q.Jx[0] = fx * xp * yp;  q.Jx[1] = -fx * ((R)1 + xp * xp); q.Jx[2] = fx * yp;
     q.Jx[3] = -fx * dz;      q.Jx[4] = (R)0;                   q.Jx[5] = fx * xp * dz;
@@ -261,6 +261,16 @@ __device__ __forceinline__ void pix_edge(const WinDev& W, const OptsDev& o, cons
     q.Jdx = (R)0;
     q.Jdy = (R)0;
   }
+}
+
+template <typename R>
+__device__ __forceinline__ void pix_edge(const WinDev& W, const OptsDev& o, const double* Rtd, R qx, R qy, R d,
+                                         bool inpx, const float* __restrict__ target,
+                                         const float* __restrict__ weight, size_t toff, bool want_res,
+                                         PixEdgeT<R>& q) {
+  const float tx = (want_res && target) ? target[toff] : 0.0f;
+  const float ty = (want_res && target) ? target[toff + W.HW] : 0.0f;
+  pix_edge_v<R>(W, o, Rtd, qx, qy, d, inpx, tx, ty, weight[toff], weight[toff + W.HW], want_res, q);
 }
 
 // ---------------------------------------------------------------------------
@@ -490,22 +500,49 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
     gc[u] = float4_t{0.f, 0.f, 0.f, 0.f};
   }
   double cost = 0.0, nval = 0.0;
+  // targets, weights and inverse depth of the next 64-pixel chunk are loaded
+  // one chunk ahead, so their latency overlaps the Gram of the current chunk
+  size_t eoff[kEdgeSlots];
+#pragma unroll
+  for (int u = 0; u < kEdgeSlots; ++u) {
+    const int s = wave + kVisWaves * u;
+    eoff[u] = s < k ? (size_t)(D.src_edges[e0 + s] - W.e_base) * 2 * HW : 0;
+  }
+  float ntx[kEdgeSlots], nty[kEdgeSlots], nwx[kEdgeSlots], nwy[kEdgeSlots];
+  double nd;
+  auto prefetch = [&](int c) {
+    const int pp = (c + lane < p_end) ? c + lane : p_beg;
+    nd = dsrc[pp];
+#pragma unroll
+    for (int u = 0; u < kEdgeSlots; ++u) {
+      if (wave + kVisWaves * u < k) {
+        const size_t t = eoff[u] + pp;
+        ntx[u] = W.target[t];
+        nty[u] = W.target[t + HW];
+        nwx[u] = W.weight[t];
+        nwy[u] = W.weight[t + HW];
+      }
+    }
+  };
+  prefetch(p_beg);
   for (int c0 = p_beg; c0 < p_end; c0 += 64) {
     const int p = c0 + lane;
     const bool inpx = p < p_end;
     const int pc = inpx ? p : p_beg;
     const R qx = (R)(((double)(pc % W.W) - W.cx) / W.fx);
     const R qy = (R)(((double)(pc / W.W) - W.cy) / W.fy);
-    const R d = (R)dsrc[pc];
+    const R d = (R)nd;
+    float ctx_[kEdgeSlots], cty[kEdgeSlots], cwx[kEdgeSlots], cwy[kEdgeSlots];
+#pragma unroll
+    for (int u = 0; u < kEdgeSlots; ++u) { ctx_[u] = ntx[u]; cty[u] = nty[u]; cwx[u] = nwx[u]; cwy[u] = nwy[u]; }
+    if (c0 + 64 < p_end) prefetch(c0 + 64);
     R Cp = (R)0, Wp = (R)0, cst = (R)0;
 #pragma unroll
     for (int u = 0; u < kEdgeSlots; ++u) {
       const int s = wave + kVisWaves * u;
       if (s < k) {
-        const int e = D.src_edges[e0 + s];
         PixEdgeT<R> q;
-        pix_edge<R>(W, o, rel_s + s * 12, qx, qy, d, inpx, W.target, W.weight,
-                    (size_t)(e - W.e_base) * 2 * HW + pc, true, q);
+        pix_edge_v<R>(W, o, rel_s + s * 12, qx, qy, d, inpx, ctx_[u], cty[u], cwx[u], cwy[u], true, q);
         Cp += q.wx * q.Jdx * q.Jdx + q.wy * q.Jdy * q.Jdy;
         Wp -= q.wx * q.Jdx * q.rx + q.wy * q.Jdy * q.ry;
         cst += q.wx * q.rx * q.rx + q.wy * q.ry * q.ry;
@@ -1061,14 +1098,27 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
     const R qx = (R)(((double)(p % W.W) - W.cx) / W.fx);
     const R qy = (R)(((double)(p / W.W) - W.cy) / W.fy);
     R et = (R)0;
-    for (int s = 0; s < k; ++s) {
-      const int e = D.src_edges[e0 + s];
-      PixEdgeT<R> q;
-      pix_edge<R>(W, o, rel_s + s * 12, qx, qy, (R)d, true, nullptr, W.weight,
-                  (size_t)(e - W.e_base) * 2 * HW + p, false, q);
-      const R ax = q.wx * q.Jdx, ay = q.wy * q.Jdy;
+    // edges in groups of 4 with all their weight loads issued first
+    for (int s0 = 0; s0 < k; s0 += 4) {
+      float wgx[4], wgy[4];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) et += (ax * q.Jx[c] + ay * q.Jy[c]) * (R)u[s * 6 + c];
+      for (int g = 0; g < 4; ++g) {
+        const int s = min(s0 + g, k - 1);
+        const size_t t = (size_t)(D.src_edges[e0 + s] - W.e_base) * 2 * HW + p;
+        wgx[g] = W.weight[t];
+        wgy[g] = W.weight[t + HW];
+      }
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int s = s0 + g;
+        if (s < k) {
+          PixEdgeT<R> q;
+          pix_edge_v<R>(W, o, rel_s + s * 12, qx, qy, (R)d, true, 0.0f, 0.0f, wgx[g], wgy[g], false, q);
+          const R ax = q.wx * q.Jdx, ay = q.wy * q.Jdy;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) et += (ax * q.Jx[c] + ay * q.Jy[c]) * (R)u[s * 6 + c];
+        }
+      }
     }
     ddv = (double)(((R)wd[pi] - et) / (R)cd);
   }
