@@ -324,13 +324,120 @@ __device__ __forceinline__ void store16(double* M, int ld, double4_t v) {
   for (int r = 0; r < 4; ++r) M[(kq + 4 * r) * ld + mrow] = v[r];
 }
 
+// Cholesky factor L and inverse X = L^-1 of an 8x8 SPD block, computed by
+// every lane redundantly in registers (no cross-lane traffic at all); packed
+// lower-triangular storage, entry (i, j) at i (i + 1) / 2 + j.  Returns the
+// first bad pivot or -1.
+__device__ __forceinline__ constexpr int tri8(int i, int j) { return i * (i + 1) / 2 + j; }
+
+__device__ __forceinline__ int leaf8(const double* M, int ld, double (&L)[36], double (&X)[36]) {
+  double a[36];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j <= i) a[tri8(i, j)] = M[i * ld + j];
+  int bad = -1;
+  double rv[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    double piv = a[tri8(j, j)];
+    if (!(piv > 0.0)) {
+      if (bad < 0) bad = j;
+      piv = 1.0;
+    }
+    const double r = rsqrt_refined(piv);
+    rv[j] = r;
+    L[tri8(j, j)] = piv * r;
+#pragma unroll
+    for (int i = 1; i < 8; ++i)
+      if (i > j) L[tri8(i, j)] = a[tri8(i, j)] * r;
+#pragma unroll
+    for (int i = 1; i < 8; ++i)
+#pragma unroll
+      for (int m = 1; m < 8; ++m)
+        if (i > j && m > j && m <= i) a[tri8(i, m)] -= L[tri8(i, j)] * L[tri8(m, j)];
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    X[tri8(c, c)] = rv[c];
+#pragma unroll
+    for (int r = 1; r < 8; ++r) {
+      if (r > c) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < 7; ++q)
+          if (q >= c && q < r) v += L[tri8(r, q)] * X[tri8(q, c)];
+        X[tri8(r, c)] = -v * rv[r];
+      }
+    }
+  }
+  return bad;
+}
+
+// packed lower 8x8 (all lanes hold it) -> rows/columns of a padded LDS block,
+// zeros above the diagonal; written by lane 0
+__device__ __forceinline__ void put8(const double (&P)[36], double* D, int ld) {
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) D[i * ld + j] = (j <= i) ? P[tri8(i, j)] : 0.0;
+  }
+}
+
+// One wave: inverse Cholesky factor of the 16x16 SPD block M (stride ld) into
+// Mi (stride ldi), by two register-resident 8x8 leaves:
+//   X11 = chol(A11)^-1, L21 = A21 X11^T, X22 = chol(A22 - L21 L21^T)^-1,
+//   X21 = -X22 L21 X11.
+// M's lower blocks are overwritten (L21, the updated A22).  S: 8 x 9 scratch.
+// Returns the first bad pivot (0..15) or -1.
+__device__ __forceinline__ int leaf16_factor_inverse(double* M, int ld, double* Mi, int ldi, double* S) {
+  const int lane = threadIdx.x & 63, i = lane >> 3, j = lane & 7;
+  double L[36], X[36];
+  int bad = leaf8(M, ld, L, X);
+  put8(X, Mi, ldi);                                           // X11
+  // L21 = A21 X11^T (one entry per lane)
+  {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v += M[(8 + i) * ld + q] * Mi[j * ldi + q];
+    M[(8 + i) * ld + j] = v;
+  }
+  // A22 -= L21 L21^T
+  {
+    double v = M[(8 + i) * ld + 8 + j];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v -= M[(8 + i) * ld + q] * M[(8 + j) * ld + q];
+    M[(8 + i) * ld + 8 + j] = v;
+  }
+  const int bad2 = leaf8(M + 8 * ld + 8, ld, L, X);
+  if (bad < 0 && bad2 >= 0) bad = 8 + bad2;
+  put8(X, Mi + 8 * ldi + 8, ldi);                             // X22
+  // P = L21 X11 -> S, X21 = -X22 P, X12 = 0
+  {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v += M[(8 + i) * ld + q] * Mi[q * ldi + j];
+    S[i * 9 + j] = v;
+  }
+  {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v += Mi[(8 + i) * ldi + 8 + q] * S[q * 9 + j];
+    Mi[(8 + i) * ldi + j] = -v;
+    Mi[i * ldi + 8 + j] = 0.0;
+  }
+  return bad;
+}
+
 // One wave: the 32 x 32 SPD tile T (LDS, stride LD) -> Li = L^-1 (LDS, stride
-// LD), via L11 = chol(A11), L21 = A21 L11^-T, L22 = chol(A22 - L21 L21^T),
-// L^-1 = [[L11^-1, 0], [-L22^-1 L21 L11^-1, L22^-1]].  T is overwritten.
+// LD), via X11 = chol(A11)^-1, L21 = A21 X11^T, X22 = chol(A22 - L21 L21^T)^-1,
+// L^-1 = [[X11, 0], [-X22 L21 X11, X22]].  T is overwritten.
 // Returns the first bad pivot (0..31) or -1.  U: 16 x 17 LDS scratch.
 __device__ __forceinline__ int factor_invert32(double* T, double* Li, double* U, double* rinv) {
-  int bad = leaf16_factor(T, LD, rinv);
-  leaf16_inverse(T, LD, rinv, Li, LD);                                   // I11
+  (void)rinv;
+  int bad = leaf16_factor_inverse(T, LD, Li, LD, U);                    // I11
   double4_t z = double4_t{0.0, 0.0, 0.0, 0.0};
   // L21 = A21 I11^T
   double4_t l21 = mm16(z, T + 16 * LD, LD, false, Li, LD, true, 1.0);
@@ -339,9 +446,8 @@ __device__ __forceinline__ int factor_invert32(double* T, double* Li, double* U,
   double4_t a22 = load16(T + 16 * LD + 16, LD);
   a22 = mm16(a22, T + 16 * LD, LD, false, T + 16 * LD, LD, true, -1.0);
   store16(T + 16 * LD + 16, LD, a22);
-  const int bad2 = leaf16_factor(T + 16 * LD + 16, LD, rinv + 16);
+  const int bad2 = leaf16_factor_inverse(T + 16 * LD + 16, LD, Li + 16 * LD + 16, LD, U);   // I22
   if (bad < 0 && bad2 >= 0) bad = 16 + bad2;
-  leaf16_inverse(T + 16 * LD + 16, LD, rinv + 16, Li + 16 * LD + 16, LD);  // I22
   // P = L21 I11 (into U), X = -I22 P
   double4_t p = mm16(z, T + 16 * LD, LD, false, Li, LD, false, 1.0);
   store16(U, 17, p);
