@@ -244,9 +244,9 @@ vi_status vi_ctx_set_autotune(vi_ctx* ctx, int32_t enable);
  * lower than that of the plain initial state).
  *
  * Network (parameters: FP32 vector of vi_warm_param_count() floats, layout
- * W1 [32][13][3][3], b1 [32], W2..W4 [32][32][3][3] with b2..b4 [32],
+ * W1 [32][15][3][3], b1 [32], W2..W4 [32][32][3][3] with b2..b4 [32],
  * Wd [1][32][3][3], bd [1], Wb [6][32], bb [6]): four 3x3 convolutions with 32
- * channels and ReLU over a keyframe's 13 input planes on a grid of 4 x 4-pixel
+ * channels and ReLU over a keyframe's 15 input planes on a grid of 4 x 4-pixel
  * cells; a 3x3 convolution to one plane gives the per-cell inverse-depth
  * correction dd; the mean of the last layer over the cells, times Wb plus bb,
  * gives the keyframe's bias correction db (gyro, accel).  BF16 activations
@@ -261,13 +261,17 @@ int32_t vi_warm_param_count(void);
 size_t vi_warm_workspace_size(int32_t n_img, int32_t hq, int32_t wq);
 
 /* Input planes of every keyframe at the windows' current state (device
- * feat [n_img][13][hq][wq] FP32, dims [n_img][2] int32):
+ * feat [n_img][15][hq][wq] FP32, dims [n_img][2] int32):
  *   0, 1  confidence-weighted mean x / y residual (Eq. 1) over the cell's
  *         pixels and the keyframe's outgoing edges, px
  *   2     mean confidence of those pixel-residuals
  *   3     mean inverse depth of the cell
  *   4-12  inertial residual (Eq. 3) of the factor (i, i+1): rotation x 100,
  *         position x 10, velocity x 10 (zero for the last keyframe)
+ *   13    depth-only Gauss-Newton step of the cell (poses held):
+ *         -sum(w J_d r) / (h + 1e-6) / 0.2 with J_d = dr/dd (Eq. 1) and
+ *         h = sum w J_d^2 over the cell's pixel-residuals
+ *   14    log(1 + h / n_cell)
  * Synchronous. */
 vi_status vi_warm_features(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,
                            int32_t hq, int32_t wq, float* feat, int32_t* dims);
@@ -298,6 +302,31 @@ vi_status vi_warm_adamw(vi_ctx* ctx, float* params, const float* grads, float* m
  * 4 c + 1.5, clamped at the borders); bias b <- b + db. */
 vi_status vi_warm_apply(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts, int32_t hq,
                         int32_t wq, const float* dd, const float* db);
+
+/* Device workspace (bytes) of vi_warm_start for these windows: the solver's
+ * workspace of the same batch followed by the warm start's buffers (input
+ * planes, corrections, a copy of the inverse depths and biases).  0 on
+ * invalid input. */
+size_t vi_warm_start_workspace_size(int32_t n_windows, const vi_window* windows, const vi_opts* opts);
+
+/* The whole warm start with plain Gauss-Newton as the judge, on the device in
+ * one call: the cost F (Eq. 1 and 3 terms, as reported by vi_ba_solve) at the
+ * windows' initial state; a copy of every inverse depth and bias; input
+ * planes, network (params as for vi_warm_forward) and corrections as
+ * vi_warm_features / vi_warm_forward / vi_warm_apply, on a canvas of the
+ * largest cell grid of the windows (maps up to 64 x 96 pixels); F at the
+ * corrected state; and every window whose corrected F is not below its
+ * initial F (or is not finite) put back to its initial inverse depths and
+ * biases.  Poses and velocities are never changed.  Per window:
+ * accepted[w] (host, optional) = 1 if the corrections were kept; the
+ * window's report (optional) gets cost_before = initial F, cost_after = F of
+ * the state left behind, iters_done = 0, and costs[0..1] = the initial and
+ * the corrected F (costs, when set, must hold 2 entries).  workspace: device,
+ * 256-byte aligned, at least vi_warm_start_workspace_size bytes.
+ * Synchronous.  Errors: VI_EINVAL (arguments, maps too large), VI_ENOMEM
+ * (workspace too small), VI_EDEVICE. */
+vi_status vi_warm_start(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,
+                        const float* params, void* workspace, size_t workspace_bytes, int32_t* accepted);
 
 #ifdef __cplusplus
 }

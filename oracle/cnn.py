@@ -17,8 +17,13 @@ the keyframe's outgoing edges at the current state (Eq. 1):
   ch 4-12  the inertial residual (Eq. 3) of the factor (i, i+1) at the current
          state, rotation x 100, position x 10, velocity x 10, as constant
          planes (zero for the last keyframe)
+  ch 13  -sum(w_x J_dx r_x + w_y J_dy r_y) / (h + 1e-6) / 0.2, the cell's
+         depth-only Gauss-Newton step (poses held) in units of 0.2, where
+         J_d = dr/dd is the inverse-depth column of the Jacobian of Eq. 1 and
+         h = sum(w_x J_dx^2 + w_y J_dy^2)
+  ch 14  log(1 + h / n_cell), the depth information per pixel
 Network (weights W, biases b, zero padding 1, ReLU after each of 4 layers):
-  h1 = relu(conv3x3(x, 13 -> 32)), h2..h4 = relu(conv3x3(h, 32 -> 32))
+  h1 = relu(conv3x3(x, 15 -> 32)), h2..h4 = relu(conv3x3(h, 32 -> 32))
   dd = conv3x3(h4, 32 -> 1)                      inverse-depth correction per cell
   db = Wb mean_cells(h4) + bb                    bias correction (6) of keyframe i
 Cells outside a keyframe's grid (images of different sizes share one padded
@@ -42,12 +47,13 @@ import numpy as np
 from . import imu as imu_mod
 from . import vision
 
-C_IN = 13
+C_IN = 15
 C = 32
 N_LAYERS = 4
 S_D = 0.02
 S_B = np.array([0.005] * 3 + [0.05] * 3)
 FEAT_SCALE_IMU = np.array([100.0] * 3 + [10.0] * 6)
+FEAT_SCALE_STEP = 0.2
 
 # flat parameter layout
 SHAPES = [("W1", (C, C_IN, 3, 3)), ("b1", (C,)),
@@ -123,7 +129,7 @@ def conv3x3_backward(x, W, gy):
 
 
 def forward(theta, x, mask):
-    """x (B, 13, h, w) on the padded canvas, mask (B, h, w) of valid cells.
+    """x (B, 15, h, w) on the padded canvas, mask (B, h, w) of valid cells.
     Returns dd (B, h, w), db (B, 6) and the activations for the backward pass."""
     P = unpack(theta)
     m = mask[:, None].astype(np.float64)
@@ -205,7 +211,7 @@ def upsample4(dd_cells, H, W):
 # input features of one window
 # --------------------------------------------------------------------------
 def features(cam, state, graph, z_min=0.1, hq=None, wq=None, use_imu=True):
-    """(N, 13, hq, wq) features and (N, hq, wq) validity of the cells of each
+    """(N, 15, hq, wq) features and (N, hq, wq) validity of the cells of each
     keyframe, following the channel list in the module header."""
     fx, fy, cx, cy, H, W = cam.intr
     N = state.R.shape[0]
@@ -223,16 +229,20 @@ def features(cam, state, graph, z_min=0.1, hq=None, wq=None, use_imu=True):
         syr = np.zeros(hq0 * wq0)
         swx = np.zeros(hq0 * wq0)
         swy = np.zeros(hq0 * wq0)
+        sg = np.zeros(hq0 * wq0)
+        sh = np.zeros(hq0 * wq0)
         k = 0
         for e in range(len(graph.ii)):
             if int(graph.ii[e]) != i:
                 continue
             j = int(graph.jj[e])
             k += 1
-            r, valid = vision.edge_residual(cam.intr, state.R[i], state.p[i], state.R[j], state.p[j],
-                                            state.d[i], graph.target[e], z_min)
+            r, valid, _, J_d = vision.edge_linearize(cam.intr, state.R[i], state.p[i], state.R[j], state.p[j],
+                                                     state.d[i], graph.target[e], z_min)
             w = np.asarray(graph.weight[e], np.float64).reshape(2, -1) * valid[None]
             c = cell.ravel()
+            sg += np.bincount(c, weights=w[0] * J_d[0] * r[0] + w[1] * J_d[1] * r[1], minlength=hq0 * wq0)
+            sh += np.bincount(c, weights=w[0] * J_d[0] ** 2 + w[1] * J_d[1] ** 2, minlength=hq0 * wq0)
             sxr += np.bincount(c, weights=w[0] * r[0], minlength=hq0 * wq0)
             syr += np.bincount(c, weights=w[1] * r[1], minlength=hq0 * wq0)
             swx += np.bincount(c, weights=w[0], minlength=hq0 * wq0)
@@ -242,6 +252,8 @@ def features(cam, state, graph, z_min=0.1, hq=None, wq=None, use_imu=True):
         X[i, 2, :hq0, :wq0] = ((swx + swy) / (2.0 * max(k, 1) * ncell)).reshape(hq0, wq0)
         dsum = np.bincount(cell.ravel(), weights=np.asarray(state.d[i], np.float64).ravel(), minlength=hq0 * wq0)
         X[i, 3, :hq0, :wq0] = (dsum / ncell).reshape(hq0, wq0)
+        X[i, 13, :hq0, :wq0] = (-sg / (sh + 1e-6) / FEAT_SCALE_STEP).reshape(hq0, wq0)
+        X[i, 14, :hq0, :wq0] = np.log1p(sh / ncell).reshape(hq0, wq0)
         if use_imu and i + 1 < N:
             P = graph.factors[i]
             r = imu_mod.residual(state.R[i], state.p[i], state.v[i], state.b[i],

@@ -69,7 +69,8 @@ class Window(C.Structure):
 EXPORTS = ["vi_ctx_create", "vi_ctx_destroy", "vi_ctx_set_stream", "vi_last_error", "vi_version",
            "imu_preintegrate", "vi_workspace_size", "vi_ba_step", "vi_ba_solve", "vi_workspace_size_batched",
            "vi_ba_solve_batched", "vi_ctx_set_autotune", "vi_warm_param_count", "vi_warm_workspace_size",
-           "vi_warm_features", "vi_warm_forward", "vi_warm_gradients", "vi_warm_adamw", "vi_warm_apply"]
+           "vi_warm_features", "vi_warm_forward", "vi_warm_gradients", "vi_warm_adamw", "vi_warm_apply",
+           "vi_warm_start_workspace_size", "vi_warm_start"]
 
 _lib = None
 
@@ -126,6 +127,10 @@ def load(path: str = LIB_PATH):
     lib.vi_warm_adamw.restype = C.c_int
     lib.vi_warm_apply.argtypes = [vp, i32, C.POINTER(Window), C.POINTER(Opts), i32, i32, vp, vp]
     lib.vi_warm_apply.restype = C.c_int
+    lib.vi_warm_start_workspace_size.argtypes = [i32, C.POINTER(Window), C.POINTER(Opts)]
+    lib.vi_warm_start_workspace_size.restype = C.c_size_t
+    lib.vi_warm_start.argtypes = [vp, i32, C.POINTER(Window), C.POINTER(Opts), vp, vp, C.c_size_t, vp]
+    lib.vi_warm_start.restype = C.c_int
     _lib = lib
     return lib
 
@@ -323,11 +328,11 @@ class Context:
 
     # -- learned warm start ---------------------------------------------------
     def warm_features(self, probs, imus, opts: Opts, hq: int, wq: int):
-        """Input planes of every keyframe of the windows: (feat [n][13][hq][wq], dims [n][2])."""
+        """Input planes of every keyframe of the windows: (feat [n][15][hq][wq], dims [n][2])."""
         torch = self.torch
         wins, _, _ = self._windows(probs, imus, False, False, 1)
         n = sum(int(d.pose.shape[0]) for d in probs)
-        feat = torch.empty((n, 13, hq, wq), dtype=torch.float32, device=probs[0].pose.device)
+        feat = torch.empty((n, 15, hq, wq), dtype=torch.float32, device=probs[0].pose.device)
         dims = torch.empty((n, 2), dtype=torch.int32, device=probs[0].pose.device)
         self._check(self.lib.vi_warm_features(self.h, len(probs), wins, C.byref(opts), hq, wq, _ptr(feat), _ptr(dims)))
         return feat, dims
@@ -363,6 +368,22 @@ class Context:
         n, hq, wq = dd.shape
         wins, _, _ = self._windows(probs, imus, False, False, 1)
         self._check(self.lib.vi_warm_apply(self.h, len(probs), wins, C.byref(opts), hq, wq, _ptr(dd), _ptr(db)))
+
+    def warm_start_workspace_size(self, probs, opts: Opts) -> int:
+        wins, _, _ = self._windows(probs, [None] * len(probs), False, False, 1)
+        return int(self.lib.vi_warm_start_workspace_size(len(probs), wins, C.byref(opts)))
+
+    def warm_start(self, probs, imus, opts: Opts, params, workspace):
+        """Warm start of every window with the plain cost as the judge; returns
+        per-window dicts (accepted, cost_init, cost_warm, cost_after)."""
+        _check_dev(workspace, (None,), self.torch.uint8, "workspace")
+        _check_dev(params, (int(self.lib.vi_warm_param_count()),), self.torch.float32, "params")
+        wins, reps, keep = self._windows(probs, imus, True, True, 1)
+        acc = np.zeros(len(probs), dtype=np.int32)
+        self._check(self.lib.vi_warm_start(self.h, len(probs), wins, C.byref(opts), _ptr(params), _ptr(workspace),
+                                           workspace.numel(), acc.ctypes.data_as(C.c_void_p)))
+        return [dict(accepted=bool(a), cost_init=float(c[0]), cost_warm=float(c[1]), cost_after=r.cost_after)
+                for a, (r, c, _) in zip(acc, reps)]
 
 
 class DeviceProblem:

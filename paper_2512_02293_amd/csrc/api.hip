@@ -243,7 +243,7 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
     W.Linv_off = (long long)L_off;
     W.x_off = (long long)x_off;
     W.flag_off = (int)P.flags_size;
-    W.nflags = (W.nblk + 1) * W.nblk;
+    W.nflags = (W.nblk + 2) * W.nblk;   // tile flags, then the back-substitution's x_b flags
     P.flags_size += (size_t)W.nflags;
     A_off += (size_t)(W.npad + kCholNB) * W.npad;
     L_off += (size_t)W.nblk * kCholNB * kCholNB;
@@ -289,6 +289,15 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
       }
     }
   P.n_tickets = (int)(P.chol_tiles.size() / 2);
+  // then the back-substitution's block columns, last column first
+  for (int c = P.nblk_max - 1; c >= 0; --c)
+    for (int w = 0; w < nw; ++w) {
+      const WinDev& W = P.win[w];
+      if (c >= W.nblk || W.npad <= kCholSmallMaxNpad) continue;
+      P.chol_tiles.push_back(w);
+      P.chol_tiles.push_back(c);
+    }
+  P.n_bs = (int)(P.chol_tiles.size() / 2) - P.n_tickets;
   P.A_size = A_off;
   P.Linv_size = L_off;
   P.x_size = x_off;
@@ -817,9 +826,135 @@ vi_status warm_windows(vi_ctx* ctx, int32_t n_windows, const vi_window* windows,
   return refresh_windows(ctx, wins);
 }
 
+// canvas of the warm start: the largest cell grid of the windows
+void warm_canvas(const std::vector<WinIn>& wins, int* hq, int* wq) {
+  *hq = 1;
+  *wq = 1;
+  for (const WinIn& in : wins) {
+    *hq = std::max(*hq, (in.cam->H + 3) / 4);
+    *wq = std::max(*wq, (in.cam->W + 3) / 4);
+  }
+}
+
+// the warm start's own buffers, after the solver's workspace
+struct WarmWork {
+  float* feat;
+  int32_t* dims;
+  float* dd;
+  float* db;
+  double* saved_d;
+  double* saved_b;
+};
+
+WarmWork warm_carve(const Plan& P, int hq, int wq, void* base, size_t* bytes) {
+  size_t solve = 0;
+  do_carve(P, nullptr, &solve);
+  Carve c;
+  c.base = base ? (char*)base + solve : nullptr;
+  const size_t n = P.N, cells = (size_t)hq * wq;
+  WarmWork ww{};
+  ww.feat = c.take<float>(n * kWCin * cells);
+  ww.dims = c.take<int32_t>(n * 2);
+  ww.dd = c.take<float>(n * cells);
+  ww.db = c.take<float>(n * 6);
+  ww.saved_d = c.take<double>((size_t)P.pix_total);
+  ww.saved_b = c.take<double>(n * 6);
+  if (bytes) *bytes = solve + c.off;
+  return ww;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t vi_warm_start_workspace_size(int32_t n_windows, const vi_window* windows, const vi_opts* opts) {
+  if (n_windows < 1 || !windows || !opts) return 0;
+  std::vector<WinIn> wins;
+  for (int w = 0; w < n_windows; ++w) {
+    WinIn in{&windows[w].cam, &windows[w].state, &windows[w].edges, windows[w].imu, nullptr};
+    if (check_window(nullptr, w, in, opts, false) != VI_OK) return 0;
+    wins.push_back(in);
+  }
+  Plan P;
+  if (build_plan(nullptr, wins, P) != VI_OK) return 0;
+  set_range(P, kRangeDefault);
+  int hq, wq;
+  warm_canvas(wins, &hq, &wq);
+  size_t b = 0;
+  warm_carve(P, hq, wq, nullptr, &b);
+  return b;
+}
+
+vi_status vi_warm_start(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,
+                        const float* params, void* workspace, size_t workspace_bytes, int32_t* accepted) {
+  if (!ctx) return VI_EINVAL;
+  if (n_windows < 1 || !windows) return fail(ctx, VI_EINVAL, "need at least one window");
+  if (!params || !workspace) return fail(ctx, VI_EINVAL, "null argument");
+  if (((uintptr_t)workspace & 255) != 0) return fail(ctx, VI_EINVAL, "workspace must be 256-byte aligned");
+  vi_status s = check_opts(ctx, opts);
+  if (s != VI_OK) return s;
+  std::vector<WinIn> wins;
+  for (int w = 0; w < n_windows; ++w) {
+    wins.push_back(WinIn{&windows[w].cam, &windows[w].state, &windows[w].edges, windows[w].imu, windows[w].report});
+    s = check_window(ctx, w, wins.back(), opts, true);
+    if (s != VI_OK) return s;
+  }
+  int hq, wq;
+  warm_canvas(wins, &hq, &wq);
+  if (hq > kWHQMax || wq > kWWQMax)
+    return fail(ctx, VI_EINVAL, "maps of up to %d x %d pixels only", 4 * kWHQMax, 4 * kWWQMax);
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  s = ensure_plan(ctx, wins);
+  if (s != VI_OK) return s;
+  Plan& P = ctx->plan;
+  size_t need = 0;
+  warm_carve(P, hq, wq, nullptr, &need);
+  if (workspace_bytes < need)
+    return fail(ctx, VI_ENOMEM, "workspace too small: %zu bytes given, %zu needed", workspace_bytes, need);
+  const Work w = do_carve(P, workspace, nullptr);
+  const WarmWork ww = warm_carve(P, hq, wq, workspace, nullptr);
+  s = refresh_windows(ctx, wins);
+  if (s != VI_OK) return s;
+  const DevPlan& D = ctx->dplan;
+  OptsDev od{opts->n_fixed, opts->use_imu ? 1 : 0, opts->bias_fixed ? 1 : 0, opts->precision, opts->lm_lambda,
+             opts->depth_eta, opts->z_min, opts->d_min};
+  if ((s = warm_begin(ctx)) != VI_OK) return s;
+  hipStream_t sp = ctx->priv;
+  launch_reset_status(sp, ctx->status, P.n_win);
+  if (od.use_imu) launch_imu_info(sp, P, D, w.Lam, ctx->status);
+  launch_final_cost(sp, P, D, w, od, 0);                                   // F at the initial state
+  launch_warm_state(sp, P, D, ww.saved_d, ww.saved_b, w.trace, 0);
+  launch_warm_features(sp, P, D, od, hq, wq, ww.feat, ww.dims);
+  launch_wnet_forward(sp, P.N, hq, wq, ww.dims, params, ww.feat, nullptr, ww.dd, ww.db);
+  launch_warm_apply(sp, P, D, hq, wq, ww.dd, ww.db, opts->d_min);
+  launch_final_cost(sp, P, D, w, od, 1);                                   // F at the corrected state
+  launch_warm_state(sp, P, D, ww.saved_d, ww.saved_b, w.trace, 1);        // put back where F did not fall
+  std::vector<double> trace((size_t)P.n_win * kTraceLen);
+  std::vector<DevStatus> hs(P.n_win);
+  HIPCHK(ctx, hipMemcpyAsync(trace.data(), w.trace, sizeof(double) * trace.size(), hipMemcpyDeviceToHost, sp));
+  HIPCHK(ctx, hipMemcpyAsync(hs.data(), ctx->status, sizeof(DevStatus) * P.n_win, hipMemcpyDeviceToHost, sp));
+  s = warm_end(ctx);
+  if (s != VI_OK) return s;
+  for (int wi = 0; wi < P.n_win; ++wi) {
+    const double f0 = trace[(size_t)wi * kTraceLen], f1 = trace[(size_t)wi * kTraceLen + 2];
+    const bool ok = f1 < f0;
+    if (accepted) accepted[wi] = ok ? 1 : 0;
+    vi_report* rep = wins[wi].rep;
+    if (rep) {
+      rep->cost_before = f0;
+      rep->cost_after = ok ? f1 : f0;
+      rep->n_valid = (int64_t)trace[(size_t)wi * kTraceLen + (ok ? 3 : 1)];
+      rep->iters_done = 0;
+      if (rep->costs) {
+        rep->costs[0] = f0;
+        rep->costs[1] = f1;
+      }
+    }
+  }
+  for (int wi = 0; wi < P.n_win; ++wi)
+    if (hs[wi].code != 0) return fail(ctx, (vi_status)hs[wi].code, "window %d: device status %d", wi, hs[wi].code);
+  return VI_OK;
+}
 
 vi_status vi_warm_features(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,
                            int32_t hq, int32_t wq, float* feat, int32_t* dims) {

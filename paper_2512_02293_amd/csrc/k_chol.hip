@@ -9,8 +9,11 @@
 // i = nblk being the right-hand-side block, of every window of the batch in
 // one launch.  Each tile is one wave:
 //   X = S_ij - sum_{k < j} L_ik L_jk^T        (FP64 MFMA 16x16x4, operands
-//                                              straight from global memory)
-//   i == j : factor X = L_jj L_jj^T in registers (lane = row) and invert it;
+//                                              straight from global memory,
+//                                              those of k + 1 in flight
+//                                              during the MFMAs of k; one
+//                                              acquire per run of published k)
+//   i == j : factor and invert X (register-resident 8 x 8 leaves joined by MFMA);
 //   i != j : L_ij = X L_jj^-T                 (FP64 MFMA)
 // and publishes the result with a release flag.  Tiles are handed out by an
 // atomic ticket counter in column-major order (column j, then window, then
@@ -19,9 +22,9 @@
 // how many workgroups are resident.  Every wait is also bounded: past the
 // limit the batch is aborted (VI_EDEVICE) and every workgroup exits.
 //
-// Back-substitution x = L^-T y runs per window in one 1024-thread workgroup,
-// block column by block column: x_b = L_bb^-T t_b, then t_c -= L_bc^T x_b
-// for every c < b in parallel over the waves.
+// Back-substitution x = L^-T y is a second dataflow, over block columns:
+// column c subtracts L_bc^T x_b from y_c as the x_b (b > c) are published,
+// then publishes x_c = L_cc^-T t_c.
 //
 // Windows with npad <= kSmallMaxNpad (sliding windows) are factored and
 // solved entirely inside one 512-thread workgroup instead (no inter-
@@ -49,13 +52,6 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void set_status(DevStatus* st, int code, int detail) {
   if (atomicCAS(&st->code, 0, code) == 0) st->detail = detail;
-}
-
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  int lo = __double2loint(v), hi = __double2hiint(v);
-  lo = __builtin_amdgcn_readlane(lo, l);
-  hi = __builtin_amdgcn_readlane(hi, l);
-  return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ int load_flag(const int* f) {
@@ -103,198 +99,9 @@ __device__ __forceinline__ double rsqrt_refined(double v) {
   return y;
 }
 
-__global__ void __launch_bounds__(64) k_chol_df(DevPlan D, int ntickets, double* __restrict__ Aall,
-                                                double* __restrict__ Linvall, int* __restrict__ flagsall,
-                                                int* __restrict__ sync, DevStatus* __restrict__ stall) {
-  __shared__ double T[NB * LD];
-  __shared__ double rinv[NB];
-  const int lane = threadIdx.x;
-  const int mrow = lane & 15, kq = lane >> 4;
-  while (true) {
-    int t = 0;
-    if (lane == 0) t = atomicAdd(sync, 1);
-    t = __builtin_amdgcn_readfirstlane(t);
-    if (t >= ntickets) return;
-    const int w = D.chol_tiles[2 * t];
-    const int ij = D.chol_tiles[2 * t + 1];
-    const int i = ij >> 16, j = ij & 0xffff;
-    const WinDev& W = D.win[w];
-    const int npad = W.npad, nblk = W.nblk;
-    double* A = Aall + W.A_off;
-    double* Lv = Linvall + W.Linv_off;
-    int* fl = flagsall + W.flag_off;
-    // X = S_ij in MFMA layout
-    double4_t acc[2][2];
-    const double* Sij = A + (size_t)(NB * i) * npad + NB * j;
-#pragma unroll
-    for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-      for (int bn = 0; bn < 2; ++bn)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          acc[bm][bn][r] = Sij[(size_t)(16 * bm + kq + 4 * r) * npad + 16 * bn + mrow];
-    // X -= L_ik L_jk^T: lane supplies A[m][q] = L_ik[m][q], B[q][n] = L_jk[n][q]
-    for (int k = 0; k < j; ++k) {
-      if (!wait_flag(fl + i * nblk + k, sync)) return;
-      if (i != j && !wait_flag(fl + j * nblk + k, sync)) return;
-      const double* Li = A + (size_t)(NB * i) * npad + NB * k;
-      const double* Lj = A + (size_t)(NB * j) * npad + NB * k;
-      double a[2][8], b[2][8];
-#pragma unroll
-      for (int s = 0; s < 8; ++s)
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          a[h][s] = -Li[(size_t)(16 * h + mrow) * npad + 4 * s + kq];
-          b[h][s] = Lj[(size_t)(16 * h + mrow) * npad + 4 * s + kq];
-        }
-#pragma unroll
-      for (int s = 0; s < 8; ++s)
-#pragma unroll
-        for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < 2; ++bn)
-            acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm][s], b[bn][s], acc[bm][bn], 0, 0, 0);
-    }
-    acc_to_lds(acc, T);
-    __syncthreads();
-    if (i == j) {
-      // factor: lane i (< 32) holds row i; lanes >= 32 mirror rows 0..31 and are ignored
-      const int row = lane & 31;
-      double x[NB];
-#pragma unroll
-      for (int c = 0; c < NB; ++c) x[c] = T[row * LD + c];
-      int bad = -1;
-#pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        double piv = readlane_d(x[c], c);
-        if (!(piv > 0.0)) {
-          if (bad < 0) bad = c;
-          piv = 1.0;
-        }
-        const double r = rsqrt_refined(piv);
-        if (lane == c) rinv[c] = r;
-        x[c] = (row == c) ? piv * r : (row > c ? x[c] * r : x[c]);
-#pragma unroll
-        for (int m = 1; m < NB; ++m) {
-          if (m > c) {
-            const double lm = readlane_d(x[c], m);
-            if (row >= m) x[m] -= x[c] * lm;
-          }
-        }
-      }
-      if (bad >= 0 && lane == 0 && NB * j + bad < W.n) set_status(stall + w, VI_ENOTPD, NB * j + bad);
-#pragma unroll
-      for (int c = 0; c < NB; ++c) T[row * LD + c] = (c <= row) ? x[c] : 0.0;
-      __syncthreads();
-      // inverse: lane c (< 32) computes column c of L^-1
-      double y[NB];
-#pragma unroll
-      for (int r = 0; r < NB; ++r) {
-        double v = (r == row) ? 1.0 : 0.0;
-#pragma unroll
-        for (int q = 0; q < NB - 1; ++q)
-          if (q < r) v -= T[r * LD + q] * y[q];
-        y[r] = v * rinv[r];
-      }
-      if (lane < NB) {
-        double* Lo = Lv + (size_t)j * NB * NB;
-#pragma unroll
-        for (int r = 0; r < NB; ++r) Lo[r * NB + lane] = y[r];
-      }
-      publish(fl + j * nblk + j);
-    } else {
-      if (!wait_flag(fl + j * nblk + j, sync)) return;
-      // L_ij = X L_jj^-T: A[m][q] = X[m][q], B[q][n] = Linv[n][q]
-      const double* Li = Lv + (size_t)j * NB * NB;
-      double4_t out[2][2];
-#pragma unroll
-      for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < 2; ++bn) out[bm][bn] = double4_t{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < 8; ++s) {
-        double a[2], b[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          a[h] = T[(16 * h + mrow) * LD + 4 * s + kq];
-          b[h] = Li[(16 * h + mrow) * NB + 4 * s + kq];
-        }
-#pragma unroll
-        for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < 2; ++bn)
-            out[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm], b[bn], out[bm][bn], 0, 0, 0);
-      }
-      double* Oij = A + (size_t)(NB * i) * npad + NB * j;
-#pragma unroll
-      for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < 2; ++bn)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) Oij[(size_t)(16 * bm + kq + 4 * r) * npad + 16 * bn + mrow] = out[bm][bn][r];
-      publish(fl + i * nblk + j);
-    }
-    __syncthreads();
-  }
-}
-
-
 // ---------------------------------------------------------------------------
 // one-wave helpers on 16 x 16 blocks in LDS (row-major with stride ld)
 // ---------------------------------------------------------------------------
-// In-place Cholesky of the SPD block M (lower triangle of the result is L,
-// upper set to zero); rinv[c] = 1 / L[c][c].  Returns the first bad pivot
-// index or -1.  Lane r (< 16) holds row r; other lanes mirror it.
-__device__ __forceinline__ int leaf16_factor(double* M, int ld, double* rinv) {
-  const int lane = threadIdx.x & 63, row = lane & 15;
-  double x[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) x[c] = M[row * ld + c];
-  int bad = -1;
-#pragma unroll
-  for (int c = 0; c < 16; ++c) {
-    double piv = readlane_d(x[c], c);
-    if (!(piv > 0.0)) {
-      if (bad < 0) bad = c;
-      piv = 1.0;
-    }
-    const double r = rsqrt_refined(piv);
-    if (lane == c) rinv[c] = r;
-    x[c] = (row == c) ? piv * r : (row > c ? x[c] * r : x[c]);
-#pragma unroll
-    for (int m = 1; m < 16; ++m) {
-      if (m > c) {   // constant trip count: fully unrolled, x stays in registers
-        const double lm = readlane_d(x[c], m);
-        if (row >= m) x[m] -= x[c] * lm;
-      }
-    }
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int c = 0; c < 16; ++c) M[row * ld + c] = (c <= row) ? x[c] : 0.0;
-  }
-  return bad;
-}
-
-// Minv = L^-1 for the lower-triangular 16 x 16 L in M (rinv = 1 / diag);
-// lane c (< 16) computes column c.
-__device__ __forceinline__ void leaf16_inverse(const double* M, int ld, const double* rinv, double* Minv, int ldi) {
-  const int lane = threadIdx.x & 63, col = lane & 15;
-  double y[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    double v = (r == col) ? 1.0 : 0.0;
-#pragma unroll
-    for (int q = 0; q < 15; ++q)
-      if (q < r) v -= M[r * ld + q] * y[q];
-    y[r] = v * rinv[r];
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) Minv[r * ldi + col] = y[r];
-  }
-}
-
 // acc += sA * (A B) for 16 x 16 blocks: A(m, q) = Aop[m * lda + q] (or its
 // transpose when ta), B(q, n) = Bop[q * ldb + n] (or Bop[n * ldb + q] when tb).
 __device__ __forceinline__ double4_t mm16(double4_t acc, const double* Aop, int lda, bool ta, const double* Bop,
@@ -331,17 +138,17 @@ __device__ __forceinline__ void store16(double* M, int ld, double4_t v) {
 __device__ __forceinline__ constexpr int tri8(int i, int j) { return i * (i + 1) / 2 + j; }
 
 __device__ __forceinline__ int leaf8(const double* M, int ld, double (&L)[36], double (&X)[36]) {
-  double a[36];
+  // right-looking, in place: L holds the partly reduced block until column j is final
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      if (j <= i) a[tri8(i, j)] = M[i * ld + j];
+      if (j <= i) L[tri8(i, j)] = M[i * ld + j];
   int bad = -1;
   double rv[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    double piv = a[tri8(j, j)];
+    double piv = L[tri8(j, j)];
     if (!(piv > 0.0)) {
       if (bad < 0) bad = j;
       piv = 1.0;
@@ -351,12 +158,12 @@ __device__ __forceinline__ int leaf8(const double* M, int ld, double (&L)[36], d
     L[tri8(j, j)] = piv * r;
 #pragma unroll
     for (int i = 1; i < 8; ++i)
-      if (i > j) L[tri8(i, j)] = a[tri8(i, j)] * r;
+      if (i > j) L[tri8(i, j)] *= r;
 #pragma unroll
     for (int i = 1; i < 8; ++i)
 #pragma unroll
       for (int m = 1; m < 8; ++m)
-        if (i > j && m > j && m <= i) a[tri8(i, m)] -= L[tri8(i, j)] * L[tri8(m, j)];
+        if (i > j && m > j && m <= i) L[tri8(i, m)] -= L[tri8(i, j)] * L[tri8(m, j)];
   }
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
@@ -435,8 +242,7 @@ __device__ __forceinline__ int leaf16_factor_inverse(double* M, int ld, double* 
 // LD), via X11 = chol(A11)^-1, L21 = A21 X11^T, X22 = chol(A22 - L21 L21^T)^-1,
 // L^-1 = [[X11, 0], [-X22 L21 X11, X22]].  T is overwritten.
 // Returns the first bad pivot (0..31) or -1.  U: 16 x 17 LDS scratch.
-__device__ __forceinline__ int factor_invert32(double* T, double* Li, double* U, double* rinv) {
-  (void)rinv;
+__device__ __forceinline__ int factor_invert32(double* T, double* Li, double* U) {
   int bad = leaf16_factor_inverse(T, LD, Li, LD, U);                    // I11
   double4_t z = double4_t{0.0, 0.0, 0.0, 0.0};
   // L21 = A21 I11^T
@@ -525,6 +331,53 @@ __device__ __forceinline__ void mm32_abt_lds(double4_t (&acc)[2][2], const doubl
   }
 }
 
+// acc(2x2 blocks of 16x16) += X Y^T over K = 32, X a swizzled LDS tile, Y a
+// padded (stride LD) LDS tile
+__device__ __forceinline__ void mm32_abt_swz_pad(double4_t (&acc)[2][2], const double* X, const double* Y) {
+  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    double a[2], b[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      a[h] = X[swz(16 * h + mrow, 4 * s + kq)];
+      b[h] = Y[(16 * h + mrow) * LD + 4 * s + kq];
+    }
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+        acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm], b[bn], acc[bm][bn], 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void acc_to_swz(const double4_t (&acc)[2][2], double* S) {
+  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) S[swz(16 * bm + kq + 4 * r, 16 * bn + mrow)] = acc[bm][bn][r];
+}
+
+__device__ __forceinline__ void swz_to_acc(double4_t (&acc)[2][2], const double* S) {
+  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[bm][bn][r] = S[swz(16 * bm + kq + 4 * r, 16 * bn + mrow)];
+}
+
+// global 32 x 32 tile -> swizzled LDS tile, all loads in flight at once (one wave)
+__device__ __forceinline__ void tile_to_swz(double* S, const double* M, size_t ld) {
+  double4_t acc[2][2];
+  load_tile32(acc, M, ld);
+  acc_to_swz(acc, S);
+}
+
 // global 32 x 32 tile -> padded LDS tile, all loads in flight at once (one wave)
 __device__ __forceinline__ void tile_to_lds(double* T, const double* M, size_t ld) {
   const int lane = threadIdx.x & 63;
@@ -550,14 +403,164 @@ __device__ __forceinline__ void fwd_block(const double* Li, double* yb) {
   if (lane < NB) yb[c] = v;
 }
 
+// A run of published tiles of a tile's k-loop: the number of consecutive
+// k' = k, k + 1, ... (at most 32, below kend) whose flags (i, k') and (j, k')
+// are both set, from one vector load of 64 flags (relaxed; the caller issues
+// the acquire fence once for the whole run).
+__device__ __forceinline__ int ready_run(const int* fi, const int* fj, int k, int kend) {
+  const int lane = threadIdx.x & 63, off = lane & 31;
+  const int* f = lane < 32 ? fi : fj;
+  const int v = (k + off < kend) ? load_flag(f + k + off) : 0;
+  const unsigned long long miss = __ballot(v == 0);
+  const unsigned comb = (unsigned)miss | (unsigned)(miss >> 32);
+  return comb ? __builtin_ctz(comb) : 32;
+}
+
+// Wait (whole wave) until *f is set, without a fence.  false: the batch was aborted.
+__device__ __forceinline__ bool spin_flag(const int* f, int* sync) {
+  int spins = 0;
+  while (__builtin_amdgcn_readfirstlane(load_flag(f)) == 0) {
+    if (__builtin_amdgcn_readfirstlane(load_flag(sync + 1)) != 0) return false;
+    if (++spins > kSpinLimit) {
+      if (threadIdx.x == 0) __hip_atomic_store(sync + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+
+// MFMA operands of one update X -= L_ik L_jk^T: lane supplies A[m][q] = L_ik[m][q]
+// (negated) and B[q][n] = L_jk[n][q] for its 16 rows and 4-column slices
+__device__ __forceinline__ void load_update(double (&a)[2][8], double (&b)[2][8], const double* Li, const double* Lj,
+                                            size_t ld) {
+  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      a[h][s2] = -Li[(size_t)(16 * h + mrow) * ld + 4 * s2 + kq];
+      b[h][s2] = Lj[(size_t)(16 * h + mrow) * ld + 4 * s2 + kq];
+    }
+}
+
+__device__ __forceinline__ void mfma_update(double4_t (&acc)[2][2], const double (&a)[2][8], const double (&b)[2][8]) {
+#pragma unroll
+  for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+        acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm][s2], b[bn][s2], acc[bm][bn], 0, 0, 0);
+}
+
+__global__ void __launch_bounds__(64) k_chol_df(DevPlan D, int ntickets, double* __restrict__ Aall,
+                                                double* __restrict__ Linvall, int* __restrict__ flagsall,
+                                                int* __restrict__ sync, DevStatus* __restrict__ stall) {
+  __shared__ double T[NB * LD];
+  __shared__ double Lt[NB * LD];
+  __shared__ double U[16 * 17];
+  const int lane = threadIdx.x;
+  const int mrow = lane & 15, kq = lane >> 4;
+  while (true) {
+    int t = 0;
+    if (lane == 0) t = atomicAdd(sync, 1);
+    t = __builtin_amdgcn_readfirstlane(t);
+    if (t >= ntickets) return;
+    const int w = D.chol_tiles[2 * t];
+    const int ij = D.chol_tiles[2 * t + 1];
+    const int i = ij >> 16, j = ij & 0xffff;
+    const WinDev& W = D.win[w];
+    const int npad = W.npad, nblk = W.nblk;
+    double* A = Aall + W.A_off;
+    double* Lv = Linvall + W.Linv_off;
+    int* fl = flagsall + W.flag_off;
+    double4_t acc[2][2];
+    load_tile32(acc, A + (size_t)(NB * i) * npad + NB * j, npad);
+    // X = S_ij - sum_k L_ik L_jk^T over runs of published k, one acquire per
+    // run, the operands of k + 1 loaded while the MFMAs of k run
+    int k = 0;
+    while (k < j) {
+      const int run = ready_run(fl + i * nblk, fl + j * nblk, k, j);
+      if (run == 0) {
+        if (!spin_flag(fl + i * nblk + k, sync)) return;
+        if (i != j && !spin_flag(fl + j * nblk + k, sync)) return;
+        continue;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int kend = k + run;
+      const double* Ri = A + (size_t)(NB * i) * npad;
+      const double* Rj = A + (size_t)(NB * j) * npad;
+      double a0[2][8], b0[2][8], a1[2][8], b1[2][8];
+      load_update(a0, b0, Ri + NB * k, Rj + NB * k, npad);
+      for (; k < kend; k += 2) {
+        const bool has1 = k + 1 < kend;
+        if (has1) load_update(a1, b1, Ri + NB * (k + 1), Rj + NB * (k + 1), npad);
+        mfma_update(acc, a0, b0);
+        if (!has1) { ++k; break; }
+        if (k + 2 < kend) load_update(a0, b0, Ri + NB * (k + 2), Rj + NB * (k + 2), npad);
+        mfma_update(acc, a1, b1);
+      }
+      k = kend;
+    }
+    acc_to_lds(acc, T);
+    __syncthreads();
+    if (i == j) {
+      // factor and invert (register leaves joined by MFMA), publish L_jj^-1
+      const int bad = factor_invert32(T, Lt, U);
+      if (bad >= 0 && lane == 0 && NB * j + bad < W.n) set_status(stall + w, VI_ENOTPD, NB * j + bad);
+      double* Lo = Lv + (size_t)j * NB * NB;
+#pragma unroll
+      for (int it = 0; it < 16; ++it) {
+        const int e = lane + 64 * it;
+        Lo[e] = Lt[(e >> 5) * LD + (e & 31)];
+      }
+      publish(fl + j * nblk + j);
+    } else {
+      if (!wait_flag(fl + j * nblk + j, sync)) return;
+      // L_ij = X L_jj^-T: A[m][q] = X[m][q], B[q][n] = Linv[n][q]
+      const double* Li = Lv + (size_t)j * NB * NB;
+      double4_t out[2][2];
+#pragma unroll
+      for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) out[bm][bn] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) {
+        double a[2], b[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          a[h] = T[(16 * h + mrow) * LD + 4 * s2 + kq];
+          b[h] = Li[(16 * h + mrow) * NB + 4 * s2 + kq];
+        }
+#pragma unroll
+        for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+          for (int bn = 0; bn < 2; ++bn)
+            out[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm], b[bn], out[bm][bn], 0, 0, 0);
+      }
+      store_tile32(out, A + (size_t)(NB * i) * npad + NB * j, npad);
+      publish(fl + i * nblk + j);
+    }
+    __syncthreads();
+  }
+}
+
 // Whole factorisation and solve of one small window per 512-thread workgroup.
 // Right-looking over 32-wide block columns inside the band, with the forward
 // substitution interleaved (y_b = L_bb^-1 s_b, then s_i -= L_ib y_b) and one
 // step of look-ahead: while waves 1.. apply the trailing update of column b,
 // wave 0 updates and factors the next diagonal tile.  The current panel
 // L_ib (b < i <= b + band) is kept in LDS for the trailing update.
+// With a band of at most kLdsBand tiles the tiles that the next step starts
+// from never leave LDS: the trailing update of column b writes the updated
+// tiles of column b + 1 (below the diagonal) into one of two column buffers
+// and the updated diagonal tile b + 2 into one of two diagonal buffers, so
+// that neither the next panel nor the next look-ahead waits on global
+// memory.  Wider bands keep every updated tile in global memory.
 constexpr int kSmallThreads = 512;
 constexpr int kPanelSlots = kSmallMaxNpad / NB;     // 16: panel tiles, then the diagonal inverses
+constexpr int kLdsBand = (kPanelSlots - 2) / 2;     // 7: two column buffers and two diagonal tiles
 __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double* __restrict__ Aall,
                                                               double* __restrict__ Linvall, double* __restrict__ xall,
                                                               DevStatus* __restrict__ stall) {
@@ -565,7 +568,6 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   __shared__ double T[NB * LD];                 // diagonal tile being factored; the solution in the back-solve
   __shared__ double Li[2][NB * LD];             // L_bb^-1 of the current and the next column
   __shared__ double U[16 * 17];
-  __shared__ double rinv[NB];
   __shared__ double yv[kSmallMaxNpad];          // right-hand side -> y = L^-1 s -> running rhs of L^T x = y
   const int w = blockIdx.x;
   const WinDev& W = D.win[w];
@@ -577,14 +579,26 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   constexpr int NW = kSmallThreads / 64;
   for (int r = tid; r < npad; r += kSmallThreads) yv[r] = A[(size_t)npad * npad + r];
+  const bool lds = bw <= kLdsBand;
+  // LDS mode: column buffer c & 1 holds tiles (i, c), c < i <= c + band, at
+  // slot i - c - 1; diagonal buffer c & 1 holds tile (c, c)
+  auto colbuf = [&](int c) { return P + (size_t)(c & 1) * kLdsBand * NB * NB; };
+  auto diagbuf = [&](int c) { return P + (size_t)(2 * kLdsBand + (c & 1)) * NB * NB; };
   if (wave == 0) {
     tile_to_lds(T, A, npad);
-    const int bad = factor_invert32(T, Li[0], U, rinv);
+    const int bad = factor_invert32(T, Li[0], U);
     if (bad >= 0 && lane == 0 && bad < n) set_status(stall + w, VI_ENOTPD, bad);
 #pragma unroll
     for (int it = 0; it < 16; ++it) {
       const int e = lane + 64 * it;
       Lv[e] = Li[0][(e >> 5) * LD + (e & 31)];
+    }
+  } else if (lds) {
+    // column 0 below the diagonal and diagonal tile 1, as given
+    const int m0 = min(bw, nblk - 1);
+    for (int u = wave - 1; u <= m0; u += NW - 1) {
+      if (u < m0) tile_to_swz(colbuf(0) + u * NB * NB, A + (size_t)(NB * (1 + u)) * npad, npad);
+      else if (nblk > 1) tile_to_swz(diagbuf(1), A + (size_t)NB * npad + NB, npad);
     }
   }
   __syncthreads();
@@ -594,6 +608,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
     const int hi = min(b + bw, nblk - 1);       // last block row of column b inside the band
     const int m = hi - b;                       // panel tiles below the diagonal
     const double* Lc = Li[b & 1];
+    double* Pc = lds ? colbuf(b) : P;           // the panel of column b, swizzled
     // panel: L_ib = A_ib L_bb^-T, b < i <= hi -> global (for the back-solve) and LDS
     for (int u = wave; u < m; u += NW) {
       const int i = b + 1 + u;
@@ -603,23 +618,20 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
 #pragma unroll
         for (int bn = 0; bn < 2; ++bn) acc[bm][bn] = double4_t{0.0, 0.0, 0.0, 0.0};
       double* Aib = A + (size_t)(NB * i) * npad + NB * b;
-      mm32_abt(acc, Aib, npad, Lc, LD, 1.0);
+      double* Pu = Pc + u * NB * NB;
+      if (lds)
+        mm32_abt_swz_pad(acc, Pu, Lc);
+      else
+        mm32_abt(acc, Aib, npad, Lc, LD, 1.0);
       store_tile32(acc, Aib, npad);
-      double* Pu = P + u * NB * NB;
-      const int mrow = lane & 15, kq = lane >> 4;
-#pragma unroll
-      for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < 2; ++bn)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) Pu[swz(16 * bm + kq + 4 * r, 16 * bn + mrow)] = acc[bm][bn][r];
+      acc_to_swz(acc, Pu);                      // same wave, reads of Pu done: in-place is safe
     }
     __syncthreads();
     // forward substitution: s_i -= L_ib y_b (one thread per row of the panel)
     {
       const int u = tid >> 5, r = tid & 31;
       if (u < m) {
-        const double* Pu = P + u * NB * NB;
+        const double* Pu = Pc + u * NB * NB;
         double v = 0.0;
 #pragma unroll
         for (int q = 0; q < NB; ++q) v += Pu[swz(r, q)] * yv[NB * b + q];
@@ -632,11 +644,14 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
         // wave just above), its factor, inverse and forward block
         const int nb1 = b + 1;
         double4_t acc[2][2];
-        load_tile32(acc, A + (size_t)(NB * nb1) * npad + NB * nb1, npad);
-        mm32_abt_lds(acc, P, P, -1.0);
+        if (lds)
+          swz_to_acc(acc, diagbuf(nb1));
+        else
+          load_tile32(acc, A + (size_t)(NB * nb1) * npad + NB * nb1, npad);
+        mm32_abt_lds(acc, Pc, Pc, -1.0);
         acc_to_lds(acc, T);
         double* Ln = Li[nb1 & 1];
-        const int bad = factor_invert32(T, Ln, U, rinv);
+        const int bad = factor_invert32(T, Ln, U);
         if (bad >= 0 && lane == 0 && NB * nb1 + bad < n) set_status(stall + w, VI_ENOTPD, NB * nb1 + bad);
 #pragma unroll
         for (int it = 0; it < 16; ++it) {
@@ -645,17 +660,36 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
         }
         fwd_block(Ln, yv + NB * nb1);
       } else {
-        // trailing update (i, j), b < j <= i <= hi, except (b+1, b+1)
+        // trailing update (i, j), b < j <= i <= hi, except (b+1, b+1); in LDS
+        // mode also the copies of the next step's inputs that no update
+        // touches here (the new band row of column b + 1, diagonal b + 2)
         const int ntri = m * (m + 1) / 2;
-        for (int u = wave; u < ntri; u += NW - 1) {
+        const int hi1 = min(b + 1 + bw, nblk - 1);
+        const bool cp_row = lds && hi1 > hi;                    // tile (hi1, b + 1), as given
+        const bool cp_diag = lds && b + 2 < nblk && b + 2 > hi;  // tile (b + 2, b + 2), as given
+        const int njobs = ntri + (cp_row ? 1 : 0) + (cp_diag ? 1 : 0);
+        for (int u = wave; u < njobs; u += NW - 1) {
+          if (u >= ntri) {
+            if (cp_row && u == ntri)
+              tile_to_swz(colbuf(b + 1) + (hi1 - b - 2) * NB * NB, A + (size_t)(NB * hi1) * npad + NB * (b + 1),
+                          npad);
+            else
+              tile_to_swz(diagbuf(b + 2), A + (size_t)(NB * (b + 2)) * npad + NB * (b + 2), npad);
+            continue;
+          }
           int jj = 0, rem = u;
           while (rem >= m - jj) { rem -= m - jj; ++jj; }
           const int j = b + 1 + jj, i = j + rem;
           double4_t acc[2][2];
           double* Aij = A + (size_t)(NB * i) * npad + NB * j;
           load_tile32(acc, Aij, npad);
-          mm32_abt_lds(acc, P + (i - b - 1) * NB * NB, P + (j - b - 1) * NB * NB, -1.0);
-          store_tile32(acc, Aij, npad);
+          mm32_abt_lds(acc, Pc + (i - b - 1) * NB * NB, Pc + (j - b - 1) * NB * NB, -1.0);
+          if (lds && j == b + 1)
+            acc_to_swz(acc, colbuf(b + 1) + (i - b - 2) * NB * NB);
+          else if (lds && i == b + 2 && j == b + 2)
+            acc_to_swz(acc, diagbuf(b + 2));
+          else
+            store_tile32(acc, Aij, npad);
         }
       }
     }
@@ -705,85 +739,95 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   for (int i = tid; i < npad; i += kSmallThreads) x[i] = (i < n) ? xs[i] : 0.0;
 }
 
-// x = L^-T y per window (blockIdx.x); 1024 threads.  After an aborted
-// factorisation every window is marked failed (its state is then left alone).
-__global__ void __launch_bounds__(1024) k_chol_backsolve(DevPlan D, const double* __restrict__ Aall,
-                                                         const double* __restrict__ Linvall, double* __restrict__ xall,
-                                                         const int* __restrict__ sync, DevStatus* __restrict__ stall) {
-  extern __shared__ double sh[];
-  const WinDev& W = D.win[blockIdx.x];
-  const int n = W.n, npad = W.npad, nblk = W.nblk;
-  if (npad <= kSmallMaxNpad) return;
-  if (load_flag(sync + 1) != 0) {
-    if (threadIdx.x == 0) set_status(stall + blockIdx.x, VI_EDEVICE, -1);
-    return;
-  }
-  const double* A = Aall + W.A_off;
-  const double* Lv = Linvall + W.Linv_off;
-  double* tv = sh;            // running right-hand side [npad]
-  double* xs = sh + npad;     // solution [npad]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int q = lane & 31, half = lane >> 5;
-  for (int r = tid; r < npad; r += 1024) tv[r] = A[(size_t)npad * npad + r];
-  __syncthreads();
-  for (int b = nblk - 1; b >= 0; --b) {
-    // prefetch this wave's first block L_bc (c = wave) while x_b is formed
-    double pre[16];
-    const bool has = wave < b;
-    if (has) {
+// x = L^-T y for the windows of the tile dataflow, as a dataflow over block
+// columns: one 256-thread workgroup per (window, block column c), handed out
+// by a ticket counter in decreasing c, so that a column only waits for
+// columns of smaller tickets.  Column c starts from t_c = y_c and, as the
+// solutions x_b of the columns b > c are published, subtracts L_bc^T x_b
+// (tile (b, c) read before its x_b is waited for); then x_c = L_cc^-T t_c is
+// written and published.  After an aborted factorisation (or a wait past its
+// bound) the window is marked failed and the waits stop; every wave runs the
+// same barriers either way.
+__global__ void __launch_bounds__(256) k_chol_bs(DevPlan D, int t0, int nbs, const double* __restrict__ Aall,
+                                                 const double* __restrict__ Linvall, double* __restrict__ xall,
+                                                 int* __restrict__ flagsall, int* __restrict__ sync,
+                                                 DevStatus* __restrict__ stall) {
+  __shared__ double part[8][NB];
+  __shared__ double tv[NB];
+  __shared__ int tk;
+  const int tid = threadIdx.x, q = tid & 31, r8 = tid >> 5, lane = tid & 63;
+  while (true) {
+    if (tid == 0) tk = atomicAdd(sync + 2, 1);
+    __syncthreads();
+    const int t = tk;
+    __syncthreads();
+    if (t >= nbs) return;
+    const int w = D.chol_tiles[2 * (t0 + t)];
+    const int c = D.chol_tiles[2 * (t0 + t) + 1] & 0xffff;
+    const WinDev& W = D.win[w];
+    const int npad = W.npad, nblk = W.nblk;
+    const double* A = Aall + W.A_off;
+    const double* Lcc = Linvall + W.Linv_off + (size_t)c * NB * NB;
+    double* x = xall + W.x_off;
+    int* xf = flagsall + W.flag_off + (nblk + 1) * nblk;     // x_b published
+    bool aborted = load_flag(sync + 1) != 0;
+    double acc = 0.0;
+    for (int b = nblk - 1; b > c; --b) {
+      double v[4], xv[4];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) pre[u] = A[(size_t)(NB * b + 16 * half + u) * npad + NB * wave + q];
+      for (int u = 0; u < 4; ++u) v[u] = A[(size_t)(NB * b + r8 + 8 * u) * npad + NB * c + q];
+      if (!aborted) aborted = !spin_flag(xf + b, sync);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#pragma unroll
+      for (int u = 0; u < 4; ++u) xv[u] = x[NB * b + r8 + 8 * u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc += v[u] * xv[u];
     }
+    part[r8][q] = acc;
+    __syncthreads();
     if (tid < NB) {
-      const double* Lb = Lv + (size_t)b * NB * NB;
-      double v = 0.0;
-      for (int r = tid; r < NB; ++r) v += Lb[r * NB + tid] * tv[NB * b + r];
-      xs[NB * b + tid] = v;
+      double s = A[(size_t)npad * npad + NB * c + q];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s -= part[k][q];
+      tv[q] = s;
     }
     __syncthreads();
-    for (int c = wave; c < b; c += 16) {
-      double v = 0.0;
-      if (c == wave) {
+    if (tid < 64) {
+      // x_c = L_cc^-T t_c: x[q] = sum_r Linv[r][q] t[r] (lanes 32..63 idle)
+      double s = 0.0;
+      if (tid < NB) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) v += pre[u] * xs[NB * b + 16 * half + u];
-      } else {
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-          v += A[(size_t)(NB * b + 16 * half + u) * npad + NB * c + q] * xs[NB * b + 16 * half + u];
+        for (int r = 0; r < NB; ++r) s += Lcc[r * NB + q] * tv[r];
+        x[NB * c + q] = (NB * c + q < W.n) ? s : 0.0;
       }
-      v += __shfl_xor(v, 32);
-      if (half == 0) tv[NB * c + q] -= v;
+      if (aborted) {
+        if (lane == 0) set_status(stall + w, VI_EDEVICE, -1);
+      } else {
+        publish(xf + c);
+      }
     }
     __syncthreads();
   }
-  double* x = xall + W.x_off;
-  for (int i = tid; i < npad; i += 1024) x[i] = (i < n) ? xs[i] : 0.0;
 }
 
 }  // namespace
 
 void chol_set_attributes() {
-  const int lds = (int)(sizeof(double) * 2 * ((15 * kMaxKeyframes + NB - 1) / NB * NB));
-  (void)hipFuncSetAttribute((const void*)k_chol_backsolve, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   (void)hipFuncSetAttribute((const void*)k_chol_small, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)(sizeof(double) * kPanelSlots * NB * NB));
 }
 
 void launch_chol(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, DevStatus* st) {
-  int npad_max = 0;
   bool small = false;
-  for (const WinDev& W : P.win) {
-    npad_max = std::max(npad_max, W.npad);
-    small = small || W.npad <= kSmallMaxNpad;
-  }
+  for (const WinDev& W : P.win) small = small || W.npad <= kSmallMaxNpad;
   if (small)
     hipLaunchKernelGGL(k_chol_small, dim3(P.n_win), dim3(kSmallThreads), sizeof(double) * kPanelSlots * NB * NB, s, D,
                        w.A, w.Linv, w.x, st);
   if (P.n_tickets > 0) {
     const int grid = std::min(P.n_tickets, kMaxDataflowWG);
     hipLaunchKernelGGL(k_chol_df, dim3(grid), dim3(64), 0, s, D, P.n_tickets, w.A, w.Linv, w.flags, w.sync, st);
-    hipLaunchKernelGGL(k_chol_backsolve, dim3(P.n_win), dim3(1024), sizeof(double) * 2 * npad_max, s, D, w.A,
-                       w.Linv, w.x, w.sync, st);
+    hipLaunchKernelGGL(k_chol_bs, dim3(std::min(P.n_bs, kMaxDataflowWG)), dim3(256), 0, s, D, P.n_tickets, P.n_bs,
+                       w.A, w.Linv, w.x, w.flags, w.sync, st);
   }
 }
 

@@ -1220,6 +1220,9 @@ __global__ void __launch_bounds__(256) k_cost_reduce(int ncost, int range_px, De
 //   4-12: inertial residual of the factor (i, i+1) (rotation x 100,
 //         position x 10, velocity x 10), constant over the cells; zero for
 //         the last keyframe or without inertial factors
+//   13: -sum(w J_d r) / (h + 1e-6) / 0.2, the depth-only Gauss-Newton step
+//       of the cell (J_d = dr/dd of Eq. 1, h = sum w J_d^2), in units of 0.2
+//   14: log(1 + h / n_cell)
 // and dims[img] = the keyframe's own cell grid.  Zero outside it.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_warm_features(OptsDev o, DevPlan D, int HQ, int WQ, float* __restrict__ feat,
@@ -1246,9 +1249,9 @@ __global__ void __launch_bounds__(256) k_warm_features(OptsDev o, DevPlan D, int
   const int p = blockIdx.x * 256 + tid;
   if (p < npix) {
     const int cy = p / WQ, cx = p % WQ;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (cy < hq0 && cx < wq0) {
-      double sxr = 0.0, syr = 0.0, swx = 0.0, swy = 0.0, sd = 0.0;
+      double sxr = 0.0, syr = 0.0, swx = 0.0, swy = 0.0, sd = 0.0, sg = 0.0, sh = 0.0;
       int nc = 0;
       for (int y = 4 * cy; y < min(4 * cy + 4, W.H); ++y)
         for (int x = 4 * cx; x < min(4 * cx + 4, W.W); ++x) {
@@ -1266,14 +1269,20 @@ __global__ void __launch_bounds__(256) k_warm_features(OptsDev o, DevPlan D, int
             syr += q.wy * q.ry;
             swx += q.wx;
             swy += q.wy;
+            sg += q.wx * q.Jdx * q.rx + q.wy * q.Jdy * q.ry;
+            sh += q.wx * q.Jdx * q.Jdx + q.wy * q.Jdy * q.Jdy;
           }
         }
       v[0] = sxr / (swx + 1e-6);
       v[1] = syr / (swy + 1e-6);
       v[2] = (swx + swy) / (2.0 * max(k, 1) * nc);
       v[3] = sd / nc;
+      v[4] = -sg / (sh + 1e-6) / 0.2;
+      v[5] = log1p(sh / nc);
     }
     for (int c = 0; c < 4; ++c) f[(size_t)c * npix + p] = (float)v[c];
+    f[(size_t)13 * npix + p] = (float)v[4];
+    f[(size_t)14 * npix + p] = (float)v[5];
   }
   if (blockIdx.x == 0) {
     for (int e = tid; e < 9 * npix; e += 256) {
@@ -1308,6 +1317,37 @@ __global__ void __launch_bounds__(256) k_warm_apply(DevPlan D, int HQ, int WQ, c
                    ay * ((1 - ax) * g[y1 * WQ + x0] + ax * g[y1 * WQ + x1]);
   double* dep = W.invdepth + (size_t)ls * W.HW + p;
   *dep = fmax(*dep + v, d_min);
+}
+
+// Keep (restore = 0) or put back (restore = 1) a keyframe's inverse depths and
+// bias: saved_d is indexed like the per-pixel workspace arrays (pix_base),
+// saved_b by global keyframe.  When restoring, a window is put back only if
+// its cost at the corrected state (trace slot 1) is not below the cost at
+// the initial state (slot 0); a non-finite corrected cost counts as not below.
+__global__ void __launch_bounds__(256) k_warm_state(DevPlan D, double* __restrict__ saved_d,
+                                                    double* __restrict__ saved_b, const double* __restrict__ trace,
+                                                    int restore) {
+  const int src = blockIdx.y;
+  const int w = D.win_of_kf[src];
+  const WinDev W = D.win[w];
+  const int ls = src - W.kf_base;
+  if (restore) {
+    const double f0 = trace[(size_t)w * kTraceLen], f1 = trace[(size_t)w * kTraceLen + 2];
+    if (f1 < f0) return;
+  }
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  double* dep = W.invdepth + (size_t)ls * W.HW;
+  double* sd = saved_d + W.pix_base + (size_t)ls * W.HW;
+  if (p < W.HW) {
+    if (restore) dep[p] = sd[p];
+    else sd[p] = dep[p];
+  }
+  if (blockIdx.x == 0 && threadIdx.x < 6) {
+    double* b = W.bias + (size_t)ls * 6 + threadIdx.x;
+    double* sb = saved_b + (size_t)src * 6 + threadIdx.x;
+    if (restore) *b = *sb;
+    else *sb = *b;
+  }
 }
 
 }  // namespace
@@ -1401,6 +1441,12 @@ void launch_warm_features(hipStream_t s, const Plan& P, const DevPlan& D, const 
 void launch_warm_apply(hipStream_t s, const Plan& P, const DevPlan& D, int HQ, int WQ, const float* dd,
                        const float* db, double d_min) {
   hipLaunchKernelGGL(k_warm_apply, dim3((P.hw_max + 255) / 256, P.N), dim3(256), 0, s, D, HQ, WQ, dd, db, d_min);
+}
+
+void launch_warm_state(hipStream_t s, const Plan& P, const DevPlan& D, double* saved_d, double* saved_b,
+                       const double* trace, int restore) {
+  hipLaunchKernelGGL(k_warm_state, dim3((P.hw_max + 255) / 256, P.N), dim3(256), 0, s, D, saved_d, saved_b, trace,
+                     restore);
 }
 
 }  // namespace vi

@@ -129,7 +129,7 @@ __device__ void conv_layer(const __bf16* in, __bf16* out, const __bf16* Wl, int 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// forward: features [n][13][HQ][WQ] (FP32) -> dd [n][HQ][WQ], db [n][6]; when
+// forward: features [n][15][HQ][WQ] (FP32) -> dd [n][HQ][WQ], db [n][6]; when
 // act is given, the BF16 activations [n][5][HQ*WQ][32] (layer 0 = the input)
 // are kept for the backward pass.
 // ---------------------------------------------------------------------------

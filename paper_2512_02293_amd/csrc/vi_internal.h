@@ -79,6 +79,7 @@ struct Plan {
   std::vector<int32_t> pair_off, pair_z, pair_zb;
   std::vector<int32_t> chol_tiles;             // ticket -> (window, (i << 16) | j)
   int n_tickets = 0;
+  int n_bs = 0;                                // back-substitution columns after the tiles in chol_tiles
   size_t flags_size = 0;
   size_t gram_size = 0, z_size = 0, zb_size = 0;
   size_t A_size = 0, Linv_size = 0, x_size = 0;
@@ -124,7 +125,7 @@ struct OptsDev {
 };
 
 // learned warm-start network (k_wnet.hip)
-constexpr int kWCin = 13, kWCinPad = 16, kWC = 32, kWLayers = 4;
+constexpr int kWCin = 15, kWCinPad = 16, kWC = 32, kWLayers = 4;
 constexpr int kWParams = kWC * kWCin * 9 + kWC + 3 * (kWC * kWC * 9 + kWC) + kWC * 9 + 1 + 6 * kWC + 6;
 constexpr int kWHQMax = 16, kWWQMax = 24;       // canvas of 4x4-pixel cells (maps up to 64 x 96)
 constexpr float kWSd = 0.02f;                   // inverse-depth correction scale of the loss
@@ -166,5 +167,7 @@ void launch_warm_features(hipStream_t s, const Plan& P, const DevPlan& D, const 
                           float* feat, int* dims);
 void launch_warm_apply(hipStream_t s, const Plan& P, const DevPlan& D, int HQ, int WQ, const float* dd,
                        const float* db, double d_min);
+void launch_warm_state(hipStream_t s, const Plan& P, const DevPlan& D, double* saved_d, double* saved_b,
+                       const double* trace, int restore);
 
 }  // namespace vi

@@ -104,6 +104,7 @@ class SceneConfig:
     init_dp: float = 0.05               # m
     init_dtheta_deg: float = 2.0
     init_depth_rel: float = 0.1
+    init_depth_smooth: bool = False     # relative depth error: smooth field (True) or per-pixel white
     init_dv_std: float = 0.05
     z_min: float = 0.1
     noiseless: bool = False             # no pixel/IMU noise, no bias random walk
@@ -147,9 +148,10 @@ def config_batched_window(w: int) -> SceneConfig:
     return config_random_window(4000 + w)
 
 
-def config_random_window(seed: int) -> SceneConfig:
+def config_random_window(seed: int, smooth_depth_init: bool = False) -> SceneConfig:
     """A window drawn from the batched-window distribution with its own seed
-    (training windows of the warm start use seeds 100000 and up)."""
+    (training windows of the warm start use seeds 100000 and up, with a smooth
+    initial depth error: ``smooth_depth_init``)."""
     rng = np.random.default_rng(seed)
     n = int(rng.integers(8, 33))
     degs = [int(rng.integers(3, min(8, n - 1) + 1)) for _ in range(n)]
@@ -157,7 +159,7 @@ def config_random_window(seed: int) -> SceneConfig:
         H, W = 48, 64
     else:
         H, W = 60, 80
-    return SceneConfig(n_kf=n, H=H, W=W, out_degrees=degs, gap_range=(5, 40))
+    return SceneConfig(n_kf=n, H=H, W=W, out_degrees=degs, gap_range=(5, 40), init_depth_smooth=smooth_depth_init)
 
 
 # --------------------------------------------------------------------------
@@ -303,6 +305,20 @@ def _depth_field(cfg: SceneConfig, rng: np.random.Generator) -> np.ndarray:
     return 0.2 + 1.8 / (1.0 + np.exp(-acc))
 
 
+def _smooth_unit_field(cfg: SceneConfig, rng: np.random.Generator) -> np.ndarray:
+    """Zero-mean, unit-variance smooth random field (four plane waves of at
+    most two cycles per image, as the depth fields), clipped to +-3."""
+    H, W = cfg.H, cfg.W
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    acc = np.zeros((H, W))
+    for _ in range(4):
+        f = rng.uniform(-2.0, 2.0, size=2)
+        f *= min(1.0, 2.0 / max(np.linalg.norm(f), 1e-12))
+        acc += rng.uniform(0.6, 1.4) * np.cos(2 * np.pi * (f[0] * xs / W + f[1] * ys / H) + rng.uniform(0, 2 * np.pi))
+    acc = acc - acc.mean()
+    return np.clip(acc / max(acc.std(), 1e-12), -3.0, 3.0)
+
+
 def _project(cfg: SceneConfig, R_i, p_i, R_j, p_j, invdepth_i):
     """Pixel coordinates in camera j of camera i's pixels back-projected at their
     inverse depth; also the depth seen from j."""
@@ -410,6 +426,8 @@ def make_problem(cfg: SceneConfig, seed: int, bias_hat_mode: str = "zero") -> Pr
         pose0[1:, 3:] = qp / np.linalg.norm(qp, axis=1, keepdims=True)
         vel0 += rng.normal(0, cfg.init_dv_std, size=vel0.shape)
     eps = np.clip(rng.normal(size=invdepth_gt.shape), -3.0, 3.0)
+    if cfg.init_depth_smooth:
+        eps = np.stack([_smooth_unit_field(cfg, rng) for _ in range(N)], 0)
     invdepth0 = invdepth_gt * (1.0 + cfg.init_depth_rel * eps)
     bias0 = np.zeros((N, 6))
     if bias_hat_mode == "gt":

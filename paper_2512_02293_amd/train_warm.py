@@ -26,7 +26,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args(argv)
 
-    from . import binding, synth, warmstart
+    from . import binding, warmstart
     log = lambda m: print(m, flush=True)
     import torch
     ctx = binding.Context(0)
@@ -52,14 +52,16 @@ def main(argv=None):
     out = args.out or warmstart.PARAMS_FILE
     net.save(out)
     log(f"trained in {t_train:.1f} s, parameters saved to {out}")
-    evalp = [synth.make_problem(synth.config_batched_window(w), 4000 + w) for w in range(64)]
+    evalp = warmstart.eval_windows()
     res = warmstart.time_to_tol(ctx, net, evalp, opts)
     summary = dict(windows=args.windows, images=int(data[0].shape[0]), epochs=args.epochs, loss=hist,
                    loss_heldout=loss_val, loss_heldout_zero_predictor=loss_zero,
                    dataset_s=t_data, train_s=t_train, eval_windows=64,
                    iters_plain_mean=float(np.mean(res["k_plain"])), iters_warm_mean=float(np.mean(res["k_warm"])),
                    K_plain=res["K_plain"], K_warm=res["K_warm"], accepted=int(sum(res["accepted"])),
-                   ms_plain=res["ms_plain"], ms_warm=res["ms_warm"])
+                   ms_plain=res["ms_plain"], ms_warm=res["ms_warm"],
+                   ms_plain_per_window_total=res["ms_plain_per_window_total"],
+                   ms_warm_per_window_total=res["ms_warm_per_window_total"])
     print(json.dumps(summary), flush=True)
     ctx.close()
 

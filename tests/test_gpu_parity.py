@@ -160,6 +160,19 @@ def test_step_uneven_out_degree_and_gaps(ctx):
     _single_step_case(ctx, prob)
 
 
+@pytest.mark.parametrize("n_kf,loop_gap,seed", [(32, 20, 21), (16, 12, 22)])
+def test_step_wide_band_small_system(ctx, n_kf, loop_gap, seed):
+    """Windows with a few long-range edges solved by the one-workgroup
+    Cholesky: 32 keyframes (480 x 480, a band of 14 tiles: more than the
+    LDS-resident column buffers hold, so every updated tile goes through
+    global memory) and 16 keyframes (240 x 240, a band of 7 tiles: the
+    largest the LDS-resident buffers take)."""
+    cfg = synth.SceneConfig(n_kf=n_kf, H=24, W=32, k_out=4, n_loop=4, loop_gap=loop_gap, gap_range=(15, 25))
+    prob = synth.make_problem(cfg, seed)
+    assert max(abs(int(a) - int(b)) for a, b in zip(prob.ii, prob.jj)) >= loop_gap
+    _single_step_case(ctx, prob)
+
+
 def test_step_sliding_window_full_size(ctx):
     """The 24-keyframe, 60x80, 288-edge window (the benchmarked shape)."""
     _single_step_case(ctx, synth.make_problem(synth.config_window(), 2))

@@ -70,7 +70,7 @@ def test_warm_features_match_oracle(ctx):
 
 def _batch(seed, n=6, hq=12, wq=16):
     rng = np.random.default_rng(seed)
-    x = rng.standard_normal((n, cnn.C_IN, hq, wq)) * np.array([2, 2, 0.3, 0.5] + [1] * 9)[None, :, None, None]
+    x = rng.standard_normal((n, cnn.C_IN, hq, wq)) * np.array([2, 2, 0.3, 0.5] + [1] * 11)[None, :, None, None]
     x[:, 2] = np.abs(x[:, 2])
     dims = np.array([[hq, wq] if k % 2 == 0 else [hq - 3, wq - 4] for k in range(n)], dtype=np.int32)
     mask = np.zeros((n, hq, wq))
@@ -153,3 +153,55 @@ def test_warm_apply_matches_oracle(ctx):
             assert np.abs(d.invdepth[i].cpu().numpy() - ref).max() <= 1e-6
             assert np.abs(d.bias[i].cpu().numpy() - (p.bias[i] + db[k])).max() <= 1e-7
             k += 1
+
+
+def _state(dps):
+    return [(d.invdepth.cpu().numpy().copy(), d.bias.cpu().numpy().copy(), d.pose.cpu().numpy().copy(),
+             d.vel.cpu().numpy().copy()) for d in dps]
+
+
+def test_warm_start_keeps_or_puts_back(ctx):
+    """vi_warm_start: a window keeps the corrections only if the plain cost
+    falls; otherwise its inverse depths and biases are put back bit for bit.
+    Poses and velocities are never touched.  The kept state equals the one of
+    the separate calls (features -> forward -> apply) bit for bit."""
+    import torch
+    from paper_2512_02293_amd import binding, warmstart
+    probs = warmstart.eval_windows(6)
+    opts = warmstart.study_opts()
+    dps = [binding.DeviceProblem(p) for p in probs]
+    imus = [ctx.imu_preintegrate(d.off, d.gyro, d.accel, d.imu_dt, d.bias_hat, d.noise) for d in dps]
+    ws = torch.empty(ctx.warm_start_workspace_size(dps, opts), dtype=torch.uint8, device="cuda:0")
+    init = _state(dps)
+    P = cnn.n_params()
+    # a network whose depth head outputs a large constant: every cost rises, every window is put back
+    bad = np.zeros(P, dtype=np.float32)
+    o_bd = sum(int(np.prod(shp)) for name, shp in cnn.SHAPES[:9])
+    assert cnn.SHAPES[9][0] == "bd"
+    bad[o_bd] = 0.5
+    res = ctx.warm_start(dps, imus, opts, _t(bad), ws)
+    for r, s0, d in zip(res, init, dps):
+        assert not r["accepted"] and r["cost_warm"] > r["cost_init"] and r["cost_after"] == r["cost_init"]
+        for a, b in zip(s0, _state([d])[0]):
+            assert np.array_equal(a, b)
+    # the trained network: kept windows lower the cost and match the separate calls
+    theta = np.load(warmstart.PARAMS_FILE)
+    res = ctx.warm_start(dps, imus, opts, _t(theta), ws)
+    got = _state(dps)
+    for d in dps:
+        d.reset_state()
+    feat, dims = ctx.warm_features(dps, imus, opts, warmstart.HQ, warmstart.WQ)
+    dd, db = ctx.warm_forward(_t(theta), feat, dims)
+    ctx.warm_apply(dps, imus, opts, dd, db)
+    sep = _state(dps)
+    n_acc = 0
+    for r, g, s, s0 in zip(res, got, sep, init):
+        print(f"accepted {r['accepted']} cost {r['cost_init']:.6g} -> {r['cost_warm']:.6g}")
+        ref = s if r["accepted"] else s0
+        n_acc += r["accepted"]
+        if r["accepted"]:
+            assert r["cost_warm"] < r["cost_init"] and r["cost_after"] == r["cost_warm"]
+        for a, b in zip(g, ref):
+            assert np.array_equal(a, b)
+        assert np.array_equal(g[2], s0[2]) and np.array_equal(g[3], s0[3])
+    assert n_acc >= 1

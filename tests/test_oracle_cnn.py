@@ -96,8 +96,46 @@ def test_features_vanish_at_noiseless_ground_truth():
     cam, st, gr = osolve.from_problem(prob, exact_targets=True)
     gt = osolve.state_from_arrays(prob.pose_gt, prob.vel_gt, prob.bias_gt, prob.invdepth_gt)
     X, mask = cnn.features(cam, gt, gr)
-    assert X.shape == (8, 13, 12, 16) and mask.all()
+    assert X.shape == (8, 15, 12, 16) and mask.all()
     assert np.abs(X[:, 0:2]).max() < 1e-9          # residuals vanish at the truth
     assert np.abs(X[:, 4:13]).max() < 1e-8         # inertial residuals vanish (discrete-consistent truth)
+    assert np.abs(X[:, 13]).max() < 1e-6           # so does the depth-only step
     assert np.allclose(X[:, 3], np.stack([cnn.cell_mean(d, 48, 64) for d in prob.invdepth_gt]))
     assert (X[:, 2] > 0).all()
+
+
+def test_depth_step_channel_recovers_a_depth_offset():
+    """Poses at the truth, noiseless targets, every inverse depth of the
+    keyframes raised by delta: the residual is J_d delta to first order, so the
+    depth-only step of every cell is -delta (channel 13 = -delta / 0.2) up to
+    O(delta^2); channel 14 equals log(1 + h / n_cell) with h formed from
+    central finite differences of the residual in the inverse depth."""
+    from oracle import vision
+    cfg = synth.config_small()
+    cfg.noiseless = True
+    cfg.zero_bias = True
+    prob = synth.make_problem(cfg, 2)
+    cam, _, gr = osolve.from_problem(prob, exact_targets=True)
+    delta = 1e-4
+    st = osolve.state_from_arrays(prob.pose_gt, prob.vel_gt, prob.bias_gt, prob.invdepth_gt + delta)
+    X, _ = cnn.features(cam, st, gr)
+    cells = X[:, 13]
+    live = np.abs(cells) > 0
+    assert live.mean() > 0.9
+    np.testing.assert_allclose(cells[live], -delta / 0.2, rtol=2e-3)
+    # channel 14 of keyframe 0 from finite differences
+    fx, fy, cx, cy, H, W = cam.intr
+    i, eps = 0, 1e-6
+    h = np.zeros(H * W)
+    for e in range(len(gr.ii)):
+        if int(gr.ii[e]) != i:
+            continue
+        j = int(gr.jj[e])
+        args = (cam.intr, st.R[i], st.p[i], st.R[j], st.p[j])
+        rp, vp = vision.edge_residual(*args, st.d[i] + eps, gr.target[e], 0.1)
+        rm, vm = vision.edge_residual(*args, st.d[i] - eps, gr.target[e], 0.1)
+        Jd = (rp - rm) / (2 * eps)
+        w = np.asarray(gr.weight[e], np.float64).reshape(2, -1) * (vp & vm)[None]
+        h += (w * Jd * Jd).sum(axis=0)
+    ref = np.log1p(cnn.cell_mean(h.reshape(H, W), H, W))
+    np.testing.assert_allclose(X[i, 14], ref, rtol=1e-6)
