@@ -328,6 +328,16 @@ size_t vi_warm_start_workspace_size(int32_t n_windows, const vi_window* windows,
 vi_status vi_warm_start(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,
                         const float* params, void* workspace, size_t workspace_bytes, int32_t* accepted);
 
+/* vi_warm_start followed by iters (>= 0) Gauss-Newton steps, as one HIP
+ * graph (captured on the first call of a shape and replayed after), so that
+ * the warm start costs no extra host round trip.  Reports and errors as for
+ * vi_ba_solve_batched over the steps that follow the warm start (iters = 0:
+ * as vi_warm_start); accepted as for vi_warm_start.  workspace: at least
+ * vi_warm_start_workspace_size bytes. */
+vi_status vi_ba_solve_warm(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,
+                           const float* params, int32_t iters, void* workspace, size_t workspace_bytes,
+                           int32_t* accepted);
+
 #ifdef __cplusplus
 }
 #endif

@@ -70,7 +70,7 @@ EXPORTS = ["vi_ctx_create", "vi_ctx_destroy", "vi_ctx_set_stream", "vi_last_erro
            "imu_preintegrate", "vi_workspace_size", "vi_ba_step", "vi_ba_solve", "vi_workspace_size_batched",
            "vi_ba_solve_batched", "vi_ctx_set_autotune", "vi_warm_param_count", "vi_warm_workspace_size",
            "vi_warm_features", "vi_warm_forward", "vi_warm_gradients", "vi_warm_adamw", "vi_warm_apply",
-           "vi_warm_start_workspace_size", "vi_warm_start"]
+           "vi_warm_start_workspace_size", "vi_warm_start", "vi_ba_solve_warm"]
 
 _lib = None
 
@@ -131,6 +131,8 @@ def load(path: str = LIB_PATH):
     lib.vi_warm_start_workspace_size.restype = C.c_size_t
     lib.vi_warm_start.argtypes = [vp, i32, C.POINTER(Window), C.POINTER(Opts), vp, vp, C.c_size_t, vp]
     lib.vi_warm_start.restype = C.c_int
+    lib.vi_ba_solve_warm.argtypes = [vp, i32, C.POINTER(Window), C.POINTER(Opts), vp, i32, vp, C.c_size_t, vp]
+    lib.vi_ba_solve_warm.restype = C.c_int
     _lib = lib
     return lib
 
@@ -384,6 +386,23 @@ class Context:
                                            workspace.numel(), acc.ctypes.data_as(C.c_void_p)))
         return [dict(accepted=bool(a), cost_init=float(c[0]), cost_warm=float(c[1]), cost_after=r.cost_after)
                 for a, (r, c, _) in zip(acc, reps)]
+
+    def solve_warm(self, probs, imus, opts: Opts, params, iters: int, workspace, costs=False):
+        """Warm start then iters GN steps in one graph; per-window reports with 'accepted'."""
+        _check_dev(workspace, (None,), self.torch.uint8, "workspace")
+        _check_dev(params, (int(self.lib.vi_warm_param_count()),), self.torch.float32, "params")
+        wins, reps, keep = self._windows(probs, imus, True, costs, max(iters, 1))
+        acc = np.zeros(len(probs), dtype=np.int32)
+        self._check(self.lib.vi_ba_solve_warm(self.h, len(probs), wins, C.byref(opts), _ptr(params), iters,
+                                              _ptr(workspace), workspace.numel(), acc.ctypes.data_as(C.c_void_p)))
+        out = []
+        for a, (r, cost_arr, _) in zip(acc, reps):
+            d = dict(accepted=bool(a), cost_before=r.cost_before, cost_after=r.cost_after, n_valid=int(r.n_valid),
+                     iters_done=int(r.iters_done))
+            if costs:
+                d["costs"] = cost_arr[: iters + 1]
+            out.append(d)
+        return out
 
 
 class DeviceProblem:

@@ -484,8 +484,69 @@ vi_status autotune_range(vi_ctx* ctx, const Work& w, const OptsDev& od) {
   return VI_OK;
 }
 
+// canvas of the warm start: the largest cell grid of the windows
+void warm_canvas(const std::vector<WinIn>& wins, int* hq, int* wq) {
+  *hq = 1;
+  *wq = 1;
+  for (const WinIn& in : wins) {
+    *hq = std::max(*hq, (in.cam->H + 3) / 4);
+    *wq = std::max(*wq, (in.cam->W + 3) / 4);
+  }
+}
+
+// the warm start's own buffers, after the solver's workspace
+struct WarmWork {
+  float* feat;
+  int32_t* dims;
+  float* dd;
+  float* db;
+  double* saved_d;
+  double* saved_b;
+  double* trace;       // [n_win][kTraceLen]: F at the initial (slot 0) and corrected (slot 1) state
+};
+
+struct WarmArgs {
+  const float* params;
+  int hq, wq;
+};
+
+WarmWork warm_carve(const Plan& P, int hq, int wq, void* base, size_t* bytes) {
+  size_t solve = 0;
+  do_carve(P, nullptr, &solve);
+  Carve c;
+  c.base = base ? (char*)base + solve : nullptr;
+  const size_t n = P.N, cells = (size_t)hq * wq;
+  WarmWork ww{};
+  ww.feat = c.take<float>(n * kWCin * cells);
+  ww.dims = c.take<int32_t>(n * 2);
+  ww.dd = c.take<float>(n * cells);
+  ww.db = c.take<float>(n * 6);
+  ww.saved_d = c.take<double>((size_t)P.pix_total);
+  ww.saved_b = c.take<double>(n * 6);
+  ww.trace = c.take<double>((size_t)P.n_win * kTraceLen);
+  if (bytes) *bytes = solve + c.off;
+  return ww;
+}
+
+// warm start before the iterations (the corrections of a window are kept only
+// where the cost falls); needs the inertial information already formed
+void launch_warm_prologue(hipStream_t sp, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& od,
+                          const WarmArgs& wa, const WarmWork& ww) {
+  launch_final_cost(sp, P, D, w, od, 0, ww.trace);
+  launch_warm_state(sp, P, D, ww.saved_d, ww.saved_b, ww.trace, 0);
+  launch_warm_features(sp, P, D, od, wa.hq, wa.wq, ww.feat, ww.dims);
+  launch_wnet_forward(sp, P.N, wa.hq, wa.wq, ww.dims, wa.params, ww.feat, nullptr, ww.dd, ww.db);
+  launch_warm_apply(sp, P, D, wa.hq, wa.wq, ww.dd, ww.db, od.d_min);
+  launch_final_cost(sp, P, D, w, od, 1, ww.trace);
+  launch_warm_state(sp, P, D, ww.saved_d, ww.saved_b, ww.trace, 1);
+}
+
+// The solver: optional warm start (wa), then iters Gauss-Newton steps and the
+// final cost, captured once per shape as a HIP graph (eager when stage times
+// are asked for).  With a warm start, iters may be 0 and accepted[w] reports
+// whether window w kept its corrections.
 vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int iters, void* workspace,
-              size_t workspace_bytes) {
+              size_t workspace_bytes, const WarmArgs* wa = nullptr, int32_t* accepted = nullptr) {
   if (!ctx) return VI_EINVAL;
   vi_status s = check_opts(ctx, o);
   if (s != VI_OK) return s;
@@ -494,7 +555,14 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
     s = check_window(ctx, (int)w, wins[w], o, true);
     if (s != VI_OK) return s;
   }
-  if (iters < 1 || iters > kMaxIters) return fail(ctx, VI_EINVAL, "iters must be in [1, %d]", kMaxIters);
+  const int min_iters = wa ? 0 : 1;
+  if (iters < min_iters || iters > kMaxIters)
+    return fail(ctx, VI_EINVAL, "iters must be in [%d, %d]", min_iters, kMaxIters);
+  if (wa) {
+    if (!wa->params) return fail(ctx, VI_EINVAL, "null warm-start parameters");
+    if (wa->hq > kWHQMax || wa->wq > kWWQMax)
+      return fail(ctx, VI_EINVAL, "warm start: maps of up to %d x %d pixels only", 4 * kWHQMax, 4 * kWWQMax);
+  }
   if (!workspace) return fail(ctx, VI_EINVAL, "null workspace");
   if (((uintptr_t)workspace & 255) != 0) return fail(ctx, VI_EINVAL, "workspace must be 256-byte aligned");
   HIPCHK(ctx, hipSetDevice(ctx->device));
@@ -502,10 +570,14 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
   if (s != VI_OK) return s;
   Plan& P = ctx->plan;
   size_t need = 0;
-  do_carve(P, nullptr, &need);
+  if (wa)
+    warm_carve(P, wa->hq, wa->wq, nullptr, &need);
+  else
+    do_carve(P, nullptr, &need);
   if (workspace_bytes < need)
     return fail(ctx, VI_ENOMEM, "workspace too small: %zu bytes given, %zu needed", workspace_bytes, need);
   Work w = do_carve(P, workspace, nullptr);
+  const WarmWork ww = wa ? warm_carve(P, wa->hq, wa->wq, workspace, nullptr) : WarmWork{};
   OptsDev od{o->n_fixed, o->use_imu ? 1 : 0, o->bias_fixed ? 1 : 0, o->precision, o->lm_lambda, o->depth_eta,
              o->z_min, o->d_min};
   const bool timing = wins[0].rep && wins[0].rep->stage_ms;
@@ -531,6 +603,7 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
     std::vector<double> acc(VI_NUM_STAGES, 0.0);
     launch_reset_status(sp, ctx->status, P.n_win);
     if (od.use_imu) launch_imu_info(sp, P, D, w.Lam, ctx->status);
+    if (wa) launch_warm_prologue(sp, P, D, w, od, *wa, ww);
     TimingUser tu{sp, ev.data()};
     for (int it = 0; it < iters; ++it) {
       HIPCHK(ctx, hipEventRecord(ev[0], sp));
@@ -560,6 +633,8 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
     std::memcpy(ob, o, sizeof(vi_opts));
     key.insert(key.end(), ob, ob + sizeof(vi_opts) / 8);
     key.push_back((uint64_t)(uintptr_t)workspace);
+    key.push_back((uint64_t)(uintptr_t)(wa ? wa->params : nullptr));
+    key.push_back(wa ? (uint64_t)(wa->hq * 1000 + wa->wq) : 0);
     for (const WinDev& W : P.win) {
       const void* ptrs[] = {W.pose, W.vel, W.bias, W.invdepth, W.target, W.weight, W.imu, W.rep_dxi, W.rep_dd};
       for (const void* p : ptrs) key.push_back((uint64_t)(uintptr_t)p);
@@ -575,6 +650,7 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
       HIPCHK(ctx, hipStreamBeginCapture(sp, hipStreamCaptureModeThreadLocal));
       launch_reset_status(sp, ctx->status, P.n_win);
       if (od.use_imu) launch_imu_info(sp, P, D, w.Lam, ctx->status);
+      if (wa) launch_warm_prologue(sp, P, D, w, od, *wa, ww);
       for (int it = 0; it < iters; ++it) launch_step(sp, P, D, w, od, it, ctx->status);
       launch_final_cost(sp, P, D, w, od, iters);
       hipGraph_t g = nullptr;
@@ -592,6 +668,9 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
   std::vector<double> trace((size_t)P.n_win * kTraceLen);
   HIPCHK(ctx, hipMemcpyAsync(hs.data(), ctx->status, sizeof(DevStatus) * P.n_win, hipMemcpyDeviceToHost, sp));
   HIPCHK(ctx, hipMemcpyAsync(trace.data(), w.trace, sizeof(double) * trace.size(), hipMemcpyDeviceToHost, sp));
+  std::vector<double> wtrace(wa ? trace.size() : 0);
+  if (wa)
+    HIPCHK(ctx, hipMemcpyAsync(wtrace.data(), ww.trace, sizeof(double) * wtrace.size(), hipMemcpyDeviceToHost, sp));
   HIPCHK(ctx, hipStreamSynchronize(sp));
   int first_bad = -1;
   for (int wi = 0; wi < P.n_win; ++wi) {
@@ -607,7 +686,20 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
     rep->cost_after = tr[2 * iters];
     if (rep->costs)
       for (int t = 0; t <= iters; ++t) rep->costs[t] = tr[2 * t];
+    if (wa && iters == 0) {
+      // the warm start alone: initial F, then F of the state left behind
+      const double* wt = wtrace.data() + (size_t)wi * kTraceLen;
+      rep->cost_before = wt[0];
+      rep->n_valid = (int64_t)wt[1];
+      if (rep->costs) {
+        rep->costs[0] = wt[0];
+        rep->costs[1] = wt[2];
+      }
+    }
   }
+  if (wa && accepted)
+    for (int wi = 0; wi < P.n_win; ++wi)
+      accepted[wi] = wtrace[(size_t)wi * kTraceLen + 2] < wtrace[(size_t)wi * kTraceLen] ? 1 : 0;
   if (first_bad >= 0) {
     const DevStatus& b = hs[first_bad];
     if (b.code == VI_ENOTPD)
@@ -826,43 +918,6 @@ vi_status warm_windows(vi_ctx* ctx, int32_t n_windows, const vi_window* windows,
   return refresh_windows(ctx, wins);
 }
 
-// canvas of the warm start: the largest cell grid of the windows
-void warm_canvas(const std::vector<WinIn>& wins, int* hq, int* wq) {
-  *hq = 1;
-  *wq = 1;
-  for (const WinIn& in : wins) {
-    *hq = std::max(*hq, (in.cam->H + 3) / 4);
-    *wq = std::max(*wq, (in.cam->W + 3) / 4);
-  }
-}
-
-// the warm start's own buffers, after the solver's workspace
-struct WarmWork {
-  float* feat;
-  int32_t* dims;
-  float* dd;
-  float* db;
-  double* saved_d;
-  double* saved_b;
-};
-
-WarmWork warm_carve(const Plan& P, int hq, int wq, void* base, size_t* bytes) {
-  size_t solve = 0;
-  do_carve(P, nullptr, &solve);
-  Carve c;
-  c.base = base ? (char*)base + solve : nullptr;
-  const size_t n = P.N, cells = (size_t)hq * wq;
-  WarmWork ww{};
-  ww.feat = c.take<float>(n * kWCin * cells);
-  ww.dims = c.take<int32_t>(n * 2);
-  ww.dd = c.take<float>(n * cells);
-  ww.db = c.take<float>(n * 6);
-  ww.saved_d = c.take<double>((size_t)P.pix_total);
-  ww.saved_b = c.take<double>(n * 6);
-  if (bytes) *bytes = solve + c.off;
-  return ww;
-}
-
 }  // namespace
 
 extern "C" {
@@ -887,73 +942,20 @@ size_t vi_warm_start_workspace_size(int32_t n_windows, const vi_window* windows,
 
 vi_status vi_warm_start(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,
                         const float* params, void* workspace, size_t workspace_bytes, int32_t* accepted) {
+  return vi_ba_solve_warm(ctx, n_windows, windows, opts, params, 0, workspace, workspace_bytes, accepted);
+}
+
+vi_status vi_ba_solve_warm(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,
+                           const float* params, int32_t iters, void* workspace, size_t workspace_bytes,
+                           int32_t* accepted) {
   if (!ctx) return VI_EINVAL;
   if (n_windows < 1 || !windows) return fail(ctx, VI_EINVAL, "need at least one window");
-  if (!params || !workspace) return fail(ctx, VI_EINVAL, "null argument");
-  if (((uintptr_t)workspace & 255) != 0) return fail(ctx, VI_EINVAL, "workspace must be 256-byte aligned");
-  vi_status s = check_opts(ctx, opts);
-  if (s != VI_OK) return s;
   std::vector<WinIn> wins;
-  for (int w = 0; w < n_windows; ++w) {
+  for (int w = 0; w < n_windows; ++w)
     wins.push_back(WinIn{&windows[w].cam, &windows[w].state, &windows[w].edges, windows[w].imu, windows[w].report});
-    s = check_window(ctx, w, wins.back(), opts, true);
-    if (s != VI_OK) return s;
-  }
-  int hq, wq;
-  warm_canvas(wins, &hq, &wq);
-  if (hq > kWHQMax || wq > kWWQMax)
-    return fail(ctx, VI_EINVAL, "maps of up to %d x %d pixels only", 4 * kWHQMax, 4 * kWWQMax);
-  HIPCHK(ctx, hipSetDevice(ctx->device));
-  s = ensure_plan(ctx, wins);
-  if (s != VI_OK) return s;
-  Plan& P = ctx->plan;
-  size_t need = 0;
-  warm_carve(P, hq, wq, nullptr, &need);
-  if (workspace_bytes < need)
-    return fail(ctx, VI_ENOMEM, "workspace too small: %zu bytes given, %zu needed", workspace_bytes, need);
-  const Work w = do_carve(P, workspace, nullptr);
-  const WarmWork ww = warm_carve(P, hq, wq, workspace, nullptr);
-  s = refresh_windows(ctx, wins);
-  if (s != VI_OK) return s;
-  const DevPlan& D = ctx->dplan;
-  OptsDev od{opts->n_fixed, opts->use_imu ? 1 : 0, opts->bias_fixed ? 1 : 0, opts->precision, opts->lm_lambda,
-             opts->depth_eta, opts->z_min, opts->d_min};
-  if ((s = warm_begin(ctx)) != VI_OK) return s;
-  hipStream_t sp = ctx->priv;
-  launch_reset_status(sp, ctx->status, P.n_win);
-  if (od.use_imu) launch_imu_info(sp, P, D, w.Lam, ctx->status);
-  launch_final_cost(sp, P, D, w, od, 0);                                   // F at the initial state
-  launch_warm_state(sp, P, D, ww.saved_d, ww.saved_b, w.trace, 0);
-  launch_warm_features(sp, P, D, od, hq, wq, ww.feat, ww.dims);
-  launch_wnet_forward(sp, P.N, hq, wq, ww.dims, params, ww.feat, nullptr, ww.dd, ww.db);
-  launch_warm_apply(sp, P, D, hq, wq, ww.dd, ww.db, opts->d_min);
-  launch_final_cost(sp, P, D, w, od, 1);                                   // F at the corrected state
-  launch_warm_state(sp, P, D, ww.saved_d, ww.saved_b, w.trace, 1);        // put back where F did not fall
-  std::vector<double> trace((size_t)P.n_win * kTraceLen);
-  std::vector<DevStatus> hs(P.n_win);
-  HIPCHK(ctx, hipMemcpyAsync(trace.data(), w.trace, sizeof(double) * trace.size(), hipMemcpyDeviceToHost, sp));
-  HIPCHK(ctx, hipMemcpyAsync(hs.data(), ctx->status, sizeof(DevStatus) * P.n_win, hipMemcpyDeviceToHost, sp));
-  s = warm_end(ctx);
-  if (s != VI_OK) return s;
-  for (int wi = 0; wi < P.n_win; ++wi) {
-    const double f0 = trace[(size_t)wi * kTraceLen], f1 = trace[(size_t)wi * kTraceLen + 2];
-    const bool ok = f1 < f0;
-    if (accepted) accepted[wi] = ok ? 1 : 0;
-    vi_report* rep = wins[wi].rep;
-    if (rep) {
-      rep->cost_before = f0;
-      rep->cost_after = ok ? f1 : f0;
-      rep->n_valid = (int64_t)trace[(size_t)wi * kTraceLen + (ok ? 3 : 1)];
-      rep->iters_done = 0;
-      if (rep->costs) {
-        rep->costs[0] = f0;
-        rep->costs[1] = f1;
-      }
-    }
-  }
-  for (int wi = 0; wi < P.n_win; ++wi)
-    if (hs[wi].code != 0) return fail(ctx, (vi_status)hs[wi].code, "window %d: device status %d", wi, hs[wi].code);
-  return VI_OK;
+  WarmArgs wa{params, 1, 1};
+  warm_canvas(wins, &wa.hq, &wa.wq);
+  return run(ctx, wins, opts, iters, workspace, workspace_bytes, &wa, accepted);
 }
 
 vi_status vi_warm_features(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts,

@@ -371,6 +371,17 @@ __device__ __forceinline__ void swz_to_acc(double4_t (&acc)[2][2], const double*
       for (int r = 0; r < 4; ++r) acc[bm][bn][r] = S[swz(16 * bm + kq + 4 * r, 16 * bn + mrow)];
 }
 
+// Workgroup barrier that waits only for this wave's LDS traffic: global stores
+// may still be in flight (for data that no other wave reads before a full
+// __syncthreads).  The empty asm statements keep the compiler from moving
+// memory operations across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); vmcnt and expcnt left at their maxima
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // global 32 x 32 tile -> swizzled LDS tile, all loads in flight at once (one wave)
 __device__ __forceinline__ void tile_to_swz(double* S, const double* M, size_t ld) {
   double4_t acc[2][2];
@@ -609,6 +620,14 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
     const int m = hi - b;                       // panel tiles below the diagonal
     const double* Lc = Li[b & 1];
     double* Pc = lds ? colbuf(b) : P;           // the panel of column b, swizzled
+    // global copy of L_bb^-1 (factored during the previous step) for the back-solve
+    if (b > 0 && wave == NW - 1) {
+#pragma unroll
+      for (int it = 0; it < 16; ++it) {
+        const int e = lane + 64 * it;
+        Lv[(size_t)b * NB * NB + e] = Lc[(e >> 5) * LD + (e & 31)];
+      }
+    }
     // panel: L_ib = A_ib L_bb^-T, b < i <= hi -> global (for the back-solve) and LDS
     for (int u = wave; u < m; u += NW) {
       const int i = b + 1 + u;
@@ -626,7 +645,8 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
       store_tile32(acc, Aib, npad);
       acc_to_swz(acc, Pu);                      // same wave, reads of Pu done: in-place is safe
     }
-    __syncthreads();
+    // the panel's global copy is read only by the back-solve (after full barriers)
+    lds_barrier();
     // forward substitution: s_i -= L_ib y_b (one thread per row of the panel)
     {
       const int u = tid >> 5, r = tid & 31;
@@ -653,12 +673,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
         double* Ln = Li[nb1 & 1];
         const int bad = factor_invert32(T, Ln, U);
         if (bad >= 0 && lane == 0 && NB * nb1 + bad < n) set_status(stall + w, VI_ENOTPD, NB * nb1 + bad);
-#pragma unroll
-        for (int it = 0; it < 16; ++it) {
-          const int e = lane + 64 * it;
-          Lv[(size_t)nb1 * NB * NB + e] = Ln[(e >> 5) * LD + (e & 31)];
-        }
-        fwd_block(Ln, yv + NB * nb1);
+        fwd_block(Ln, yv + NB * nb1);           // its global copy is written during the next step
       } else {
         // trailing update (i, j), b < j <= i <= hi, except (b+1, b+1); in LDS
         // mode also the copies of the next step's inputs that no update

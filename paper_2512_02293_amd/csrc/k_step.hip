@@ -805,16 +805,26 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
   // exactly symmetric, so only its a >= b entries are used: one writer per slot).
   const double* gp = gpart + D.gram_off[src];
   const size_t gstride = (size_t)ntiles * 256;
-  for (int i = tid; i < ntiles * 256; i += NT) {
-    const int t = i >> 8, e = i & 255;
-    int I = 0;
-    while ((I + 1) * (I + 2) / 2 <= t) ++I;
-    const int J = t - I * (I + 1) / 2;
-    const int a = 16 * I + (e >> 4), b = 16 * J + (e & 15);
-    if (a < nq && b < nq && a >= b) {
-      const double v = sum_partials<8>(gp + i, gstride, nkr);
-      Qs[a * nq + b] = v;
-      Qs[b * nq + a] = v;
+  const int nent = ntiles * 256;
+  // two entries per thread and pass: the partial loads of both are in flight together
+  for (int i0 = tid; i0 < nent; i0 += 2 * NT) {
+    const int i1 = min(i0 + NT, nent - 1);
+    const double v0 = sum_partials<16>(gp + i0, gstride, nkr);
+    const double v1 = sum_partials<16>(gp + i1, gstride, nkr);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = h ? i0 + NT : i0;
+      if (i >= nent) continue;
+      const int t = i >> 8, e = i & 255;
+      int I = 0;
+      while ((I + 1) * (I + 2) / 2 <= t) ++I;
+      const int J = t - I * (I + 1) / 2;
+      const int a = 16 * I + (e >> 4), b = 16 * J + (e & 15);
+      if (a < nq && b < nq && a >= b) {
+        const double v = h ? v1 : v0;
+        Qs[a * nq + b] = v;
+        Qs[b * nq + a] = v;
+      }
     }
   }
   for (int i = tid; i < k * 36; i += NT) {
@@ -826,11 +836,11 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
     if (rc < 9) Rj[s * 9 + rc] = Rjs[rc];
     const int a = min(r, c), b = max(r, c);
     const int q = a * 6 - a * (a - 1) / 2 + (b - a);
-    Hs[i] = sum_partials<8>(hpart + (size_t)(e0 + s) * nkr_max * 32 + q, 32, nkr);
+    Hs[i] = sum_partials<16>(hpart + (size_t)(e0 + s) * nkr_max * 32 + q, 32, nkr);
   }
   for (int i = tid; i < k * 6; i += NT) {
     const int s = i / 6;
-    gs[i] = sum_partials<8>(hpart + (size_t)(e0 + s) * nkr_max * 32 + 21 + i % 6, 32, nkr);
+    gs[i] = sum_partials<16>(hpart + (size_t)(e0 + s) * nkr_max * 32 + 21 + i % 6, 32, nkr);
   }
   __syncthreads();
   for (int i = tid; i < k * 6; i += NT) gs[i] -= Qs[ncol * nq + i];
@@ -982,10 +992,28 @@ __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, c
     if (coord_active(o, a, ra) && coord_active(o, b, cb)) {
       double bd = 0.0;
       if (ra < 6 && cb < 6) {
+        // the pair blocks of (a, b) in list order, eight gathers in flight
         const int p0 = poff[a * N + b], p1 = poff[a * N + b + 1];
-        for (int it = p0; it < p1; ++it) {
-          val += Z[D.pair_z[it] + ra * 6 + cb];
-          if (r == c) bd += ZB[D.pair_zb[it] + ra];
+        for (int it0 = p0; it0 < p1; it0 += 8) {
+          int iz[8], ib[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int it = min(it0 + u, p1 - 1);
+            iz[u] = D.pair_z[it];
+            ib[u] = D.pair_zb[it];
+          }
+          double vz[8], vb[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            vz[u] = Z[iz[u] + ra * 6 + cb];
+            vb[u] = (r == c) ? ZB[ib[u] + ra] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (it0 + u < p1) {
+              val += vz[u];
+              bd += vb[u];
+            }
         }
       }
       if (o.use_imu) {
@@ -1013,7 +1041,14 @@ __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, c
     if (coord_active(o, b, cb)) {
       if (cb < 6) {
         const int p0 = poff[b * N + b], p1 = poff[b * N + b + 1];
-        for (int it = p0; it < p1; ++it) val += ZV[D.pair_zb[it] + cb];
+        for (int it0 = p0; it0 < p1; it0 += 8) {
+          double v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) v[u] = ZV[D.pair_zb[min(it0 + u, p1 - 1)] + cb];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (it0 + u < p1) val += v[u];
+        }
       }
       if (o.use_imu) {
         if (b > 0) val += gw[(size_t)(b - 1) * 30 + 15 + cb];
@@ -1227,6 +1262,9 @@ __global__ void __launch_bounds__(256) k_cost_reduce(int ncost, int range_px, De
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256) k_warm_features(OptsDev o, DevPlan D, int HQ, int WQ, float* __restrict__ feat,
                                                        int* __restrict__ dims) {
+  // 16 canvas cells per workgroup, one thread per pixel of a cell (lane
+  // 16 c + j: cell c, pixel (j / 4, j % 4) of it); the cell sums are reduced
+  // over the 16 lanes of the cell in a fixed order
   __shared__ double rel_s[kMaxOutDegree * 12];
   __shared__ double rimu[15];
   const int src = blockIdx.y;
@@ -1246,50 +1284,56 @@ __global__ void __launch_bounds__(256) k_warm_features(OptsDev o, DevPlan D, int
   }
   __syncthreads();
   float* f = feat + (size_t)src * kWCin * npix;
-  const int p = blockIdx.x * 256 + tid;
-  if (p < npix) {
-    const int cy = p / WQ, cx = p % WQ;
-    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (cy < hq0 && cx < wq0) {
-      double sxr = 0.0, syr = 0.0, swx = 0.0, swy = 0.0, sd = 0.0, sg = 0.0, sh = 0.0;
-      int nc = 0;
-      for (int y = 4 * cy; y < min(4 * cy + 4, W.H); ++y)
-        for (int x = 4 * cx; x < min(4 * cx + 4, W.W); ++x) {
-          const int pix = y * W.W + x;
-          const double d = W.invdepth[(size_t)ls * W.HW + pix];
-          sd += d;
-          ++nc;
-          const double qx = ((double)x - W.cx) / W.fx, qy = ((double)y - W.cy) / W.fy;
-          for (int s2 = 0; s2 < k; ++s2) {
-            const int e = D.src_edges[e0 + s2];
-            PixEdge q;
-            pix_edge<double>(W, o, rel_s + s2 * 12, qx, qy, d, true, W.target, W.weight,
-                             (size_t)(e - W.e_base) * 2 * W.HW + pix, true, q);
-            sxr += q.wx * q.rx;
-            syr += q.wy * q.ry;
-            swx += q.wx;
-            swy += q.wy;
-            sg += q.wx * q.Jdx * q.rx + q.wy * q.Jdy * q.ry;
-            sh += q.wx * q.Jdx * q.Jdx + q.wy * q.Jdy * q.Jdy;
-          }
-        }
-      v[0] = sxr / (swx + 1e-6);
-      v[1] = syr / (swy + 1e-6);
-      v[2] = (swx + swy) / (2.0 * max(k, 1) * nc);
-      v[3] = sd / nc;
-      v[4] = -sg / (sh + 1e-6) / 0.2;
-      v[5] = log1p(sh / nc);
+  const int p = blockIdx.x * 16 + (tid >> 4), j = tid & 15;
+  const int cy = p / WQ, cx = p % WQ;
+  const bool cell_in = p < npix && cy < hq0 && cx < wq0;
+  const int y = 4 * cy + (j >> 2), x = 4 * cx + (j & 3);
+  // per pixel: sum_e w r (x, y), sum_e w (x, y), sum_e w J_d r, sum_e w J_d^2, d, pixel count
+  double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (cell_in && y < W.H && x < W.W) {
+    const int pix = y * W.W + x;
+    const double d = W.invdepth[(size_t)ls * W.HW + pix];
+    v[6] = d;
+    v[7] = 1.0;
+    const double qx = ((double)x - W.cx) / W.fx, qy = ((double)y - W.cy) / W.fy;
+    for (int s2 = 0; s2 < k; ++s2) {
+      const int e = D.src_edges[e0 + s2];
+      PixEdge q;
+      pix_edge<double>(W, o, rel_s + s2 * 12, qx, qy, d, true, W.target, W.weight,
+                       (size_t)(e - W.e_base) * 2 * W.HW + pix, true, q);
+      v[0] += q.wx * q.rx;
+      v[1] += q.wy * q.ry;
+      v[2] += q.wx;
+      v[3] += q.wy;
+      v[4] += q.wx * q.Jdx * q.rx + q.wy * q.Jdy * q.ry;
+      v[5] += q.wx * q.Jdx * q.Jdx + q.wy * q.Jdy * q.Jdy;
     }
-    for (int c = 0; c < 4; ++c) f[(size_t)c * npix + p] = (float)v[c];
-    f[(size_t)13 * npix + p] = (float)v[4];
-    f[(size_t)14 * npix + p] = (float)v[5];
+  }
+#pragma unroll
+  for (int m = 8; m >= 1; m >>= 1)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) v[c] += __shfl_xor(v[c], m);
+  if (j == 0 && p < npix) {
+    double out[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (cell_in) {
+      const double nc = v[7];
+      out[0] = v[0] / (v[2] + 1e-6);
+      out[1] = v[1] / (v[3] + 1e-6);
+      out[2] = (v[2] + v[3]) / (2.0 * max(k, 1) * nc);
+      out[3] = v[6] / nc;
+      out[4] = -v[4] / (v[5] + 1e-6) / 0.2;
+      out[5] = log1p(v[5] / nc);
+    }
+    const int ch[6] = {0, 1, 2, 3, 13, 14};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) f[(size_t)ch[c] * npix + p] = (float)out[c];
   }
   if (blockIdx.x == 0) {
     for (int e = tid; e < 9 * npix; e += 256) {
       const int c = e / npix, pp = e % npix;
-      const int cy = pp / WQ, cx = pp % WQ;
+      const int yy = pp / WQ, xx = pp % WQ;
       const double scale = c < 3 ? 100.0 : 10.0;
-      f[(size_t)(4 + c) * npix + pp] = (cy < hq0 && cx < wq0) ? (float)(rimu[c] * scale) : 0.0f;
+      f[(size_t)(4 + c) * npix + pp] = (yy < hq0 && xx < wq0) ? (float)(rimu[c] * scale) : 0.0f;
     }
   }
 }
@@ -1421,7 +1465,8 @@ void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, 
   done(kStBacksub);
 }
 
-void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o, int slot) {
+void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o, int slot,
+                       double* trace) {
   const int N = P.N;
   const int ncost = cost_slots(P);
   auto kvc = (o.precision == VI_PREC_MIXED) ? k_vis_cost<float> : k_vis_cost<double>;
@@ -1430,12 +1475,12 @@ void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Wor
   if (o.use_imu && P.F > 0)
     hipLaunchKernelGGL(k_imu_cost, dim3((P.F + 63) / 64), dim3(64), 0, s, P.F, D, w.Lam, w.icost);
   hipLaunchKernelGGL(k_cost_reduce, dim3(P.n_win), dim3(256), 0, s, ncost, kVisBlock, D, w.vcost, w.icost,
-                     o.use_imu, w.trace, slot);
+                     o.use_imu, trace ? trace : w.trace, slot);
 }
 
 void launch_warm_features(hipStream_t s, const Plan& P, const DevPlan& D, const OptsDev& o, int HQ, int WQ,
                           float* feat, int* dims) {
-  hipLaunchKernelGGL(k_warm_features, dim3((HQ * WQ + 255) / 256, P.N), dim3(256), 0, s, o, D, HQ, WQ, feat, dims);
+  hipLaunchKernelGGL(k_warm_features, dim3((HQ * WQ + 15) / 16, P.N), dim3(256), 0, s, o, D, HQ, WQ, feat, dims);
 }
 
 void launch_warm_apply(hipStream_t s, const Plan& P, const DevPlan& D, int HQ, int WQ, const float* dd,

@@ -69,12 +69,26 @@ __device__ __forceinline__ void zero_canvas(__bf16* c, int ncell) {
 __device__ void load_weights(__bf16* Wl, const float* W, int cout, int cin, int kpad, int KP, bool transpose) {
   const int rows = transpose ? cin : cout;
   const int rin = transpose ? cout : cin;      // real channels of the K axis
-  for (int e = threadIdx.x; e < rows * KP; e += kThreads) {
-    const int n = e / KP, k = e % KP;
-    const int tap = k / kpad, c = k % kpad;
-    float v = 0.0f;
-    if (tap < 9 && c < rin) v = transpose ? W[(c * cin + n) * 9 + (8 - tap)] : W[(n * cin + c) * 9 + tap];
-    Wl[n * (KP + 8) + k] = (__bf16)v;
+  const int kshift = kpad == 16 ? 4 : 5;       // kpad is 16 or 32
+  // eight elements per thread and pass, their global loads in flight together
+  constexpr int U = 8;
+  const int total = rows * KP;
+  for (int e0 = threadIdx.x; e0 < total; e0 += U * kThreads) {
+    float v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kThreads;
+      const int n = e / KP, k = e - (e / KP) * KP;
+      const int tap = k >> kshift, c = k & (kpad - 1);
+      v[u] = 0.0f;
+      if (e < total && tap < 9 && c < rin)
+        v[u] = transpose ? W[(c * cin + n) * 9 + (8 - tap)] : W[(n * cin + c) * 9 + tap];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * kThreads;
+      if (e < total) Wl[(e / KP) * (KP + 8) + (e - (e / KP) * KP)] = (__bf16)v[u];
+    }
   }
 }
 
@@ -145,8 +159,10 @@ __global__ void __launch_bounds__(kThreads) k_wnet_forward(const float* __restri
   __bf16* Wl = cB + ncell * PS;                       // [32][296]
   __shared__ float bias[kWC];
   __shared__ float pool[kThreads];
+  __shared__ float wd[kWC * 9];                      // depth head, rounded to bf16
   const Canvas cv{HQ, WQ, dims[2 * img], dims[2 * img + 1]};
   const int npix = HQ * WQ;
+  for (int e = threadIdx.x; e < kWC * 9; e += kThreads) wd[e] = (float)(__bf16)theta[kOffWd + e];
   zero_canvas(cA, ncell);
   zero_canvas(cB, ncell);
   __syncthreads();
@@ -181,13 +197,14 @@ __global__ void __launch_bounds__(kThreads) k_wnet_forward(const float* __restri
     __bf16* t = in; in = out; out = t;
   }
   // heads on h4 (in): per-cell depth correction and pooled bias correction
-  const float* Wd = theta + kOffWd;
+  const float bd = theta[kOffBd];
   for (int p = threadIdx.x; p < npix; p += kThreads) {
     const int y = p / WQ, x = p % WQ;
-    float v = theta[kOffBd];
+    float v = bd;
     for (int tap = 0; tap < 9; ++tap) {
       const __bf16* h = in + cv.cell(y + tap / 3 - 1, x + tap % 3 - 1) * PS;
-      for (int c = 0; c < kWC; ++c) v += (float)(__bf16)Wd[c * 9 + tap] * (float)h[c];
+#pragma unroll
+      for (int c = 0; c < kWC; ++c) v += wd[c * 9 + tap] * (float)h[c];
     }
     dd[(size_t)img * npix + p] = cv.valid(p) ? v : 0.0f;
   }

@@ -151,7 +151,7 @@ void launch_tune_stages(hipStream_t s, const Plan& P, const DevPlan& D, const Wo
                         StageMark mark, void* mark_user);
 void launch_reset_status(hipStream_t s, DevStatus* st, int n);
 void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o,
-                       int slot);
+                       int slot, double* trace = nullptr);   // trace: w.trace unless given
 void launch_chol(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, DevStatus* st);
 void step_set_attributes(int kmax);
 // warm start

@@ -234,7 +234,9 @@ def time_to_tol(ctx, net, probs, opts, max_iters=REF_ITERS, rel_tol=1e-6, reps=3
         count of any window: K_plain vs warm start + K_warm iterations;
       * per window: each window alone, as a sliding-window solver runs it,
         k_plain(w) iterations vs warm start + k_warm(w) iterations, summed
-        over the windows."""
+        over the windows.
+    The warm path is one vi_ba_solve_warm call (warm start and GN in one
+    graph); the plain path one vi_ba_solve_batched call."""
     import torch
     dps, imus = _upload(ctx, probs)
     nb = max(ctx.workspace_size_batched(dps, opts), ctx.warm_start_workspace_size(dps, opts))
@@ -279,8 +281,7 @@ def time_to_tol(ctx, net, probs, opts, max_iters=REF_ITERS, rel_tol=1e-6, reps=3
             ctx.solve_batched(sel_d, sel_i, opts, k, ws)
 
     def warm(sel_d, sel_i, k):
-        ctx.warm_start(sel_d, sel_i, opts, net.params, ws)
-        gn(sel_d, sel_i, k)
+        ctx.solve_warm(sel_d, sel_i, opts, net.params, k, ws)
 
     t_batch_plain = timed(lambda: gn(dps, imus, K_plain))
     t_batch_warm = timed(lambda: warm(dps, imus, K_warm))

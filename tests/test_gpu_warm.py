@@ -205,3 +205,30 @@ def test_warm_start_keeps_or_puts_back(ctx):
             assert np.array_equal(a, b)
         assert np.array_equal(g[2], s0[2]) and np.array_equal(g[3], s0[3])
     assert n_acc >= 1
+
+
+def test_solve_warm_equals_warm_start_then_solve(ctx):
+    """vi_ba_solve_warm (warm start and GN in one graph) leaves the same state
+    and reports the same costs as vi_warm_start followed by vi_ba_solve_batched,
+    bit for bit, on two calls in a row (capture, then replay)."""
+    import torch
+    from paper_2512_02293_amd import binding, warmstart
+    probs = warmstart.eval_windows(4)
+    opts = warmstart.study_opts()
+    dps = [binding.DeviceProblem(p) for p in probs]
+    imus = [ctx.imu_preintegrate(d.off, d.gyro, d.accel, d.imu_dt, d.bias_hat, d.noise) for d in dps]
+    ws = torch.empty(ctx.warm_start_workspace_size(dps, opts), dtype=torch.uint8, device="cuda:0")
+    theta = _t(np.load(warmstart.PARAMS_FILE))
+    res = ctx.warm_start(dps, imus, opts, theta, ws)
+    reps = ctx.solve_batched(dps, imus, opts, 3, ws, costs=True)
+    ref = _state(dps)
+    for call in range(2):
+        for d in dps:
+            d.reset_state()
+        got = ctx.solve_warm(dps, imus, opts, theta, 3, ws, costs=True)
+        for r0, r1, g, s in zip(res, got, _state(dps), ref):
+            assert r1["accepted"] == r0["accepted"]
+            for a, b in zip(g, s):
+                assert np.array_equal(a, b)
+        for r, g in zip(reps, got):
+            assert np.array_equal(r["costs"], g["costs"]), (call, r["costs"], g["costs"])
