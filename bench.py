@@ -30,6 +30,25 @@ METRIC = "pixel-residuals/s + ms per GN iter (24-KF window); time-to-tol learned
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 GN_ITERS = 8
+# kernel behind each stage of the benchmarked window, and the committed HBM
+# counter readings (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a plain copy)
+STAGE_KERNEL = {"cholesky": "k_chol_small", "vis_gram_imu": "k_vis_gram<double>"}
+HBM_COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
+
+
+def measured_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the committed counter readings,
+    or None when there are none or the kernel's source changed since."""
+    import hashlib
+    try:
+        with open(HBM_COUNTERS) as fh:
+            rec = json.load(fh)["kernels"][kernel]
+        with open(os.path.join(ROOT, rec["source"]), "rb") as fh:
+            if hashlib.sha256(fh.read()).hexdigest() != rec["sha256"]:
+                return None
+        return float(rec["bytes_per_dispatch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -42,7 +61,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the 64-window batch and the warm-start time-to-tolerance lines")
+                    help="skip the 64-window batch, the global problem and the warm-start lines")
+    ap.add_argument("--only", choices=["global", "warm-windows"], default=None,
+                    help="run only that secondary workload and print its JSON (profiling runs)")
     return ap.parse_args()
 
 
@@ -68,8 +89,11 @@ def stage_models(prob):
                              work=gram_flops + 132.0 * E * HW, work_name="algorithmic_flops_per_launch",
                              per_unit="132 flops per pixel-residual + (6k+1)(6k+2) flops per source pixel",
                              hbm_bytes=float(E * HW * 16 + N * HW * 24)),
-        "cholesky": dict(bound="alu", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, scale=1e12, work=n ** 3 / 3.0,
-                         work_name="algorithmic_flops_per_launch", per_unit="n^3/3 flops, n = 15 N"),
+        "cholesky": dict(bound="mfma", unit="TFLOP/s", peak=FP64_PEAK_TFLOPS, scale=1e12, work=n ** 3 / 3.0,
+                         work_name="algorithmic_flops_per_launch", per_unit="n^3/3 flops, n = 15 N",
+                         note="one window is one 512-thread workgroup on one CU (FP64 MFMA peak of one CU: "
+                              "78.6/256 = 0.307 TFLOP/s); the factor's critical path is a chain of 32x32 "
+                              "diagonal-tile factorisations"),
     }
 
 
@@ -83,6 +107,12 @@ def main():
     import torch
 
     from paper_2512_02293_amd import binding, synth
+    if args.only is not None:
+        ctx = binding.Context(0)
+        out = global_problem(ctx) if args.only == "global" else warm_windows(ctx)
+        print(json.dumps(out))
+        ctx.close()
+        return
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
@@ -134,8 +164,11 @@ def main():
     m = models[key]
     achieved = m["work"] / (per_iter_ms[key] * 1e-3) / m["scale"]
     roof = {"bound": m["bound"], "achieved": achieved, "peak": m["peak"], "unit": m["unit"],
-            "frac": achieved / m["peak"], "traffic": None, "stage": key, "dominant_stage": dom,
-            "stage_ms": per_iter_ms[key], m["work_name"]: m["work"], "per_unit": m["per_unit"]}
+            "frac": achieved / m["peak"], "traffic": measured_traffic(STAGE_KERNEL.get(key, "")), "stage": key,
+            "kernel": STAGE_KERNEL.get(key), "dominant_stage": dom, "stage_ms": per_iter_ms[key],
+            m["work_name"]: m["work"], "per_unit": m["per_unit"]}
+    if "note" in m:
+        roof["note"] = m["note"]
     if "hbm_bytes" in m:
         roof["hbm_gbs_algorithmic"] = m["hbm_bytes"] / (per_iter_ms[key] * 1e-3) / 1e9
 
@@ -220,6 +253,7 @@ def extras(ctx):
                        "pixel_residuals_per_s": pxres / t_b, "ms_batch": 1e3 * t_b,
                        "ms_one_solve_per_window": 1e3 * t_s,
                        "note": "per-window solves include one graph capture per window shape"}}
+    res["global"] = global_problem(ctx)
     if os.path.exists(warmstart.PARAMS_FILE):
         net = warmstart.WarmNet.load(ctx)
         r = warmstart.time_to_tol(ctx, net, warmstart.eval_windows(), warmstart.study_opts())
@@ -237,6 +271,75 @@ def extras(ctx):
                     "window solved alone (sliding-window use), warm start = vi_warm_start (features, network, "
                     "corrections, cost check and device-side fallback) + GN"}
     return res
+
+
+def global_problem(ctx, iters=2, reps=3):
+    """The 512-keyframe problem (config_global, seed 3): GN iterations in FP64
+    and in mixed precision, graph-replayed, plus per-stage GPU times of one
+    eager step each."""
+    import torch
+
+    from paper_2512_02293_amd import binding, synth
+    prob = synth.make_problem(synth.config_global(), 3)
+    dp = binding.DeviceProblem(prob)
+    imu = ctx.imu_preintegrate(dp.off, dp.gyro, dp.accel, dp.imu_dt, dp.bias_hat, dp.noise)
+    res = {"workload": "512 keyframes, 60x80 maps, 5832 edges (11 nearest + 200 loop edges), reduced system "
+                       "7680 x 7680; GN iterations from the initial state"}
+    for name, prec in (("fp64", binding.VI_PREC_FP64), ("mixed", binding.VI_PREC_MIXED)):
+        o = binding.make_opts(precision=prec)
+        ws = torch.empty(ctx.workspace_size(dp.cam, prob.n_kf, dp.ii, dp.jj, o), dtype=torch.uint8, device="cuda:0")
+        st = None
+        for _ in range(2):
+            dp.reset_state()
+            st = ctx.solve(dp.cam, dp.pose, dp.vel, dp.bias, dp.invdepth, dp.ii, dp.jj, dp.target, dp.weight, imu, o,
+                           1, ws, stage_ms=True)["stage_ms"]
+        best = 1e30
+        for _ in range(reps + 1):
+            dp.reset_state()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.solve(dp.cam, dp.pose, dp.vel, dp.bias, dp.invdepth, dp.ii, dp.jj, dp.target, dp.weight, imu, o,
+                      iters, ws)
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t0)
+        res[name] = {"ms_per_gn_iter": 1e3 * best / iters,
+                     "pixel_residuals_per_s": prob.n_edges * prob.H * prob.W * iters / best,
+                     "stage_ms_one_step": {k: round(v, 4) for k, v in st.items()}}
+    return res
+
+
+def warm_windows(ctx, n=8, iters=5, reps=6):
+    """Eight windows of the warm-start study, each solved alone: iters GN
+    iterations plain, and the warm start followed by the same iterations."""
+    import numpy as np
+    import torch
+
+    from paper_2512_02293_amd import warmstart
+    probs = warmstart.eval_windows(n)
+    opts = warmstart.study_opts()
+    dps, imus = warmstart._upload(ctx, probs)
+    nb = max(ctx.warm_start_workspace_size([d], opts) for d in dps)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+    theta = torch.as_tensor(np.load(warmstart.PARAMS_FILE), device="cuda:0")
+    rows = []
+    for d, im in zip(dps, imus):
+        row = {"n_kf": int(d.pose.shape[0])}
+        for mode in ("plain", "warm"):
+            best = 1e30
+            for _ in range(reps):
+                d.reset_state()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if mode == "plain":
+                    ctx.solve_batched([d], [im], opts, iters, ws)
+                else:
+                    ctx.solve_warm([d], [im], opts, theta, iters, ws)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            row[f"ms_{mode}"] = 1e3 * best
+        rows.append(row)
+    return {"workload": f"{n} warm-start evaluation windows, each alone, {iters} GN iterations plain vs warm start "
+                        f"+ {iters} iterations", "windows": rows}
 
 
 def cpu_baseline(prob, iters):

@@ -19,7 +19,7 @@ using namespace vi;
 namespace {
 
 // candidate pixels-per-workgroup of the fused assembly (multiples of 64)
-const int kRanges[] = {128, 192, 256, 320, 448, 640};
+const int kRanges[] = {128, 192, 256, 320, 384, 448, 512, 640};
 constexpr int kRangeMin = 128;
 constexpr int kRangeDefault = 320;
 
