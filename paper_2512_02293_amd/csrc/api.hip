@@ -503,6 +503,7 @@ struct WarmWork {
   double* saved_d;
   double* saved_b;
   double* trace;       // [n_win][kTraceLen]: F at the initial (slot 0) and corrected (slot 1) state
+  void* wprep;         // the network's weights in their LDS layout
 };
 
 struct WarmArgs {
@@ -524,6 +525,7 @@ WarmWork warm_carve(const Plan& P, int hq, int wq, void* base, size_t* bytes) {
   ww.saved_d = c.take<double>((size_t)P.pix_total);
   ww.saved_b = c.take<double>(n * 6);
   ww.trace = c.take<double>((size_t)P.n_win * kTraceLen);
+  ww.wprep = c.take<char>(wnet_prep_bytes());
   if (bytes) *bytes = solve + c.off;
   return ww;
 }
@@ -535,7 +537,7 @@ void launch_warm_prologue(hipStream_t sp, const Plan& P, const DevPlan& D, const
   launch_final_cost(sp, P, D, w, od, 0, ww.trace);
   launch_warm_state(sp, P, D, ww.saved_d, ww.saved_b, ww.trace, 0);
   launch_warm_features(sp, P, D, od, wa.hq, wa.wq, ww.feat, ww.dims);
-  launch_wnet_forward(sp, P.N, wa.hq, wa.wq, ww.dims, wa.params, ww.feat, nullptr, ww.dd, ww.db);
+  launch_wnet_forward(sp, P.N, wa.hq, wa.wq, ww.dims, wa.params, ww.feat, nullptr, ww.dd, ww.db, ww.wprep);
   launch_warm_apply(sp, P, D, wa.hq, wa.wq, ww.dd, ww.db, od.d_min);
   launch_final_cost(sp, P, D, w, od, 1, ww.trace);
   launch_warm_state(sp, P, D, ww.saved_d, ww.saved_b, ww.trace, 1);

@@ -580,6 +580,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   __shared__ double Li[2][NB * LD];             // L_bb^-1 of the current and the next column
   __shared__ double U[16 * 17];
   __shared__ double yv[kSmallMaxNpad];          // right-hand side -> y = L^-1 s -> running rhs of L^T x = y
+  __shared__ int yready;                        // step b + 1 once rows of block b + 1 of yv are updated
   const int w = blockIdx.x;
   const WinDev& W = D.win[w];
   const int npad = W.npad, nblk = W.nblk, n = W.n;
@@ -614,14 +615,21 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   }
   __syncthreads();
   if (wave == 0) fwd_block(Li[0], yv);
+  if (tid == 0) yready = 0;
   __syncthreads();
+  // Wave roles: wave 0 carries the chain of diagonal factorisations; wave 4
+  // shares its SIMD and so takes only memory work (copies, the deferred global
+  // copy of L_bb^-1, panel tiles beyond the seventh); the six other waves
+  // take the panel, the forward substitution and the trailing update.
+  const int pw = wave < 4 ? wave : (wave == 4 ? 7 : wave - 1);   // panel order: 0,1,2,3,5,6,7, then 4
+  const int cw = wave < 4 ? wave - 1 : wave - 2;                 // compute worker 0..5 (waves 1-3, 5-7)
   for (int b = 0; b < nblk; ++b) {
     const int hi = min(b + bw, nblk - 1);       // last block row of column b inside the band
     const int m = hi - b;                       // panel tiles below the diagonal
     const double* Lc = Li[b & 1];
     double* Pc = lds ? colbuf(b) : P;           // the panel of column b, swizzled
     // global copy of L_bb^-1 (factored during the previous step) for the back-solve
-    if (b > 0 && wave == NW - 1) {
+    if (b > 0 && wave == 4) {
 #pragma unroll
       for (int it = 0; it < 16; ++it) {
         const int e = lane + 64 * it;
@@ -629,7 +637,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
       }
     }
     // panel: L_ib = A_ib L_bb^-T, b < i <= hi -> global (for the back-solve) and LDS
-    for (int u = wave; u < m; u += NW) {
+    for (int u = pw; u < m; u += NW) {
       const int i = b + 1 + u;
       double4_t acc[2][2];
 #pragma unroll
@@ -647,15 +655,21 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
     }
     // the panel's global copy is read only by the back-solve (after full barriers)
     lds_barrier();
-    // forward substitution: s_i -= L_ib y_b (one thread per row of the panel)
-    {
-      const int u = tid >> 5, r = tid & 31;
-      if (u < m) {
+    // forward substitution: s_i -= L_ib y_b, one thread per row of the panel
+    // on the six compute waves; block b + 1 (wave 1) is flagged for wave 0
+    if (wave != 0 && wave != 4) {
+      const int t6 = cw * 64 + lane;
+      for (int u = t6 >> 5; u < m; u += 12) {
+        const int r = t6 & 31;
         const double* Pu = Pc + u * NB * NB;
         double v = 0.0;
 #pragma unroll
         for (int q = 0; q < NB; ++q) v += Pu[swz(r, q)] * yv[NB * b + q];
         yv[NB * (b + 1 + u) + r] -= v;
+      }
+      if (wave == 1) {
+        __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes are done
+        if (lane == 0) __hip_atomic_store(&yready, b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
     if (m > 0) {
@@ -673,6 +687,11 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
         double* Ln = Li[nb1 & 1];
         const int bad = factor_invert32(T, Ln, U);
         if (bad >= 0 && lane == 0 && NB * nb1 + bad < n) set_status(stall + w, VI_ENOTPD, NB * nb1 + bad);
+        // rows of block b + 1 of yv come from wave 1 (bounded wait; it never waits on this wave)
+        for (int spin = 0; spin < (1 << 22); ++spin) {
+          if (__hip_atomic_load(&yready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == b + 1) break;
+          __builtin_amdgcn_s_sleep(1);
+        }
         fwd_block(Ln, yv + NB * nb1);           // its global copy is written during the next step
       } else {
         // trailing update (i, j), b < j <= i <= hi, except (b+1, b+1); in LDS
@@ -682,16 +701,13 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
         const int hi1 = min(b + 1 + bw, nblk - 1);
         const bool cp_row = lds && hi1 > hi;                    // tile (hi1, b + 1), as given
         const bool cp_diag = lds && b + 2 < nblk && b + 2 > hi;  // tile (b + 2, b + 2), as given
-        const int njobs = ntri + (cp_row ? 1 : 0) + (cp_diag ? 1 : 0);
-        for (int u = wave; u < njobs; u += NW - 1) {
-          if (u >= ntri) {
-            if (cp_row && u == ntri)
-              tile_to_swz(colbuf(b + 1) + (hi1 - b - 2) * NB * NB, A + (size_t)(NB * hi1) * npad + NB * (b + 1),
-                          npad);
-            else
-              tile_to_swz(diagbuf(b + 2), A + (size_t)(NB * (b + 2)) * npad + NB * (b + 2), npad);
-            continue;
-          }
+        if (wave == 4) {
+          if (cp_row)
+            tile_to_swz(colbuf(b + 1) + (hi1 - b - 2) * NB * NB, A + (size_t)(NB * hi1) * npad + NB * (b + 1),
+                        npad);
+          if (cp_diag) tile_to_swz(diagbuf(b + 2), A + (size_t)(NB * (b + 2)) * npad + NB * (b + 2), npad);
+        }
+        for (int u = (wave == 4) ? ntri : 1 + cw; u < ntri; u += NW - 2) {
           int jj = 0, rem = u;
           while (rem >= m - jj) { rem -= m - jj; ++jj; }
           const int j = b + 1 + jj, i = j + rem;

@@ -92,6 +92,30 @@ __device__ void load_weights(__bf16* Wl, const float* W, int cout, int cin, int 
   }
 }
 
+// The forward weights of layer l (1..4) as they sit in LDS: [32][KP + 8] bf16
+// with KP = 160 for the first layer and 288 after; layers back to back.
+__host__ __device__ constexpr int prep_kp(int l) { return l == 1 ? 160 : 288; }
+__host__ __device__ constexpr int prep_off(int l) {
+  return l == 1 ? 0 : kWC * (prep_kp(1) + 8) + (l - 2) * kWC * (prep_kp(2) + 8);
+}
+
+// theta -> the four layers' LDS images (one workgroup per layer)
+__global__ void __launch_bounds__(kThreads) k_wnet_prep(const float* __restrict__ theta, __bf16* __restrict__ wprep) {
+  const int l = blockIdx.x + 1;
+  const int cin = l == 1 ? kWCin : kWC, kpad = l == 1 ? kWCinPad : kWC, KP = prep_kp(l);
+  const int kshift = kpad == 16 ? 4 : 5;
+  const int row = KP + 8, total = kWC * row;
+  const float* W = theta + w_off(l);
+  __bf16* out = wprep + prep_off(l);
+  for (int e = threadIdx.x; e < total; e += kThreads) {
+    const int n = e / row, k = e - n * row;
+    const int tap = k >> kshift, c = k & (kpad - 1);
+    float v = 0.0f;
+    if (k < KP && tap < 9 && c < cin) v = W[(n * cin + c) * 9 + tap];
+    out[e] = (__bf16)v;
+  }
+}
+
 // out[cell][o] = act(sum_k in[cell + tap][ci] W[o][k] + bias[o]) for the 16 * ntile
 // canvas cells; CIN = channels of the input canvas used on the K axis, COUT
 // (16 or 32) output channels.  bias may be null; relu applies max(., 0).
@@ -150,7 +174,7 @@ __device__ void conv_layer(const __bf16* in, __bf16* out, const __bf16* Wl, int 
 __global__ void __launch_bounds__(kThreads) k_wnet_forward(const float* __restrict__ theta, int HQ, int WQ,
                                                            const int* __restrict__ dims, const float* __restrict__ feat,
                                                            __bf16* __restrict__ act, float* __restrict__ dd,
-                                                           float* __restrict__ db) {
+                                                           float* __restrict__ db, const __bf16* __restrict__ wprep) {
   extern __shared__ char smem[];
   const int img = blockIdx.x;
   const int ncell = (HQ + 2) * (WQ + 2);
@@ -187,7 +211,15 @@ __global__ void __launch_bounds__(kThreads) k_wnet_forward(const float* __restri
   for (int l = 1; l <= kWLayers; ++l) {
     const int cin = l == 1 ? kWCin : kWC;
     const int KP = l == 1 ? 160 : 288;
-    load_weights(Wl, theta + w_off(l), kWC, cin, l == 1 ? kWCinPad : kWC, KP, false);
+    if (wprep) {
+      // the prepared LDS image: 16-byte copies, all in flight together
+      const uint4* src = (const uint4*)(wprep + prep_off(l));
+      uint4* dst = (uint4*)Wl;
+      const int n16 = kWC * (KP + 8) / 8;
+      for (int e = threadIdx.x; e < n16; e += kThreads) dst[e] = src[e];
+    } else {
+      load_weights(Wl, theta + w_off(l), kWC, cin, l == 1 ? kWCinPad : kWC, KP, false);
+    }
     for (int o = threadIdx.x; o < kWC; o += kThreads) bias[o] = theta[b_off(l) + o];
     __syncthreads();
     if (l == 1) conv_layer<kWCinPad, kWC>(in, out, Wl, KP, bias, cv, true);
@@ -476,10 +508,13 @@ void wnet_set_attributes() {
 }
 
 void launch_wnet_forward(hipStream_t s, int n, int HQ, int WQ, const int* dims, const float* theta, const float* feat,
-                         void* act, float* dd, float* db) {
+                         void* act, float* dd, float* db, void* wprep) {
+  if (wprep) hipLaunchKernelGGL(k_wnet_prep, dim3(kWLayers), dim3(kThreads), 0, s, theta, (__bf16*)wprep);
   hipLaunchKernelGGL(k_wnet_forward, dim3(n), dim3(kThreads), wnet_fwd_lds(HQ, WQ), s, theta, HQ, WQ, dims, feat,
-                     (__bf16*)act, dd, db);
+                     (__bf16*)act, dd, db, (const __bf16*)wprep);
 }
+
+size_t wnet_prep_bytes() { return sizeof(__bf16) * (size_t)prep_off(kWLayers + 1); }
 
 void launch_wnet_backward(hipStream_t s, int n, int HQ, int WQ, const int* dims, const float* theta, const void* act,
                           const float* dd, const float* db, const float* lab_dd, const float* lab_db, float nv,

@@ -156,8 +156,11 @@ void launch_chol(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, 
 void step_set_attributes(int kmax);
 // warm start
 void wnet_set_attributes();
+// wprep (optional device scratch of wnet_prep_bytes()): the layers' weights are
+// converted to their LDS image once per call instead of once per image
 void launch_wnet_forward(hipStream_t s, int n, int HQ, int WQ, const int* dims, const float* theta, const float* feat,
-                         void* act, float* dd, float* db);
+                         void* act, float* dd, float* db, void* wprep = nullptr);
+size_t wnet_prep_bytes();
 void launch_wnet_backward(hipStream_t s, int n, int HQ, int WQ, const int* dims, const float* theta, const void* act,
                           const float* dd, const float* db, const float* lab_dd, const float* lab_db, float nv,
                           float* g_dd, float* g_db, float* loss, float* partial, float* grads);
