@@ -371,14 +371,26 @@ __device__ __forceinline__ void swz_to_acc(double4_t (&acc)[2][2], const double*
       for (int r = 0; r < 4; ++r) acc[bm][bn][r] = S[swz(16 * bm + kq + 4 * r, 16 * bn + mrow)];
 }
 
-// Workgroup barrier that waits only for this wave's LDS traffic: global stores
-// may still be in flight (for data that no other wave reads before a full
-// __syncthreads).  The empty asm statements keep the compiler from moving
-// memory operations across it.
-__device__ __forceinline__ void lds_barrier() {
+// LDS flags between the waves of one workgroup.  LDS operations of a wave
+// complete in order, so a flag written after the wave's data writes have
+// completed is seen only after them, and reads issued after the flag was seen
+// return the new data.
+__device__ __forceinline__ void lds_publish(int* f, int v) {
   asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); vmcnt and expcnt left at their maxima
-  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_s_waitcnt(0xc07f);   // this wave's LDS writes are done
+  if ((threadIdx.x & 63) == 0) __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  asm volatile("" ::: "memory");
+}
+
+// Wait until *f == v in every active lane (f may differ between lanes); the
+// publishing waves never wait on the waiting one, so the wait ends; it is
+// bounded all the same.
+__device__ __forceinline__ void lds_wait(const int* f, int v) {
+  for (int spin = 0; spin < (1 << 22); ++spin) {
+    const bool pending = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != v;
+    if (__ballot(pending) == 0) break;
+    __builtin_amdgcn_s_sleep(1);
+  }
   asm volatile("" ::: "memory");
 }
 
@@ -581,6 +593,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   __shared__ double U[16 * 17];
   __shared__ double yv[kSmallMaxNpad];          // right-hand side -> y = L^-1 s -> running rhs of L^T x = y
   __shared__ int yready;                        // step b + 1 once rows of block b + 1 of yv are updated
+  __shared__ int pready[kPanelSlots];           // step b + 1 once panel tile u of column b is in LDS
   const int w = blockIdx.x;
   const WinDev& W = D.win[w];
   const int npad = W.npad, nblk = W.nblk, n = W.n;
@@ -616,6 +629,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   __syncthreads();
   if (wave == 0) fwd_block(Li[0], yv);
   if (tid == 0) yready = 0;
+  if (tid < kPanelSlots) pready[tid] = 0;
   __syncthreads();
   // Wave roles: wave 0 carries the chain of diagonal factorisations; wave 4
   // shares its SIMD and so takes only memory work (copies, the deferred global
@@ -652,25 +666,25 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
         mm32_abt(acc, Aib, npad, Lc, LD, 1.0);
       store_tile32(acc, Aib, npad);
       acc_to_swz(acc, Pu);                      // same wave, reads of Pu done: in-place is safe
+      lds_publish(&pready[u], b + 1);
     }
-    // the panel's global copy is read only by the back-solve (after full barriers)
-    lds_barrier();
+    // no barrier here: the look-ahead needs only its own panel tile, and the
+    // other consumers wait for the flags of the tiles they read (the panel's
+    // global copy is read only by the back-solve, after full barriers)
     // forward substitution: s_i -= L_ib y_b, one thread per row of the panel
     // on the six compute waves; block b + 1 (wave 1) is flagged for wave 0
     if (wave != 0 && wave != 4) {
       const int t6 = cw * 64 + lane;
       for (int u = t6 >> 5; u < m; u += 12) {
         const int r = t6 & 31;
+        lds_wait(&pready[u], b + 1);
         const double* Pu = Pc + u * NB * NB;
         double v = 0.0;
 #pragma unroll
         for (int q = 0; q < NB; ++q) v += Pu[swz(r, q)] * yv[NB * b + q];
         yv[NB * (b + 1 + u) + r] -= v;
       }
-      if (wave == 1) {
-        __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes are done
-        if (lane == 0) __hip_atomic_store(&yready, b + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
+      if (wave == 1) lds_publish(&yready, b + 1);
     }
     if (m > 0) {
       if (wave == 0) {
@@ -687,11 +701,8 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
         double* Ln = Li[nb1 & 1];
         const int bad = factor_invert32(T, Ln, U);
         if (bad >= 0 && lane == 0 && NB * nb1 + bad < n) set_status(stall + w, VI_ENOTPD, NB * nb1 + bad);
-        // rows of block b + 1 of yv come from wave 1 (bounded wait; it never waits on this wave)
-        for (int spin = 0; spin < (1 << 22); ++spin) {
-          if (__hip_atomic_load(&yready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) == b + 1) break;
-          __builtin_amdgcn_s_sleep(1);
-        }
+        // rows of block b + 1 of yv come from wave 1 (it never waits on this wave)
+        lds_wait(&yready, b + 1);
         fwd_block(Ln, yv + NB * nb1);           // its global copy is written during the next step
       } else {
         // trailing update (i, j), b < j <= i <= hi, except (b+1, b+1); in LDS
@@ -714,6 +725,8 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
           double4_t acc[2][2];
           double* Aij = A + (size_t)(NB * i) * npad + NB * j;
           load_tile32(acc, Aij, npad);
+          lds_wait(&pready[i - b - 1], b + 1);
+          lds_wait(&pready[j - b - 1], b + 1);
           mm32_abt_lds(acc, Pc + (i - b - 1) * NB * NB, Pc + (j - b - 1) * NB * NB, -1.0);
           if (lds && j == b + 1)
             acc_to_swz(acc, colbuf(b + 1) + (i - b - 2) * NB * NB);
