@@ -131,14 +131,16 @@ __device__ __forceinline__ void store16(double* M, int ld, double4_t v) {
   for (int r = 0; r < 4; ++r) M[(kq + 4 * r) * ld + mrow] = v[r];
 }
 
-// Cholesky factor L and inverse X = L^-1 of an 8x8 SPD block, computed by
-// every lane redundantly in registers (no cross-lane traffic at all); packed
-// lower-triangular storage, entry (i, j) at i (i + 1) / 2 + j.  Returns the
+// Cholesky factor L and inverse X = L^-1 of an 8x8 SPD block M (stride ld),
+// computed by every lane redundantly in registers (no cross-lane traffic;
+// packed lower-triangular storage, entry (i, j) at i (i + 1) / 2 + j); X is
+// written to D (stride ldd, zeros above the diagonal) by lane 0.  Returns the
 // first bad pivot or -1.
 __device__ __forceinline__ constexpr int tri8(int i, int j) { return i * (i + 1) / 2 + j; }
 
-__device__ __forceinline__ int leaf8(const double* M, int ld, double (&L)[36], double (&X)[36]) {
+__device__ __forceinline__ int leaf8_inv(const double* M, int ld, double* D, int ldd) {
   // right-looking, in place: L holds the partly reduced block until column j is final
+  double L[36];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
@@ -165,32 +167,29 @@ __device__ __forceinline__ int leaf8(const double* M, int ld, double (&L)[36], d
       for (int m = 1; m < 8; ++m)
         if (i > j && m > j && m <= i) L[tri8(i, m)] -= L[tri8(i, j)] * L[tri8(m, j)];
   }
+  // X = L^-1 column by column (forward substitution against e_c), each column
+  // written out as soon as it is known, so that only one column is live
+  const bool w0 = (threadIdx.x & 63) == 0;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
-    X[tri8(c, c)] = rv[c];
+    double x[8];
+    x[c] = rv[c];
 #pragma unroll
     for (int r = 1; r < 8; ++r) {
       if (r > c) {
         double v = 0.0;
 #pragma unroll
         for (int q = 0; q < 7; ++q)
-          if (q >= c && q < r) v += L[tri8(r, q)] * X[tri8(q, c)];
-        X[tri8(r, c)] = -v * rv[r];
+          if (q >= c && q < r) v += L[tri8(r, q)] * x[q];
+        x[r] = -v * rv[r];
       }
+    }
+    if (w0) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) D[r * ldd + c] = (r >= c) ? x[r] : 0.0;
     }
   }
   return bad;
-}
-
-// packed lower 8x8 (all lanes hold it) -> rows/columns of a padded LDS block,
-// zeros above the diagonal; written by lane 0
-__device__ __forceinline__ void put8(const double (&P)[36], double* D, int ld) {
-  if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-      for (int j = 0; j < 8; ++j) D[i * ld + j] = (j <= i) ? P[tri8(i, j)] : 0.0;
-  }
 }
 
 // One wave: inverse Cholesky factor of the 16x16 SPD block M (stride ld) into
@@ -201,9 +200,7 @@ __device__ __forceinline__ void put8(const double (&P)[36], double* D, int ld) {
 // Returns the first bad pivot (0..15) or -1.
 __device__ __forceinline__ int leaf16_factor_inverse(double* M, int ld, double* Mi, int ldi, double* S) {
   const int lane = threadIdx.x & 63, i = lane >> 3, j = lane & 7;
-  double L[36], X[36];
-  int bad = leaf8(M, ld, L, X);
-  put8(X, Mi, ldi);                                           // X11
+  int bad = leaf8_inv(M, ld, Mi, ldi);                        // X11
   // L21 = A21 X11^T (one entry per lane)
   {
     double v = 0.0;
@@ -218,9 +215,8 @@ __device__ __forceinline__ int leaf16_factor_inverse(double* M, int ld, double* 
     for (int q = 0; q < 8; ++q) v -= M[(8 + i) * ld + q] * M[(8 + j) * ld + q];
     M[(8 + i) * ld + 8 + j] = v;
   }
-  const int bad2 = leaf8(M + 8 * ld + 8, ld, L, X);
+  const int bad2 = leaf8_inv(M + 8 * ld + 8, ld, Mi + 8 * ldi + 8, ldi);   // X22
   if (bad < 0 && bad2 >= 0) bad = 8 + bad2;
-  put8(X, Mi + 8 * ldi + 8, ldi);                             // X22
   // P = L21 X11 -> S, X21 = -X22 P, X12 = 0
   {
     double v = 0.0;
