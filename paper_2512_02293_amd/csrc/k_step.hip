@@ -760,7 +760,7 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ p, siz
   return s;
 }
 
-constexpr int kLocalThreads = 512;
+constexpr int kLocalThreads = 1024;
 
 __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int ncost, int range, DevPlan D,
                                                          const double* __restrict__ Rw, const double* __restrict__ rel,
