@@ -184,17 +184,39 @@ __global__ void __launch_bounds__(kThreads) k_wnet_forward(const float* __restri
   __shared__ float bias[kWC];
   __shared__ float pool[kThreads];
   __shared__ float wd[kWC * 9];                      // depth head, rounded to bf16
+  __shared__ float wb[6 * kWC + 6];                  // bias head (Wb, bb)
   const Canvas cv{HQ, WQ, dims[2 * img], dims[2 * img + 1]};
   const int npix = HQ * WQ;
   for (int e = threadIdx.x; e < kWC * 9; e += kThreads) wd[e] = (float)(__bf16)theta[kOffWd + e];
-  zero_canvas(cA, ncell);
-  zero_canvas(cB, ncell);
+  for (int e = threadIdx.x; e < 6 * kWC + 6; e += kThreads) wb[e] = theta[kOffWb + e];
+  {
+    // only the border ring of the two canvases needs zeros: every interior
+    // cell is written (by the input planes, channels 0..15 of cA, and by each
+    // layer) before it is read
+    const int W2 = WQ + 2, nb = 2 * W2 + 2 * HQ;
+    for (int e = threadIdx.x; e < 2 * nb * PS; e += kThreads) {
+      const int cnv = e / (nb * PS), r = e % (nb * PS), b = r / PS, ch = r % PS;
+      const int cell = b < W2 ? b : (b < 2 * W2 ? (HQ + 1) * W2 + (b - W2)
+                                                 : (1 + (b - 2 * W2) / 2) * W2 + ((b - 2 * W2) & 1) * (WQ + 1));
+      (cnv ? cB : cA)[cell * PS + ch] = (__bf16)0.0f;
+    }
+  }
   __syncthreads();
   const float* f = feat + (size_t)img * kWCin * npix;
-  for (int e = threadIdx.x; e < kWCinPad * npix; e += kThreads) {
-    const int c = e / npix, p = e % npix;
-    const float v = (c < kWCin && cv.valid(p)) ? f[(size_t)c * npix + p] : 0.0f;
-    cA[cv.cell(p / WQ, p % WQ) * PS + c] = (__bf16)v;
+  {
+    // eight planes per pass, their loads in flight together
+    constexpr int U = 8;
+    for (int p = threadIdx.x; p < npix; p += kThreads) {
+      const bool ok = cv.valid(p);
+      const int cell = cv.cell(p / WQ, p % WQ) * PS;
+      for (int c0 = 0; c0 < kWCinPad; c0 += U) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = (c0 + u < kWCin && ok) ? f[(size_t)(c0 + u) * npix + p] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < U; ++u) cA[cell + c0 + u] = (__bf16)v[u];
+      }
+    }
   }
   __syncthreads();
   auto save = [&](const __bf16* c, int layer, int ch) {
@@ -242,22 +264,31 @@ __global__ void __launch_bounds__(kThreads) k_wnet_forward(const float* __restri
   }
   // pooled channel means: thread (c, part) sums a slice of the cells
   {
+    // cells p = part, part + P, ... with P = kThreads / 32, (y, x) stepped without divisions
+    constexpr int P = kThreads / 32;
     const int c = threadIdx.x & 31, part = threadIdx.x >> 5;
     float s = 0.0f;
-    for (int p = part; p < npix; p += kThreads / 32)
-      if (cv.valid(p)) s += (float)in[cv.cell(p / WQ, p % WQ) * PS + c];
+    int y = part / WQ, x = part % WQ;
+    for (int p = part; p < npix; p += P) {
+      if (y < cv.hq && x < cv.wq) s += (float)in[cv.cell(y, x) * PS + c];
+      x += P;
+      while (x >= WQ) { x -= WQ; ++y; }
+    }
     pool[threadIdx.x] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kWC) {
+    // channel means, summed over the parts in order
+    const int c = threadIdx.x;
+    float s = 0.0f;
+    for (int part = 0; part < kThreads / 32; ++part) s += pool[part * 32 + c];
+    wd[c] = s / (float)max(cv.hq * cv.wq, 1);         // the depth head's weights are no longer needed
   }
   __syncthreads();
   if (threadIdx.x < 6) {
     const int k = threadIdx.x;
-    const float cnt = (float)max(cv.hq * cv.wq, 1);
-    float v = theta[kOffBb + k];
-    for (int c = 0; c < kWC; ++c) {
-      float s = 0.0f;
-      for (int part = 0; part < kThreads / 32; ++part) s += pool[part * 32 + c];
-      v += theta[kOffWb + k * kWC + c] * (s / cnt);
-    }
+    float v = wb[6 * kWC + k];
+    for (int c = 0; c < kWC; ++c) v += wb[k * kWC + c] * wd[c];
     db[(size_t)img * 6 + k] = v;
   }
 }
