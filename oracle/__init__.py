@@ -17,9 +17,10 @@ Modules
   solve      one step (linearise, eliminate, solve, retract) and the iteration
   cnn        the learned warm-start network (features, forward, backward,
              AdamW), the reference of the warm-start kernels
+  gauss      the loop-closure update of a Gaussian map (Sec. 3.3, Eq. 7-8)
 
 Parity status per function is listed in each module header.  Every function
 here is pinned by a CPU test against something other than itself (closed
 forms, finite differences, a dense textbook solve, invariants).
 """
-from . import so3, preint, vision, imu, normal_eq, dense, solve, cnn  # noqa: F401
+from . import so3, preint, vision, imu, normal_eq, dense, solve, cnn, gauss  # noqa: F401

@@ -453,3 +453,83 @@ def tiny_config(n_kf: int = 3, H: int = 4, W: int = 5, k_out: int = 2,
     """Tiny windows used for brute-force checks (finite differences, dense solves)."""
     return SceneConfig(n_kf=n_kf, H=H, W=W, k_out=k_out, noiseless=noiseless,
                        zero_bias=zero_bias, kf_gap=kf_gap)
+
+
+# --------------------------------------------------------------------------
+# Gaussian map and a loop-closure pose correction (input of the map update)
+# --------------------------------------------------------------------------
+@dataclass
+class GaussianMap:
+    """A map of K Gaussians anchored to N keyframes, with the keyframe poses
+    before and after a loop-closure correction.  Means are world-frame FP32
+    [K][3]; covariances are the 6 upper-triangle entries (xx, xy, xz, yy, yz,
+    zz) in FP32 [K][6]; anchors are int32 [K]; poses are camera-to-world FP64
+    [N][7] (t, q xyzw); scale_change is FP64 [N]."""
+    mean: np.ndarray
+    cov: np.ndarray
+    anchor: np.ndarray
+    pose_pre: np.ndarray
+    pose_post: np.ndarray
+    scale_change: np.ndarray
+
+
+def make_gaussian_map(n_kf: int, per_kf: int, seed: int, H: int = 480, W: int = 640,
+                      reorder_frac: float = 0.05, chunk: int = 1 << 20) -> GaussianMap:
+    """Seeded map: keyframes on a loop of radius 2 m looking outwards; each
+    keyframe unprojects ``per_kf`` pixels at inverse depths in [0.2, 2] into
+    Gaussians whose axes follow the pixel footprint (a random orientation, scales
+    0.5..2 pixel footprints).  Gaussians are stored in keyframe order (as they
+    are created) with a fraction ``reorder_frac`` of positions permuted, as
+    pruning and densification leave them.  The loop-closure correction grows
+    along the trajectory: up to 3 degrees of rotation, 0.3 m of translation and a
+    scale change of up to 5 %, plus small per-keyframe noise."""
+    rng = np.random.default_rng(seed)
+    fx = fy = 0.8 * W
+    cx, cy = 0.5 * W, 0.5 * H
+    ang = 2 * np.pi * np.arange(n_kf) / max(n_kf, 1)
+    t_pre = np.stack([2.0 * np.cos(ang), 2.0 * np.sin(ang), 0.1 * np.sin(3 * ang)], 1)
+    # camera z axis points outwards (yaw ang), small roll/pitch wobble
+    yaw = _quat_from_rotvec(np.stack([np.zeros(n_kf), np.zeros(n_kf), ang], 1))
+    tilt = _quat_from_rotvec(np.stack([0.5 * np.pi + 0.05 * rng.normal(size=n_kf),
+                                       0.05 * rng.normal(size=n_kf), np.zeros(n_kf)], 1))
+    q_pre = _qmul(yaw, _qmul(_quat_from_rotvec(np.tile([0.0, 0.5 * np.pi, 0.0], (n_kf, 1))), tilt))
+    frac = np.arange(n_kf) / max(n_kf - 1, 1)
+    corr_axis = _unit(rng, 1)[0]
+    dq = _quat_from_rotvec(np.deg2rad(3.0) * frac[:, None] * corr_axis + 1e-3 * rng.normal(size=(n_kf, 3)))
+    q_post = _qmul(dq, q_pre)
+    t_post = t_pre + 0.3 * frac[:, None] * _unit(rng, 1)[0] + 0.005 * rng.normal(size=(n_kf, 3))
+    scale_change = np.exp(np.log(1.05) * frac + 0.002 * rng.normal(size=n_kf))
+    pose_pre = np.concatenate([t_pre, q_pre], 1)
+    pose_post = np.concatenate([t_post, q_post], 1)
+
+    K = n_kf * per_kf
+    anchor = np.repeat(np.arange(n_kf, dtype=np.int32), per_kf)
+    if reorder_frac > 0 and K > 1:
+        pos = rng.choice(K, size=int(reorder_frac * K), replace=False)
+        anchor[pos] = anchor[rng.permutation(pos)]
+    mean = np.empty((K, 3), np.float32)
+    cov = np.empty((K, 6), np.float32)
+    Rk = _quat_to_mat(q_pre)
+    for s in range(0, K, chunk):
+        e = min(K, s + chunk)
+        n = e - s
+        a = anchor[s:e]
+        u = rng.uniform(0, W, n)
+        v = rng.uniform(0, H, n)
+        z = 1.0 / rng.uniform(0.2, 2.0, n)
+        xc = np.stack([(u - cx) / fx * z, (v - cy) / fy * z, z], 1)
+        foot = z / fx
+        Ra = Rk.reshape(n_kf, 9)[a]
+        for r in range(3):
+            mean[s:e, r] = Ra[:, 3 * r] * xc[:, 0] + Ra[:, 3 * r + 1] * xc[:, 1] + Ra[:, 3 * r + 2] * xc[:, 2] + t_pre[a, r]
+        # Sigma = Q diag(sc^2) Q^T with Q the rotation of a random unit quaternion
+        qv = rng.normal(size=(4, n))
+        qv /= np.sqrt(np.sum(qv * qv, axis=0))
+        x, y, zq, w = qv
+        Q = [[1 - 2 * (y * y + zq * zq), 2 * (x * y - zq * w), 2 * (x * zq + y * w)],
+             [2 * (x * y + zq * w), 1 - 2 * (x * x + zq * zq), 2 * (y * zq - x * w)],
+             [2 * (x * zq - y * w), 2 * (y * zq + x * w), 1 - 2 * (x * x + y * y)]]
+        var = (foot[:, None] * rng.uniform(0.5, 2.0, (n, 3))) ** 2
+        for e6, (r, c) in enumerate(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))):
+            cov[s:e, e6] = Q[r][0] * Q[c][0] * var[:, 0] + Q[r][1] * Q[c][1] * var[:, 1] + Q[r][2] * Q[c][2] * var[:, 2]
+    return GaussianMap(mean, cov, anchor, pose_pre, pose_post, scale_change)
