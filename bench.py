@@ -33,6 +33,9 @@ GN_ITERS = 8
 # kernel behind each stage of the benchmarked window, and the committed HBM
 # counter readings (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a plain copy)
 STAGE_KERNEL = {"cholesky": "k_chol_small", "vis_gram_imu": "k_vis_gram<double>"}
+REANCHOR_KERNEL = "k_reanchor<true, true>"
+# Gaussian-map update: anchor 4 B + mean 12 B read and written + covariance 24 B read and written
+REANCHOR_BYTES_PER_GAUSSIAN = 4 + 2 * 12 + 2 * 24
 HBM_COUNTERS = os.path.join(ROOT, "profiles", "hbm_counters.json")
 
 
@@ -62,9 +65,22 @@ def parse():
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 64-window batch, the global problem and the warm-start lines")
-    ap.add_argument("--only", choices=["global", "warm-windows"], default=None,
+    ap.add_argument("--only", choices=["global", "warm-windows", "gaussian-reanchor"], default=None,
                     help="run only that secondary workload and print its JSON (profiling runs)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain copy of known size (256 MiB read + 256 MiB written per launch),
+    the reference that scales the HBM byte counters."""
+    import torch
+    src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)       # one elementwise kernel: 256 MiB read, 256 MiB written
+    torch.cuda.synchronize()
+    return {"kernel": "elementwise multiply by 1 (MulFunctor)", "read": src.numel() * 4, "write": dst.numel() * 4,
+            "launches": 3}
 
 
 def stage_models(prob):
@@ -109,7 +125,10 @@ def main():
     from paper_2512_02293_amd import binding, synth
     if args.only is not None:
         ctx = binding.Context(0)
-        out = global_problem(ctx) if args.only == "global" else warm_windows(ctx)
+        out = {"global": global_problem, "warm-windows": warm_windows,
+               "gaussian-reanchor": gaussian_reanchor}[args.only](ctx)
+        if args.copy_calibration:
+            out["copy_calibration_bytes"] = copy_calibration()
         print(json.dumps(out))
         ctx.close()
         return
@@ -194,14 +213,7 @@ def main():
         "roofline": roof,
     }
     if args.copy_calibration:
-        # a plain copy of known size: 256 MiB read + 256 MiB written per launch
-        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 1.0, out=dst)       # one elementwise kernel: 256 MiB read, 256 MiB written
-        torch.cuda.synchronize()
-        out["copy_calibration_bytes"] = {"kernel": "elementwise multiply by 1 (MulFunctor)",
-                                         "read": src.numel() * 4, "write": dst.numel() * 4, "launches": 3}
+        out["copy_calibration_bytes"] = copy_calibration()
     if not args.no_extras:
         out.update(extras(ctx))
     if not args.no_cpu_baseline:
@@ -254,6 +266,7 @@ def extras(ctx):
                        "ms_one_solve_per_window": 1e3 * t_s,
                        "note": "per-window solves include one graph capture per window shape"}}
     res["global"] = global_problem(ctx)
+    res["gaussian_reanchor"] = gaussian_reanchor(ctx)
     if os.path.exists(warmstart.PARAMS_FILE):
         net = warmstart.WarmNet.load(ctx)
         r = warmstart.time_to_tol(ctx, net, warmstart.eval_windows(), warmstart.study_opts())
@@ -306,6 +319,62 @@ def global_problem(ctx, iters=2, reps=3):
                      "pixel_residuals_per_s": prob.n_edges * prob.H * prob.W * iters / best,
                      "stage_ms_one_step": {k: round(v, 4) for k, v in st.items()}}
     return res
+
+
+def gaussian_reanchor(ctx, n_kf=512, per_kf=16384, reps=50):
+    """Loop-closure update of a Gaussian map (Eq. 7-8): 512 keyframes x 16384
+    Gaussians, FP32 means and covariances, out of place; GPU time per call from
+    HIP events on the context's stream (torch's current stream) around `reps`
+    back-to-back calls (queued behind a spin kernel, so that the GPU runs them
+    without host gaps), and the same for calls on an empty map (only the
+    per-keyframe table kernel runs), whose difference is the map kernel's time."""
+    import torch
+
+    from paper_2512_02293_amd import synth
+    g = synth.make_gaussian_map(n_kf, per_kf, 11)
+    dev = lambda a: torch.as_tensor(a, device="cuda:0")
+    pre, post, ds = dev(g.pose_pre), dev(g.pose_post), dev(g.scale_change)
+    anchor, mean, cov = dev(g.anchor), dev(g.mean), dev(g.cov)
+    mean_out, cov_out = torch.empty_like(mean), torch.empty_like(cov)
+    ws = torch.empty(ctx.reanchor_workspace_size(n_kf), dtype=torch.uint8, device="cuda:0")
+    K = int(anchor.shape[0])
+
+    def call():
+        ctx.gaussian_reanchor(pre, post, ds, anchor, mean, cov, mean_out, cov_out, ws)
+
+    def table_only():
+        ctx.gaussian_reanchor(pre, post, ds, anchor[:0], mean[:0], cov[:0], mean_out[:0], cov_out[:0], ws)
+
+    def per_call_ms(fn):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        # hold the stream with a spin kernel while the host queues every call, so
+        # that the events time back-to-back GPU work, not host launch overhead
+        torch.cuda._sleep(50_000_000)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms = per_call_ms(call)
+    ms_table = per_call_ms(table_only)
+    ms_map = ms - ms_table
+    alg = K * REANCHOR_BYTES_PER_GAUSSIAN
+    gbs = alg / (ms_map * 1e-3) / 1e9
+    return {"workload": f"Gaussian map update after a loop closure: {n_kf} keyframes x {per_kf} Gaussians "
+                        f"({K} total), FP32 means and 6-entry covariances, out of place",
+            "gaussians_per_s": K / (ms * 1e-3), "ms_per_call": ms, "ms_map_kernel": ms_map,
+            "ms_keyframe_table": ms_table,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(REANCHOR_KERNEL),
+                         "kernel": REANCHOR_KERNEL, "algorithmic_bytes_per_launch": alg,
+                         "per_unit": "76 B per Gaussian (anchor 4, mean 12 + 12, covariance 24 + 24)",
+                         "note": "map-kernel time = time per call minus time per call on an empty map (the "
+                                 "per-keyframe table kernel alone), both from HIP events on the context's stream"}}
 
 
 def warm_windows(ctx, n=8, iters=5, reps=6):

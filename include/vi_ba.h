@@ -338,6 +338,49 @@ vi_status vi_ba_solve_warm(vi_ctx* ctx, int32_t n_windows, const vi_window* wind
                            const float* params, int32_t iters, void* workspace, size_t workspace_bytes,
                            int32_t* accepted);
 
+/* ---------------------------------------------------------------------------
+ * Loop-closure update of a Gaussian map (Sec. 3.3, "Loop Closure Gaussian
+ * Update", Eq. 7-8).  After pose-graph bundle adjustment each keyframe k has
+ * its pose before (R-, t-) and after (R+, t+) the correction and a scale
+ * change ds_k.  A Gaussian created from keyframe k gets
+ *   mean  <- R+ (ds_k (R-)^T (mean - t-)) + t+              (Eq. 7)
+ *   Sigma <- R+ (ds_k^2 (R-)^T Sigma R-) (R+)^T              (Eq. 8)
+ * and keeps its opacity and colour (not touched here).  Poses are camera-to-
+ * world (t, q xyzw) as 7 doubles, the quaternion normalised before use.  The
+ * update is evaluated as the per-keyframe similarity x -> A x + b with
+ * A = ds_k R+ (R-)^T and b = t+ - A t-, folded in FP64 and applied in FP32. */
+typedef struct {
+  int64_t n;                 /* number of Gaussians K >= 0 */
+  const int32_t* anchor;     /* device [K]: keyframe each Gaussian was created from */
+  const float* mean_in;      /* device [K][3] world-frame means */
+  const float* cov_in;       /* device [K][6] (xx, xy, xz, yy, yz, zz), or NULL: means only */
+  float* mean_out;           /* device [K][3]; equal to mean_in (in place) or not overlapping it */
+  float* cov_out;            /* device [K][6]; NULL iff cov_in is NULL; in place or disjoint */
+} vi_gaussians;
+
+/* Device workspace (bytes) of vi_gaussian_reanchor for n_kf keyframes (48 per
+ * keyframe, rounded up to 256). */
+size_t vi_reanchor_workspace_size(int32_t n_kf);
+
+/* Apply Eq. 7-8 to every Gaussian of *g.
+ *   pose_pre, pose_post  device [n_kf][7] poses before / after the correction
+ *   scale_change         device [n_kf] ds_k
+ *   workspace            device, 16-byte aligned, >= vi_reanchor_workspace_size(n_kf)
+ *   n_rejected           optional device int32: set to the number of Gaussians left
+ *                        unchanged (copied to the outputs as they are) because their
+ *                        anchor is outside 0..n_kf-1 or their keyframe's update is not
+ *                        valid (ds_k not positive and finite, a pose not finite, a zero
+ *                        quaternion)
+ * Asynchronous on the context's stream; the workspace and outputs must not be
+ * reused before the stream reaches this work.  Vector (16-byte) memory access
+ * is used when all arrays are 16-byte aligned, element access otherwise.
+ * Errors (host checks, nothing launched): VI_EINVAL (n_kf < 1, K < 0, null
+ * arrays, cov_in / cov_out not both given, an output that partly overlaps its
+ * input), VI_ENOMEM (workspace too small), VI_EDEVICE. */
+vi_status vi_gaussian_reanchor(vi_ctx* ctx, int32_t n_kf, const double* pose_pre, const double* pose_post,
+                               const double* scale_change, const vi_gaussians* g, void* workspace,
+                               size_t workspace_bytes, int32_t* n_rejected);
+
 #ifdef __cplusplus
 }
 #endif

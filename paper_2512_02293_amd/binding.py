@@ -66,11 +66,17 @@ class Window(C.Structure):
                 ("report", C.POINTER(Report))]
 
 
+class Gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("anchor", C.c_void_p), ("mean_in", C.c_void_p), ("cov_in", C.c_void_p),
+                ("mean_out", C.c_void_p), ("cov_out", C.c_void_p)]
+
+
 EXPORTS = ["vi_ctx_create", "vi_ctx_destroy", "vi_ctx_set_stream", "vi_last_error", "vi_version",
            "imu_preintegrate", "vi_workspace_size", "vi_ba_step", "vi_ba_solve", "vi_workspace_size_batched",
            "vi_ba_solve_batched", "vi_ctx_set_autotune", "vi_warm_param_count", "vi_warm_workspace_size",
            "vi_warm_features", "vi_warm_forward", "vi_warm_gradients", "vi_warm_adamw", "vi_warm_apply",
-           "vi_warm_start_workspace_size", "vi_warm_start", "vi_ba_solve_warm"]
+           "vi_warm_start_workspace_size", "vi_warm_start", "vi_ba_solve_warm", "vi_reanchor_workspace_size",
+           "vi_gaussian_reanchor"]
 
 _lib = None
 
@@ -131,6 +137,10 @@ def load(path: str = LIB_PATH):
     lib.vi_warm_start_workspace_size.restype = C.c_size_t
     lib.vi_warm_start.argtypes = [vp, i32, C.POINTER(Window), C.POINTER(Opts), vp, vp, C.c_size_t, vp]
     lib.vi_warm_start.restype = C.c_int
+    lib.vi_reanchor_workspace_size.argtypes = [i32]
+    lib.vi_reanchor_workspace_size.restype = C.c_size_t
+    lib.vi_gaussian_reanchor.argtypes = [vp, i32, vp, vp, vp, C.POINTER(Gaussians), vp, C.c_size_t, vp]
+    lib.vi_gaussian_reanchor.restype = C.c_int
     lib.vi_ba_solve_warm.argtypes = [vp, i32, C.POINTER(Window), C.POINTER(Opts), vp, i32, vp, C.c_size_t, vp]
     lib.vi_ba_solve_warm.restype = C.c_int
     _lib = lib
@@ -361,6 +371,39 @@ class Context:
                                                _ptr(label_dd), _ptr(label_db), float(n_valid), _ptr(workspace),
                                                workspace.numel(), _ptr(grads), C.byref(loss)))
         return float(loss.value), grads
+
+    def reanchor_workspace_size(self, n_kf: int) -> int:
+        return int(self.lib.vi_reanchor_workspace_size(int(n_kf)))
+
+    def gaussian_reanchor(self, pose_pre, pose_post, scale_change, anchor, mean_in, cov_in=None, mean_out=None,
+                          cov_out=None, ws=None, n_rejected=None):
+        """Loop-closure update of a Gaussian map (vi_gaussian_reanchor, Eq. 7-8).
+        Device tensors: poses float64 [N][7], scale_change float64 [N], anchor
+        int32 [K], means float32 [K][3], covariances float32 [K][6] (optional).
+        Outputs default to the inputs (in place).  Asynchronous on the context's
+        stream; n_rejected (device int32 [1], optional) receives the count of
+        Gaussians left unchanged."""
+        import torch
+        N = int(pose_pre.shape[0])
+        K = int(anchor.shape[0])
+        _check_dev(pose_pre, (N, 7), torch.float64, "pose_pre")
+        _check_dev(pose_post, (N, 7), torch.float64, "pose_post")
+        _check_dev(scale_change, (N,), torch.float64, "scale_change")
+        _check_dev(anchor, (K,), torch.int32, "anchor")
+        _check_dev(mean_in, (K, 3), torch.float32, "mean_in")
+        mean_out = mean_in if mean_out is None else mean_out
+        _check_dev(mean_out, (K, 3), torch.float32, "mean_out")
+        if cov_in is not None:
+            _check_dev(cov_in, (K, 6), torch.float32, "cov_in")
+            cov_out = cov_in if cov_out is None else cov_out
+            _check_dev(cov_out, (K, 6), torch.float32, "cov_out")
+        elif cov_out is not None:
+            raise ValueError("cov_out given without cov_in")
+        if ws is None:
+            ws = torch.empty(max(self.reanchor_workspace_size(N), 256), dtype=torch.uint8, device=mean_in.device)
+        g = Gaussians(K, _ptr(anchor), _ptr(mean_in), _ptr(cov_in), _ptr(mean_out), _ptr(cov_out))
+        self._check(self.lib.vi_gaussian_reanchor(self.h, N, _ptr(pose_pre), _ptr(pose_post), _ptr(scale_change),
+                                                  C.byref(g), _ptr(ws), ws.numel(), _ptr(n_rejected)))
 
     def warm_adamw(self, params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4):
         self._check(self.lib.vi_warm_adamw(self.h, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(t), float(lr),

@@ -1051,4 +1051,40 @@ vi_status vi_warm_apply(vi_ctx* ctx, int32_t n_windows, const vi_window* windows
   return warm_end(ctx);
 }
 
+size_t vi_reanchor_workspace_size(int32_t n_kf) { return n_kf > 0 ? align256(reanchor_table_bytes(n_kf)) : 0; }
+
+vi_status vi_gaussian_reanchor(vi_ctx* ctx, int32_t n_kf, const double* pose_pre, const double* pose_post,
+                               const double* scale_change, const vi_gaussians* g, void* workspace,
+                               size_t workspace_bytes, int32_t* n_rejected) {
+  if (!ctx) return VI_EINVAL;
+  if (!g || !pose_pre || !pose_post || !scale_change || !workspace) return fail(ctx, VI_EINVAL, "null argument");
+  if (n_kf < 1) return fail(ctx, VI_EINVAL, "need at least one keyframe");
+  const int64_t K = g->n;
+  if (K < 0 || K > reanchor_max_gaussians()) return fail(ctx, VI_EINVAL, "bad Gaussian count %lld", (long long)K);
+  if ((g->cov_in == nullptr) != (g->cov_out == nullptr))
+    return fail(ctx, VI_EINVAL, "cov_in and cov_out must both be given or both be NULL");
+  if (K > 0 && (!g->anchor || !g->mean_in || !g->mean_out)) return fail(ctx, VI_EINVAL, "null Gaussian array");
+  if (workspace_bytes < reanchor_table_bytes(n_kf)) return fail(ctx, VI_ENOMEM, "workspace too small");
+  if (((uintptr_t)workspace & 15) != 0) return fail(ctx, VI_EINVAL, "workspace must be 16-byte aligned");
+  // an output is either its input (in place) or disjoint from every input
+  struct Range { const char* p; size_t n; };
+  auto overlap = [](Range a, Range b) { return a.p < b.p + b.n && b.p < a.p + a.n; };
+  const Range mi{(const char*)g->mean_in, (size_t)K * 12}, mo{(const char*)g->mean_out, (size_t)K * 12};
+  const Range ci{(const char*)g->cov_in, g->cov_in ? (size_t)K * 24 : 0};
+  const Range co{(const char*)g->cov_out, g->cov_out ? (size_t)K * 24 : 0};
+  const Range an{(const char*)g->anchor, (size_t)K * 4};
+  if (K > 0) {
+    if (mo.p != mi.p && overlap(mo, mi)) return fail(ctx, VI_EINVAL, "mean_out partly overlaps mean_in");
+    if (co.n && co.p != ci.p && overlap(co, ci)) return fail(ctx, VI_EINVAL, "cov_out partly overlaps cov_in");
+    if (overlap(mo, an) || (co.n && (overlap(co, an) || overlap(co, mi) || overlap(co, mo) || overlap(mo, ci))))
+      return fail(ctx, VI_EINVAL, "an output overlaps another array");
+  }
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  launch_reanchor(ctx->user, n_kf, pose_pre, pose_post, scale_change, workspace, K, g->anchor, g->mean_in,
+                  g->cov_in, g->mean_out, g->cov_out, n_rejected);
+  HIPCHK(ctx, hipGetLastError());
+  ctx->err.clear();
+  return VI_OK;
+}
+
 }  // extern "C"

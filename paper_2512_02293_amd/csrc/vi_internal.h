@@ -164,6 +164,13 @@ size_t wnet_prep_bytes();
 void launch_wnet_backward(hipStream_t s, int n, int HQ, int WQ, const int* dims, const float* theta, const void* act,
                           const float* dd, const float* db, const float* lab_dd, const float* lab_db, float nv,
                           float* g_dd, float* g_db, float* loss, float* partial, float* grads);
+// loop-closure update of a Gaussian map (k_gauss.hip)
+size_t reanchor_table_bytes(int n_kf);
+int64_t reanchor_max_gaussians();
+void launch_reanchor(hipStream_t s, int n_kf, const double* pose_pre, const double* pose_post, const double* ds,
+                     void* table, int64_t K, const int32_t* anchor, const float* mean_in, const float* cov_in,
+                     float* mean_out, float* cov_out, int* n_rej);
+
 void launch_wnet_adamw(hipStream_t s, int P, float* theta, const float* g, float* m, float* v, int t, float lr,
                        float b1, float b2, float eps, float wd);
 void launch_warm_features(hipStream_t s, const Plan& P, const DevPlan& D, const OptsDev& o, int HQ, int WQ,

@@ -46,6 +46,7 @@ def test_struct_layouts_match_c():
       O(vi_camera, H) O(vi_camera, gravity) O(vi_preint, cov) O(vi_preint, cov_bias)
       O(vi_state, invdepth) O(vi_edges, weight) O(vi_opts, lm_lambda) O(vi_opts, d_min)
       O(vi_report, n_valid) O(vi_report, dxi) O(vi_report, stage_ms)
+      P(vi_gaussians) O(vi_gaussians, anchor) O(vi_gaussians, cov_out)
       return 0;
     }
     """
@@ -70,6 +71,8 @@ def test_struct_layouts_match_c():
         "vi_opts.lm_lambda": binding.Opts.lm_lambda.offset, "vi_opts.d_min": binding.Opts.d_min.offset,
         "vi_report.n_valid": binding.Report.n_valid.offset, "vi_report.dxi": binding.Report.dxi.offset,
         "vi_report.stage_ms": binding.Report.stage_ms.offset,
+        "vi_gaussians": C.sizeof(binding.Gaussians), "vi_gaussians.anchor": binding.Gaussians.anchor.offset,
+        "vi_gaussians.cov_out": binding.Gaussians.cov_out.offset,
     }
     assert got == py
 
@@ -102,3 +105,12 @@ def test_workspace_size_host_only():
     assert ws(1, [0], [0]) == 0                # too few keyframes
     many = list(range(1, 20))
     assert ws(20, [0] * 19, many) == 0         # out-degree above the supported maximum
+
+
+def test_reanchor_host_checks():
+    """vi_gaussian_reanchor rejects bad arguments on the host (nothing is
+    launched; the pointers are never dereferenced)."""
+    lib = binding.load()
+    assert lib.vi_reanchor_workspace_size(512) == 512 * 48
+    assert lib.vi_reanchor_workspace_size(3) == 256
+    assert lib.vi_reanchor_workspace_size(0) == 0
