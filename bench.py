@@ -65,7 +65,8 @@ def parse():
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 64-window batch, the global problem and the warm-start lines")
-    ap.add_argument("--only", choices=["global", "warm-windows", "gaussian-reanchor"], default=None,
+    ap.add_argument("--only", choices=["global", "warm-windows", "gaussian-reanchor", "predict-keyframe"],
+                    default=None,
                     help="run only that secondary workload and print its JSON (profiling runs)")
     return ap.parse_args()
 
@@ -125,8 +126,8 @@ def main():
     from paper_2512_02293_amd import binding, synth
     if args.only is not None:
         ctx = binding.Context(0)
-        out = {"global": global_problem, "warm-windows": warm_windows,
-               "gaussian-reanchor": gaussian_reanchor}[args.only](ctx)
+        out = {"global": global_problem, "warm-windows": warm_windows, "gaussian-reanchor": gaussian_reanchor,
+               "predict-keyframe": predict_keyframe}[args.only](ctx)
         if args.copy_calibration:
             out["copy_calibration_bytes"] = copy_calibration()
         print(json.dumps(out))
@@ -267,6 +268,7 @@ def extras(ctx):
                        "note": "per-window solves include one graph capture per window shape"}}
     res["global"] = global_problem(ctx)
     res["gaussian_reanchor"] = gaussian_reanchor(ctx)
+    res["predict_keyframe"] = predict_keyframe(ctx)
     if os.path.exists(warmstart.PARAMS_FILE):
         net = warmstart.WarmNet.load(ctx)
         r = warmstart.time_to_tol(ctx, net, warmstart.eval_windows(), warmstart.study_opts())
@@ -375,6 +377,38 @@ def gaussian_reanchor(ctx, n_kf=512, per_kf=16384, reps=50):
                          "per_unit": "76 B per Gaussian (anchor 4, mean 12 + 12, covariance 24 + 24)",
                          "note": "map-kernel time = time per call minus time per call on an empty map (the "
                                  "per-keyframe table kernel alone), both from HIP events on the context's stream"}}
+
+
+def predict_keyframe(ctx, n=64, reps=200):
+    """New-keyframe prediction from preintegration with the covariance-trace
+    fallback: one prediction for each of the 64 batched windows (its last
+    factor), GPU time per call from HIP events around back-to-back calls queued
+    behind a spin kernel."""
+    import torch
+
+    from paper_2512_02293_amd import binding, synth
+    probs = [synth.make_problem(synth.config_batched_window(w), 4000 + w) for w in range(n)]
+    dps = [binding.DeviceProblem(p) for p in probs]
+    imus = [ctx.imu_preintegrate(d.off, d.gyro, d.accel, d.imu_dt, d.bias_hat, d.noise) for d in dps]
+    imu = torch.stack([m[-1] for m in imus]).contiguous()
+    q0 = torch.stack([d.pose[-2] for d in dps]).contiguous()
+    v0 = torch.stack([d.vel[-2] for d in dps]).contiguous()
+    b0 = torch.stack([d.bias[-2] for d in dps]).contiguous()
+    g = probs[0].gravity
+    out = ctx.predict_keyframe(q0, v0, b0, imu, g)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda._sleep(50_000_000)
+    e0.record()
+    for _ in range(reps):
+        ctx.predict_keyframe(q0, v0, b0, imu, g, 1e-4, *out)
+    e1.record()
+    torch.cuda.synchronize()
+    us = 1e3 * e0.elapsed_time(e1) / reps
+    return {"workload": f"{n} new keyframes (the last factor of each batched window), FP64",
+            "us_per_call": us, "used_imu": int(out[3].sum().item()),
+            "roofline": {"bound": "latency", "note": "one lane per prediction (about 600 FP64 operations and "
+                                                     "1.4 KB of input each); the time is launch and memory latency"}}
 
 
 def warm_windows(ctx, n=8, iters=5, reps=6):

@@ -338,6 +338,32 @@ vi_status vi_ba_solve_warm(vi_ctx* ctx, int32_t n_windows, const vi_window* wind
                            const float* params, int32_t iters, void* workspace, size_t workspace_bytes,
                            int32_t* accepted);
 
+
+/* Initial state of new keyframes from IMU preintegration (Sec. 3.1, frontend
+ * tracking: the pose of a new keyframe is initialised by preintegration,
+ * falling back to the previous keyframe's pose when the trace of the factor's
+ * covariance exceeds a threshold; the experiments use 1e-4).  For each of n
+ * predictions k, with the state (R_i, p_i, v_i, b_i) of the previous keyframe
+ * and the factor imu[k] preintegrated from it to the new keyframe:
+ *   if tr(cov) + sum(cov_bias) <= tau (the trace of Sigma^iner):
+ *     dR~ = dR Exp(J_rot (b_g - bh_g)), dv~ = dv + J_vel (b - bh), dp~ = dp + J_pos (b - bh)
+ *     R_j = R_i dR~, v_j = v_i + g dt + R_i dv~, p_j = p_i + v_i dt + g dt^2 / 2 + R_i dp~, b_j = b_i
+ *     (the state at which the inertial residual of Eq. 3 is zero), used_imu[k] = 1;
+ *   otherwise (also when the trace is not a number): the new keyframe takes the
+ *     previous keyframe's pose, velocity and bias, used_imu[k] = 0.
+ *   pose_prev, vel_prev, bias_prev  device [n][7], [n][3], [n][6]
+ *   imu                             device [n] factors from the previous keyframe to the new one
+ *   gravity                         host [3], world frame (e.g. 0, 0, -9.81)
+ *   tau                             threshold >= 0 (1e-4 in the paper's experiments)
+ *   pose_new, vel_new, bias_new     device, same shapes; each equal to its input (in
+ *                                   place) or not overlapping any input
+ *   used_imu                        optional device [n] int32
+ * Asynchronous on the context's stream.  VI_EINVAL for n < 0, null arrays, a
+ * negative or NaN tau, or a partly overlapping output. */
+vi_status vi_predict_keyframe(vi_ctx* ctx, int32_t n, const double* pose_prev, const double* vel_prev,
+                              const double* bias_prev, const vi_preint* imu, const double* gravity, double tau,
+                              double* pose_new, double* vel_new, double* bias_new, int32_t* used_imu);
+
 /* ---------------------------------------------------------------------------
  * Loop-closure update of a Gaussian map (Sec. 3.3, "Loop Closure Gaussian
  * Update", Eq. 7-8).  After pose-graph bundle adjustment each keyframe k has

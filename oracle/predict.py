@@ -14,7 +14,7 @@ the bias b_i to first order (as in Eq. 3), then
 When the trace of the factor's covariance Sigma^iner (the 9x9 preintegration
 covariance and the 6 bias random-walk variances, blkdiag as in Eq. 3's
 information) exceeds tau, the new keyframe takes the previous keyframe's state
-instead.
+instead; a trace that is not a number counts as exceeding it.
 
 Pinned by (tests/test_oracle_predict.py): on noiseless, discrete-consistent
 data it reproduces the simulator's ground-truth state of keyframe j; the
@@ -37,7 +37,7 @@ def inertial_cov_trace(P):
 def predict(Ri, pi, vi, bi, P, g, tau=TAU_INIT):
     """-> (R_j, p_j, v_j, b_j, used_imu)."""
     Ri, pi, vi, bi = (np.asarray(a, dtype=np.float64) for a in (Ri, pi, vi, bi))
-    if inertial_cov_trace(P) > tau:
+    if not inertial_cov_trace(P) <= tau:
         return Ri.copy(), pi.copy(), vi.copy(), bi.copy(), False
     db = bi - P.bias_hat
     dR = P.dR @ Exp(P.J_rot @ db[:3])

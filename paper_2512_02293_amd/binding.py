@@ -76,7 +76,7 @@ EXPORTS = ["vi_ctx_create", "vi_ctx_destroy", "vi_ctx_set_stream", "vi_last_erro
            "vi_ba_solve_batched", "vi_ctx_set_autotune", "vi_warm_param_count", "vi_warm_workspace_size",
            "vi_warm_features", "vi_warm_forward", "vi_warm_gradients", "vi_warm_adamw", "vi_warm_apply",
            "vi_warm_start_workspace_size", "vi_warm_start", "vi_ba_solve_warm", "vi_reanchor_workspace_size",
-           "vi_gaussian_reanchor"]
+           "vi_gaussian_reanchor", "vi_predict_keyframe"]
 
 _lib = None
 
@@ -141,6 +141,9 @@ def load(path: str = LIB_PATH):
     lib.vi_reanchor_workspace_size.restype = C.c_size_t
     lib.vi_gaussian_reanchor.argtypes = [vp, i32, vp, vp, vp, C.POINTER(Gaussians), vp, C.c_size_t, vp]
     lib.vi_gaussian_reanchor.restype = C.c_int
+    lib.vi_predict_keyframe.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(C.c_double * 3), C.c_double, vp, vp, vp,
+                                        vp]
+    lib.vi_predict_keyframe.restype = C.c_int
     lib.vi_ba_solve_warm.argtypes = [vp, i32, C.POINTER(Window), C.POINTER(Opts), vp, i32, vp, C.c_size_t, vp]
     lib.vi_ba_solve_warm.restype = C.c_int
     _lib = lib
@@ -404,6 +407,33 @@ class Context:
         g = Gaussians(K, _ptr(anchor), _ptr(mean_in), _ptr(cov_in), _ptr(mean_out), _ptr(cov_out))
         self._check(self.lib.vi_gaussian_reanchor(self.h, N, _ptr(pose_pre), _ptr(pose_post), _ptr(scale_change),
                                                   C.byref(g), _ptr(ws), ws.numel(), _ptr(n_rejected)))
+
+    def predict_keyframe(self, pose_prev, vel_prev, bias_prev, imu, gravity, tau=1e-4, pose_new=None,
+                         vel_new=None, bias_new=None, used_imu=None):
+        """Initial state of new keyframes from preintegration (vi_predict_keyframe).
+        Device tensors float64 [n][7], [n][3], [n][6]; imu = float64 [n][154]
+        factors (as returned by imu_preintegrate); gravity = 3 host floats.
+        Returns (pose_new, vel_new, bias_new, used_imu), allocating what is not
+        given.  Asynchronous on the context's stream."""
+        import torch
+        n = int(pose_prev.shape[0])
+        _check_dev(pose_prev, (n, 7), torch.float64, "pose_prev")
+        _check_dev(vel_prev, (n, 3), torch.float64, "vel_prev")
+        _check_dev(bias_prev, (n, 6), torch.float64, "bias_prev")
+        _check_dev(imu, (n, PREINT_DOUBLES), torch.float64, "imu")
+        pose_new = torch.empty_like(pose_prev) if pose_new is None else pose_new
+        vel_new = torch.empty_like(vel_prev) if vel_new is None else vel_new
+        bias_new = torch.empty_like(bias_prev) if bias_new is None else bias_new
+        used_imu = torch.empty(n, dtype=torch.int32, device=pose_prev.device) if used_imu is None else used_imu
+        _check_dev(pose_new, (n, 7), torch.float64, "pose_new")
+        _check_dev(vel_new, (n, 3), torch.float64, "vel_new")
+        _check_dev(bias_new, (n, 6), torch.float64, "bias_new")
+        _check_dev(used_imu, (n,), torch.int32, "used_imu")
+        g = (C.c_double * 3)(*[float(x) for x in gravity])
+        self._check(self.lib.vi_predict_keyframe(self.h, n, _ptr(pose_prev), _ptr(vel_prev), _ptr(bias_prev),
+                                                 _ptr(imu), C.byref(g), float(tau), _ptr(pose_new), _ptr(vel_new),
+                                                 _ptr(bias_new), _ptr(used_imu)))
+        return pose_new, vel_new, bias_new, used_imu
 
     def warm_adamw(self, params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4):
         self._check(self.lib.vi_warm_adamw(self.h, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(t), float(lr),

@@ -1087,4 +1087,33 @@ vi_status vi_gaussian_reanchor(vi_ctx* ctx, int32_t n_kf, const double* pose_pre
   return VI_OK;
 }
 
+vi_status vi_predict_keyframe(vi_ctx* ctx, int32_t n, const double* pose_prev, const double* vel_prev,
+                              const double* bias_prev, const vi_preint* imu, const double* gravity, double tau,
+                              double* pose_new, double* vel_new, double* bias_new, int32_t* used_imu) {
+  if (!ctx) return VI_EINVAL;
+  if (n < 0) return fail(ctx, VI_EINVAL, "negative count");
+  if (!gravity) return fail(ctx, VI_EINVAL, "null gravity");
+  if (!(tau >= 0.0)) return fail(ctx, VI_EINVAL, "tau must be >= 0");
+  if (n > 0 && (!pose_prev || !vel_prev || !bias_prev || !imu || !pose_new || !vel_new || !bias_new))
+    return fail(ctx, VI_EINVAL, "null argument");
+  if (n > 0) {
+    struct Range { const char* p; size_t n; };
+    auto overlap = [](Range a, Range b) { return a.p < b.p + b.n && b.p < a.p + a.n; };
+    const Range in[4] = {{(const char*)pose_prev, 56u * n}, {(const char*)vel_prev, 24u * n},
+                         {(const char*)bias_prev, 48u * n}, {(const char*)imu, sizeof(vi_preint) * n}};
+    const Range out[4] = {{(const char*)pose_new, 56u * n}, {(const char*)vel_new, 24u * n},
+                          {(const char*)bias_new, 48u * n}, {(const char*)used_imu, used_imu ? 4u * n : 0u}};
+    for (int o = 0; o < 4; ++o)
+      for (int i = 0; i < 4; ++i)
+        if (out[o].n && !(o == i && out[o].p == in[i].p) && overlap(out[o], in[i]))
+          return fail(ctx, VI_EINVAL, "output %d overlaps input %d", o, i);
+  }
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  launch_predict_kf(ctx->user, n, pose_prev, vel_prev, bias_prev, imu, gravity, tau, pose_new, vel_new, bias_new,
+                    used_imu);
+  HIPCHK(ctx, hipGetLastError());
+  ctx->err.clear();
+  return VI_OK;
+}
+
 }  // extern "C"

@@ -245,6 +245,63 @@ __global__ void __launch_bounds__(64) k_imu_info(int F, DevPlan D, double* __res
   }
 }
 
+// Initial state of a new keyframe j from the state of keyframe i and the
+// factor preintegrated from i to j (Sec. 3.1, frontend tracking): the state
+// that zeroes the inertial residual of Eq. 3 (deltas corrected to the bias b_i
+// to first order), unless tr(Sigma^iner) (the 9x9 preintegration covariance
+// and the 6 bias random-walk variances) is above tau or not finite, in which
+// case keyframe j takes keyframe i's state.  One lane per prediction.
+__global__ void k_predict_kf(int n, const double* pose_i, const double* vel_i, const double* bias_i,
+                             const vi_preint* __restrict__ imu, double gx, double gy, double gz, double tau,
+                             double* pose_j, double* vel_j, double* bias_j, int32_t* used) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const vi_preint* P = imu + k;
+  double tr = 0.0;
+  for (int i = 0; i < 9; ++i) tr += P->cov[10 * i];
+  for (int i = 0; i < 6; ++i) tr += P->cov_bias[i];
+  double q[7], v[3], b[6];
+  for (int i = 0; i < 7; ++i) q[i] = pose_i[7 * k + i];
+  for (int i = 0; i < 3; ++i) v[i] = vel_i[3 * k + i];
+  for (int i = 0; i < 6; ++i) b[i] = bias_i[6 * k + i];
+  const bool use = tr <= tau;
+  if (use) {
+    double db[6], w[3], E[9], dRc[9], Ri[9], Rj[9], dv[3], dp[3], Rdv[3], Rdp[3];
+    for (int i = 0; i < 6; ++i) db[i] = b[i] - P->bias_hat[i];
+    m3_vec(P->J_rot, db, w);
+    so3_exp(w, E);
+    m3_mul(P->dR, E, dRc);
+    for (int r = 0; r < 3; ++r) {
+      double sv = P->dv[r], sp = P->dp[r];
+      for (int c = 0; c < 6; ++c) {
+        sv += P->J_vel[6 * r + c] * db[c];
+        sp += P->J_pos[6 * r + c] * db[c];
+      }
+      dv[r] = sv;
+      dp[r] = sp;
+    }
+    quat_to_rot(q + 3, Ri);
+    m3_mul(Ri, dRc, Rj);
+    m3_vec(Ri, dv, Rdv);
+    m3_vec(Ri, dp, Rdp);
+    const double g[3] = {gx, gy, gz}, dt = P->dt;
+    double pn[3], vn[3];
+    for (int r = 0; r < 3; ++r) {
+      vn[r] = v[r] + g[r] * dt + Rdv[r];
+      pn[r] = q[r] + v[r] * dt + 0.5 * g[r] * dt * dt + Rdp[r];
+    }
+    rot_to_quat(Rj, q + 3);
+    for (int r = 0; r < 3; ++r) {
+      q[r] = pn[r];
+      v[r] = vn[r];
+    }
+  }
+  for (int i = 0; i < 7; ++i) pose_j[7 * k + i] = q[i];
+  for (int i = 0; i < 3; ++i) vel_j[3 * k + i] = v[i];
+  for (int i = 0; i < 6; ++i) bias_j[6 * k + i] = b[i];
+  if (used) used[k] = use ? 1 : 0;
+}
+
 }  // namespace
 
 void launch_preint(hipStream_t s, int F, const int32_t* off, const double* gyro, const double* accel,
@@ -252,6 +309,14 @@ void launch_preint(hipStream_t s, int F, const int32_t* off, const double* gyro,
                    DevStatus* st) {
   if (F <= 0) return;
   hipLaunchKernelGGL(k_preint, dim3(F), dim3(64), 0, s, F, off, gyro, accel, dt, bias_hat, noise, out, st);
+}
+
+void launch_predict_kf(hipStream_t s, int n, const double* pose_i, const double* vel_i, const double* bias_i,
+                       const vi_preint* imu, const double* g, double tau, double* pose_j, double* vel_j,
+                       double* bias_j, int32_t* used) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_predict_kf, dim3((n + 63) / 64), dim3(64), 0, s, n, pose_i, vel_i, bias_i, imu, g[0], g[1],
+                     g[2], tau, pose_j, vel_j, bias_j, used);
 }
 
 void launch_imu_info(hipStream_t s, const Plan& P, const DevPlan& D, double* Lam, DevStatus* st) {

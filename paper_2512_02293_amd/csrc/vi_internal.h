@@ -140,6 +140,9 @@ void launch_preint(hipStream_t s, int F, const int32_t* off, const double* gyro,
                    const double* accel, const double* dt, const double* bias_hat,
                    vi_imu_noise noise, vi_preint* out, DevStatus* st);
 void launch_imu_info(hipStream_t s, const Plan& P, const DevPlan& D, double* Lam, DevStatus* st);
+void launch_predict_kf(hipStream_t s, int n, const double* pose_i, const double* vel_i, const double* bias_i,
+                       const vi_preint* imu, const double* g, double tau, double* pose_j, double* vel_j,
+                       double* bias_j, int32_t* used);
 // Stages of one step, for per-stage event timing.
 enum Stage { kStVis = 0, kStLocal, kStAssemble, kStChol, kStBacksub, kNumStages };
 // `mark`, when non-null, is called between stages (used to record timing events).

@@ -138,6 +138,30 @@ __device__ inline void quat_to_rot(const double* q, double* R) {
   R[6] = s * (x * z - y * w);       R[7] = s * (y * z + x * w);       R[8] = 1.0 - s * (x * x + y * y);
 }
 
+// Unit quaternion (x, y, z, w) of a rotation matrix, from the largest of
+// 1 + tr R, 1 + 2 R_00 - tr R, 1 + 2 R_11 - tr R, 1 + 2 R_22 - tr R (the
+// numerically safe pivot), normalised at the end.
+__device__ inline void rot_to_quat(const double* R, double* q) {
+  const double tr = R[0] + R[4] + R[8];
+  const double c[4] = {1.0 + tr, 1.0 + 2.0 * R[0] - tr, 1.0 + 2.0 * R[4] - tr, 1.0 + 2.0 * R[8] - tr};
+  int k = 0;
+  for (int i = 1; i < 4; ++i)
+    if (c[i] > c[k]) k = i;
+  const double s = 0.5 / sqrt(c[k]);   // 4 * (the pivot component) = 2 sqrt(c[k])
+  double x, y, z, w;
+  if (k == 0) {
+    w = 0.5 * sqrt(c[0]); x = (R[7] - R[5]) * s; y = (R[2] - R[6]) * s; z = (R[3] - R[1]) * s;
+  } else if (k == 1) {
+    x = 0.5 * sqrt(c[1]); w = (R[7] - R[5]) * s; y = (R[1] + R[3]) * s; z = (R[2] + R[6]) * s;
+  } else if (k == 2) {
+    y = 0.5 * sqrt(c[2]); w = (R[2] - R[6]) * s; x = (R[1] + R[3]) * s; z = (R[5] + R[7]) * s;
+  } else {
+    z = 0.5 * sqrt(c[3]); w = (R[3] - R[1]) * s; x = (R[2] + R[6]) * s; y = (R[5] + R[7]) * s;
+  }
+  const double n = 1.0 / sqrt(x * x + y * y + z * z + w * w);
+  q[0] = x * n; q[1] = y * n; q[2] = z * n; q[3] = w * n;
+}
+
 // q <- normalise(q (x) exp_q(w)): the quaternion form of R <- R Exp(w).
 __device__ inline void quat_retract(double* q, const double* w) {
   const double t2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
