@@ -20,9 +20,11 @@ Modules
   gauss      the loop-closure update of a Gaussian map (Sec. 3.3, Eq. 7-8)
   predict    a new keyframe's initial state from preintegration, with the
              covariance-trace fallback (Sec. 3.1, frontend tracking)
+  inertial_init  IMU initialisation stage 2, inertial-only optimisation of
+             gravity direction, log-scale, velocities and biases (Sec. 3.2)
 
 Parity status per function is listed in each module header.  Every function
 here is pinned by a CPU test against something other than itself (closed
 forms, finite differences, a dense textbook solve, invariants).
 """
-from . import so3, preint, vision, imu, normal_eq, dense, solve, cnn, gauss, predict  # noqa: F401
+from . import so3, preint, vision, imu, normal_eq, dense, solve, cnn, gauss, predict, inertial_init  # noqa: F401

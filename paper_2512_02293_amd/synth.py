@@ -533,3 +533,57 @@ def make_gaussian_map(n_kf: int, per_kf: int, seed: int, H: int = 480, W: int = 
         for e6, (r, c) in enumerate(((0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2))):
             cov[s:e, e6] = Q[r][0] * Q[c][0] * var[:, 0] + Q[r][1] * Q[c][1] * var[:, 1] + Q[r][2] * Q[c][2] * var[:, 2]
     return GaussianMap(mean, cov, anchor, pose_pre, pose_post, scale_change)
+
+
+# --------------------------------------------------------------------------
+# inertial-only initialisation: the window as a monocular visual front end
+# would see it (input of the IMU initialisation, stage 2)
+# --------------------------------------------------------------------------
+@dataclass
+class InertialInitProblem:
+    """Keyframe poses in an arbitrary visual frame at an unknown scale, the IMU
+    stream between the keyframes, and the truth the initialisation should
+    recover.  The visual frame w' is the gravity-aligned world frame rotated by
+    R_wg (true) and shrunk by e^-s (true): p^vis = e^-s R_wg p, R^vis = R_wg R,
+    v^vis = e^-s R_wg v; gravity in w' is R_wg (0, 0, -9.81)."""
+    pose_vis: np.ndarray      # (N, 7) (p^vis, q xyzw)
+    imu_off: np.ndarray
+    gyro: np.ndarray
+    accel: np.ndarray
+    imu_dt: np.ndarray
+    bias_hat: np.ndarray
+    noise: np.ndarray
+    R_wg: np.ndarray          # (3, 3) truth
+    s: float                  # truth
+    v_vis: np.ndarray         # (N, 3) truth
+    b: np.ndarray             # (N, 6) truth
+
+
+def make_inertial_init_problem(cfg: SceneConfig, seed: int, tilt_deg: float = 25.0, log_scale: float = 0.9,
+                               pose_noise: Tuple[float, float] = (0.0, 0.0),
+                               bias_hat_mode: str = "zero") -> InertialInitProblem:
+    """Window ``cfg`` (seed ``seed``) seen by a visual front end: its frame is
+    tilted by ``tilt_deg`` about a random horizontal axis (and turned by a random
+    yaw), its scale is e^-log_scale; ``pose_noise`` = (position std in m,
+    rotation std in degrees) of the visual poses' errors (metric, before the
+    scale change)."""
+    p = make_problem(cfg, seed, bias_hat_mode=bias_hat_mode)
+    rng = np.random.default_rng(seed + 7919)
+    axis = rng.normal(size=3)
+    axis[2] = 0.0
+    axis /= np.linalg.norm(axis)
+    q_tilt = _quat_from_rotvec(np.deg2rad(tilt_deg) * axis)
+    q_yaw = _quat_from_rotvec(np.array([0.0, 0.0, rng.uniform(-np.pi, np.pi)]))
+    q_vw = _qmul(q_tilt, q_yaw)
+    R_vw = _quat_to_mat(q_vw)
+    N = p.pose_gt.shape[0]
+    src = p.pose_gt.copy()
+    src[:, :3] += pose_noise[0] * rng.normal(size=(N, 3))
+    src[:, 3:7] = _qmul(src[:, 3:7], _quat_from_rotvec(np.deg2rad(pose_noise[1]) * rng.normal(size=(N, 3))))
+    shrink = np.exp(-log_scale)
+    pos = shrink * src[:, :3] @ R_vw.T
+    quat = _qmul(np.broadcast_to(q_vw, src[:, 3:7].shape), src[:, 3:7])
+    return InertialInitProblem(
+        pose_vis=np.concatenate([pos, quat], 1), imu_off=p.imu_off, gyro=p.gyro, accel=p.accel,
+        imu_dt=p.imu_dt, bias_hat=p.bias_hat, noise=p.noise, R_wg=R_vw, s=float(log_scale),
+        v_vis=shrink * p.vel_gt @ R_vw.T, b=p.bias_gt.copy())
