@@ -365,6 +365,43 @@ vi_status vi_predict_keyframe(vi_ctx* ctx, int32_t n, const double* pose_prev, c
                               double* pose_new, double* vel_new, double* bias_new, int32_t* used_imu);
 
 /* ---------------------------------------------------------------------------
+ * IMU initialisation, stage 2: inertial-only optimisation (Sec. 3.2, "Stage 2:
+ * Inertial-Only Optimization", and the IMU-initialisation paragraph of the
+ * implementation details).  The visual poses (R_i, p_i^vis) of the first
+ * keyframes, known up to scale, are held fixed; positions and velocities are
+ * e^s p_i^vis and e^s v_i^vis with a global log-scale s, gravity is
+ * g = R_wg (0, 0, G), and R_wg, s, every v_i^vis and every bias b_i minimise
+ * the inertial energy (Eq. 2, residuals as in Eq. 3 with these substitutions,
+ * information as for the step).  R_wg is perturbed on the right about the
+ * first two axes of the gravity frame (a turn about gravity is not
+ * observable); damping as for the step (H_rr += lm_lambda H_rr on all 3 + 9N
+ * unknowns); a fixed number of Gauss-Newton iterations. */
+typedef struct {
+  int32_t n_kf;              /* 2 <= N <= 32 keyframes */
+  const double* pose_vis;    /* device [N][7] visual poses (p^vis, q xyzw), fixed */
+  const vi_preint* imu;      /* device [N-1] factors (i, i+1) */
+  double* vel_vis;           /* device [N][3] velocities in the visual scale: initial guess in, estimate out */
+  double* bias;              /* device [N][6] (b_g, b_a): in / out */
+  double* rot_wg;            /* device [4] quaternion (x, y, z, w) of R_wg: in / out */
+  double* log_scale;         /* device [1] s: in / out */
+  double* cost;              /* optional device [iters + 1]: cost before each iteration and at the end */
+} vi_inertial_init;
+
+/* Device workspace (bytes) of vi_inertial_init_solve for these problems; 0 on
+ * invalid input. */
+size_t vi_inertial_init_workspace_size(int32_t n_problems, const vi_inertial_init* problems);
+
+/* `iters` (>= 0) iterations on every problem (host array of n_problems
+ * descriptors), one workgroup per problem in one launch.  gravity_z: G of
+ * g_I = (0, 0, G) (e.g. -9.81).  Synchronous.  Errors: VI_EINVAL (arguments),
+ * VI_ENOMEM (workspace too small), VI_ENOTPD (a non-positive-definite factor
+ * covariance or normal matrix), VI_ENONFINITE (non-finite cost); on error the
+ * state of the failing problem is left as it was. */
+vi_status vi_inertial_init_solve(vi_ctx* ctx, int32_t n_problems, const vi_inertial_init* problems,
+                                 double gravity_z, double lm_lambda, int32_t iters, void* workspace,
+                                 size_t workspace_bytes);
+
+/* ---------------------------------------------------------------------------
  * Loop-closure update of a Gaussian map (Sec. 3.3, "Loop Closure Gaussian
  * Update", Eq. 7-8).  After pose-graph bundle adjustment each keyframe k has
  * its pose before (R-, t-) and after (R+, t+) the correction and a scale

@@ -66,6 +66,11 @@ class Window(C.Structure):
                 ("report", C.POINTER(Report))]
 
 
+class InertialInit(C.Structure):
+    _fields_ = [("n_kf", C.c_int32), ("pose_vis", C.c_void_p), ("imu", C.c_void_p), ("vel_vis", C.c_void_p),
+                ("bias", C.c_void_p), ("rot_wg", C.c_void_p), ("log_scale", C.c_void_p), ("cost", C.c_void_p)]
+
+
 class Gaussians(C.Structure):
     _fields_ = [("n", C.c_int64), ("anchor", C.c_void_p), ("mean_in", C.c_void_p), ("cov_in", C.c_void_p),
                 ("mean_out", C.c_void_p), ("cov_out", C.c_void_p)]
@@ -76,7 +81,8 @@ EXPORTS = ["vi_ctx_create", "vi_ctx_destroy", "vi_ctx_set_stream", "vi_last_erro
            "vi_ba_solve_batched", "vi_ctx_set_autotune", "vi_warm_param_count", "vi_warm_workspace_size",
            "vi_warm_features", "vi_warm_forward", "vi_warm_gradients", "vi_warm_adamw", "vi_warm_apply",
            "vi_warm_start_workspace_size", "vi_warm_start", "vi_ba_solve_warm", "vi_reanchor_workspace_size",
-           "vi_gaussian_reanchor", "vi_predict_keyframe"]
+           "vi_gaussian_reanchor", "vi_predict_keyframe", "vi_inertial_init_workspace_size",
+           "vi_inertial_init_solve"]
 
 _lib = None
 
@@ -144,6 +150,11 @@ def load(path: str = LIB_PATH):
     lib.vi_predict_keyframe.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(C.c_double * 3), C.c_double, vp, vp, vp,
                                         vp]
     lib.vi_predict_keyframe.restype = C.c_int
+    lib.vi_inertial_init_workspace_size.argtypes = [i32, C.POINTER(InertialInit)]
+    lib.vi_inertial_init_workspace_size.restype = C.c_size_t
+    lib.vi_inertial_init_solve.argtypes = [vp, i32, C.POINTER(InertialInit), C.c_double, C.c_double, i32, vp,
+                                           C.c_size_t]
+    lib.vi_inertial_init_solve.restype = C.c_int
     lib.vi_ba_solve_warm.argtypes = [vp, i32, C.POINTER(Window), C.POINTER(Opts), vp, i32, vp, C.c_size_t, vp]
     lib.vi_ba_solve_warm.restype = C.c_int
     _lib = lib
@@ -434,6 +445,32 @@ class Context:
                                                  _ptr(imu), C.byref(g), float(tau), _ptr(pose_new), _ptr(vel_new),
                                                  _ptr(bias_new), _ptr(used_imu)))
         return pose_new, vel_new, bias_new, used_imu
+
+    def inertial_init_solve(self, problems, gravity_z=-9.81, lm_lambda=0.0, iters=10, ws=None):
+        """IMU initialisation stage 2 (vi_inertial_init_solve) on a batch.
+        problems: list of dicts of device float64 tensors: pose_vis [N][7],
+        imu [N-1][154], vel_vis [N][3], bias [N][6], rot_wg [4], log_scale [1],
+        optional cost [iters + 1]; the state tensors are updated in place.
+        Synchronous."""
+        import torch
+        descs = (InertialInit * len(problems))()
+        for k, q in enumerate(problems):
+            N = int(q["pose_vis"].shape[0])
+            _check_dev(q["pose_vis"], (N, 7), torch.float64, "pose_vis")
+            _check_dev(q["imu"], (N - 1, PREINT_DOUBLES), torch.float64, "imu")
+            _check_dev(q["vel_vis"], (N, 3), torch.float64, "vel_vis")
+            _check_dev(q["bias"], (N, 6), torch.float64, "bias")
+            _check_dev(q["rot_wg"], (4,), torch.float64, "rot_wg")
+            _check_dev(q["log_scale"], (1,), torch.float64, "log_scale")
+            if q.get("cost") is not None:
+                _check_dev(q["cost"], (iters + 1,), torch.float64, "cost")
+            descs[k] = InertialInit(N, _ptr(q["pose_vis"]), _ptr(q["imu"]), _ptr(q["vel_vis"]), _ptr(q["bias"]),
+                                    _ptr(q["rot_wg"]), _ptr(q["log_scale"]), _ptr(q.get("cost")))
+        nb = int(self.lib.vi_inertial_init_workspace_size(len(problems), descs))
+        if ws is None:
+            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device="cuda:%d" % self.device)
+        self._check(self.lib.vi_inertial_init_solve(self.h, len(problems), descs, float(gravity_z), float(lm_lambda),
+                                                    int(iters), _ptr(ws), ws.numel()))
 
     def warm_adamw(self, params, grads, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=1e-4):
         self._check(self.lib.vi_warm_adamw(self.h, _ptr(params), _ptr(grads), _ptr(m), _ptr(v), int(t), float(lr),

@@ -1116,4 +1116,64 @@ vi_status vi_predict_keyframe(vi_ctx* ctx, int32_t n, const double* pose_prev, c
   return VI_OK;
 }
 
+size_t vi_inertial_init_workspace_size(int32_t n_problems, const vi_inertial_init* problems) {
+  if (n_problems < 1 || !problems) return 0;
+  size_t b = align256(sizeof(IInitDesc) * n_problems);
+  for (int p = 0; p < n_problems; ++p) {
+    const int N = problems[p].n_kf;
+    if (N < 2 || N > kIInitMaxKeyframes) return 0;
+    b += align256(iinit_whiten_doubles(N) * sizeof(double));
+  }
+  return b;
+}
+
+vi_status vi_inertial_init_solve(vi_ctx* ctx, int32_t n_problems, const vi_inertial_init* problems,
+                                 double gravity_z, double lm_lambda, int32_t iters, void* workspace,
+                                 size_t workspace_bytes) {
+  if (!ctx) return VI_EINVAL;
+  if (n_problems < 1 || !problems || !workspace) return fail(ctx, VI_EINVAL, "null argument or no problems");
+  if (iters < 0) return fail(ctx, VI_EINVAL, "iters must be >= 0");
+  if (!std::isfinite(gravity_z) || gravity_z == 0.0) return fail(ctx, VI_EINVAL, "gravity_z must be finite, non-zero");
+  if (!(lm_lambda >= 0.0) || !std::isfinite(lm_lambda)) return fail(ctx, VI_EINVAL, "lm_lambda must be >= 0");
+  int max_n = 2;
+  for (int p = 0; p < n_problems; ++p) {
+    const vi_inertial_init& q = problems[p];
+    if (q.n_kf < 2 || q.n_kf > kIInitMaxKeyframes)
+      return fail(ctx, VI_EINVAL, "problem %d: n_kf must be in 2..%d", p, kIInitMaxKeyframes);
+    if (!q.pose_vis || !q.imu || !q.vel_vis || !q.bias || !q.rot_wg || !q.log_scale)
+      return fail(ctx, VI_EINVAL, "problem %d: null array", p);
+    max_n = std::max(max_n, (int)q.n_kf);
+  }
+  const size_t need = vi_inertial_init_workspace_size(n_problems, problems);
+  if (workspace_bytes < need) return fail(ctx, VI_ENOMEM, "workspace too small (%zu < %zu)", workspace_bytes, need);
+  if (((uintptr_t)workspace & 255) != 0) return fail(ctx, VI_EINVAL, "workspace must be 256-byte aligned");
+  std::vector<IInitDesc> h(n_problems);
+  char* wp = (char*)workspace + align256(sizeof(IInitDesc) * n_problems);
+  for (int p = 0; p < n_problems; ++p) {
+    const vi_inertial_init& q = problems[p];
+    h[p] = IInitDesc{q.n_kf, 0, q.pose_vis, q.imu, q.vel_vis, q.bias, q.rot_wg, q.log_scale, q.cost, (double*)wp};
+    wp += align256(iinit_whiten_doubles(q.n_kf) * sizeof(double));
+  }
+  vi_status st = ensure_status(ctx, n_problems);
+  if (st != VI_OK) return st;
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->priv, ctx->ev_in, 0));
+  HIPCHK(ctx, hipMemcpyAsync(workspace, h.data(), sizeof(IInitDesc) * n_problems, hipMemcpyHostToDevice, ctx->priv));
+  launch_reset_status(ctx->priv, ctx->status, n_problems);
+  launch_inertial_init(ctx->priv, n_problems, (const IInitDesc*)workspace, max_n, gravity_z, lm_lambda, iters,
+                       ctx->status);
+  HIPCHK(ctx, hipGetLastError());
+  std::vector<DevStatus> hs(n_problems);
+  HIPCHK(ctx, hipMemcpyAsync(hs.data(), ctx->status, sizeof(DevStatus) * n_problems, hipMemcpyDeviceToHost,
+                             ctx->priv));
+  HIPCHK(ctx, hipStreamSynchronize(ctx->priv));
+  for (int p = 0; p < n_problems; ++p)
+    if (hs[p].code != 0)
+      return fail(ctx, (vi_status)hs[p].code, "problem %d: %s (stage %d)", p,
+                  hs[p].code == VI_ENONFINITE ? "non-finite cost" : "not positive definite", hs[p].detail);
+  ctx->err.clear();
+  return VI_OK;
+}
+
 }  // extern "C"

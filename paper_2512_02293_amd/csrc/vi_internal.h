@@ -167,6 +167,25 @@ size_t wnet_prep_bytes();
 void launch_wnet_backward(hipStream_t s, int n, int HQ, int WQ, const int* dims, const float* theta, const void* act,
                           const float* dd, const float* db, const float* lab_dd, const float* lab_db, float nv,
                           float* g_dd, float* g_db, float* loss, float* partial, float* grads);
+// inertial-only initialisation (k_iinit.hip): one descriptor per problem, in the workspace
+struct IInitDesc {
+  int N;
+  int pad;
+  const double* pose_vis;
+  const vi_preint* imu;
+  double* vel;
+  double* bias;
+  double* rot_wg;
+  double* log_scale;
+  double* cost;
+  double* wf;            // whitening scratch [N-1][87]
+};
+constexpr int kIInitMaxKeyframes = 32;
+size_t iinit_lds_bytes(int N);
+size_t iinit_whiten_doubles(int N);
+void launch_inertial_init(hipStream_t s, int n, const IInitDesc* descs, int max_n_kf, double G, double lambda,
+                          int iters, DevStatus* status);
+
 // loop-closure update of a Gaussian map (k_gauss.hip)
 size_t reanchor_table_bytes(int n_kf);
 int64_t reanchor_max_gaussians();
