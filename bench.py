@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle GN iterations in the CPU sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="let the library time the candidate pixel tilings of the fused assembly on this window "
+                         "(once, before the timed steps) and keep the fastest")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 64-window batch, the global problem and the warm-start lines")
     ap.add_argument("--only", choices=["global", "warm-windows", "gaussian-reanchor", "predict-keyframe",
@@ -142,6 +145,7 @@ def main():
     N, E, H, W = prob.n_kf, prob.n_edges, prob.H, prob.W
     HW = H * W
     ctx = binding.Context(0)
+    ctx.set_autotune(bool(args.autotune))
     dp = binding.DeviceProblem(prob, dev)
     opts = binding.make_opts()
     ws = torch.empty(ctx.workspace_size(dp.cam, N, dp.ii, dp.jj, opts), dtype=torch.uint8, device=dev)
@@ -210,7 +214,8 @@ def main():
         "config": {"workload": "sliding window: 24 keyframes, 60x80 inverse-depth maps, 288 edges (12 nearest "
                                "by index), 200 Hz IMU / 10 Hz keyframes, 8 GN iterations, FP64",
                    "n_kf": N, "n_edges": E, "H": H, "W": W, "gn_iters": GN_ITERS,
-                   "pixel_residuals_per_step": pxres_per_step, "final_cost": float(rep["cost_after"])},
+                   "pixel_residuals_per_step": pxres_per_step, "final_cost": float(rep["cost_after"]),
+                   "assembly_tile_px": int(rep["tile_px"]), "autotune": bool(args.autotune)},
         "stage_ms_per_iter": {k: round(v, 5) for k, v in per_iter_ms.items()},
         "roofline": roof,
     }
@@ -367,6 +372,15 @@ def gaussian_reanchor(ctx, n_kf=512, per_kf=16384, reps=50):
     ms = per_call_ms(call)
     ms_table = per_call_ms(table_only)
     ms_map = ms - ms_table
+    # the oracle on a bounded sample of the same map (first 2^20 Gaussians), one core
+    from threadpoolctl import threadpool_limits
+
+    from oracle import gauss as ogauss
+    ns = 1 << 20
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        ogauss.reanchor(g.mean[:ns], g.cov[:ns], g.anchor[:ns], g.pose_pre, g.pose_post, g.scale_change)
+        dt_cpu = time.perf_counter() - t0
     alg = K * REANCHOR_BYTES_PER_GAUSSIAN
     gbs = alg / (ms_map * 1e-3) / 1e9
     return {"workload": f"Gaussian map update after a loop closure: {n_kf} keyframes x {per_kf} Gaussians "
@@ -378,7 +392,10 @@ def gaussian_reanchor(ctx, n_kf=512, per_kf=16384, reps=50):
                          "kernel": REANCHOR_KERNEL, "algorithmic_bytes_per_launch": alg,
                          "per_unit": "76 B per Gaussian (anchor 4, mean 12 + 12, covariance 24 + 24)",
                          "note": "map-kernel time = time per call minus time per call on an empty map (the "
-                                 "per-keyframe table kernel alone), both from HIP events on the context's stream"}}
+                                 "per-keyframe table kernel alone), both from HIP events on the context's stream"},
+            "cpu_baseline": {"value": ns / dt_cpu, "unit": "Gaussians/s", "cores": 1, "kind": "oracle",
+                             "sample": f"the first {ns} Gaussians of the same map ({dt_cpu:.2f} s, NumPy float64, "
+                                       f"1 BLAS thread)"}}
 
 
 def predict_keyframe(ctx, n=64, reps=200):
@@ -407,8 +424,18 @@ def predict_keyframe(ctx, n=64, reps=200):
     e1.record()
     torch.cuda.synchronize()
     us = 1e3 * e0.elapsed_time(e1) / reps
+    # the oracle on the same 64 predictions (its own preintegration of the factors is not timed)
+    from oracle import predict as opred
+    from oracle import preint as opreint
+    facs = [opreint.preintegrate_all(p.imu_off, p.gyro, p.accel, p.imu_dt, p.bias_hat, p.noise)[-1] for p in probs]
+    t0 = time.perf_counter()
+    for p, P in zip(probs, facs):
+        opred.predict_pose7(p.pose[-2], p.vel[-2], p.bias[-2], P, p.gravity)
+    dt_cpu = time.perf_counter() - t0
     return {"workload": f"{n} new keyframes (the last factor of each batched window), FP64",
             "us_per_call": us, "used_imu": int(out[3].sum().item()),
+            "cpu_baseline": {"value": 1e6 * dt_cpu, "unit": "us per 64 predictions", "cores": 1, "kind": "oracle",
+                             "sample": "the same 64 predictions (NumPy float64)"},
             "roofline": {"bound": "latency", "note": "one lane per prediction (about 600 FP64 operations and "
                                                      "1.4 KB of input each); the time is launch and memory latency"}}
 
@@ -449,7 +476,27 @@ def inertial_init(ctx, n=64, n_kf=20, iters=10, reps=5):
         ctx.inertial_init_solve(probs, iters=iters)
         best = min(best, time.perf_counter() - t0)
     c = torch.stack([q["cost"] for q in probs]).cpu().numpy()
-    return {"workload": f"{n} problems of {n_kf} keyframes (200 Hz IMU, 0.1 s gaps), visual poses with 0.2 mm / "
+    # the oracle on 2 of the 64 problems, same iterations, one core
+    from threadpoolctl import threadpool_limits
+
+    from oracle import inertial_init as oii
+    from oracle import preint as opreint
+    from oracle.so3 import quat_to_R
+    n_cpu = 2
+    dt_cpu = 0.0
+    with threadpool_limits(limits=1):
+        for w in range(n_cpu):
+            ip = synth.make_inertial_init_problem(synth.tiny_config(n_kf=n_kf), 6000 + w, pose_noise=(2e-4, 0.01))
+            fs = opreint.preintegrate_all(ip.imu_off, ip.gyro, ip.accel, ip.imu_dt, ip.bias_hat, ip.noise)
+            Rv = np.stack([quat_to_R(q) for q in ip.pose_vis[:, 3:7]])
+            st0 = oii.InitState(np.eye(3), 0.0, np.zeros((n_kf, 3)), np.zeros((n_kf, 6)))
+            t0 = time.perf_counter()
+            oii.solve(Rv, ip.pose_vis[:, :3], st0, fs, np.array([0.0, 0.0, -9.81]), iters)
+            dt_cpu += time.perf_counter() - t0
+    return {"cpu_baseline": {"value": 1e3 * dt_cpu / n_cpu, "unit": "ms per problem", "cores": 1, "kind": "oracle",
+                             "sample": f"{n_cpu} of the {n} problems, {iters} iterations each (NumPy float64, "
+                                       f"1 BLAS thread)"},
+            "workload": f"{n} problems of {n_kf} keyframes (200 Hz IMU, 0.1 s gaps), visual poses with 0.2 mm / "
                         f"0.01 deg errors, frame tilted 25 deg and shrunk by e^-0.9, {iters} iterations, FP64",
             "ms_per_call": 1e3 * best, "median_cost_reduction": float(np.median(c[:, -1] / c[:, 0])),
             "roofline": {"bound": "latency", "note": "one 256-thread workgroup per problem; about 3 barriers per "
