@@ -467,7 +467,9 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
   const int k = D.src_off[src + 1] - e0;
   const int ncol = 6 * k;
   const int T = (ncol + 16) / 16;
-  const int LDW = 16 * T;
+  // E-tile row stride: one element more than the T 16-column tiles, so that the
+  // lanes (one pixel row each) writing the same column hit different LDS banks
+  const int LDW = 16 * T + 1;
   const int ntiles = T * (T + 1) / 2;
   double* rel_s = sm;                             // [kMaxOutDegree][12]
   R* Lt = (R*)(rel_s + kMaxOutDegree * 12);       // [64][LDW]
@@ -1398,7 +1400,7 @@ __global__ void __launch_bounds__(256) k_warm_state(DevPlan D, double* __restric
 
 static size_t vis_lds(int kmax) {
   const size_t T = (6 * (size_t)kmax + 16) / 16;
-  const size_t vis = (size_t)kMaxOutDegree * 12 + 64 * 16 * T + 2 * kVisWaves * 64 + 64;
+  const size_t vis = (size_t)kMaxOutDegree * 12 + 64 * (16 * T + 1) + 2 * kVisWaves * 64 + 64;
   const size_t imu = 450 + 450 + 225 + 15;
   return sizeof(double) * std::max(vis, imu);
 }
