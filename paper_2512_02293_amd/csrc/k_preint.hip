@@ -4,9 +4,9 @@
 // matrix used by the inertial residual of Eq. 2-3.
 //
 // One 64-lane workgroup per factor.  The sample loop is inherently serial; the
-// lanes share each sample's work: the 63 mean/Jacobian entries and the 81
-// covariance entries are updated in parallel, with the transition matrix A of
-// the (rot, vel, pos) error state built in LDS.
+// lanes share each sample's work in two phases: T = A cov with the new mean and
+// bias Jacobians, then the 45 lower-triangle entries of cov = T A^T + Q, using
+// the block structure of the transition A of the (rot, vel, pos) error state.
 #include "vi_internal.h"
 #include "vi_math.h"
 
@@ -18,14 +18,21 @@ __device__ __forceinline__ void set_status(DevStatus* st, int code, int detail) 
   if (atomicCAS(&st->code, 0, code) == 0) st->detail = detail;
 }
 
+// row r of M1 = dR [a]x (column m of [a]x is a x e_m)
+__device__ __forceinline__ void m1_row(const double* dR, const double* a, int r, double* m1) {
+  const double d0 = dR[r * 3 + 0], d1 = dR[r * 3 + 1], d2 = dR[r * 3 + 2];
+  m1[0] = d1 * a[2] - d2 * a[1];
+  m1[1] = d2 * a[0] - d0 * a[2];
+  m1[2] = d0 * a[1] - d1 * a[0];
+}
+
 // LDS layout of one factor's running state
 struct PreintLds {
   double dR[9], dv[3], dp[3], JR[9], Jvg[9], Jva[9], Jpg[9], Jpa[9];
   double nR[9], nv[3], np_[3], nJR[9], nJvg[9], nJva[9], nJpg[9], nJpa[9];
-  double Ra[3], M1[9];                   // per-sample: dR a, dR [a]x
+  double M1[9];                          // per-sample: dR [a]x
   double pdRk[64][9], pJrk[64][9], pa[64][3], ph[64];   // 64 samples: Exp(w h), Jr(w h), a, h
-  double M1JR[9];
-  double A[81], Qn[81], T[81], cov[81];
+  double T[81], cov[81];
 };
 
 __global__ void __launch_bounds__(64) k_preint(int F, const int32_t* __restrict__ off,
@@ -71,68 +78,45 @@ __global__ void __launch_bounds__(64) k_preint(int F, const int32_t* __restrict_
     __syncthreads();
     for (int u = 0; u < nb; ++u) {
       const double h = S.ph[u];
+      const double hh = h * h;
       total += h;
       const double* dRk = S.pdRk[u];
       const double* Jrk = S.pJrk[u];
       const double* a = S.pa[u];
-      // phase 1: dR a and dR [a]x (lanes 0..11)
-      if (l < 9) {
-        const int r = l / 3, c = l % 3;
-        // ([a]x)[m][c] = eps_{m c n}... written out: column c of [a]x
-        const double axc[3] = {c == 0 ? 0.0 : (c == 1 ? -a[2] : a[1]),
-                               c == 0 ? a[2] : (c == 1 ? 0.0 : -a[0]),
-                               c == 0 ? -a[1] : (c == 1 ? a[0] : 0.0)};
-        S.M1[l] = S.dR[r * 3 + 0] * axc[0] + S.dR[r * 3 + 1] * axc[1] + S.dR[r * 3 + 2] * axc[2];
-      } else if (l < 12) {
-        const int r = l - 9;
-        S.Ra[r] = S.dR[r * 3 + 0] * a[0] + S.dR[r * 3 + 1] * a[1] + S.dR[r * 3 + 2] * a[2];
-      }
-      __syncthreads();
-      // phase 2: transition A, noise Qn, and M1 * J^rot
+      // The transition of the (rot, vel, pos) error state is block lower
+      // triangular: A = [[dRk^T, 0, 0], [-M1 h, I, 0], [-M1 h^2 / 2, I h, I]]
+      // with M1 = dR [a]x; only its non-trivial terms are multiplied.
+      // phase 1: T = A cov; the new mean and bias Jacobians (old values on the right); M1 for phase 2
       for (int e = l; e < 81; e += 64) {
-        const int r = e / 9, c = e % 9, br = r / 3, bc = c / 3, rr = r % 3, cc = c % 3;
+        const int r = e / 9, c = e % 9, br = r / 3, rr = r % 3;
         double v = 0.0;
-        if (br == 0 && bc == 0) v = dRk[cc * 3 + rr];                          // dRk^T
-        else if (br == 1 && bc == 0) v = -S.M1[rr * 3 + cc] * h;               // -dR [a]x h
-        else if (br == 2 && bc == 0) v = -0.5 * S.M1[rr * 3 + cc] * h * h;    // -1/2 dR [a]x h^2
-        else if (br == 2 && bc == 1) v = (rr == cc) ? h : 0.0;                 // I h
-        else if (br == bc) v = (rr == cc) ? 1.0 : 0.0;
-        S.A[e] = v;
-        // noise: Bg (sg^2/h) Bg^T with Bg = [Jr h; 0; 0]; Ba (sa^2/h) Ba^T with
-        // Ba = [0; dR h; 1/2 dR h^2] and dR dR^T = I
-        double q = 0.0;
-        if (br == 0 && bc == 0) {
-          double jj = 0.0;
-          for (int m = 0; m < 3; ++m) jj += Jrk[rr * 3 + m] * Jrk[cc * 3 + m];
-          q = sg2 * h * jj;
-        } else if (br >= 1 && bc >= 1 && rr == cc) {
-          const double fr = (br == 1) ? h : 0.5 * h * h;
-          const double fc = (bc == 1) ? h : 0.5 * h * h;
-          q = sa2 / h * fr * fc;
+        if (br == 0) {
+          for (int m = 0; m < 3; ++m) v += dRk[m * 3 + rr] * S.cov[m * 9 + c];
+        } else {
+          double m1[3];
+          m1_row(S.dR, a, rr, m1);
+          const double f0 = br == 1 ? -h : -0.5 * hh;
+          for (int m = 0; m < 3; ++m) v += (f0 * m1[m]) * S.cov[m * 9 + c];
+          if (br == 1) {
+            v += S.cov[(3 + rr) * 9 + c];
+          } else {
+            v += h * S.cov[(3 + rr) * 9 + c];
+            v += S.cov[(6 + rr) * 9 + c];
+          }
         }
-        S.Qn[e] = q;
-      }
-      if (l < 9) {
-        const int r = l / 3, c = l % 3;
-        double v = 0.0;
-        for (int m = 0; m < 3; ++m) v += S.M1[r * 3 + m] * S.JR[m * 3 + c];
-        S.M1JR[l] = v;
-      }
-      __syncthreads();
-      // phase 3: T = A cov, and the new mean / Jacobians (old values on the right)
-      for (int e = l; e < 81; e += 64) {
-        const int r = e / 9, c = e % 9;
-        double v = 0.0;
-        for (int m = 0; m < 9; ++m) v += S.A[r * 9 + m] * S.cov[m * 9 + c];
         S.T[e] = v;
       }
       if (l < 9) {
         const int r = l / 3, c = l % 3;
-        const double hh = h * h;
+        double m1[3];
+        m1_row(S.dR, a, r, m1);
+        S.M1[l] = m1[c];
+        double mj = 0.0;
+        for (int m = 0; m < 3; ++m) mj += m1[m] * S.JR[m * 3 + c];
         S.nJpa[l] = S.Jpa[l] + S.Jva[l] * h - 0.5 * S.dR[l] * hh;
-        S.nJpg[l] = S.Jpg[l] + S.Jvg[l] * h - 0.5 * S.M1JR[l] * hh;
+        S.nJpg[l] = S.Jpg[l] + S.Jvg[l] * h - 0.5 * mj * hh;
         S.nJva[l] = S.Jva[l] - S.dR[l] * h;
-        S.nJvg[l] = S.Jvg[l] - S.M1JR[l] * h;
+        S.nJvg[l] = S.Jvg[l] - mj * h;
         double v = 0.0, w = 0.0;
         for (int m = 0; m < 3; ++m) {
           v += dRk[m * 3 + r] * S.JR[m * 3 + c];     // dRk^T J^rot
@@ -142,23 +126,52 @@ __global__ void __launch_bounds__(64) k_preint(int F, const int32_t* __restrict_
         S.nR[l] = w;
       } else if (l >= 16 && l < 19) {
         const int i = l - 16;
-        S.np_[i] = S.dp[i] + S.dv[i] * h + 0.5 * S.Ra[i] * h * h;
-        S.nv[i] = S.dv[i] + S.Ra[i] * h;
+        const double ra = S.dR[i * 3 + 0] * a[0] + S.dR[i * 3 + 1] * a[1] + S.dR[i * 3 + 2] * a[2];
+        S.np_[i] = S.dp[i] + S.dv[i] * h + 0.5 * ra * hh;
+        S.nv[i] = S.dv[i] + ra * h;
       }
       __syncthreads();
-      // phase 4: cov = T A^T + Qn; commit the mean
-      for (int e = l; e < 81; e += 64) {
-        const int r = e / 9, c = e % 9;
+      // phase 2: cov = T A^T + Q (lower triangle, mirrored; Q = Bg (sg^2/h) Bg^T +
+      // Ba (sa^2/h) Ba^T with Bg = [Jr h; 0; 0], Ba = [0; dR h; dR h^2 / 2], dR dR^T = I);
+      // commit the mean and the Jacobians
+      if (l < 45) {
+        int r = 0;
+        while ((r + 1) * (r + 2) / 2 <= l) ++r;
+        const int c = l - r * (r + 1) / 2;
+        const int bc = c / 3, cc = c % 3, br = r / 3, rr = r % 3;
+        const double* Tr = S.T + r * 9;
         double v = 0.0;
-        for (int m = 0; m < 9; ++m) v += S.T[r * 9 + m] * S.A[c * 9 + m];
-        S.cov[e] = v + S.Qn[e];
-      }
-      if (l < 9) {
-        S.dR[l] = S.nR[l]; S.JR[l] = S.nJR[l];
-        S.Jvg[l] = S.nJvg[l]; S.Jva[l] = S.nJva[l]; S.Jpg[l] = S.nJpg[l]; S.Jpa[l] = S.nJpa[l];
-      } else if (l >= 16 && l < 19) {
-        S.dp[l - 16] = S.np_[l - 16];
-        S.dv[l - 16] = S.nv[l - 16];
+        if (bc == 0) {
+          for (int m = 0; m < 3; ++m) v += Tr[m] * dRk[m * 3 + cc];
+        } else {
+          const double f0 = bc == 1 ? -h : -0.5 * hh;
+          for (int m = 0; m < 3; ++m) v += Tr[m] * (f0 * S.M1[cc * 3 + m]);
+          if (bc == 1) {
+            v += Tr[3 + cc];
+          } else {
+            v += Tr[3 + cc] * h;
+            v += Tr[6 + cc];
+          }
+        }
+        double q = 0.0;
+        if (br == 0 && bc == 0) {
+          double jj = 0.0;
+          for (int m = 0; m < 3; ++m) jj += Jrk[rr * 3 + m] * Jrk[cc * 3 + m];
+          q = sg2 * h * jj;
+        } else if (br >= 1 && bc >= 1 && rr == cc) {
+          const double fr = (br == 1) ? h : 0.5 * hh;
+          const double fc = (bc == 1) ? h : 0.5 * hh;
+          q = sa2 / h * fr * fc;
+        }
+        S.cov[r * 9 + c] = v + q;
+        S.cov[c * 9 + r] = v + q;
+      } else if (l < 54) {
+        const int i = l - 45;
+        S.dR[i] = S.nR[i]; S.JR[i] = S.nJR[i];
+        S.Jvg[i] = S.nJvg[i]; S.Jva[i] = S.nJva[i]; S.Jpg[i] = S.nJpg[i]; S.Jpa[i] = S.nJpa[i];
+      } else if (l < 57) {
+        S.dp[l - 54] = S.np_[l - 54];
+        S.dv[l - 54] = S.nv[l - 54];
       }
       __syncthreads();
     }
