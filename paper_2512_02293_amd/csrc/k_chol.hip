@@ -628,9 +628,10 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   if (tid < kPanelSlots) pready[tid] = 0;
   __syncthreads();
   // Wave roles: wave 0 carries the chain of diagonal factorisations; wave 4
-  // shares its SIMD and so takes only memory work (copies, the deferred global
-  // copy of L_bb^-1, panel tiles beyond the seventh); the six other waves
-  // take the panel, the forward substitution and the trailing update.
+  // shares its SIMD and so takes the memory work (copies, the deferred global
+  // copy of L_bb^-1, panel tiles beyond the seventh) and then every seventh
+  // trailing tile; the six other waves take the panel, the forward
+  // substitution and the rest of the trailing update.
   const int pw = wave < 4 ? wave : (wave == 4 ? 7 : wave - 1);   // panel order: 0,1,2,3,5,6,7, then 4
   const int cw = wave < 4 ? wave - 1 : wave - 2;                 // compute worker 0..5 (waves 1-3, 5-7)
   for (int b = 0; b < nblk; ++b) {
@@ -714,7 +715,10 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
                         npad);
           if (cp_diag) tile_to_swz(diagbuf(b + 2), A + (size_t)(NB * (b + 2)) * npad + NB * (b + 2), npad);
         }
-        for (int u = (wave == 4) ? ntri : 1 + cw; u < ntri; u += NW - 2) {
+        // seven workers: the six compute waves and, after its copies, wave 4 (the
+        // MFMA pipe of SIMD 0 is mostly idle beside the look-ahead chain)
+        const int tw = (wave == 4) ? NW - 2 : cw;
+        for (int u = 1 + tw; u < ntri; u += NW - 1) {
           int jj = 0, rem = u;
           while (rem >= m - jj) { rem -= m - jj; ++jj; }
           const int j = b + 1 + jj, i = j + rem;
