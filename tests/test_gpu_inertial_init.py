@@ -124,3 +124,16 @@ def test_errors_leave_the_state(ctx):
     big = _upload(*_problem(33, 1)[:2], 1)
     with pytest.raises(binding.ViError, match="EINVAL"):
         ctx.inertial_init_solve([big], iters=1)
+
+
+def test_zero_iterations_report_the_initial_cost_and_keep_the_state(ctx):
+    ip, fs, R = _problem(8, 31, pose_noise=(2e-4, 0.01))
+    q = _upload(ip, fs, 0)
+    before = {k: v.clone() for k, v in q.items()}
+    ctx.inertial_init_solve([q], iters=0)
+    c0 = oi.cost(R, ip.pose_vis[:, :3], _zero(8), fs, G_I)
+    assert q["cost"].cpu().numpy()[0] == pytest.approx(c0, rel=1e-12)
+    import torch
+    for k in ("vel_vis", "bias", "log_scale"):
+        assert torch.equal(q[k], before[k])
+    np.testing.assert_allclose(quat_to_R(q["rot_wg"].cpu().numpy()), np.eye(3), atol=1e-15)
