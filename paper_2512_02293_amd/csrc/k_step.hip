@@ -1223,21 +1223,28 @@ __global__ void __launch_bounds__(256) k_vis_cost(OptsDev o, DevPlan D, int ncos
   }
 }
 
-__global__ void k_imu_cost(int F, DevPlan D, const double* __restrict__ Lam, double* __restrict__ icost) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+// r^T Lambda r per inertial factor, one wave per factor: every lane forms the
+// residual (the same values), lane a < 15 takes row a of the quadratic form
+// (its 15 loads in flight together), the wave sums the rows.
+__global__ void __launch_bounds__(256) k_imu_cost(int F, DevPlan D, const double* __restrict__ Lam,
+                                                  double* __restrict__ icost) {
+  const int f = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (f >= F) return;
+  const int lane = threadIdx.x & 63;
   const WinDev& W = D.win[D.win_of_f[f]];
   const int lf = f - W.f_base;
   double r[15];
   imu_residual_jacobian(W.pose, W.vel, W.bias, W.imu + lf, W.g, lf, r, nullptr);
-  const double* Lm = Lam + (size_t)f * 225;
-  double c = 0.0;
-  for (int a = 0; a < 15; ++a) {
-    double u = 0.0;
-    for (int b = 0; b < 15; ++b) u += Lm[a * 15 + b] * r[b];
-    c += r[a] * u;
+  const int a = lane < 15 ? lane : 0;
+  const double* La = Lam + (size_t)f * 225 + a * 15;
+  double u = 0.0, ra = 0.0;
+#pragma unroll
+  for (int b = 0; b < 15; ++b) {
+    u += La[b] * r[b];
+    if (b == a) ra = r[b];
   }
-  icost[f] = c;
+  const double c = wave_sum(lane < 15 ? ra * u : 0.0);
+  if (lane == 0) icost[f] = c;
 }
 
 __global__ void __launch_bounds__(256) k_cost_reduce(int ncost, int range_px, DevPlan D,
@@ -1262,8 +1269,11 @@ __global__ void __launch_bounds__(256) k_cost_reduce(int ncost, int range_px, De
 //   14: log(1 + h / n_cell)
 // and dims[img] = the keyframe's own cell grid.  Zero outside it.
 // ---------------------------------------------------------------------------
+// saved_d / saved_b (optional): a copy of every inverse depth and bias of the
+// state the planes are formed at (as k_warm_state keeps it), made on the way
 __global__ void __launch_bounds__(256) k_warm_features(OptsDev o, DevPlan D, int HQ, int WQ, float* __restrict__ feat,
-                                                       int* __restrict__ dims) {
+                                                       int* __restrict__ dims, double* __restrict__ saved_d,
+                                                       double* __restrict__ saved_b) {
   // 16 canvas cells per workgroup, one thread per pixel of a cell (lane
   // 16 c + j: cell c, pixel (j / 4, j % 4) of it); the cell sums are reduced
   // over the 16 lanes of the cell in a fixed order
@@ -1284,6 +1294,7 @@ __global__ void __launch_bounds__(256) k_warm_features(OptsDev o, DevPlan D, int
     dims[2 * src] = hq0;
     dims[2 * src + 1] = wq0;
   }
+  if (saved_b && blockIdx.x == 0 && tid < 6) saved_b[(size_t)src * 6 + tid] = W.bias[(size_t)ls * 6 + tid];
   __syncthreads();
   float* f = feat + (size_t)src * kWCin * npix;
   const int p = blockIdx.x * 16 + (tid >> 4), j = tid & 15;
@@ -1295,6 +1306,7 @@ __global__ void __launch_bounds__(256) k_warm_features(OptsDev o, DevPlan D, int
   if (cell_in && y < W.H && x < W.W) {
     const int pix = y * W.W + x;
     const double d = W.invdepth[(size_t)ls * W.HW + pix];
+    if (saved_d) saved_d[W.pix_base + (size_t)ls * W.HW + pix] = d;
     v[6] = d;
     v[7] = 1.0;
     const double qx = ((double)x - W.cx) / W.fx, qy = ((double)y - W.cy) / W.fy;
@@ -1475,14 +1487,15 @@ void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Wor
   hipLaunchKernelGGL(kvc, dim3((P.hw_max + kVisBlock - 1) / kVisBlock, N), dim3(256), 0, s, o, D, ncost,
                      w.vcost);
   if (o.use_imu && P.F > 0)
-    hipLaunchKernelGGL(k_imu_cost, dim3((P.F + 63) / 64), dim3(64), 0, s, P.F, D, w.Lam, w.icost);
+    hipLaunchKernelGGL(k_imu_cost, dim3((P.F + 3) / 4), dim3(256), 0, s, P.F, D, w.Lam, w.icost);
   hipLaunchKernelGGL(k_cost_reduce, dim3(P.n_win), dim3(256), 0, s, ncost, kVisBlock, D, w.vcost, w.icost,
                      o.use_imu, trace ? trace : w.trace, slot);
 }
 
 void launch_warm_features(hipStream_t s, const Plan& P, const DevPlan& D, const OptsDev& o, int HQ, int WQ,
-                          float* feat, int* dims) {
-  hipLaunchKernelGGL(k_warm_features, dim3((HQ * WQ + 15) / 16, P.N), dim3(256), 0, s, o, D, HQ, WQ, feat, dims);
+                          float* feat, int* dims, double* saved_d, double* saved_b) {
+  hipLaunchKernelGGL(k_warm_features, dim3((HQ * WQ + 15) / 16, P.N), dim3(256), 0, s, o, D, HQ, WQ, feat, dims,
+                     saved_d, saved_b);
 }
 
 void launch_warm_apply(hipStream_t s, const Plan& P, const DevPlan& D, int HQ, int WQ, const float* dd,

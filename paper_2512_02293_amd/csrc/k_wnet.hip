@@ -99,20 +99,19 @@ __host__ __device__ constexpr int prep_off(int l) {
   return l == 1 ? 0 : kWC * (prep_kp(1) + 8) + (l - 2) * kWC * (prep_kp(2) + 8);
 }
 
-// theta -> the four layers' LDS images (one workgroup per layer)
+// theta -> the four layers' LDS images, one workgroup per (output row, layer)
 __global__ void __launch_bounds__(kThreads) k_wnet_prep(const float* __restrict__ theta, __bf16* __restrict__ wprep) {
-  const int l = blockIdx.x + 1;
+  const int l = blockIdx.y + 1, n = blockIdx.x;
   const int cin = l == 1 ? kWCin : kWC, kpad = l == 1 ? kWCinPad : kWC, KP = prep_kp(l);
   const int kshift = kpad == 16 ? 4 : 5;
-  const int row = KP + 8, total = kWC * row;
+  const int row = KP + 8;
   const float* W = theta + w_off(l);
-  __bf16* out = wprep + prep_off(l);
-  for (int e = threadIdx.x; e < total; e += kThreads) {
-    const int n = e / row, k = e - n * row;
+  __bf16* out = wprep + prep_off(l) + (size_t)n * row;
+  for (int k = threadIdx.x; k < row; k += kThreads) {
     const int tap = k >> kshift, c = k & (kpad - 1);
     float v = 0.0f;
     if (k < KP && tap < 9 && c < cin) v = W[(n * cin + c) * 9 + tap];
-    out[e] = (__bf16)v;
+    out[k] = (__bf16)v;
   }
 }
 
@@ -540,7 +539,7 @@ void wnet_set_attributes() {
 
 void launch_wnet_forward(hipStream_t s, int n, int HQ, int WQ, const int* dims, const float* theta, const float* feat,
                          void* act, float* dd, float* db, void* wprep) {
-  if (wprep) hipLaunchKernelGGL(k_wnet_prep, dim3(kWLayers), dim3(kThreads), 0, s, theta, (__bf16*)wprep);
+  if (wprep) hipLaunchKernelGGL(k_wnet_prep, dim3(kWC, kWLayers), dim3(kThreads), 0, s, theta, (__bf16*)wprep);
   hipLaunchKernelGGL(k_wnet_forward, dim3(n), dim3(kThreads), wnet_fwd_lds(HQ, WQ), s, theta, HQ, WQ, dims, feat,
                      (__bf16*)act, dd, db, (const __bf16*)wprep);
 }

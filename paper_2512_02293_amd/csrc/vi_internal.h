@@ -196,7 +196,8 @@ void launch_reanchor(hipStream_t s, int n_kf, const double* pose_pre, const doub
 void launch_wnet_adamw(hipStream_t s, int P, float* theta, const float* g, float* m, float* v, int t, float lr,
                        float b1, float b2, float eps, float wd);
 void launch_warm_features(hipStream_t s, const Plan& P, const DevPlan& D, const OptsDev& o, int HQ, int WQ,
-                          float* feat, int* dims);
+                          float* feat, int* dims, double* saved_d = nullptr,
+                          double* saved_b = nullptr);
 void launch_warm_apply(hipStream_t s, const Plan& P, const DevPlan& D, int HQ, int WQ, const float* dd,
                        const float* db, double d_min);
 void launch_warm_state(hipStream_t s, const Plan& P, const DevPlan& D, double* saved_d, double* saved_b,
