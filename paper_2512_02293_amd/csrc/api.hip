@@ -538,8 +538,8 @@ void launch_warm_prologue(hipStream_t sp, const Plan& P, const DevPlan& D, const
   // the input planes, with the copy of the inverse depths and biases taken on the way
   launch_warm_features(sp, P, D, od, wa.hq, wa.wq, ww.feat, ww.dims, ww.saved_d, ww.saved_b);
   launch_wnet_forward(sp, P.N, wa.hq, wa.wq, ww.dims, wa.params, ww.feat, nullptr, ww.dd, ww.db, ww.wprep);
-  launch_warm_apply(sp, P, D, wa.hq, wa.wq, ww.dd, ww.db, od.d_min);
-  launch_final_cost(sp, P, D, w, od, 1, ww.trace);
+  // the corrections are applied by the cost kernel of the corrected state
+  launch_final_cost(sp, P, D, w, od, 1, ww.trace, ww.dd, ww.db, wa.hq, wa.wq, od.d_min);
   launch_warm_state(sp, P, D, ww.saved_d, ww.saved_b, ww.trace, 1);
 }
 

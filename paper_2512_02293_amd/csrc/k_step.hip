@@ -1172,8 +1172,29 @@ __global__ void k_reset_status(DevStatus* st, int n) {
 // ---------------------------------------------------------------------------
 // cost at the current state (residuals only)
 // ---------------------------------------------------------------------------
+// corrected inverse depth of pixel p of keyframe src (up4 of its cell grid)
+__device__ __forceinline__ double warm_corrected_depth(const WinDev& W, int src, int p, int HQ, int WQ,
+                                                       const float* __restrict__ dd, double d, double d_min) {
+  const int hq0 = (W.H + 3) / 4, wq0 = (W.W + 3) / 4;
+  const float* g = dd + (size_t)src * HQ * WQ;
+  const int y = p / W.W, x = p % W.W;
+  const double fy = fmin(fmax((y - 1.5) / 4.0, 0.0), hq0 - 1.0);
+  const double fx = fmin(fmax((x - 1.5) / 4.0, 0.0), wq0 - 1.0);
+  const int y0 = (int)floor(fy), x0 = (int)floor(fx);
+  const int y1 = min(y0 + 1, hq0 - 1), x1 = min(x0 + 1, wq0 - 1);
+  const double ay = fy - y0, ax = fx - x0;
+  const double v = (1 - ay) * ((1 - ax) * g[y0 * WQ + x0] + ax * g[y0 * WQ + x1]) +
+                   ay * ((1 - ax) * g[y1 * WQ + x0] + ax * g[y1 * WQ + x1]);
+  return fmax(d + v, d_min);
+}
+
 template <typename R>
-__global__ void __launch_bounds__(256) k_vis_cost(OptsDev o, DevPlan D, int ncost, double* __restrict__ vcost) {
+// With dd set, the warm-start corrections are applied first (each workgroup to
+// its own pixels, workgroup 0 of a keyframe to its bias) and the cost is that
+// of the corrected state.
+__global__ void __launch_bounds__(256) k_vis_cost(OptsDev o, DevPlan D, int ncost, double* __restrict__ vcost,
+                                                  const float* __restrict__ dd, const float* __restrict__ db, int HQ,
+                                                  int WQ, double d_min) {
   __shared__ double red[2][4];
   __shared__ double rel[kMaxOutDegree * 12];
   const int src = blockIdx.y, kr = blockIdx.x;
@@ -1191,7 +1212,15 @@ __global__ void __launch_bounds__(256) k_vis_cost(OptsDev o, DevPlan D, int ncos
   const int pc = inpx ? p : 0;
   const R qx = (R)(((double)(pc % W.W) - W.cx) / W.fx);
   const R qy = (R)(((double)(pc / W.W) - W.cy) / W.fy);
-  const R d = (R)W.invdepth[(size_t)ls * HW + pc];
+  double dsrc = W.invdepth[(size_t)ls * HW + pc];
+  if (dd) {
+    if (inpx) {
+      dsrc = warm_corrected_depth(W, src, pc, HQ, WQ, dd, dsrc, d_min);
+      W.invdepth[(size_t)ls * HW + pc] = dsrc;
+    }
+    if (kr == 0 && tid < 6) W.bias[(size_t)ls * 6 + tid] += (double)db[(size_t)src * 6 + tid];
+  }
+  const R d = (R)dsrc;
   const R fx = (R)W.fx, fy = (R)W.fy, cx = (R)W.cx, cy = (R)W.cy;
   double cost = 0.0, nval = 0.0;
   for (int s = 0; s < k; ++s) {
@@ -1360,21 +1389,11 @@ __global__ void __launch_bounds__(256) k_warm_apply(DevPlan D, int HQ, int WQ, c
   const int src = blockIdx.y;
   const WinDev W = D.win[D.win_of_kf[src]];
   const int ls = src - W.kf_base;
-  const int hq0 = (W.H + 3) / 4, wq0 = (W.W + 3) / 4;
-  const float* g = dd + (size_t)src * HQ * WQ;
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (blockIdx.x == 0 && threadIdx.x < 6) W.bias[(size_t)ls * 6 + threadIdx.x] += (double)db[(size_t)src * 6 + threadIdx.x];
   if (p >= W.HW) return;
-  const int y = p / W.W, x = p % W.W;
-  const double fy = fmin(fmax((y - 1.5) / 4.0, 0.0), hq0 - 1.0);
-  const double fx = fmin(fmax((x - 1.5) / 4.0, 0.0), wq0 - 1.0);
-  const int y0 = (int)floor(fy), x0 = (int)floor(fx);
-  const int y1 = min(y0 + 1, hq0 - 1), x1 = min(x0 + 1, wq0 - 1);
-  const double ay = fy - y0, ax = fx - x0;
-  const double v = (1 - ay) * ((1 - ax) * g[y0 * WQ + x0] + ax * g[y0 * WQ + x1]) +
-                   ay * ((1 - ax) * g[y1 * WQ + x0] + ax * g[y1 * WQ + x1]);
   double* dep = W.invdepth + (size_t)ls * W.HW + p;
-  *dep = fmax(*dep + v, d_min);
+  *dep = warm_corrected_depth(W, src, p, HQ, WQ, dd, *dep, d_min);
 }
 
 // Keep (restore = 0) or put back (restore = 1) a keyframe's inverse depths and
@@ -1480,12 +1499,12 @@ void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, 
 }
 
 void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o, int slot,
-                       double* trace) {
+                       double* trace, const float* dd, const float* db, int HQ, int WQ, double d_min) {
   const int N = P.N;
   const int ncost = cost_slots(P);
   auto kvc = (o.precision == VI_PREC_MIXED) ? k_vis_cost<float> : k_vis_cost<double>;
   hipLaunchKernelGGL(kvc, dim3((P.hw_max + kVisBlock - 1) / kVisBlock, N), dim3(256), 0, s, o, D, ncost,
-                     w.vcost);
+                     w.vcost, dd, db, HQ, WQ, d_min);
   if (o.use_imu && P.F > 0)
     hipLaunchKernelGGL(k_imu_cost, dim3((P.F + 3) / 4), dim3(256), 0, s, P.F, D, w.Lam, w.icost);
   hipLaunchKernelGGL(k_cost_reduce, dim3(P.n_win), dim3(256), 0, s, ncost, kVisBlock, D, w.vcost, w.icost,

@@ -153,8 +153,11 @@ void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, 
 void launch_tune_stages(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o,
                         StageMark mark, void* mark_user);
 void launch_reset_status(hipStream_t s, DevStatus* st, int n);
+// dd / db (optional): warm-start corrections (cells [n][HQ][WQ], [n][6]) applied
+// to the state first, so that the cost is that of the corrected state
 void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o,
-                       int slot, double* trace = nullptr);   // trace: w.trace unless given
+                       int slot, double* trace = nullptr, const float* dd = nullptr, const float* db = nullptr,
+                       int HQ = 0, int WQ = 0, double d_min = 0.0);   // trace: w.trace unless given
 void launch_chol(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, DevStatus* st);
 void step_set_attributes(int kmax);
 // warm start
