@@ -390,6 +390,16 @@ __device__ __forceinline__ void lds_wait(const int* f, int v) {
   asm volatile("" ::: "memory");
 }
 
+// Wait until *f >= v (a counter that only grows); bounded like lds_wait.
+__device__ __forceinline__ void lds_wait_ge(const int* f, int v) {
+  for (int spin = 0; spin < (1 << 22); ++spin) {
+    const bool pending = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < v;
+    if (__ballot(pending) == 0) break;
+    __builtin_amdgcn_s_sleep(1);
+  }
+  asm volatile("" ::: "memory");
+}
+
 // global 32 x 32 tile -> swizzled LDS tile, all loads in flight at once (one wave)
 __device__ __forceinline__ void tile_to_swz(double* S, const double* M, size_t ld) {
   double4_t acc[2][2];
@@ -590,6 +600,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   __shared__ double yv[kSmallMaxNpad];          // right-hand side -> y = L^-1 s -> running rhs of L^T x = y
   __shared__ int yready;                        // step b + 1 once rows of block b + 1 of yv are updated
   __shared__ int pready[kPanelSlots];           // step b + 1 once panel tile u of column b is in LDS
+  __shared__ int xdone;                         // back-substitution: blocks of x published so far
   const int w = blockIdx.x;
   const WinDev& W = D.win[w];
   const int npad = W.npad, nblk = W.nblk, n = W.n;
@@ -625,6 +636,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   __syncthreads();
   if (wave == 0) fwd_block(Li[0], yv);
   if (tid == 0) yready = 0;
+  if (tid == 0) xdone = 0;
   if (tid < kPanelSlots) pready[tid] = 0;
   __syncthreads();
   // Wave roles: wave 0 carries the chain of diagonal factorisations; wave 4
@@ -739,46 +751,48 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
     }
     __syncthreads();
   }
-  // back-substitution x = L^-T y inside the band; the diagonal inverses go to LDS
+  // back-substitution x = L^-T y inside the band, as a dataflow between the
+  // waves instead of two barriers per block: block c of x, its diagonal
+  // inverse and every update of its right-hand side belong to wave c mod NW.
+  // For b = nblk-1 .. 0 the owner of block b forms x_b = L_bb^-T y_b (all its
+  // updates are in) and publishes it (xdone = nblk - b, in order of b); the
+  // owners of the blocks c in [b - band, b) then apply y_c -= L_bc^T x_b with
+  // the tile of L_bc loaded before they wait for x_b.
   double* xs = T;
-  for (int e = tid; e < nblk * NB * NB; e += kSmallThreads) {
-    const int bb = e >> 10, rc = e & 1023;
-    P[bb * NB * NB + swz(rc >> 5, rc & 31)] = Lv[e];
+  for (int c = wave; c < nblk; c += NW) {
+#pragma unroll
+    for (int it = 0; it < 16; ++it) {
+      const int e = lane + 64 * it;
+      P[c * NB * NB + swz(e >> 5, e & 31)] = Lv[(size_t)c * NB * NB + e];
+    }
   }
-  __syncthreads();
   const int q = lane & 31, half = lane >> 5;
   for (int b = nblk - 1; b >= 0; --b) {
-    const int c0 = max(0, b - bw);
-    // prefetch this wave's first block L_bc while x_b is formed
-    const int cw = c0 + wave;
-    double pre[16];
-    if (cw < b) {
+    if (b % NW == wave) {
+      lds_wait_ge(&xdone, nblk - 1 - b);        // x_{b+1} is out, so is the last update of y_b
+      if (lane < NB) {
+        const double* Lb = P + b * NB * NB;
+        double v = 0.0;
 #pragma unroll
-      for (int uu = 0; uu < 16; ++uu) pre[uu] = A[(size_t)(NB * b + 16 * half + uu) * npad + NB * cw + q];
-    }
-    if (tid < NB) {
-      const double* Lb = P + b * NB * NB;
-      double v = 0.0;
-#pragma unroll
-      for (int r = 0; r < NB; ++r) v += Lb[swz(r, tid)] * yv[NB * b + r];
-      xs[NB * b + tid] = v;
-    }
-    __syncthreads();
-    for (int c = cw; c < b; c += NW) {
-      double v = 0.0;
-      if (c == cw) {
-#pragma unroll
-        for (int uu = 0; uu < 16; ++uu) v += pre[uu] * xs[NB * b + 16 * half + uu];
-      } else {
-#pragma unroll
-        for (int uu = 0; uu < 16; ++uu)
-          v += A[(size_t)(NB * b + 16 * half + uu) * npad + NB * c + q] * xs[NB * b + 16 * half + uu];
+        for (int r = 0; r < NB; ++r) v += Lb[swz(r, lane)] * yv[NB * b + r];
+        xs[NB * b + lane] = v;
       }
+      lds_publish(&xdone, nblk - b);
+    }
+    const int c0 = max(0, b - bw);
+    for (int c = c0 + ((wave - c0 % NW) + NW) % NW; c < b; c += NW) {
+      double pre[16];
+#pragma unroll
+      for (int uu = 0; uu < 16; ++uu) pre[uu] = A[(size_t)(NB * b + 16 * half + uu) * npad + NB * c + q];
+      lds_wait_ge(&xdone, nblk - b);
+      double v = 0.0;
+#pragma unroll
+      for (int uu = 0; uu < 16; ++uu) v += pre[uu] * xs[NB * b + 16 * half + uu];
       v += __shfl_xor(v, 32);
       if (half == 0) yv[NB * c + q] -= v;
     }
-    __syncthreads();
   }
+  __syncthreads();
   double* x = xall + W.x_off;
   for (int i = tid; i < npad; i += kSmallThreads) x[i] = (i < n) ? xs[i] : 0.0;
 }
