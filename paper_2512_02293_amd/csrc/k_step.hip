@@ -808,14 +808,26 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
   const double* gp = gpart + D.gram_off[src];
   const size_t gstride = (size_t)ntiles * 256;
   const int nent = ntiles * 256;
-  // two entries per thread and pass: the partial loads of both are in flight together
-  for (int i0 = tid; i0 < nent; i0 += 2 * NT) {
-    const int i1 = min(i0 + NT, nent - 1);
-    const double v0 = sum_partials<16>(gp + i0, gstride, nkr);
-    const double v1 = sum_partials<16>(gp + i1, gstride, nkr);
+  // Every thread first forms all the sums it owns in a pass (four Gram
+  // entries; in the first pass also one edge-Hessian entry and one gradient
+  // entry), so that the partial loads of all of them are in flight together,
+  // and then writes them to LDS.  One pass covers up to 12 edges.
+  const bool own_h = tid < k * 36, own_g = tid < k * 6;
+  for (int base = 0; base < nent; base += 4 * NT) {
+    double vq[4], vh = 0.0, vg = 0.0;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = h ? i0 + NT : i0;
+    for (int h = 0; h < 4; ++h) vq[h] = sum_partials<8>(gp + min(base + tid + h * NT, nent - 1), gstride, nkr);
+    const bool first = base == 0;
+    if (first && own_h) {
+      const int rc = tid % 36, r = rc / 6, c = rc % 6;
+      const int a = min(r, c), b = max(r, c);
+      const int qq = a * 6 - a * (a - 1) / 2 + (b - a);
+      vh = sum_partials<8>(hpart + (size_t)(e0 + tid / 36) * nkr_max * 32 + qq, 32, nkr);
+    }
+    if (first && own_g) vg = sum_partials<8>(hpart + (size_t)(e0 + tid / 6) * nkr_max * 32 + 21 + tid % 6, 32, nkr);
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      const int i = base + tid + h * NT;
       if (i >= nent) continue;
       const int t = i >> 8, e = i & 255;
       int I = 0;
@@ -823,26 +835,20 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
       const int J = t - I * (I + 1) / 2;
       const int a = 16 * I + (e >> 4), b = 16 * J + (e & 15);
       if (a < nq && b < nq && a >= b) {
-        const double v = h ? v1 : v0;
-        Qs[a * nq + b] = v;
-        Qs[b * nq + a] = v;
+        Qs[a * nq + b] = vq[h];
+        Qs[b * nq + a] = vq[h];
       }
     }
-  }
-  for (int i = tid; i < k * 36; i += NT) {
-    const int s = i / 36, rc = i % 36, r = rc / 6, c = rc % 6;
-    const int e = D.src_edges[e0 + s];
-    const double* Rt = rel + (size_t)e * 12;
-    const double* Rjs = Rw + (size_t)D.jj[e] * 9;
-    Mi[i] = Mi_at(Rt, Rjs, r, c);
-    if (rc < 9) Rj[s * 9 + rc] = Rjs[rc];
-    const int a = min(r, c), b = max(r, c);
-    const int q = a * 6 - a * (a - 1) / 2 + (b - a);
-    Hs[i] = sum_partials<16>(hpart + (size_t)(e0 + s) * nkr_max * 32 + q, 32, nkr);
-  }
-  for (int i = tid; i < k * 6; i += NT) {
-    const int s = i / 6;
-    gs[i] = sum_partials<16>(hpart + (size_t)(e0 + s) * nkr_max * 32 + 21 + i % 6, 32, nkr);
+    if (first && own_h) {
+      const int hs_s = tid / 36, rc = tid % 36;
+      const int e = D.src_edges[e0 + hs_s];
+      const double* Rt = rel + (size_t)e * 12;
+      const double* Rjs = Rw + (size_t)D.jj[e] * 9;
+      Mi[tid] = Mi_at(Rt, Rjs, rc / 6, rc % 6);
+      if (rc < 9) Rj[hs_s * 9 + rc] = Rjs[rc];
+      Hs[tid] = vh;
+    }
+    if (first && own_g) gs[tid] = vg;
   }
   __syncthreads();
   for (int i = tid; i < k * 6; i += NT) gs[i] -= Qs[ncol * nq + i];
@@ -910,27 +916,46 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
     Zs[(size_t)(0 * K1 + t + 1) * 36 + a * 6 + b] = v;
     Zs[(size_t)((t + 1) * K1 + 0) * 36 + b * 6 + a] = v;
   }
-  for (int i = tid; i < 36; i += NT) {
-    const int a = i / 6, b = i % 6;
+  // per-edge terms of Z_00 = sum_t W_t M_i,t and of the first block row of
+  // the diagonal / right-hand side (sum_s M_i,s^T H_s M_i,s, M_i,s^T (g - y)),
+  // into the Gram's LDS area (no longer needed), then summed over the edges
+  // in order
+  double* scr = Qs;
+  for (int i = tid; i < k * 36; i += NT) {
+    const int t = i / 36, a = (i % 36) / 6, b = i % 6;
     double v = 0.0;
-    for (int t = 0; t < k; ++t)
 #pragma unroll
-      for (int m = 0; m < 6; ++m) v += Wt[t * 36 + a * 6 + m] * Mi[t * 36 + m * 6 + b];
-    Zs[a * 6 + b] = v;
+    for (int m = 0; m < 6; ++m) v += Wt[t * 36 + a * 6 + m] * Mi[t * 36 + m * 6 + b];
+    scr[i] = v;
+  }
+  for (int i = tid; i < k * 6; i += NT) {
+    const int s2 = i / 6, a = i % 6;
+    const double* M = Mi + s2 * 36;
+    double zb = 0.0, zv = 0.0;
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      double hm = 0.0;
+#pragma unroll
+      for (int nn = 0; nn < 6; ++nn) hm += Hs[s2 * 36 + m * 6 + nn] * M[nn * 6 + a];
+      zb += M[m * 6 + a] * hm;
+      zv += M[m * 6 + a] * gs[s2 * 6 + m];
+    }
+    scr[k * 36 + 2 * i] = zb;
+    scr[k * 36 + 2 * i + 1] = zv;
+  }
+  __syncthreads();
+  for (int i = tid; i < 36; i += NT) {
+    double v = 0.0;
+    for (int t = 0; t < k; ++t) v += scr[t * 36 + i];
+    Zs[i] = v;
   }
   for (int i = tid; i < 6 * K1; i += NT) {
     const int ra = i / 6, a = i % 6;
     double zb = 0.0, zv = 0.0;
     if (ra == 0) {
       for (int s2 = 0; s2 < k; ++s2) {
-        const double* M = Mi + s2 * 36;
-        for (int m = 0; m < 6; ++m) {
-          double hm = 0.0;
-#pragma unroll
-          for (int nn = 0; nn < 6; ++nn) hm += Hs[s2 * 36 + m * 6 + nn] * M[nn * 6 + a];
-          zb += M[m * 6 + a] * hm;
-          zv += M[m * 6 + a] * gs[s2 * 6 + m];
-        }
+        zb += scr[k * 36 + 2 * (s2 * 6 + a)];
+        zv += scr[k * 36 + 2 * (s2 * 6 + a) + 1];
       }
     } else {
       // M_j = -P: diag(P^T H P) and -P^T (g - y)
