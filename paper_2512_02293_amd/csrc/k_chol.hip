@@ -167,27 +167,22 @@ __device__ __forceinline__ int leaf8_inv(const double* M, int ld, double* D, int
       for (int m = 1; m < 8; ++m)
         if (i > j && m > j && m <= i) L[tri8(i, m)] -= L[tri8(i, j)] * L[tri8(m, j)];
   }
-  // X = L^-1 column by column (forward substitution against e_c), each column
-  // written out as soon as it is known, so that only one column is live
-  const bool w0 = (threadIdx.x & 63) == 0;
+  // X = L^-1: lane c (mod 8) forms column c by forward substitution against
+  // e_c (x_r = 0 above the diagonal, x_c = 1 / L_cc), so that the eight
+  // columns are computed side by side and stored with one write per row
+  const int c = threadIdx.x & 7;
+  double x[8];
 #pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    double x[8];
-    x[c] = rv[c];
+  for (int r = 0; r < 8; ++r) {
+    double v = 0.0;
 #pragma unroll
-    for (int r = 1; r < 8; ++r) {
-      if (r > c) {
-        double v = 0.0;
+    for (int q = 0; q < 7; ++q)
+      if (q < r) v += L[tri8(r, q)] * x[q];
+    x[r] = (r == c) ? rv[r] : ((r < c) ? 0.0 : -v * rv[r]);
+  }
+  if ((threadIdx.x & 63) < 8) {
 #pragma unroll
-        for (int q = 0; q < 7; ++q)
-          if (q >= c && q < r) v += L[tri8(r, q)] * x[q];
-        x[r] = -v * rv[r];
-      }
-    }
-    if (w0) {
-#pragma unroll
-      for (int r = 0; r < 8; ++r) D[r * ldd + c] = (r >= c) ? x[r] : 0.0;
-    }
+    for (int r = 0; r < 8; ++r) D[r * ldd + c] = x[r];
   }
   return bad;
 }
