@@ -240,7 +240,7 @@ vi_status vi_ctx_set_autotune(vi_ctx* ctx, int32_t enable);
  * Learned warm start.  The paper's step has no learned initialisation; this
  * is an addition: a small convolutional network proposes inverse-depth and
  * bias corrections of a window before Gauss-Newton, and plain Gauss-Newton
- * remains the judge (a caller keeps the corrected state only if its cost is
+ * remains the arbiter (a caller keeps the corrected state only if its cost is
  * lower than that of the plain initial state).
  *
  * Network (parameters: FP32 vector of vi_warm_param_count() floats, layout
@@ -309,7 +309,7 @@ vi_status vi_warm_apply(vi_ctx* ctx, int32_t n_windows, const vi_window* windows
  * invalid input. */
 size_t vi_warm_start_workspace_size(int32_t n_windows, const vi_window* windows, const vi_opts* opts);
 
-/* The whole warm start with plain Gauss-Newton as the judge, on the device in
+/* The whole warm start with plain Gauss-Newton as the arbiter, on the device in
  * one call: the cost F (Eq. 1 and 3 terms, as reported by vi_ba_solve) at the
  * windows' initial state; a copy of every inverse depth and bias; input
  * planes, network (params as for vi_warm_forward) and corrections as

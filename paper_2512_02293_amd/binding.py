@@ -486,7 +486,7 @@ class Context:
         return int(self.lib.vi_warm_start_workspace_size(len(probs), wins, C.byref(opts)))
 
     def warm_start(self, probs, imus, opts: Opts, params, workspace):
-        """Warm start of every window with the plain cost as the judge; returns
+        """Warm start of every window with the plain cost as the arbiter; returns
         per-window dicts (accepted, cost_init, cost_warm, cost_after)."""
         _check_dev(workspace, (None,), self.torch.uint8, "workspace")
         _check_dev(params, (int(self.lib.vi_warm_param_count()),), self.torch.float32, "params")

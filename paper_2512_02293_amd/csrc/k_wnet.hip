@@ -3,7 +3,7 @@
 // per-cell inverse-depth head and a pooled bias head; forward, backward,
 // gradient reduction and AdamW.  The paper has no counterpart of this network;
 // it proposes the starting inverse depths and biases of a window, and plain
-// Gauss-Newton stays the fallback and the judge of the result.
+// Gauss-Newton stays the fallback and the arbiter of the result.
 //
 // Numerics: activations, activation gradients and the MFMA operands are BF16;
 // products accumulate in FP32 (MFMA 16x16x32 bf16 -> f32); the master weights,

@@ -223,7 +223,7 @@ def _iters_to_tol(costs, target):
 
 def time_to_tol(ctx, net, probs, opts, max_iters=REF_ITERS, rel_tol=1e-6, reps=3):
     """Plain GN from the initial state vs the learned warm start (with the
-    plain cost as the judge, vi_warm_start) followed by GN.
+    plain cost as the arbiter, vi_warm_start) followed by GN.
 
     The target of every window is its plain-GN cost after max_iters
     iterations (converged) times (1 + rel_tol); k_plain / k_warm are the GN
