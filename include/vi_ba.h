@@ -236,6 +236,21 @@ vi_status vi_ba_solve_batched(vi_ctx* ctx, int32_t n_windows, const vi_window* w
  * shape in the context; later calls reuse it.  Off by default (320 pixels). */
 vi_status vi_ctx_set_autotune(vi_ctx* ctx, int32_t enable);
 
+/* Tolerance stop of the Gauss-Newton iterations (Sec. 3.1 iterates the damped
+ * step; the paper gives no stopping rule, so this one is the library's).  With
+ * rel_tol > 0, every later vi_ba_solve, vi_ba_solve_batched and
+ * vi_ba_solve_warm call on this context freezes a window before its step t
+ * (t >= 1) when F_{t-1} - F_t <= rel_tol * F_{t-1}, F_t being the cost at the
+ * state that step t would linearise (so also when the cost went up or is not
+ * finite).  A frozen window takes no further step and its later assembly and
+ * one-workgroup Cholesky work is skipped, while the other windows of a batch
+ * go on; report->iters_done counts the steps applied, report->costs[t] stays
+ * at the frozen value, report->cost_after is F at the state left behind.  The
+ * same `iters` launches are made (one graph per shape and tolerance), so the
+ * time saved is that of the skipped work.  0 (the default) never stops.
+ * Errors: VI_EINVAL for a null context or rel_tol outside [0, 1). */
+vi_status vi_ctx_set_tolerance(vi_ctx* ctx, double rel_tol);
+
 /* ---------------------------------------------------------------------------
  * Learned warm start.  The paper's step has no learned initialisation; this
  * is an addition: a small convolutional network proposes inverse-depth and

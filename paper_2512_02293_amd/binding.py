@@ -78,7 +78,7 @@ class Gaussians(C.Structure):
 
 EXPORTS = ["vi_ctx_create", "vi_ctx_destroy", "vi_ctx_set_stream", "vi_last_error", "vi_version",
            "imu_preintegrate", "vi_workspace_size", "vi_ba_step", "vi_ba_solve", "vi_workspace_size_batched",
-           "vi_ba_solve_batched", "vi_ctx_set_autotune", "vi_warm_param_count", "vi_warm_workspace_size",
+           "vi_ba_solve_batched", "vi_ctx_set_autotune", "vi_ctx_set_tolerance", "vi_warm_param_count", "vi_warm_workspace_size",
            "vi_warm_features", "vi_warm_forward", "vi_warm_gradients", "vi_warm_adamw", "vi_warm_apply",
            "vi_warm_start_workspace_size", "vi_warm_start", "vi_ba_solve_warm", "vi_reanchor_workspace_size",
            "vi_gaussian_reanchor", "vi_predict_keyframe", "vi_inertial_init_workspace_size",
@@ -123,6 +123,8 @@ def load(path: str = LIB_PATH):
     lib.vi_ba_solve_batched.restype = C.c_int
     lib.vi_ctx_set_autotune.argtypes = [C.c_void_p, C.c_int32]
     lib.vi_ctx_set_autotune.restype = C.c_int
+    lib.vi_ctx_set_tolerance.argtypes = [C.c_void_p, C.c_double]
+    lib.vi_ctx_set_tolerance.restype = C.c_int
     vp, i32, f32 = C.c_void_p, C.c_int32, C.c_float
     lib.vi_warm_param_count.argtypes = []
     lib.vi_warm_param_count.restype = i32
@@ -295,6 +297,10 @@ class Context:
 
     def set_autotune(self, enable: bool):
         self._check(self.lib.vi_ctx_set_autotune(self.h, int(bool(enable))))
+
+    def set_tolerance(self, rel_tol: float):
+        """Tolerance stop of later solves on this context (vi_ctx_set_tolerance); 0 turns it off."""
+        self._check(self.lib.vi_ctx_set_tolerance(self.h, float(rel_tol)))
 
     # -- batches of independent windows ---------------------------------------
     def _windows(self, probs, imus, with_reports, costs, iters, stage_ms=False):

@@ -55,6 +55,7 @@ struct vi_ctx {
   int attr_kmax = -1;
   // autotuning
   bool autotune = false;
+  double tol = 0.0;                // tolerance stop of the solves (0: off)
   std::map<std::tuple<int, int, int, int>, int> tuned;
   // graph cache
   bool have_graph = false;
@@ -581,7 +582,7 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
   Work w = do_carve(P, workspace, nullptr);
   const WarmWork ww = wa ? warm_carve(P, wa->hq, wa->wq, workspace, nullptr) : WarmWork{};
   OptsDev od{o->n_fixed, o->use_imu ? 1 : 0, o->bias_fixed ? 1 : 0, o->precision, o->lm_lambda, o->depth_eta,
-             o->z_min, o->d_min};
+             o->z_min, o->d_min, ctx->tol};
   const bool timing = wins[0].rep && wins[0].rep->stage_ms;
 
   // order after the caller's pending work
@@ -631,6 +632,9 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
     key.push_back(ctx->plan_version);
     key.push_back((uint64_t)iters);
     key.push_back((uint64_t)P.range);
+    uint64_t tb;
+    std::memcpy(&tb, &od.tol, sizeof(tb));
+    key.push_back(tb);
     uint64_t ob[sizeof(vi_opts) / 8];
     std::memcpy(ob, o, sizeof(vi_opts));
     key.insert(key.end(), ob, ob + sizeof(vi_opts) / 8);
@@ -768,6 +772,13 @@ vi_status vi_ctx_set_stream(vi_ctx* ctx, void* stream) {
 vi_status vi_ctx_set_autotune(vi_ctx* ctx, int32_t enable) {
   if (!ctx) return VI_EINVAL;
   ctx->autotune = enable != 0;
+  return VI_OK;
+}
+
+vi_status vi_ctx_set_tolerance(vi_ctx* ctx, double rel_tol) {
+  if (!ctx) return VI_EINVAL;
+  if (!(rel_tol >= 0.0 && rel_tol < 1.0)) return fail(ctx, VI_EINVAL, "rel_tol must be in [0, 1)");
+  ctx->tol = rel_tol;
   return VI_OK;
 }
 

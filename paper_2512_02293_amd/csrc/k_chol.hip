@@ -599,7 +599,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   const int w = blockIdx.x;
   const WinDev& W = D.win[w];
   const int npad = W.npad, nblk = W.nblk, n = W.n;
-  if (npad > kSmallMaxNpad) return;
+  if (npad > kSmallMaxNpad || stall[w].conv != 0) return;   // frozen windows take no step
   const int bw = W.band;
   double* A = Aall + W.A_off;
   double* Lv = Linvall + W.Linv_off;

@@ -443,20 +443,22 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
                                                           double* __restrict__ Cd, double* __restrict__ wd,
                                                           double* __restrict__ hpart, double* __restrict__ gpart,
                                                           double* __restrict__ vcost, double* __restrict__ Hf,
-                                                          double* __restrict__ gf, double* __restrict__ icost) {
+                                                          double* __restrict__ gf, double* __restrict__ icost,
+                                                          const DevStatus* __restrict__ st) {
   constexpr bool kF64 = sizeof(R) == 8;
   extern __shared__ double sm[];
   __shared__ double red[2][kVisWaves];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   if ((int)blockIdx.y < imu_rows) {
     const int f = (int)blockIdx.y * (int)gridDim.x + (int)blockIdx.x;
-    if (f < F && o.use_imu) {
+    if (f < F && o.use_imu && !(st && st[D.win_of_f[f]].conv)) {   // frozen windows keep their blocks
       const WinDev W = D.win[D.win_of_f[f]];
       imu_factor_block(f, W, Lam, Hf, gf, icost, sm);
     }
     return;
   }
   const int src = blockIdx.y - imu_rows, kr = blockIdx.x;
+  if (st && st[D.win_of_kf[src]].conv) return;      // frozen by the tolerance stop: its state is unchanged
   const WinDev W = D.win[D.win_of_kf[src]];
   const int HW = W.HW;
   const int p_beg = kr * range;
@@ -771,11 +773,20 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
                                                          double* __restrict__ ZB, double* __restrict__ ZV,
                                                          const double* __restrict__ vcost,
                                                          const double* __restrict__ icost, int use_imu,
-                                                         double* __restrict__ trace, int slot) {
+                                                         double* __restrict__ trace, int slot, double tol,
+                                                         DevStatus* __restrict__ st) {
   extern __shared__ double sm[];
   if ((int)blockIdx.x >= N) {
     const int w = blockIdx.x - N;
     cost_reduce_block(D.win[w], w, ncost, range, vcost, icost, use_imu, trace, slot, sm);
+    // tolerance stop: F at this linearisation point against the previous one
+    // (written by this same thread); once the relative decrease is at most tol
+    // the window takes no further step
+    if (threadIdx.x == 0 && st && tol > 0.0 && slot > 0) {
+      const double prev = trace[(size_t)w * kTraceLen + 2 * (slot - 1)];
+      const double cur = trace[(size_t)w * kTraceLen + 2 * slot];
+      if (!(prev - cur > tol * prev)) st[w].conv = 1;
+    }
     return;
   }
   const int src = blockIdx.x;
@@ -1107,7 +1118,7 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
   const int tid = threadIdx.x;
   if ((int)blockIdx.y >= N) {
     const int w = blockIdx.y - N;
-    if (blockIdx.x != 0 || st[w].code != 0) return;
+    if (blockIdx.x != 0 || st[w].code != 0 || st[w].conv != 0) return;
     const WinDev& W = D.win[w];
     const double* xw = x + W.x_off;
     for (int t = tid; t < W.N; t += 256) {
@@ -1129,7 +1140,7 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
   const int w = D.win_of_kf[src];
   const WinDev W = D.win[w];
   const int HW = W.HW;
-  if (st[w].code != 0 || (int)blockIdx.x * 256 >= HW) return;
+  if (st[w].code != 0 || st[w].conv != 0 || (int)blockIdx.x * 256 >= HW) return;
   const int ls = src - W.kf_base;
   const int e0 = D.src_off[src];
   const int k = D.src_off[src + 1] - e0;
@@ -1191,7 +1202,7 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
 
 __global__ void k_reset_status(DevStatus* st, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) { st[i].code = 0; st[i].detail = 0; st[i].iters = 0; st[i].pad = 0; }
+  if (i < n) { st[i].code = 0; st[i].detail = 0; st[i].iters = 0; st[i].conv = 0; }
 }
 
 // ---------------------------------------------------------------------------
@@ -1482,7 +1493,7 @@ void step_set_attributes(int kmax) {
 
 // the fused assembly (with the inertial factors) and the local blocks
 static void launch_front(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o, int iter,
-                         StageMark mark, void* mark_user) {
+                         StageMark mark, void* mark_user, DevStatus* st) {
   const int N = P.N;
   auto done = [&](int stage) { if (mark) mark(mark_user, stage); };
   const int F = (o.use_imu && P.F > 0) ? P.F : 0;
@@ -1492,24 +1503,24 @@ static void launch_front(hipStream_t s, const Plan& P, const DevPlan& D, const W
   auto kern = (o.precision == VI_PREC_MIXED) ? k_vis_gram<float> : k_vis_gram<double>;
   hipLaunchKernelGGL(kern, dim3(nkr_run, N + imu_rows), dim3(kVisThreads), vis_lds(P.kmax), s, o, D, imu_rows, F,
                      P.nkr_max, ncost, P.range, w.Lam, w.Rw, w.rel, w.Cd, w.wd, w.hpart, w.gpart, w.vcost, w.Hf,
-                     w.gf, w.icost);
+                     w.gf, w.icost, st);
   done(kStVis);
   hipLaunchKernelGGL(k_local, dim3(N + P.n_win), dim3(kLocalThreads), local_lds(P.kmax), s, N, P.nkr_max, ncost,
-                     P.range, D,
-                     w.Rw, w.rel, w.hpart, w.gpart, w.Z, w.ZB, w.ZV, w.vcost, w.icost, o.use_imu, w.trace, iter);
+                     P.range, D, w.Rw, w.rel, w.hpart, w.gpart, w.Z, w.ZB, w.ZV, w.vcost, w.icost, o.use_imu, w.trace,
+                     iter, o.tol, st);
   done(kStLocal);
 }
 
 void launch_tune_stages(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o,
                         StageMark mark, void* mark_user) {
-  launch_front(s, P, D, w, o, 0, mark, mark_user);
+  launch_front(s, P, D, w, o, 0, mark, mark_user, nullptr);
 }
 
 void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o, int iter,
                  DevStatus* st, StageMark mark, void* mark_user) {
   const int N = P.N;
   auto done = [&](int stage) { if (mark) mark(mark_user, stage); };
-  launch_front(s, P, D, w, o, iter, mark, mark_user);
+  launch_front(s, P, D, w, o, iter, mark, mark_user, st);
   size_t total_max = 0;
   for (const WinDev& W : P.win) total_max = std::max(total_max, (size_t)(W.npad + kCholNB) * W.npad);
   hipLaunchKernelGGL(k_assemble, dim3((unsigned)((total_max + 255) / 256), P.n_win), dim3(256), 0, s, o, D, w.Z,

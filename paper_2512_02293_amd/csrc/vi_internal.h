@@ -34,7 +34,7 @@ struct DevStatus {
   int code;
   int detail;
   int iters;
-  int pad;
+  int conv;          // 1 once the tolerance stop has frozen the window
 };
 
 // Per-window device descriptor.
@@ -122,6 +122,7 @@ struct Work {
 struct OptsDev {
   int n_fixed, use_imu, bias_fixed, precision;
   double lambda, eta, z_min, d_min;
+  double tol;        // relative cost decrease below which a window stops (0: never)
 };
 
 // learned warm-start network (k_wnet.hip)
