@@ -289,6 +289,7 @@ def extras(ctx):
             "per_window_ms_plain_total": r["ms_plain_per_window_total"],
             "per_window_ms_warm_total": r["ms_warm_per_window_total"],
             "per_window_speedup": r["ms_plain_per_window_total"] / r["ms_warm_per_window_total"],
+            "batch_tolerance_stop": r["stop"],
             "note": "batch: all windows in one set of launches, bounded by the slowest window; per window: each "
                     "window solved alone (sliding-window use), warm start = vi_warm_start (features, network, "
                     "corrections, cost check and device-side fallback) + GN"}

@@ -221,7 +221,7 @@ def _iters_to_tol(costs, target):
     return int(hit[0]) if hit.size else None
 
 
-def time_to_tol(ctx, net, probs, opts, max_iters=REF_ITERS, rel_tol=1e-6, reps=3):
+def time_to_tol(ctx, net, probs, opts, max_iters=REF_ITERS, rel_tol=1e-6, reps=3, stop_tol=1e-7):
     """Plain GN from the initial state vs the learned warm start (with the
     plain cost as the arbiter, vi_warm_start) followed by GN.
 
@@ -236,7 +236,12 @@ def time_to_tol(ctx, net, probs, opts, max_iters=REF_ITERS, rel_tol=1e-6, reps=3
         k_plain(w) iterations vs warm start + k_warm(w) iterations, summed
         over the windows.
     The warm path is one vi_ba_solve_warm call (warm start and GN in one
-    graph); the plain path one vi_ba_solve_batched call."""
+    graph); the plain path one vi_ba_solve_batched call.
+      * batch with the tolerance stop (vi_ctx_set_tolerance, stop_tol): the
+        same max(K_plain, K_warm) launches each way, every window frozen once
+        its relative cost decrease falls to stop_tol, so that the time follows
+        the work of the windows still iterating; reported with how many
+        windows end at or below their target."""
     import torch
     dps, imus = _upload(ctx, probs)
     nb = max(ctx.workspace_size_batched(dps, opts), ctx.warm_start_workspace_size(dps, opts))
@@ -285,6 +290,22 @@ def time_to_tol(ctx, net, probs, opts, max_iters=REF_ITERS, rel_tol=1e-6, reps=3
 
     t_batch_plain = timed(lambda: gn(dps, imus, K_plain))
     t_batch_warm = timed(lambda: warm(dps, imus, K_warm))
+    K = max(K_plain, K_warm)
+    ctx.set_tolerance(stop_tol)
+    try:
+        reset()
+        stop_plain = ctx.solve_batched(dps, imus, opts, K, ws)
+        reset()
+        stop_warm = ctx.solve_warm(dps, imus, opts, net.params, K, ws)
+        t_stop_plain = timed(lambda: gn(dps, imus, K))
+        t_stop_warm = timed(lambda: warm(dps, imus, K))
+    finally:
+        ctx.set_tolerance(0.0)
+    stop = dict(tol=stop_tol, iters=K, ms_plain=1e3 * t_stop_plain, ms_warm=1e3 * t_stop_warm,
+                steps_plain=int(sum(r["iters_done"] for r in stop_plain)),
+                steps_warm=int(sum(r["iters_done"] for r in stop_warm)),
+                reached_plain=int(sum(bool(r["cost_after"] <= t) for r, t in zip(stop_plain, target))),
+                reached_warm=int(sum(bool(r["cost_after"] <= t) for r, t in zip(stop_warm, target))))
     t_win_plain = t_win_warm = 0.0
     for d, im, kp, kw in zip(dps, imus, k_plain, k_warm):
         gn([d], [im], kp)                               # graph of this shape and count, captured once
@@ -294,4 +315,4 @@ def time_to_tol(ctx, net, probs, opts, max_iters=REF_ITERS, rel_tol=1e-6, reps=3
     return dict(k_plain=k_plain, k_warm=k_warm, accepted=accepted, reached=reached, K_plain=K_plain, K_warm=K_warm,
                 ms_plain=1e3 * t_batch_plain, ms_warm=1e3 * t_batch_warm,
                 ms_plain_per_window_total=1e3 * t_win_plain, ms_warm_per_window_total=1e3 * t_win_warm,
-                final_plain=[c[-1] for c in plain_costs], final_warm=[c[-1] for c in warm_costs])
+                final_plain=[c[-1] for c in plain_costs], final_warm=[c[-1] for c in warm_costs], stop=stop)
