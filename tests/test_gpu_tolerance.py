@@ -126,3 +126,34 @@ def test_tolerance_stop_single_window_and_errors(ctx):
     for bad in (-1e-3, 1.0, float("nan")):
         with pytest.raises(binding.ViError, match="EINVAL"):
             ctx.set_tolerance(bad)
+
+
+def test_tolerance_stop_after_the_warm_start(ctx):
+    """vi_ba_solve_warm with the stop: the warm start is unchanged (the same
+    corrections kept), and each window's Gauss-Newton part stops where the
+    trace of the same call without the stop meets the rule."""
+    import torch
+    from paper_2512_02293_amd import binding, warmstart
+    iters, tol = 8, 1e-6
+    probs = warmstart.eval_windows(4)
+    opts = warmstart.study_opts()
+    dps = [binding.DeviceProblem(p) for p in probs]
+    imus = [ctx.imu_preintegrate(d.off, d.gyro, d.accel, d.imu_dt, d.bias_hat, d.noise) for d in dps]
+    ws = torch.empty(ctx.warm_start_workspace_size(dps, opts), dtype=torch.uint8, device="cuda:0")
+    theta = torch.as_tensor(np.ascontiguousarray(np.load(warmstart.PARAMS_FILE)), dtype=torch.float32,
+                            device="cuda:0")
+    ctx.set_tolerance(0.0)
+    plain = ctx.solve_warm(dps, imus, opts, theta, iters, ws, costs=True)
+    expected = [_expected_stop(r["costs"], tol, iters) for r in plain]
+    print("expected stops", expected, flush=True)
+    assert any(k < iters for k in expected)
+    for d in dps:
+        d.reset_state()
+    ctx.set_tolerance(tol)
+    got = ctx.solve_warm(dps, imus, opts, theta, iters, ws, costs=True)
+    ctx.set_tolerance(0.0)
+    for r, g, k in zip(plain, got, expected):
+        assert g["accepted"] == r["accepted"]
+        assert g["iters_done"] == k, (g["iters_done"], k)
+        np.testing.assert_allclose(g["costs"][:k + 1], r["costs"][:k + 1], rtol=1e-12)
+        np.testing.assert_allclose(g["costs"][k:], g["costs"][k], rtol=1e-12)
