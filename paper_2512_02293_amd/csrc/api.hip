@@ -251,7 +251,7 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
     x_off += (size_t)W.npad;
     P.nblk_max = std::max(P.nblk_max, W.nblk);
     std::vector<std::vector<std::pair<int, int>>> items((size_t)W.N * W.N);
-    int bw_kf = 1;   // inertial factors couple consecutive keyframes
+    int bw_vis = 0;   // keyframe distance of the vision terms' pose-pose couplings
     for (int g = W.kf_base; g < W.kf_base + W.N; ++g) {
       const int k = cnt[g];
       std::vector<int> T(1, g - W.kf_base);
@@ -259,11 +259,14 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
       for (int ta = 0; ta <= k; ++ta)
         for (int tb = 0; tb <= k; ++tb) {
           items[(size_t)T[ta] * W.N + T[tb]].push_back({P.z_off[g] + (ta * (k + 1) + tb) * 36, P.zb_off[g] + 6 * ta});
-          bw_kf = std::max(bw_kf, std::abs(T[ta] - T[tb]));
+          bw_vis = std::max(bw_vis, std::abs(T[ta] - T[tb]));
         }
     }
-    // scalar half-bandwidth of S and the tile band of S and of its factor
-    const int wsc = 15 * bw_kf + 14;
+    // scalar half-bandwidth of S and the tile band of S and of its factor: the
+    // vision terms couple only the 6 pose unknowns at the head of each
+    // keyframe's 15 (15 d + 5 apart for keyframes d apart), the inertial factors
+    // the full blocks of consecutive keyframes (15 + 14)
+    const int wsc = std::max(15 * bw_vis + 5, 15 + 14);
     W.band = std::min(W.nblk - 1, (wsc + kCholNB - 1) / kCholNB);
     // this window's table: entries pair_base .. pair_base + N*N (the last one is its end)
     W.pair_base = (int)P.pair_off.size();
