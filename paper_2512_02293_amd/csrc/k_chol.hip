@@ -593,7 +593,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   __shared__ double Li[2][NB * LD];             // L_bb^-1 of the current and the next column
   __shared__ double U[16 * 17];
   __shared__ double yv[kSmallMaxNpad];          // right-hand side -> y = L^-1 s -> running rhs of L^T x = y
-  __shared__ int yready;                        // step b + 1 once rows of block b + 1 of yv are updated
+  __shared__ int ydone;                         // step b once block b of yv holds y_b = L_bb^-1 s_b
   __shared__ int pready[kPanelSlots];           // step b + 1 once panel tile u of column b is in LDS
   __shared__ int xdone;                         // back-substitution: blocks of x published so far
   const int w = blockIdx.x;
@@ -630,7 +630,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   }
   __syncthreads();
   if (wave == 0) fwd_block(Li[0], yv);
-  if (tid == 0) yready = 0;
+  if (tid == 0) ydone = 0;
   if (tid == 0) xdone = 0;
   if (tid < kPanelSlots) pready[tid] = 0;
   __syncthreads();
@@ -654,6 +654,12 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
         Lv[(size_t)b * NB * NB + e] = Lc[(e >> 5) * LD + (e & 31)];
       }
     }
+    // y_b = L_bb^-1 s_b (its rows were completed during the previous step) on
+    // wave 1, off the look-ahead chain; the forward substitution waits for it
+    if (b > 0 && wave == 1) {
+      fwd_block(Lc, yv + NB * b);
+      lds_publish(&ydone, b);
+    }
     // panel: L_ib = A_ib L_bb^-T, b < i <= hi -> global (for the back-solve) and LDS
     for (int u = pw; u < m; u += NW) {
       const int i = b + 1 + u;
@@ -676,8 +682,9 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
     // other consumers wait for the flags of the tiles they read (the panel's
     // global copy is read only by the back-solve, after full barriers)
     // forward substitution: s_i -= L_ib y_b, one thread per row of the panel
-    // on the six compute waves; block b + 1 (wave 1) is flagged for wave 0
+    // on the six compute waves, once y_b is in
     if (wave != 0 && wave != 4) {
+      lds_wait(&ydone, b);
       const int t6 = cw * 64 + lane;
       for (int u = t6 >> 5; u < m; u += 12) {
         const int r = t6 & 31;
@@ -688,12 +695,10 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
         for (int q = 0; q < NB; ++q) v += Pu[swz(r, q)] * yv[NB * b + q];
         yv[NB * (b + 1 + u) + r] -= v;
       }
-      if (wave == 1) lds_publish(&yready, b + 1);
     }
     if (m > 0) {
       if (wave == 0) {
-        // look-ahead: the next diagonal tile (its rhs rows were updated by this
-        // wave just above), its factor, inverse and forward block
+        // look-ahead: the next diagonal tile, its factor and inverse
         const int nb1 = b + 1;
         double4_t acc[2][2];
         if (lds)
@@ -705,9 +710,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
         double* Ln = Li[nb1 & 1];
         const int bad = factor_invert32(T, Ln, U);
         if (bad >= 0 && lane == 0 && NB * nb1 + bad < n) set_status(stall + w, VI_ENOTPD, NB * nb1 + bad);
-        // rows of block b + 1 of yv come from wave 1 (it never waits on this wave)
-        lds_wait(&yready, b + 1);
-        fwd_block(Ln, yv + NB * nb1);           // its global copy is written during the next step
+        // its global copy and y_{b+1} are formed during the next step
       } else {
         // trailing update (i, j), b < j <= i <= hi, except (b+1, b+1); in LDS
         // mode also the copies of the next step's inputs that no update
