@@ -60,7 +60,7 @@ typedef enum {
   VI_ENOMEM = -2,        /* workspace too small or device allocation failed */
   VI_EDEVICE = -3,       /* HIP runtime error */
   VI_ENOTPD = -4,        /* reduced system not positive definite (pivot <= 0) */
-  VI_ENONFINITE = -5,    /* non-finite value in the assembled system */
+  VI_ENONFINITE = -5,    /* non-finite value in the assembled system or in an inverse depth */
   VI_EUNSUPPORTED = -6   /* option combination not implemented */
 } vi_status;
 
@@ -314,7 +314,9 @@ vi_status vi_warm_adamw(vi_ctx* ctx, float* params, const float* grads, float* m
 
 /* Apply corrections in place: inverse depth d <- max(d + up(dd), opts->d_min),
  * up = bilinear upsampling of the keyframe's cell grid (cell centres at
- * 4 c + 1.5, clamped at the borders); bias b <- b + db. */
+ * 4 c + 1.5, clamped at the borders); bias b <- b + db when the step solves
+ * the biases (opts->use_imu set and opts->bias_fixed clear), otherwise the
+ * biases are left as they are. */
 vi_status vi_warm_apply(vi_ctx* ctx, int32_t n_windows, const vi_window* windows, const vi_opts* opts, int32_t hq,
                         int32_t wq, const float* dd, const float* db);
 
@@ -332,7 +334,8 @@ size_t vi_warm_start_workspace_size(int32_t n_windows, const vi_window* windows,
  * largest cell grid of the windows (maps up to 64 x 96 pixels); F at the
  * corrected state; and every window whose corrected F is not below its
  * initial F (or is not finite) put back to its initial inverse depths and
- * biases.  Poses and velocities are never changed.  Per window:
+ * biases.  Poses and velocities are never changed, nor are the biases when
+ * opts leaves them unsolved (use_imu clear or bias_fixed set).  Per window:
  * accepted[w] (host, optional) = 1 if the corrections were kept; the
  * window's report (optional) gets cost_before = initial F, cost_after = F of
  * the state left behind, iters_done = 0, and costs[0..1] = the initial and

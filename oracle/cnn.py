@@ -39,8 +39,11 @@ over each cell).  Training uses AdamW (decoupled weight decay).
 Test infrastructure (see the package header).  Pinned by: conv3x3 against
 scipy.signal.correlate2d, the whole backward pass against central finite
 differences, the AdamW step against its closed form for zero moments, the
-upsampling against constant and linear inputs, and zero residual channels on
-noiseless ground truth.
+upsampling against constant and linear inputs, zero residual channels on
+noiseless ground truth, every input channel of a hand-built two-keyframe
+window against values worked out from its geometry (unequal x / y weights,
+a factor with known deltas), and the loss against its value on a two-image
+example with a masked cell.
 """
 import numpy as np
 

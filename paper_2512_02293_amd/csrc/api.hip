@@ -1061,7 +1061,8 @@ vi_status vi_warm_apply(vi_ctx* ctx, int32_t n_windows, const vi_window* windows
   s = warm_windows(ctx, n_windows, windows, opts, hq, wq, wins);
   if (s != VI_OK) return s;
   if ((s = warm_begin(ctx)) != VI_OK) return s;
-  launch_warm_apply(ctx->priv, ctx->plan, ctx->dplan, hq, wq, dd, db, opts->d_min);
+  launch_warm_apply(ctx->priv, ctx->plan, ctx->dplan, hq, wq, dd, db, opts->d_min,
+                    (opts->use_imu && !opts->bias_fixed) ? 1 : 0);
   return warm_end(ctx);
 }
 

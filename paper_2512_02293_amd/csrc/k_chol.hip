@@ -375,24 +375,29 @@ __device__ __forceinline__ void lds_publish(int* f, int v) {
 
 // Wait until *f == v in every active lane (f may differ between lanes); the
 // publishing waves never wait on the waiting one, so the wait ends; it is
-// bounded all the same.
-__device__ __forceinline__ void lds_wait(const int* f, int v) {
-  for (int spin = 0; spin < (1 << 22); ++spin) {
+// bounded all the same.  Returns false when the bound was reached (the
+// caller then fails the window: the data it waited for is not there).
+__device__ __forceinline__ bool lds_wait(const int* f, int v) {
+  bool ok = false;
+  for (int spin = 0; spin < kSpinLimit; ++spin) {
     const bool pending = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != v;
-    if (__ballot(pending) == 0) break;
+    if (__ballot(pending) == 0) { ok = true; break; }
     __builtin_amdgcn_s_sleep(1);
   }
   asm volatile("" ::: "memory");
+  return ok;
 }
 
 // Wait until *f >= v (a counter that only grows); bounded like lds_wait.
-__device__ __forceinline__ void lds_wait_ge(const int* f, int v) {
-  for (int spin = 0; spin < (1 << 22); ++spin) {
+__device__ __forceinline__ bool lds_wait_ge(const int* f, int v) {
+  bool ok = false;
+  for (int spin = 0; spin < kSpinLimit; ++spin) {
     const bool pending = __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) < v;
-    if (__ballot(pending) == 0) break;
+    if (__ballot(pending) == 0) { ok = true; break; }
     __builtin_amdgcn_s_sleep(1);
   }
   asm volatile("" ::: "memory");
+  return ok;
 }
 
 // global 32 x 32 tile -> swizzled LDS tile, all loads in flight at once (one wave)
@@ -639,6 +644,14 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   // copy of L_bb^-1, panel tiles beyond the seventh) and then every seventh
   // trailing tile; the six other waves take the panel, the forward
   // substitution and the rest of the trailing update.
+  // a bounded wait that expired fails the window (VI_EDEVICE): the solution is
+  // not used and the window's state is left as it was
+  auto wait_eq = [&](const int* f, int v) {
+    if (!lds_wait(f, v) && lane == 0) set_status(stall + w, VI_EDEVICE, -2);
+  };
+  auto wait_ge = [&](const int* f, int v) {
+    if (!lds_wait_ge(f, v) && lane == 0) set_status(stall + w, VI_EDEVICE, -2);
+  };
   const int pw = wave < 4 ? wave : (wave == 4 ? 7 : wave - 1);   // panel order: 0,1,2,3,5,6,7, then 4
   const int cw = wave < 4 ? wave - 1 : wave - 2;                 // compute worker 0..5 (waves 1-3, 5-7)
   for (int b = 0; b < nblk; ++b) {
@@ -684,11 +697,11 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
     // forward substitution: s_i -= L_ib y_b, one thread per row of the panel
     // on the six compute waves, once y_b is in
     if (wave != 0 && wave != 4) {
-      lds_wait(&ydone, b);
+      wait_eq(&ydone, b);
       const int t6 = cw * 64 + lane;
       for (int u = t6 >> 5; u < m; u += 12) {
         const int r = t6 & 31;
-        lds_wait(&pready[u], b + 1);
+        wait_eq(&pready[u], b + 1);
         const double* Pu = Pc + u * NB * NB;
         double v = 0.0;
 #pragma unroll
@@ -735,8 +748,8 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
           double4_t acc[2][2];
           double* Aij = A + (size_t)(NB * i) * npad + NB * j;
           load_tile32(acc, Aij, npad);
-          lds_wait(&pready[i - b - 1], b + 1);
-          lds_wait(&pready[j - b - 1], b + 1);
+          wait_eq(&pready[i - b - 1], b + 1);
+          wait_eq(&pready[j - b - 1], b + 1);
           mm32_abt_lds(acc, Pc + (i - b - 1) * NB * NB, Pc + (j - b - 1) * NB * NB, -1.0);
           if (lds && j == b + 1)
             acc_to_swz(acc, colbuf(b + 1) + (i - b - 2) * NB * NB);
@@ -767,7 +780,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   const int q = lane & 31, half = lane >> 5;
   for (int b = nblk - 1; b >= 0; --b) {
     if (b % NW == wave) {
-      lds_wait_ge(&xdone, nblk - 1 - b);        // x_{b+1} is out, so is the last update of y_b
+      wait_ge(&xdone, nblk - 1 - b);        // x_{b+1} is out, so is the last update of y_b
       if (lane < NB) {
         const double* Lb = P + b * NB * NB;
         double v = 0.0;
@@ -782,7 +795,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
       double pre[16];
 #pragma unroll
       for (int uu = 0; uu < 16; ++uu) pre[uu] = A[(size_t)(NB * b + 16 * half + uu) * npad + NB * c + q];
-      lds_wait_ge(&xdone, nblk - b);
+      wait_ge(&xdone, nblk - b);
       double v = 0.0;
 #pragma unroll
       for (int uu = 0; uu < 16; ++uu) v += pre[uu] * xs[NB * b + 16 * half + uu];

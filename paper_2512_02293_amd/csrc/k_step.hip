@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
                                                           double* __restrict__ hpart, double* __restrict__ gpart,
                                                           double* __restrict__ vcost, double* __restrict__ Hf,
                                                           double* __restrict__ gf, double* __restrict__ icost,
-                                                          const DevStatus* __restrict__ st) {
+                                                          DevStatus* __restrict__ st) {
   constexpr bool kF64 = sizeof(R) == 8;
   extern __shared__ double sm[];
   __shared__ double red[2][kVisWaves];
@@ -591,6 +591,8 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
     part[kVisWaves * 64 + wave * 64 + lane] = Wp;
     __syncthreads();
     if (wave == 0) {
+      // a non-finite inverse depth fails the window (the state is left as it is)
+      if (st && inpx && !isfinite(d)) set_status(st + D.win_of_kf[src], VI_ENONFINITE, -1);
       double C = o.eta, Wv = 0.0;
 #pragma unroll
       for (int q = 0; q < kVisWaves; ++q) {
@@ -1254,7 +1256,8 @@ __global__ void __launch_bounds__(256) k_vis_cost(OptsDev o, DevPlan D, int ncos
       dsrc = warm_corrected_depth(W, src, pc, HQ, WQ, dd, dsrc, d_min);
       W.invdepth[(size_t)ls * HW + pc] = dsrc;
     }
-    if (kr == 0 && tid < 6) W.bias[(size_t)ls * 6 + tid] += (double)db[(size_t)src * 6 + tid];
+    // biases that the step does not solve (no inertial terms, or held fixed) keep their value
+    if (kr == 0 && tid < 6 && o.use_imu && !o.bias_fixed) W.bias[(size_t)ls * 6 + tid] += (double)db[(size_t)src * 6 + tid];
   }
   const R d = (R)dsrc;
   const R fx = (R)W.fx, fy = (R)W.fy, cx = (R)W.cx, cy = (R)W.cy;
@@ -1419,14 +1422,15 @@ __global__ void __launch_bounds__(256) k_warm_features(OptsDev o, DevPlan D, int
 
 // Apply the proposed corrections: d <- max(d + up4(dd), d_min) per pixel, where
 // up4 reads the keyframe's cell grid bilinearly at ((y - 1.5) / 4, (x - 1.5) / 4)
-// clamped to the grid, and b <- b + db per keyframe.
+// clamped to the grid, and b <- b + db per keyframe when the biases are
+// solved (apply_bias; otherwise they keep their value).
 __global__ void __launch_bounds__(256) k_warm_apply(DevPlan D, int HQ, int WQ, const float* __restrict__ dd,
-                                                    const float* __restrict__ db, double d_min) {
+                                                    const float* __restrict__ db, double d_min, int apply_bias) {
   const int src = blockIdx.y;
   const WinDev W = D.win[D.win_of_kf[src]];
   const int ls = src - W.kf_base;
   const int p = blockIdx.x * 256 + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x < 6) W.bias[(size_t)ls * 6 + threadIdx.x] += (double)db[(size_t)src * 6 + threadIdx.x];
+  if (apply_bias && blockIdx.x == 0 && threadIdx.x < 6) W.bias[(size_t)ls * 6 + threadIdx.x] += (double)db[(size_t)src * 6 + threadIdx.x];
   if (p >= W.HW) return;
   double* dep = W.invdepth + (size_t)ls * W.HW + p;
   *dep = warm_corrected_depth(W, src, p, HQ, WQ, dd, *dep, d_min);
@@ -1554,8 +1558,9 @@ void launch_warm_features(hipStream_t s, const Plan& P, const DevPlan& D, const 
 }
 
 void launch_warm_apply(hipStream_t s, const Plan& P, const DevPlan& D, int HQ, int WQ, const float* dd,
-                       const float* db, double d_min) {
-  hipLaunchKernelGGL(k_warm_apply, dim3((P.hw_max + 255) / 256, P.N), dim3(256), 0, s, D, HQ, WQ, dd, db, d_min);
+                       const float* db, double d_min, int apply_bias) {
+  hipLaunchKernelGGL(k_warm_apply, dim3((P.hw_max + 255) / 256, P.N), dim3(256), 0, s, D, HQ, WQ, dd, db, d_min,
+                     apply_bias);
 }
 
 void launch_warm_state(hipStream_t s, const Plan& P, const DevPlan& D, double* saved_d, double* saved_b,

@@ -203,7 +203,7 @@ void launch_warm_features(hipStream_t s, const Plan& P, const DevPlan& D, const 
                           float* feat, int* dims, double* saved_d = nullptr,
                           double* saved_b = nullptr);
 void launch_warm_apply(hipStream_t s, const Plan& P, const DevPlan& D, int HQ, int WQ, const float* dd,
-                       const float* db, double d_min);
+                       const float* db, double d_min, int apply_bias);
 void launch_warm_state(hipStream_t s, const Plan& P, const DevPlan& D, double* saved_d, double* saved_b,
                        const double* trace, int restore);
 

@@ -92,6 +92,7 @@ class SceneConfig:
     imu_rate: float = 200.0
     kf_gap: int = 20                    # IMU samples between keyframes
     gap_range: Optional[Tuple[int, int]] = None   # uniform integer gaps instead
+    gaps: Optional[List[int]] = None    # explicit IMU samples per keyframe gap (n_kf - 1 of them)
     sigma_px: float = 0.5
     w_lo: float = 0.1
     w_hi: float = 1.0
@@ -271,7 +272,7 @@ def _edge_list(cfg: SceneConfig, rng: np.random.Generator):
             jj.append(j)
     have = set(zip(ii, jj))
     n_loop = 0
-    period_kf = int(round(TRAJ_PERIOD_S * cfg.imu_rate / cfg.kf_gap)) if cfg.gap_range is None else 0
+    period_kf = int(round(TRAJ_PERIOD_S * cfg.imu_rate / cfg.kf_gap)) if (cfg.gap_range is None and cfg.gaps is None) else 0
     tries = 0
     while n_loop < cfg.n_loop and tries < 100000:
         tries += 1
@@ -344,7 +345,10 @@ def make_problem(cfg: SceneConfig, seed: int, bias_hat_mode: str = "zero") -> Pr
     rng = np.random.default_rng(seed)
     N = cfg.n_kf
     dt_imu = 1.0 / cfg.imu_rate
-    if cfg.gap_range is None:
+    if cfg.gaps is not None:
+        assert len(cfg.gaps) == N - 1
+        gaps = np.asarray(cfg.gaps, dtype=np.int64)
+    elif cfg.gap_range is None:
         gaps = np.full(N - 1, cfg.kf_gap, dtype=np.int64)
     else:
         gaps = rng.integers(cfg.gap_range[0], cfg.gap_range[1] + 1, size=N - 1)
@@ -453,6 +457,41 @@ def tiny_config(n_kf: int = 3, H: int = 4, W: int = 5, k_out: int = 2,
     """Tiny windows used for brute-force checks (finite differences, dense solves)."""
     return SceneConfig(n_kf=n_kf, H=H, W=W, k_out=k_out, noiseless=noiseless,
                        zero_bias=zero_bias, kf_gap=kf_gap)
+
+
+def add_degenerate_pixels(prob: Problem, seed: int, frac_near: float = 0.06, frac_nonpos: float = 0.02,
+                          frac_zero_w: float = 0.03, frac_zero_wx: float = 0.01, frac_no_info: float = 0.01) -> Problem:
+    """Plant the degenerate cases of the vision term in a problem's initial
+    state and weights (in place; returns the problem):
+      * frac_near of every keyframe's pixels get an inverse depth in [6, 25]
+        (points 4-17 cm from camera i, so most of their pixel-residuals lie
+        within z_min of camera j and are not valid, some just beyond it);
+      * frac_nonpos get an inverse depth of 0 or a negative one (not valid);
+      * frac_zero_w of the (edge, pixel) pairs get zero weight in both
+        coordinates, frac_zero_wx only in x;
+      * frac_no_info of every keyframe's pixels get zero weight on all of its
+        outgoing edges (no information: C = 0 before damping)."""
+    rng = np.random.default_rng(seed)
+    N, H, W = prob.invdepth.shape
+    HW = H * W
+    d = prob.invdepth.reshape(N, HW)
+    for i in range(N):
+        perm = rng.permutation(HW)
+        n1, n2, n3 = int(frac_near * HW), int(frac_nonpos * HW), int(frac_no_info * HW)
+        near, nonpos, noinfo = perm[:n1], perm[n1:n1 + n2], perm[n1 + n2:n1 + n2 + n3]
+        d[i, near] = rng.uniform(6.0, 25.0, size=n1)
+        d[i, nonpos] = np.where(rng.random(n2) < 0.5, 0.0, -rng.uniform(0.01, 1.0, size=n2))
+        w = prob.weight[prob.ii == i].reshape(-1, 2, HW)
+        w[:, :, noinfo] = 0.0
+        prob.weight[prob.ii == i] = w.reshape(-1, 2, H, W)
+    E = prob.n_edges
+    wt = prob.weight.reshape(E, 2, HW)
+    m0 = rng.random((E, HW)) < frac_zero_w
+    wt[:, 0][m0] = 0.0
+    wt[:, 1][m0] = 0.0
+    mx = rng.random((E, HW)) < frac_zero_wx
+    wt[:, 0][mx] = 0.0
+    return prob
 
 
 # --------------------------------------------------------------------------

@@ -1,10 +1,12 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Tolerances (per result, from the required accuracy of the step): the pose,
-velocity and bias increments agree norm-wise per group to 1e-4 relative, the
-inverse-depth increments to 1e-3 relative; integer results (valid pixel
-counts, iterations done) agree exactly.  Both sides run in FP64 here, so the
-measured errors are printed as well (they sit near 1e-10).
+Tolerances: the required accuracy of the step is 1e-4 relative per group of
+the pose, velocity and bias increments and 1e-3 on the inverse-depth
+increments.  Both sides run in FP64 here and compute the same damped step up
+to rounding order (measured 1e-13 .. 1e-10, printed), so the asserts are much
+tighter, 1e-8 relative per group and on the inverse-depth increments, and a
+dropped coupling or a mis-ordered update cannot hide below the required bar;
+integer results (valid pixel counts, iterations done) agree exactly.
 """
 import numpy as np
 import pytest
@@ -16,6 +18,7 @@ from paper_2512_02293_amd import synth
 pytestmark = pytest.mark.gpu
 
 GROUPS = {"dtheta": slice(0, 3), "dp": slice(3, 6), "dv": slice(6, 9), "dbg": slice(9, 12), "dba": slice(12, 15)}
+FP64_TOL = 1e-8
 
 
 @pytest.fixture(scope="module")
@@ -86,11 +89,11 @@ def _compare_step(rep, dxi, dd, orep, tag):
     print(tag, {k: f"{v:.2e}" for k, v in errs.items()})
     for g in GROUPS:
         if g in errs:
-            assert errs[g] <= 1e-4, (tag, g, errs[g])
-    assert errs["dd"] <= 1e-3, (tag, errs["dd"])
+            assert errs[g] <= FP64_TOL, (tag, g, errs[g])
+    assert errs["dd"] <= FP64_TOL, (tag, errs["dd"])
     assert rep["n_valid"] == orep["n_valid"], tag
     assert rep["cost_before"] == pytest.approx(orep["cost_before"], rel=1e-9), tag
-    assert rep["cost_after"] == pytest.approx(orep["cost_after"], rel=1e-6), tag
+    assert rep["cost_after"] == pytest.approx(orep["cost_after"], rel=1e-9), tag
 
 
 def test_library_is_native(ctx):
@@ -129,8 +132,8 @@ def _single_step_case(ctx, prob, **optkw):
     # committed state
     R_gpu = np.stack([so3.quat_to_R(q) for q in dp.pose.cpu().numpy()[:, 3:]])
     ang = max(np.linalg.norm(so3.Log(a.T @ b)) for a, b in zip(R_gpu, new.R))
-    assert ang <= 1e-4 * max(np.abs(orep["dxi"][:, 0:3]).max(), 1e-12) + 1e-12
-    assert np.abs(dp.invdepth.cpu().numpy() - new.d).max() <= 1e-3 * np.abs(orep["dd"]).max()
+    assert ang <= FP64_TOL * max(np.abs(orep["dxi"][:, 0:3]).max(), 1e-12) + 1e-13
+    assert np.abs(dp.invdepth.cpu().numpy() - new.d).max() <= FP64_TOL * np.abs(orep["dd"]).max()
 
 
 def test_step_small_window(ctx):

@@ -232,3 +232,36 @@ def test_solve_warm_equals_warm_start_then_solve(ctx):
                 assert np.array_equal(a, b)
         for r, g in zip(reps, got):
             assert np.array_equal(r["costs"], g["costs"]), (call, r["costs"], g["costs"])
+
+
+@pytest.mark.parametrize("mode", ["bias_fixed", "no_imu"])
+def test_warm_start_leaves_unsolved_biases(ctx, mode):
+    """With the biases left out of the step (bias_fixed, or no inertial terms),
+    neither the warm start nor the warm-started solve changes them: the
+    biases stay bit-identical while the inverse depths take the corrections."""
+    import torch
+    from paper_2512_02293_amd import binding, warmstart
+    probs = warmstart.eval_windows(4)
+    base = warmstart.study_opts()
+    kw = dict(n_fixed=base.n_fixed, lm_lambda=base.lm_lambda, depth_eta=base.depth_eta, z_min=base.z_min,
+              d_min=base.d_min)
+    opts = binding.make_opts(bias_fixed=True, **kw) if mode == "bias_fixed" else binding.make_opts(use_imu=False, **kw)
+    dps = [binding.DeviceProblem(p) for p in probs]
+    imus = [ctx.imu_preintegrate(d.off, d.gyro, d.accel, d.imu_dt, d.bias_hat, d.noise) for d in dps]
+    ws = torch.empty(ctx.warm_start_workspace_size(dps, opts), dtype=torch.uint8, device="cuda:0")
+    theta = _t(np.load(warmstart.PARAMS_FILE))
+    init = _state(dps)
+    # the network proposes a non-zero bias correction for these windows
+    feat, dims = ctx.warm_features(dps, imus, opts, warmstart.HQ, warmstart.WQ)
+    dd, db = ctx.warm_forward(theta, feat, dims)
+    assert float(db.abs().max()) > 0.0
+    ctx.warm_apply(dps, imus, opts, dd, db)
+    after = _state(dps)
+    for a, s0 in zip(after, init):
+        assert np.array_equal(a[1], s0[1])
+        assert not np.array_equal(a[0], s0[0])
+    for d in dps:
+        d.reset_state()
+    ctx.solve_warm(dps, imus, opts, theta, 2, ws)
+    for a, s0 in zip(_state(dps), init):
+        assert np.array_equal(a[1], s0[1])

@@ -139,3 +139,95 @@ def test_depth_step_channel_recovers_a_depth_offset():
         h += (w * Jd * Jd).sum(axis=0)
     ref = np.log1p(cnn.cell_mean(h.reshape(H, W), H, W))
     np.testing.assert_allclose(X[i, 14], ref, rtol=1e-6)
+
+
+def _hand_window():
+    """Two keyframes, identity rotations, keyframe 1 at (-0.1, 0, 0): the
+    edge 0 -> 1 has R_ji = I, t_ji = (0.1, 0, 0), so with fx = fy = 10 a pixel
+    (x, y) of inverse depth d projects to (x + d, y) and the inverse-depth
+    column of the Jacobian is (J_dx, J_dy) = (-1, 0).  4 x 8 pixels = two
+    4 x 4 cells.  The targets are that projection plus chosen residuals."""
+    from oracle.normal_eq import Camera, Graph, State
+    from oracle.preint import Preintegrated
+    from oracle.so3 import Exp
+    H, W = 4, 8
+    cam = Camera(10.0, 10.0, 0.0, 0.0, H, W, np.array([0.0, 0.0, -9.81]))
+    d0 = np.zeros((H, W))
+    d0[:, :4] = 0.5
+    d0[:, 4:] = np.array([1.0, 1.2, 1.4, 1.6])[:, None]
+    ys, xs = np.mgrid[0:H, 0:W].astype(float)
+    rx, ry = np.zeros((H, W)), np.zeros((H, W))
+    wx, wy = np.zeros((H, W)), np.zeros((H, W))
+    # cell 0: r_x = 1 (w_x = 1) on even columns, 3 (w_x = 0.2) on odd ones; r_y = -1 (w_y = 0.25)
+    even = (xs[:, :4] % 2) == 0
+    rx[:, :4] = np.where(even, 1.0, 3.0)
+    wx[:, :4] = np.where(even, 1.0, 0.2)
+    ry[:, :4], wy[:, :4] = -1.0, 0.25
+    # cell 1: r_x = 0 (w_x = 0.5); r_y = 2 (w_y = 0.1) on rows 0-1, 0 (w_y = 0.9) on rows 2-3
+    rx[:, 4:], wx[:, 4:] = 0.0, 0.5
+    ry[:2, 4:], wy[:2, 4:] = 2.0, 0.1
+    ry[2:, 4:], wy[2:, 4:] = 0.0, 0.9
+    target = np.stack([xs + d0 + rx, ys + ry])[None]
+    weight = np.stack([wx, wy])[None]
+    theta = np.array([0.01, -0.02, 0.005])
+    fac = Preintegrated(dt=0.1, dR=Exp(theta), dv=np.array([0.0, 0.2, 0.0]), dp=np.array([0.3, 0.0, 0.0]),
+                        J_rot=np.zeros((3, 3)), J_vel=np.zeros((3, 6)), J_pos=np.zeros((3, 6)), cov=np.eye(9),
+                        bias_hat=np.zeros(6), cov_bias=np.ones(6))
+    st = State(R=np.stack([np.eye(3)] * 2), p=np.array([[0.0, 0, 0], [-0.1, 0, 0]]),
+               v=np.array([[1.0, 0, 0], [1.0, 0, 0]]), b=np.zeros((2, 6)), d=np.stack([d0, np.full((H, W), 0.7)]))
+    gr = Graph(ii=np.array([0]), jj=np.array([1]), target=target, weight=weight, factors=[fac])
+    return cam, st, gr
+
+
+def test_features_hand_computed_cells():
+    """Every channel of a hand-built window against values worked out from its
+    geometry: weighted means with unequal x / y weights (ch 0-2), the cell
+    mean depth (ch 3), the inertial residual of a factor with known deltas at
+    a chosen state, scaled 100 / 10 / 10 (ch 4-12), and the depth-only step
+    and information with J_d = (-1, 0) (ch 13-14)."""
+    cam, st, gr = _hand_window()
+    X, mask = cnn.features(cam, st, gr)
+    assert X.shape == (2, 15, 1, 2) and mask.all()
+    c0, c1 = X[0, :, 0, 0], X[0, :, 0, 1]
+    # cell 0: sum w_x r_x = 8 * 1 + 8 * 0.2 * 3 = 12.8, sum w_x = 9.6; sum w_y r_y = -4, sum w_y = 4
+    assert c0[0] == pytest.approx(12.8 / (9.6 + 1e-6), rel=1e-14)
+    assert c0[1] == pytest.approx(-4.0 / (4.0 + 1e-6), rel=1e-14)
+    assert c0[2] == pytest.approx((9.6 + 4.0) / 32.0, rel=1e-14)
+    assert c0[3] == pytest.approx(0.5, rel=1e-14)
+    # J_dx = -1: sum w J_d r = -12.8, h = sum w_x = 9.6
+    assert c0[13] == pytest.approx(12.8 / (9.6 + 1e-6) / 0.2, rel=1e-12)
+    assert c0[14] == pytest.approx(np.log1p(9.6 / 16.0), rel=1e-14)
+    # cell 1: no x residual; sum w_y r_y = 8 * 0.1 * 2 = 1.6, sum w_y = 0.8 + 7.2 = 8
+    assert abs(c1[0]) < 1e-14
+    assert c1[1] == pytest.approx(1.6 / (8.0 + 1e-6), rel=1e-14)
+    assert c1[2] == pytest.approx((8.0 + 8.0) / 32.0, rel=1e-14)
+    assert c1[3] == pytest.approx(1.3, rel=1e-14)
+    assert abs(c1[13]) < 1e-13
+    assert c1[14] == pytest.approx(np.log1p(0.5), rel=1e-14)
+    # inertial residual of factor (0, 1): rotation Log(dR^T) = -theta;
+    # position p1 - p0 - v0 dt - g dt^2 / 2 - dp = (-0.5, 0, 0.04905);
+    # velocity v1 - v0 - g dt - dv = (0, -0.2, 0.981)
+    ref = np.concatenate([-100.0 * np.array([0.01, -0.02, 0.005]), 10.0 * np.array([-0.5, 0.0, 0.04905]),
+                          10.0 * np.array([0.0, -0.2, 0.981])])
+    for cell in (c0, c1):
+        np.testing.assert_allclose(cell[4:13], ref, rtol=1e-12, atol=1e-14)
+    # keyframe 1: no outgoing edge, last keyframe (no factor after it)
+    assert np.all(X[1, [0, 1, 2, 13, 14]] == 0.0) and np.all(X[1, 4:13] == 0.0)
+    np.testing.assert_allclose(X[1, 3], 0.7, rtol=1e-14)
+    # without inertial terms the constant planes are zero
+    Xn, _ = cnn.features(cam, st, gr, use_imu=False)
+    assert np.all(Xn[:, 4:13] == 0.0) and np.array_equal(Xn[:, :4], X[:, :4])
+
+
+def test_loss_closed_form():
+    """Two images on a 1 x 2 canvas, the second one cell wide: every valid
+    cell is off by s_d (term 1 each, mean over the 3 valid cells = 1; the
+    masked cell is off by 0.5 and must not count), and the bias corrections
+    are off by s_b in the first gyro axis of image 0 and by 2 s_b in the last
+    accelerometer axis of image 1 (sum 1 + 4 = 5, mean over 2 images = 2.5)."""
+    mask = np.array([[[1.0, 1.0]], [[1.0, 0.0]]])
+    dd_lab = np.array([[[0.1, -0.2]], [[0.3, 0.0]]])
+    dd = dd_lab + np.array([[[0.02, -0.02]], [[0.02, 0.5]]])
+    db_lab = np.array([[0.001, 0, 0, 0, 0, 0.2], [0, 0, 0, 0, 0, -0.1]])
+    db = db_lab + np.array([[0.005, 0, 0, 0, 0, 0], [0, 0, 0, 0, 0, 0.1]])
+    assert cnn.loss(dd, db, dd_lab, db_lab, mask) == pytest.approx(3.5, rel=1e-12)
