@@ -462,6 +462,19 @@ vi_status vi_gaussian_reanchor(vi_ctx* ctx, int32_t n_kf, const double* pose_pre
                                const double* scale_change, const vi_gaussians* g, void* workspace,
                                size_t workspace_bytes, int32_t* n_rejected);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid it): vi_gaussian_reanchor
+ * without a workspace.  The per-keyframe table lives in a fixed device array
+ * of the library (48 B per keyframe, at most 16384 keyframes = 768 KiB per
+ * GPU, held until the process ends); the call allocates nothing.  Same
+ * arguments, results, stream semantics and errors as vi_gaussian_reanchor,
+ * plus VI_EINVAL when n_kf exceeds 16384.  All calls on one GPU share that
+ * array: calls that can overlap on the same GPU (different streams or
+ * contexts without ordering between them) race and must not be issued;
+ * calls on one context's stream run in order and are safe. */
+vi_status vi_gaussian_reanchor_noalloc(vi_ctx* ctx, int32_t n_kf, const double* pose_pre, const double* pose_post,
+                                       const double* scale_change, const vi_gaussians* g, int32_t* n_rejected);
+
 #ifdef __cplusplus
 }
 #endif

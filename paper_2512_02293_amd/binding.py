@@ -81,7 +81,7 @@ EXPORTS = ["vi_ctx_create", "vi_ctx_destroy", "vi_ctx_set_stream", "vi_last_erro
            "vi_ba_solve_batched", "vi_ctx_set_autotune", "vi_ctx_set_tolerance", "vi_warm_param_count", "vi_warm_workspace_size",
            "vi_warm_features", "vi_warm_forward", "vi_warm_gradients", "vi_warm_adamw", "vi_warm_apply",
            "vi_warm_start_workspace_size", "vi_warm_start", "vi_ba_solve_warm", "vi_reanchor_workspace_size",
-           "vi_gaussian_reanchor", "vi_predict_keyframe", "vi_inertial_init_workspace_size",
+           "vi_gaussian_reanchor", "vi_gaussian_reanchor_noalloc", "vi_predict_keyframe", "vi_inertial_init_workspace_size",
            "vi_inertial_init_solve"]
 
 _lib = None
@@ -149,6 +149,8 @@ def load(path: str = LIB_PATH):
     lib.vi_reanchor_workspace_size.restype = C.c_size_t
     lib.vi_gaussian_reanchor.argtypes = [vp, i32, vp, vp, vp, C.POINTER(Gaussians), vp, C.c_size_t, vp]
     lib.vi_gaussian_reanchor.restype = C.c_int
+    lib.vi_gaussian_reanchor_noalloc.argtypes = [vp, i32, vp, vp, vp, C.POINTER(Gaussians), vp]
+    lib.vi_gaussian_reanchor_noalloc.restype = C.c_int
     lib.vi_predict_keyframe.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(C.c_double * 3), C.c_double, vp, vp, vp,
                                         vp]
     lib.vi_predict_keyframe.restype = C.c_int
@@ -402,7 +404,8 @@ class Context:
         int32 [K], means float32 [K][3], covariances float32 [K][6] (optional).
         Outputs default to the inputs (in place).  Asynchronous on the context's
         stream; n_rejected (device int32 [1], optional) receives the count of
-        Gaussians left unchanged."""
+        Gaussians left unchanged.  ws="noalloc" calls the allocation-free entry
+        point (vi_gaussian_reanchor_noalloc) instead."""
         import torch
         N = int(pose_pre.shape[0])
         K = int(anchor.shape[0])
@@ -419,9 +422,14 @@ class Context:
             _check_dev(cov_out, (K, 6), torch.float32, "cov_out")
         elif cov_out is not None:
             raise ValueError("cov_out given without cov_in")
+        g = Gaussians(K, _ptr(anchor), _ptr(mean_in), _ptr(cov_in), _ptr(mean_out), _ptr(cov_out))
+        if ws == "noalloc":
+            # vi_gaussian_reanchor_noalloc: the library's fixed keyframe table, no workspace
+            self._check(self.lib.vi_gaussian_reanchor_noalloc(self.h, N, _ptr(pose_pre), _ptr(pose_post),
+                                                              _ptr(scale_change), C.byref(g), _ptr(n_rejected)))
+            return
         if ws is None:
             ws = torch.empty(max(self.reanchor_workspace_size(N), 256), dtype=torch.uint8, device=mean_in.device)
-        g = Gaussians(K, _ptr(anchor), _ptr(mean_in), _ptr(cov_in), _ptr(mean_out), _ptr(cov_out))
         self._check(self.lib.vi_gaussian_reanchor(self.h, N, _ptr(pose_pre), _ptr(pose_post), _ptr(scale_change),
                                                   C.byref(g), _ptr(ws), ws.numel(), _ptr(n_rejected)))
 

@@ -737,7 +737,8 @@ vi_status vi_ctx_create(int32_t device, void* stream, vi_ctx** out) {
   vi_ctx* c = new vi_ctx();
   c->device = device;
   c->user = (hipStream_t)stream;
-  if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&c->priv, hipStreamNonBlocking) != hipSuccess ||
+  if (hipSetDevice(device) != hipSuccess || reanchor_scratch_init(device) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->priv, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming) != hipSuccess || ensure_status(c, 1) != VI_OK) {
     vi_ctx_destroy(c);
     return VI_EDEVICE;
@@ -1068,19 +1069,16 @@ vi_status vi_warm_apply(vi_ctx* ctx, int32_t n_windows, const vi_window* windows
 
 size_t vi_reanchor_workspace_size(int32_t n_kf) { return n_kf > 0 ? align256(reanchor_table_bytes(n_kf)) : 0; }
 
-vi_status vi_gaussian_reanchor(vi_ctx* ctx, int32_t n_kf, const double* pose_pre, const double* pose_post,
-                               const double* scale_change, const vi_gaussians* g, void* workspace,
-                               size_t workspace_bytes, int32_t* n_rejected) {
-  if (!ctx) return VI_EINVAL;
-  if (!g || !pose_pre || !pose_post || !scale_change || !workspace) return fail(ctx, VI_EINVAL, "null argument");
+// host checks shared by both Gaussian-map entry points
+static vi_status reanchor_check(vi_ctx* ctx, int32_t n_kf, const double* pose_pre, const double* pose_post,
+                                const double* scale_change, const vi_gaussians* g) {
+  if (!g || !pose_pre || !pose_post || !scale_change) return fail(ctx, VI_EINVAL, "null argument");
   if (n_kf < 1) return fail(ctx, VI_EINVAL, "need at least one keyframe");
   const int64_t K = g->n;
   if (K < 0 || K > reanchor_max_gaussians()) return fail(ctx, VI_EINVAL, "bad Gaussian count %lld", (long long)K);
   if ((g->cov_in == nullptr) != (g->cov_out == nullptr))
     return fail(ctx, VI_EINVAL, "cov_in and cov_out must both be given or both be NULL");
   if (K > 0 && (!g->anchor || !g->mean_in || !g->mean_out)) return fail(ctx, VI_EINVAL, "null Gaussian array");
-  if (workspace_bytes < reanchor_table_bytes(n_kf)) return fail(ctx, VI_ENOMEM, "workspace too small");
-  if (((uintptr_t)workspace & 15) != 0) return fail(ctx, VI_EINVAL, "workspace must be 16-byte aligned");
   // an output is either its input (in place) or disjoint from every input
   struct Range { const char* p; size_t n; };
   auto overlap = [](Range a, Range b) { return a.p < b.p + b.n && b.p < a.p + a.n; };
@@ -1094,8 +1092,39 @@ vi_status vi_gaussian_reanchor(vi_ctx* ctx, int32_t n_kf, const double* pose_pre
     if (overlap(mo, an) || (co.n && (overlap(co, an) || overlap(co, mi) || overlap(co, mo) || overlap(mo, ci))))
       return fail(ctx, VI_EINVAL, "an output overlaps another array");
   }
+  return VI_OK;
+}
+
+vi_status vi_gaussian_reanchor(vi_ctx* ctx, int32_t n_kf, const double* pose_pre, const double* pose_post,
+                               const double* scale_change, const vi_gaussians* g, void* workspace,
+                               size_t workspace_bytes, int32_t* n_rejected) {
+  if (!ctx) return VI_EINVAL;
+  vi_status s = reanchor_check(ctx, n_kf, pose_pre, pose_post, scale_change, g);
+  if (s != VI_OK) return s;
+  if (!workspace) return fail(ctx, VI_EINVAL, "null argument");
+  if (workspace_bytes < reanchor_table_bytes(n_kf)) return fail(ctx, VI_ENOMEM, "workspace too small");
+  if (((uintptr_t)workspace & 15) != 0) return fail(ctx, VI_EINVAL, "workspace must be 16-byte aligned");
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  launch_reanchor(ctx->user, n_kf, pose_pre, pose_post, scale_change, workspace, K, g->anchor, g->mean_in,
+  launch_reanchor(ctx->user, n_kf, pose_pre, pose_post, scale_change, workspace, g->n, g->anchor, g->mean_in,
+                  g->cov_in, g->mean_out, g->cov_out, n_rejected);
+  HIPCHK(ctx, hipGetLastError());
+  ctx->err.clear();
+  return VI_OK;
+}
+
+vi_status vi_gaussian_reanchor_noalloc(vi_ctx* ctx, int32_t n_kf, const double* pose_pre, const double* pose_post,
+                                       const double* scale_change, const vi_gaussians* g, int32_t* n_rejected) {
+  if (!ctx) return VI_EINVAL;
+  vi_status s = reanchor_check(ctx, n_kf, pose_pre, pose_post, scale_change, g);
+  if (s != VI_OK) return s;
+  if (n_kf > reanchor_noalloc_max_keyframes())
+    return fail(ctx, VI_EINVAL, "%d keyframes exceed the allocation-free limit of %d", n_kf,
+                reanchor_noalloc_max_keyframes());
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  void* table = reanchor_scratch(ctx->device);      // the device address, looked up when the context was created
+  if (!table) return fail(ctx, VI_EDEVICE, "no keyframe table on device %d", ctx->device);
+  // every row the map kernel reads (0 .. n_kf-1) is rewritten by this call first
+  launch_reanchor(ctx->user, n_kf, pose_pre, pose_post, scale_change, table, g->n, g->anchor, g->mean_in,
                   g->cov_in, g->mean_out, g->cov_out, n_rejected);
   HIPCHK(ctx, hipGetLastError());
   ctx->err.clear();

@@ -18,11 +18,25 @@
 // is read once.  Means and covariances pass through LDS so that global memory
 // sees only contiguous wave-wide float4 spans, with non-temporal loads and
 // stores (the map is streamed once per call).
+#include <mutex>
+
 #include "vi_internal.h"
 #include "vi_math.h"
 
 namespace vi {
+
+// Keyframe table of the allocation-free entry point: a file-scope device
+// array (one copy per GPU, kept until the process ends).  In host code its
+// name is only a stand-in: kernels get the device address obtained per device
+// by reanchor_scratch_init.  Every call on a GPU shares that GPU's copy, so
+// calls that overlap on one GPU race.
+constexpr int kReanchorNoAllocMaxKeyframes = 16384;          // 16384 x 48 B = 768 KiB
+static __device__ __align__(256) float4 scratch[3 * kReanchorNoAllocMaxKeyframes];
+
 namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
 
 constexpr int kGaussThreads = 256;
 constexpr int kGaussPerBlock = 4 * kGaussThreads;
@@ -219,6 +233,24 @@ void launch_map(hipStream_t s, int64_t blocks, int64_t K, int n_kf, const int32_
 }  // namespace
 
 size_t reanchor_table_bytes(int n_kf) { return (size_t)n_kf * 3 * sizeof(float4); }
+
+int reanchor_noalloc_max_keyframes() { return kReanchorNoAllocMaxKeyframes; }
+
+hipError_t reanchor_scratch_init(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
+
+void* reanchor_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < kMaxScratchDevices) ? g_scratch_ptr[device] : nullptr;
+}
 
 int64_t reanchor_max_gaussians() { return (int64_t)kGaussPerBlock * 0x7fffffffLL; }
 

@@ -192,6 +192,13 @@ void launch_inertial_init(hipStream_t s, int n, const IInitDesc* descs, int max_
 
 // loop-closure update of a Gaussian map (k_gauss.hip)
 size_t reanchor_table_bytes(int n_kf);
+// allocation-free variant: the keyframe table in a file-scope device array of
+// k_gauss.hip.  reanchor_scratch_init (with `device` current) looks up that
+// array's address on the device once; reanchor_scratch returns it (nullptr
+// before a successful init).
+int reanchor_noalloc_max_keyframes();
+hipError_t reanchor_scratch_init(int device);
+void* reanchor_scratch(int device);
 int64_t reanchor_max_gaussians();
 void launch_reanchor(hipStream_t s, int n_kf, const double* pose_pre, const double* pose_post, const double* ds,
                      void* table, int64_t K, const int32_t* anchor, const float* mean_in, const float* cov_in,
