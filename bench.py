@@ -29,6 +29,7 @@ if ROOT not in sys.path:
 METRIC = "pixel-residuals/s + ms per GN iter (24-KF window); time-to-tol learned vs plain"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 GN_ITERS = 8
 # kernel behind each stage of the benchmarked window, and the committed HBM
 # counter readings (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a plain copy)
@@ -69,7 +70,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 64-window batch, the global problem and the warm-start lines")
     ap.add_argument("--only", choices=["global", "warm-windows", "gaussian-reanchor", "predict-keyframe",
-                                       "inertial-init"],
+                                       "inertial-init", "assembly"],
                     default=None,
                     help="run only that secondary workload and print its JSON (profiling runs)")
     return ap.parse_args()
@@ -131,7 +132,8 @@ def main():
     if args.only is not None:
         ctx = binding.Context(0)
         out = {"global": global_problem, "warm-windows": warm_windows, "gaussian-reanchor": gaussian_reanchor,
-               "predict-keyframe": predict_keyframe, "inertial-init": inertial_init}[args.only](ctx)
+               "predict-keyframe": predict_keyframe, "inertial-init": inertial_init,
+               "assembly": assembly_roofline}[args.only](ctx)
         if args.copy_calibration:
             out["copy_calibration_bytes"] = copy_calibration()
         print(json.dumps(out))
@@ -294,6 +296,88 @@ def extras(ctx):
                     "window solved alone (sliding-window use), warm start = vi_warm_start (features, network, "
                     "corrections, cost check and device-side fallback) + GN"}
     return res
+
+
+def assembly_work(probs):
+    """Algorithmic work of one launch of the fused assembly on these windows:
+    HBM bytes per the per-pixel-residual count of the mixed path (target and
+    weight, FP32: 16 B per pixel-residual; the source's inverse depth read
+    and its increment written, FP32: 8 B per source pixel, i.e. 8/k B per
+    pixel-residual), and the symmetric half of the Schur Gram,
+    (6k)(6k + 1) flops per source pixel of a keyframe with k outgoing edges."""
+    import numpy as np
+    pxres = bytes_ = flops = 0.0
+    for p in probs:
+        HW = p.H * p.W
+        ks = np.bincount(p.ii, minlength=p.n_kf)
+        pxres += float(p.n_edges * HW)
+        bytes_ += 16.0 * p.n_edges * HW + 8.0 * int((ks > 0).sum()) * HW
+        flops += float(sum(6 * k * (6 * k + 1) for k in ks)) * HW
+    return pxres, bytes_, flops
+
+
+def assembly_roofline(ctx, reps=5):
+    """HBM and FP32-MFMA position of the fused assembly (k_vis_gram<float>,
+    the mixed path) on the two workloads whose inputs exceed the 256 MB
+    last-level cache: the 512-keyframe problem and the 64-window batch.  The
+    kernel time is the assembly stage of eager steps (HIP events recorded by
+    the library on its own stream around that one launch), best of `reps`."""
+    import torch
+
+    from paper_2512_02293_amd import binding, synth
+    o = binding.make_opts(precision=binding.VI_PREC_MIXED)
+    out = {}
+    # the 512-keyframe problem
+    prob = synth.make_problem(synth.config_global(), 3)
+    dp = binding.DeviceProblem(prob)
+    imu = ctx.imu_preintegrate(dp.off, dp.gyro, dp.accel, dp.imu_dt, dp.bias_hat, dp.noise)
+    ws = torch.empty(ctx.workspace_size(dp.cam, prob.n_kf, dp.ii, dp.jj, o), dtype=torch.uint8, device="cuda:0")
+    ms = []
+    for _ in range(reps + 1):
+        dp.reset_state()
+        ms.append(ctx.solve(dp.cam, dp.pose, dp.vel, dp.bias, dp.invdepth, dp.ii, dp.jj, dp.target, dp.weight, imu,
+                            o, 1, ws, stage_ms=True)["stage_ms"]["vis_gram_imu"])
+    del ws
+    out["global_512kf"] = _assembly_entry(
+        [prob], min(ms[1:]), "512 keyframes, 60x80 maps, 5832 edges (11 nearest + 200 loop edges), mixed precision",
+        16.0 + 8.0 / (prob.n_edges / prob.n_kf), "k_vis_gram<float>@global_512kf")
+    # the 64-window batch
+    probs = [synth.make_problem(synth.config_batched_window(w), 4000 + w) for w in range(64)]
+    dps = [binding.DeviceProblem(p) for p in probs]
+    imus = [ctx.imu_preintegrate(d.off, d.gyro, d.accel, d.imu_dt, d.bias_hat, d.noise) for d in dps]
+    ws = torch.empty(ctx.workspace_size_batched(dps, o), dtype=torch.uint8, device="cuda:0")
+    ms = []
+    for _ in range(reps + 1):
+        for d in dps:
+            d.reset_state()
+        ms.append(ctx.solve_batched(dps, imus, o, 1, ws, stage_ms=True)[0]["stage_ms"]["vis_gram_imu"])
+    pxres, _, _ = assembly_work(probs)
+    E = sum(p.n_edges for p in probs)
+    N = sum(p.n_kf for p in probs)
+    out["batch_64_windows"] = _assembly_entry(
+        probs, min(ms[1:]), "64 independent windows (N ~ U{8..32}, 3-8 edges per keyframe, 48x64 or 60x80 maps), "
+                            "mixed precision, all windows in one launch", 16.0 + 8.0 * N / E,
+        "k_vis_gram<float>@batch_64_windows")
+    return out
+
+
+def _assembly_entry(probs, ms, workload, bytes_per_pxres, traffic_key):
+    pxres, bytes_, flops = assembly_work(probs)
+    t = ms * 1e-3
+    gbs = bytes_ / t / 1e9
+    tf = flops / t / 1e12
+    traffic = measured_traffic(traffic_key)
+    return {"workload": workload, "kernel": "k_vis_gram<float>", "ms_per_launch": ms,
+            "pixel_residuals_per_launch": pxres, "pixel_residuals_per_s": pxres / t,
+            "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": gbs / HBM_PEAK_GBS, "traffic": traffic,
+                         "traffic_over_algorithmic": (traffic / bytes_) if traffic else None,
+                         "algorithmic_bytes_per_launch": bytes_,
+                         "per_unit": f"{bytes_per_pxres:.2f} B per pixel-residual (target + weight 16 B, FP32 "
+                                     f"inverse depth read and increment written 8 B per source pixel)"},
+            "gram_mfma": {"achieved": tf, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tf / FP32_PEAK_TFLOPS,
+                          "algorithmic_flops_per_launch": flops,
+                          "per_unit": "(6k)(6k + 1) flops per source pixel (symmetric half of the Schur Gram)"}}
 
 
 def global_problem(ctx, iters=2, reps=3):

@@ -19,9 +19,9 @@ using namespace vi;
 namespace {
 
 // candidate pixels-per-workgroup of the fused assembly (multiples of 64)
-const int kRanges[] = {128, 192, 256, 320, 384, 448, 512, 640};
+const int kRanges[] = {128, 192, 256, 320, 384, 448, 512, 640, 1024, 1536, 2048, 3072, 4096, 8192};
 constexpr int kRangeMin = 128;
-constexpr int kRangeDefault = 320;
+constexpr int kAssemblyWGTarget = 256;   // default tiling: about one assembly workgroup per compute unit
 
 struct WinIn {
   const vi_camera* cam;
@@ -313,6 +313,19 @@ void set_range(Plan& P, int range) {
   for (WinDev& W : P.win) W.nkr = (W.HW + range - 1) / range;
 }
 
+// default pixel range of the fused assembly: the source pixels of the batch
+// over about one workgroup per compute unit (a multiple of 64, at least
+// kRangeMin), so that small windows still fill the chip and large problems
+// keep whole keyframes in one workgroup (one set of Gram partials each)
+int default_range(const Plan& P) {
+  long long px = 0;
+  for (int g = 0; g < P.N; ++g)
+    if (P.src_off[g + 1] > P.src_off[g]) px += P.win[P.win_of_kf[g]].HW;
+  long long r = (px + kAssemblyWGTarget - 1) / kAssemblyWGTarget;
+  r = (r + 63) / 64 * 64;
+  return (int)std::max<long long>(kRangeMin, std::min<long long>(r, (P.hw_max + 63) / 64 * 64));
+}
+
 struct Carve {
   size_t off = 0;
   char* base = nullptr;
@@ -402,7 +415,7 @@ vi_status ensure_plan(vi_ctx* ctx, const std::vector<WinIn>& wins) {
   Plan P;
   vi_status s = build_plan(ctx, wins, P);
   if (s != VI_OK) return s;
-  set_range(P, kRangeDefault);
+  set_range(P, default_range(P));
   ctx->plan = std::move(P);
   ctx->plan_sig = std::move(sig);
   ctx->have_plan = false;
@@ -463,9 +476,15 @@ vi_status autotune_range(vi_ctx* ctx, const Work& w, const OptsDev& od) {
   launch_reset_status(sp, ctx->status, P.n_win);
   if (od.use_imu) launch_imu_info(sp, P, ctx->dplan, w.Lam, ctx->status);
   TimingUser tu{sp, ev};
-  int best = kRangeDefault;
+  int best = default_range(P);
   float best_ms = 1e30f;
-  for (int r : kRanges) {
+  std::vector<int> cand(std::begin(kRanges), std::end(kRanges));
+  cand.push_back(best);
+  std::sort(cand.begin(), cand.end());
+  bool whole = false;            // a candidate already covers a whole keyframe
+  for (int r : cand) {
+    if (whole) break;
+    whole = r >= P.hw_max;
     set_range(P, r);
     HIPCHK(ctx, hipMemcpy(ctx->d_win, P.win.data(), sizeof(WinDev) * P.n_win, hipMemcpyHostToDevice));
     float tot = 0.f;
@@ -832,7 +851,7 @@ size_t vi_workspace_size_batched(int32_t n_windows, const vi_window* windows, co
   }
   Plan P;
   if (build_plan(nullptr, wins, P) != VI_OK) return 0;
-  set_range(P, kRangeDefault);
+  set_range(P, default_range(P));
   size_t b = 0;
   do_carve(P, nullptr, &b);
   return b;
@@ -949,7 +968,7 @@ size_t vi_warm_start_workspace_size(int32_t n_windows, const vi_window* windows,
   }
   Plan P;
   if (build_plan(nullptr, wins, P) != VI_OK) return 0;
-  set_range(P, kRangeDefault);
+  set_range(P, default_range(P));
   int hq, wq;
   warm_canvas(wins, &hq, &wq);
   size_t b = 0;

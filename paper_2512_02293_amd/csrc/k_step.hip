@@ -405,24 +405,43 @@ __device__ void imu_factor_block(int f, const WinDev& W, const double* __restric
 // ---------------------------------------------------------------------------
 // Fused vision assembly and Schur Gram.  One 512-thread workgroup per (source
 // keyframe, pixel range), walked in chunks of 64 pixels; lane = pixel, wave w
-// takes the source's edges w, w+8, w+16.  Per (pixel, edge): residual and
-// Jacobians; per pixel: C and w_d; per edge: the local 6x6 Hessian (21) and
-// gradient (6), reduced over the wave in two 16-value passes (reduce16) into
-// lane registers; the 6 local E-entries of every (pixel, edge) go to an LDS
-// tile [64 px][6k | w_d], on which the eight waves then run the Gram
+// takes the source's edges w, w + 8, w + 16.  Per (pixel, edge): residual and
+// Jacobians in local edge coordinates; per pixel: C and w_d; per edge: the
+// local 6x6 Hessian and gradient, summed in each lane's registers over the
+// chunks of a block and reduced over the wave once per block (two 16-value
+// reduce16 passes).  Of the 21 upper Hessian entries 20 can be non-zero: the
+// x row of the local Jacobian has no y-translation term and the y row no
+// x-translation term, and the formulas below skip those products.  The 6
+// local E-entries of every (pixel, edge) go to a column-major LDS tile
+// [6k | w_d | 0][64 px] (two buffers: chunk i + 1 is written while slower
+// waves still read chunk i), on which the eight waves then run the Gram
 //   Q' = sum_p [L_p; w_d,p][L_p; w_d,p]^T / C_p
-// on FP64 MFMA 16x16x4 over lower-triangular 16x16 tiles.  The E-block never
-// leaves the chip.  MFMA operand layout: lane l supplies A[l%16][l/16] and
-// B[l/16][l%16]; it receives D[l/16 + 4 r][l%16] in element r.  Inertial
-// factors ride along as extra workgroups (the first imu_rows rows of the grid,
-// so that their serial rotation algebra starts first and overlaps the vision
-// workgroups).
+// over lower-triangular 16x16 tiles on MFMA 16x16x4 (FP64, or FP32 in mixed
+// mode).  The pixels of a chunk are dealt to the MFMA's K index so that the
+// 16 operands a lane supplies for one tile are 16 consecutive pixels of one
+// tile column, read with 128-bit LDS loads.  MFMA operand layout: lane l
+// supplies A[l%16][l/16] and B[l/16][l%16]; it receives D[l/16 + 4 r][l%16]
+// (FP64) or D[4 (l/16) + r][l%16] (FP32) in element r.  FP32 sums (mixed
+// mode) run over blocks of 8 chunks (512 pixels) and are Kahan-added across
+// blocks; FP64 sums run over the whole range.  The E-block never leaves the
+// chip.  The column sums C and w_d of a chunk are formed by the last wave
+// (which has the fewest edges and Gram tiles).  Inertial factors ride along
+// as extra workgroups (the first imu_rows rows of the grid, so that their
+// serial rotation algebra starts first and overlaps the vision workgroups).
 // ---------------------------------------------------------------------------
 constexpr int kVisThreads = 512;
 constexpr int kVisWaves = kVisThreads / 64;
-constexpr int kMaxTilesPerWave = 4;     // T <= 7 for 6k+1 <= 112: 28 tiles over 8 waves
-constexpr int kEdgeSlots = (kMaxOutDegree + kVisWaves - 1) / kVisWaves;
-static_assert(kMaxTilesPerWave * kVisWaves >= 28, "Gram tiles per wave");
+constexpr int kVisSumWave = kVisWaves - 1;     // forms C and w_d of each chunk
+constexpr int kVisBlockChunks = 8;             // chunks per FP32 block sum
+
+// E-tile column stride in elements: 64 pixel rows plus padding, so that the
+// 128-bit reads of the 16 columns one instruction touches hit distinct banks
+template <typename R>
+constexpr int vis_ldc() { return sizeof(R) == 4 ? 68 : 66; }
+
+// Gram tiles (lower triangle of T x T) and edge slots per wave for a source
+// with k outgoing edges
+__host__ __device__ constexpr int vis_tiles_T(int k) { return (6 * k + 16) / 16; }
 
 __device__ __forceinline__ void tile_ij(int t, int& I, int& J) {
   int i = 0;
@@ -432,11 +451,111 @@ __device__ __forceinline__ void tile_ij(int t, int& I, int& J) {
 }
 
 typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef double double2_t __attribute__((ext_vector_type(2)));
 
-// R = double: FP64 MFMA 16x16x4 (output D[l/16 + 4 r][l%16]).  R = float:
-// FP32 MFMA 16x16x4 (output D[4 (l/16) + r][l%16]), each 64-pixel block
-// accumulated from zero and then Kahan-added into the running Gram.
+// 16 consecutive LDS values (16-byte aligned) into registers
+__device__ __forceinline__ void lds_load16(const float* p, float (&v)[16]) {
+  const float4_t* q = (const float4_t*)p;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float4_t x = q[i];
+    v[4 * i] = x[0]; v[4 * i + 1] = x[1]; v[4 * i + 2] = x[2]; v[4 * i + 3] = x[3];
+  }
+}
+__device__ __forceinline__ void lds_load16(const double* p, double (&v)[16]) {
+  const double2_t* q = (const double2_t*)p;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const double2_t x = q[i];
+    v[2 * i] = x[0]; v[2 * i + 1] = x[1];
+  }
+}
+
+// per-lane sums of one edge over the chunks of a block: local Hessian (upper
+// triangle, row-major, 21 entries; entry (3, 4) stays zero) and gradient (6)
 template <typename R>
+struct EdgeAcc {
+  R h[21], g[6];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < 21; ++i) h[i] = (R)0;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) g[i] = (R)0;
+  }
+};
+
+// One (pixel, edge) pair: projection P = R_ji q + t_ji d, validity, residual
+// r = target - (f P_xy / P_z + c), the local Jacobian rows J_x = f_x u_x,
+// J_y = f_y u_y with
+//   u_x = (x y, -(1 + x^2), y, -d', 0, x d'),  u_y = (1 + y^2, -x y, -x, 0, -d', y d')
+// (x = P_x / P_z, y = P_y / P_z, d' = d / P_z: a perturbation phi, rho of the
+// relative transform in camera j moves P by phi x P + d rho), and the depth
+// Jacobian J_d = f (-(t_x - x t_z) / P_z, -(t_y - y t_z) / P_z).  Adds the
+// pair's terms to the lane's Hessian / gradient sums, C, w_d and the cost,
+// and writes its 6 E-entries (J_loc^T W J_d) to column base e of the tile.
+// An invalid pair contributes zero everywhere (branch-free: its weights and
+// residual are replaced by zero, its depth by a harmless 1).
+template <typename R, int LDC>
+__device__ __forceinline__ void vis_pair(const R* rt, R fx, R fy, R cx, R cy, R zmin, R qx, R qy, R d, bool inpx,
+                                         float tgx, float tgy, float wgx, float wgy, EdgeAcc<R>& A, R* e, R& Cp,
+                                         R& Wp, R& cst, R& nv) {
+  const R Px = rt[0] * qx + rt[1] * qy + rt[2] + rt[9] * d;
+  const R Py = rt[3] * qx + rt[4] * qy + rt[5] + rt[10] * d;
+  const R Pz = rt[6] * qx + rt[7] * qy + rt[8] + rt[11] * d;
+  const bool valid = inpx && d > (R)0 && Pz > zmin * d;
+  const R iz = recip<R>(valid ? Pz : (R)1);
+  const R xp = Px * iz, yp = Py * iz, dz = d * iz;
+  const R wx = valid ? (R)wgx : (R)0, wy = valid ? (R)wgy : (R)0;
+  const R rx = valid ? (R)tgx - (fx * xp + cx) : (R)0;
+  const R ry = valid ? (R)tgy - (fy * yp + cy) : (R)0;
+  const R xy = xp * yp;
+  const R ux[6] = {xy, -((R)1 + xp * xp), yp, -dz, (R)0, xp * dz};
+  const R uy[6] = {(R)1 + yp * yp, -xy, -xp, (R)0, -dz, yp * dz};
+  const R jdx = -iz * (rt[9] - xp * rt[11]);
+  const R jdy = -iz * (rt[10] - yp * rt[11]);
+  const R wxf = wx * fx, wyf = wy * fy;
+  const R hx = wxf * fx, hy = wyf * fy;       // w f^2
+  const R ax = hx * jdx, ay = hy * jdy;       // w f J_d (per unit u)
+  const R bx = wxf * rx, by = wyf * ry;       // w f r
+  Cp += ax * jdx + ay * jdy;
+  Wp -= bx * jdx + by * jdy;
+  cst += wx * rx * rx + wy * ry * ry;
+  nv += valid ? (R)1 : (R)0;
+  // E-entries J_loc^T W J_d
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    R v;
+    if (c == 3) v = ax * ux[3];
+    else if (c == 4) v = ay * uy[4];
+    else v = ax * ux[c] + ay * uy[c];
+    e[c * LDC] = v;
+  }
+  // Hessian and gradient sums (the zero entries of u_x, u_y skipped)
+  R px[6], py[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    px[a] = hx * ux[a];
+    py[a] = hy * uy[a];
+  }
+  int m = 0;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+#pragma unroll
+    for (int b = a; b < 6; ++b) {
+      if (a != 4 && b != 4) A.h[m] += px[a] * ux[b];
+      if (a != 3 && b != 3) A.h[m] += py[a] * uy[b];
+      ++m;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    if (a != 4) A.g[a] -= bx * ux[a];
+    if (a != 3) A.g[a] -= by * uy[a];
+  }
+}
+
+// SLOTS: edge slots per wave (k <= 8 SLOTS); TS: Gram tiles per wave (T (T + 1) / 2 <= 8 TS).
+template <typename R, int SLOTS, int TS>
 __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, int imu_rows, int F, int nkr_max,
                                                           int ncost, int range, const double* __restrict__ Lam,
                                                           double* __restrict__ Rw, double* __restrict__ rel,
@@ -446,6 +565,7 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
                                                           double* __restrict__ gf, double* __restrict__ icost,
                                                           DevStatus* __restrict__ st) {
   constexpr bool kF64 = sizeof(R) == 8;
+  constexpr int LDC = vis_ldc<R>();
   extern __shared__ double sm[];
   __shared__ double red[2][kVisWaves];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -468,57 +588,62 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
   const int e0 = D.src_off[src];
   const int k = D.src_off[src + 1] - e0;
   const int ncol = 6 * k;
-  const int T = (ncol + 16) / 16;
-  // E-tile row stride: one element more than the T 16-column tiles, so that the
-  // lanes (one pixel row each) writing the same column hit different LDS banks
-  const int LDW = 16 * T + 1;
+  const int T = vis_tiles_T(k);
   const int ntiles = T * (T + 1) / 2;
-  double* rel_s = sm;                             // [kMaxOutDegree][12]
-  R* Lt = (R*)(rel_s + kMaxOutDegree * 12);       // [64][LDW]
-  R* part = Lt + 64 * LDW;                        // [2][kVisWaves][64]
-  R* invcd = part + 2 * kVisWaves * 64;           // [64]
+  const int tsz = 16 * T * LDC;                   // one E-tile buffer
+  R* rel_s = (R*)sm;                              // [kMaxOutDegree][12]
+  R* Et = rel_s + kMaxOutDegree * 12;             // [2][16 T][LDC]
+  R* part = Et + 2 * tsz;                         // [2][kVisWaves][64]  C and w_d partials
+  R* invcd = part + 2 * kVisWaves * 64;           // [2][64]
   if (tid < k) {
     const int e = D.src_edges[e0 + tid];
-    edge_rel(W.pose, ls, D.jj[e] - W.kf_base, rel_s + tid * 12);
+    double r12[12];
+    edge_rel(W.pose, ls, D.jj[e] - W.kf_base, r12);
+#pragma unroll
+    for (int q = 0; q < 12; ++q) rel_s[tid * 12 + q] = (R)r12[q];
     if (kr == 0)
-      for (int q = 0; q < 12; ++q) rel[(size_t)e * 12 + q] = rel_s[tid * 12 + q];
+      for (int q = 0; q < 12; ++q) rel[(size_t)e * 12 + q] = r12[q];
   }
   if (kr == 0 && tid == 0) {
     double Rm[9];
     quat_to_rot(W.pose + (size_t)ls * 7 + 3, Rm);
     for (int q = 0; q < 9; ++q) Rw[(size_t)src * 9 + q] = Rm[q];
   }
-  for (int i = tid; i < 64 * LDW; i += kVisThreads) Lt[i] = (R)0;
+  for (int i = tid; i < 2 * tsz; i += kVisThreads) Et[i] = (R)0;
   __syncthreads();
 
   const double* dsrc = W.invdepth + (size_t)ls * HW;
   double* Cds = Cd + W.pix_base + (size_t)ls * HW;
   double* wds = wd + W.pix_base + (size_t)ls * HW;
-  BlockSum<R> acc_a[kEdgeSlots], acc_b[kEdgeSlots];
-  double4_t gacc[kMaxTilesPerWave];             // FP64 path
-  float4_t gs[kMaxTilesPerWave], gc[kMaxTilesPerWave];   // FP32 path: Kahan sum and compensation
+  const R fx = (R)W.fx, fy = (R)W.fy, cx = (R)W.cx, cy = (R)W.cy, zmin = (R)o.z_min;
+  const R ifx = (R)(1.0 / W.fx), ify = (R)(1.0 / W.fy);
+  EdgeAcc<R> acc[SLOTS];
+  BlockSum<R> hs_a[SLOTS], hs_b[SLOTS];
 #pragma unroll
-  for (int u = 0; u < kMaxTilesPerWave; ++u) {
+  for (int u = 0; u < SLOTS; ++u) acc[u].zero();
+  double4_t gacc[TS];                                   // FP64 Gram
+  float4_t gblk[TS], gs[TS], gc[TS];                    // FP32 Gram: block sum, Kahan sum and compensation
+#pragma unroll
+  for (int u = 0; u < TS; ++u) {
     gacc[u] = double4_t{0.0, 0.0, 0.0, 0.0};
-    gs[u] = float4_t{0.f, 0.f, 0.f, 0.f};
-    gc[u] = float4_t{0.f, 0.f, 0.f, 0.f};
+    gblk[u] = gs[u] = gc[u] = float4_t{0.f, 0.f, 0.f, 0.f};
   }
   double cost = 0.0, nval = 0.0;
-  // targets, weights and inverse depth of the next 64-pixel chunk are loaded
-  // one chunk ahead, so their latency overlaps the Gram of the current chunk
-  size_t eoff[kEdgeSlots];
+  // targets, weights and inverse depth of the next chunk are loaded one chunk
+  // ahead, so that their latency overlaps the Gram of the current chunk
+  size_t eoff[SLOTS];
 #pragma unroll
-  for (int u = 0; u < kEdgeSlots; ++u) {
+  for (int u = 0; u < SLOTS; ++u) {
     const int s = wave + kVisWaves * u;
     eoff[u] = s < k ? (size_t)(D.src_edges[e0 + s] - W.e_base) * 2 * HW : 0;
   }
-  float ntx[kEdgeSlots], nty[kEdgeSlots], nwx[kEdgeSlots], nwy[kEdgeSlots];
+  float ntx[SLOTS], nty[SLOTS], nwx[SLOTS], nwy[SLOTS];
   double nd;
   auto prefetch = [&](int c) {
     const int pp = (c + lane < p_end) ? c + lane : p_beg;
     nd = dsrc[pp];
 #pragma unroll
-    for (int u = 0; u < kEdgeSlots; ++u) {
+    for (int u = 0; u < SLOTS; ++u) {
       if (wave + kVisWaves * u < k) {
         const size_t t = eoff[u] + pp;
         ntx[u] = W.target[t];
@@ -528,69 +653,61 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
       }
     }
   };
+  // this lane's pixel (column x, row y) in the current chunk
+  int xq = (p_beg + lane) % W.W, yq = (p_beg + lane) / W.W;
+  const int g4 = lane >> 4, m16 = lane & 15;
   prefetch(p_beg);
-  for (int c0 = p_beg; c0 < p_end; c0 += 64) {
+  int nblk = 0;
+  for (int c0 = p_beg, it = 0; c0 < p_end; c0 += 64, ++it) {
+    const int buf = it & 1;
+    R* E = Et + buf * tsz;
     const int p = c0 + lane;
     const bool inpx = p < p_end;
-    const int pc = inpx ? p : p_beg;
-    const R qx = (R)(((double)(pc % W.W) - W.cx) / W.fx);
-    const R qy = (R)(((double)(pc / W.W) - W.cy) / W.fy);
+    const R qx = ((R)xq - cx) * ifx;
+    const R qy = ((R)yq - cy) * ify;
+    xq += 64;
+    while (xq >= W.W) { xq -= W.W; ++yq; }
     const R d = (R)nd;
-    float ctx_[kEdgeSlots], cty[kEdgeSlots], cwx[kEdgeSlots], cwy[kEdgeSlots];
+    float ctx_[SLOTS], cty[SLOTS], cwx[SLOTS], cwy[SLOTS];
 #pragma unroll
-    for (int u = 0; u < kEdgeSlots; ++u) { ctx_[u] = ntx[u]; cty[u] = nty[u]; cwx[u] = nwx[u]; cwy[u] = nwy[u]; }
+    for (int u = 0; u < SLOTS; ++u) { ctx_[u] = ntx[u]; cty[u] = nty[u]; cwx[u] = nwx[u]; cwy[u] = nwy[u]; }
     if (c0 + 64 < p_end) prefetch(c0 + 64);
-    R Cp = (R)0, Wp = (R)0, cst = (R)0;
+    R Cp = (R)0, Wp = (R)0, cst = (R)0, nv = (R)0;
 #pragma unroll
-    for (int u = 0; u < kEdgeSlots; ++u) {
+    for (int u = 0; u < SLOTS; ++u) {
       const int s = wave + kVisWaves * u;
-      if (s < k) {
-        PixEdgeT<R> q;
-        pix_edge_v<R>(W, o, rel_s + s * 12, qx, qy, d, inpx, ctx_[u], cty[u], cwx[u], cwy[u], true, q);
-        Cp += q.wx * q.Jdx * q.Jdx + q.wy * q.Jdy * q.Jdy;
-        Wp -= q.wx * q.Jdx * q.rx + q.wy * q.Jdy * q.ry;
-        cst += q.wx * q.rx * q.rx + q.wy * q.ry * q.ry;
-        nval += q.valid ? 1.0 : 0.0;
-        const R ax = q.wx * q.Jdx, ay = q.wy * q.Jdy;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) Lt[lane * LDW + 6 * s + c] = ax * q.Jx[c] + ay * q.Jy[c];
-        // local Hessian (upper triangle, row-major: 21) and gradient (6)
-        R v[16];
-        int m = 0;
-        const R bx = q.wx * q.rx, by = q.wy * q.ry;
-#pragma unroll
-        for (int a = 0; a < 6; ++a) {
-          const R px = q.wx * q.Jx[a], py = q.wy * q.Jy[a];
-#pragma unroll
-          for (int b = a; b < 6; ++b) {
-            const R h = px * q.Jx[b] + py * q.Jy[b];
-            if (m < 16) v[m] = h;
-            ++m;
-          }
-        }
-        acc_a[u].add(reduce16(v, lane));
-        m = 0;
-#pragma unroll
-        for (int a = 0; a < 6; ++a) {
-          const R px = q.wx * q.Jx[a], py = q.wy * q.Jy[a];
-#pragma unroll
-          for (int b = a; b < 6; ++b) {
-            if (m >= 16) v[m - 16] = px * q.Jx[b] + py * q.Jy[b];
-            ++m;
-          }
-        }
-#pragma unroll
-        for (int a = 0; a < 6; ++a) v[5 + a] = -(q.Jx[a] * bx + q.Jy[a] * by);
-#pragma unroll
-        for (int a = 11; a < 16; ++a) v[a] = (R)0;
-        acc_b[u].add(reduce16(v, lane));
-      }
+      if (s < k)
+        vis_pair<R, LDC>(rel_s + s * 12, fx, fy, cx, cy, zmin, qx, qy, d, inpx, ctx_[u], cty[u], cwx[u], cwy[u],
+                         acc[u], E + 6 * s * LDC + lane, Cp, Wp, cst, nv);
     }
     cost += (double)cst;
+    nval += (double)nv;
     part[wave * 64 + lane] = Cp;
     part[kVisWaves * 64 + wave * 64 + lane] = Wp;
+    const bool last = c0 + 64 >= p_end;
+    const bool flush = last || (!kF64 && ++nblk == kVisBlockChunks);
+    if (flush) {
+      // per-edge block sums: reduce over the wave, add into the running sums
+#pragma unroll
+      for (int u = 0; u < SLOTS; ++u) {
+        if (wave + kVisWaves * u < k) {
+          R v[16];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) v[i] = acc[u].h[i];
+          hs_a[u].add(reduce16(v, lane));
+#pragma unroll
+          for (int i = 0; i < 5; ++i) v[i] = acc[u].h[16 + i];
+#pragma unroll
+          for (int i = 0; i < 6; ++i) v[5 + i] = acc[u].g[i];
+#pragma unroll
+          for (int i = 11; i < 16; ++i) v[i] = (R)0;
+          hs_b[u].add(reduce16(v, lane));
+          acc[u].zero();
+        }
+      }
+    }
     __syncthreads();
-    if (wave == 0) {
+    if (wave == kVisSumWave) {
       // a non-finite inverse depth fails the window (the state is left as it is)
       if (st && inpx && !isfinite(d)) set_status(st + D.win_of_kf[src], VI_ENONFINITE, -1);
       double C = o.eta, Wv = 0.0;
@@ -603,47 +720,52 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
         Cds[p] = C;
         wds[p] = Wv;
       }
-      invcd[lane] = (inpx && C > 0.0) ? (R)(1.0 / C) : (R)0;
-      Lt[lane * LDW + ncol] = inpx ? (R)Wv : (R)0;
+      invcd[buf * 64 + lane] = (inpx && C > 0.0) ? (R)(1.0 / C) : (R)0;
+      E[ncol * LDC + lane] = inpx ? (R)Wv : (R)0;
     }
     __syncthreads();
+    // Gram of this chunk: lane (g4, m16) supplies pixels 16 g4 .. 16 g4 + 15
+    {
+      R inv[16];
+      lds_load16(invcd + buf * 64 + 16 * g4, inv);
 #pragma unroll
-    for (int u = 0; u < kMaxTilesPerWave; ++u) {
-      const int t = wave + kVisWaves * u;
-      if (t < ntiles) {
-        int I, J;
-        tile_ij(t, I, J);
-        const int ca = 16 * I + (lane & 15);
-        const int cb = 16 * J + (lane & 15);
-        if constexpr (kF64) {
-#pragma unroll 4
-          for (int kk = 0; kk < 16; ++kk) {
-            const int row = kk * 4 + (lane >> 4);
-            const double a = Lt[row * LDW + ca];
-            const double b = Lt[row * LDW + cb] * invcd[row];
-            gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gacc[u], 0, 0, 0);
+      for (int u = 0; u < TS; ++u) {
+        const int t = wave + kVisWaves * u;
+        if (t < ntiles) {
+          int I, J;
+          tile_ij(t, I, J);
+          R a[16], b[16];
+          lds_load16(E + (16 * I + m16) * LDC + 16 * g4, a);
+          lds_load16(E + (16 * J + m16) * LDC + 16 * g4, b);
+          if constexpr (kF64) {
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk)
+              gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk] * inv[kk], gacc[u], 0, 0, 0);
+          } else {
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk)
+              gblk[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b[kk] * inv[kk], gblk[u], 0, 0, 0);
           }
-        } else {
-          float4_t blk = float4_t{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-          for (int kk = 0; kk < 16; ++kk) {
-            const int row = kk * 4 + (lane >> 4);
-            const float a = Lt[row * LDW + ca];
-            const float b = Lt[row * LDW + cb] * invcd[row];
-            blk = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, blk, 0, 0, 0);
+        }
+      }
+      if constexpr (!kF64) {
+        if (flush) {
+#pragma unroll
+          for (int u = 0; u < TS; ++u) {
+            const float4_t y = gblk[u] - gc[u];
+            const float4_t tt = gs[u] + y;
+            gc[u] = (tt - gs[u]) - y;
+            gs[u] = tt;
+            gblk[u] = float4_t{0.f, 0.f, 0.f, 0.f};
           }
-          const float4_t y = blk - gc[u];
-          const float4_t tt = gs[u] + y;
-          gc[u] = (tt - gs[u]) - y;
-          gs[u] = tt;
         }
       }
     }
-    __syncthreads();
+    if (flush) nblk = 0;
   }
   double* out = gpart + D.gram_off[src] + (size_t)kr * ntiles * 256;
 #pragma unroll
-  for (int u = 0; u < kMaxTilesPerWave; ++u) {
+  for (int u = 0; u < TS; ++u) {
     const int t = wave + kVisWaves * u;
     if (t < ntiles) {
 #pragma unroll
@@ -661,13 +783,13 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
   }
   // per-edge partials: lane l holds element l >> 2 of each 16-value half
 #pragma unroll
-  for (int u = 0; u < kEdgeSlots; ++u) {
+  for (int u = 0; u < SLOTS; ++u) {
     const int s = wave + kVisWaves * u;
     if (s < k && (lane & 3) == 0) {
       double* hp = hpart + ((size_t)(e0 + s) * nkr_max + kr) * 32;
       const int el = lane >> 2;
-      hp[el] = acc_a[u].value();
-      if (el < 11) hp[16 + el] = acc_b[u].value();
+      hp[el] = hs_a[u].value();
+      if (el < 11) hp[16 + el] = hs_b[u].value();
     }
   }
   cost = wave_sum(cost);
@@ -1469,11 +1591,31 @@ __global__ void __launch_bounds__(256) k_warm_state(DevPlan D, double* __restric
 
 }  // namespace
 
-static size_t vis_lds(int kmax) {
-  const size_t T = (6 * (size_t)kmax + 16) / 16;
-  const size_t vis = (size_t)kMaxOutDegree * 12 + 64 * (16 * T + 1) + 2 * kVisWaves * 64 + 64;
-  const size_t imu = 450 + 450 + 225 + 15;
-  return sizeof(double) * std::max(vis, imu);
+// dynamic LDS of the fused assembly: relative transforms, two E-tile
+// buffers, the C / w_d partials and 1/C of two chunks; the inertial
+// workgroups need 1140 doubles
+static size_t vis_lds(int kmax, bool f64) {
+  const size_t T = vis_tiles_T(kmax);
+  const size_t esz = f64 ? sizeof(double) : sizeof(float);
+  const size_t ldc = f64 ? vis_ldc<double>() : vis_ldc<float>();
+  const size_t vis = esz * ((size_t)kMaxOutDegree * 12 + 2 * 16 * T * ldc + 2 * kVisWaves * 64 + 2 * 64);
+  const size_t imu = sizeof(double) * (450 + 450 + 225 + 15);
+  return std::max(vis, imu);
+}
+
+typedef void (*VisKernel)(OptsDev, DevPlan, int, int, int, int, int, const double*, double*, double*, double*,
+                          double*, double*, double*, double*, double*, double*, double*, DevStatus*);
+
+// the instantiation of the fused assembly for the largest out-degree of a batch:
+// edge slots per wave ceil(kmax / 8), Gram tiles per wave ceil(T (T + 1) / 16)
+template <typename R>
+static VisKernel vis_kernel(int kmax) {
+  const int T = vis_tiles_T(kmax);
+  const int ts = (T * (T + 1) / 2 + kVisWaves - 1) / kVisWaves;
+  const int slots = (kmax + kVisWaves - 1) / kVisWaves;
+  if (slots <= 1) return ts <= 1 ? k_vis_gram<R, 1, 1> : k_vis_gram<R, 1, 2>;
+  if (slots == 2) return ts <= 2 ? k_vis_gram<R, 2, 2> : (ts == 3 ? k_vis_gram<R, 2, 3> : k_vis_gram<R, 2, 4>);
+  return k_vis_gram<R, 3, 4>;
 }
 static size_t local_lds(int kmax) {
   const size_t k = kmax, nq = 6 * k + 1;
@@ -1488,10 +1630,14 @@ void chol_set_attributes();
 
 void step_set_attributes(int kmax) {
   chol_set_attributes();
-  (void)hipFuncSetAttribute((const void*)k_vis_gram<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)vis_lds(kmax));
-  (void)hipFuncSetAttribute((const void*)k_vis_gram<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)vis_lds(kmax));
+  // every instantiation of the fused assembly may run for some batch: each
+  // gets the LDS cap of the largest out-degree it serves
+  for (int km = 1; km <= kMaxOutDegree; ++km) {
+    (void)hipFuncSetAttribute((const void*)vis_kernel<double>(km), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)vis_lds(kMaxOutDegree, true));
+    (void)hipFuncSetAttribute((const void*)vis_kernel<float>(km), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)vis_lds(kMaxOutDegree, false));
+  }
   (void)hipFuncSetAttribute((const void*)k_local, hipFuncAttributeMaxDynamicSharedMemorySize, (int)local_lds(kmax));
 }
 
@@ -1504,8 +1650,9 @@ static void launch_front(hipStream_t s, const Plan& P, const DevPlan& D, const W
   const int nkr_run = (P.hw_max + P.range - 1) / P.range;          // workgroups per source in x
   const int imu_rows = (F + nkr_run - 1) / nkr_run;
   const int ncost = cost_slots(P);
-  auto kern = (o.precision == VI_PREC_MIXED) ? k_vis_gram<float> : k_vis_gram<double>;
-  hipLaunchKernelGGL(kern, dim3(nkr_run, N + imu_rows), dim3(kVisThreads), vis_lds(P.kmax), s, o, D, imu_rows, F,
+  const bool f64 = o.precision != VI_PREC_MIXED;
+  VisKernel kern = f64 ? vis_kernel<double>(P.kmax) : vis_kernel<float>(P.kmax);
+  hipLaunchKernelGGL(kern, dim3(nkr_run, N + imu_rows), dim3(kVisThreads), vis_lds(P.kmax, f64), s, o, D, imu_rows, F,
                      P.nkr_max, ncost, P.range, w.Lam, w.Rw, w.rel, w.Cd, w.wd, w.hpart, w.gpart, w.vcost, w.Hf,
                      w.gf, w.icost, st);
   done(kStVis);

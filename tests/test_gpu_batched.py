@@ -131,7 +131,7 @@ def test_autotuned_tiling_matches_default(ctx):
     finally:
         ctx.set_autotune(False)
     print("tile_px default", reps0[0]["tile_px"], "tuned", reps1[0]["tile_px"])
-    assert reps1[0]["tile_px"] in (128, 192, 256, 320, 384, 448, 512, 640)
+    assert reps1[0]["tile_px"] >= 128 and reps1[0]["tile_px"] % 64 == 0
     assert reps2[0]["tile_px"] == reps1[0]["tile_px"]
     for w in range(3):
         assert reps1[w]["n_valid"] == reps0[w]["n_valid"]
