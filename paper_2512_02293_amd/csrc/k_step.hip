@@ -568,7 +568,8 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
   constexpr int LDC = vis_ldc<R>();
   extern __shared__ double sm[];
   __shared__ double red[2][kVisWaves];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: per-wave choices stay scalar
   if ((int)blockIdx.y < imu_rows) {
     const int f = (int)blockIdx.y * (int)gridDim.x + (int)blockIdx.x;
     if (f < F && o.use_imu && !(st && st[D.win_of_f[f]].conv)) {   // frozen windows keep their blocks
@@ -720,7 +721,7 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
         Cds[p] = C;
         wds[p] = Wv;
       }
-      invcd[buf * 64 + lane] = (inpx && C > 0.0) ? (R)(1.0 / C) : (R)0;
+      invcd[buf * 64 + lane] = (inpx && C > 0.0) ? recip<R>((R)C) : (R)0;
       E[ncol * LDC + lane] = inpx ? (R)Wv : (R)0;
     }
     __syncthreads();
@@ -734,17 +735,21 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
         if (t < ntiles) {
           int I, J;
           tile_ij(t, I, J);
+          // all 32 operands of the tile loaded first, B scaled by 1/C into its
+          // own registers, then 16 back-to-back MFMAs
           R a[16], b[16];
           lds_load16(E + (16 * I + m16) * LDC + 16 * g4, a);
           lds_load16(E + (16 * J + m16) * LDC + 16 * g4, b);
+#pragma unroll
+          for (int kk = 0; kk < 16; ++kk) b[kk] *= inv[kk];
           if constexpr (kF64) {
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk)
-              gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk] * inv[kk], gacc[u], 0, 0, 0);
+              gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], gacc[u], 0, 0, 0);
           } else {
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk)
-              gblk[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b[kk] * inv[kk], gblk[u], 0, 0, 0);
+              gblk[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b[kk], gblk[u], 0, 0, 0);
           }
         }
       }
