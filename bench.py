@@ -250,11 +250,17 @@ def extras(ctx):
             d.reset_state()
         ctx.solve_batched(dps, imus, opts, GN_ITERS, ws)
 
+    # one context per window: each keeps the captured graph of its own shape,
+    # so the per-window leg replays graphs as the batch does
+    ctxs = [binding.Context(0) for _ in dps]
+    wss = [torch.empty(c.workspace_size(d.cam, d.pose.shape[0], d.ii, d.jj, opts), dtype=torch.uint8,
+                       device="cuda:0") for c, d in zip(ctxs, dps)]
+
     def singles():
-        for d, im in zip(dps, imus):
+        for c, d, im, w in zip(ctxs, dps, imus, wss):
             d.reset_state()
-            ctx.solve(d.cam, d.pose, d.vel, d.bias, d.invdepth, d.ii, d.jj, d.target, d.weight, im, opts,
-                      GN_ITERS, ws)
+            c.solve(d.cam, d.pose, d.vel, d.bias, d.invdepth, d.ii, d.jj, d.target, d.weight, im, opts,
+                    GN_ITERS, w)
 
     def best(fn, reps=5):
         fn()
@@ -268,12 +274,16 @@ def extras(ctx):
         return t
 
     t_b = best(batch)
-    t_s = best(singles, reps=1)
+    t_s = best(singles, reps=3)
+    for c in ctxs:
+        c.close()
     res = {"batched": {"workload": "64 independent windows, N ~ U{8..32} keyframes, 3-8 edges each, 48x64 or "
                                    "60x80 maps, uneven IMU gaps, 8 GN iterations, FP64",
                        "pixel_residuals_per_s": pxres / t_b, "ms_batch": 1e3 * t_b,
                        "ms_one_solve_per_window": 1e3 * t_s,
-                       "note": "per-window solves include one graph capture per window shape"}}
+                       "note": "per-window leg: one context per window, each replaying its own captured graph "
+                               "(captured during the warm-up), the windows solved one after another"}}
+    res["assembly_roofline"] = assembly_roofline(ctx)
     res["global"] = global_problem(ctx)
     res["gaussian_reanchor"] = gaussian_reanchor(ctx)
     res["predict_keyframe"] = predict_keyframe(ctx)
@@ -321,10 +331,13 @@ def assembly_roofline(ctx, reps=5):
     the mixed path) on the two workloads whose inputs exceed the 256 MB
     last-level cache: the 512-keyframe problem and the 64-window batch.  The
     kernel time is the assembly stage of eager steps (HIP events recorded by
-    the library on its own stream around that one launch), best of `reps`."""
+    the library on its own stream around that one launch), best of `reps`.
+    A context of its own with the library's default tiling (the same in the
+    full benchmark line and in the `--only assembly` profiling runs)."""
     import torch
 
     from paper_2512_02293_amd import binding, synth
+    ctx = binding.Context(0)
     o = binding.make_opts(precision=binding.VI_PREC_MIXED)
     out = {}
     # the 512-keyframe problem
@@ -358,6 +371,7 @@ def assembly_roofline(ctx, reps=5):
         probs, min(ms[1:]), "64 independent windows (N ~ U{8..32}, 3-8 edges per keyframe, 48x64 or 60x80 maps), "
                             "mixed precision, all windows in one launch", 16.0 + 8.0 * N / E,
         "k_vis_gram<float>@batch_64_windows")
+    ctx.close()
     return out
 
 
@@ -622,8 +636,49 @@ def warm_windows(ctx, n=8, iters=5, reps=6):
                         f"+ {iters} iterations", "windows": rows}
 
 
-def cpu_baseline(prob, iters):
-    """The FP64 oracle, single-threaded, on a bounded sample of the same window."""
+def host_description():
+    """CPU model and core counts of the machine the benchmark runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def _oracle_worker(j, n_workers, n_windows, barrier, queue):
+    """Worker j of the all-core oracle timing: generates its share of the
+    batched windows (j, j + n_workers, ...), waits for every worker, then runs
+    one oracle GN step (with the oracle's own preintegration) on each and
+    reports (pixel-residuals, start, end) on the wall clock."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import normal_eq as ne
+    from oracle import solve as osolve
+    from paper_2512_02293_amd import synth
+    probs = [synth.make_problem(synth.config_batched_window(w), 4000 + w) for w in range(j, n_windows, n_workers)]
+    barrier.wait()
+    with threadpool_limits(limits=1):
+        t0 = time.time()
+        for prob in probs:
+            cam, st, gr = osolve.from_problem(prob)
+            osolve.step(cam, st, gr, ne.Options())
+        t1 = time.time()
+    queue.put((sum(p.n_edges * p.H * p.W for p in probs), t0, t1))
+
+
+def cpu_baseline(prob, iters, all_cores=True):
+    """The FP64 oracle on bounded samples: single-threaded on the benchmarked
+    window, and on all usable host cores (a process pool, one batched window
+    per task, each one GN step) on the 64-window batch."""
     from threadpoolctl import threadpool_limits
 
     from oracle import normal_eq as ne
@@ -634,9 +689,31 @@ def cpu_baseline(prob, iters):
         st, _ = osolve.solve(cam, st, gr, ne.Options(), iters)
         dt = time.perf_counter() - t0
     pxres = prob.n_edges * prob.H * prob.W * iters
-    return {"value": pxres / dt, "unit": "pixel-residuals/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle preintegration + {iters} of the 8 GN iterations on the same 24-KF window "
-                      f"({dt:.1f} s, NumPy float64, 1 BLAS thread)"}
+    host = host_description()
+    out = {"value": pxres / dt, "unit": "pixel-residuals/s", "cores": 1, "kind": "oracle",
+           "sample": f"oracle preintegration + {iters} of the 8 GN iterations on the same 24-KF window "
+                     f"({dt:.1f} s, NumPy float64, 1 BLAS thread)", "host": host}
+    if all_cores:
+        import multiprocessing as mp
+        workers = max(1, min(16, host["usable_cores"] or 1))
+        n_windows = 64
+        # fresh interpreters (spawn): the workers never touch the GPU
+        mpc = mp.get_context("spawn")
+        barrier, queue = mpc.Barrier(workers), mpc.Queue()
+        procs = [mpc.Process(target=_oracle_worker, args=(j, workers, n_windows, barrier, queue))
+                 for j in range(workers)]
+        for pr in procs:
+            pr.start()
+        res = [queue.get(timeout=600) for _ in procs]
+        for pr in procs:
+            pr.join()
+        wall = max(r[2] for r in res) - min(r[1] for r in res)
+        px = sum(r[0] for r in res)
+        out["all_cores"] = {"value": px / wall, "unit": "pixel-residuals/s", "cores": workers, "kind": "oracle",
+                            "sample": f"one oracle GN step (with its preintegration) of each of the {n_windows} "
+                                      f"batched windows, {workers} worker processes of 1 BLAS thread each "
+                                      f"(windows generated before a common start), {wall:.1f} s wall"}
+    return out
 
 
 if __name__ == "__main__":
