@@ -22,9 +22,11 @@ Modules
              covariance-trace fallback (Sec. 3.1, frontend tracking)
   inertial_init  IMU initialisation stage 2, inertial-only optimisation of
              gravity direction, log-scale, velocities and biases (Sec. 3.2)
+  pgba       loop-closure pose-graph bundle adjustment in Sim(3) (Sec. 3.1,
+             Eq. 5): loop-pair vision terms and relative-pose terms
 
 Parity status per function is listed in each module header.  Every function
 here is pinned by a CPU test against something other than itself (closed
 forms, finite differences, a dense textbook solve, invariants).
 """
-from . import so3, preint, vision, imu, normal_eq, dense, solve, cnn, gauss, predict, inertial_init  # noqa: F401
+from . import so3, preint, vision, imu, normal_eq, dense, solve, cnn, gauss, predict, inertial_init, pgba  # noqa: F401

@@ -495,6 +495,132 @@ def add_degenerate_pixels(prob: Problem, seed: int, frac_near: float = 0.06, fra
 
 
 # --------------------------------------------------------------------------
+# pose-graph bundle adjustment in Sim(3) (loop closure)
+# --------------------------------------------------------------------------
+@dataclass
+class PGBAProblem:
+    """Keyframes with Sim(3) poses (camera-to-world s R x + p), loop pairs with
+    dense targets and weights, and relative Sim(3) measurements of the pose
+    graph.  Estimate arrays are the solver's initial state."""
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    H: int
+    W: int
+    pose: np.ndarray         # (N, 7) p, q (x, y, z, w)
+    scale: np.ndarray        # (N,)
+    invdepth: np.ndarray     # (N, H, W)
+    ii: np.ndarray           # (E*,) int32 loop-pair sources
+    jj: np.ndarray           # (E*,) int32
+    target: np.ndarray       # (E*, 2, H, W) float32
+    weight: np.ndarray       # (E*, 2, H, W) float32
+    target64: np.ndarray     # (E*, 2, H, W) float64 (exact values, for noiseless pins)
+    rel_ii: np.ndarray       # (E+,) int32
+    rel_jj: np.ndarray       # (E+,) int32
+    rel_meas: np.ndarray     # (E+, 8) measured relative similarity E_ij = T_j^-1 T_i: t (3), q (4), s
+    rel_info: np.ndarray     # (E+, 7, 7) information in the (rotation, translation, log-scale) order
+    pose_gt: np.ndarray
+    scale_gt: np.ndarray
+    invdepth_gt: np.ndarray
+
+    @property
+    def n_kf(self) -> int:
+        return self.pose.shape[0]
+
+    @property
+    def n_edges(self) -> int:
+        return int(self.ii.shape[0])
+
+
+def _quat_to_mat_np(q):
+    return _quat_to_mat(np.asarray(q, dtype=np.float64)[None])[0]
+
+
+def _mat_to_quat(R):
+    tr = np.trace(R)
+    if tr > 0:
+        s = 2.0 * np.sqrt(tr + 1.0)
+        q = np.array([(R[2, 1] - R[1, 2]) / s, (R[0, 2] - R[2, 0]) / s, (R[1, 0] - R[0, 1]) / s, 0.25 * s])
+    else:
+        k = int(np.argmax(np.diag(R)))
+        i, j, m = k, (k + 1) % 3, (k + 2) % 3
+        s = 2.0 * np.sqrt(1.0 + R[i, i] - R[j, j] - R[m, m])
+        q = np.zeros(4)
+        q[i] = 0.25 * s
+        q[j] = (R[j, i] + R[i, j]) / s
+        q[m] = (R[m, i] + R[i, m]) / s
+        q[3] = (R[m, j] - R[j, m]) / s
+    return q / np.linalg.norm(q) * (1.0 if q[3] >= 0 else -1.0)
+
+
+def make_pgba_problem(cfg: SceneConfig, seed: int, loops, rel_pairs, log_scale_drift: float = 0.1,
+                      noiseless: bool = False, rel_sigma=(0.005, 0.01, 0.005), init_dlogs: float = 0.05) -> PGBAProblem:
+    """A loop-closure problem on the trajectory of ``make_problem(cfg, seed)``:
+    the true keyframe scales drift as exp(log_scale_drift i / (N - 1)) (the
+    scale drift the pose graph corrects); ``loops`` lists the loop pairs (i, j)
+    whose dense targets are the true projections (+ N(0, sigma_px^2) unless
+    noiseless) with weights U[w_lo, w_hi] (0 where the point is behind camera
+    j); ``rel_pairs`` lists the pose-graph edges, measured as the true E_ij
+    times Exp(n), n ~ N(0, diag(rel_sigma^2)) per (rotation, translation,
+    log-scale) axis (none if noiseless), with information diag(rel_sigma^-2).
+    Initial estimate: the true state with the rotation, position and
+    inverse-depth perturbations of ``make_problem`` and log-scale errors
+    U[-init_dlogs, init_dlogs], keyframe 0 held at the truth (gauge)."""
+    base = make_problem(cfg, seed)
+    rng = np.random.default_rng(seed + 7919)
+    N, H, W = cfg.n_kf, cfg.H, cfg.W
+    s_gt = np.exp(log_scale_drift * np.arange(N) / max(N - 1, 1))
+    R_gt = np.stack([_quat_to_mat_np(q) for q in base.pose_gt[:, 3:]])
+    p_gt = base.pose_gt[:, :3]
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.float64)
+    ray = np.stack([(xs - cfg.cx) / cfg.fx, (ys - cfg.cy) / cfg.fy, np.ones_like(xs)], 0)
+    ii = np.array([a for a, b in loops], dtype=np.int32)
+    jj = np.array([b for a, b in loops], dtype=np.int32)
+    E = len(loops)
+    target = np.zeros((E, 2, H, W))
+    weight = np.zeros((E, 2, H, W), dtype=np.float32)
+    for e, (i, j) in enumerate(loops):
+        Xw = s_gt[i] * np.einsum("ab,bhw->ahw", R_gt[i], ray / base.invdepth_gt[i][None]) + p_gt[i][:, None, None]
+        Xj = np.einsum("ba,bhw->ahw", R_gt[j], Xw - p_gt[j][:, None, None]) / s_gt[j]
+        z = Xj[2]
+        ok = z > cfg.z_min
+        with np.errstate(divide="ignore", invalid="ignore"):
+            uv = np.stack([cfg.fx * Xj[0] / z + cfg.cx, cfg.fy * Xj[1] / z + cfg.cy])
+        target[e] = np.where(ok[None], uv, 0.0)
+        weight[e] = np.where(ok[None], rng.uniform(cfg.w_lo, cfg.w_hi, size=(2, H, W)), 0.0)
+    if not noiseless:
+        target = target + rng.normal(0, cfg.sigma_px, size=target.shape)
+    rel_ii = np.array([a for a, b in rel_pairs], dtype=np.int32)
+    rel_jj = np.array([b for a, b in rel_pairs], dtype=np.int32)
+    sig = np.array([rel_sigma[0]] * 3 + [rel_sigma[1]] * 3 + [rel_sigma[2]])
+    rel_meas = np.zeros((len(rel_pairs), 8))
+    for f, (i, j) in enumerate(rel_pairs):
+        # E_ij = T_j^-1 T_i: scale s_i / s_j, rotation R_j^T R_i, translation R_j^T (p_i - p_j) / s_j
+        s = s_gt[i] / s_gt[j]
+        R = R_gt[j].T @ R_gt[i]
+        t = R_gt[j].T @ (p_gt[i] - p_gt[j]) / s_gt[j]
+        if not noiseless:
+            n = rng.normal(size=7) * sig
+            # right-multiply by a small similarity: rotation Exp(n_rot), translation n_t, scale e^n_s
+            dR = _quat_to_mat_np(_quat_from_rotvec(n[0:3]))
+            t = t + s * R @ n[3:6]
+            R = R @ dR
+            s = s * np.exp(n[6])
+        rel_meas[f] = np.r_[t, _mat_to_quat(R), s]
+    rel_info = np.tile(np.diag(1.0 / sig ** 2), (len(rel_pairs), 1, 1))
+    pose0 = base.pose.copy()
+    pose0[0] = base.pose_gt[0]
+    s0 = s_gt * np.exp(rng.uniform(-init_dlogs, init_dlogs, size=N))
+    s0[0] = s_gt[0]
+    pose_gt = base.pose_gt.copy()
+    return PGBAProblem(fx=cfg.fx, fy=cfg.fy, cx=cfg.cx, cy=cfg.cy, H=H, W=W, pose=pose0, scale=s0,
+                       invdepth=base.invdepth.copy(), ii=ii, jj=jj, target=target.astype(np.float32),
+                       weight=weight, target64=target, rel_ii=rel_ii, rel_jj=rel_jj, rel_meas=rel_meas, rel_info=rel_info,
+                       pose_gt=pose_gt, scale_gt=s_gt, invdepth_gt=base.invdepth_gt.copy())
+
+
+# --------------------------------------------------------------------------
 # Gaussian map and a loop-closure pose correction (input of the map update)
 # --------------------------------------------------------------------------
 @dataclass
