@@ -475,6 +475,62 @@ vi_status vi_gaussian_reanchor(vi_ctx* ctx, int32_t n_kf, const double* pose_pre
 vi_status vi_gaussian_reanchor_noalloc(vi_ctx* ctx, int32_t n_kf, const double* pose_pre, const double* pose_post,
                                        const double* scale_change, const vi_gaussians* g, int32_t* n_rejected);
 
+/* ---------------------------------------------------------------------------
+ * Loop closure: pose-graph bundle adjustment in Sim(3) (Sec. 3.1, "Loop
+ * Closure: Pose Graph Bundle Adjustment", Eq. 5).  Minimises the vision
+ * energy of Eq. 1 over the loop pairs E* plus relative-pose terms over the
+ * pose graph E+,
+ *   sum_{E*} sum_u w_x r_x^2 + w_y r_y^2 + sum_{E+} r_ij^T Lambda_ij r_ij,
+ *   r_ij = Log(T~_ij E_ij^-1),  E_ij = T_j^-1 T_i,
+ * over the keyframes' similarities T_i = (s_i, R_i, p_i) (camera to world,
+ * X_w = s_i R_i X_c + p_i; E_ij takes camera i coordinates to camera j
+ * coordinates, so the vision term of pair (i, j) reads X_j = E_ij X_i) and
+ * the inverse depths of the loop pairs' source keyframes.  The paper writes
+ * the same residual with world-to-camera poses, log(T~_ij T_i T_j^-1).
+ * Sim(3) tangent vectors are ordered (rotation phi, translation rho,
+ * log-scale sigma), the Lie-algebra matrix being [[sigma I + [phi]x, rho],
+ * [0, 0]].  7 unknowns per keyframe: R <- R Exp(dtheta), p <- p + dp,
+ * s <- s exp(dsigma); inverse depths as for the step (d <- max(d + dd,
+ * d_min)).  Damping as for the step (lm_lambda on the pose diagonal,
+ * depth_eta on C); the first opts->n_fixed keyframes are held entirely (the
+ * seven gauge freedoms of Sim(3) with n_fixed = 1).  opts->use_imu and
+ * opts->bias_fixed are ignored; opts->precision selects FP64 or FP32 vision
+ * assembly as for the step (the reduced system and its Cholesky are FP64).
+ * --------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_rel;             /* relative-pose factors (edges of E+) */
+  const int32_t* ii;         /* host [n_rel] keyframe i */
+  const int32_t* jj;         /* host [n_rel] keyframe j (!= i) */
+  const double* meas;        /* device [n_rel][8]: measured E_ij = T_j^-1 T_i as t (3), q (x y z w), s > 0 */
+  const double* info;        /* device [n_rel][49]: Lambda_ij = (Sigma^rel_ij)^-1, row-major, symmetric
+                                positive semi-definite, (rotation, translation, log-scale) order */
+} vi_rel_poses;
+
+/* Device workspace (bytes) of vi_pgba_solve for this problem shape (0 on
+ * invalid input). */
+size_t vi_pgba_workspace_size(const vi_camera* cam, int32_t n_kf, const vi_edges* loops, const vi_rel_poses* rel,
+                              const vi_opts* opts);
+
+/* iters damped Gauss-Newton steps in place.
+ *   cam                  intrinsics and map size (gravity unused)
+ *   pose                 device [n_kf][7] (p, q x y z w), in / out
+ *   scale                device [n_kf] s > 0, in / out
+ *   invdepth             device [n_kf][H][W] FP64, in / out (only the loop
+ *                        pairs' sources change)
+ *   loops                loop pairs E* (ii, jj host; target, weight device
+ *                        [E*][2][H][W] FP32, as vi_edges), at least one pair,
+ *                        at most 18 per source keyframe
+ *   rel                  pose-graph edges E+ (n_rel >= 0)
+ *   report               optional: costs before each step and final,
+ *                        n_valid, iters_done; dxi (device [n_kf][7]) and dd
+ *                        (device [n_kf][H][W]) of the last step when set
+ * Synchronous.  Errors as vi_ba_solve (VI_EINVAL on host checks, VI_ENOTPD,
+ * VI_ENONFINITE, VI_EDEVICE); on error the failing step leaves the state as
+ * it was.  The tolerance stop of vi_ctx_set_tolerance applies. */
+vi_status vi_pgba_solve(vi_ctx* ctx, const vi_camera* cam, int32_t n_kf, double* pose, double* scale,
+                        double* invdepth, const vi_edges* loops, const vi_rel_poses* rel, const vi_opts* opts,
+                        int32_t iters, void* workspace, size_t workspace_bytes, vi_report* report);
+
 #ifdef __cplusplus
 }
 #endif

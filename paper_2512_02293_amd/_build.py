@@ -11,7 +11,7 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_NAME = "libviba.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
-SOURCES = ["csrc/api.hip", "csrc/k_step.hip", "csrc/k_chol.hip", "csrc/k_preint.hip", "csrc/k_wnet.hip", "csrc/k_gauss.hip", "csrc/k_iinit.hip"]
+SOURCES = ["csrc/api.hip", "csrc/k_step.hip", "csrc/k_chol.hip", "csrc/k_preint.hip", "csrc/k_wnet.hip", "csrc/k_gauss.hip", "csrc/k_iinit.hip", "csrc/k_pgba.hip"]
 ARCH = "gfx950"
 FLAGS = [
     "-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-shared",

@@ -71,6 +71,11 @@ class InertialInit(C.Structure):
                 ("bias", C.c_void_p), ("rot_wg", C.c_void_p), ("log_scale", C.c_void_p), ("cost", C.c_void_p)]
 
 
+class RelPoses(C.Structure):
+    _fields_ = [("n_rel", C.c_int32), ("ii", C.c_void_p), ("jj", C.c_void_p), ("meas", C.c_void_p),
+                ("info", C.c_void_p)]
+
+
 class Gaussians(C.Structure):
     _fields_ = [("n", C.c_int64), ("anchor", C.c_void_p), ("mean_in", C.c_void_p), ("cov_in", C.c_void_p),
                 ("mean_out", C.c_void_p), ("cov_out", C.c_void_p)]
@@ -81,7 +86,8 @@ EXPORTS = ["vi_ctx_create", "vi_ctx_destroy", "vi_ctx_set_stream", "vi_last_erro
            "vi_ba_solve_batched", "vi_ctx_set_autotune", "vi_ctx_set_tolerance", "vi_warm_param_count", "vi_warm_workspace_size",
            "vi_warm_features", "vi_warm_forward", "vi_warm_gradients", "vi_warm_adamw", "vi_warm_apply",
            "vi_warm_start_workspace_size", "vi_warm_start", "vi_ba_solve_warm", "vi_reanchor_workspace_size",
-           "vi_gaussian_reanchor", "vi_gaussian_reanchor_noalloc", "vi_predict_keyframe", "vi_inertial_init_workspace_size",
+           "vi_gaussian_reanchor", "vi_gaussian_reanchor_noalloc", "vi_pgba_workspace_size", "vi_pgba_solve",
+           "vi_predict_keyframe", "vi_inertial_init_workspace_size",
            "vi_inertial_init_solve"]
 
 _lib = None
@@ -151,6 +157,12 @@ def load(path: str = LIB_PATH):
     lib.vi_gaussian_reanchor.restype = C.c_int
     lib.vi_gaussian_reanchor_noalloc.argtypes = [vp, i32, vp, vp, vp, C.POINTER(Gaussians), vp]
     lib.vi_gaussian_reanchor_noalloc.restype = C.c_int
+    lib.vi_pgba_workspace_size.argtypes = [C.POINTER(Camera), i32, C.POINTER(Edges), C.POINTER(RelPoses),
+                                           C.POINTER(Opts)]
+    lib.vi_pgba_workspace_size.restype = C.c_size_t
+    lib.vi_pgba_solve.argtypes = [vp, C.POINTER(Camera), i32, vp, vp, vp, C.POINTER(Edges), C.POINTER(RelPoses),
+                                  C.POINTER(Opts), i32, vp, C.c_size_t, C.POINTER(Report)]
+    lib.vi_pgba_solve.restype = C.c_int
     lib.vi_predict_keyframe.argtypes = [vp, i32, vp, vp, vp, vp, C.POINTER(C.c_double * 3), C.c_double, vp, vp, vp,
                                         vp]
     lib.vi_predict_keyframe.restype = C.c_int
@@ -433,6 +445,45 @@ class Context:
         self._check(self.lib.vi_gaussian_reanchor(self.h, N, _ptr(pose_pre), _ptr(pose_post), _ptr(scale_change),
                                                   C.byref(g), _ptr(ws), ws.numel(), _ptr(n_rejected)))
 
+    # -- loop closure: pose-graph bundle adjustment in Sim(3) ----------------------
+    def _pgba_args(self, pg):
+        torch = self.torch
+        N, E, H, W = int(pg.pose.shape[0]), int(pg.ii.shape[0]), int(pg.cam.H), int(pg.cam.W)
+        _check_dev(pg.pose, (N, 7), torch.float64, "pose")
+        _check_dev(pg.scale, (N,), torch.float64, "scale")
+        _check_dev(pg.invdepth, (N, H, W), torch.float64, "invdepth")
+        _check_dev(pg.target, (E, 2, H, W), torch.float32, "target")
+        _check_dev(pg.weight, (E, 2, H, W), torch.float32, "weight")
+        R = int(pg.rel_ii.shape[0])
+        _check_dev(pg.rel_meas, (R, 8), torch.float64, "rel_meas")
+        _check_dev(pg.rel_info, (R, 7, 7), torch.float64, "rel_info")
+        ed = Edges(E, pg.ii.ctypes.data_as(C.c_void_p), pg.jj.ctypes.data_as(C.c_void_p), _ptr(pg.target),
+                   _ptr(pg.weight))
+        rel = RelPoses(R, pg.rel_ii.ctypes.data_as(C.c_void_p), pg.rel_jj.ctypes.data_as(C.c_void_p),
+                       _ptr(pg.rel_meas), _ptr(pg.rel_info))
+        return N, ed, rel
+
+    def pgba_workspace_size(self, pg, opts: Opts) -> int:
+        N, ed, rel = self._pgba_args(pg)
+        return int(self.lib.vi_pgba_workspace_size(C.byref(pg.cam), N, C.byref(ed), C.byref(rel), C.byref(opts)))
+
+    def pgba_solve(self, pg, opts: Opts, iters: int, workspace, dxi=None, dd=None):
+        """vi_pgba_solve on a DevicePGBA problem (state updated in place); returns the report."""
+        N, ed, rel = self._pgba_args(pg)
+        if dxi is not None:
+            _check_dev(dxi, (N, 7), self.torch.float64, "dxi")
+        if dd is not None:
+            _check_dev(dd, tuple(pg.invdepth.shape), self.torch.float64, "dd")
+        _check_dev(workspace, (None,), self.torch.uint8, "workspace")
+        costs = np.zeros(iters + 1)
+        rep = Report(0.0, 0.0, 0, 0, 0, _ptr(dxi), _ptr(dd), costs.ctypes.data_as(C.c_void_p), None)
+        rc = self.lib.vi_pgba_solve(self.h, C.byref(pg.cam), N, _ptr(pg.pose), _ptr(pg.scale), _ptr(pg.invdepth),
+                                    C.byref(ed), C.byref(rel), C.byref(opts), iters, _ptr(workspace),
+                                    workspace.numel(), C.byref(rep))
+        self._check(rc)
+        return dict(cost_before=rep.cost_before, cost_after=rep.cost_after, n_valid=int(rep.n_valid),
+                    iters_done=int(rep.iters_done), costs=costs)
+
     def predict_keyframe(self, pose_prev, vel_prev, bias_prev, imu, gravity, tau=1e-4, pose_new=None,
                          vel_new=None, bias_new=None, used_imu=None):
         """Initial state of new keyframes from preintegration (vi_predict_keyframe).
@@ -559,3 +610,30 @@ class DeviceProblem:
         self.vel.copy_(torch.as_tensor(p.vel))
         self.bias.copy_(torch.as_tensor(p.bias))
         self.invdepth.copy_(torch.as_tensor(p.invdepth))
+
+
+class DevicePGBA:
+    """A synthetic pose-graph problem's arrays on the GPU."""
+
+    def __init__(self, prob, device="cuda:0"):
+        import torch
+        self.prob = prob
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
+        self.pose = t(prob.pose, torch.float64)
+        self.scale = t(prob.scale, torch.float64)
+        self.invdepth = t(prob.invdepth, torch.float64)
+        self.target = t(prob.target, torch.float32)
+        self.weight = t(prob.weight, torch.float32)
+        self.rel_meas = t(prob.rel_meas, torch.float64)
+        self.rel_info = t(prob.rel_info, torch.float64)
+        self.ii = np.ascontiguousarray(prob.ii, dtype=np.int32)
+        self.jj = np.ascontiguousarray(prob.jj, dtype=np.int32)
+        self.rel_ii = np.ascontiguousarray(prob.rel_ii, dtype=np.int32)
+        self.rel_jj = np.ascontiguousarray(prob.rel_jj, dtype=np.int32)
+        self.cam = make_camera(prob.fx, prob.fy, prob.cx, prob.cy, prob.H, prob.W)
+
+    def reset_state(self):
+        import torch
+        self.pose.copy_(torch.as_tensor(self.prob.pose))
+        self.scale.copy_(torch.as_tensor(self.prob.scale))
+        self.invdepth.copy_(torch.as_tensor(self.prob.invdepth))

@@ -29,6 +29,8 @@ struct WinIn {
   const vi_edges* ed;
   const vi_preint* imu;
   vi_report* rep;
+  double* scale = nullptr;                // pose-graph adjustment: keyframe scales
+  const vi_rel_poses* rel = nullptr;      // pose-graph adjustment: relative-pose factors (marks the mode)
 };
 
 }  // namespace
@@ -139,6 +141,12 @@ std::vector<int32_t> plan_signature(const std::vector<WinIn>& wins) {
     s.push_back(in.ed->n_edges);
     s.insert(s.end(), in.ed->ii, in.ed->ii + in.ed->n_edges);
     s.insert(s.end(), in.ed->jj, in.ed->jj + in.ed->n_edges);
+    if (in.rel) {
+      s.push_back(-7);     // pose-graph mode marker
+      s.push_back(in.rel->n_rel);
+      s.insert(s.end(), in.rel->ii, in.rel->ii + in.rel->n_rel);
+      s.insert(s.end(), in.rel->jj, in.rel->jj + in.rel->n_rel);
+    }
   }
   return s;
 }
@@ -146,6 +154,11 @@ std::vector<int32_t> plan_signature(const std::vector<WinIn>& wins) {
 vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
   P = Plan();
   const int nw = (int)wins.size();
+  // pose-graph adjustment (one window): 7 unknowns per keyframe, 7x7 blocks,
+  // relative-pose factors instead of inertial ones
+  const bool pg = nw > 0 && wins[0].rel != nullptr;
+  const int PD = pg ? 7 : 15, ZD = pg ? 49 : 36, ZBD = pg ? 7 : 6;
+  P.pdim = PD;
   P.n_win = nw;
   P.win.resize(nw);
   int kf = 0, ed = 0, fa = 0;
@@ -161,7 +174,7 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
     W.kf_base = kf;
     W.e_base = ed;
     W.f_base = fa;
-    W.F = W.N - 1;
+    W.F = pg ? 0 : W.N - 1;
     W.pix_base = pix;
     const int E = in.ed->n_edges;
     for (int e = 0; e < E; ++e) {
@@ -220,13 +233,33 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
   for (int g = 0; g < P.N; ++g) {
     const int k = cnt[g];
     const WinDev& W = P.win[P.win_of_kf[g]];
-    const int T = k > 0 ? (6 * k + 16) / 16 : 0;
+    // the fused assembly writes the tiles of (6 k + 1) columns for every
+    // source, one tile (the right-hand-side column alone) when k = 0
+    const int T = (6 * k + 16) / 16;
     P.gram_off[g] = (int32_t)go;
     P.z_off[g] = (int32_t)zo;
     P.zb_off[g] = (int32_t)zbo;
     go += (size_t)T * (T + 1) / 2 * 256 * ((W.HW + kRangeMin - 1) / kRangeMin);
-    zo += (size_t)(k + 1) * (k + 1) * 36;
-    zbo += (size_t)6 * (k + 1);
+    zo += (size_t)(k + 1) * (k + 1) * ZD;
+    zbo += (size_t)ZBD * (k + 1);
+  }
+  if (pg) {
+    // relative-pose factors: four 7x7 blocks ((i,i), (i,j), (j,i), (j,j)) and 14 diagonal / right-hand-side entries
+    const vi_rel_poses* rel = wins[0].rel;
+    P.R = rel->n_rel;
+    for (int f = 0; f < P.R; ++f) {
+      const int i = rel->ii[f], j = rel->jj[f];
+      if (i < 0 || i >= P.win[0].N || j < 0 || j >= P.win[0].N || i == j)
+        return fail(ctx, VI_EINVAL, "relative pose %d: bad keyframe pair (%d, %d)", f, i, j);
+      P.rel_ii.push_back(i);
+      P.rel_jj.push_back(j);
+      P.rel_z.push_back((int32_t)zo);
+      P.rel_zb.push_back((int32_t)zbo);
+      zo += 4 * 49;
+      zbo += 14;
+    }
+    P.win[0].rel_base = 0;
+    P.win[0].n_rel = P.R;
   }
   if (go > INT32_MAX || zo > INT32_MAX) return fail(ctx, VI_EUNSUPPORTED, "batch too large for 32-bit offsets");
   P.gram_size = go;
@@ -237,7 +270,7 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
   size_t A_off = 0, L_off = 0, x_off = 0;
   for (int w = 0; w < nw; ++w) {
     WinDev& W = P.win[w];
-    W.n = 15 * W.N;
+    W.n = PD * W.N;
     W.npad = (W.n + kCholNB - 1) / kCholNB * kCholNB;
     W.nblk = W.npad / kCholNB;
     W.A_off = (long long)A_off;
@@ -258,15 +291,28 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
       for (int s = P.src_off[g]; s < P.src_off[g + 1]; ++s) T.push_back(P.jj[P.src_edges[s]] - W.kf_base);
       for (int ta = 0; ta <= k; ++ta)
         for (int tb = 0; tb <= k; ++tb) {
-          items[(size_t)T[ta] * W.N + T[tb]].push_back({P.z_off[g] + (ta * (k + 1) + tb) * 36, P.zb_off[g] + 6 * ta});
+          items[(size_t)T[ta] * W.N + T[tb]].push_back({P.z_off[g] + (ta * (k + 1) + tb) * ZD, P.zb_off[g] + ZBD * ta});
           bw_vis = std::max(bw_vis, std::abs(T[ta] - T[tb]));
         }
     }
-    // scalar half-bandwidth of S and the tile band of S and of its factor: the
-    // vision terms couple only the 6 pose unknowns at the head of each
-    // keyframe's 15 (15 d + 5 apart for keyframes d apart), the inertial factors
-    // the full blocks of consecutive keyframes (15 + 14)
-    const int wsc = std::max(15 * bw_vis + 5, 15 + 14);
+    int bw_rel = 0;
+    if (pg) {
+      for (int f = 0; f < P.R; ++f) {
+        const int i = P.rel_ii[f], j = P.rel_jj[f];
+        const int zf = P.rel_z[f], zbf = P.rel_zb[f];
+        items[(size_t)i * W.N + i].push_back({zf, zbf});
+        items[(size_t)i * W.N + j].push_back({zf + 49, zbf});
+        items[(size_t)j * W.N + i].push_back({zf + 98, zbf + 7});
+        items[(size_t)j * W.N + j].push_back({zf + 147, zbf + 7});
+        bw_rel = std::max(bw_rel, std::abs(i - j));
+      }
+    }
+    // scalar half-bandwidth of S and the tile band of S and of its factor.
+    // Visual-inertial step: the vision terms couple only the 6 pose unknowns at
+    // the head of each keyframe's 15 (15 d + 5 apart for keyframes d apart),
+    // the inertial factors the full blocks of consecutive keyframes (15 + 14).
+    // Pose graph: full 7-blocks of keyframes d apart (7 d + 6).
+    const int wsc = pg ? 7 * std::max(bw_vis, bw_rel) + 6 : std::max(15 * bw_vis + 5, 15 + 14);
     W.band = std::min(W.nblk - 1, (wsc + kCholNB - 1) / kCholNB);
     // this window's table: entries pair_base .. pair_base + N*N (the last one is its end)
     W.pair_base = (int)P.pair_off.size();
@@ -363,6 +409,7 @@ Work do_carve(const Plan& P, void* base, size_t* bytes) {
   w.x = c.take<double>(P.x_size);
   w.dd = c.take<double>((size_t)P.pix_total);
   w.trace = c.take<double>((size_t)P.n_win * kTraceLen);
+  w.rcost = c.take<double>((size_t)std::max(P.R, 1));
   if (bytes) *bytes = c.off;
   return w;
 }
@@ -372,7 +419,7 @@ vi_status upload_plan(vi_ctx* ctx) {
   const Plan& P = ctx->plan;
   const std::vector<int32_t>* parts[] = {&P.ii, &P.jj, &P.win_of_kf, &P.win_of_f, &P.src_off, &P.src_edges,
                                          &P.gram_off, &P.z_off, &P.zb_off, &P.pair_off, &P.pair_z, &P.pair_zb,
-                                         &P.chol_tiles};
+                                         &P.chol_tiles, &P.rel_ii, &P.rel_jj, &P.rel_z, &P.rel_zb};
   size_t total = align256(sizeof(WinDev) * P.n_win);
   for (auto* v : parts) total += align256(std::max<size_t>(v->size(), 1) * sizeof(int32_t));
   if (total > ctx->d_plan_cap) {
@@ -383,7 +430,7 @@ vi_status upload_plan(vi_ctx* ctx) {
   }
   std::vector<char> host(total, 0);
   size_t off = align256(sizeof(WinDev) * P.n_win);
-  const int32_t* dptr[13];
+  const int32_t* dptr[17];
   int idx = 0;
   for (auto* v : parts) {
     if (!v->empty()) std::memcpy(host.data() + off, v->data(), v->size() * sizeof(int32_t));
@@ -397,6 +444,7 @@ vi_status upload_plan(vi_ctx* ctx) {
   D.ii = dptr[0]; D.jj = dptr[1]; D.win_of_kf = dptr[2]; D.win_of_f = dptr[3]; D.src_off = dptr[4];
   D.src_edges = dptr[5]; D.gram_off = dptr[6]; D.z_off = dptr[7]; D.zb_off = dptr[8];
   D.pair_off = dptr[9]; D.pair_z = dptr[10]; D.pair_zb = dptr[11]; D.chol_tiles = dptr[12];
+  D.rel_ii = dptr[13]; D.rel_jj = dptr[14]; D.rel_z = dptr[15]; D.rel_zb = dptr[16];
   return VI_OK;
 }
 
@@ -427,6 +475,7 @@ vi_status ensure_plan(vi_ctx* ctx, const std::vector<WinIn>& wins) {
   ctx->plan_version++;
   if (ctx->plan.kmax > ctx->attr_kmax) {
     step_set_attributes(ctx->plan.kmax);
+    pg_set_attributes();
     ctx->attr_kmax = ctx->plan.kmax;
   }
   return VI_OK;
@@ -444,6 +493,9 @@ vi_status refresh_windows(vi_ctx* ctx, const std::vector<WinIn>& wins) {
     W.target = in.ed->target; W.weight = in.ed->weight; W.imu = in.imu;
     W.rep_dxi = in.rep ? in.rep->dxi : nullptr;
     W.rep_dd = in.rep ? in.rep->dd : nullptr;
+    W.scale = in.scale;
+    W.rel_meas = in.rel ? in.rel->meas : nullptr;
+    W.rel_info = in.rel ? in.rel->info : nullptr;
   }
   HIPCHK(ctx, hipMemcpy(ctx->d_win, P.win.data(), sizeof(WinDev) * P.n_win, hipMemcpyHostToDevice));
   return VI_OK;
@@ -742,6 +794,109 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
   return VI_OK;
 }
 
+
+// Host checks of a pose-graph problem; fills the window description.
+vi_status pg_window(vi_ctx* ctx, const vi_camera* cam, int32_t n_kf, double* pose, double* scale, double* invdepth,
+                    const vi_edges* loops, const vi_rel_poses* rel, const vi_opts* o, vi_report* rep, bool full,
+                    vi_state& st, WinIn& in) {
+  if (!cam || !loops || !rel) return fail(ctx, VI_EINVAL, "null argument");
+  vi_status s = check_opts(ctx, o);
+  if (s != VI_OK) return s;
+  if (rel->n_rel < 0) return fail(ctx, VI_EINVAL, "negative relative-pose count");
+  if (rel->n_rel > 0 && (!rel->ii || !rel->jj)) return fail(ctx, VI_EINVAL, "null relative-pose index array");
+  if (full && rel->n_rel > 0 && (!rel->meas || !rel->info))
+    return fail(ctx, VI_EINVAL, "null relative-pose measurement array");
+  if (full && (!pose || !scale || !invdepth)) return fail(ctx, VI_EINVAL, "null state array");
+  st = vi_state{};
+  st.n_kf = n_kf;
+  st.pose = pose;
+  st.vel = pose;          // not used by the pose-graph adjustment
+  st.bias = pose;
+  st.invdepth = invdepth;
+  in = WinIn{cam, &st, loops, nullptr, rep};
+  in.scale = scale;
+  in.rel = rel;
+  vi_opts oo = *o;
+  oo.use_imu = 0;
+  return check_window(ctx, 0, in, &oo, full);
+}
+
+// iters damped Gauss-Newton steps of the pose-graph adjustment in Sim(3),
+// launched eagerly on the private stream; per step: fused vision assembly
+// (loop pairs), per-source 7x7 blocks, relative-pose factors, cost of the
+// linearisation point, reduced system, Cholesky, back-substitution and
+// retraction; then the final cost
+vi_status run_pgba(vi_ctx* ctx, const vi_camera* cam, int32_t n_kf, double* pose, double* scale, double* invdepth,
+                   const vi_edges* loops, const vi_rel_poses* rel, const vi_opts* o, int iters, void* workspace,
+                   size_t workspace_bytes, vi_report* rep) {
+  vi_state st;
+  WinIn in{nullptr, nullptr, nullptr, nullptr, nullptr};
+  vi_status s = pg_window(ctx, cam, n_kf, pose, scale, invdepth, loops, rel, o, rep, true, st, in);
+  if (s != VI_OK) return s;
+  if (iters < 1 || iters > kMaxIters) return fail(ctx, VI_EINVAL, "iters must be in [1, %d]", kMaxIters);
+  if (!workspace) return fail(ctx, VI_EINVAL, "null workspace");
+  if (((uintptr_t)workspace & 255) != 0) return fail(ctx, VI_EINVAL, "workspace must be 256-byte aligned");
+  HIPCHK(ctx, hipSetDevice(ctx->device));
+  std::vector<WinIn> wins{in};
+  s = ensure_plan(ctx, wins);
+  if (s != VI_OK) return s;
+  Plan& P = ctx->plan;
+  size_t need = 0;
+  do_carve(P, nullptr, &need);
+  if (workspace_bytes < need)
+    return fail(ctx, VI_ENOMEM, "workspace too small: %zu bytes given, %zu needed", workspace_bytes, need);
+  Work w = do_carve(P, workspace, nullptr);
+  OptsDev od{o->n_fixed, 0, 0, o->precision, o->lm_lambda, o->depth_eta, o->z_min, o->d_min, ctx->tol};
+  HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
+  HIPCHK(ctx, hipStreamWaitEvent(ctx->priv, ctx->ev_in, 0));
+  hipStream_t sp = ctx->priv;
+  s = refresh_windows(ctx, wins);
+  if (s != VI_OK) return s;
+  const DevPlan& D = ctx->dplan;
+  const int ncost = cost_slots(P);
+  launch_reset_status(sp, ctx->status, P.n_win);
+  for (int it = 0; it < iters; ++it) {
+    launch_vis_assembly(sp, P, D, w, od, ctx->status);
+    launch_pg_local(sp, P, D, w, ctx->status);
+    launch_pg_relpose(sp, P, D, w, ctx->status, true);
+    launch_pg_cost(sp, P, D, w, ncost, P.range, it, od.tol, ctx->status);
+    launch_pg_assemble(sp, P, D, w, od.n_fixed, od.lambda, ctx->status);
+    launch_chol(sp, P, D, w, ctx->status);
+    launch_pg_backsub(sp, P, D, w, od, ctx->status);
+  }
+  launch_vis_cost(sp, P, D, w, od);
+  launch_pg_relpose(sp, P, D, w, ctx->status, false);
+  launch_pg_cost(sp, P, D, w, ncost, kVisBlock, iters, 0.0, nullptr);
+  HIPCHK(ctx, hipGetLastError());
+  DevStatus hs;
+  std::vector<double> trace(kTraceLen);
+  HIPCHK(ctx, hipMemcpyAsync(&hs, ctx->status, sizeof(DevStatus), hipMemcpyDeviceToHost, sp));
+  HIPCHK(ctx, hipMemcpyAsync(trace.data(), w.trace, sizeof(double) * kTraceLen, hipMemcpyDeviceToHost, sp));
+  HIPCHK(ctx, hipStreamSynchronize(sp));
+  if (rep) {
+    rep->iters_done = hs.iters;
+    rep->tile_px = P.range;
+    const int last = std::max(0, std::min(hs.iters, iters) - 1);
+    rep->cost_before = trace[2 * last];
+    rep->n_valid = (int64_t)trace[2 * last + 1];
+    rep->cost_after = trace[2 * iters];
+    if (rep->costs)
+      for (int t = 0; t <= iters; ++t) rep->costs[t] = trace[2 * t];
+    if (rep->stage_ms)
+      for (int k = 0; k < VI_NUM_STAGES; ++k) rep->stage_ms[k] = 0.0f;
+  }
+  if (hs.code != 0) {
+    if (hs.code == VI_ENOTPD)
+      return fail(ctx, VI_ENOTPD, "reduced system not positive definite at coordinate %d (step %d)", hs.detail,
+                  hs.iters);
+    if (hs.code == VI_ENONFINITE)
+      return fail(ctx, VI_ENONFINITE, "non-finite reduced system at coordinate %d (step %d)", hs.detail, hs.iters);
+    return fail(ctx, (vi_status)hs.code, "device error %d (detail %d)", hs.code, hs.detail);
+  }
+  ctx->err.clear();
+  return VI_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -875,6 +1030,29 @@ vi_status vi_ba_solve_batched(vi_ctx* ctx, int32_t n_windows, const vi_window* w
   for (int w = 0; w < n_windows; ++w)
     wins.push_back(WinIn{&windows[w].cam, &windows[w].state, &windows[w].edges, windows[w].imu, windows[w].report});
   return run(ctx, wins, opts, iters, workspace, workspace_bytes);
+}
+
+size_t vi_pgba_workspace_size(const vi_camera* cam, int32_t n_kf, const vi_edges* loops, const vi_rel_poses* rel,
+                              const vi_opts* opts) {
+  vi_state st;
+  WinIn in{nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (pg_window(nullptr, cam, n_kf, nullptr, nullptr, nullptr, loops, rel, opts, nullptr, false, st, in) != VI_OK)
+    return 0;
+  std::vector<WinIn> wins{in};
+  Plan P;
+  if (build_plan(nullptr, wins, P) != VI_OK) return 0;
+  set_range(P, default_range(P));
+  size_t b = 0;
+  do_carve(P, nullptr, &b);
+  return b;
+}
+
+vi_status vi_pgba_solve(vi_ctx* ctx, const vi_camera* cam, int32_t n_kf, double* pose, double* scale,
+                        double* invdepth, const vi_edges* loops, const vi_rel_poses* rel, const vi_opts* opts,
+                        int32_t iters, void* workspace, size_t workspace_bytes, vi_report* report) {
+  if (!ctx) return VI_EINVAL;
+  return run_pgba(ctx, cam, n_kf, pose, scale, invdepth, loops, rel, opts, iters, workspace, workspace_bytes,
+                  report);
 }
 
 vi_status vi_ba_step(vi_ctx* ctx, const vi_camera* cam, vi_state* state, const vi_edges* edges,

@@ -189,17 +189,23 @@ struct BlockSum {
   __device__ __forceinline__ double value() const { return (double)s - (double)c; }
 };
 
-// relative transform of edge (i -> j) of one window: R_ji = R_j^T R_i,
-// t_ji = R_j^T (p_i - p_j); i, j are indices into the window's pose array
-__device__ __forceinline__ void edge_rel(const double* __restrict__ pose, int i, int j, double* o) {
+// relative transform of edge (i -> j) of one window, the map that takes
+// camera i coordinates to camera j coordinates: R_ji = R_j^T R_i,
+// t_ji = R_j^T (p_i - p_j); with keyframe scales (Sim(3) poses of the
+// pose-graph adjustment, X_w = s R X + p) o[0..8] = (s_i / s_j) R_ji and
+// t_ji = R_j^T (p_i - p_j) / s_j.  i, j index the window's pose array.
+__device__ __forceinline__ void edge_rel(const WinDev& W, int i, int j, double* o) {
+  const double* pose = W.pose;
   double Ri[9], Rj[9], Rji[9], dp[3], tji[3];
   quat_to_rot(pose + (size_t)i * 7 + 3, Ri);
   quat_to_rot(pose + (size_t)j * 7 + 3, Rj);
   m3_tmul(Rj, Ri, Rji);
   for (int k = 0; k < 3; ++k) dp[k] = pose[(size_t)i * 7 + k] - pose[(size_t)j * 7 + k];
   m3_tvec(Rj, dp, tji);
-  for (int k = 0; k < 9; ++k) o[k] = Rji[k];
-  for (int k = 0; k < 3; ++k) o[9 + k] = tji[k];
+  const double sij = W.scale ? W.scale[i] / W.scale[j] : 1.0;
+  const double isj = W.scale ? 1.0 / W.scale[j] : 1.0;
+  for (int k = 0; k < 9; ++k) o[k] = sij * Rji[k];
+  for (int k = 0; k < 3; ++k) o[9 + k] = isj * tji[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -599,16 +605,19 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
   if (tid < k) {
     const int e = D.src_edges[e0 + tid];
     double r12[12];
-    edge_rel(W.pose, ls, D.jj[e] - W.kf_base, r12);
+    edge_rel(W, ls, D.jj[e] - W.kf_base, r12);
 #pragma unroll
     for (int q = 0; q < 12; ++q) rel_s[tid * 12 + q] = (R)r12[q];
     if (kr == 0)
       for (int q = 0; q < 12; ++q) rel[(size_t)e * 12 + q] = r12[q];
   }
   if (kr == 0 && tid == 0) {
+    // R of the keyframe (R / s with keyframe scales: R^T / s maps world
+    // offsets into the scaled camera frame)
     double Rm[9];
     quat_to_rot(W.pose + (size_t)ls * 7 + 3, Rm);
-    for (int q = 0; q < 9; ++q) Rw[(size_t)src * 9 + q] = Rm[q];
+    const double is = W.scale ? 1.0 / W.scale[ls] : 1.0;
+    for (int q = 0; q < 9; ++q) Rw[(size_t)src * 9 + q] = is * Rm[q];
   }
   for (int i = tid; i < 2 * tsz; i += kVisThreads) Et[i] = (R)0;
   __syncthreads();
@@ -1370,7 +1379,7 @@ __global__ void __launch_bounds__(256) k_vis_cost(OptsDev o, DevPlan D, int ncos
   const int e0 = D.src_off[src];
   const int k = D.src_off[src + 1] - e0;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid < k) edge_rel(W.pose, ls, D.jj[D.src_edges[e0 + tid]] - W.kf_base, rel + tid * 12);
+  if (tid < k) edge_rel(W, ls, D.jj[D.src_edges[e0 + tid]] - W.kf_base, rel + tid * 12);
   __syncthreads();
   const int p = kr * kVisBlock + tid;
   const bool inpx = p < HW;
@@ -1482,7 +1491,7 @@ __global__ void __launch_bounds__(256) k_warm_features(OptsDev o, DevPlan D, int
   const int tid = threadIdx.x;
   const int hq0 = (W.H + 3) / 4, wq0 = (W.W + 3) / 4;
   const int npix = HQ * WQ;
-  if (tid < k) edge_rel(W.pose, ls, D.jj[D.src_edges[e0 + tid]] - W.kf_base, rel_s + tid * 12);
+  if (tid < k) edge_rel(W, ls, D.jj[D.src_edges[e0 + tid]] - W.kf_base, rel_s + tid * 12);
   if (blockIdx.x == 0 && tid == 0) {
     for (int q = 0; q < 15; ++q) rimu[q] = 0.0;
     if (o.use_imu && ls + 1 < W.N) imu_residual_jacobian(W.pose, W.vel, W.bias, W.imu + ls, W.g, ls, rimu, nullptr);
@@ -1665,6 +1674,22 @@ static void launch_front(hipStream_t s, const Plan& P, const DevPlan& D, const W
                      P.range, D, w.Rw, w.rel, w.hpart, w.gpart, w.Z, w.ZB, w.ZV, w.vcost, w.icost, o.use_imu, w.trace,
                      iter, o.tol, st);
   done(kStLocal);
+}
+
+void launch_vis_assembly(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o,
+                         DevStatus* st) {
+  const int nkr_run = (P.hw_max + P.range - 1) / P.range;
+  const bool f64 = o.precision != VI_PREC_MIXED;
+  VisKernel kern = f64 ? vis_kernel<double>(P.kmax) : vis_kernel<float>(P.kmax);
+  hipLaunchKernelGGL(kern, dim3(nkr_run, P.N), dim3(kVisThreads), vis_lds(P.kmax, f64), s, o, D, 0, 0, P.nkr_max,
+                     cost_slots(P), P.range, w.Lam, w.Rw, w.rel, w.Cd, w.wd, w.hpart, w.gpart, w.vcost, w.Hf, w.gf,
+                     w.icost, st);
+}
+
+void launch_vis_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o) {
+  auto kvc = (o.precision == VI_PREC_MIXED) ? k_vis_cost<float> : k_vis_cost<double>;
+  hipLaunchKernelGGL(kvc, dim3((P.hw_max + kVisBlock - 1) / kVisBlock, P.N), dim3(256), 0, s, o, D, cost_slots(P),
+                     w.vcost, nullptr, nullptr, 0, 0, 0.0);
 }
 
 void launch_tune_stages(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o,

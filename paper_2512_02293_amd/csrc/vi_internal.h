@@ -58,6 +58,11 @@ struct WinDev {
   const vi_preint* imu;
   double* rep_dxi;
   double* rep_dd;
+  // pose-graph adjustment in Sim(3) (null / 0 for the visual-inertial step)
+  double* scale;                     // [N] keyframe scales s (X_w = s R X_c + p), updated in place
+  const double* rel_meas;            // [n_rel][8] measured E_ij = T_j^-1 T_i: t (3), q (4), s
+  const double* rel_info;            // [n_rel][49] information, (rotation, translation, log-scale) order
+  int rel_base, n_rel;               // global index of the window's first relative-pose factor
 };
 
 // Host-built description of one batch.
@@ -78,6 +83,10 @@ struct Plan {
   std::vector<int32_t> gram_off, z_off, zb_off;
   std::vector<int32_t> pair_off, pair_z, pair_zb;
   std::vector<int32_t> chol_tiles;             // ticket -> (window, (i << 16) | j)
+  int pdim = 15;                               // unknowns per keyframe: 15 (visual-inertial) or 7 (Sim(3) graph)
+  int R = 0;                                   // relative-pose factors (pose-graph adjustment)
+  std::vector<int32_t> rel_ii, rel_jj;         // global keyframe indices per factor
+  std::vector<int32_t> rel_z, rel_zb;          // offsets of each factor's four 7x7 blocks in Z and its 14 in ZB/ZV
   int n_tickets = 0;
   int n_bs = 0;                                // back-substitution columns after the tiles in chol_tiles
   size_t flags_size = 0;
@@ -91,6 +100,7 @@ struct DevPlan {
   const int32_t *gram_off, *z_off, *zb_off;
   const int32_t *pair_off, *pair_z, *pair_zb;
   const int32_t* chol_tiles;
+  const int32_t *rel_ii, *rel_jj, *rel_z, *rel_zb;
   const WinDev* win;
 };
 
@@ -117,6 +127,7 @@ struct Work {
   double* x;         // per window [npad]
   double* dd;        // [pix_total]
   double* trace;     // [n_win][kTraceLen]  cost, n_valid per slot
+  double* rcost;     // [R]  relative-pose factor costs (pose-graph adjustment)
 };
 
 struct OptsDev {
@@ -160,6 +171,22 @@ void launch_final_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Wor
                        int slot, double* trace = nullptr, const float* dd = nullptr, const float* db = nullptr,
                        int HQ = 0, int WQ = 0, double d_min = 0.0);   // trace: w.trace unless given
 void launch_chol(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, DevStatus* st);
+// the fused vision assembly alone (no inertial workgroups) and the vision cost
+// of the current state (vcost in ranges of kVisBlock pixels)
+void launch_vis_assembly(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o,
+                         DevStatus* st);
+void launch_vis_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o);
+// pose-graph adjustment in Sim(3) (k_pgba.hip)
+size_t pg_local_lds(int kmax);
+void pg_set_attributes();
+void launch_pg_local(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, DevStatus* st);
+void launch_pg_relpose(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, DevStatus* st, bool jac);
+void launch_pg_assemble(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, int n_fixed, double lambda,
+                        DevStatus* st);
+void launch_pg_backsub(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, const OptsDev& o,
+                       DevStatus* st);
+void launch_pg_cost(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, int ncost, int range_px,
+                    int slot, double tol, DevStatus* st);
 void step_set_attributes(int kmax);
 // warm start
 void wnet_set_attributes();

@@ -10,6 +10,7 @@
 * A source keyframe with the largest supported out-degree (18: a 7-tile
   Schur Gram, 28 lower tiles, every Gram slot of the assembly in use), in
   FP64 and in mixed precision.
+* Keyframes with no outgoing edge (targets only).
 * Non-finite inputs: VI_ENONFINITE and the state left bit for bit.
 * The 64-window batch in mixed precision, every window against the oracle.
 
@@ -131,6 +132,21 @@ def test_step_out_degree_18(ctx, precision):
         _step_vs_oracle(ctx, prob)
     else:
         _step_vs_oracle(ctx, prob, precision=1, tol_group=1e-4, tol_depth=1e-3)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_step_keyframes_without_outgoing_edges(ctx, precision):
+    """Keyframes that are targets only (out-degree 0, first, middle and last
+    of the window): no Schur block of their own, inverse depths untouched
+    (dd = 0), yet the fused assembly still visits them."""
+    cfg = synth.SceneConfig(n_kf=8, H=24, W=32, out_degrees=[3, 0, 2, 3, 0, 3, 2, 0])
+    prob = synth.make_problem(cfg, 61)
+    assert (np.bincount(prob.ii, minlength=8) == 0).sum() == 3
+    if precision == 0:
+        rep, orep = _step_vs_oracle(ctx, prob)
+    else:
+        rep, orep = _step_vs_oracle(ctx, prob, precision=1, tol_group=1e-4, tol_depth=1e-3)
+    assert not orep["dd"][[1, 4, 7]].any()
 
 
 @pytest.mark.parametrize("what", ["target_nan", "weight_nan", "target_inf", "invdepth_nan"])
