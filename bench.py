@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 64-window batch, the global problem and the warm-start lines")
     ap.add_argument("--only", choices=["global", "warm-windows", "gaussian-reanchor", "predict-keyframe",
-                                       "inertial-init", "assembly"],
+                                       "inertial-init", "assembly", "pgba"],
                     default=None,
                     help="run only that secondary workload and print its JSON (profiling runs)")
     return ap.parse_args()
@@ -131,9 +131,10 @@ def main():
     from paper_2512_02293_amd import binding, synth
     if args.only is not None:
         ctx = binding.Context(0)
+        ctx.set_autotune(bool(args.autotune))
         out = {"global": global_problem, "warm-windows": warm_windows, "gaussian-reanchor": gaussian_reanchor,
                "predict-keyframe": predict_keyframe, "inertial-init": inertial_init,
-               "assembly": assembly_roofline}[args.only](ctx)
+               "assembly": assembly_roofline, "pgba": lambda c: pgba_loop_closure(c, cpu=not args.no_cpu_baseline)}[args.only](ctx)
         if args.copy_calibration:
             out["copy_calibration_bytes"] = copy_calibration()
         print(json.dumps(out))
@@ -285,6 +286,7 @@ def extras(ctx):
                                "(captured during the warm-up), the windows solved one after another"}}
     res["assembly_roofline"] = assembly_roofline(ctx)
     res["global"] = global_problem(ctx)
+    res["pgba"] = pgba_loop_closure(ctx)
     res["gaussian_reanchor"] = gaussian_reanchor(ctx)
     res["predict_keyframe"] = predict_keyframe(ctx)
     res["inertial_init"] = inertial_init(ctx)
@@ -426,6 +428,60 @@ def global_problem(ctx, iters=2, reps=3):
         res[name] = {"ms_per_gn_iter": 1e3 * best / iters,
                      "pixel_residuals_per_s": prob.n_edges * prob.H * prob.W * iters / best,
                      "stage_ms_one_step": {k: round(v, 4) for k, v in st.items()}}
+    return res
+
+
+def pgba_loop_closure(ctx, iters=4, reps=3, cpu=True):
+    """Pose-graph bundle adjustment in Sim(3) (vi_pgba_solve) on the 512-keyframe
+    loop closure (synth.pgba_loop_closure_problem):
+    iters damped GN steps from the initial state, FP64 and mixed, best of reps
+    wall times of the (synchronous) call; the oracle's step on the host cores
+    beside it."""
+    import numpy as np
+    import torch
+
+    from paper_2512_02293_amd import binding, synth
+    prob = synth.pgba_loop_closure_problem()
+    pg = binding.DevicePGBA(prob)
+    pxres = prob.n_edges * prob.H * prob.W
+    res = {"workload": f"loop closure, {prob.n_kf} keyframes (Sim(3), 7 unknowns each), {prob.n_edges} loop pairs "
+                       f"of 60x80 maps, {len(prob.rel_ii)} relative poses (next 3 keyframes), reduced system "
+                       f"{7 * prob.n_kf} x {7 * prob.n_kf}; {iters} GN steps from the initial state",
+           "pixel_residuals_per_gn_iter": pxres, "relative_poses": int(len(prob.rel_ii))}
+    for name, prec in (("fp64", binding.VI_PREC_FP64), ("mixed", binding.VI_PREC_MIXED)):
+        o = binding.make_opts(use_imu=False, precision=prec)
+        ws = torch.empty(ctx.pgba_workspace_size(pg, o), dtype=torch.uint8, device="cuda:0")
+        pg.reset_state()
+        ctx.pgba_solve(pg, o, iters, ws)
+        best, rep = 1e30, None
+        for _ in range(reps):
+            pg.reset_state()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rep = ctx.pgba_solve(pg, o, iters, ws)
+            best = min(best, time.perf_counter() - t0)
+        res[name] = {"ms_per_gn_iter": 1e3 * best / iters, "pixel_residuals_per_s": pxres * iters / best,
+                     "cost_first": float(rep["costs"][0]), "cost_last": float(rep["costs"][-1]),
+                     "assembly_tile_px": rep["tile_px"]}
+    if cpu:
+        from threadpoolctl import threadpool_info
+
+        from oracle import pgba
+        from oracle.so3 import quat_to_R
+        cam = (prob.fx, prob.fy, prob.cx, prob.cy, prob.H, prob.W)
+        st = pgba.PGState(R=np.stack([quat_to_R(q) for q in prob.pose[:, 3:7]]), p=prob.pose[:, :3].copy(),
+                          s=prob.scale.copy(), d=prob.invdepth.copy())
+        Tm = np.stack([pgba.mat(m[7], quat_to_R(m[3:7]), m[0:3]) for m in prob.rel_meas])
+        gr = pgba.PGGraph(ii=prob.ii, jj=prob.jj, target=prob.target.astype(np.float64),
+                          weight=prob.weight.astype(np.float64), rel_ii=prob.rel_ii, rel_jj=prob.rel_jj, rel_T=Tm,
+                          rel_info=prob.rel_info)
+        t0 = time.perf_counter()
+        pgba.step(cam, st, gr, pgba.PGOptions())
+        t_step = time.perf_counter() - t0
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+        res["cpu_baseline"] = {"value": 1e3 * t_step, "unit": "ms per GN step", "cores": threads, "kind": "oracle",
+                               "sample": "one oracle step on the same problem (NumPy float64, BLAS on its default "
+                                         "threads), linearisation, Schur solve and the cost of the new state"}
     return res
 
 

@@ -482,7 +482,7 @@ class Context:
                                     workspace.numel(), C.byref(rep))
         self._check(rc)
         return dict(cost_before=rep.cost_before, cost_after=rep.cost_after, n_valid=int(rep.n_valid),
-                    iters_done=int(rep.iters_done), costs=costs)
+                    iters_done=int(rep.iters_done), tile_px=int(rep.tile_px), costs=costs)
 
     def predict_keyframe(self, pose_prev, vel_prev, bias_prev, imu, gravity, tau=1e-4, pose_new=None,
                          vel_new=None, bias_new=None, used_imu=None):

@@ -151,6 +151,130 @@ std::vector<int32_t> plan_signature(const std::vector<WinIn>& wins) {
   return s;
 }
 
+// ---------------------------------------------------------------------------
+// Order of the keyframes in a window's reduced system, and the envelope of S.
+// The Cholesky factor of S is nonzero only inside the envelope of S (in each
+// row, from the first nonzero column to the diagonal), so the tile dataflow
+// only visits tiles (i, j) with fc[i] <= j, and inside a tile only the
+// k >= max(fc[i], fc[j]).  Loop edges widen the envelope far beyond the band
+// of nearby keyframes; a reverse Cuthill-McKee order of the keyframe coupling
+// graph (breadth-first from a pseudo-peripheral keyframe, neighbours by
+// increasing degree, the whole sequence reversed) narrows it again.  The
+// order is taken only when it lowers the factorisation's work.
+// ---------------------------------------------------------------------------
+struct Coupling {
+  int a, b;
+  bool full;   // all unknowns of both keyframes coupled (else only the 6 pose unknowns at the head of each block)
+};
+
+std::vector<int> rcm_order(int N, const std::vector<std::vector<int>>& adj) {
+  std::vector<int> deg(N), order, dist(N, -1), comp;
+  for (int v = 0; v < N; ++v) deg[v] = (int)adj[v].size();
+  std::vector<char> done(N, 0);
+  order.reserve(N);
+  auto by_degree = [&](int x, int y) { return deg[x] != deg[y] ? deg[x] < deg[y] : x < y; };
+  // breadth-first levels from r over the component; returns the eccentricity and the last level
+  auto levels = [&](int r, std::vector<int>& last) {
+    for (int v : comp) dist[v] = -1;
+    std::vector<int> q{r};
+    dist[r] = 0;
+    for (size_t h = 0; h < q.size(); ++h)
+      for (int u : adj[q[h]])
+        if (dist[u] < 0) {
+          dist[u] = dist[q[h]] + 1;
+          q.push_back(u);
+        }
+    const int ecc = dist[q.back()];
+    last.clear();
+    for (int v : q)
+      if (dist[v] == ecc) last.push_back(v);
+    return ecc;
+  };
+  for (int s0 = 0; s0 < N; ++s0) {
+    if (done[s0]) continue;
+    // the component of s0
+    comp.assign(1, s0);
+    dist[s0] = 0;
+    for (size_t h = 0; h < comp.size(); ++h)
+      for (int u : adj[comp[h]])
+        if (dist[u] < 0) {
+          dist[u] = 0;
+          comp.push_back(u);
+        }
+    int root = *std::min_element(comp.begin(), comp.end(), by_degree);
+    std::vector<int> last, last2;
+    int ecc = levels(root, last);
+    for (int guard = 0; guard < N; ++guard) {
+      const int v = *std::min_element(last.begin(), last.end(), by_degree);
+      const int e2 = levels(v, last2);
+      if (e2 <= ecc) break;
+      root = v;
+      ecc = e2;
+      last.swap(last2);
+    }
+    // Cuthill-McKee sequence of the component
+    const size_t base = order.size();
+    order.push_back(root);
+    done[root] = 1;
+    std::vector<int> nb;
+    for (size_t h = base; h < order.size(); ++h) {
+      nb.clear();
+      for (int u : adj[order[h]])
+        if (!done[u]) nb.push_back(u);
+      std::sort(nb.begin(), nb.end(), by_degree);
+      for (int u : nb) {
+        done[u] = 1;
+        order.push_back(u);
+      }
+    }
+  }
+  std::reverse(order.begin(), order.end());
+  return order;
+}
+
+// first nonzero scalar column of each scalar row of S (lower triangle) with
+// keyframe a at block position pos[a]
+void scalar_envelope(int N, int PD, const std::vector<Coupling>& cpl, const std::vector<int>& pos,
+                     std::vector<int>& fcs) {
+  fcs.assign((size_t)N * PD, 0);
+  for (int a = 0; a < N; ++a)
+    for (int r = 0; r < PD; ++r) fcs[(size_t)pos[a] * PD + r] = pos[a] * PD;
+  for (const Coupling& c : cpl) {
+    int qa = pos[c.a], qb = pos[c.b];
+    if (qa == qb) continue;
+    if (qa < qb) std::swap(qa, qb);
+    const int rows = c.full ? PD : 6;
+    for (int r = 0; r < rows; ++r) fcs[(size_t)qa * PD + r] = std::min(fcs[(size_t)qa * PD + r], qb * PD);
+  }
+}
+
+// tile envelope (nblk + 1 entries, the last one the right-hand-side row), the
+// tile-update count of the dataflow factorisation over it and the tile band
+struct Envelope {
+  std::vector<int> fc;
+  long long work = 0;
+  int band = 0;
+};
+
+Envelope tile_envelope(const std::vector<int>& fcs, int n, int nblk) {
+  Envelope E;
+  E.fc.assign(nblk + 1, 0);
+  int wsc = 0;
+  for (int i = 0; i < nblk; ++i) {
+    int f = i;
+    for (int r = i * kCholNB; r < std::min(n, (i + 1) * kCholNB); ++r) {
+      f = std::min(f, fcs[r] / kCholNB);
+      wsc = std::max(wsc, r - fcs[r]);
+    }
+    E.fc[i] = f;
+  }
+  E.fc[nblk] = 0;
+  for (int i = 0; i <= nblk; ++i)
+    for (int j = E.fc[i]; j <= std::min(i, nblk - 1); ++j) E.work += 1 + (j - std::max(E.fc[i], E.fc[j]));
+  E.band = std::min(nblk - 1, (wsc + kCholNB - 1) / kCholNB);
+  return E;
+}
+
 vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
   P = Plan();
   const int nw = (int)wins.size();
@@ -195,6 +319,8 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
     P.hw_max = std::max(P.hw_max, W.HW);
   }
   P.N = kf;
+  P.kf_pos.assign(P.N, 0);
+  P.kf_at.assign(P.N, 0);
   P.E = ed;
   P.F = fa;
   P.pix_total = pix;
@@ -284,18 +410,14 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
     x_off += (size_t)W.npad;
     P.nblk_max = std::max(P.nblk_max, W.nblk);
     std::vector<std::vector<std::pair<int, int>>> items((size_t)W.N * W.N);
-    int bw_vis = 0;   // keyframe distance of the vision terms' pose-pose couplings
     for (int g = W.kf_base; g < W.kf_base + W.N; ++g) {
       const int k = cnt[g];
       std::vector<int> T(1, g - W.kf_base);
       for (int s = P.src_off[g]; s < P.src_off[g + 1]; ++s) T.push_back(P.jj[P.src_edges[s]] - W.kf_base);
       for (int ta = 0; ta <= k; ++ta)
-        for (int tb = 0; tb <= k; ++tb) {
+        for (int tb = 0; tb <= k; ++tb)
           items[(size_t)T[ta] * W.N + T[tb]].push_back({P.z_off[g] + (ta * (k + 1) + tb) * ZD, P.zb_off[g] + ZBD * ta});
-          bw_vis = std::max(bw_vis, std::abs(T[ta] - T[tb]));
-        }
     }
-    int bw_rel = 0;
     if (pg) {
       for (int f = 0; f < P.R; ++f) {
         const int i = P.rel_ii[f], j = P.rel_jj[f];
@@ -304,16 +426,50 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
         items[(size_t)i * W.N + j].push_back({zf + 49, zbf});
         items[(size_t)j * W.N + i].push_back({zf + 98, zbf + 7});
         items[(size_t)j * W.N + j].push_back({zf + 147, zbf + 7});
-        bw_rel = std::max(bw_rel, std::abs(i - j));
       }
     }
-    // scalar half-bandwidth of S and the tile band of S and of its factor.
-    // Visual-inertial step: the vision terms couple only the 6 pose unknowns at
-    // the head of each keyframe's 15 (15 d + 5 apart for keyframes d apart),
-    // the inertial factors the full blocks of consecutive keyframes (15 + 14).
-    // Pose graph: full 7-blocks of keyframes d apart (7 d + 6).
-    const int wsc = pg ? 7 * std::max(bw_vis, bw_rel) + 6 : std::max(15 * bw_vis + 5, 15 + 14);
-    W.band = std::min(W.nblk - 1, (wsc + kCholNB - 1) / kCholNB);
+    // couplings of S: the vision terms couple only the 6 pose unknowns at the
+    // head of each keyframe's 15 in the visual-inertial layout (all 7 in the
+    // pose graph); the inertial factors the full blocks of consecutive keyframes
+    std::vector<Coupling> cpl;
+    std::vector<std::vector<int>> adj(W.N);
+    for (int a = 0; a < W.N; ++a)
+      for (int b = 0; b < a; ++b)
+        if (!items[(size_t)a * W.N + b].empty()) cpl.push_back({a, b, pg});
+    if (!pg)
+      for (int a = 0; a + 1 < W.N; ++a) cpl.push_back({a + 1, a, true});
+    for (const Coupling& c : cpl) {
+      adj[c.a].push_back(c.b);
+      adj[c.b].push_back(c.a);
+    }
+    for (auto& v : adj) {
+      std::sort(v.begin(), v.end());
+      v.erase(std::unique(v.begin(), v.end()), v.end());
+    }
+    // natural order unless the reverse Cuthill-McKee order lowers the work of
+    // the factorisation path this window takes (tile updates of the dataflow
+    // path, the band of the one-workgroup path)
+    std::vector<int> pos(W.N), fcs;
+    for (int a = 0; a < W.N; ++a) pos[a] = a;
+    scalar_envelope(W.N, PD, cpl, pos, fcs);
+    Envelope env = tile_envelope(fcs, W.n, W.nblk);
+    const std::vector<int> rcm = rcm_order(W.N, adj);
+    std::vector<int> pos2(W.N);
+    for (int q = 0; q < W.N; ++q) pos2[rcm[q]] = q;
+    scalar_envelope(W.N, PD, cpl, pos2, fcs);
+    Envelope env2 = tile_envelope(fcs, W.n, W.nblk);
+    const bool small_path = W.npad <= kCholSmallMaxNpad;
+    if (small_path ? env2.band < env.band : env2.work < env.work) {
+      pos.swap(pos2);
+      env = std::move(env2);
+    }
+    for (int a = 0; a < W.N; ++a) {
+      P.kf_pos[W.kf_base + a] = pos[a];
+      P.kf_at[W.kf_base + pos[a]] = a;
+    }
+    W.band = env.band;
+    W.fc_off = (int)P.chol_fc.size();
+    P.chol_fc.insert(P.chol_fc.end(), env.fc.begin(), env.fc.end());
     // this window's table: entries pair_base .. pair_base + N*N (the last one is its end)
     W.pair_base = (int)P.pair_off.size();
     for (size_t q = 0; q < items.size(); ++q) {
@@ -334,6 +490,7 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
       const WinDev& W = P.win[w];
       if (j >= W.nblk || W.npad <= kCholSmallMaxNpad) continue;
       for (int i = j; i <= W.nblk; ++i) {
+        if (P.chol_fc[W.fc_off + i] > j) continue;      // outside the envelope: zero in S and in L
         P.chol_tiles.push_back(w);
         P.chol_tiles.push_back((i << 16) | j);
       }
@@ -354,6 +511,14 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
   return VI_OK;
 }
 
+// a coordinate of window w's reduced system (in its block order) as
+// keyframe * unknowns-per-keyframe + unknown
+int natural_coord(const Plan& P, int w, int c) {
+  const WinDev& W = P.win[w];
+  if (c < 0 || c >= W.n) return c;
+  return P.kf_at[W.kf_base + c / P.pdim] * P.pdim + c % P.pdim;
+}
+
 void set_range(Plan& P, int range) {
   P.range = range;
   for (WinDev& W : P.win) W.nkr = (W.HW + range - 1) / range;
@@ -367,7 +532,11 @@ int default_range(const Plan& P) {
   long long px = 0;
   for (int g = 0; g < P.N; ++g)
     if (P.src_off[g + 1] > P.src_off[g]) px += P.win[P.win_of_kf[g]].HW;
-  long long r = (px + kAssemblyWGTarget - 1) / kAssemblyWGTarget;
+  // pose graph: a source has few loop pairs (out-degree 1-3), so a chunk of
+  // pixels carries little work to hide the loads behind; shorter ranges
+  // (about four workgroups per compute unit) keep more chunks in flight
+  const long long target = P.pdim == 7 ? 4 * kAssemblyWGTarget : kAssemblyWGTarget;
+  long long r = (px + target - 1) / target;
   r = (r + 63) / 64 * 64;
   return (int)std::max<long long>(kRangeMin, std::min<long long>(r, (P.hw_max + 63) / 64 * 64));
 }
@@ -419,7 +588,8 @@ vi_status upload_plan(vi_ctx* ctx) {
   const Plan& P = ctx->plan;
   const std::vector<int32_t>* parts[] = {&P.ii, &P.jj, &P.win_of_kf, &P.win_of_f, &P.src_off, &P.src_edges,
                                          &P.gram_off, &P.z_off, &P.zb_off, &P.pair_off, &P.pair_z, &P.pair_zb,
-                                         &P.chol_tiles, &P.rel_ii, &P.rel_jj, &P.rel_z, &P.rel_zb};
+                                         &P.chol_tiles, &P.rel_ii, &P.rel_jj, &P.rel_z, &P.rel_zb,
+                                         &P.kf_pos, &P.kf_at, &P.chol_fc};
   size_t total = align256(sizeof(WinDev) * P.n_win);
   for (auto* v : parts) total += align256(std::max<size_t>(v->size(), 1) * sizeof(int32_t));
   if (total > ctx->d_plan_cap) {
@@ -430,7 +600,7 @@ vi_status upload_plan(vi_ctx* ctx) {
   }
   std::vector<char> host(total, 0);
   size_t off = align256(sizeof(WinDev) * P.n_win);
-  const int32_t* dptr[17];
+  const int32_t* dptr[20];
   int idx = 0;
   for (auto* v : parts) {
     if (!v->empty()) std::memcpy(host.data() + off, v->data(), v->size() * sizeof(int32_t));
@@ -445,6 +615,7 @@ vi_status upload_plan(vi_ctx* ctx) {
   D.src_edges = dptr[5]; D.gram_off = dptr[6]; D.z_off = dptr[7]; D.zb_off = dptr[8];
   D.pair_off = dptr[9]; D.pair_z = dptr[10]; D.pair_zb = dptr[11]; D.chol_tiles = dptr[12];
   D.rel_ii = dptr[13]; D.rel_jj = dptr[14]; D.rel_z = dptr[15]; D.rel_zb = dptr[16];
+  D.kf_pos = dptr[17]; D.kf_at = dptr[18]; D.chol_fc = dptr[19];
   return VI_OK;
 }
 
@@ -516,7 +687,8 @@ void mark_event(void* user, int stage_done) {
 // local-block stages only, which write the workspace, never the caller's state.
 vi_status autotune_range(vi_ctx* ctx, const Work& w, const OptsDev& od) {
   Plan& P = ctx->plan;
-  const auto key = std::make_tuple(P.hw_max, P.kmax, P.N, P.n_win);
+  const bool pg = P.pdim == 7;
+  const auto key = std::make_tuple(P.hw_max, P.kmax, P.N, P.n_win * (pg ? -1 : 1));
   auto it = ctx->tuned.find(key);
   if (it != ctx->tuned.end()) {
     set_range(P, it->second);
@@ -542,7 +714,14 @@ vi_status autotune_range(vi_ctx* ctx, const Work& w, const OptsDev& od) {
     float tot = 0.f;
     for (int rep = 0; rep < 3; ++rep) {
       HIPCHK(ctx, hipEventRecord(ev[0], sp));
-      launch_tune_stages(sp, P, ctx->dplan, w, od, mark_event, &tu);
+      if (pg) {
+        // pose graph: the fused assembly of the loop pairs and the per-source blocks
+        launch_vis_assembly(sp, P, ctx->dplan, w, od, ctx->status);
+        launch_pg_local(sp, P, ctx->dplan, w, ctx->status);
+        HIPCHK(ctx, hipEventRecord(ev[kStLocal + 1], sp));
+      } else {
+        launch_tune_stages(sp, P, ctx->dplan, w, od, mark_event, &tu);
+      }
       HIPCHK(ctx, hipEventSynchronize(ev[kStLocal + 1]));
       float ms = 0.f;
       HIPCHK(ctx, hipEventElapsedTime(&ms, ev[0], ev[kStLocal + 1]));
@@ -784,7 +963,7 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
     const DevStatus& b = hs[first_bad];
     if (b.code == VI_ENOTPD)
       return fail(ctx, VI_ENOTPD, "window %d: reduced system not positive definite at coordinate %d (step %d)",
-                  first_bad, b.detail, b.iters);
+                  first_bad, natural_coord(P, first_bad, b.detail), b.iters);
     if (b.code == VI_ENONFINITE)
       return fail(ctx, VI_ENONFINITE, "window %d: non-finite reduced system at coordinate %d (step %d)", first_bad,
                   b.detail, b.iters);
@@ -852,6 +1031,12 @@ vi_status run_pgba(vi_ctx* ctx, const vi_camera* cam, int32_t n_kf, double* pose
   hipStream_t sp = ctx->priv;
   s = refresh_windows(ctx, wins);
   if (s != VI_OK) return s;
+  if (ctx->autotune) {
+    s = autotune_range(ctx, w, od);
+    if (s != VI_OK) return s;
+    s = refresh_windows(ctx, wins);
+    if (s != VI_OK) return s;
+  }
   const DevPlan& D = ctx->dplan;
   const int ncost = cost_slots(P);
   launch_reset_status(sp, ctx->status, P.n_win);
@@ -887,8 +1072,8 @@ vi_status run_pgba(vi_ctx* ctx, const vi_camera* cam, int32_t n_kf, double* pose
   }
   if (hs.code != 0) {
     if (hs.code == VI_ENOTPD)
-      return fail(ctx, VI_ENOTPD, "reduced system not positive definite at coordinate %d (step %d)", hs.detail,
-                  hs.iters);
+      return fail(ctx, VI_ENOTPD, "reduced system not positive definite at coordinate %d (step %d)",
+                  natural_coord(P, 0, hs.detail), hs.iters);
     if (hs.code == VI_ENONFINITE)
       return fail(ctx, VI_ENONFINITE, "non-finite reduced system at coordinate %d (step %d)", hs.detail, hs.iters);
     return fail(ctx, (vi_status)hs.code, "device error %d (detail %d)", hs.code, hs.detail);

@@ -73,6 +73,15 @@ __device__ __forceinline__ bool wait_flag(const int* f, int* sync) {
   return true;
 }
 
+// The lane index behind an opaque move: address arithmetic derived from it
+// is recomputed where it is used instead of being hoisted out of the step
+// loops and held (spilled) across them.
+__device__ __forceinline__ int lane_id() {
+  int l;
+  asm volatile("v_and_b32 %0, 63, %1" : "=v"(l) : "v"((int)threadIdx.x));
+  return l;
+}
+
 __device__ __forceinline__ void publish(int* f) {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   if (threadIdx.x == 0) __hip_atomic_store(f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -106,7 +115,7 @@ __device__ __forceinline__ double rsqrt_refined(double v) {
 // transpose when ta), B(q, n) = Bop[q * ldb + n] (or Bop[n * ldb + q] when tb).
 __device__ __forceinline__ double4_t mm16(double4_t acc, const double* Aop, int lda, bool ta, const double* Bop,
                                           int ldb, bool tb, double sA) {
-  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int q = 4 * s + kq;
@@ -118,7 +127,7 @@ __device__ __forceinline__ double4_t mm16(double4_t acc, const double* Aop, int 
 }
 
 __device__ __forceinline__ double4_t load16(const double* M, int ld) {
-  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
   double4_t v;
 #pragma unroll
   for (int r = 0; r < 4; ++r) v[r] = M[(kq + 4 * r) * ld + mrow];
@@ -126,7 +135,7 @@ __device__ __forceinline__ double4_t load16(const double* M, int ld) {
 }
 
 __device__ __forceinline__ void store16(double* M, int ld, double4_t v) {
-  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int r = 0; r < 4; ++r) M[(kq + 4 * r) * ld + mrow] = v[r];
 }
@@ -260,7 +269,7 @@ __device__ __forceinline__ int factor_invert32(double* T, double* Li, double* U)
 // with strides ldx, ldy (global or LDS)
 __device__ __forceinline__ void mm32_abt(double4_t (&acc)[2][2], const double* X, size_t ldx, const double* Y,
                                          size_t ldy, double sA) {
-  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
   double a[2][8], b[2][8];
 #pragma unroll
   for (int s = 0; s < 8; ++s)
@@ -279,7 +288,7 @@ __device__ __forceinline__ void mm32_abt(double4_t (&acc)[2][2], const double* X
 }
 
 __device__ __forceinline__ void load_tile32(double4_t (&acc)[2][2], const double* M, size_t ld) {
-  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
@@ -289,7 +298,7 @@ __device__ __forceinline__ void load_tile32(double4_t (&acc)[2][2], const double
 }
 
 __device__ __forceinline__ void store_tile32(const double4_t (&acc)[2][2], double* M, size_t ld) {
-  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
@@ -305,7 +314,7 @@ __device__ __forceinline__ int swz(int r, int c) { return r * NB + (c ^ ((r * 4)
 
 // acc(2x2 blocks of 16x16) += sA * X Y^T over K = 32, X and Y swizzled LDS tiles
 __device__ __forceinline__ void mm32_abt_lds(double4_t (&acc)[2][2], const double* X, const double* Y, double sA) {
-  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     double a[2], b[2];
@@ -325,7 +334,7 @@ __device__ __forceinline__ void mm32_abt_lds(double4_t (&acc)[2][2], const doubl
 // acc(2x2 blocks of 16x16) += X Y^T over K = 32, X a swizzled LDS tile, Y a
 // padded (stride LD) LDS tile
 __device__ __forceinline__ void mm32_abt_swz_pad(double4_t (&acc)[2][2], const double* X, const double* Y) {
-  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int s = 0; s < 8; ++s) {
     double a[2], b[2];
@@ -343,7 +352,7 @@ __device__ __forceinline__ void mm32_abt_swz_pad(double4_t (&acc)[2][2], const d
 }
 
 __device__ __forceinline__ void acc_to_swz(const double4_t (&acc)[2][2], double* S) {
-  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
@@ -353,7 +362,7 @@ __device__ __forceinline__ void acc_to_swz(const double4_t (&acc)[2][2], double*
 }
 
 __device__ __forceinline__ void swz_to_acc(double4_t (&acc)[2][2], const double* S) {
-  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
@@ -463,7 +472,7 @@ __device__ __forceinline__ bool spin_flag(const int* f, int* sync) {
 // (negated) and B[q][n] = L_jk[n][q] for its 16 rows and 4-column slices
 __device__ __forceinline__ void load_update(double (&a)[2][8], double (&b)[2][8], const double* Li, const double* Lj,
                                             size_t ld) {
-  const int lane = threadIdx.x & 63, mrow = lane & 15, kq = lane >> 4;
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int s2 = 0; s2 < 8; ++s2)
 #pragma unroll
@@ -507,8 +516,10 @@ __global__ void __launch_bounds__(64) k_chol_df(DevPlan D, int ntickets, double*
     double4_t acc[2][2];
     load_tile32(acc, A + (size_t)(NB * i) * npad + NB * j, npad);
     // X = S_ij - sum_k L_ik L_jk^T over runs of published k, one acquire per
-    // run, the operands of k + 1 loaded while the MFMAs of k run
-    int k = 0;
+    // run, the operands of k + 1 loaded while the MFMAs of k run; L_ik and
+    // L_jk are zero left of the envelope (k < fc[i] or k < fc[j])
+    const int* fc = D.chol_fc + W.fc_off;
+    int k = max(fc[i], fc[j]);
     while (k < j) {
       const int run = ready_run(fl + i * nblk, fl + j * nblk, k, j);
       if (run == 0) {
@@ -740,14 +751,35 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
         }
         // seven workers: the six compute waves and, after its copies, wave 4 (the
         // MFMA pipe of SIMD 0 is mostly idle beside the look-ahead chain)
+        // Each tile's successor is loaded while the tile is updated (one
+        // global latency per wave and step instead of one per tile).
         const int tw = (wave == 4) ? NW - 2 : cw;
-        for (int u = 1 + tw; u < ntri; u += NW - 1) {
+        auto tile_of = [&](int u, int& i, int& j) {
           int jj = 0, rem = u;
           while (rem >= m - jj) { rem -= m - jj; ++jj; }
-          const int j = b + 1 + jj, i = j + rem;
+          j = b + 1 + jj;
+          i = j + rem;
+        };
+        double4_t nxt[2][2];
+        if (1 + tw < ntri) {
+          int i, j;
+          tile_of(1 + tw, i, j);
+          load_tile32(nxt, A + (size_t)(NB * i) * npad + NB * j, npad);
+        }
+        for (int u = 1 + tw; u < ntri; u += NW - 1) {
+          int i, j;
+          tile_of(u, i, j);
           double4_t acc[2][2];
+#pragma unroll
+          for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+            for (int bn = 0; bn < 2; ++bn) acc[bm][bn] = nxt[bm][bn];
+          if (u + NW - 1 < ntri) {
+            int i2, j2;
+            tile_of(u + NW - 1, i2, j2);
+            load_tile32(nxt, A + (size_t)(NB * i2) * npad + NB * j2, npad);
+          }
           double* Aij = A + (size_t)(NB * i) * npad + NB * j;
-          load_tile32(acc, Aij, npad);
           wait_eq(&pready[i - b - 1], b + 1);
           wait_eq(&pready[j - b - 1], b + 1);
           mm32_abt_lds(acc, Pc + (i - b - 1) * NB * NB, Pc + (j - b - 1) * NB * NB, -1.0);
@@ -839,18 +871,44 @@ __global__ void __launch_bounds__(256) k_chol_bs(DevPlan D, int t0, int nbs, con
     const double* Lcc = Linvall + W.Linv_off + (size_t)c * NB * NB;
     double* x = xall + W.x_off;
     int* xf = flagsall + W.flag_off + (nblk + 1) * nblk;     // x_b published
+    const int* fc = D.chol_fc + W.fc_off;
     bool aborted = load_flag(sync + 1) != 0;
+    // column q of L_cc^-1 for the last step, loaded before any wait
+    double lcc[NB];
+    if (tid < NB) {
+#pragma unroll
+      for (int r = 0; r < NB; ++r) lcc[r] = Lcc[r * NB + q];
+    }
+    // t_c = y_c - sum_b L_bc^T x_b over b = nblk-1 .. c+1 (in that order)
+    // inside the envelope: the flags of up to 32 blocks are read at once (a
+    // block outside the envelope counts as ready) and every ready run is
+    // summed with one acquire and its loads in flight
     double acc = 0.0;
-    for (int b = nblk - 1; b > c; --b) {
-      double v[4], xv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = A[(size_t)(NB * b + r8 + 8 * u) * npad + NB * c + q];
-      if (!aborted) aborted = !spin_flag(xf + b, sync);
+    int b = nblk - 1;
+    while (b > c) {
+      const int bq = b - (lane & 31);
+      const int ready = (bq > c && fc[bq] <= c) ? load_flag(xf + bq) : 1;   // blocks outside the envelope: not needed
+      const unsigned long long miss = __ballot(ready == 0);
+      const int run = min((int)(miss ? __builtin_ctzll(miss) : 32), b - c);
+      if (run == 0) {
+        if (!aborted) aborted = !spin_flag(xf + b, sync);
+        if (aborted) {
+          b = c;                      // the batch was aborted: no more waits
+          break;
+        }
+        continue;
+      }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      for (const int bend = b - run; b > bend; --b) {
+        if (fc[b] > c) continue;      // L_bc = 0 outside the envelope
+        double v[4], xv[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) xv[u] = x[NB * b + r8 + 8 * u];
+        for (int u = 0; u < 4; ++u) v[u] = A[(size_t)(NB * b + r8 + 8 * u) * npad + NB * c + q];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc += v[u] * xv[u];
+        for (int u = 0; u < 4; ++u) xv[u] = x[NB * b + r8 + 8 * u];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += v[u] * xv[u];
+      }
     }
     part[r8][q] = acc;
     __syncthreads();
@@ -866,7 +924,7 @@ __global__ void __launch_bounds__(256) k_chol_bs(DevPlan D, int t0, int nbs, con
       double s = 0.0;
       if (tid < NB) {
 #pragma unroll
-        for (int r = 0; r < NB; ++r) s += Lcc[r * NB + q] * tv[r];
+        for (int r = 0; r < NB; ++r) s += lcc[r] * tv[r];
         x[NB * c + q] = (NB * c + q < W.n) ? s : 0.0;
       }
       if (aborted) {

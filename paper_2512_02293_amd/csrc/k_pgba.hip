@@ -421,7 +421,8 @@ __global__ void k_assemble_pg(int n_fixed, double lambda, DevPlan D, const doubl
   const int* poff = D.pair_off + W.pair_base;
   double val = 0.0;
   if (r < n && c < n) {
-    const int a = r / 7, ra = r % 7, b = c / 7, cb = c % 7;
+    // block positions -> keyframes (the window's order of the reduced system)
+    const int a = D.kf_at[W.kf_base + r / 7], ra = r % 7, b = D.kf_at[W.kf_base + c / 7], cb = c % 7;
     if (pg_active(a, n_fixed) && pg_active(b, n_fixed)) {
       double bd = 0.0;
       const int p0 = poff[a * N + b], p1 = poff[a * N + b + 1];
@@ -433,16 +434,16 @@ __global__ void k_assemble_pg(int n_fixed, double lambda, DevPlan D, const doubl
     } else {
       val = (r == c) ? 1.0 : 0.0;
     }
-    if (!isfinite(val)) set_status_pg(st + w, VI_ENONFINITE, r);
+    if (!isfinite(val)) set_status_pg(st + w, VI_ENONFINITE, 7 * a + ra);
   } else if (r < npad) {
     val = (r == c) ? 1.0 : 0.0;
   } else if (r == npad && c < n) {
-    const int b = c / 7, cb = c % 7;
+    const int b = D.kf_at[W.kf_base + c / 7], cb = c % 7;
     if (pg_active(b, n_fixed)) {
       const int p0 = poff[b * N + b], p1 = poff[b * N + b + 1];
       for (int it = p0; it < p1; ++it) val += ZV[D.pair_zb[it] + cb];
     }
-    if (!isfinite(val)) set_status_pg(st + w, VI_ENONFINITE, n + c);
+    if (!isfinite(val)) set_status_pg(st + w, VI_ENONFINITE, n + 7 * b + cb);
   }
   A[W.A_off + idx] = val;
 }
@@ -464,7 +465,7 @@ __global__ void __launch_bounds__(256) k_backsub_pg(double z_min, double d_min, 
     const WinDev& W = D.win[w];
     const double* xw = x + W.x_off;
     for (int t = tid; t < W.N; t += 256) {
-      const double* dx = xw + (size_t)t * 7;
+      const double* dx = xw + (size_t)D.kf_pos[W.kf_base + t] * 7;
       double* q = W.pose + (size_t)t * 7;
       quat_retract(q + 3, dx);
       for (int k = 0; k < 3; ++k) q[k] += dx[3 + k];
@@ -490,8 +491,8 @@ __global__ void __launch_bounds__(256) k_backsub_pg(double z_min, double d_min, 
     const int lj = D.jj[e] - W.kf_base;
     double Mi[42], Mj[42];
     pg_maps(rel + (size_t)e * 12, Rw + (size_t)D.jj[e] * 9, W.scale[ls] / W.scale[lj], Mi, Mj);
-    const double* xi = xw + (size_t)ls * 7;
-    const double* xj = xw + (size_t)lj * 7;
+    const double* xi = xw + (size_t)D.kf_pos[src] * 7;
+    const double* xj = xw + (size_t)D.kf_pos[D.jj[e]] * 7;
     for (int c = 0; c < 6; ++c) {
       double v = 0.0;
       for (int m = 0; m < 7; ++m) v += Mi[c * 7 + m] * xi[m] + Mj[c * 7 + m] * xj[m];

@@ -619,6 +619,20 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
     const double is = W.scale ? 1.0 / W.scale[ls] : 1.0;
     for (int q = 0; q < 9; ++q) Rw[(size_t)src * 9 + q] = is * Rm[q];
   }
+  if (k == 0) {
+    // a keyframe without outgoing edges has no residuals (its C, w_d, Gram and
+    // blocks are never read): only the non-finite inverse-depth check and an
+    // empty cost slot.  k is uniform over the workgroup.
+    bool bad = false;
+    for (int p = p_beg + tid; p < p_end; p += kVisThreads) bad = bad || !isfinite(W.invdepth[(size_t)ls * HW + p]);
+    if (st && bad) set_status(st + D.win_of_kf[src], VI_ENONFINITE, -1);
+    if (tid == 0) {
+      const size_t b = ((size_t)src * ncost + kr) * 2;
+      vcost[b] = 0.0;
+      vcost[b + 1] = 0.0;
+    }
+    return;
+  }
   for (int i = tid; i < 2 * tsz; i += kVisThreads) Et[i] = (R)0;
   __syncthreads();
 
@@ -1164,7 +1178,8 @@ __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, c
   const int* poff = D.pair_off + W.pair_base;
   double val = 0.0;
   if (r < n && c < n) {
-    const int a = r / 15, ra = r % 15, b = c / 15, cb = c % 15;
+    // block positions -> keyframes (the window's order of the reduced system)
+    const int a = D.kf_at[W.kf_base + r / 15], ra = r % 15, b = D.kf_at[W.kf_base + c / 15], cb = c % 15;
     if (coord_active(o, a, ra) && coord_active(o, b, cb)) {
       double bd = 0.0;
       if (ra < 6 && cb < 6) {
@@ -1209,11 +1224,11 @@ __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, c
     } else {
       val = (r == c) ? 1.0 : 0.0;
     }
-    if (!isfinite(val)) set_status(st + w, VI_ENONFINITE, r);
+    if (!isfinite(val)) set_status(st + w, VI_ENONFINITE, 15 * a + ra);
   } else if (r < npad) {
     val = (r == c) ? 1.0 : 0.0;
   } else if (r == npad && c < n) {
-    const int b = c / 15, cb = c % 15;
+    const int b = D.kf_at[W.kf_base + c / 15], cb = c % 15;
     if (coord_active(o, b, cb)) {
       if (cb < 6) {
         const int p0 = poff[b * N + b], p1 = poff[b * N + b + 1];
@@ -1231,7 +1246,7 @@ __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, c
         if (b < N - 1) val += gw[(size_t)b * 30 + cb];
       }
     }
-    if (!isfinite(val)) set_status(st + w, VI_ENONFINITE, n + c);
+    if (!isfinite(val)) set_status(st + w, VI_ENONFINITE, n + 15 * b + cb);
   }
   A[W.A_off + idx] = val;
 }
@@ -1260,7 +1275,7 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
     const WinDev& W = D.win[w];
     const double* xw = x + W.x_off;
     for (int t = tid; t < W.N; t += 256) {
-      const double* dx = xw + (size_t)t * 15;
+      const double* dx = xw + (size_t)D.kf_pos[W.kf_base + t] * 15;
       double* q = W.pose + (size_t)t * 7;
       quat_retract(q + 3, dx);
       for (int k = 0; k < 3; ++k) {
@@ -1289,8 +1304,8 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
     const int e = D.src_edges[e0 + s];
     const double* Rt = rel + (size_t)e * 12;
     const double* Rj = Rw + (size_t)D.jj[e] * 9;
-    const double* xi = xw + (size_t)ls * 15;
-    const double* xj = xw + (size_t)(D.jj[e] - W.kf_base) * 15;
+    const double* xi = xw + (size_t)D.kf_pos[src] * 15;
+    const double* xj = xw + (size_t)D.kf_pos[D.jj[e]] * 15;
     double v = 0.0;
     for (int m = 0; m < 6; ++m) v += Mi_at(Rt, Rj, c, m) * xi[m] + Mj_at(Rj, c, m) * xj[m];
     u[i] = v;

@@ -47,6 +47,7 @@ struct WinDev {
   int pair_base;                     // offset of this window's pair table
   int flag_off, nflags;              // Cholesky tile flags [(nblk + 1) * nblk]
   int band;                          // tiles (i, j) with i - j > band are zero in S and in L
+  int fc_off;                        // offset of the tile envelope (nblk + 1 entries) in chol_fc
   long long pix_base;                // global offset of the first keyframe's first pixel
   long long A_off, Linv_off, x_off;  // reduced system, diagonal-tile inverses, solution
   double* pose;
@@ -83,6 +84,12 @@ struct Plan {
   std::vector<int32_t> gram_off, z_off, zb_off;
   std::vector<int32_t> pair_off, pair_z, pair_zb;
   std::vector<int32_t> chol_tiles;             // ticket -> (window, (i << 16) | j)
+  // keyframe order of each window's reduced system: keyframe a (local) has
+  // its unknowns at block position kf_pos[kf_base + a]; kf_at is the inverse
+  std::vector<int32_t> kf_pos, kf_at;
+  // per window, first nonzero tile column of every tile row of S and L (the
+  // right-hand-side row last, 0): tiles (i, j < fc[i]) are zero in both
+  std::vector<int32_t> chol_fc;
   int pdim = 15;                               // unknowns per keyframe: 15 (visual-inertial) or 7 (Sim(3) graph)
   int R = 0;                                   // relative-pose factors (pose-graph adjustment)
   std::vector<int32_t> rel_ii, rel_jj;         // global keyframe indices per factor
@@ -101,6 +108,7 @@ struct DevPlan {
   const int32_t *pair_off, *pair_z, *pair_zb;
   const int32_t* chol_tiles;
   const int32_t *rel_ii, *rel_jj, *rel_z, *rel_zb;
+  const int32_t *kf_pos, *kf_at, *chol_fc;
   const WinDev* win;
 };
 

@@ -620,6 +620,22 @@ def make_pgba_problem(cfg: SceneConfig, seed: int, loops, rel_pairs, log_scale_d
                        pose_gt=pose_gt, scale_gt=s_gt, invdepth_gt=base.invdepth_gt.copy())
 
 
+def pgba_loop_closure_problem(seed: int = 3) -> PGBAProblem:
+    """Loop closure on the 512-keyframe trajectory of config_global(): 200
+    near-revisit loop edges drawn by that configuration's edge generator
+    (|i - j| >= loop_gap, at most 3 per source for seed 3) are the loop
+    pairs E*, the relative poses
+    E+ link every keyframe to its next three (1530), and the keyframe scales
+    drift by 10 % along the trajectory."""
+    cfg = config_global()
+    ii, jj = _edge_list(cfg, np.random.default_rng(seed))
+    ii, jj = np.array(ii), np.array(jj)
+    far = np.abs(ii - jj) >= cfg.loop_gap
+    loops = list(zip(ii[far].tolist(), jj[far].tolist()))
+    rel = [(i, i + s) for s in range(1, 4) for i in range(cfg.n_kf - s)]
+    return make_pgba_problem(cfg, seed, loops, rel)
+
+
 # --------------------------------------------------------------------------
 # Gaussian map and a loop-closure pose correction (input of the map update)
 # --------------------------------------------------------------------------

@@ -174,3 +174,28 @@ def test_pgba_errors_leave_state(ctx):
     assert ei.value.code == binding.VI_ENONFINITE
     for a, t in zip(before, (pg.pose, pg.scale, pg.invdepth)):
         assert torch.equal(a, t.cpu())
+
+
+def test_pgba_step_loop_closure_512(ctx):
+    """The benchmarked loop closure at full size: 512 keyframes (reduced system
+    3584 x 3584, tile-dataflow Cholesky), 200 loop pairs of 60x80 maps, 1530
+    relative poses; one FP64 step against the oracle's."""
+    prob = synth.pgba_loop_closure_problem()
+    assert prob.n_kf == 512 and prob.n_edges == 200 and len(prob.rel_ii) == 1530
+    _check_step(ctx, prob, 1e-8, 1e-8)
+
+
+def test_pgba_autotuned_tiling_matches_oracle():
+    """With the autotuner on, the fused assembly of the loop pairs runs with the
+    fastest pixel range of the candidates; the step is the same."""
+    from paper_2512_02293_amd import binding
+    c = binding.Context(0)
+    try:
+        c.set_autotune(True)
+        rng = np.random.default_rng(2)
+        loops = sorted({(int(i), int(j)) for i, j in rng.integers(0, 40, size=(60, 2)) if abs(int(i) - int(j)) >= 12})
+        prob = _problem(40, 30, 40, loops[:25], k_rel=3, seed=12)
+        rep, _ = _check_step(c, prob, 1e-8, 1e-8)
+        assert rep["tile_px"] % 64 == 0 and rep["tile_px"] >= 128
+    finally:
+        c.close()
