@@ -489,10 +489,18 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
     for (int w = 0; w < nw; ++w) {
       const WinDev& W = P.win[w];
       if (j >= W.nblk || W.npad <= kCholSmallMaxNpad) continue;
-      for (int i = j; i <= W.nblk; ++i) {
-        if (P.chol_fc[W.fc_off + i] > j) continue;      // outside the envelope: zero in S and in L
+      const int32_t* fc = &P.chol_fc[W.fc_off];
+      // the diagonal tile, unless the ticket of tile (j, j - 1) carries it;
+      // tile (j + 1, j) then carries the diagonal tile j + 1 (kPairTicket);
+      // tiles outside the envelope are zero in S and in L
+      if (j == 0 || fc[j] > j - 1) {
         P.chol_tiles.push_back(w);
-        P.chol_tiles.push_back((i << 16) | j);
+        P.chol_tiles.push_back((j << 16) | j);
+      }
+      for (int i = j + 1; i <= W.nblk; ++i) {
+        if (fc[i] > j) continue;
+        P.chol_tiles.push_back(w);
+        P.chol_tiles.push_back((i << 16) | j | ((i == j + 1 && i < W.nblk) ? kPairTicketFlag : 0));
       }
     }
   P.n_tickets = (int)(P.chol_tiles.size() / 2);

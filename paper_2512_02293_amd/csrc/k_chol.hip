@@ -492,6 +492,74 @@ __device__ __forceinline__ void mfma_update(double4_t (&acc)[2][2], const double
         acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm][s2], b[bn][s2], acc[bm][bn], 0, 0, 0);
 }
 
+// k-loop of a dataflow ticket over [k, kend): X -= L_ik L_jk^T, and with PAIR
+// also Y += L_ik L_ik^T (ONLY2: Y alone; the operand a = -L_ik serves as both
+// MFMA inputs, so Y holds the negated diagonal update), over runs of
+// published k with one acquire per run and the operands of k + 1 loaded while
+// the MFMAs of k run.  false: the batch was aborted.
+template <bool PAIR, bool ONLY2>
+__device__ __forceinline__ bool df_kloop(double4_t (&acc)[2][2], double4_t (&acc2)[2][2], const double* Ri,
+                                         const double* Rj, size_t npad, const int* fi, const int* fj, int k, int kend,
+                                         int* sync) {
+  auto step = [&](const double (&a)[2][8], const double (&b)[2][8]) {
+    if (!ONLY2) mfma_update(acc, a, b);
+    if (PAIR || ONLY2) mfma_update(acc2, a, a);
+  };
+  while (k < kend) {
+    const int run = ready_run(fi, fj, k, kend);
+    if (run == 0) {
+      if (!spin_flag(fi + k, sync)) return false;
+      if (fj != fi && !spin_flag(fj + k, sync)) return false;
+      continue;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int ke = k + run;
+    double a0[2][8], b0[2][8], a1[2][8], b1[2][8];
+    load_update(a0, b0, Ri + NB * k, Rj + NB * k, npad);
+    for (; k < ke; k += 2) {
+      const bool has1 = k + 1 < ke;
+      if (has1) load_update(a1, b1, Ri + NB * (k + 1), Rj + NB * (k + 1), npad);
+      step(a0, b0);
+      if (!has1) { ++k; break; }
+      if (k + 2 < ke) load_update(a0, b0, Ri + NB * (k + 2), Rj + NB * (k + 2), npad);
+      step(a1, b1);
+    }
+    k = ke;
+  }
+  return true;
+}
+
+// L_ij = X L_jj^-T for the tile X in T (LDS, padded), L_jj^-1 row-major at Li
+__device__ __forceinline__ void solve_panel(double4_t (&out)[2][2], const double* T, const double* Li) {
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn) out[bm][bn] = double4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s2 = 0; s2 < 8; ++s2) {
+    double a[2], b[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      a[h] = T[(16 * h + mrow) * LD + 4 * s2 + kq];
+      b[h] = Li[(16 * h + mrow) * NB + 4 * s2 + kq];
+    }
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn)
+        out[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm], b[bn], out[bm][bn], 0, 0, 0);
+  }
+}
+
+// Tickets: (window, (i << 16) | j), with kPairTicket set on the ticket of
+// tile (j + 1, j) when it also carries the diagonal tile (j + 1, j + 1): that
+// wave accumulates X_ij and X_ii together (the operands L_ik are shared),
+// publishes L_ij as soon as L_jj^-1 is in, then subtracts L_ij L_ij^T, factors
+// the diagonal tile and publishes L_ii^-1 itself, so that the chain from one
+// diagonal factor to the next holds one hand-off instead of two.
+constexpr int kPairTicket = kPairTicketFlag;
+
 __global__ void __launch_bounds__(64) k_chol_df(DevPlan D, int ntickets, double* __restrict__ Aall,
                                                 double* __restrict__ Linvall, int* __restrict__ flagsall,
                                                 int* __restrict__ sync, DevStatus* __restrict__ stall) {
@@ -499,7 +567,6 @@ __global__ void __launch_bounds__(64) k_chol_df(DevPlan D, int ntickets, double*
   __shared__ double Lt[NB * LD];
   __shared__ double U[16 * 17];
   const int lane = threadIdx.x;
-  const int mrow = lane & 15, kq = lane >> 4;
   while (true) {
     int t = 0;
     if (lane == 0) t = atomicAdd(sync, 1);
@@ -507,41 +574,37 @@ __global__ void __launch_bounds__(64) k_chol_df(DevPlan D, int ntickets, double*
     if (t >= ntickets) return;
     const int w = D.chol_tiles[2 * t];
     const int ij = D.chol_tiles[2 * t + 1];
-    const int i = ij >> 16, j = ij & 0xffff;
+    const bool pair = (ij & kPairTicket) != 0;
+    const int i = (ij >> 16) & 0x3fff, j = ij & 0xffff;
     const WinDev& W = D.win[w];
     const int npad = W.npad, nblk = W.nblk;
     double* A = Aall + W.A_off;
     double* Lv = Linvall + W.Linv_off;
     int* fl = flagsall + W.flag_off;
-    double4_t acc[2][2];
-    load_tile32(acc, A + (size_t)(NB * i) * npad + NB * j, npad);
-    // X = S_ij - sum_k L_ik L_jk^T over runs of published k, one acquire per
-    // run, the operands of k + 1 loaded while the MFMAs of k run; L_ik and
-    // L_jk are zero left of the envelope (k < fc[i] or k < fc[j])
     const int* fc = D.chol_fc + W.fc_off;
-    int k = max(fc[i], fc[j]);
-    while (k < j) {
-      const int run = ready_run(fl + i * nblk, fl + j * nblk, k, j);
-      if (run == 0) {
-        if (!spin_flag(fl + i * nblk + k, sync)) return;
-        if (i != j && !spin_flag(fl + j * nblk + k, sync)) return;
-        continue;
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      const int kend = k + run;
-      const double* Ri = A + (size_t)(NB * i) * npad;
-      const double* Rj = A + (size_t)(NB * j) * npad;
-      double a0[2][8], b0[2][8], a1[2][8], b1[2][8];
-      load_update(a0, b0, Ri + NB * k, Rj + NB * k, npad);
-      for (; k < kend; k += 2) {
-        const bool has1 = k + 1 < kend;
-        if (has1) load_update(a1, b1, Ri + NB * (k + 1), Rj + NB * (k + 1), npad);
-        mfma_update(acc, a0, b0);
-        if (!has1) { ++k; break; }
-        if (k + 2 < kend) load_update(a0, b0, Ri + NB * (k + 2), Rj + NB * (k + 2), npad);
-        mfma_update(acc, a1, b1);
-      }
-      k = kend;
+    const double* Ri = A + (size_t)(NB * i) * npad;
+    const double* Rj = A + (size_t)(NB * j) * npad;
+    // X = S_ij - sum_k L_ik L_jk^T; L_ik and L_jk are zero left of the
+    // envelope (k < fc[i] or k < fc[j])
+    double4_t acc[2][2], acc2[2][2];
+    load_tile32(acc, Ri + NB * j, npad);
+    const int k1 = max(fc[i], fc[j]);
+    if (!pair) {
+      if (!df_kloop<false, false>(acc, acc2, Ri, Rj, npad, fl + i * nblk, fl + j * nblk, k1, j, sync)) return;
+    } else {
+      // and X2 = S_ii - sum_{k < j} L_ik L_ik^T alongside (k >= fc[i]), as
+      // its negative -S_ii + sum L_ik L_ik^T
+      load_tile32(acc2, Ri + NB * i, npad);
+#pragma unroll
+      for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) acc2[bm][bn] = -acc2[bm][bn];
+      if (!df_kloop<true, true>(acc, acc2, Ri, Ri, npad, fl + i * nblk, fl + i * nblk, fc[i], k1, sync)) return;
+      if (!df_kloop<true, false>(acc, acc2, Ri, Rj, npad, fl + i * nblk, fl + j * nblk, k1, j, sync)) return;
+#pragma unroll
+      for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) acc2[bm][bn] = -acc2[bm][bn];
     }
     acc_to_lds(acc, T);
     __syncthreads();
@@ -559,28 +622,29 @@ __global__ void __launch_bounds__(64) k_chol_df(DevPlan D, int ntickets, double*
     } else {
       if (!wait_flag(fl + j * nblk + j, sync)) return;
       // L_ij = X L_jj^-T: A[m][q] = X[m][q], B[q][n] = Linv[n][q]
-      const double* Li = Lv + (size_t)j * NB * NB;
       double4_t out[2][2];
-#pragma unroll
-      for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < 2; ++bn) out[bm][bn] = double4_t{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s2 = 0; s2 < 8; ++s2) {
-        double a[2], b[2];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          a[h] = T[(16 * h + mrow) * LD + 4 * s2 + kq];
-          b[h] = Li[(16 * h + mrow) * NB + 4 * s2 + kq];
-        }
-#pragma unroll
-        for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-          for (int bn = 0; bn < 2; ++bn)
-            out[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm], b[bn], out[bm][bn], 0, 0, 0);
-      }
+      solve_panel(out, T, Lv + (size_t)j * NB * NB);
       store_tile32(out, A + (size_t)(NB * i) * npad + NB * j, npad);
       publish(fl + i * nblk + j);
+      if (pair) {
+        // X2 -= L_ij L_ij^T (L_ij through LDS into the operand layout), then
+        // factor and invert the diagonal tile (i, i) and publish L_ii^-1
+        __syncthreads();
+        acc_to_lds(out, Lt);
+        __syncthreads();
+        mm32_abt(acc2, Lt, LD, Lt, LD, -1.0);
+        acc_to_lds(acc2, T);
+        __syncthreads();
+        const int bad = factor_invert32(T, Lt, U);
+        if (bad >= 0 && lane == 0 && NB * i + bad < W.n) set_status(stall + w, VI_ENOTPD, NB * i + bad);
+        double* Lo = Lv + (size_t)i * NB * NB;
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+          const int e = lane + 64 * it;
+          Lo[e] = Lt[(e >> 5) * LD + (e & 31)];
+        }
+        publish(fl + i * nblk + i);
+      }
     }
     __syncthreads();
   }

@@ -24,6 +24,7 @@ constexpr int kMaxOutDegree = 18;     // per-source outgoing edges (Gram tile bu
 constexpr int kVisBlock = 256;        // pixels per workgroup of the per-pixel kernels
 constexpr int kCholNB = 32;           // Cholesky tile size
 constexpr int kCholSmallMaxNpad = 512;  // systems up to this size are solved by one workgroup
+constexpr int kPairTicketFlag = 1 << 30;  // Cholesky ticket of tile (j + 1, j) that also factors tile (j + 1, j + 1)
 constexpr int kMaxIters = 64;         // cost trace capacity of vi_ba_solve
 constexpr int kMaxKeyframes = 640;    // per window: the back-substitution keeps 2 x 15 N doubles in LDS
 constexpr int kTraceLen = 2 * (kMaxIters + 1);
