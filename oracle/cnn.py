@@ -240,8 +240,8 @@ def features(cam, state, graph, z_min=0.1, hq=None, wq=None, use_imu=True):
                 continue
             j = int(graph.jj[e])
             k += 1
-            r, valid, _, J_d = vision.edge_linearize(cam.intr, state.R[i], state.p[i], state.R[j], state.p[j],
-                                                     state.d[i], graph.target[e], z_min)
+            r, valid, _, J_d = vision.edge_linearize_body(cam.intr, cam.T_bc, state.R[i], state.p[i], state.R[j],
+                                                          state.p[j], state.d[i], graph.target[e], z_min)
             w = np.asarray(graph.weight[e], np.float64).reshape(2, -1) * valid[None]
             c = cell.ravel()
             sg += np.bincount(c, weights=w[0] * J_d[0] * r[0] + w[1] * J_d[1] * r[1], minlength=hq0 * wq0)

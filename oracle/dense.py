@@ -26,8 +26,8 @@ def full_system(cam, state, graph, opts):
     rows_J, rows_r, rows_w = [], [], []
     for e in range(len(graph.ii)):
         i, j = int(graph.ii[e]), int(graph.jj[e])
-        r, valid, Jp, Jd = vision.edge_linearize(cam.intr, state.R[i], state.p[i], state.R[j],
-                                                 state.p[j], state.d[i], graph.target[e], opts.z_min)
+        r, valid, Jp, Jd = vision.edge_linearize_body(cam.intr, cam.T_bc, state.R[i], state.p[i], state.R[j],
+                                                      state.p[j], state.d[i], graph.target[e], opts.z_min)
         w = np.where(valid[None], np.asarray(graph.weight[e], np.float64).reshape(2, -1), 0.0)
         for c in range(2):
             for p in range(HW):

@@ -25,7 +25,7 @@ positive semi-definiteness of H, and the Cholesky factor against
 numpy.linalg.cholesky.
 """
 from dataclasses import dataclass, field
-from typing import Dict, List, Tuple
+from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
@@ -69,6 +69,7 @@ class Camera:
     H: int
     W: int
     gravity: np.ndarray
+    T_bc: Optional[Tuple[np.ndarray, np.ndarray]] = None   # body-from-camera (R_bc, t_bc); None = identity
 
     @property
     def intr(self):
@@ -122,8 +123,8 @@ def linearize(cam, state, graph, opts):
         E[i] = (np.array(T), np.zeros((len(T), 6, HW)))
     for e in range(len(graph.ii)):
         i, j = int(graph.ii[e]), int(graph.jj[e])
-        r, valid, Jp, Jd = vision.edge_linearize(
-            cam.intr, state.R[i], state.p[i], state.R[j], state.p[j],
+        r, valid, Jp, Jd = vision.edge_linearize_body(
+            cam.intr, cam.T_bc, state.R[i], state.p[i], state.R[j], state.p[j],
             state.d[i], graph.target[e], opts.z_min)
         w = np.where(valid[None], np.asarray(graph.weight[e], np.float64).reshape(2, -1), 0.0)
         n_valid += int(valid.sum())

@@ -38,8 +38,12 @@ def from_problem(prob, exact_targets=False):
     """Camera, state, graph and options from a synthetic problem's arrays.
     ``exact_targets`` uses the float64 targets (noiseless pins) instead of the
     float32 ones every solver receives."""
+    T_bc = None
+    if getattr(prob, "T_bc", None) is not None:
+        t = np.asarray(prob.T_bc, dtype=np.float64)
+        T_bc = (quat_to_R(t[3:7] / np.linalg.norm(t[3:7])), t[:3].copy())
     cam = Camera(prob.fx, prob.fy, prob.cx, prob.cy, prob.H, prob.W,
-                 np.asarray(prob.gravity, dtype=np.float64))
+                 np.asarray(prob.gravity, dtype=np.float64), T_bc)
     st = state_from_arrays(prob.pose, prob.vel, prob.bias, prob.invdepth)
     tgt = prob.target64 if exact_targets else prob.target.astype(np.float64)
     factors = preint.preintegrate_all(prob.imu_off, prob.gyro, prob.accel, prob.imu_dt,
@@ -55,8 +59,8 @@ def cost(cam, state, graph, opts):
     n_valid = 0
     for e in range(len(graph.ii)):
         i, j = int(graph.ii[e]), int(graph.jj[e])
-        r, valid = vision.edge_residual(cam.intr, state.R[i], state.p[i], state.R[j], state.p[j],
-                                        state.d[i], graph.target[e], opts.z_min)
+        r, valid = vision.edge_residual_body(cam.intr, cam.T_bc, state.R[i], state.p[i], state.R[j], state.p[j],
+                                             state.d[i], graph.target[e], opts.z_min)
         w = np.asarray(graph.weight[e], np.float64).reshape(2, -1)
         F += float((np.where(valid[None], w, 0.0) * r * r).sum())
         n_valid += int(valid.sum())

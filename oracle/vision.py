@@ -19,9 +19,21 @@ R <- R Exp(dtheta) and additive world-frame p:
     dX_j/dd       = -R_ij K^-1[u;1] / d^2
 and r's Jacobian is -dPi/dX times these.
 
+Camera-IMU extrinsics (Sec. 3.1, inertial residual: left out of the
+printed equations, used by the implementation): the state holds world-from-
+body poses (R_b, p_b); the camera of a keyframe is T_wc = T_wb T_bc with the
+constant body-from-camera T_bc = (R_bc, t_bc), i.e. R_c = R_b R_bc and
+p_c = p_b + R_b t_bc, and the residual above is taken between camera poses.
+A body increment (dtheta, dp) moves the camera by
+    dtheta_c = R_bc^T dtheta,   dp_c = dp - R_b [t_bc]x dtheta
+to first order, so the Jacobian with respect to the body increments is the
+camera Jacobian times K = [[R_bc^T, 0], [-R_b [t_bc]x, I]] per keyframe
+(edge_linearize_body).  With T_bc = identity both coincide.
+
 Test infrastructure (see the package header).  Pinned by: zero residual at
 noiseless ground truth, hand closed forms for identity rotation, and the
-Jacobians against central finite differences.
+Jacobians against central finite differences (also through the body
+retraction with a non-identity T_bc).
 """
 import numpy as np
 
@@ -103,3 +115,46 @@ def edge_linearize(cam, Ri, pi, Rj, pj, d, target, z_min):
     J_pose = np.transpose(J[:, :, 0:12], (1, 0, 2))  # (2, n, 12)
     J_d = J[:, :, 12].T                               # (2, n)
     return r, valid, J_pose, J_d
+
+
+def skew(v):
+    v = np.asarray(v, dtype=np.float64)
+    return np.array([[0.0, -v[2], v[1]], [v[2], 0.0, -v[0]], [-v[1], v[0], 0.0]])
+
+
+def camera_pose(R_b, p_b, T_bc):
+    """World-from-camera rotation and position of a keyframe with world-from-
+    body pose (R_b, p_b); T_bc = (R_bc, t_bc) or None for the identity."""
+    if T_bc is None:
+        return R_b, p_b
+    R_bc, t_bc = T_bc
+    return R_b @ R_bc, p_b + R_b @ t_bc
+
+
+def body_map(R_b, T_bc):
+    """6x6 K with (dtheta_c, dp_c) = K (dtheta, dp) for a body increment."""
+    K = np.eye(6)
+    if T_bc is not None:
+        R_bc, t_bc = T_bc
+        K[0:3, 0:3] = R_bc.T
+        K[3:6, 0:3] = -R_b @ skew(t_bc)
+    return K
+
+
+def edge_residual_body(cam, T_bc, Ri, pi, Rj, pj, d, target, z_min):
+    """edge_residual between the cameras of body poses i and j."""
+    Rci, pci = camera_pose(Ri, pi, T_bc)
+    Rcj, pcj = camera_pose(Rj, pj, T_bc)
+    return edge_residual(cam, Rci, pci, Rcj, pcj, d, target, z_min)
+
+
+def edge_linearize_body(cam, T_bc, Ri, pi, Rj, pj, d, target, z_min):
+    """edge_linearize between the cameras of body poses i and j, with the
+    pose Jacobian taken with respect to the body increments
+    (dtheta_i, dp_i, dtheta_j, dp_j)."""
+    Rci, pci = camera_pose(Ri, pi, T_bc)
+    Rcj, pcj = camera_pose(Rj, pj, T_bc)
+    r, valid, Jp, Jd = edge_linearize(cam, Rci, pci, Rcj, pcj, d, target, z_min)
+    if T_bc is not None:
+        Jp = np.concatenate([Jp[..., 0:6] @ body_map(Ri, T_bc), Jp[..., 6:12] @ body_map(Rj, T_bc)], axis=-1)
+    return r, valid, Jp, Jd

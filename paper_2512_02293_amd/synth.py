@@ -110,6 +110,8 @@ class SceneConfig:
     z_min: float = 0.1
     noiseless: bool = False             # no pixel/IMU noise, no bias random walk
     zero_bias: bool = False             # true bias identically zero
+    # body-from-camera extrinsic (t (3), q xyzw (4)); None: the camera is the body
+    T_bc: Optional[Tuple[float, ...]] = None
 
     @property
     def fx(self) -> float:
@@ -204,6 +206,7 @@ class Problem:
     invdepth_gt: np.ndarray
     kf_tick: np.ndarray      # (N,) IMU tick index of each keyframe
     z_min: float = 0.1
+    T_bc: Optional[np.ndarray] = None   # (7,) body-from-camera t, q xyzw; None = identity
 
     @property
     def n_kf(self) -> int:
@@ -408,9 +411,16 @@ def make_problem(cfg: SceneConfig, seed: int, bias_hat_mode: str = "zero") -> Pr
     H, W = cfg.H, cfg.W
     target64 = np.empty((E, 2, H, W))
     weight = np.empty((E, 2, H, W), dtype=np.float32)
+    # cameras of the keyframes: T_wc = T_wb T_bc (the IMU trajectory is the body's)
+    Rc_gt, pc_gt = R_gt, pose_gt[:, :3]
+    if cfg.T_bc is not None:
+        tb = np.asarray(cfg.T_bc, dtype=np.float64)
+        R_bc = _quat_to_mat(tb[3:7] / np.linalg.norm(tb[3:7]))
+        Rc_gt = R_gt @ R_bc
+        pc_gt = pose_gt[:, :3] + np.einsum("nab,b->na", R_gt, tb[:3])
     for e in range(E):
         i, j = int(ii[e]), int(jj[e])
-        uv, z = _project(cfg, R_gt[i], pose_gt[i, :3], R_gt[j], pose_gt[j, :3], invdepth_gt[i])
+        uv, z = _project(cfg, Rc_gt[i], pc_gt[i], Rc_gt[j], pc_gt[j], invdepth_gt[i])
         ok = z > cfg.z_min
         uv = np.where(ok[None], uv, 0.0)
         target64[e] = uv
@@ -449,6 +459,7 @@ def make_problem(cfg: SceneConfig, seed: int, bias_hat_mode: str = "zero") -> Pr
         noise=np.array([cfg.sigma_g, cfg.sigma_a, cfg.sigma_bgw, cfg.sigma_baw]),
         pose_gt=pose_gt, vel_gt=vel_gt, bias_gt=bias_gt, invdepth_gt=invdepth_gt,
         kf_tick=kf_tick, z_min=cfg.z_min,
+        T_bc=None if cfg.T_bc is None else np.asarray(cfg.T_bc, dtype=np.float64),
     )
 
 
