@@ -82,6 +82,11 @@ typedef struct {
   double fx, fy, cx, cy;     /* pinhole intrinsics, pixels */
   int32_t H, W;              /* inverse-depth map rows and columns */
   double gravity[3];         /* world gravity vector g (Eq. 3), e.g. {0, 0, -9.81} */
+  double T_bc[7];            /* camera-IMU extrinsic, body-from-camera (t, q xyzw): the state's poses are the
+                                IMU body's (world-from-body), the camera of a keyframe is T_wb T_bc (Sec. 3.1,
+                                inertial residual).  A zero quaternion reads as the identity (a zero-initialised
+                                struct keeps the camera at the body); otherwise it is normalised.  Not used by
+                                the pose-graph adjustment, whose poses are camera poses. */
 } vi_camera;
 
 typedef struct {

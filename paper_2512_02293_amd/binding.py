@@ -31,7 +31,7 @@ class ViError(RuntimeError):
 
 class Camera(C.Structure):
     _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
-                ("H", C.c_int32), ("W", C.c_int32), ("gravity", C.c_double * 3)]
+                ("H", C.c_int32), ("W", C.c_int32), ("gravity", C.c_double * 3), ("T_bc", C.c_double * 7)]
 
 
 class ImuNoise(C.Structure):
@@ -192,8 +192,10 @@ def _check_dev(t, shape, dtype, name, min_rows=None):
         raise ValueError(f"{name}: {int(t.shape[0])} rows, {min_rows} needed")
 
 
-def make_camera(fx, fy, cx, cy, H, W, gravity=(0.0, 0.0, -9.81)) -> Camera:
-    return Camera(fx, fy, cx, cy, H, W, (C.c_double * 3)(*gravity))
+def make_camera(fx, fy, cx, cy, H, W, gravity=(0.0, 0.0, -9.81), T_bc=None) -> Camera:
+    """T_bc: body-from-camera (t, q xyzw), None for the identity."""
+    tb = (0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0) if T_bc is None else tuple(float(v) for v in T_bc)
+    return Camera(fx, fy, cx, cy, H, W, (C.c_double * 3)(*gravity), (C.c_double * 7)(*tb))
 
 
 def make_opts(n_fixed=1, use_imu=True, bias_fixed=False, lm_lambda=1e-4, depth_eta=1e-8, z_min=0.1,
@@ -600,7 +602,8 @@ class DeviceProblem:
         self.ii = np.ascontiguousarray(prob.ii, dtype=np.int32)
         self.jj = np.ascontiguousarray(prob.jj, dtype=np.int32)
         self.off = np.ascontiguousarray(prob.imu_off, dtype=np.int32)
-        self.cam = make_camera(prob.fx, prob.fy, prob.cx, prob.cy, prob.H, prob.W, tuple(prob.gravity))
+        self.cam = make_camera(prob.fx, prob.fy, prob.cx, prob.cy, prob.H, prob.W, tuple(prob.gravity),
+                               getattr(prob, "T_bc", None))
         self.noise = tuple(float(x) for x in prob.noise)
 
     def reset_state(self):

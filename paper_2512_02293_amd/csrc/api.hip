@@ -101,6 +101,8 @@ vi_status check_window(vi_ctx* ctx, int w, const WinIn& in, const vi_opts* o, bo
     return fail(ctx, VI_EINVAL, "window %d: bad map size %d x %d", w, cam->H, cam->W);
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(cam->gravity[k])) return fail(ctx, VI_EINVAL, "window %d: gravity must be finite", w);
+  for (int k = 0; k < 7; ++k)
+    if (!std::isfinite(cam->T_bc[k])) return fail(ctx, VI_EINVAL, "window %d: T_bc must be finite", w);
   if (st->n_kf < 2) return fail(ctx, VI_EINVAL, "window %d: need at least 2 keyframes (got %d)", w, st->n_kf);
   if (st->n_kf > kMaxKeyframes)
     return fail(ctx, VI_EUNSUPPORTED, "window %d: at most %d keyframes are supported (dense reduced system)", w,
@@ -660,6 +662,24 @@ vi_status ensure_plan(vi_ctx* ctx, const std::vector<WinIn>& wins) {
   return VI_OK;
 }
 
+// body-from-camera extrinsic (t, q xyzw) -> row-major R_bc, t_bc and whether
+// it differs from the identity; a zero quaternion (or no extrinsic) is the identity
+void extrinsic_rotation(const double* T, double* R, double* t, int* ext) {
+  double q[4] = {0.0, 0.0, 0.0, 1.0};
+  double n = 0.0;
+  if (T)
+    for (int k = 0; k < 4; ++k) n += T[3 + k] * T[3 + k];
+  if (T && n > 0.0)
+    for (int k = 0; k < 4; ++k) q[k] = T[3 + k] / std::sqrt(n);
+  const double x = q[0], y = q[1], z = q[2], w = q[3];
+  const double Rm[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - z * w),     2 * (x * z + y * w),
+                        2 * (x * y + z * w),     1 - 2 * (x * x + z * z), 2 * (y * z - x * w),
+                        2 * (x * z - y * w),     2 * (y * z + x * w),     1 - 2 * (x * x + y * y)};
+  for (int k = 0; k < 9; ++k) R[k] = Rm[k];
+  for (int k = 0; k < 3; ++k) t[k] = T ? T[k] : 0.0;
+  *ext = (T && (t[0] != 0.0 || t[1] != 0.0 || t[2] != 0.0 || (n > 0.0 && (x != 0.0 || y != 0.0 || z != 0.0)))) ? 1 : 0;
+}
+
 // this call's window pointers -> host window table -> device
 vi_status refresh_windows(vi_ctx* ctx, const std::vector<WinIn>& wins) {
   Plan& P = ctx->plan;
@@ -668,6 +688,8 @@ vi_status refresh_windows(vi_ctx* ctx, const std::vector<WinIn>& wins) {
     const WinIn& in = wins[w];
     W.fx = in.cam->fx; W.fy = in.cam->fy; W.cx = in.cam->cx; W.cy = in.cam->cy;
     for (int k = 0; k < 3; ++k) W.g[k] = in.cam->gravity[k];
+    // camera-IMU extrinsic (the pose-graph adjustment's poses are camera poses: none there)
+    extrinsic_rotation(in.rel ? nullptr : in.cam->T_bc, W.Rbc, W.tbc, &W.ext);
     W.pose = in.st->pose; W.vel = in.st->vel; W.bias = in.st->bias; W.invdepth = in.st->invdepth;
     W.target = in.ed->target; W.weight = in.ed->weight; W.imu = in.imu;
     W.rep_dxi = in.rep ? in.rep->dxi : nullptr;
@@ -905,10 +927,12 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
     for (const WinDev& W : P.win) {
       const void* ptrs[] = {W.pose, W.vel, W.bias, W.invdepth, W.target, W.weight, W.imu, W.rep_dxi, W.rep_dd};
       for (const void* p : ptrs) key.push_back((uint64_t)(uintptr_t)p);
-      uint64_t cam[7];
-      const double cv[7] = {W.fx, W.fy, W.cx, W.cy, W.g[0], W.g[1], W.g[2]};
+      uint64_t cam[19];
+      const double cv[19] = {W.fx,     W.fy,     W.cx,     W.cy,     W.g[0],   W.g[1],   W.g[2],
+                             W.Rbc[0], W.Rbc[1], W.Rbc[2], W.Rbc[3], W.Rbc[4], W.Rbc[5], W.Rbc[6],
+                             W.Rbc[7], W.Rbc[8], W.tbc[0], W.tbc[1], W.tbc[2]};
       std::memcpy(cam, cv, sizeof(cv));
-      key.insert(key.end(), cam, cam + 7);
+      key.insert(key.end(), cam, cam + 19);
     }
     if (!ctx->have_graph || key != ctx->gkey) {
       if (ctx->exec) { (void)hipGraphExecDestroy(ctx->exec); ctx->exec = nullptr; }

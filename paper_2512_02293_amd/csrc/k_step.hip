@@ -194,13 +194,29 @@ struct BlockSum {
 // t_ji = R_j^T (p_i - p_j); with keyframe scales (Sim(3) poses of the
 // pose-graph adjustment, X_w = s R X + p) o[0..8] = (s_i / s_j) R_ji and
 // t_ji = R_j^T (p_i - p_j) / s_j.  i, j index the window's pose array.
+// Camera of keyframe a (window index): with the camera-IMU extrinsic the
+// state's pose is the body's and the camera is T_wb T_bc, R_c = R_b R_bc,
+// p_c = p_b + R_b t_bc (Sec. 3.1, inertial residual).
+__device__ __forceinline__ void cam_pose(const WinDev& W, int a, double* Rc, double* pc) {
+  const double* pose = W.pose + (size_t)a * 7;
+  if (!W.ext) {
+    quat_to_rot(pose + 3, Rc);
+    for (int k = 0; k < 3; ++k) pc[k] = pose[k];
+    return;
+  }
+  double Rb[9], u[3];
+  quat_to_rot(pose + 3, Rb);
+  m3_mul(Rb, W.Rbc, Rc);
+  m3_vec(Rb, W.tbc, u);
+  for (int k = 0; k < 3; ++k) pc[k] = pose[k] + u[k];
+}
+
 __device__ __forceinline__ void edge_rel(const WinDev& W, int i, int j, double* o) {
-  const double* pose = W.pose;
-  double Ri[9], Rj[9], Rji[9], dp[3], tji[3];
-  quat_to_rot(pose + (size_t)i * 7 + 3, Ri);
-  quat_to_rot(pose + (size_t)j * 7 + 3, Rj);
+  double Ri[9], Rj[9], Rji[9], pi[3], pj[3], dp[3], tji[3];
+  cam_pose(W, i, Ri, pi);
+  cam_pose(W, j, Rj, pj);
   m3_tmul(Rj, Ri, Rji);
-  for (int k = 0; k < 3; ++k) dp[k] = pose[(size_t)i * 7 + k] - pose[(size_t)j * 7 + k];
+  for (int k = 0; k < 3; ++k) dp[k] = pi[k] - pj[k];
   m3_tvec(Rj, dp, tji);
   const double sij = W.scale ? W.scale[i] / W.scale[j] : 1.0;
   const double isj = W.scale ? 1.0 / W.scale[j] : 1.0;
@@ -612,10 +628,10 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
       for (int q = 0; q < 12; ++q) rel[(size_t)e * 12 + q] = r12[q];
   }
   if (kr == 0 && tid == 0) {
-    // R of the keyframe (R / s with keyframe scales: R^T / s maps world
-    // offsets into the scaled camera frame)
-    double Rm[9];
-    quat_to_rot(W.pose + (size_t)ls * 7 + 3, Rm);
+    // camera rotation R_c of the keyframe (R_c / s with keyframe scales:
+    // R^T / s maps world offsets into the scaled camera frame)
+    double Rm[9], pc[3];
+    cam_pose(W, ls, Rm, pc);
     const double is = W.scale ? 1.0 / W.scale[ls] : 1.0;
     for (int q = 0; q < 9; ++q) Rw[(size_t)src * 9 + q] = is * Rm[q];
   }
@@ -864,6 +880,44 @@ __device__ __forceinline__ double Mj_at(const double* Rj, int r, int c) {
   return -Rj[(c - 3) * 3 + (r - 3)];
 }
 
+// With the camera-IMU extrinsic the unknowns are body increments; the camera
+// moves by K (dtheta, dp) with K = [[R_bc^T, 0], [-R_b [t_bc]x, I]] and
+// R_b = R_c R_bc^T, so the local maps become M K.  Rc: the camera rotation.
+__device__ __forceinline__ double K_at(const WinDev& W, const double* Rc, int m, int c) {
+  if (m < 3) return c < 3 ? W.Rbc[c * 3 + m] : 0.0;
+  if (c >= 3) return (m == c) ? 1.0 : 0.0;
+  // -(R_b [t]x)[m-3][c], R_b[p][q] = sum_u Rc[p][u] Rbc[q][u]
+  double tx[9];
+  skew(W.tbc, tx);
+  double v = 0.0;
+  for (int q = 0; q < 3; ++q) {
+    double rb = 0.0;
+    for (int u = 0; u < 3; ++u) rb += Rc[(m - 3) * 3 + u] * W.Rbc[q * 3 + u];
+    v += rb * tx[q * 3 + c];
+  }
+  return -v;
+}
+
+__device__ __forceinline__ double Mi_body(const WinDev& W, const double* Rt, const double* Rj, const double* Rci,
+                                          int r, int c) {
+  if (!W.ext || c >= 3) return Mi_at(Rt, Rj, r, c);
+  double v = 0.0;
+  for (int m = 0; m < 6; ++m) v += Mi_at(Rt, Rj, r, m) * K_at(W, Rci, m, c);
+  return v;
+}
+
+// M_j K_j = [[-R_bc^T, 0], [R_bc^T [t_bc]x, -R_j^T]] (R_j: the camera rotation)
+__device__ __forceinline__ double Mj_body(const WinDev& W, const double* Rj, int r, int c) {
+  if (!W.ext) return Mj_at(Rj, r, c);
+  if (r < 3) return c < 3 ? -W.Rbc[c * 3 + r] : 0.0;
+  if (c >= 3) return -Rj[(c - 3) * 3 + (r - 3)];
+  double tx[9];
+  skew(W.tbc, tx);
+  double v = 0.0;
+  for (int q = 0; q < 3; ++q) v += W.Rbc[q * 3 + (r - 3)] * tx[q * 3 + c];
+  return v;
+}
+
 // cost trace of window w: sum of its vision partials (ranges of range_px pixels
 // per source keyframe) and of its inertial factor costs.  Any power-of-two
 // block size; s0 holds 2 * blockDim.x doubles.
@@ -942,7 +996,8 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
     return;
   }
   const int src = blockIdx.x;
-  const int nkr = D.win[D.win_of_kf[src]].nkr;
+  const WinDev& Wsrc = D.win[D.win_of_kf[src]];
+  const int nkr = Wsrc.nkr;
   const int e0 = D.src_off[src];
   const int k = D.src_off[src + 1] - e0;
   const int tid = threadIdx.x;
@@ -960,9 +1015,9 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
   const int T = (ncol + 16) / 16;
   const int ntiles = T * (T + 1) / 2;
   double* Qs = sm;                  // [nq][nq] symmetric
-  double* Mi = Qs + nq * nq;        // [k][36]  M_i of edge s
-  double* Rj = Mi + 36 * k;         // [k][9]   R_j of edge s (M_j = -blockdiag(I, R_j^T))
-  double* Hs = Rj + 9 * k;          // [k][36]  full symmetric
+  double* Mi = Qs + nq * nq;        // [k][36]  M_i of edge s (in body increments: M_i K_i)
+  double* Mj = Mi + 36 * k;         // [k][36]  M_j of edge s (M_j K_j)
+  double* Hs = Mj + 36 * k;         // [k][36]  full symmetric
   double* gs = Hs + 36 * k;         // [k][6]   g - y
   double* Wt = gs + 6 * k;          // [k][36]
   // Gram partials -> Q.  The lower tiles hold the data; the lower triangle is
@@ -1007,8 +1062,8 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
       const int e = D.src_edges[e0 + hs_s];
       const double* Rt = rel + (size_t)e * 12;
       const double* Rjs = Rw + (size_t)D.jj[e] * 9;
-      Mi[tid] = Mi_at(Rt, Rjs, rc / 6, rc % 6);
-      if (rc < 9) Rj[hs_s * 9 + rc] = Rjs[rc];
+      Mi[tid] = Mi_body(Wsrc, Rt, Rjs, Rw + (size_t)src * 9, rc / 6, rc % 6);
+      Mj[tid] = Mj_body(Wsrc, Rjs, rc / 6, rc % 6);
       Hs[tid] = vh;
     }
     if (first && own_g) gs[tid] = vg;
@@ -1031,51 +1086,39 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
     }
     Wt[i] = v;
   }
-  // Z_s+1,t+1 = M_j,s^T X_st M_j,t = P_s^T X_st P_t with P = blockdiag(I, R_j^T):
-  // [[X11, X12 R_t^T], [R_s X21, R_s X22 R_t^T]]
+  // Z_s+1,t+1 = M_j,s^T X_st M_j,t (M_j has a zero 3x3 block: zero entries skipped)
   for (int i = tid; i < k * k * 36; i += NT) {
     const int st = i / 36, s2 = st / k, t = st % k, a = (i % 36) / 6, b = i % 6;
     const double* Qb = Qs + (6 * s2) * nq + 6 * t;
     const bool diag = s2 == t;
     const double* Hb = Hs + s2 * 36;
-    auto X = [&](int m, int n) { return (diag ? Hb[m * 6 + n] : 0.0) - Qb[m * nq + n]; };
-    const double* Rs = Rj + s2 * 9;
-    const double* Rt = Rj + t * 9;
-    double v;
-    if (a < 3 && b < 3) {
-      v = X(a, b);
-    } else if (a < 3) {
-      v = 0.0;
+    const double* Ms = Mj + s2 * 36;
+    const double* Mt = Mj + t * 36;
+    double v = 0.0;
 #pragma unroll
-      for (int n = 0; n < 3; ++n) v += X(a, 3 + n) * Rt[(b - 3) * 3 + n];
-    } else if (b < 3) {
-      v = 0.0;
+    for (int m = 0; m < 6; ++m) {
+      const double ma = Ms[m * 6 + a];
+      if (ma == 0.0) continue;
+      double u = 0.0;
 #pragma unroll
-      for (int m = 0; m < 3; ++m) v += Rs[(a - 3) * 3 + m] * X(3 + m, b);
-    } else {
-      v = 0.0;
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        double u = 0.0;
-#pragma unroll
-        for (int n = 0; n < 3; ++n) u += X(3 + m, 3 + n) * Rt[(b - 3) * 3 + n];
-        v += Rs[(a - 3) * 3 + m] * u;
+      for (int n = 0; n < 6; ++n) {
+        const double mb = Mt[n * 6 + b];
+        if (mb == 0.0) continue;
+        u += ((diag ? Hb[m * 6 + n] : 0.0) - Qb[m * nq + n]) * mb;
       }
+      v += ma * u;
     }
     Zs[(size_t)((s2 + 1) * K1 + t + 1) * 36 + a * 6 + b] = v;
   }
   __syncthreads();
-  // Z_0,t+1 = W_t M_j,t = -W_t P_t and its transpose; Z_00 = sum_t W_t M_i,t
+  // Z_0,t+1 = W_t M_j,t and its transpose; Z_00 = sum_t W_t M_i,t
   for (int i = tid; i < k * 36; i += NT) {
     const int t = i / 36, a = (i % 36) / 6, b = i % 6;
     const double* Wb = Wt + t * 36 + a * 6;
-    double v;
-    if (b < 3) {
-      v = -Wb[b];
-    } else {
-      const double* Rt = Rj + t * 9;
-      v = -(Wb[3] * Rt[(b - 3) * 3 + 0] + Wb[4] * Rt[(b - 3) * 3 + 1] + Wb[5] * Rt[(b - 3) * 3 + 2]);
-    }
+    const double* Mt = Mj + t * 36;
+    double v = 0.0;
+#pragma unroll
+    for (int n = 0; n < 6; ++n) v += Wb[n] * Mt[n * 6 + b];
     Zs[(size_t)(0 * K1 + t + 1) * 36 + a * 6 + b] = v;
     Zs[(size_t)((t + 1) * K1 + 0) * 36 + b * 6 + a] = v;
   }
@@ -1121,23 +1164,18 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
         zv += scr[k * 36 + 2 * (s2 * 6 + a) + 1];
       }
     } else {
-      // M_j = -P: diag(P^T H P) and -P^T (g - y)
+      // diag(M_j^T H M_j) and M_j^T (g - y)
       const int s2 = ra - 1;
       const double* H = Hs + s2 * 36;
       const double* g = gs + s2 * 6;
-      if (a < 3) {
-        zb = H[a * 6 + a];
-        zv = -g[a];
-      } else {
-        const double* R = Rj + s2 * 9 + (a - 3) * 3;   // row a-3 of R_j: P[3+m][a] = R_j[a-3][m]
+      const double* M = Mj + s2 * 36;
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          double hm = 0.0;
+      for (int m = 0; m < 6; ++m) {
+        double hm = 0.0;
 #pragma unroll
-          for (int nn = 0; nn < 3; ++nn) hm += H[(3 + m) * 6 + 3 + nn] * R[nn];
-          zb += R[m] * hm;
-          zv -= R[m] * g[3 + m];
-        }
+        for (int nn = 0; nn < 6; ++nn) hm += H[m * 6 + nn] * M[nn * 6 + a];
+        zb += M[m * 6 + a] * hm;
+        zv += M[m * 6 + a] * g[m];
       }
     }
     ZBs[i] = zb;
@@ -1307,7 +1345,8 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
     const double* xi = xw + (size_t)D.kf_pos[src] * 15;
     const double* xj = xw + (size_t)D.kf_pos[D.jj[e]] * 15;
     double v = 0.0;
-    for (int m = 0; m < 6; ++m) v += Mi_at(Rt, Rj, c, m) * xi[m] + Mj_at(Rj, c, m) * xj[m];
+    const double* Rci = Rw + (size_t)src * 9;
+    for (int m = 0; m < 6; ++m) v += Mi_body(W, Rt, Rj, Rci, c, m) * xi[m] + Mj_body(W, Rj, c, m) * xj[m];
     u[i] = v;
   }
   __syncthreads();
@@ -1648,7 +1687,7 @@ static VisKernel vis_kernel(int kmax) {
 }
 static size_t local_lds(int kmax) {
   const size_t k = kmax, nq = 6 * k + 1;
-  return sizeof(double) * std::max<size_t>(nq * nq + 3 * 36 * k + 9 * k + 6 * k, 2 * kLocalThreads);
+  return sizeof(double) * std::max<size_t>(nq * nq + 4 * 36 * k + 6 * k, 2 * kLocalThreads);
 }
 
 void launch_reset_status(hipStream_t s, DevStatus* st, int n) {

@@ -41,6 +41,8 @@ struct DevStatus {
 // Per-window device descriptor.
 struct WinDev {
   double fx, fy, cx, cy, g[3];
+  double Rbc[9], tbc[3];             // camera-IMU extrinsic (body-from-camera), row-major rotation
+  int ext;                           // 1: T_bc is not the identity (vision terms go through it)
   int H, W, HW, N;
   int kf_base, e_base, f_base, F;    // global index of the first keyframe / edge / factor
   int nkr;                           // pixel ranges per source in the fused assembly + Gram

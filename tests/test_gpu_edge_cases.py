@@ -11,6 +11,7 @@
   Schur Gram, 28 lower tiles, every Gram slot of the assembly in use), in
   FP64 and in mixed precision.
 * Keyframes with no outgoing edge (targets only).
+* A camera-IMU extrinsic T_bc away from the identity.
 * Non-finite inputs: VI_ENONFINITE and the state left bit for bit.
 * The 64-window batch in mixed precision, every window against the oracle.
 
@@ -31,6 +32,7 @@ from paper_2512_02293_amd import synth
 pytestmark = pytest.mark.gpu
 
 GROUPS = {"dtheta": slice(0, 3), "dp": slice(3, 6), "dv": slice(6, 9), "dbg": slice(9, 12), "dba": slice(12, 15)}
+T_BC = (0.04, -0.02, 0.015, *so3.R_to_quat(so3.Exp(np.deg2rad(np.array([6.0, -4.0, 9.0])))))
 FP64_TOL = 1e-8
 
 
@@ -147,6 +149,20 @@ def test_step_keyframes_without_outgoing_edges(ctx, precision):
     else:
         rep, orep = _step_vs_oracle(ctx, prob, precision=1, tol_group=1e-4, tol_depth=1e-3)
     assert not orep["dd"][[1, 4, 7]].any()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_step_with_camera_imu_extrinsic(ctx, precision):
+    """Cameras rotated (about 12 degrees) and offset (4.8 cm) from the IMU body
+    (Sec. 3.1: T_bc enters the vision terms, the inertial factors stay in the
+    body frame)."""
+    cfg = synth.SceneConfig(n_kf=7, H=37, W=53, k_out=4)
+    cfg.T_bc = T_BC
+    prob = synth.make_problem(cfg, 71)
+    if precision == 0:
+        _step_vs_oracle(ctx, prob)
+    else:
+        _step_vs_oracle(ctx, prob, precision=1, tol_group=1e-4, tol_depth=1e-3)
 
 
 @pytest.mark.parametrize("what", ["target_nan", "weight_nan", "target_inf", "invdepth_nan"])
