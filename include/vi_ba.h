@@ -134,7 +134,7 @@ typedef struct {
   double* pose;              /* device [N][7] (p, q xyzw) */
   double* vel;               /* device [N][3] world frame */
   double* bias;              /* device [N][6] (b_g, b_a) */
-  double* invdepth;          /* device [N][H][W] inverse depth (float64) */
+  void* invdepth;            /* device [N][H][W] inverse depth: float64, or float32 with vi_opts.invdepth_f32 */
 } vi_state;
 
 /* Frame graph: directed co-visible pairs and their correspondence targets
@@ -159,11 +159,20 @@ typedef struct {
 #define VI_PREC_FP64 0
 #define VI_PREC_MIXED 1
 
+/* How the IMU biases are solved (vi_opts.bias_mode; Table 6 (a) and (f)). */
+#define VI_BIAS_PER_KF 0     /* one bias per keyframe, random walk between keyframes (Eq. 3) */
+#define VI_BIAS_FIXED 1      /* the biases are not solved (kept at their input values) */
+#define VI_BIAS_GLOBAL 2     /* one bias shared by every keyframe of the window */
+
 typedef struct {
   int32_t n_fixed;           /* gauge: leading keyframes whose pose is held (>= 1 typical) */
   int32_t use_imu;           /* 0: vision only (velocity and bias are not solved) */
-  int32_t bias_fixed;        /* 1: biases are not solved */
+  int32_t bias_mode;         /* VI_BIAS_PER_KF, VI_BIAS_FIXED or VI_BIAS_GLOBAL */
   int32_t precision;         /* VI_PREC_FP64 or VI_PREC_MIXED */
+  int32_t invdepth_f32;      /* 1: vi_state.invdepth of every window is float32 [N][H][W] (VI_PREC_MIXED only:
+                                the maps are read and written in FP32, the depth update is formed in FP64 and
+                                rounded once); 0: float64 */
+  int32_t reserved;          /* must be 0 */
   double lm_lambda;          /* Marquardt factor on the pose/vel/bias diagonal (>= 0) */
   double depth_eta;          /* added to the inverse-depth diagonal C (>= 0) */
   double z_min;              /* minimum depth in the target camera, m */

@@ -50,9 +50,9 @@ class Edges(C.Structure):
 
 
 class Opts(C.Structure):
-    _fields_ = [("n_fixed", C.c_int32), ("use_imu", C.c_int32), ("bias_fixed", C.c_int32),
-                ("precision", C.c_int32), ("lm_lambda", C.c_double), ("depth_eta", C.c_double),
-                ("z_min", C.c_double), ("d_min", C.c_double)]
+    _fields_ = [("n_fixed", C.c_int32), ("use_imu", C.c_int32), ("bias_mode", C.c_int32),
+                ("precision", C.c_int32), ("invdepth_f32", C.c_int32), ("reserved", C.c_int32),
+                ("lm_lambda", C.c_double), ("depth_eta", C.c_double), ("z_min", C.c_double), ("d_min", C.c_double)]
 
 
 class Report(C.Structure):
@@ -198,11 +198,16 @@ def make_camera(fx, fy, cx, cy, H, W, gravity=(0.0, 0.0, -9.81), T_bc=None) -> C
     return Camera(fx, fy, cx, cy, H, W, (C.c_double * 3)(*gravity), (C.c_double * 7)(*tb))
 
 
+VI_BIAS_PER_KF, VI_BIAS_FIXED, VI_BIAS_GLOBAL = 0, 1, 2
+
+
 def make_opts(n_fixed=1, use_imu=True, bias_fixed=False, lm_lambda=1e-4, depth_eta=1e-8, z_min=0.1,
-              d_min=1e-3, precision=0) -> Opts:
-    """precision: VI_PREC_FP64 (0) or VI_PREC_MIXED (1)."""
-    return Opts(n_fixed, int(bool(use_imu)), int(bool(bias_fixed)), int(precision), lm_lambda, depth_eta, z_min,
-                d_min)
+              d_min=1e-3, precision=0, bias_mode=None, invdepth_f32=False) -> Opts:
+    """precision: VI_PREC_FP64 (0) or VI_PREC_MIXED (1); bias_mode: VI_BIAS_* (bias_fixed=True is
+    VI_BIAS_FIXED); invdepth_f32: the states' inverse depths are float32 (mixed precision only)."""
+    mode = (VI_BIAS_FIXED if bias_fixed else VI_BIAS_PER_KF) if bias_mode is None else int(bias_mode)
+    return Opts(n_fixed, int(bool(use_imu)), mode, int(precision), int(bool(invdepth_f32)), 0, lm_lambda, depth_eta,
+                z_min, d_min)
 
 
 class Context:
@@ -276,7 +281,7 @@ class Context:
         _check_dev(pose, (N, 7), torch.float64, "pose")
         _check_dev(vel, (N, 3), torch.float64, "vel")
         _check_dev(bias, (N, 6), torch.float64, "bias")
-        _check_dev(invdepth, (N, H, W), torch.float64, "invdepth")
+        _check_dev(invdepth, (N, H, W), torch.float32 if opts.invdepth_f32 else torch.float64, "invdepth")
         _check_dev(target, (E, 2, H, W), torch.float32, "target")
         _check_dev(weight, (E, 2, H, W), torch.float32, "weight")
         if imu is not None:
@@ -319,7 +324,7 @@ class Context:
         self._check(self.lib.vi_ctx_set_tolerance(self.h, float(rel_tol)))
 
     # -- batches of independent windows ---------------------------------------
-    def _windows(self, probs, imus, with_reports, costs, iters, stage_ms=False):
+    def _windows(self, opts, probs, imus, with_reports, costs, iters, stage_ms=False):
         torch = self.torch
         n = len(probs)
         wins = (Window * n)()
@@ -329,7 +334,8 @@ class Context:
             N, E, H, W = int(dp.pose.shape[0]), int(dp.ii.shape[0]), int(dp.cam.H), int(dp.cam.W)
             for t, shape, dt, name in ((dp.pose, (N, 7), torch.float64, "pose"), (dp.vel, (N, 3), torch.float64, "vel"),
                                        (dp.bias, (N, 6), torch.float64, "bias"),
-                                       (dp.invdepth, (N, H, W), torch.float64, "invdepth"),
+                                       (dp.invdepth, (N, H, W),
+                                        torch.float32 if opts.invdepth_f32 else torch.float64, "invdepth"),
                                        (dp.target, (E, 2, H, W), torch.float32, "target"),
                                        (dp.weight, (E, 2, H, W), torch.float32, "weight")):
                 _check_dev(t, shape, dt, f"window {w} {name}")
@@ -352,13 +358,13 @@ class Context:
         return wins, reps, keep
 
     def workspace_size_batched(self, probs, opts: Opts) -> int:
-        wins, _, _ = self._windows(probs, [None] * len(probs), False, False, 1)
+        wins, _, _ = self._windows(opts, probs, [None] * len(probs), False, False, 1)
         return int(self.lib.vi_workspace_size_batched(len(probs), wins, C.byref(opts)))
 
     def solve_batched(self, probs, imus, opts: Opts, iters: int, workspace, costs=False, stage_ms=False):
         """Solve every window of a batch in the same launches; returns per-window reports."""
         _check_dev(workspace, (None,), self.torch.uint8, "workspace")
-        wins, reps, keep = self._windows(probs, imus, True, costs, iters, stage_ms)
+        wins, reps, keep = self._windows(opts, probs, imus, True, costs, iters, stage_ms)
         rc = self.lib.vi_ba_solve_batched(self.h, len(probs), wins, C.byref(opts), iters, _ptr(workspace),
                                           workspace.numel())
         out = []
@@ -378,7 +384,7 @@ class Context:
     def warm_features(self, probs, imus, opts: Opts, hq: int, wq: int):
         """Input planes of every keyframe of the windows: (feat [n][15][hq][wq], dims [n][2])."""
         torch = self.torch
-        wins, _, _ = self._windows(probs, imus, False, False, 1)
+        wins, _, _ = self._windows(opts, probs, imus, False, False, 1)
         n = sum(int(d.pose.shape[0]) for d in probs)
         feat = torch.empty((n, 15, hq, wq), dtype=torch.float32, device=probs[0].pose.device)
         dims = torch.empty((n, 2), dtype=torch.int32, device=probs[0].pose.device)
@@ -545,11 +551,11 @@ class Context:
 
     def warm_apply(self, probs, imus, opts: Opts, dd, db):
         n, hq, wq = dd.shape
-        wins, _, _ = self._windows(probs, imus, False, False, 1)
+        wins, _, _ = self._windows(opts, probs, imus, False, False, 1)
         self._check(self.lib.vi_warm_apply(self.h, len(probs), wins, C.byref(opts), hq, wq, _ptr(dd), _ptr(db)))
 
     def warm_start_workspace_size(self, probs, opts: Opts) -> int:
-        wins, _, _ = self._windows(probs, [None] * len(probs), False, False, 1)
+        wins, _, _ = self._windows(opts, probs, [None] * len(probs), False, False, 1)
         return int(self.lib.vi_warm_start_workspace_size(len(probs), wins, C.byref(opts)))
 
     def warm_start(self, probs, imus, opts: Opts, params, workspace):
@@ -557,7 +563,7 @@ class Context:
         per-window dicts (accepted, cost_init, cost_warm, cost_after)."""
         _check_dev(workspace, (None,), self.torch.uint8, "workspace")
         _check_dev(params, (int(self.lib.vi_warm_param_count()),), self.torch.float32, "params")
-        wins, reps, keep = self._windows(probs, imus, True, True, 1)
+        wins, reps, keep = self._windows(opts, probs, imus, True, True, 1)
         acc = np.zeros(len(probs), dtype=np.int32)
         self._check(self.lib.vi_warm_start(self.h, len(probs), wins, C.byref(opts), _ptr(params), _ptr(workspace),
                                            workspace.numel(), acc.ctypes.data_as(C.c_void_p)))
@@ -568,7 +574,7 @@ class Context:
         """Warm start then iters GN steps in one graph; per-window reports with 'accepted'."""
         _check_dev(workspace, (None,), self.torch.uint8, "workspace")
         _check_dev(params, (int(self.lib.vi_warm_param_count()),), self.torch.float32, "params")
-        wins, reps, keep = self._windows(probs, imus, True, costs, max(iters, 1))
+        wins, reps, keep = self._windows(opts, probs, imus, True, costs, max(iters, 1))
         acc = np.zeros(len(probs), dtype=np.int32)
         self._check(self.lib.vi_ba_solve_warm(self.h, len(probs), wins, C.byref(opts), _ptr(params), iters,
                                               _ptr(workspace), workspace.numel(), acc.ctypes.data_as(C.c_void_p)))
@@ -585,14 +591,14 @@ class Context:
 class DeviceProblem:
     """A synthetic problem's arrays moved to the GPU (inputs resident in HBM)."""
 
-    def __init__(self, prob, device="cuda:0"):
+    def __init__(self, prob, device="cuda:0", invdepth_f32=False):
         import torch
         self.prob = prob
         t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
         self.pose = t(prob.pose, torch.float64)
         self.vel = t(prob.vel, torch.float64)
         self.bias = t(prob.bias, torch.float64)
-        self.invdepth = t(prob.invdepth, torch.float64)
+        self.invdepth = t(prob.invdepth, torch.float32 if invdepth_f32 else torch.float64)
         self.target = t(prob.target, torch.float32)
         self.weight = t(prob.weight, torch.float32)
         self.gyro = t(prob.gyro, torch.float64)
@@ -612,7 +618,7 @@ class DeviceProblem:
         self.pose.copy_(torch.as_tensor(p.pose))
         self.vel.copy_(torch.as_tensor(p.vel))
         self.bias.copy_(torch.as_tensor(p.bias))
-        self.invdepth.copy_(torch.as_tensor(p.invdepth))
+        self.invdepth.copy_(torch.as_tensor(p.invdepth).to(self.invdepth.dtype))
 
 
 class DevicePGBA:

@@ -129,6 +129,13 @@ vi_status check_opts(vi_ctx* ctx, const vi_opts* o) {
     return fail(ctx, VI_EINVAL, "damping must be finite and >= 0");
   if (!std::isfinite(o->z_min) || !(o->d_min >= 0.0) || !std::isfinite(o->d_min))
     return fail(ctx, VI_EINVAL, "z_min must be finite and d_min finite and >= 0");
+  if (o->bias_mode != VI_BIAS_PER_KF && o->bias_mode != VI_BIAS_FIXED && o->bias_mode != VI_BIAS_GLOBAL)
+    return fail(ctx, VI_EINVAL, "opts.bias_mode must be VI_BIAS_PER_KF, VI_BIAS_FIXED or VI_BIAS_GLOBAL");
+  if (o->bias_mode == VI_BIAS_GLOBAL) return fail(ctx, VI_EUNSUPPORTED, "VI_BIAS_GLOBAL is not supported");
+  if (o->invdepth_f32 != 0 && o->invdepth_f32 != 1) return fail(ctx, VI_EINVAL, "opts.invdepth_f32 must be 0 or 1");
+  if (o->invdepth_f32 && o->precision != VI_PREC_MIXED)
+    return fail(ctx, VI_EINVAL, "float32 inverse depths (opts.invdepth_f32) need VI_PREC_MIXED");
+  if (o->reserved != 0) return fail(ctx, VI_EINVAL, "opts.reserved must be 0");
   return VI_OK;
 }
 
@@ -681,7 +688,7 @@ void extrinsic_rotation(const double* T, double* R, double* t, int* ext) {
 }
 
 // this call's window pointers -> host window table -> device
-vi_status refresh_windows(vi_ctx* ctx, const std::vector<WinIn>& wins) {
+vi_status refresh_windows(vi_ctx* ctx, const std::vector<WinIn>& wins, bool depth_f32 = false) {
   Plan& P = ctx->plan;
   for (int w = 0; w < P.n_win; ++w) {
     WinDev& W = P.win[w];
@@ -690,7 +697,9 @@ vi_status refresh_windows(vi_ctx* ctx, const std::vector<WinIn>& wins) {
     for (int k = 0; k < 3; ++k) W.g[k] = in.cam->gravity[k];
     // camera-IMU extrinsic (the pose-graph adjustment's poses are camera poses: none there)
     extrinsic_rotation(in.rel ? nullptr : in.cam->T_bc, W.Rbc, W.tbc, &W.ext);
-    W.pose = in.st->pose; W.vel = in.st->vel; W.bias = in.st->bias; W.invdepth = in.st->invdepth;
+    W.pose = in.st->pose; W.vel = in.st->vel; W.bias = in.st->bias;
+    W.invdepth = depth_f32 ? nullptr : (double*)in.st->invdepth;
+    W.invdepth32 = depth_f32 ? (float*)in.st->invdepth : nullptr;
     W.target = in.ed->target; W.weight = in.ed->weight; W.imu = in.imu;
     W.rep_dxi = in.rep ? in.rep->dxi : nullptr;
     W.rep_dd = in.rep ? in.rep->dd : nullptr;
@@ -864,7 +873,7 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
     return fail(ctx, VI_ENOMEM, "workspace too small: %zu bytes given, %zu needed", workspace_bytes, need);
   Work w = do_carve(P, workspace, nullptr);
   const WarmWork ww = wa ? warm_carve(P, wa->hq, wa->wq, workspace, nullptr) : WarmWork{};
-  OptsDev od{o->n_fixed, o->use_imu ? 1 : 0, o->bias_fixed ? 1 : 0, o->precision, o->lm_lambda, o->depth_eta,
+  OptsDev od{o->n_fixed, o->use_imu ? 1 : 0, o->bias_mode == VI_BIAS_FIXED ? 1 : 0, o->precision, o->lm_lambda, o->depth_eta,
              o->z_min, o->d_min, ctx->tol};
   const bool timing = wins[0].rep && wins[0].rep->stage_ms;
 
@@ -873,12 +882,12 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
   HIPCHK(ctx, hipStreamWaitEvent(ctx->priv, ctx->ev_in, 0));
   hipStream_t sp = ctx->priv;
 
-  s = refresh_windows(ctx, wins);
+  s = refresh_windows(ctx, wins, o->invdepth_f32 != 0);
   if (s != VI_OK) return s;
   if (ctx->autotune) {
     s = autotune_range(ctx, w, od);
     if (s != VI_OK) return s;
-    s = refresh_windows(ctx, wins);
+    s = refresh_windows(ctx, wins, o->invdepth_f32 != 0);
     if (s != VI_OK) return s;
   }
   const DevPlan& D = ctx->dplan;
@@ -925,7 +934,8 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
     key.push_back((uint64_t)(uintptr_t)(wa ? wa->params : nullptr));
     key.push_back(wa ? (uint64_t)(wa->hq * 1000 + wa->wq) : 0);
     for (const WinDev& W : P.win) {
-      const void* ptrs[] = {W.pose, W.vel, W.bias, W.invdepth, W.target, W.weight, W.imu, W.rep_dxi, W.rep_dd};
+      const void* ptrs[] = {W.pose,   W.vel,    W.bias, W.invdepth, W.invdepth32, W.target,
+                            W.weight, W.imu,    W.rep_dxi, W.rep_dd};
       for (const void* p : ptrs) key.push_back((uint64_t)(uintptr_t)p);
       uint64_t cam[19];
       const double cv[19] = {W.fx,     W.fy,     W.cx,     W.cy,     W.g[0],   W.g[1],   W.g[2],
@@ -1013,6 +1023,7 @@ vi_status pg_window(vi_ctx* ctx, const vi_camera* cam, int32_t n_kf, double* pos
   if (!cam || !loops || !rel) return fail(ctx, VI_EINVAL, "null argument");
   vi_status s = check_opts(ctx, o);
   if (s != VI_OK) return s;
+  if (o->invdepth_f32) return fail(ctx, VI_EINVAL, "the pose-graph adjustment takes float64 inverse depths");
   if (rel->n_rel < 0) return fail(ctx, VI_EINVAL, "negative relative-pose count");
   if (rel->n_rel > 0 && (!rel->ii || !rel->jj)) return fail(ctx, VI_EINVAL, "null relative-pose index array");
   if (full && rel->n_rel > 0 && (!rel->meas || !rel->info))
@@ -1346,7 +1357,7 @@ vi_status warm_windows(vi_ctx* ctx, int32_t n_windows, const vi_window* windows,
   }
   s = ensure_plan(ctx, wins);
   if (s != VI_OK) return s;
-  return refresh_windows(ctx, wins);
+  return refresh_windows(ctx, wins, o->invdepth_f32 != 0);
 }
 
 }  // namespace
@@ -1399,7 +1410,7 @@ vi_status vi_warm_features(vi_ctx* ctx, int32_t n_windows, const vi_window* wind
   s = warm_windows(ctx, n_windows, windows, opts, hq, wq, wins);
   if (s != VI_OK) return s;
   if ((s = warm_begin(ctx)) != VI_OK) return s;
-  OptsDev od{opts->n_fixed, opts->use_imu ? 1 : 0, opts->bias_fixed ? 1 : 0, opts->precision, opts->lm_lambda,
+  OptsDev od{opts->n_fixed, opts->use_imu ? 1 : 0, opts->bias_mode == VI_BIAS_FIXED ? 1 : 0, opts->precision, opts->lm_lambda,
              opts->depth_eta, opts->z_min, opts->d_min};
   launch_warm_features(ctx->priv, ctx->plan, ctx->dplan, od, hq, wq, feat, dims);
   return warm_end(ctx);
@@ -1477,7 +1488,7 @@ vi_status vi_warm_apply(vi_ctx* ctx, int32_t n_windows, const vi_window* windows
   if (s != VI_OK) return s;
   if ((s = warm_begin(ctx)) != VI_OK) return s;
   launch_warm_apply(ctx->priv, ctx->plan, ctx->dplan, hq, wq, dd, db, opts->d_min,
-                    (opts->use_imu && !opts->bias_fixed) ? 1 : 0);
+                    (opts->use_imu && opts->bias_mode == VI_BIAS_PER_KF) ? 1 : 0);
   return warm_end(ctx);
 }
 

@@ -194,6 +194,17 @@ struct BlockSum {
 // t_ji = R_j^T (p_i - p_j); with keyframe scales (Sim(3) poses of the
 // pose-graph adjustment, X_w = s R X + p) o[0..8] = (s_i / s_j) R_ji and
 // t_ji = R_j^T (p_i - p_j) / s_j.  i, j index the window's pose array.
+// inverse depth i of a window (FP64, or FP32 when the caller keeps FP32 maps)
+__device__ __forceinline__ double dep_load(const WinDev& W, size_t i) {
+  return W.invdepth32 ? (double)W.invdepth32[i] : W.invdepth[i];
+}
+__device__ __forceinline__ void dep_store(const WinDev& W, size_t i, double v) {
+  if (W.invdepth32)
+    W.invdepth32[i] = (float)v;
+  else
+    W.invdepth[i] = v;
+}
+
 // Camera of keyframe a (window index): with the camera-IMU extrinsic the
 // state's pose is the body's and the camera is T_wb T_bc, R_c = R_b R_bc,
 // p_c = p_b + R_b t_bc (Sec. 3.1, inertial residual).
@@ -640,7 +651,7 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
     // blocks are never read): only the non-finite inverse-depth check and an
     // empty cost slot.  k is uniform over the workgroup.
     bool bad = false;
-    for (int p = p_beg + tid; p < p_end; p += kVisThreads) bad = bad || !isfinite(W.invdepth[(size_t)ls * HW + p]);
+    for (int p = p_beg + tid; p < p_end; p += kVisThreads) bad = bad || !isfinite(dep_load(W, (size_t)ls * HW + p));
     if (st && bad) set_status(st + D.win_of_kf[src], VI_ENONFINITE, -1);
     if (tid == 0) {
       const size_t b = ((size_t)src * ncost + kr) * 2;
@@ -652,7 +663,7 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
   for (int i = tid; i < 2 * tsz; i += kVisThreads) Et[i] = (R)0;
   __syncthreads();
 
-  const double* dsrc = W.invdepth + (size_t)ls * HW;
+  const size_t dsrc = (size_t)ls * HW;            // this keyframe's inverse depths start here
   double* Cds = Cd + W.pix_base + (size_t)ls * HW;
   double* wds = wd + W.pix_base + (size_t)ls * HW;
   const R fx = (R)W.fx, fy = (R)W.fy, cx = (R)W.cx, cy = (R)W.cy, zmin = (R)o.z_min;
@@ -681,7 +692,7 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
   double nd;
   auto prefetch = [&](int c) {
     const int pp = (c + lane < p_end) ? c + lane : p_beg;
-    nd = dsrc[pp];
+    nd = dep_load(W, dsrc + pp);
 #pragma unroll
     for (int u = 0; u < SLOTS; ++u) {
       if (wave + kVisWaves * u < k) {
@@ -1355,8 +1366,7 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
   const size_t pl = (size_t)ls * HW + p;
   const size_t pi = W.pix_base + pl;
   const double cd = Cd[pi];
-  double* dep = W.invdepth + pl;
-  const double d = *dep;
+  const double d = dep_load(W, pl);
   double ddv = 0.0;
   if (cd > 0.0 && k > 0) {
     // E^T dxi at this pixel: sum over edges of L_e,p . u_e, with L = J_loc^T W J_d
@@ -1387,7 +1397,7 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
     }
     ddv = (double)(((R)wd[pi] - et) / (R)cd);
   }
-  *dep = fmax(d + ddv, o.d_min);
+  dep_store(W, pl, fmax(d + ddv, o.d_min));
   if (W.rep_dd) W.rep_dd[pl] = ddv;
   else dd_ws[pi] = ddv;
 }
@@ -1440,11 +1450,12 @@ __global__ void __launch_bounds__(256) k_vis_cost(OptsDev o, DevPlan D, int ncos
   const int pc = inpx ? p : 0;
   const R qx = (R)(((double)(pc % W.W) - W.cx) / W.fx);
   const R qy = (R)(((double)(pc / W.W) - W.cy) / W.fy);
-  double dsrc = W.invdepth[(size_t)ls * HW + pc];
+  double dsrc = dep_load(W, (size_t)ls * HW + pc);
   if (dd) {
     if (inpx) {
       dsrc = warm_corrected_depth(W, src, pc, HQ, WQ, dd, dsrc, d_min);
-      W.invdepth[(size_t)ls * HW + pc] = dsrc;
+      dep_store(W, (size_t)ls * HW + pc, dsrc);
+      dsrc = dep_load(W, (size_t)ls * HW + pc);   // the stored value (rounded when FP32)
     }
     // biases that the step does not solve (no inertial terms, or held fixed) keep their value
     if (kr == 0 && tid < 6 && o.use_imu && !o.bias_fixed) W.bias[(size_t)ls * 6 + tid] += (double)db[(size_t)src * 6 + tid];
@@ -1563,7 +1574,7 @@ __global__ void __launch_bounds__(256) k_warm_features(OptsDev o, DevPlan D, int
   double v[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (cell_in && y < W.H && x < W.W) {
     const int pix = y * W.W + x;
-    const double d = W.invdepth[(size_t)ls * W.HW + pix];
+    const double d = dep_load(W, (size_t)ls * W.HW + pix);
     if (saved_d) saved_d[W.pix_base + (size_t)ls * W.HW + pix] = d;
     v[6] = d;
     v[7] = 1.0;
@@ -1622,8 +1633,8 @@ __global__ void __launch_bounds__(256) k_warm_apply(DevPlan D, int HQ, int WQ, c
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (apply_bias && blockIdx.x == 0 && threadIdx.x < 6) W.bias[(size_t)ls * 6 + threadIdx.x] += (double)db[(size_t)src * 6 + threadIdx.x];
   if (p >= W.HW) return;
-  double* dep = W.invdepth + (size_t)ls * W.HW + p;
-  *dep = warm_corrected_depth(W, src, p, HQ, WQ, dd, *dep, d_min);
+  const size_t pd = (size_t)ls * W.HW + p;
+  dep_store(W, pd, warm_corrected_depth(W, src, p, HQ, WQ, dd, dep_load(W, pd), d_min));
 }
 
 // Keep (restore = 0) or put back (restore = 1) a keyframe's inverse depths and
@@ -1643,11 +1654,11 @@ __global__ void __launch_bounds__(256) k_warm_state(DevPlan D, double* __restric
     if (f1 < f0) return;
   }
   const int p = blockIdx.x * 256 + threadIdx.x;
-  double* dep = W.invdepth + (size_t)ls * W.HW;
+  const size_t pd = (size_t)ls * W.HW + p;
   double* sd = saved_d + W.pix_base + (size_t)ls * W.HW;
   if (p < W.HW) {
-    if (restore) dep[p] = sd[p];
-    else sd[p] = dep[p];
+    if (restore) dep_store(W, pd, sd[p]);
+    else sd[p] = dep_load(W, pd);
   }
   if (blockIdx.x == 0 && threadIdx.x < 6) {
     double* b = W.bias + (size_t)ls * 6 + threadIdx.x;

@@ -56,7 +56,8 @@ struct WinDev {
   double* pose;
   double* vel;
   double* bias;
-  double* invdepth;
+  double* invdepth;                  // FP64 inverse depths, or null when they are FP32:
+  float* invdepth32;                 // FP32 inverse depths (mixed precision), or null
   const float* target;
   const float* weight;
   const vi_preint* imu;

@@ -44,7 +44,7 @@ def test_struct_layouts_match_c():
       P(vi_camera) P(vi_imu_noise) P(vi_preint) P(vi_state) P(vi_edges) P(vi_opts) P(vi_report) P(vi_window)
       O(vi_window, state) O(vi_window, edges) O(vi_window, imu) O(vi_window, report)
       O(vi_camera, H) O(vi_camera, gravity) O(vi_camera, T_bc) O(vi_preint, cov) O(vi_preint, cov_bias)
-      O(vi_state, invdepth) O(vi_edges, weight) O(vi_opts, lm_lambda) O(vi_opts, d_min)
+      O(vi_state, invdepth) O(vi_edges, weight) O(vi_opts, invdepth_f32) O(vi_opts, lm_lambda) O(vi_opts, d_min)
       O(vi_report, n_valid) O(vi_report, dxi) O(vi_report, stage_ms)
       P(vi_gaussians) O(vi_gaussians, anchor) O(vi_gaussians, cov_out)
       return 0;
@@ -69,7 +69,7 @@ def test_struct_layouts_match_c():
         "vi_camera.T_bc": binding.Camera.T_bc.offset,
         "vi_preint.cov": 8 * 61, "vi_preint.cov_bias": 8 * 148,
         "vi_state.invdepth": binding.State.invdepth.offset, "vi_edges.weight": binding.Edges.weight.offset,
-        "vi_opts.lm_lambda": binding.Opts.lm_lambda.offset, "vi_opts.d_min": binding.Opts.d_min.offset,
+        "vi_opts.invdepth_f32": binding.Opts.invdepth_f32.offset, "vi_opts.lm_lambda": binding.Opts.lm_lambda.offset, "vi_opts.d_min": binding.Opts.d_min.offset,
         "vi_report.n_valid": binding.Report.n_valid.offset, "vi_report.dxi": binding.Report.dxi.offset,
         "vi_report.stage_ms": binding.Report.stage_ms.offset,
         "vi_gaussians": C.sizeof(binding.Gaussians), "vi_gaussians.anchor": binding.Gaussians.anchor.offset,

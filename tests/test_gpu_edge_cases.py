@@ -12,6 +12,8 @@
   FP64 and in mixed precision.
 * Keyframes with no outgoing edge (targets only).
 * A camera-IMU extrinsic T_bc away from the identity.
+* Float32 inverse-depth maps in mixed precision (one step against the
+  oracle, and a solve against the same solve on float64 maps).
 * Non-finite inputs: VI_ENONFINITE and the state left bit for bit.
 * The 64-window batch in mixed precision, every window against the oracle.
 
@@ -59,16 +61,17 @@ def _bopts(precision=0, **kw):
                                 precision=precision)
 
 
-def _step_vs_oracle(ctx, prob, precision=0, tol_group=FP64_TOL, tol_depth=FP64_TOL, **kw):
+def _step_vs_oracle(ctx, prob, precision=0, tol_group=FP64_TOL, tol_depth=FP64_TOL, f32=False, **kw):
     import torch
     from paper_2512_02293_amd import binding
     oopts, bopts = _bopts(precision, **kw)
-    dp = binding.DeviceProblem(prob)
+    bopts.invdepth_f32 = int(f32)
+    dp = binding.DeviceProblem(prob, invdepth_f32=f32)
     imu = ctx.imu_preintegrate(dp.off, dp.gyro, dp.accel, dp.imu_dt, dp.bias_hat, dp.noise)
     ws = torch.empty(ctx.workspace_size(dp.cam, prob.n_kf, dp.ii, dp.jj, bopts), dtype=torch.uint8,
                      device="cuda:0")
     dxi = torch.zeros((prob.n_kf, 15), dtype=torch.float64, device="cuda:0")
-    dd = torch.zeros_like(dp.invdepth)
+    dd = torch.zeros(tuple(dp.invdepth.shape), dtype=torch.float64, device="cuda:0")
     rep = ctx.solve(dp.cam, dp.pose, dp.vel, dp.bias, dp.invdepth, dp.ii, dp.jj, dp.target, dp.weight, imu,
                     bopts, 1, ws, dxi=dxi, dd=dd)
     cam, st, gr = osolve.from_problem(prob)
@@ -163,6 +166,44 @@ def test_step_with_camera_imu_extrinsic(ctx, precision):
         _step_vs_oracle(ctx, prob)
     else:
         _step_vs_oracle(ctx, prob, precision=1, tol_group=1e-4, tol_depth=1e-3)
+
+
+def test_mixed_step_with_float32_inverse_depths(ctx):
+    """Mixed precision with the caller's inverse-depth maps in float32 (read and
+    written in FP32, the update formed in FP64 and rounded once); the oracle
+    starts from the same float32 values."""
+    prob = synth.add_degenerate_pixels(synth.make_problem(synth.SceneConfig(n_kf=7, H=37, W=53, k_out=4), 81), 82)
+    prob.invdepth = prob.invdepth.astype(np.float32).astype(np.float64)
+    _step_vs_oracle(ctx, prob, precision=1, tol_group=1e-4, tol_depth=1e-3, f32=True)
+
+
+def test_float32_inverse_depths_over_a_solve(ctx):
+    """Six mixed-precision iterations with float32 maps against the same solve
+    with float64 maps: the cost trace agrees to the rounding of the stored
+    depths (1e-5 relative), and the option is refused in FP64 and by the
+    pose-graph adjustment."""
+    import torch
+    from paper_2512_02293_amd import binding
+    prob = synth.make_problem(synth.config_small(), 83)
+    prob.invdepth = prob.invdepth.astype(np.float32).astype(np.float64)
+    costs = {}
+    for f32 in (False, True):
+        o = binding.make_opts(precision=1, invdepth_f32=f32)
+        dp = binding.DeviceProblem(prob, invdepth_f32=f32)
+        imu = ctx.imu_preintegrate(dp.off, dp.gyro, dp.accel, dp.imu_dt, dp.bias_hat, dp.noise)
+        ws = torch.empty(ctx.workspace_size(dp.cam, prob.n_kf, dp.ii, dp.jj, o), dtype=torch.uint8, device="cuda:0")
+        rep = ctx.solve(dp.cam, dp.pose, dp.vel, dp.bias, dp.invdepth, dp.ii, dp.jj, dp.target, dp.weight, imu, o,
+                        6, ws, costs=True)
+        costs[f32] = np.asarray(rep["costs"])
+        if f32:
+            assert dp.invdepth.dtype == torch.float32
+    print("costs f64 maps", costs[False][[0, -1]], "f32 maps", costs[True][[0, -1]])
+    np.testing.assert_allclose(costs[True], costs[False], rtol=1e-5)
+    with pytest.raises(binding.ViError) as ei:
+        o = binding.make_opts(precision=0, invdepth_f32=True)
+        dp = binding.DeviceProblem(prob, invdepth_f32=True)
+        ctx.solve(dp.cam, dp.pose, dp.vel, dp.bias, dp.invdepth, dp.ii, dp.jj, dp.target, dp.weight, imu, o, 1, ws)
+    assert ei.value.code == binding.VI_EINVAL
 
 
 @pytest.mark.parametrize("what", ["target_nan", "weight_nan", "target_inf", "invdepth_nan"])
