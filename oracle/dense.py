@@ -18,8 +18,9 @@ from . import vision
 from .normal_eq import active_mask
 
 
-def full_system(cam, state, graph, opts):
-    """Dense (H, g) over [xi (15N), d (N*HW)] with g = -J^T W rho."""
+def full_system(cam, state, graph, opts, global_bias=False):
+    """Dense (H, g) over [xi (15N), d (N*HW)] with g = -J^T W rho.  global_bias:
+    each inertial factor's bias columns are added into the last keyframe's."""
     N = state.R.shape[0]
     HW = cam.H * cam.W
     n = 15 * N + N * HW
@@ -53,6 +54,12 @@ def full_system(cam, state, graph, opts):
             Jij = imu_mod.jacobian(*args)
             Jf[:, 15 * i:15 * i + 15] = Jij[:, 0:15]
             Jf[:, 15 * j:15 * j + 15] = Jij[:, 15:30]
+            if global_bias:
+                last = 15 * (N - 1) + 9
+                for k in (i, j):
+                    if k != N - 1:
+                        Jf[:, last:last + 6] += Jf[:, 15 * k + 9:15 * k + 15]
+                        Jf[:, 15 * k + 9:15 * k + 15] = 0.0
             L = imu_mod.information(P)
             H += Jf.T @ L @ Jf
             g -= Jf.T @ L @ r
@@ -60,10 +67,14 @@ def full_system(cam, state, graph, opts):
 
 
 def dense_step(cam, state, graph, opts):
-    """Increments (dxi (N,15), dd (N,HW)) from the damped full system."""
+    """Increments (dxi (N,15), dd (N,HW)) from the damped full system.  With
+    one global bias the stacked Jacobian's bias columns of all keyframes are
+    summed into the last keyframe's (the column of the shared unknown) before
+    forming the normal equations."""
     N = state.R.shape[0]
     HW = cam.H * cam.W
-    H, g = full_system(cam, state, graph, opts)
+    glob = opts.bias_global and opts.use_imu and not opts.bias_fixed
+    H, g = full_system(cam, state, graph, opts, glob)
     nx = 15 * N
     Hd = H.copy()
     k = np.arange(nx)
@@ -73,4 +84,7 @@ def dense_step(cam, state, graph, opts):
     act = np.concatenate([active_mask(N, opts).ravel(), np.ones(N * HW, dtype=bool)])
     x = np.zeros(H.shape[0])
     x[act] = np.linalg.solve(Hd[np.ix_(act, act)], g[act])
-    return x[:nx].reshape(N, 15), x[nx:].reshape(N, HW)
+    dxi = x[:nx].reshape(N, 15)
+    if glob:
+        dxi[:, 9:15] = dxi[N - 1, 9:15]
+    return dxi, x[nx:].reshape(N, HW)

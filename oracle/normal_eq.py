@@ -15,7 +15,10 @@ full system before elimination, B_rr += lambda * B_rr on active pose/velocity/
 bias coordinates and C += eta, so the Schur solution equals the damped full
 solve exactly; lambda = eta = 0 is pure Gauss-Newton.  The gauge is fixed by
 removing the pose coordinates of the first ``n_fixed`` keyframes; with the IMU
-off, velocity and bias are removed; with the bias fixed, bias is removed.
+off, velocity and bias are removed; with the bias fixed, bias is removed; with
+one global bias the biases of all keyframes are the one unknown held in the
+last keyframe's slot (fold_global_bias) and the step moves every keyframe's
+bias by its increment.
 Pixels whose C is zero carry no information (their E column is zero too) and
 get dd = 0.
 
@@ -42,6 +45,7 @@ class Options:
     n_fixed: int = 1
     use_imu: bool = True
     bias_fixed: bool = False
+    bias_global: bool = False      # one bias shared by every keyframe (Table 6 (f))
     lm_lambda: float = 1e-4
     depth_eta: float = 1e-8
     z_min: float = 0.1
@@ -104,7 +108,26 @@ def active_mask(N, opts):
         a[:, 6:15] = False
     if opts.bias_fixed:
         a[:, 9:15] = False
+    elif opts.bias_global:
+        a[:-1, 9:15] = False          # the shared bias sits in the last keyframe's slot
     return a
+
+
+def fold_global_bias(neq, N):
+    """One bias for the whole window (Table 6 (f)): every keyframe's bias is
+    the single unknown b, held in the last keyframe's bias slot.  With G the
+    15N x 15N map that copies that slot into every keyframe's bias (and is the
+    identity on poses and velocities), the normal equations become G^T B G and
+    G^T w_xi; E couples depths to poses only and is unchanged.  The random-walk
+    term b_j - b_i is then constant and drops out of the step."""
+    G = np.zeros((15 * N, 15 * N))
+    for a in range(N):
+        for c in range(9):
+            G[15 * a + c, 15 * a + c] = 1.0
+        for c in range(9, 15):
+            G[15 * a + c, 15 * (N - 1) + c] = 1.0
+    return NormalEquations(B=G.T @ neq.B @ G, w_xi=G.T @ neq.w_xi, C=neq.C, w_d=neq.w_d, E=neq.E, cost=neq.cost,
+                           n_valid=neq.n_valid)
 
 
 def linearize(cam, state, graph, opts):

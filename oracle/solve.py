@@ -18,7 +18,7 @@ import numpy as np
 
 from . import imu as imu_mod
 from . import preint, vision
-from .normal_eq import (Camera, Graph, Options, State, linearize, schur_solve,
+from .normal_eq import (Camera, Graph, Options, State, fold_global_bias, linearize, schur_solve,
                         active_mask, NotPositiveDefinite)  # noqa: F401
 from .so3 import Exp, quat_to_R, R_to_quat
 
@@ -85,7 +85,11 @@ def step(cam, state, graph, opts):
     """One damped Gauss-Newton step.  Returns (new_state, report)."""
     neq = linearize(cam, state, graph, opts)
     N = state.R.shape[0]
+    if opts.bias_global and opts.use_imu and not opts.bias_fixed:
+        neq = fold_global_bias(neq, N)
     dxi, dd = schur_solve(neq, opts, N)
+    if opts.bias_global and opts.use_imu and not opts.bias_fixed:
+        dxi[:, 9:15] = dxi[N - 1, 9:15]
     new = retract(state, dxi, dd, opts.d_min)
     F1, _ = cost(cam, new, graph, opts)
     return new, dict(dxi=dxi, dd=dd.reshape(state.d.shape), cost_before=neq.cost,
