@@ -131,7 +131,6 @@ vi_status check_opts(vi_ctx* ctx, const vi_opts* o) {
     return fail(ctx, VI_EINVAL, "z_min must be finite and d_min finite and >= 0");
   if (o->bias_mode != VI_BIAS_PER_KF && o->bias_mode != VI_BIAS_FIXED && o->bias_mode != VI_BIAS_GLOBAL)
     return fail(ctx, VI_EINVAL, "opts.bias_mode must be VI_BIAS_PER_KF, VI_BIAS_FIXED or VI_BIAS_GLOBAL");
-  if (o->bias_mode == VI_BIAS_GLOBAL) return fail(ctx, VI_EUNSUPPORTED, "VI_BIAS_GLOBAL is not supported");
   if (o->invdepth_f32 != 0 && o->invdepth_f32 != 1) return fail(ctx, VI_EINVAL, "opts.invdepth_f32 must be 0 or 1");
   if (o->invdepth_f32 && o->precision != VI_PREC_MIXED)
     return fail(ctx, VI_EINVAL, "float32 inverse depths (opts.invdepth_f32) need VI_PREC_MIXED");
@@ -140,9 +139,10 @@ vi_status check_opts(vi_ctx* ctx, const vi_opts* o) {
 }
 
 // Shape signature: everything the plan depends on (sizes and the frame graphs).
-std::vector<int32_t> plan_signature(const std::vector<WinIn>& wins) {
+std::vector<int32_t> plan_signature(const std::vector<WinIn>& wins, bool bias_global) {
   std::vector<int32_t> s;
   s.push_back((int32_t)wins.size());
+  s.push_back(bias_global ? 1 : 0);
   for (const WinIn& in : wins) {
     s.push_back(in.st->n_kf);
     s.push_back(in.cam->H);
@@ -284,7 +284,7 @@ Envelope tile_envelope(const std::vector<int>& fcs, int n, int nblk) {
   return E;
 }
 
-vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
+vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P, bool bias_global = false) {
   P = Plan();
   const int nw = (int)wins.size();
   // pose-graph adjustment (one window): 7 unknowns per keyframe, 7x7 blocks,
@@ -447,6 +447,10 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P) {
         if (!items[(size_t)a * W.N + b].empty()) cpl.push_back({a, b, pg});
     if (!pg)
       for (int a = 0; a + 1 < W.N; ++a) cpl.push_back({a + 1, a, true});
+    // one bias for the window: it sits in the last keyframe's slot and couples
+    // with every keyframe that an inertial factor touches
+    if (!pg && bias_global)
+      for (int a = 0; a + 2 < W.N; ++a) cpl.push_back({W.N - 1, a, true});
     for (const Coupling& c : cpl) {
       adj[c.a].push_back(c.b);
       adj[c.b].push_back(c.a);
@@ -645,11 +649,11 @@ vi_status ensure_status(vi_ctx* ctx, int n) {
   return VI_OK;
 }
 
-vi_status ensure_plan(vi_ctx* ctx, const std::vector<WinIn>& wins) {
-  std::vector<int32_t> sig = plan_signature(wins);
+vi_status ensure_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, bool bias_global = false) {
+  std::vector<int32_t> sig = plan_signature(wins, bias_global);
   if (ctx->have_plan && sig == ctx->plan_sig) return VI_OK;
   Plan P;
-  vi_status s = build_plan(ctx, wins, P);
+  vi_status s = build_plan(ctx, wins, P, bias_global);
   if (s != VI_OK) return s;
   set_range(P, default_range(P));
   ctx->plan = std::move(P);
@@ -861,7 +865,7 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
   if (!workspace) return fail(ctx, VI_EINVAL, "null workspace");
   if (((uintptr_t)workspace & 255) != 0) return fail(ctx, VI_EINVAL, "workspace must be 256-byte aligned");
   HIPCHK(ctx, hipSetDevice(ctx->device));
-  s = ensure_plan(ctx, wins);
+  s = ensure_plan(ctx, wins, o->use_imu && o->bias_mode == VI_BIAS_GLOBAL);
   if (s != VI_OK) return s;
   Plan& P = ctx->plan;
   size_t need = 0;
@@ -874,7 +878,7 @@ vi_status run(vi_ctx* ctx, const std::vector<WinIn>& wins, const vi_opts* o, int
   Work w = do_carve(P, workspace, nullptr);
   const WarmWork ww = wa ? warm_carve(P, wa->hq, wa->wq, workspace, nullptr) : WarmWork{};
   OptsDev od{o->n_fixed, o->use_imu ? 1 : 0, o->bias_mode == VI_BIAS_FIXED ? 1 : 0, o->precision, o->lm_lambda, o->depth_eta,
-             o->z_min, o->d_min, ctx->tol};
+             o->z_min, o->d_min, ctx->tol, (o->use_imu && o->bias_mode == VI_BIAS_GLOBAL) ? 1 : 0};
   const bool timing = wins[0].rep && wins[0].rep->stage_ms;
 
   // order after the caller's pending work
@@ -1355,7 +1359,7 @@ vi_status warm_windows(vi_ctx* ctx, int32_t n_windows, const vi_window* windows,
       return fail(ctx, VI_EINVAL, "window %d: its %d x %d cell grid does not fit the %d x %d canvas", w,
                   (windows[w].cam.H + 3) / 4, (windows[w].cam.W + 3) / 4, hq, wq);
   }
-  s = ensure_plan(ctx, wins);
+  s = ensure_plan(ctx, wins, o->use_imu && o->bias_mode == VI_BIAS_GLOBAL);
   if (s != VI_OK) return s;
   return refresh_windows(ctx, wins, o->invdepth_f32 != 0);
 }
@@ -1411,7 +1415,8 @@ vi_status vi_warm_features(vi_ctx* ctx, int32_t n_windows, const vi_window* wind
   if (s != VI_OK) return s;
   if ((s = warm_begin(ctx)) != VI_OK) return s;
   OptsDev od{opts->n_fixed, opts->use_imu ? 1 : 0, opts->bias_mode == VI_BIAS_FIXED ? 1 : 0, opts->precision, opts->lm_lambda,
-             opts->depth_eta, opts->z_min, opts->d_min};
+             opts->depth_eta, opts->z_min, opts->d_min, 0.0,
+             (opts->use_imu && opts->bias_mode == VI_BIAS_GLOBAL) ? 1 : 0};
   launch_warm_features(ctx->priv, ctx->plan, ctx->dplan, od, hq, wq, feat, dims);
   return warm_end(ctx);
 }

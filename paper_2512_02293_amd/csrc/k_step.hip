@@ -894,24 +894,30 @@ __device__ __forceinline__ double Mj_at(const double* Rj, int r, int c) {
 // With the camera-IMU extrinsic the unknowns are body increments; the camera
 // moves by K (dtheta, dp) with K = [[R_bc^T, 0], [-R_b [t_bc]x, I]] and
 // R_b = R_c R_bc^T, so the local maps become M K.  Rc: the camera rotation.
+// W is the window in device memory (indexed reads, no private copies).
+__device__ __forceinline__ double skew_at(const double* t, int q, int c) {
+  // [t]x = [[0, -t2, t1], [t2, 0, -t0], [-t1, t0, 0]]
+  if (q == c) return 0.0;
+  const double v = t[3 - q - c];
+  return ((q + 1) % 3 == c) ? -v : v;
+}
+
 __device__ __forceinline__ double K_at(const WinDev& W, const double* Rc, int m, int c) {
   if (m < 3) return c < 3 ? W.Rbc[c * 3 + m] : 0.0;
   if (c >= 3) return (m == c) ? 1.0 : 0.0;
   // -(R_b [t]x)[m-3][c], R_b[p][q] = sum_u Rc[p][u] Rbc[q][u]
-  double tx[9];
-  skew(W.tbc, tx);
   double v = 0.0;
   for (int q = 0; q < 3; ++q) {
     double rb = 0.0;
     for (int u = 0; u < 3; ++u) rb += Rc[(m - 3) * 3 + u] * W.Rbc[q * 3 + u];
-    v += rb * tx[q * 3 + c];
+    v += rb * skew_at(W.tbc, q, c);
   }
   return -v;
 }
 
 __device__ __forceinline__ double Mi_body(const WinDev& W, const double* Rt, const double* Rj, const double* Rci,
                                           int r, int c) {
-  if (!W.ext || c >= 3) return Mi_at(Rt, Rj, r, c);
+  if (c >= 3) return Mi_at(Rt, Rj, r, c);
   double v = 0.0;
   for (int m = 0; m < 6; ++m) v += Mi_at(Rt, Rj, r, m) * K_at(W, Rci, m, c);
   return v;
@@ -919,13 +925,10 @@ __device__ __forceinline__ double Mi_body(const WinDev& W, const double* Rt, con
 
 // M_j K_j = [[-R_bc^T, 0], [R_bc^T [t_bc]x, -R_j^T]] (R_j: the camera rotation)
 __device__ __forceinline__ double Mj_body(const WinDev& W, const double* Rj, int r, int c) {
-  if (!W.ext) return Mj_at(Rj, r, c);
   if (r < 3) return c < 3 ? -W.Rbc[c * 3 + r] : 0.0;
   if (c >= 3) return -Rj[(c - 3) * 3 + (r - 3)];
-  double tx[9];
-  skew(W.tbc, tx);
   double v = 0.0;
-  for (int q = 0; q < 3; ++q) v += W.Rbc[q * 3 + (r - 3)] * tx[q * 3 + c];
+  for (int q = 0; q < 3; ++q) v += W.Rbc[q * 3 + (r - 3)] * skew_at(W.tbc, q, c);
   return v;
 }
 
@@ -1009,6 +1012,7 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
   const int src = blockIdx.x;
   const WinDev& Wsrc = D.win[D.win_of_kf[src]];
   const int nkr = Wsrc.nkr;
+  const bool ext = Wsrc.ext != 0;     // camera-IMU extrinsic: general M_j (else its block structure is used)
   const int e0 = D.src_off[src];
   const int k = D.src_off[src + 1] - e0;
   const int tid = threadIdx.x;
@@ -1026,8 +1030,9 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
   const int T = (ncol + 16) / 16;
   const int ntiles = T * (T + 1) / 2;
   double* Qs = sm;                  // [nq][nq] symmetric
-  double* Mi = Qs + nq * nq;        // [k][36]  M_i of edge s (in body increments: M_i K_i)
-  double* Mj = Mi + 36 * k;         // [k][36]  M_j of edge s (M_j K_j)
+  double* Mi = Qs + nq * nq;        // [k][36]  M_i of edge s (with the extrinsic: M_i K_i)
+  double* Rj = Mi + 36 * k;         // [k][9]   R_j of edge s (M_j = -blockdiag(I, R_j^T))
+  double* Mj = Rj + 9 * k;          // [k][36]  M_j K_j (with the extrinsic only)
   double* Hs = Mj + 36 * k;         // [k][36]  full symmetric
   double* gs = Hs + 36 * k;         // [k][6]   g - y
   double* Wt = gs + 6 * k;          // [k][36]
@@ -1073,11 +1078,22 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
       const int e = D.src_edges[e0 + hs_s];
       const double* Rt = rel + (size_t)e * 12;
       const double* Rjs = Rw + (size_t)D.jj[e] * 9;
-      Mi[tid] = Mi_body(Wsrc, Rt, Rjs, Rw + (size_t)src * 9, rc / 6, rc % 6);
-      Mj[tid] = Mj_body(Wsrc, Rjs, rc / 6, rc % 6);
+      if (!ext) Mi[tid] = Mi_at(Rt, Rjs, rc / 6, rc % 6);
+      if (rc < 9) Rj[hs_s * 9 + rc] = Rjs[rc];
       Hs[tid] = vh;
     }
     if (first && own_g) gs[tid] = vg;
+  }
+  if (ext) {
+    // the maps of body increments, M_i K_i and M_j K_j (a pass of its own,
+    // after the partial sums' registers are free)
+    for (int i = tid; i < 36 * k; i += NT) {
+      const int s2 = i / 36, rc = i % 36;
+      const int e = D.src_edges[e0 + s2];
+      const double* Rjs = Rw + (size_t)D.jj[e] * 9;
+      Mi[i] = Mi_body(Wsrc, rel + (size_t)e * 12, Rjs, Rw + (size_t)src * 9, rc / 6, rc % 6);
+      Mj[i] = Mj_body(Wsrc, Rjs, rc / 6, rc % 6);
+    }
   }
   __syncthreads();
   for (int i = tid; i < k * 6; i += NT) gs[i] -= Qs[ncol * nq + i];
@@ -1097,39 +1113,71 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
     }
     Wt[i] = v;
   }
-  // Z_s+1,t+1 = M_j,s^T X_st M_j,t (M_j has a zero 3x3 block: zero entries skipped)
+  // Z_s+1,t+1 = M_j,s^T X_st M_j,t; without the extrinsic M_j = -P with
+  // P = blockdiag(I, R_j^T): [[X11, X12 R_t^T], [R_s X21, R_s X22 R_t^T]]
   for (int i = tid; i < k * k * 36; i += NT) {
     const int st = i / 36, s2 = st / k, t = st % k, a = (i % 36) / 6, b = i % 6;
     const double* Qb = Qs + (6 * s2) * nq + 6 * t;
     const bool diag = s2 == t;
     const double* Hb = Hs + s2 * 36;
-    const double* Ms = Mj + s2 * 36;
-    const double* Mt = Mj + t * 36;
+    auto X = [&](int m, int n) { return (diag ? Hb[m * 6 + n] : 0.0) - Qb[m * nq + n]; };
     double v = 0.0;
+    if (ext) {
+      // general M_j (its upper-right 3x3 block is zero: zero entries skipped)
+      const double* Ms = Mj + s2 * 36;
+      const double* Mt = Mj + t * 36;
 #pragma unroll
-    for (int m = 0; m < 6; ++m) {
-      const double ma = Ms[m * 6 + a];
-      if (ma == 0.0) continue;
-      double u = 0.0;
+      for (int m = 0; m < 6; ++m) {
+        const double ma = Ms[m * 6 + a];
+        if (ma == 0.0) continue;
+        double u = 0.0;
 #pragma unroll
-      for (int n = 0; n < 6; ++n) {
-        const double mb = Mt[n * 6 + b];
-        if (mb == 0.0) continue;
-        u += ((diag ? Hb[m * 6 + n] : 0.0) - Qb[m * nq + n]) * mb;
+        for (int n = 0; n < 6; ++n) {
+          const double mb = Mt[n * 6 + b];
+          if (mb != 0.0) u += X(m, n) * mb;
+        }
+        v += ma * u;
       }
-      v += ma * u;
+    } else {
+      const double* Rs = Rj + s2 * 9;
+      const double* Rt = Rj + t * 9;
+      if (a < 3 && b < 3) {
+        v = X(a, b);
+      } else if (a < 3) {
+#pragma unroll
+        for (int n = 0; n < 3; ++n) v += X(a, 3 + n) * Rt[(b - 3) * 3 + n];
+      } else if (b < 3) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) v += Rs[(a - 3) * 3 + m] * X(3 + m, b);
+      } else {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          double u = 0.0;
+#pragma unroll
+          for (int n = 0; n < 3; ++n) u += X(3 + m, 3 + n) * Rt[(b - 3) * 3 + n];
+          v += Rs[(a - 3) * 3 + m] * u;
+        }
+      }
     }
     Zs[(size_t)((s2 + 1) * K1 + t + 1) * 36 + a * 6 + b] = v;
   }
   __syncthreads();
-  // Z_0,t+1 = W_t M_j,t and its transpose; Z_00 = sum_t W_t M_i,t
+  // Z_0,t+1 = W_t M_j,t (= -W_t P_t without the extrinsic) and its transpose;
+  // Z_00 = sum_t W_t M_i,t
   for (int i = tid; i < k * 36; i += NT) {
     const int t = i / 36, a = (i % 36) / 6, b = i % 6;
     const double* Wb = Wt + t * 36 + a * 6;
-    const double* Mt = Mj + t * 36;
     double v = 0.0;
+    if (ext) {
+      const double* Mt = Mj + t * 36;
 #pragma unroll
-    for (int n = 0; n < 6; ++n) v += Wb[n] * Mt[n * 6 + b];
+      for (int n = 0; n < 6; ++n) v += Wb[n] * Mt[n * 6 + b];
+    } else if (b < 3) {
+      v = -Wb[b];
+    } else {
+      const double* Rt = Rj + t * 9;
+      v = -(Wb[3] * Rt[(b - 3) * 3 + 0] + Wb[4] * Rt[(b - 3) * 3 + 1] + Wb[5] * Rt[(b - 3) * 3 + 2]);
+    }
     Zs[(size_t)(0 * K1 + t + 1) * 36 + a * 6 + b] = v;
     Zs[(size_t)((t + 1) * K1 + 0) * 36 + b * 6 + a] = v;
   }
@@ -1174,7 +1222,7 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
         zb += scr[k * 36 + 2 * (s2 * 6 + a)];
         zv += scr[k * 36 + 2 * (s2 * 6 + a) + 1];
       }
-    } else {
+    } else if (ext) {
       // diag(M_j^T H M_j) and M_j^T (g - y)
       const int s2 = ra - 1;
       const double* H = Hs + s2 * 36;
@@ -1187,6 +1235,25 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
         for (int nn = 0; nn < 6; ++nn) hm += H[m * 6 + nn] * M[nn * 6 + a];
         zb += M[m * 6 + a] * hm;
         zv += M[m * 6 + a] * g[m];
+      }
+    } else {
+      // M_j = -P: diag(P^T H P) and -P^T (g - y)
+      const int s2 = ra - 1;
+      const double* H = Hs + s2 * 36;
+      const double* g = gs + s2 * 6;
+      if (a < 3) {
+        zb = H[a * 6 + a];
+        zv = -g[a];
+      } else {
+        const double* R = Rj + s2 * 9 + (a - 3) * 3;   // row a-3 of R_j: P[3+m][a] = R_j[a-3][m]
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          double hm = 0.0;
+#pragma unroll
+          for (int nn = 0; nn < 3; ++nn) hm += H[(3 + m) * 6 + 3 + nn] * R[nn];
+          zb += R[m] * hm;
+          zv -= R[m] * g[3 + m];
+        }
       }
     }
     ZBs[i] = zb;
@@ -1201,11 +1268,63 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
 // (so the Cholesky forward pass produces L^-1 s in that row), and whose
 // padding is the identity.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool coord_active(const OptsDev& o, int a, int ra) {
+__device__ __forceinline__ bool coord_active(const OptsDev& o, int a, int ra, int N) {
   if (ra < 6) return a >= o.n_fixed;
   if (!o.use_imu) return false;
-  if (o.bias_fixed && ra >= 9) return false;
+  if (ra >= 9 && o.bias_fixed) return false;
+  if (ra >= 9 && o.bias_global) return a == N - 1;   // the shared bias sits in the last keyframe's slot
   return true;
+}
+
+// inertial part of the entry ((a, ra), (b, cb)) of B: the blocks of the
+// factors (a - 1, a) and (a, a + 1) of the window (Hw: [F][30][30])
+__device__ __forceinline__ double imu_hess(const double* Hw, int N, int a, int ra, int b, int cb) {
+  double v = 0.0;
+  if (a == b) {
+    if (a > 0) v += Hw[(size_t)(a - 1) * 900 + (15 + ra) * 30 + 15 + cb];
+    if (a < N - 1) v += Hw[(size_t)a * 900 + ra * 30 + cb];
+  } else if (b == a + 1) {
+    v += Hw[(size_t)a * 900 + ra * 30 + 15 + cb];
+  } else if (a == b + 1) {
+    v += Hw[(size_t)b * 900 + (15 + ra) * 30 + cb];
+  }
+  return v;
+}
+
+// inertial part of w_xi at (b, cb) (gw: [F][30])
+__device__ __forceinline__ double imu_grad(const double* gw, int N, int b, int cb) {
+  double v = 0.0;
+  if (b > 0) v += gw[(size_t)(b - 1) * 30 + 15 + cb];
+  if (b < N - 1) v += gw[(size_t)b * 30 + cb];
+  return v;
+}
+
+// The same entries with one bias for the window (Table 6 (f)): the bias
+// coordinates of every keyframe are the one unknown in the last keyframe's
+// slot, so the folded system G^T B G sums an entry over the keyframes whose
+// bias it touches (those of the inertial factors next to the other index)
+__device__ double imu_hess_folded(const double* Hw, int N, int a, int ra, int b, int cb, bool global) {
+  const bool ga = global && ra >= 9, gb = global && cb >= 9;
+  if (!ga && !gb) return imu_hess(Hw, N, a, ra, b, cb);
+  double v = 0.0;
+  if (ga && gb) {
+    for (int f = 0; f < N - 1; ++f) {
+      const double* H = Hw + (size_t)f * 900;
+      v += H[ra * 30 + cb] + H[ra * 30 + 15 + cb] + H[(15 + ra) * 30 + cb] + H[(15 + ra) * 30 + 15 + cb];
+    }
+  } else if (gb) {
+    for (int b2 = max(a - 1, 0); b2 <= min(a + 1, N - 1); ++b2) v += imu_hess(Hw, N, a, ra, b2, cb);
+  } else {
+    for (int a2 = max(b - 1, 0); a2 <= min(b + 1, N - 1); ++a2) v += imu_hess(Hw, N, a2, ra, b, cb);
+  }
+  return v;
+}
+
+__device__ double imu_grad_folded(const double* gw, int N, int b, int cb, bool global) {
+  if (!(global && cb >= 9)) return imu_grad(gw, N, b, cb);
+  double v = 0.0;
+  for (int b2 = 0; b2 < N; ++b2) v += imu_grad(gw, N, b2, cb);
+  return v;
 }
 
 __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, const double* __restrict__ ZB,
@@ -1229,7 +1348,7 @@ __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, c
   if (r < n && c < n) {
     // block positions -> keyframes (the window's order of the reduced system)
     const int a = D.kf_at[W.kf_base + r / 15], ra = r % 15, b = D.kf_at[W.kf_base + c / 15], cb = c % 15;
-    if (coord_active(o, a, ra) && coord_active(o, b, cb)) {
+    if (coord_active(o, a, ra, N) && coord_active(o, b, cb, N)) {
       double bd = 0.0;
       if (ra < 6 && cb < 6) {
         // the pair blocks of (a, b) in list order, eight gathers in flight
@@ -1257,15 +1376,7 @@ __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, c
         }
       }
       if (o.use_imu) {
-        double vi = 0.0;
-        if (a == b) {
-          if (a > 0) vi += Hw[(size_t)(a - 1) * 900 + (15 + ra) * 30 + 15 + cb];
-          if (a < N - 1) vi += Hw[(size_t)a * 900 + ra * 30 + cb];
-        } else if (b == a + 1) {
-          vi += Hw[(size_t)a * 900 + ra * 30 + 15 + cb];
-        } else if (a == b + 1) {
-          vi += Hw[(size_t)b * 900 + (15 + ra) * 30 + cb];
-        }
+        const double vi = imu_hess_folded(Hw, N, a, ra, b, cb, o.bias_global != 0);
         val += vi;
         if (r == c) bd += vi;
       }
@@ -1278,7 +1389,7 @@ __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, c
     val = (r == c) ? 1.0 : 0.0;
   } else if (r == npad && c < n) {
     const int b = D.kf_at[W.kf_base + c / 15], cb = c % 15;
-    if (coord_active(o, b, cb)) {
+    if (coord_active(o, b, cb, N)) {
       if (cb < 6) {
         const int p0 = poff[b * N + b], p1 = poff[b * N + b + 1];
         for (int it0 = p0; it0 < p1; it0 += 8) {
@@ -1290,10 +1401,7 @@ __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, c
             if (it0 + u < p1) val += v[u];
         }
       }
-      if (o.use_imu) {
-        if (b > 0) val += gw[(size_t)(b - 1) * 30 + 15 + cb];
-        if (b < N - 1) val += gw[(size_t)b * 30 + cb];
-      }
+      if (o.use_imu) val += imu_grad_folded(gw, N, b, cb, o.bias_global != 0);
     }
     if (!isfinite(val)) set_status(st + w, VI_ENONFINITE, n + 15 * b + cb);
   }
@@ -1317,23 +1425,29 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
                                                          DevStatus* st) {
   __shared__ double u[kMaxOutDegree * 6];
   __shared__ double rel_s[kMaxOutDegree * 12];
+  __shared__ double xcam[(kMaxOutDegree + 1) * 6];
   const int tid = threadIdx.x;
   if ((int)blockIdx.y >= N) {
     const int w = blockIdx.y - N;
     if (blockIdx.x != 0 || st[w].code != 0 || st[w].conv != 0) return;
     const WinDev& W = D.win[w];
     const double* xw = x + W.x_off;
+    // one bias for the window: its increment (the last keyframe's slot) moves every keyframe's
+    const double* dxb = o.bias_global ? xw + (size_t)D.kf_pos[W.kf_base + W.N - 1] * 15 : nullptr;
     for (int t = tid; t < W.N; t += 256) {
       const double* dx = xw + (size_t)D.kf_pos[W.kf_base + t] * 15;
+      const double* db = dxb ? dxb + 9 : dx + 9;
       double* q = W.pose + (size_t)t * 7;
       quat_retract(q + 3, dx);
       for (int k = 0; k < 3; ++k) {
         q[k] += dx[3 + k];
         W.vel[(size_t)t * 3 + k] += dx[6 + k];
       }
-      for (int k = 0; k < 6; ++k) W.bias[(size_t)t * 6 + k] += dx[9 + k];
-      if (W.rep_dxi)
-        for (int k = 0; k < 15; ++k) W.rep_dxi[(size_t)t * 15 + k] = dx[k];
+      for (int k = 0; k < 6; ++k) W.bias[(size_t)t * 6 + k] += db[k];
+      if (W.rep_dxi) {
+        for (int k = 0; k < 9; ++k) W.rep_dxi[(size_t)t * 15 + k] = dx[k];
+        for (int k = 0; k < 6; ++k) W.rep_dxi[(size_t)t * 15 + 9 + k] = db[k];
+      }
     }
     if (tid == 0) st[w].iters += 1;
     return;
@@ -1348,16 +1462,30 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
   const int k = D.src_off[src + 1] - e0;
   const double* xw = x + W.x_off;
   for (int i = tid; i < 12 * k; i += 256) rel_s[i] = rel[(size_t)D.src_edges[e0 + i / 12] * 12 + i % 12];
+  if (W.ext) {
+    // the body increments of the source (slot 0) and of the targets as
+    // camera increments, K x (W.ext is uniform over the workgroup)
+    const WinDev& Wg = D.win[w];
+    for (int i = tid; i < 6 * (k + 1); i += 256) {
+      const int s = i / 6, c = i % 6;
+      const int kf = s == 0 ? src : D.jj[D.src_edges[e0 + s - 1]];
+      const double* Rc = Rw + (size_t)kf * 9;
+      const double* xb = xw + (size_t)D.kf_pos[kf] * 15;
+      double v = 0.0;
+      for (int m = 0; m < 6; ++m) v += K_at(Wg, Rc, c, m) * xb[m];
+      xcam[i] = v;
+    }
+    __syncthreads();
+  }
   for (int i = tid; i < 6 * k; i += 256) {
     const int s = i / 6, c = i % 6;
     const int e = D.src_edges[e0 + s];
     const double* Rt = rel + (size_t)e * 12;
     const double* Rj = Rw + (size_t)D.jj[e] * 9;
-    const double* xi = xw + (size_t)D.kf_pos[src] * 15;
-    const double* xj = xw + (size_t)D.kf_pos[D.jj[e]] * 15;
+    const double* xi = W.ext ? xcam : xw + (size_t)D.kf_pos[src] * 15;
+    const double* xj = W.ext ? xcam + 6 * (s + 1) : xw + (size_t)D.kf_pos[D.jj[e]] * 15;
     double v = 0.0;
-    const double* Rci = Rw + (size_t)src * 9;
-    for (int m = 0; m < 6; ++m) v += Mi_body(W, Rt, Rj, Rci, c, m) * xi[m] + Mj_body(W, Rj, c, m) * xj[m];
+    for (int m = 0; m < 6; ++m) v += Mi_at(Rt, Rj, c, m) * xi[m] + Mj_at(Rj, c, m) * xj[m];
     u[i] = v;
   }
   __syncthreads();
@@ -1698,7 +1826,7 @@ static VisKernel vis_kernel(int kmax) {
 }
 static size_t local_lds(int kmax) {
   const size_t k = kmax, nq = 6 * k + 1;
-  return sizeof(double) * std::max<size_t>(nq * nq + 4 * 36 * k + 6 * k, 2 * kLocalThreads);
+  return sizeof(double) * std::max<size_t>(nq * nq + 4 * 36 * k + 9 * k + 6 * k, 2 * kLocalThreads);
 }
 
 void launch_reset_status(hipStream_t s, DevStatus* st, int n) {

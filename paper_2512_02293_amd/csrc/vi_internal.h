@@ -146,6 +146,7 @@ struct OptsDev {
   int n_fixed, use_imu, bias_fixed, precision;
   double lambda, eta, z_min, d_min;
   double tol;        // relative cost decrease below which a window stops (0: never)
+  int bias_global;   // one bias per window, in the last keyframe's slot (with use_imu)
 };
 
 // learned warm-start network (k_wnet.hip)

@@ -83,8 +83,10 @@ def test_batched_equals_single_window_solves(ctx, n_win):
               f"{rep['costs'][-1]:.4e}")
         assert reps_b[w]["iters_done"] == iters
         assert reps_b[w]["n_valid"] == rep["n_valid"]
-        assert np.allclose(reps_b[w]["costs"], rep["costs"], rtol=1e-12, atol=0)
-        _close(states_b[w], _state(dp), 1e-12)
+        # the batch sizes its pixel ranges for all windows together, a lone
+        # window for itself: the same sums grouped differently (rounding only)
+        assert np.allclose(reps_b[w]["costs"], rep["costs"], rtol=1e-11, atol=0)
+        _close(states_b[w], _state(dp), 1e-11)
 
 
 def test_batched_matches_oracle(ctx):

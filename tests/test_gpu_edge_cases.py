@@ -14,6 +14,7 @@
 * A camera-IMU extrinsic T_bc away from the identity.
 * Float32 inverse-depth maps in mixed precision (one step against the
   oracle, and a solve against the same solve on float64 maps).
+* One IMU bias shared by the window (Table 6 (f)).
 * Non-finite inputs: VI_ENONFINITE and the state left bit for bit.
 * The 64-window batch in mixed precision, every window against the oracle.
 
@@ -57,6 +58,7 @@ def _bopts(precision=0, **kw):
     from paper_2512_02293_amd import binding
     o = ne.Options(**kw)
     return o, binding.make_opts(n_fixed=o.n_fixed, use_imu=o.use_imu, bias_fixed=o.bias_fixed,
+                                bias_mode=binding.VI_BIAS_GLOBAL if o.bias_global else None,
                                 lm_lambda=o.lm_lambda, depth_eta=o.depth_eta, z_min=o.z_min, d_min=o.d_min,
                                 precision=precision)
 
@@ -204,6 +206,21 @@ def test_float32_inverse_depths_over_a_solve(ctx):
         dp = binding.DeviceProblem(prob, invdepth_f32=True)
         ctx.solve(dp.cam, dp.pose, dp.vel, dp.bias, dp.invdepth, dp.ii, dp.jj, dp.target, dp.weight, imu, o, 1, ws)
     assert ei.value.code == binding.VI_EINVAL
+
+
+@pytest.mark.parametrize("precision,cfg_name", [(0, "ragged"), (1, "ragged"), (0, "window")])
+def test_step_with_one_global_bias(ctx, precision, cfg_name):
+    """One IMU bias for the whole window (Table 6 (f)): the shared unknown in
+    the last keyframe's slot couples with every keyframe (an arrow in the
+    reduced system); every keyframe's bias moves by its increment."""
+    cfg = synth.SceneConfig(n_kf=7, H=37, W=53, k_out=4) if cfg_name == "ragged" else synth.config_window()
+    prob = synth.make_problem(cfg, 91)
+    prob.bias[:] = np.array([0.002, -0.001, 0.003, 0.02, -0.01, 0.03])
+    if precision == 0:
+        rep, orep = _step_vs_oracle(ctx, prob, bias_global=True)
+    else:
+        rep, orep = _step_vs_oracle(ctx, prob, precision=1, tol_group=1e-4, tol_depth=1e-3, bias_global=True)
+    assert np.all(orep["dxi"][:, 9:15] == orep["dxi"][-1, 9:15])
 
 
 @pytest.mark.parametrize("what", ["target_nan", "weight_nan", "target_inf", "invdepth_nan"])
