@@ -1,7 +1,7 @@
 """Train the warm-start network on windows the solver itself generates and
 solves, then compare time to tolerance against plain Gauss-Newton.
 
-    python -m paper_2512_02293_amd.train_warm [--windows 20000] [--epochs 8] [--out PATH]
+    python -m paper_2512_02293_amd.train_warm [--windows 20000] [--epochs 40] [--out PATH]
 
 Needs a GPU.  Prints one progress line per dataset chunk and per epoch, then a
 JSON summary line (loss history, iteration counts and times to tolerance of
@@ -18,7 +18,7 @@ import numpy as np
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--windows", type=int, default=20000)
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--epochs", type=int, default=40)   # the committed parameters were trained with 40
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--workers", type=int, default=16)
