@@ -40,13 +40,14 @@ def study_opts():
 PARAMS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "warm_params.npy")
 
 
-def _make(seed):
-    return synth.make_problem(synth.config_random_window(seed, smooth_depth_init=True), seed)
+def _make(seed, smooth=True):
+    return synth.make_problem(synth.config_random_window(seed, smooth_depth_init=smooth), seed)
 
 
-def eval_windows(n=64):
-    """The evaluation windows of the time-to-tolerance comparison."""
-    return [_make(4000 + w) for w in range(n)]
+def eval_windows(n=64, smooth=True):
+    """The evaluation windows of the time-to-tolerance comparison (smooth=False:
+    the batched windows' own per-pixel initial depth error)."""
+    return [_make(4000 + w, smooth) for w in range(n)]
 
 
 def generate(seeds, workers=None):
@@ -312,7 +313,32 @@ def time_to_tol(ctx, net, probs, opts, max_iters=REF_ITERS, rel_tol=1e-6, reps=3
         t_win_plain += timed(lambda: gn([d], [im], kp), [d])
         warm([d], [im], kw)
         t_win_warm += timed(lambda: warm([d], [im], kw), [d])
+    # each window alone with the stopping rule instead of a known iteration
+    # count: up to K iterations, frozen once its relative cost decrease falls
+    # to stop_tol (what a sliding-window solver without a reference run does)
+    t_ws_plain = t_ws_warm = 0.0
+    ws_reached_plain = ws_reached_warm = 0
+    ws_steps_plain = ws_steps_warm = 0
+    ctx.set_tolerance(stop_tol)
+    try:
+        for d, im, t in zip(dps, imus, target):
+            reset([d])
+            r = ctx.solve_batched([d], [im], opts, K, ws)[0]
+            ws_reached_plain += int(r["cost_after"] <= t)
+            ws_steps_plain += int(r["iters_done"])
+            t_ws_plain += timed(lambda: gn([d], [im], K), [d])
+            reset([d])
+            r = ctx.solve_warm([d], [im], opts, net.params, K, ws)[0]
+            ws_reached_warm += int(r["cost_after"] <= t)
+            ws_steps_warm += int(r["iters_done"])
+            t_ws_warm += timed(lambda: warm([d], [im], K), [d])
+    finally:
+        ctx.set_tolerance(0.0)
+    per_window_stop = dict(tol=stop_tol, max_iters=K, ms_plain_total=1e3 * t_ws_plain,
+                           ms_warm_total=1e3 * t_ws_warm, steps_plain=ws_steps_plain, steps_warm=ws_steps_warm,
+                           reached_plain=ws_reached_plain, reached_warm=ws_reached_warm)
     return dict(k_plain=k_plain, k_warm=k_warm, accepted=accepted, reached=reached, K_plain=K_plain, K_warm=K_warm,
                 ms_plain=1e3 * t_batch_plain, ms_warm=1e3 * t_batch_warm,
                 ms_plain_per_window_total=1e3 * t_win_plain, ms_warm_per_window_total=1e3 * t_win_warm,
-                final_plain=[c[-1] for c in plain_costs], final_warm=[c[-1] for c in warm_costs], stop=stop)
+                final_plain=[c[-1] for c in plain_costs], final_warm=[c[-1] for c in warm_costs], stop=stop,
+                per_window_stop=per_window_stop)
