@@ -504,6 +504,15 @@ __device__ __forceinline__ void lds_load16(const double* p, double (&v)[16]) {
   }
 }
 
+// an empty asm that takes the 16 values as in-out operands: every load and
+// product that forms them is issued before it, and nothing that uses them
+// moves above it (one LDS wait per Gram tile instead of one per 4 MFMAs)
+__device__ __forceinline__ void pin16(float (&v)[16]) {
+  asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7]),
+               "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]), "+v"(v[14]), "+v"(v[15]));
+}
+__device__ __forceinline__ void pin16(double (&)[16]) {}
+
 // per-lane sums of one edge over the chunks of a block: local Hessian (upper
 // triangle, row-major, 21 entries; entry (3, 4) stays zero) and gradient (6)
 template <typename R>
@@ -704,6 +713,25 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
       }
     }
   };
+  // FP32 with at most two edges per wave: the relative transforms of this
+  // wave's edges stay in registers for the whole range (else read from LDS)
+  constexpr bool kRegRel = !kF64 && SLOTS <= 2;
+  R rtv[kRegRel ? SLOTS : 1][12];
+  if constexpr (kRegRel) {
+#pragma unroll
+    for (int u = 0; u < SLOTS; ++u) {
+      const int sl = min(wave + kVisWaves * u, k - 1);
+#pragma unroll
+      for (int q = 0; q < 12; ++q) rtv[u][q] = rel_s[sl * 12 + q];
+    }
+  }
+  // Gram tiles of this wave (uniform; FP32: found once for the range)
+  int tI[TS], tJ[TS];
+#pragma unroll
+  for (int u = 0; u < TS; ++u) {
+    tI[u] = tJ[u] = 0;
+    if (!kF64 && wave + kVisWaves * u < ntiles) tile_ij(wave + kVisWaves * u, tI[u], tJ[u]);
+  }
   // this lane's pixel (column x, row y) in the current chunk
   int xq = (p_beg + lane) % W.W, yq = (p_beg + lane) / W.W;
   const int g4 = lane >> 4, m16 = lane & 15;
@@ -727,9 +755,14 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
 #pragma unroll
     for (int u = 0; u < SLOTS; ++u) {
       const int s = wave + kVisWaves * u;
-      if (s < k)
-        vis_pair<R, LDC>(rel_s + s * 12, fx, fy, cx, cy, zmin, qx, qy, d, inpx, ctx_[u], cty[u], cwx[u], cwy[u],
-                         acc[u], E + 6 * s * LDC + lane, Cp, Wp, cst, nv);
+      if (s < k) {
+        if constexpr (kRegRel)
+          vis_pair<R, LDC>(rtv[u], fx, fy, cx, cy, zmin, qx, qy, d, inpx, ctx_[u], cty[u], cwx[u], cwy[u],
+                           acc[u], E + 6 * s * LDC + lane, Cp, Wp, cst, nv);
+        else
+          vis_pair<R, LDC>(rel_s + s * 12, fx, fy, cx, cy, zmin, qx, qy, d, inpx, ctx_[u], cty[u], cwx[u], cwy[u],
+                           acc[u], E + 6 * s * LDC + lane, Cp, Wp, cst, nv);
+      }
     }
     cost += (double)cst;
     nval += (double)nv;
@@ -783,15 +816,19 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
       for (int u = 0; u < TS; ++u) {
         const int t = wave + kVisWaves * u;
         if (t < ntiles) {
-          int I, J;
-          tile_ij(t, I, J);
           // all 32 operands of the tile loaded first, B scaled by 1/C into its
           // own registers, then 16 back-to-back MFMAs
+          int I = tI[u], J = tJ[u];
+          if constexpr (kF64) tile_ij(t, I, J);
           R a[16], b[16];
           lds_load16(E + (16 * I + m16) * LDC + 16 * g4, a);
           lds_load16(E + (16 * J + m16) * LDC + 16 * g4, b);
 #pragma unroll
           for (int kk = 0; kk < 16; ++kk) b[kk] *= inv[kk];
+          if constexpr (!kF64) {
+            pin16(a);
+            pin16(b);
+          }
           if constexpr (kF64) {
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk)
