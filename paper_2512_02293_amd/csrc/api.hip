@@ -597,7 +597,6 @@ Work do_carve(const Plan& P, void* base, size_t* bytes) {
   w.sync = c.take<int32_t>(4);
   w.Linv = c.take<double>(P.Linv_size);
   w.x = c.take<double>(P.x_size);
-  w.dd = c.take<double>((size_t)P.pix_total);
   w.trace = c.take<double>((size_t)P.n_win * kTraceLen);
   w.rcost = c.take<double>((size_t)std::max(P.R, 1));
   if (bytes) *bytes = c.off;

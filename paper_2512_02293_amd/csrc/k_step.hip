@@ -1458,8 +1458,7 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
                                                          const double* __restrict__ rel,
                                                          const double* __restrict__ Cd,
                                                          const double* __restrict__ wd,
-                                                         const double* __restrict__ x, double* __restrict__ dd_ws,
-                                                         DevStatus* st) {
+                                                         const double* __restrict__ x, DevStatus* st) {
   __shared__ double u[kMaxOutDegree * 6];
   __shared__ double rel_s[kMaxOutDegree * 12];
   __shared__ double xcam[(kMaxOutDegree + 1) * 6];
@@ -1564,7 +1563,6 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
   }
   dep_store(W, pl, fmax(d + ddv, o.d_min));
   if (W.rep_dd) W.rep_dd[pl] = ddv;
-  else dd_ws[pi] = ddv;
 }
 
 __global__ void k_reset_status(DevStatus* st, int n) {
@@ -1941,7 +1939,7 @@ void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, 
   done(kStChol);
   auto kbs = (o.precision == VI_PREC_MIXED) ? k_backsub_retract<float> : k_backsub_retract<double>;
   hipLaunchKernelGGL(kbs, dim3((P.hw_max + 255) / 256, N + P.n_win), dim3(256), 0, s, o, N, D, w.Rw,
-                     w.rel, w.Cd, w.wd, w.x, w.dd, st);
+                     w.rel, w.Cd, w.wd, w.x, st);
   done(kStBacksub);
 }
 

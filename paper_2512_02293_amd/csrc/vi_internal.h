@@ -137,7 +137,6 @@ struct Work {
   int32_t* sync;     // [0] ticket counter, [1] abort flag
   double* Linv;      // per window [nblk][NB*NB]
   double* x;         // per window [npad]
-  double* dd;        // [pix_total]
   double* trace;     // [n_win][kTraceLen]  cost, n_valid per slot
   double* rcost;     // [R]  relative-pose factor costs (pose-graph adjustment)
 };
