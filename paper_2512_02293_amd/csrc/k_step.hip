@@ -1000,25 +1000,26 @@ __device__ void cost_reduce_block(const WinDev& W, int w, int ncost, int range_p
   }
 }
 
-// Sum of n partials p[0], p[stride], ... in a fixed order, with U loads in
-// flight per step (the loads are clamped in range and masked, so they can all
-// be issued before the first one returns).
-template <int U>
-__device__ __forceinline__ double sum_partials(const double* __restrict__ p, size_t stride, int n) {
-  double acc[U];
+// Sums of n partials for NS streams at once, s-th stream p[s][0], p[s][stride[s]],
+// ..., each in order of its index: U partials of every stream are loaded per
+// round (clamped in range and masked), so that NS x U loads are in flight
+// before the first one returns.
+template <int U, int NS>
+__device__ __forceinline__ void sum_partials(const double* const (&p)[NS], const size_t (&stride)[NS], int n,
+                                             double (&out)[NS]) {
 #pragma unroll
-  for (int u = 0; u < U; ++u) acc[u] = 0.0;
+  for (int q = 0; q < NS; ++q) out[q] = 0.0;
   for (int r0 = 0; r0 < n; r0 += U) {
-    double v[U];
+    double v[NS][U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = p[(size_t)min(r0 + u, n - 1) * stride];
+    for (int q = 0; q < NS; ++q)
 #pragma unroll
-    for (int u = 0; u < U; ++u) acc[u] += (r0 + u < n) ? v[u] : 0.0;
+      for (int u = 0; u < U; ++u) v[q][u] = p[q][(size_t)min(r0 + u, n - 1) * stride[q]];
+#pragma unroll
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+      for (int u = 0; u < U; ++u) out[q] += (r0 + u < n) ? v[q][u] : 0.0;
   }
-  double s = 0.0;
-#pragma unroll
-  for (int u = 0; u < U; ++u) s += acc[u];
-  return s;
 }
 
 constexpr int kLocalThreads = 1024;
@@ -1085,17 +1086,35 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
   // and then writes them to LDS.  One pass covers up to 12 edges.
   const bool own_h = tid < k * 36, own_g = tid < k * 6;
   for (int base = 0; base < nent; base += 4 * NT) {
-    double vq[4], vh = 0.0, vg = 0.0;
-#pragma unroll
-    for (int h = 0; h < 4; ++h) vq[h] = sum_partials<8>(gp + min(base + tid + h * NT, nent - 1), gstride, nkr);
     const bool first = base == 0;
+    // streams: four Gram entries, one edge-Hessian entry, one gradient entry
+    // (the last two only in the first pass; else they repeat the first stream)
+    const double* ps[6];
+    size_t strd[6];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      ps[h] = gp + min(base + tid + h * NT, nent - 1);
+      strd[h] = gstride;
+    }
+    ps[4] = ps[5] = ps[0];
+    strd[4] = strd[5] = gstride;
     if (first && own_h) {
       const int rc = tid % 36, r = rc / 6, c = rc % 6;
       const int a = min(r, c), b = max(r, c);
       const int qq = a * 6 - a * (a - 1) / 2 + (b - a);
-      vh = sum_partials<8>(hpart + (size_t)(e0 + tid / 36) * nkr_max * 32 + qq, 32, nkr);
+      ps[4] = hpart + (size_t)(e0 + tid / 36) * nkr_max * 32 + qq;
+      strd[4] = 32;
     }
-    if (first && own_g) vg = sum_partials<8>(hpart + (size_t)(e0 + tid / 6) * nkr_max * 32 + 21 + tid % 6, 32, nkr);
+    if (first && own_g) {
+      ps[5] = hpart + (size_t)(e0 + tid / 6) * nkr_max * 32 + 21 + tid % 6;
+      strd[5] = 32;
+    }
+    double sums[6];
+    sum_partials<4, 6>(ps, strd, nkr, sums);
+    double vq[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) vq[h] = sums[h];
+    const double vh = sums[4], vg = sums[5];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const int i = base + tid + h * NT;
@@ -1152,8 +1171,15 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
   }
   // Z_s+1,t+1 = M_j,s^T X_st M_j,t; without the extrinsic M_j = -P with
   // P = blockdiag(I, R_j^T): [[X11, X12 R_t^T], [R_s X21, R_s X22 R_t^T]]
-  for (int i = tid; i < k * k * 36; i += NT) {
-    const int st = i / 36, s2 = st / k, t = st % k, a = (i % 36) / 6, b = i % 6;
+  // Four waves per quadrant of the 6x6 blocks (a < 3 or not, b < 3 or not), so
+  // that the lanes of a wave take the same branch below: in each quadrant 28
+  // groups of 9 lanes (one lane per entry of the 3x3 quadrant) walk the block
+  // pairs st = s k + t, 28 apart (no integer division in the walk)
+  static_assert(NT == 1024, "four waves per quadrant");
+  const int quad = tid >> 8, lt = tid & 255, grp = lt / 9, ab = lt % 9;
+  const int a = ab / 3 + 3 * (quad >> 1), b = ab % 3 + 3 * (quad & 1);
+  int s2 = grp / k, t = grp % k;
+  for (int st = grp; grp < 28 && st < k * k; st += 28) {
     const double* Qb = Qs + (6 * s2) * nq + 6 * t;
     const bool diag = s2 == t;
     const double* Hb = Hs + s2 * 36;
@@ -1197,6 +1223,11 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(int N, int nkr_max, int
       }
     }
     Zs[(size_t)((s2 + 1) * K1 + t + 1) * 36 + a * 6 + b] = v;
+    t += 28;
+    while (t >= k) {
+      t -= k;
+      ++s2;
+    }
   }
   __syncthreads();
   // Z_0,t+1 = W_t M_j,t (= -W_t P_t without the extrinsic) and its transpose;
