@@ -511,7 +511,9 @@ __device__ __forceinline__ void pin16(float (&v)[16]) {
   asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7]),
                "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]), "+v"(v[12]), "+v"(v[13]), "+v"(v[14]), "+v"(v[15]));
 }
-__device__ __forceinline__ void pin16(double (&)[16]) {}
+__device__ __forceinline__ void pin8(double (&v)[8]) {
+  asm volatile("" : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]), "+v"(v[6]), "+v"(v[7]));
+}
 
 // per-lane sums of one edge over the chunks of a block: local Hessian (upper
 // triangle, row-major, 21 entries; entry (3, 4) stays zero) and gradient (6)
@@ -820,20 +822,36 @@ __global__ void __launch_bounds__(kVisThreads) k_vis_gram(OptsDev o, DevPlan D, 
           // own registers, then 16 back-to-back MFMAs
           int I = tI[u], J = tJ[u];
           if constexpr (kF64) tile_ij(t, I, J);
-          R a[16], b[16];
-          lds_load16(E + (16 * I + m16) * LDC + 16 * g4, a);
-          lds_load16(E + (16 * J + m16) * LDC + 16 * g4, b);
+          if constexpr (kF64) {
+            // in quarters of 4 k-steps: each quarter's 8 operands loaded and
+            // scaled, then its 4 MFMAs (one LDS wait per quarter, bounded registers)
+            const double* pa = E + (16 * I + m16) * LDC + 16 * g4;
+            const double* pb = E + (16 * J + m16) * LDC + 16 * g4;
 #pragma unroll
-          for (int kk = 0; kk < 16; ++kk) b[kk] *= inv[kk];
-          if constexpr (!kF64) {
+            for (int qq = 0; qq < 4; ++qq) {
+              double q8[8];
+              const double2_t* xa = (const double2_t*)(pa + 4 * qq);
+              const double2_t* xb = (const double2_t*)(pb + 4 * qq);
+#pragma unroll
+              for (int h = 0; h < 2; ++h) {
+                const double2_t va = xa[h], vb = xb[h];
+                q8[2 * h] = va[0]; q8[2 * h + 1] = va[1];
+                q8[4 + 2 * h] = vb[0] * inv[4 * qq + 2 * h]; q8[4 + 2 * h + 1] = vb[1] * inv[4 * qq + 2 * h + 1];
+              }
+              pin8(q8);
+#pragma unroll
+              for (int kk = 0; kk < 4; ++kk)
+                gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(q8[kk], q8[4 + kk], gacc[u], 0, 0, 0);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          } else {
+            R a[16], b[16];
+            lds_load16(E + (16 * I + m16) * LDC + 16 * g4, a);
+            lds_load16(E + (16 * J + m16) * LDC + 16 * g4, b);
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) b[kk] *= inv[kk];
             pin16(a);
             pin16(b);
-          }
-          if constexpr (kF64) {
-#pragma unroll
-            for (int kk = 0; kk < 16; ++kk)
-              gacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], b[kk], gacc[u], 0, 0, 0);
-          } else {
 #pragma unroll
             for (int kk = 0; kk < 16; ++kk)
               gblk[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[kk], b[kk], gblk[u], 0, 0, 0);
