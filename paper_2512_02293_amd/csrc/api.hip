@@ -517,11 +517,12 @@ vi_status build_plan(vi_ctx* ctx, const std::vector<WinIn>& wins, Plan& P, bool 
       }
     }
   P.n_tickets = (int)(P.chol_tiles.size() / 2);
-  // then the back-substitution's block columns, last column first
+  // then the back-substitution's block columns, last column first, two per
+  // ticket (c and c - 1; the ticket of block 0 alone when nblk is odd)
   for (int c = P.nblk_max - 1; c >= 0; --c)
     for (int w = 0; w < nw; ++w) {
       const WinDev& W = P.win[w];
-      if (c >= W.nblk || W.npad <= kCholSmallMaxNpad) continue;
+      if (c >= W.nblk || W.npad <= kCholSmallMaxNpad || (W.nblk - 1 - c) % 2 != 0) continue;
       P.chol_tiles.push_back(w);
       P.chol_tiles.push_back(c);
     }

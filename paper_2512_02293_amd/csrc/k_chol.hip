@@ -917,8 +917,9 @@ __global__ void __launch_bounds__(256) k_chol_bs(DevPlan D, int t0, int nbs, con
                                                  const double* __restrict__ Linvall, double* __restrict__ xall,
                                                  int* __restrict__ flagsall, int* __restrict__ sync,
                                                  DevStatus* __restrict__ stall) {
-  __shared__ double part[8][NB];
+  __shared__ double part[2][8][NB];
   __shared__ double tv[NB];
+  __shared__ double xa[NB];
   __shared__ int tk;
   const int tid = threadIdx.x, q = tid & 31, r8 = tid >> 5, lane = tid & 63;
   while (true) {
@@ -927,8 +928,13 @@ __global__ void __launch_bounds__(256) k_chol_bs(DevPlan D, int t0, int nbs, con
     const int t = tk;
     __syncthreads();
     if (t >= nbs) return;
+    // two block columns per ticket: c and c - 1 (when c > 0), so that the
+    // chain of the back-substitution hands over between workgroups at every
+    // second block only
     const int w = D.chol_tiles[2 * (t0 + t)];
     const int c = D.chol_tiles[2 * (t0 + t) + 1] & 0xffff;
+    const bool two = c > 0;
+    const int cb = c - 1;
     const WinDev& W = D.win[w];
     const int npad = W.npad, nblk = W.nblk;
     const double* A = Aall + W.A_off;
@@ -937,17 +943,37 @@ __global__ void __launch_bounds__(256) k_chol_bs(DevPlan D, int t0, int nbs, con
     int* xf = flagsall + W.flag_off + (nblk + 1) * nblk;     // x_b published
     const int* fc = D.chol_fc + W.fc_off;
     bool aborted = load_flag(sync + 1) != 0;
-    // column q of L_cc^-1 for the last step, loaded before any wait
-    double lcc[NB];
+    // columns q of L_cc^-1, of L_(c-1)(c-1)^-1 and of L_c,c-1 for the last
+    // steps, loaded before any wait
+    double lcc[NB], lbb[NB], lcb[NB];
     if (tid < NB) {
 #pragma unroll
       for (int r = 0; r < NB; ++r) lcc[r] = Lcc[r * NB + q];
+      if (two) {
+        const double* Lbb = Linvall + W.Linv_off + (size_t)cb * NB * NB;
+#pragma unroll
+        for (int r = 0; r < NB; ++r) lbb[r] = Lbb[r * NB + q];
+        const bool in_env = fc[c] <= cb;      // L_c,c-1 = 0 outside the envelope
+#pragma unroll
+        for (int r = 0; r < NB; ++r) lcb[r] = in_env ? A[(size_t)(NB * c + r) * npad + NB * cb + q] : 0.0;
+      }
     }
-    // t_c = y_c - sum_b L_bc^T x_b over b = nblk-1 .. c+1 (in that order)
-    // inside the envelope: the flags of up to 32 blocks are read at once (a
-    // block outside the envelope counts as ready) and every ready run is
-    // summed with one acquire and its loads in flight
-    double acc = 0.0;
+    // t_c = y_c - sum_b L_bc^T x_b over b = nblk-1 .. c+1 (in that order),
+    // and the same sum for column c - 1, inside the envelope: the flags of up
+    // to 32 blocks are read at once (a block outside the envelope counts as
+    // ready) and every ready run is summed with one acquire and its loads in
+    // flight.  The tiles of block c + 1, whose x comes last (it waits for the
+    // previous ticket), are loaded before any wait: the factor is final.
+    double acc = 0.0, accb = 0.0;
+    double vl[4], vlb[4];
+    if (c + 1 < nblk) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const size_t row = (size_t)(NB * (c + 1) + r8 + 8 * u) * npad;
+        vl[u] = fc[c + 1] <= c ? A[row + NB * c + q] : 0.0;
+        vlb[u] = (two && fc[c + 1] <= cb) ? A[row + NB * cb + q] : 0.0;
+      }
+    }
     int b = nblk - 1;
     while (b > c) {
       const int bq = b - (lane & 31);
@@ -964,37 +990,75 @@ __global__ void __launch_bounds__(256) k_chol_bs(DevPlan D, int t0, int nbs, con
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       for (const int bend = b - run; b > bend; --b) {
-        if (fc[b] > c) continue;      // L_bc = 0 outside the envelope
-        double v[4], xv[4];
+        if (fc[b] > c) continue;      // L_bc = 0 outside the envelope (and L_b,c-1)
+        const bool use_b = two && fc[b] <= cb;
+        double v[4], vb[4], xv[4];
+        if (b == c + 1) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = A[(size_t)(NB * b + r8 + 8 * u) * npad + NB * c + q];
+          for (int u = 0; u < 4; ++u) { v[u] = vl[u]; vb[u] = vlb[u]; }
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const size_t row = (size_t)(NB * b + r8 + 8 * u) * npad;
+            v[u] = A[row + NB * c + q];
+            vb[u] = use_b ? A[row + NB * cb + q] : 0.0;
+          }
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) xv[u] = x[NB * b + r8 + 8 * u];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc += v[u] * xv[u];
+        for (int u = 0; u < 4; ++u) {
+          acc += v[u] * xv[u];
+          accb += vb[u] * xv[u];
+        }
       }
     }
-    part[r8][q] = acc;
+    part[0][r8][q] = acc;
+    part[1][r8][q] = accb;
     __syncthreads();
     if (tid < NB) {
       double s = A[(size_t)npad * npad + NB * c + q];
 #pragma unroll
-      for (int k = 0; k < 8; ++k) s -= part[k][q];
+      for (int k = 0; k < 8; ++k) s -= part[0][k][q];
+      tv[q] = s;
+    }
+    __syncthreads();
+    if (tid < NB) {
+      // x_c = L_cc^-T t_c: x[q] = sum_r Linv[r][q] t[r]
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < NB; ++r) s += lcc[r] * tv[r];
+      s = (NB * c + q < W.n) ? s : 0.0;
+      x[NB * c + q] = s;
+      xa[q] = s;
+    }
+    __syncthreads();
+    if (two && tid < NB) {
+      // t_c-1 = y_c-1 - sum_b L_b,c-1^T x_b - L_c,c-1^T x_c, then x_c-1
+      double s = A[(size_t)npad * npad + NB * cb + q];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) s -= part[1][k][q];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) s -= lcb[r] * xa[r];
       tv[q] = s;
     }
     __syncthreads();
     if (tid < 64) {
-      // x_c = L_cc^-T t_c: x[q] = sum_r Linv[r][q] t[r] (lanes 32..63 idle)
-      double s = 0.0;
-      if (tid < NB) {
+      if (two && tid < NB) {
+        double s = 0.0;
 #pragma unroll
-        for (int r = 0; r < NB; ++r) s += lcc[r] * tv[r];
-        x[NB * c + q] = (NB * c + q < W.n) ? s : 0.0;
+        for (int r = 0; r < NB; ++r) s += lbb[r] * tv[r];
+        x[NB * cb + q] = (NB * cb + q < W.n) ? s : 0.0;
       }
       if (aborted) {
         if (lane == 0) set_status(stall + w, VI_EDEVICE, -1);
       } else {
-        publish(xf + c);
+        // both blocks published by one release
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (threadIdx.x == 0) {
+          __hip_atomic_store(xf + c, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (two) __hip_atomic_store(xf + cb, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
       }
     }
     __syncthreads();
