@@ -1507,7 +1507,7 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
                                                          const double* __restrict__ rel,
                                                          const double* __restrict__ Cd,
                                                          const double* __restrict__ wd,
-                                                         const double* __restrict__ x, DevStatus* st) {
+                                                         const double* __restrict__ x, int ppt, DevStatus* st) {
   __shared__ double u[kMaxOutDegree * 6];
   __shared__ double rel_s[kMaxOutDegree * 12];
   __shared__ double xcam[(kMaxOutDegree + 1) * 6];
@@ -1541,7 +1541,7 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
   const int w = D.win_of_kf[src];
   const WinDev W = D.win[w];
   const int HW = W.HW;
-  if (st[w].code != 0 || st[w].conv != 0 || (int)blockIdx.x * 256 >= HW) return;
+  if (st[w].code != 0 || st[w].conv != 0 || (int)blockIdx.x * 256 * ppt >= HW) return;
   const int ls = src - W.kf_base;
   const int e0 = D.src_off[src];
   const int k = D.src_off[src + 1] - e0;
@@ -1574,44 +1574,47 @@ __global__ void __launch_bounds__(256) k_backsub_retract(OptsDev o, int N, DevPl
     u[i] = v;
   }
   __syncthreads();
-  const int p = blockIdx.x * 256 + tid;
-  if (p >= HW) return;
-  const size_t pl = (size_t)ls * HW + p;
-  const size_t pi = W.pix_base + pl;
-  const double cd = Cd[pi];
-  const double d = dep_load(W, pl);
-  double ddv = 0.0;
-  if (cd > 0.0 && k > 0) {
-    // E^T dxi at this pixel: sum over edges of L_e,p . u_e, with L = J_loc^T W J_d
-    const R qx = (R)(((double)(p % W.W) - W.cx) / W.fx);
-    const R qy = (R)(((double)(p / W.W) - W.cy) / W.fy);
-    R et = (R)0;
-    // edges in groups of 4 with all their weight loads issued first
-    for (int s0 = 0; s0 < k; s0 += 4) {
-      float wgx[4], wgy[4];
+  // ppt pixels per thread, 256 apart (the setup above is shared by all of them)
+  for (int j = 0; j < ppt; ++j) {
+    const int p = (blockIdx.x * ppt + j) * 256 + tid;
+    if (p >= HW) break;
+    const size_t pl = (size_t)ls * HW + p;
+    const size_t pi = W.pix_base + pl;
+    const double cd = Cd[pi];
+    const double d = dep_load(W, pl);
+    double ddv = 0.0;
+    if (cd > 0.0 && k > 0) {
+      // E^T dxi at this pixel: sum over edges of L_e,p . u_e, with L = J_loc^T W J_d
+      const R qx = (R)(((double)(p % W.W) - W.cx) / W.fx);
+      const R qy = (R)(((double)(p / W.W) - W.cy) / W.fy);
+      R et = (R)0;
+      // edges in groups of 4 with all their weight loads issued first
+      for (int s0 = 0; s0 < k; s0 += 4) {
+        float wgx[4], wgy[4];
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int s = min(s0 + g, k - 1);
-        const size_t t = (size_t)(D.src_edges[e0 + s] - W.e_base) * 2 * HW + p;
-        wgx[g] = W.weight[t];
-        wgy[g] = W.weight[t + HW];
-      }
+        for (int g = 0; g < 4; ++g) {
+          const int s = min(s0 + g, k - 1);
+          const size_t t = (size_t)(D.src_edges[e0 + s] - W.e_base) * 2 * HW + p;
+          wgx[g] = W.weight[t];
+          wgy[g] = W.weight[t + HW];
+        }
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int s = s0 + g;
-        if (s < k) {
-          PixEdgeT<R> q;
-          pix_edge_v<R>(W, o, rel_s + s * 12, qx, qy, (R)d, true, 0.0f, 0.0f, wgx[g], wgy[g], false, q);
-          const R ax = q.wx * q.Jdx, ay = q.wy * q.Jdy;
+        for (int g = 0; g < 4; ++g) {
+          const int s = s0 + g;
+          if (s < k) {
+            PixEdgeT<R> q;
+            pix_edge_v<R>(W, o, rel_s + s * 12, qx, qy, (R)d, true, 0.0f, 0.0f, wgx[g], wgy[g], false, q);
+            const R ax = q.wx * q.Jdx, ay = q.wy * q.Jdy;
 #pragma unroll
-          for (int c = 0; c < 6; ++c) et += (ax * q.Jx[c] + ay * q.Jy[c]) * (R)u[s * 6 + c];
+            for (int c = 0; c < 6; ++c) et += (ax * q.Jx[c] + ay * q.Jy[c]) * (R)u[s * 6 + c];
+          }
         }
       }
+      ddv = (double)(((R)wd[pi] - et) / (R)cd);
     }
-    ddv = (double)(((R)wd[pi] - et) / (R)cd);
+    dep_store(W, pl, fmax(d + ddv, o.d_min));
+    if (W.rep_dd) W.rep_dd[pl] = ddv;
   }
-  dep_store(W, pl, fmax(d + ddv, o.d_min));
-  if (W.rep_dd) W.rep_dd[pl] = ddv;
 }
 
 __global__ void k_reset_status(DevStatus* st, int n) {
@@ -1987,8 +1990,13 @@ void launch_step(hipStream_t s, const Plan& P, const DevPlan& D, const Work& w, 
   launch_chol(s, P, D, w, st);
   done(kStChol);
   auto kbs = (o.precision == VI_PREC_MIXED) ? k_backsub_retract<float> : k_backsub_retract<double>;
-  hipLaunchKernelGGL(kbs, dim3((P.hw_max + 255) / 256, N + P.n_win), dim3(256), 0, s, o, N, D, w.Rw,
-                     w.rel, w.Cd, w.wd, w.x, st);
+  // pixels per thread: 1 for small batches, up to 4 once the batch holds more
+  // than about 2048 workgroups' worth (the per-workgroup setup, a few
+  // dependent loads, is then shared by more pixels)
+  const int ppt = (int)std::min<long long>(4, std::max<long long>(1, P.pix_total / (256LL * 2048)));
+  const int pxb = 256 * ppt;
+  hipLaunchKernelGGL(kbs, dim3((P.hw_max + pxb - 1) / pxb, N + P.n_win), dim3(256), 0, s, o, N, D, w.Rw,
+                     w.rel, w.Cd, w.wd, w.x, ppt, st);
   done(kStBacksub);
 }
 
