@@ -418,6 +418,13 @@ __global__ void k_assemble_pg(int n_fixed, double lambda, DevPlan D, const doubl
   if (w == 0 && idx < 4) sync[idx] = 0;
   if (idx >= total) return;
   const int r = (int)(idx / npad), c = (int)(idx % npad);
+  // systems on the tile dataflow read only the lower tiles inside the
+  // envelope of S (and the right-hand-side row): the other entries are not
+  // formed
+  if (npad > kCholSmallMaxNpad && r < npad) {
+    const int ti = r / kCholNB, tj = c / kCholNB;
+    if (tj > ti || tj < D.chol_fc[W.fc_off + ti]) return;
+  }
   const int* poff = D.pair_off + W.pair_base;
   double val = 0.0;
   if (r < n && c < n) {

@@ -1427,6 +1427,13 @@ __global__ void k_assemble(OptsDev o, DevPlan D, const double* __restrict__ Z, c
   if (w == 0 && idx < 4) sync[idx] = 0;
   if (idx >= total) return;
   const int r = (int)(idx / npad), c = (int)(idx % npad);
+  // systems on the tile dataflow read only the lower tiles inside the
+  // envelope of S (and the right-hand-side row): the other entries are not
+  // formed
+  if (npad > kCholSmallMaxNpad && r < npad) {
+    const int ti = r / kCholNB, tj = c / kCholNB;
+    if (tj > ti || tj < D.chol_fc[W.fc_off + ti]) return;
+  }
   const double* Hw = Hf + (size_t)W.f_base * 900;
   const double* gw = gf + (size_t)W.f_base * 30;
   const int* poff = D.pair_off + W.pair_base;
