@@ -149,3 +149,22 @@ def test_mixed_loop_window(ctx):
         if g in errs:
             assert errs[g] <= MIXED_TOL_GROUP, (g, errs[g])
     assert errs["dd"] <= MIXED_TOL_DEPTH
+
+
+def test_dataflow_cholesky_fp64_odd_tile_count(ctx):
+    """35 keyframes (reduced system 525, padded to 544 = 17 tiles of 32): the
+    tile dataflow with an odd number of block columns, so that the
+    back-substitution's last ticket carries block 0 alone; FP64 against the
+    FP64 oracle at 1e-8."""
+    from paper_2512_02293_amd import binding
+    prob = synth.make_problem(synth.SceneConfig(n_kf=35, H=48, W=64, k_out=6, n_loop=6, loop_gap=20), 37)
+    rep, dxi, dd, o = _step(ctx, prob, binding.VI_PREC_FP64)
+    cam, st, gr = osolve.from_problem(prob)
+    _, orep = osolve.step(cam, st, gr, o)
+    errs = _errors(dxi, dd, orep)
+    print("fp64 odd tile count:", {k: f"{v:.2e}" for k, v in errs.items()})
+    for g in GROUPS:
+        if g in errs:
+            assert errs[g] <= 1e-8, (g, errs[g])
+    assert errs["dd"] <= 1e-8
+    assert rep["n_valid"] == orep["n_valid"]
