@@ -291,9 +291,10 @@ __device__ inline void sim3_jr_inv(const double* x, double* J) {
   }
 }
 
-// one relative-pose factor: residual, Jacobians, blocks J^T Lambda J, -J^T Lambda r, cost
-__device__ void relpose_factor(const WinDev& W, int i, int j, const double* meas, const double* info, double* r,
-                               double* Ji, double* Jj) {
+// one relative-pose factor: its residual and, when Ji is set, its Jacobians
+// with respect to the two keyframes (the caller weights them by Lambda)
+__device__ void relpose_factor(const WinDev& W, int i, int j, const double* meas, double* r, double* Ji,
+                               double* Jj) {
   Sim3 Ti, Tj, Tji, E, Ei, Tm, M;
   sim3_pose(W.pose + (size_t)i * 7, W.scale[i], Ti);
   sim3_pose(W.pose + (size_t)j * 7, W.scale[j], Tj);
@@ -360,7 +361,7 @@ __global__ void __launch_bounds__(64) k_relpose(int R, DevPlan D, double* __rest
   const double* meas = W.rel_meas + (size_t)lf * 8;
   const double* L = W.rel_info + (size_t)lf * 49;
   double r[7], Ji[49], Jj[49];
-  relpose_factor(W, gi - W.kf_base, gj - W.kf_base, meas, L, r, want_jac ? Ji : nullptr, want_jac ? Jj : nullptr);
+  relpose_factor(W, gi - W.kf_base, gj - W.kf_base, meas, r, want_jac ? Ji : nullptr, want_jac ? Jj : nullptr);
   double Lr[7], c = 0.0;
   for (int a = 0; a < 7; ++a) {
     double v = 0.0;
