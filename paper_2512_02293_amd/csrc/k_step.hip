@@ -1685,22 +1685,37 @@ __global__ void __launch_bounds__(256) k_vis_cost(OptsDev o, DevPlan D, int ncos
   const R d = (R)dsrc;
   const R fx = (R)W.fx, fy = (R)W.fy, cx = (R)W.cx, cy = (R)W.cy;
   double cost = 0.0, nval = 0.0;
-  for (int s = 0; s < k; ++s) {
-    const int e = D.src_edges[e0 + s];
-    R Rt[12];
+  // edges in groups of 4 with all their target and weight loads issued first
+  // (the sums still run over the edges in order)
+  for (int s0 = 0; s0 < k; s0 += 4) {
+    float tgx[4], tgy[4], wgx[4], wgy[4];
 #pragma unroll
-    for (int c = 0; c < 12; ++c) Rt[c] = (R)rel[s * 12 + c];
-    const R Px = Rt[0] * qx + Rt[1] * qy + Rt[2] + Rt[9] * d;
-    const R Py = Rt[3] * qx + Rt[4] * qy + Rt[5] + Rt[10] * d;
-    const R Pz = Rt[6] * qx + Rt[7] * qy + Rt[8] + Rt[11] * d;
-    const bool valid = inpx && d > (R)0 && Pz > (R)o.z_min * d;
-    if (valid) {
+    for (int g = 0; g < 4; ++g) {
+      const int e = D.src_edges[e0 + min(s0 + g, k - 1)];
       const size_t toff = (size_t)(e - W.e_base) * 2 * HW + pc;
-      const R iz = recip<R>(Pz);
-      const R rx = (R)W.target[toff] - (fx * Px * iz + cx);
-      const R ry = (R)W.target[toff + HW] - (fy * Py * iz + cy);
-      cost += (double)((R)W.weight[toff] * rx * rx + (R)W.weight[toff + HW] * ry * ry);
-      nval += 1.0;
+      tgx[g] = W.target[toff];
+      tgy[g] = W.target[toff + HW];
+      wgx[g] = W.weight[toff];
+      wgy[g] = W.weight[toff + HW];
+    }
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int s = s0 + g;
+      if (s >= k) break;
+      R Rt[12];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) Rt[c] = (R)rel[s * 12 + c];
+      const R Px = Rt[0] * qx + Rt[1] * qy + Rt[2] + Rt[9] * d;
+      const R Py = Rt[3] * qx + Rt[4] * qy + Rt[5] + Rt[10] * d;
+      const R Pz = Rt[6] * qx + Rt[7] * qy + Rt[8] + Rt[11] * d;
+      const bool valid = inpx && d > (R)0 && Pz > (R)o.z_min * d;
+      if (valid) {
+        const R iz = recip<R>(Pz);
+        const R rx = (R)tgx[g] - (fx * Px * iz + cx);
+        const R ry = (R)tgy[g] - (fy * Py * iz + cy);
+        cost += (double)((R)wgx[g] * rx * rx + (R)wgy[g] * ry * ry);
+        nval += 1.0;
+      }
     }
   }
   cost = wave_sum(cost);
