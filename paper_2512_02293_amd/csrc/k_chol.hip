@@ -331,6 +331,25 @@ __device__ __forceinline__ void mm32_abt_lds(double4_t (&acc)[2][2], const doubl
   }
 }
 
+// The same for a diagonal tile, acc += sA X X^T: the upper-right 16x16
+// quarter, which no later step reads (the factor of a diagonal tile uses its
+// lower blocks only), is not formed
+__device__ __forceinline__ void mm32_abt_lds_diag(double4_t (&acc)[2][2], const double* X, double sA) {
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    double a[2], b[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      b[h] = X[swz(16 * h + mrow, 4 * s + kq)];
+      a[h] = sA * b[h];
+    }
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0], b[0], acc[0][0], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[0], acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1], b[1], acc[1][1], 0, 0, 0);
+  }
+}
+
 // acc(2x2 blocks of 16x16) += X Y^T over K = 32, X a swizzled LDS tile, Y a
 // padded (stride LD) LDS tile
 __device__ __forceinline__ void mm32_abt_swz_pad(double4_t (&acc)[2][2], const double* X, const double* Y) {
@@ -793,7 +812,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
           swz_to_acc(acc, diagbuf(nb1));
         else
           load_tile32(acc, A + (size_t)(NB * nb1) * npad + NB * nb1, npad);
-        mm32_abt_lds(acc, Pc, Pc, -1.0);
+        mm32_abt_lds_diag(acc, Pc, -1.0);
         acc_to_lds(acc, T);
         double* Ln = Li[nb1 & 1];
         const int bad = factor_invert32(T, Ln, U);
@@ -846,7 +865,10 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
           double* Aij = A + (size_t)(NB * i) * npad + NB * j;
           wait_eq(&pready[i - b - 1], b + 1);
           wait_eq(&pready[j - b - 1], b + 1);
-          mm32_abt_lds(acc, Pc + (i - b - 1) * NB * NB, Pc + (j - b - 1) * NB * NB, -1.0);
+          if (i == j)
+            mm32_abt_lds_diag(acc, Pc + (i - b - 1) * NB * NB, -1.0);
+          else
+            mm32_abt_lds(acc, Pc + (i - b - 1) * NB * NB, Pc + (j - b - 1) * NB * NB, -1.0);
           if (lds && j == b + 1)
             acc_to_swz(acc, colbuf(b + 1) + (i - b - 2) * NB * NB);
           else if (lds && i == b + 2 && j == b + 2)
