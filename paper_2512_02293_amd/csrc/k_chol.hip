@@ -287,6 +287,26 @@ __device__ __forceinline__ void mm32_abt(double4_t (&acc)[2][2], const double* X
         acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm][s], b[bn][s], acc[bm][bn], 0, 0, 0);
 }
 
+// acc += sA X X^T into a diagonal tile: the upper-right 16x16 quarter, which
+// the tile's factor never reads, is not formed
+__device__ __forceinline__ void mm32_aat_diag(double4_t (&acc)[2][2], const double* X, size_t ldx, double sA) {
+  const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
+  double a[2][8], b[2][8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      b[h][s] = X[(16 * h + mrow) * ldx + 4 * s + kq];
+      a[h][s] = sA * b[h][s];
+    }
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0][s], b[0][s], acc[0][0], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1][s], b[0][s], acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1][s], b[1][s], acc[1][1], 0, 0, 0);
+  }
+}
+
 __device__ __forceinline__ void load_tile32(double4_t (&acc)[2][2], const double* M, size_t ld) {
   const int lane = lane_id(), mrow = lane & 15, kq = lane >> 4;
 #pragma unroll
@@ -511,6 +531,17 @@ __device__ __forceinline__ void mfma_update(double4_t (&acc)[2][2], const double
         acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm][s2], b[bn][s2], acc[bm][bn], 0, 0, 0);
 }
 
+// the same into a diagonal tile, acc += a a^T: its upper-right 16x16 quarter,
+// which the tile's factor never reads, is not formed
+__device__ __forceinline__ void mfma_update_diag(double4_t (&acc)[2][2], const double (&a)[2][8]) {
+#pragma unroll
+  for (int s2 = 0; s2 < 8; ++s2) {
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[0][s2], a[0][s2], acc[0][0], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1][s2], a[0][s2], acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[1][s2], a[1][s2], acc[1][1], 0, 0, 0);
+  }
+}
+
 // k-loop of a dataflow ticket over [k, kend): X -= L_ik L_jk^T, and with PAIR
 // also Y += L_ik L_ik^T (ONLY2: Y alone; the operand a = -L_ik serves as both
 // MFMA inputs, so Y holds the negated diagonal update), over runs of
@@ -522,7 +553,7 @@ __device__ __forceinline__ bool df_kloop(double4_t (&acc)[2][2], double4_t (&acc
                                          int* sync) {
   auto step = [&](const double (&a)[2][8], const double (&b)[2][8]) {
     if (!ONLY2) mfma_update(acc, a, b);
-    if (PAIR || ONLY2) mfma_update(acc2, a, a);
+    if (PAIR || ONLY2) mfma_update_diag(acc2, a);
   };
   while (k < kend) {
     const int run = ready_run(fi, fj, k, kend);
@@ -651,7 +682,7 @@ __global__ void __launch_bounds__(64) k_chol_df(DevPlan D, int ntickets, double*
         __syncthreads();
         acc_to_lds(out, Lt);
         __syncthreads();
-        mm32_abt(acc2, Lt, LD, Lt, LD, -1.0);
+        mm32_aat_diag(acc2, Lt, LD, -1.0);
         acc_to_lds(acc2, T);
         __syncthreads();
         const int bad = factor_invert32(T, Lt, U);
