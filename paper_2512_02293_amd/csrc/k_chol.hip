@@ -100,12 +100,14 @@ __device__ __forceinline__ void acc_to_lds(const double4_t (&acc)[2][2], double*
 }
 
 __device__ __forceinline__ double rsqrt_refined(double v) {
-  // hardware reciprocal square root, then two Newton steps to full precision
-  double y = __builtin_amdgcn_rsq(v);
-  const double h = 0.5 * v;
-  y = y * (1.5 - h * y * y);
-  y = y * (1.5 - h * y * y);
-  return y;
+  // hardware reciprocal square root (relative error about 2^-23), then one
+  // third-order step: with e = 1 - v y^2, v^-1/2 = y (1 - e)^-1/2 =
+  // y (1 + e/2 + 3 e^2/8 + 5 e^3/16 + ...); the dropped terms are below 2^-64
+  // relative.  Four dependent operations after the estimate, where two
+  // Newton steps take six (the pivot chain of the leaf factor runs through it).
+  const double y = __builtin_amdgcn_rsq(v);
+  const double e = __builtin_fma(-v, y * y, 1.0);
+  return __builtin_fma(y * e, __builtin_fma(0.375, e, 0.5), y);
 }
 
 // ---------------------------------------------------------------------------
@@ -159,14 +161,15 @@ __device__ __forceinline__ int leaf8_inv(const double* M, int ld, double* D, int
   double rv[8];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    double piv = L[tri8(j, j)];
-    if (!(piv > 0.0)) {
-      if (bad < 0) bad = j;
-      piv = 1.0;
-    }
-    const double r = rsqrt_refined(piv);
+    // a pivot that is not positive is taken as 1 (so that the block stays
+    // finite) and reported; the estimate starts from |pivot| so that this
+    // choice stays off the dependent chain from one pivot to the next
+    const double piv = L[tri8(j, j)];
+    const bool ok = piv > 0.0;
+    if (!ok && bad < 0) bad = j;
+    const double r = ok ? rsqrt_refined(__builtin_fabs(piv)) : 1.0;
     rv[j] = r;
-    L[tri8(j, j)] = piv * r;
+    L[tri8(j, j)] = ok ? piv * r : 1.0;
 #pragma unroll
     for (int i = 1; i < 8; ++i)
       if (i > j) L[tri8(i, j)] *= r;
