@@ -769,9 +769,10 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
   __syncthreads();
   // Wave roles: wave 0 carries the chain of diagonal factorisations; wave 4
   // shares its SIMD and so takes the memory work (copies, the deferred global
-  // copy of L_bb^-1, panel tiles beyond the seventh) and then every seventh
-  // trailing tile; the six other waves take the panel, the forward
-  // substitution and the rest of the trailing update.
+  // copy of L_bb^-1, panel tiles beyond the seventh) and then, in steps with
+  // at least 14 trailing tiles, every seventh of them; the six other waves
+  // take the panel, the forward substitution and the rest of the trailing
+  // update.
   // a bounded wait that expired fails the window (VI_EDEVICE): the solution is
   // not used and the window's state is left as it was
   auto wait_eq = [&](const int* f, int v) {
@@ -866,11 +867,17 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
                         npad);
           if (cp_diag) tile_to_swz(diagbuf(b + 2), A + (size_t)(NB * (b + 2)) * npad + NB * (b + 2), npad);
         }
-        // seven workers: the six compute waves and, after its copies, wave 4 (the
-        // MFMA pipe of SIMD 0 is mostly idle beside the look-ahead chain)
+        // workers: the six compute waves and, after its copies, wave 4, whose
+        // SIMD also runs the look-ahead chain.  A wave's tiles run one after
+        // the other, so the step takes about as long as the largest number of
+        // tiles per wave: wave 4 joins only when a seventh worker lowers that
+        // number (at least 14 tiles), and otherwise leaves SIMD 0 to the chain
+        // (the same tiles per wave, and a faster chain).
         // Each tile's successor is loaded while the tile is updated (one
         // global latency per wave and step instead of one per tile).
         const int tw = (wave == 4) ? NW - 2 : cw;
+        const int nt = ntri - 1;
+        const int nwk = (nt + 6) / 7 < (nt + 5) / 6 ? NW - 1 : NW - 2;
         auto tile_of = [&](int u, int& i, int& j) {
           int jj = 0, rem = u;
           while (rem >= m - jj) { rem -= m - jj; ++jj; }
@@ -878,12 +885,12 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
           i = j + rem;
         };
         double4_t nxt[2][2];
-        if (1 + tw < ntri) {
+        if (tw < nwk && 1 + tw < ntri) {
           int i, j;
           tile_of(1 + tw, i, j);
           load_tile32(nxt, A + (size_t)(NB * i) * npad + NB * j, npad);
         }
-        for (int u = 1 + tw; u < ntri; u += NW - 1) {
+        for (int u = tw < nwk ? 1 + tw : ntri; u < ntri; u += nwk) {
           int i, j;
           tile_of(u, i, j);
           double4_t acc[2][2];
@@ -891,9 +898,9 @@ __global__ void __launch_bounds__(kSmallThreads) k_chol_small(DevPlan D, double*
           for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
             for (int bn = 0; bn < 2; ++bn) acc[bm][bn] = nxt[bm][bn];
-          if (u + NW - 1 < ntri) {
+          if (u + nwk < ntri) {
             int i2, j2;
-            tile_of(u + NW - 1, i2, j2);
+            tile_of(u + nwk, i2, j2);
             load_tile32(nxt, A + (size_t)(NB * i2) * npad + NB * j2, npad);
           }
           double* Aij = A + (size_t)(NB * i) * npad + NB * j;
