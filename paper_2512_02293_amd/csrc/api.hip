@@ -45,6 +45,7 @@ struct vi_ctx {
   int status_cap = 0;
   int32_t* d_off = nullptr;        // device CSR for imu_preintegrate
   size_t d_off_cap = 0;
+  std::vector<int32_t> off_on_dev; // what d_off holds (empty: not known), so an unchanged CSR is not sent again
   // plan
   Plan plan;
   bool have_plan = false;
@@ -54,6 +55,7 @@ struct vi_ctx {
   size_t d_plan_cap = 0;
   DevPlan dplan{};
   WinDev* d_win = nullptr;         // device window table (inside d_plan)
+  std::vector<char> win_on_dev;    // bytes d_win holds (empty: not known), so an unchanged table is not sent again
   int attr_kmax = -1;
   // autotuning
   bool autotune = false;
@@ -628,6 +630,7 @@ vi_status upload_plan(vi_ctx* ctx) {
     dptr[idx++] = (const int32_t*)(ctx->d_plan + off);
     off += align256(std::max<size_t>(v->size(), 1) * sizeof(int32_t));
   }
+  ctx->win_on_dev.clear();
   HIPCHK(ctx, hipMemcpy(ctx->d_plan, host.data(), total, hipMemcpyHostToDevice));
   DevPlan& D = ctx->dplan;
   ctx->d_win = (WinDev*)ctx->d_plan;
@@ -711,7 +714,13 @@ vi_status refresh_windows(vi_ctx* ctx, const std::vector<WinIn>& wins, bool dept
     W.rel_meas = in.rel ? in.rel->meas : nullptr;
     W.rel_info = in.rel ? in.rel->info : nullptr;
   }
-  HIPCHK(ctx, hipMemcpy(ctx->d_win, P.win.data(), sizeof(WinDev) * P.n_win, hipMemcpyHostToDevice));
+  // a blocking copy: send it only when the table differs from what the device holds
+  const size_t nb = sizeof(WinDev) * P.n_win;
+  const char* hb = (const char*)P.win.data();
+  if (ctx->win_on_dev.size() == nb && std::memcmp(ctx->win_on_dev.data(), hb, nb) == 0) return VI_OK;
+  ctx->win_on_dev.clear();
+  HIPCHK(ctx, hipMemcpy(ctx->d_win, hb, nb, hipMemcpyHostToDevice));
+  ctx->win_on_dev.assign(hb, hb + nb);
   return VI_OK;
 }
 
@@ -753,6 +762,7 @@ vi_status autotune_range(vi_ctx* ctx, const Work& w, const OptsDev& od) {
     if (whole) break;
     whole = r >= P.hw_max;
     set_range(P, r);
+    ctx->win_on_dev.clear();
     HIPCHK(ctx, hipMemcpy(ctx->d_win, P.win.data(), sizeof(WinDev) * P.n_win, hipMemcpyHostToDevice));
     float tot = 0.f;
     for (int rep = 0; rep < 3; ++rep) {
@@ -1208,6 +1218,7 @@ vi_status imu_preintegrate(vi_ctx* ctx, int32_t F, const int32_t* off, const dou
   HIPCHK(ctx, hipSetDevice(ctx->device));
   const size_t bytes = sizeof(int32_t) * (F + 1);
   if (bytes > ctx->d_off_cap) {
+    ctx->off_on_dev.clear();
     if (ctx->d_off) HIPCHK(ctx, hipFree(ctx->d_off));
     ctx->d_off = nullptr;
     HIPCHK(ctx, hipMalloc((void**)&ctx->d_off, bytes));
@@ -1215,7 +1226,13 @@ vi_status imu_preintegrate(vi_ctx* ctx, int32_t F, const int32_t* off, const dou
   }
   HIPCHK(ctx, hipEventRecord(ctx->ev_in, ctx->user));
   HIPCHK(ctx, hipStreamWaitEvent(ctx->priv, ctx->ev_in, 0));
-  HIPCHK(ctx, hipMemcpyAsync(ctx->d_off, off, bytes, hipMemcpyHostToDevice, ctx->priv));
+  // the CSR is sent only when it differs from what the device holds (the
+  // previous call has completed: it ends with a synchronisation)
+  if (ctx->off_on_dev.size() != (size_t)F + 1 || std::memcmp(ctx->off_on_dev.data(), off, bytes) != 0) {
+    ctx->off_on_dev.clear();
+    HIPCHK(ctx, hipMemcpyAsync(ctx->d_off, off, bytes, hipMemcpyHostToDevice, ctx->priv));
+    ctx->off_on_dev.assign(off, off + F + 1);
+  }
   launch_reset_status(ctx->priv, ctx->status, 1);
   launch_preint(ctx->priv, F, ctx->d_off, gyro, accel, dt, bias_hat, *noise, out, ctx->status);
   HIPCHK(ctx, hipGetLastError());
