@@ -3,10 +3,11 @@
 // and covariance, following Forster et al.) and the per-factor information
 // matrix used by the inertial residual of Eq. 2-3.
 //
-// One 64-lane workgroup per factor.  The sample loop is inherently serial; the
-// lanes share each sample's work in two phases: T = A cov with the new mean and
-// bias Jacobians, then the 45 lower-triangle entries of cov = T A^T + Q, using
-// the block structure of the transition A of the (rot, vel, pos) error state.
+// One 192-thread workgroup per factor.  The sample loop is inherently serial;
+// the threads share each sample's work in two phases: T = A cov (one entry per
+// thread) beside the new mean and bias Jacobians, then the 45 lower-triangle
+// entries of cov = T A^T + Q, using the block structure of the transition A of
+// the (rot, vel, pos) error state.
 #include "vi_internal.h"
 #include "vi_math.h"
 
@@ -26,6 +27,11 @@ __device__ __forceinline__ void m1_row(const double* dR, const double* a, int r,
   m1[2] = d0 * a[1] - d1 * a[0];
 }
 
+// Three waves per factor: in phase 1 the 81 entries of T = A cov take one
+// lane each (waves 0 and 1) while wave 2 updates the mean and the bias
+// Jacobians; phase 2 and the per-sample precomputation run on wave 0.
+constexpr int kPreintThreads = 192;
+
 // LDS layout of one factor's running state
 struct PreintLds {
   double dR[9], dv[3], dp[3], JR[9], Jvg[9], Jva[9], Jpg[9], Jpa[9];
@@ -35,7 +41,7 @@ struct PreintLds {
   double T[81], cov[81];
 };
 
-__global__ void __launch_bounds__(64) k_preint(int F, const int32_t* __restrict__ off,
+__global__ void __launch_bounds__(kPreintThreads) k_preint(int F, const int32_t* __restrict__ off,
                                                const double* __restrict__ gyro,
                                                const double* __restrict__ accel,
                                                const double* __restrict__ dt,
@@ -56,7 +62,7 @@ __global__ void __launch_bounds__(64) k_preint(int F, const int32_t* __restrict_
     S.JR[l] = 0.0; S.Jvg[l] = 0.0; S.Jva[l] = 0.0; S.Jpg[l] = 0.0; S.Jpa[l] = 0.0;
   }
   if (l < 3) { S.dv[l] = 0.0; S.dp[l] = 0.0; }
-  for (int e = l; e < 81; e += 64) S.cov[e] = 0.0;
+  for (int e = l; e < 81; e += kPreintThreads) S.cov[e] = 0.0;
   double total = 0.0;
   __syncthreads();
 
@@ -87,7 +93,8 @@ __global__ void __launch_bounds__(64) k_preint(int F, const int32_t* __restrict_
       // triangular: A = [[dRk^T, 0, 0], [-M1 h, I, 0], [-M1 h^2 / 2, I h, I]]
       // with M1 = dR [a]x; only its non-trivial terms are multiplied.
       // phase 1: T = A cov; the new mean and bias Jacobians (old values on the right); M1 for phase 2
-      for (int e = l; e < 81; e += 64) {
+      if (l < 81) {
+        const int e = l;
         const int r = e / 9, c = e % 9, br = r / 3, rr = r % 3;
         double v = 0.0;
         if (br == 0) {
@@ -106,26 +113,27 @@ __global__ void __launch_bounds__(64) k_preint(int F, const int32_t* __restrict_
         }
         S.T[e] = v;
       }
-      if (l < 9) {
-        const int r = l / 3, c = l % 3;
+      const int lj = l - 128;                    // wave 2
+      if (lj >= 0 && lj < 9) {
+        const int r = lj / 3, c = lj % 3;
         double m1[3];
         m1_row(S.dR, a, r, m1);
-        S.M1[l] = m1[c];
+        S.M1[lj] = m1[c];
         double mj = 0.0;
         for (int m = 0; m < 3; ++m) mj += m1[m] * S.JR[m * 3 + c];
-        S.nJpa[l] = S.Jpa[l] + S.Jva[l] * h - 0.5 * S.dR[l] * hh;
-        S.nJpg[l] = S.Jpg[l] + S.Jvg[l] * h - 0.5 * mj * hh;
-        S.nJva[l] = S.Jva[l] - S.dR[l] * h;
-        S.nJvg[l] = S.Jvg[l] - mj * h;
+        S.nJpa[lj] = S.Jpa[lj] + S.Jva[lj] * h - 0.5 * S.dR[lj] * hh;
+        S.nJpg[lj] = S.Jpg[lj] + S.Jvg[lj] * h - 0.5 * mj * hh;
+        S.nJva[lj] = S.Jva[lj] - S.dR[lj] * h;
+        S.nJvg[lj] = S.Jvg[lj] - mj * h;
         double v = 0.0, w = 0.0;
         for (int m = 0; m < 3; ++m) {
           v += dRk[m * 3 + r] * S.JR[m * 3 + c];     // dRk^T J^rot
           w += S.dR[r * 3 + m] * dRk[m * 3 + c];     // dR dRk
         }
-        S.nJR[l] = v - Jrk[l] * h;
-        S.nR[l] = w;
-      } else if (l >= 16 && l < 19) {
-        const int i = l - 16;
+        S.nJR[lj] = v - Jrk[lj] * h;
+        S.nR[lj] = w;
+      } else if (lj >= 16 && lj < 19) {
+        const int i = lj - 16;
         const double ra = S.dR[i * 3 + 0] * a[0] + S.dR[i * 3 + 1] * a[1] + S.dR[i * 3 + 2] * a[2];
         S.np_[i] = S.dp[i] + S.dv[i] * h + 0.5 * ra * hh;
         S.nv[i] = S.dv[i] + ra * h;
@@ -190,7 +198,7 @@ __global__ void __launch_bounds__(64) k_preint(int F, const int32_t* __restrict_
   }
   if (l < 3) { o->dv[l] = S.dv[l]; o->dp[l] = S.dp[l]; }
   // internal (rot, vel, pos) -> residual order (rot, pos, vel)
-  for (int e = l; e < 81; e += 64) {
+  for (int e = l; e < 81; e += kPreintThreads) {
     const int r = e / 9, c = e % 9;
     const int pr = (r < 3) ? r : (r < 6 ? r + 3 : r - 3);
     const int pc = (c < 3) ? c : (c < 6 ? c + 3 : c - 3);
@@ -321,7 +329,7 @@ void launch_preint(hipStream_t s, int F, const int32_t* off, const double* gyro,
                    const double* dt, const double* bias_hat, vi_imu_noise noise, vi_preint* out,
                    DevStatus* st) {
   if (F <= 0) return;
-  hipLaunchKernelGGL(k_preint, dim3(F), dim3(64), 0, s, F, off, gyro, accel, dt, bias_hat, noise, out, st);
+  hipLaunchKernelGGL(k_preint, dim3(F), dim3(kPreintThreads), 0, s, F, off, gyro, accel, dt, bias_hat, noise, out, st);
 }
 
 void launch_predict_kf(hipStream_t s, int n, const double* pose_i, const double* vel_i, const double* bias_i,
