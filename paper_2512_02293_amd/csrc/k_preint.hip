@@ -211,10 +211,13 @@ __global__ void __launch_bounds__(kPreintThreads) k_preint(int F, const int32_t*
   }
 }
 
-// Lambda = blkdiag(cov^-1, diag(1 / cov_bias)) per factor.  The 9x9 inverse
-// goes through a Cholesky factor in LDS (one lane per column of the inverse).
+// Lambda = blkdiag(cov^-1, diag(1 / cov_bias)) per factor.  Every lane forms
+// the Cholesky factor of the 9x9 covariance in registers (packed lower
+// triangle; no lane waits on another), then lane c < 9 forms column c of its
+// inverse by forward substitution; Lambda's 9x9 block is L^-T L^-1.
+__device__ __forceinline__ constexpr int tri9(int i, int j) { return i * (i + 1) / 2 + j; }
+
 __global__ void __launch_bounds__(64) k_imu_info(int F, DevPlan D, double* __restrict__ Lam, DevStatus* stall) {
-  __shared__ double C[81];
   __shared__ double Li[81];     // L^-1
   const int f = blockIdx.x;
   const int l = threadIdx.x;
@@ -223,32 +226,44 @@ __global__ void __launch_bounds__(64) k_imu_info(int F, DevPlan D, double* __res
   const WinDev& W = D.win[w];
   const vi_preint* P = W.imu + (f - W.f_base);
   DevStatus* st = stall + w;
-  for (int e = l; e < 81; e += 64) C[e] = P->cov[e];
-  __syncthreads();
-  if (l == 0) {
-    // in-place lower Cholesky
-    bool ok = true;
-    for (int k = 0; k < 9; ++k) {
-      double d = C[k * 9 + k];
-      for (int m = 0; m < k; ++m) d -= C[k * 9 + m] * C[k * 9 + m];
-      if (!(d > 0.0)) { ok = false; d = 1.0; }
-      d = sqrt(d);
-      C[k * 9 + k] = d;
-      for (int i = k + 1; i < 9; ++i) {
-        double v = C[i * 9 + k];
-        for (int m = 0; m < k; ++m) v -= C[i * 9 + m] * C[k * 9 + m];
-        C[i * 9 + k] = v / d;
+  double L[45];
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = 0; j < 9; ++j)
+      if (j <= i) L[tri9(i, j)] = P->cov[i * 9 + j];
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    double d = L[tri9(k, k)];
+#pragma unroll
+    for (int m = 0; m < 9; ++m)
+      if (m < k) d -= L[tri9(k, m)] * L[tri9(k, m)];
+    if (!(d > 0.0)) { ok = false; d = 1.0; }
+    d = sqrt(d);
+    L[tri9(k, k)] = d;
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      if (i > k) {
+        double v = L[tri9(i, k)];
+#pragma unroll
+        for (int m = 0; m < 9; ++m)
+          if (m < k) v -= L[tri9(i, m)] * L[tri9(k, m)];
+        L[tri9(i, k)] = v / d;
       }
-    }
-    if (!ok) set_status(st, VI_ENOTPD, -1 - (f - W.f_base));
   }
-  __syncthreads();
+  if (!ok && l == 0) set_status(st, VI_ENOTPD, -1 - (f - W.f_base));
   if (l < 9) {
-    // column l of L^-1 by forward substitution
+    // column l of L^-1: x_r = 0 above the diagonal, (e_l - sum_m L_rm x_m) / L_rr from it on
+    double x[9];
+#pragma unroll
     for (int r = 0; r < 9; ++r) {
       double v = (r == l) ? 1.0 : 0.0;
-      for (int m = l; m < r; ++m) v -= C[r * 9 + m] * Li[m * 9 + l];
-      Li[r * 9 + l] = (r < l) ? 0.0 : v / C[r * 9 + r];
+#pragma unroll
+      for (int m = 0; m < 9; ++m)
+        if (m < r && m >= l) v -= L[tri9(r, m)] * x[m];
+      x[r] = (r < l) ? 0.0 : v / L[tri9(r, r)];
+      Li[r * 9 + l] = x[r];
     }
   }
   __syncthreads();
