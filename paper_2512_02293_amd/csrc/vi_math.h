@@ -85,11 +85,15 @@ __device__ inline void so3_log(const double* R, double* w) {
   for (int r = 0; r < 3; ++r)
 #pragma unroll
     for (int q = 0; q < 3; ++q) M[r * 3 + q] = (R[r * 3 + q] + R[q * 3 + r] - (r == q ? 2.0 * c : 0.0)) / den;
+  // column k of the largest diagonal entry, chosen by selects (an index into
+  // M would put M in scratch memory)
   int k = 0;
-  if (M[4] > M[k * 4]) k = 1;
-  if (M[8] > M[k * 4]) k = 2;
-  const double nk = sqrt(fmax(M[k * 4], 1e-300));
-  double u[3] = {M[0 * 3 + k] / nk, M[1 * 3 + k] / nk, M[2 * 3 + k] / nk};
+  double mk = M[0];
+  if (M[4] > mk) { k = 1; mk = M[4]; }
+  if (M[8] > mk) { k = 2; mk = M[8]; }
+  const double nk = sqrt(fmax(mk, 1e-300));
+  double u[3] = {(k == 0 ? M[0] : k == 1 ? M[1] : M[2]) / nk, (k == 0 ? M[3] : k == 1 ? M[4] : M[5]) / nk,
+                 (k == 0 ? M[6] : k == 1 ? M[7] : M[8]) / nk};
   if (u[0] * vx + u[1] * vy + u[2] * vz < 0.0) { u[0] = -u[0]; u[1] = -u[1]; u[2] = -u[2]; }
   w[0] = t * u[0]; w[1] = t * u[1]; w[2] = t * u[2];
 }
@@ -145,9 +149,11 @@ __device__ inline void rot_to_quat(const double* R, double* q) {
   const double tr = R[0] + R[4] + R[8];
   const double c[4] = {1.0 + tr, 1.0 + 2.0 * R[0] - tr, 1.0 + 2.0 * R[4] - tr, 1.0 + 2.0 * R[8] - tr};
   int k = 0;
+  double ck = c[0];                     // c[k], kept by value (an index into c would put c in scratch memory)
+#pragma unroll
   for (int i = 1; i < 4; ++i)
-    if (c[i] > c[k]) k = i;
-  const double s = 0.5 / sqrt(c[k]);   // 4 * (the pivot component) = 2 sqrt(c[k])
+    if (c[i] > ck) { k = i; ck = c[i]; }
+  const double s = 0.5 / sqrt(ck);     // 4 * (the pivot component) = 2 sqrt(c[k])
   double x, y, z, w;
   if (k == 0) {
     w = 0.5 * sqrt(c[0]); x = (R[7] - R[5]) * s; y = (R[2] - R[6]) * s; z = (R[3] - R[1]) * s;
